@@ -1,0 +1,1044 @@
+/*
+ * FP64 reference implementation of the KF track fit and combinatorial track
+ * finding.  TEST INFRASTRUCTURE ONLY: the tests, smoke() and the CPU-baseline
+ * leg of the benchmark use it; the product path never does.
+ *
+ * It is written for clarity, not speed: full 6x6 matrices, plain loops, one
+ * candidate at a time.  The definitions it follows:
+ *   - helix in a uniform field B along +z, state (x, y, z, c=q/pT, phi, theta),
+ *     transverse arc length s, curvature h = dphi/ds = -kappa*B*c
+ *     (kappa = 0.00299792458 GeV/(T cm));
+ *   - propagation to the next layer (paper Sec. 3.1: layer-to-layer
+ *     propagation following the geometry description): barrel radius by a
+ *     bracketed Newton iteration, disk z in closed form;
+ *   - transport Jacobian including the path-length derivative (implicit
+ *     function theorem on the surface equation);
+ *   - multiple scattering at every crossed layer (paper Sec. 3.1: material
+ *     per layer) with the PDG Highland width;
+ *   - Kalman update with a 2D hit measured in the hit's local frame,
+ *     Joseph-form covariance (the traditional KF of the paper's Sec. 1);
+ *   - layer-by-layer combinatorial finding (paper Sec. 2 and Sec. 4: hit
+ *     search windows, chi2 selection, candidate scoring, bounded candidate
+ *     count per seed).
+ */
+#include "kf_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KAPPA 0.00299792458
+#define NEXT_BARREL_EPS 0.05      /* cm: a barrel is "ahead" if r > rho + eps */
+#define DISK_AHEAD_EPS 0.05       /* cm: a disk is "ahead" if |dz| > eps in the travel direction */
+#define WIN_REL 1.001             /* window = chi2-ellipse bounding box, 1e-3 relative margin */
+#define WIN_ABS 1e-4              /* plus an absolute margin (rad or cm) */
+#define CLOSE_REL 1e-3            /* relative margin below which a decision counts as a tie */
+#define NO_HIT 0x7fffffff
+#define MAXL 64
+
+static const double PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                        */
+
+static int pidx(int i, int j)
+{
+    if (i > j) { int t = i; i = j; j = t; }
+    return i * (11 - i) / 2 + j;
+}
+
+static void unpack(const double* Pk, double P[6][6])
+{
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) P[i][j] = Pk[pidx(i, j)];
+}
+
+static void pack(double P[6][6], double* Pk)
+{
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) Pk[pidx(i, j)] = 0.5 * (P[i][j] + P[j][i]);
+}
+
+static double wrap_pi(double a)
+{
+    /* to (-pi, pi] */
+    while (a > PI) a -= 2.0 * PI;
+    while (a <= -PI) a += 2.0 * PI;
+    return a;
+}
+
+/* sin(u)/u */
+static double sinc(double u)
+{
+    if (fabs(u) < 1e-4) return 1.0 - u * u / 6.0;
+    return sin(u) / u;
+}
+
+/* d/du [sin(u)/u] = (u cos u - sin u) / u^2 */
+static double dsinc(double u)
+{
+    if (fabs(u) < 0.05) {
+        double u2 = u * u;
+        return u * (-1.0 / 3.0 + u2 * (1.0 / 30.0 + u2 * (-1.0 / 840.0 + u2 / 45360.0)));
+    }
+    return (u * cos(u) - sin(u)) / (u * u);
+}
+
+/* C = A B for 6x6 */
+static void mul66(double A[6][6], double B[6][6], double C[6][6])
+{
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 6; ++k) acc += A[i][k] * B[k][j];
+            C[i][j] = acc;
+        }
+}
+
+/* C = A B^T for 6x6 */
+static void mul66t(double A[6][6], double B[6][6], double C[6][6])
+{
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 6; ++k) acc += A[i][k] * B[j][k];
+            C[i][j] = acc;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* helix                                                                */
+
+void orc_helix(const double p[6], double s, double bz, double out[6])
+{
+    double h = -KAPPA * bz * p[3];
+    double u = 0.5 * h * s;
+    double a = p[4] + u;
+    double sc = sinc(u);
+    out[0] = p[0] + s * cos(a) * sc;
+    out[1] = p[1] + s * sin(a) * sc;
+    out[2] = p[2] + s * cos(p[5]) / sin(p[5]);
+    out[3] = p[3];
+    out[4] = wrap_pi(p[4] + h * s);
+    out[5] = p[5];
+}
+
+/* ------------------------------------------------------------------ */
+/* propagation to a barrel radius: bracketed Newton on r(s) = r_l        */
+/*
+ * Bracket [s_lo, s_hi] = [0, s_apex]: from a start inside the cylinder,
+ * r(s) has exactly one outward crossing of r_l before the point of largest
+ * radius (the apex) when the layer is reachable (|C| + R >= r_l, C the centre
+ * of curvature, R the radius).  Newton steps that leave the bracket, or a
+ * non-positive slope, are replaced by bisection.  Convergence: |r - r_l| <
+ * tol, then one more Newton step.  Iterations count the evaluations of r(s).
+ */
+int orc_solve_barrel(const orc_cfg* cfg, const double p[6], double r_l, double s_init,
+                     double* s_out, int* iters_out)
+{
+    double h = -KAPPA * cfg->bz * p[3];
+    double cphi = cos(p[4]), sphi = sin(p[4]);
+    double s_lo = 0.0, s_hi = 1e30;
+    if (h != 0.0) {
+        double cx = p[0] - sphi / h, cy = p[1] + cphi / h;
+        double R = 1.0 / fabs(h);
+        double dc = hypot(cx, cy);
+        if (dc + R < r_l) {
+            if (iters_out) *iters_out = 0;
+            return ORC_ST_UNREACHABLE;
+        }
+        /* angle swept (in the direction of motion) from the current point to the apex */
+        double v0x = p[0] - cx, v0y = p[1] - cy;
+        double v1x = R * cx / dc, v1y = R * cy / dc;
+        double alpha = atan2(v0x * v1y - v0y * v1x, v0x * v1x + v0y * v1y);
+        double sw = fmod((h > 0 ? alpha : -alpha), 2.0 * PI);
+        if (sw < 0) sw += 2.0 * PI;
+        s_hi = sw / fabs(h);
+    }
+    double s;
+    if (s_init >= 0.0) {
+        s = s_init;
+    } else {
+        /* straight-line intersection of the tangent with the cylinder */
+        double pu = p[0] * cphi + p[1] * sphi;
+        double disc = pu * pu - (p[0] * p[0] + p[1] * p[1]) + r_l * r_l;
+        s = disc > 0.0 ? -pu + sqrt(disc) : -pu;
+    }
+    if (s < s_lo) s = s_lo;
+    if (s > s_hi) s = s_hi;
+    for (int it = 1; it <= cfg->max_newton; ++it) {
+        double q[6];
+        orc_helix(p, s, cfg->bz, q);
+        double r = hypot(q[0], q[1]);
+        double res = r - r_l;
+        double drds = (q[0] * cos(q[4]) + q[1] * sin(q[4])) / r;
+        if (res < 0.0) { if (s > s_lo) s_lo = s; }
+        else { if (s < s_hi) s_hi = s; }
+        if (fabs(res) < cfg->newton_tol) {
+            if (drds > 0.0) s -= res / drds;
+            *s_out = s;
+            if (iters_out) *iters_out = it;
+            return ORC_ST_OK;
+        }
+        double sn = s - res / drds;
+        if (!(drds > 0.0) || !(sn > s_lo && sn < s_hi)) sn = 0.5 * (s_lo + s_hi);
+        s = sn;
+    }
+    *s_out = s;
+    if (iters_out) *iters_out = cfg->max_newton;
+    return ORC_ST_NOCONV;
+}
+
+/* path length to a layer, no covariance */
+static int path_to_layer(const orc_cfg* cfg, int layer, const double p[6], double* s, int* iters)
+{
+    const orc_layer* L = &cfg->layers[layer];
+    if (L->kind == 0) return orc_solve_barrel(cfg, p, L->r_or_z, -1.0, s, iters);
+    double ct = cos(p[5]);
+    if (ct == 0.0) return ORC_ST_UNREACHABLE;
+    *s = (L->r_or_z - p[2]) * sin(p[5]) / ct;
+    if (iters) *iters = 1;
+    return *s >= 0.0 ? ORC_ST_OK : ORC_ST_UNREACHABLE;
+}
+
+/* ------------------------------------------------------------------ */
+/* transport Jacobian at path length s                                 */
+
+static void jacobian_at(const orc_cfg* cfg, const orc_layer* L, const double p[6], double s,
+                        double F[6][6])
+{
+    double kb = KAPPA * cfg->bz;
+    double h = -kb * p[3];
+    double u = 0.5 * h * s;
+    double a = p[4] + u;
+    double sc = sinc(u), dsc = dsinc(u);
+    double ca = cos(a), sa = sin(a);
+    double st = sin(p[5]), ct = cos(p[5]);
+    double q[6];
+    orc_helix(p, s, cfg->bz, q);
+
+    /* partial derivatives at fixed s */
+    double D[6][6];
+    memset(D, 0, sizeof(D));
+    for (int i = 0; i < 6; ++i) D[i][i] = 1.0;
+    D[0][4] = -s * sa * sc;
+    D[1][4] = s * ca * sc;
+    double dxdh = 0.5 * s * s * (ca * dsc - sa * sc);
+    double dydh = 0.5 * s * s * (sa * dsc + ca * sc);
+    D[0][3] = -kb * dxdh;
+    D[1][3] = -kb * dydh;
+    D[4][3] = -kb * s;
+    D[2][5] = -s / (st * st);
+
+    /* derivative of the helix with respect to s */
+    double phis = p[4] + h * s;
+    double fs[6] = {cos(phis), sin(phis), ct / st, 0.0, h, 0.0};
+
+    /* derivative of the path length with respect to the starting state */
+    double dsdp[6] = {0, 0, 0, 0, 0, 0};
+    if (L->kind == 0) {
+        double den = q[0] * fs[0] + q[1] * fs[1];
+        for (int j = 0; j < 6; ++j) dsdp[j] = -(q[0] * D[0][j] + q[1] * D[1][j]) / den;
+    } else {
+        dsdp[2] = -st / ct;
+        dsdp[5] = (L->r_or_z - p[2]) / (ct * ct);
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) F[i][j] = D[i][j] + fs[i] * dsdp[j];
+}
+
+int orc_jacobian(const orc_cfg* cfg, int layer, const double p[6], double Fo[36])
+{
+    double s;
+    int st = path_to_layer(cfg, layer, p, &s, NULL);
+    if (st) return st;
+    double F[6][6];
+    jacobian_at(cfg, &cfg->layers[layer], p, s, F);
+    memcpy(Fo, F, sizeof(F));
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* multiple-scattering process noise at a layer (PDG Highland formula)  */
+
+static void add_scatter(const orc_cfg* cfg, const orc_layer* L, const double q[6], double P[6][6])
+{
+    if (!(L->x0 > 0.0)) return;
+    double st = sin(q[5]), ct = cos(q[5]);
+    double cosa;
+    if (L->kind == 0) cosa = st * cos(q[4] - atan2(q[1], q[0]));
+    else cosa = ct;
+    cosa = fabs(cosa);
+    if (cosa < 1e-6) cosa = 1e-6;
+    double t = L->x0 / cosa;
+    double pmom = 1.0 / (fabs(q[3]) * st);
+    double beta = pmom / sqrt(pmom * pmom + cfg->mass * cfg->mass);
+    double th0 = 0.0136 / (beta * pmom) * sqrt(t) * (1.0 + 0.038 * log(t / (beta * beta)));
+    double t2 = th0 * th0;
+    double cot = ct / st;
+    P[4][4] += t2 / (st * st);
+    P[5][5] += t2;
+    P[3][5] += -q[3] * cot * t2;
+    P[5][3] += -q[3] * cot * t2;
+    P[3][3] += q[3] * q[3] * cot * cot * t2;
+}
+
+int orc_propagate(const orc_cfg* cfg, int layer, const double p[6], const double Pk[21],
+                  double p_out[6], double P_out[21], double* s_out, int* iters_out,
+                  int add_noise)
+{
+    double s;
+    int it = 0;
+    int st = path_to_layer(cfg, layer, p, &s, &it);
+    if (iters_out) *iters_out = it;
+    if (st) return st;
+    const orc_layer* L = &cfg->layers[layer];
+    double q[6], F[6][6], P[6][6], T[6][6], Pn[6][6];
+    orc_helix(p, s, cfg->bz, q);
+    jacobian_at(cfg, L, p, s, F);
+    unpack(Pk, P);
+    mul66(F, P, T);
+    mul66t(T, F, Pn);
+    if (add_noise) add_scatter(cfg, L, q, Pn);
+    memcpy(p_out, q, sizeof(q));
+    pack(Pn, P_out);
+    if (s_out) *s_out = s;
+    for (int i = 0; i < 6; ++i)
+        if (!isfinite(q[i])) return ORC_ST_NAN;
+    return ORC_ST_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* measurement model and update                                        */
+
+/* H (2x6) and residual r for a hit; local frame at the hit's azimuth:
+ * u along phi, v along z (barrel) or along r (disk). */
+static void measurement(const double p[6], const double hit[5], int kind, double H[2][6],
+                        double r[2])
+{
+    double rho = hypot(hit[0], hit[1]);
+    double c = hit[0] / rho, s = hit[1] / rho;
+    memset(H, 0, sizeof(double) * 12);
+    H[0][0] = -s;
+    H[0][1] = c;
+    r[0] = -s * (hit[0] - p[0]) + c * (hit[1] - p[1]);
+    if (kind == 0) {
+        H[1][2] = 1.0;
+        r[1] = hit[2] - p[2];
+    } else {
+        H[1][0] = c;
+        H[1][1] = s;
+        r[1] = c * (hit[0] - p[0]) + s * (hit[1] - p[1]);
+    }
+}
+
+/* S = H P H^T + V and its inverse; returns 0 when S is not positive definite */
+static int innovation(double P[6][6], double H[2][6], const double hit[5], double S[2][2],
+                      double Si[2][2])
+{
+    double HP[2][6];
+    for (int a = 0; a < 2; ++a)
+        for (int j = 0; j < 6; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 6; ++k) acc += H[a][k] * P[k][j];
+            HP[a][j] = acc;
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double acc = 0.0;
+            for (int k = 0; k < 6; ++k) acc += HP[a][k] * H[b][k];
+            S[a][b] = acc;
+        }
+    S[0][0] += hit[3] * hit[3];
+    S[1][1] += hit[4] * hit[4];
+    double det = S[0][0] * S[1][1] - S[0][1] * S[1][0];
+    if (!(det > 0.0) || !(S[0][0] > 0.0)) return 0;
+    Si[0][0] = S[1][1] / det;
+    Si[1][1] = S[0][0] / det;
+    Si[0][1] = -S[0][1] / det;
+    Si[1][0] = -S[1][0] / det;
+    return 1;
+}
+
+double orc_chi2(const double p[6], const double Pk[21], const double hit[5], int kind)
+{
+    double P[6][6], H[2][6], r[2], S[2][2], Si[2][2];
+    unpack(Pk, P);
+    measurement(p, hit, kind, H, r);
+    if (!innovation(P, H, hit, S, Si)) return INFINITY;
+    return r[0] * (Si[0][0] * r[0] + Si[0][1] * r[1]) + r[1] * (Si[1][0] * r[0] + Si[1][1] * r[1]);
+}
+
+int orc_update(const double p[6], const double Pk[21], const double hit[5], int kind,
+               double p_out[6], double P_out[21], double* chi2_out)
+{
+    double P[6][6], H[2][6], r[2], S[2][2], Si[2][2];
+    unpack(Pk, P);
+    measurement(p, hit, kind, H, r);
+    if (!innovation(P, H, hit, S, Si)) return ORC_ST_NONPD;
+    double chi2 = r[0] * (Si[0][0] * r[0] + Si[0][1] * r[1]) +
+                  r[1] * (Si[1][0] * r[0] + Si[1][1] * r[1]);
+    /* gain K = P H^T S^-1 */
+    double PHt[6][2], K[6][2];
+    for (int i = 0; i < 6; ++i)
+        for (int a = 0; a < 2; ++a) {
+            double acc = 0.0;
+            for (int k = 0; k < 6; ++k) acc += P[i][k] * H[a][k];
+            PHt[i][a] = acc;
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int a = 0; a < 2; ++a) K[i][a] = PHt[i][0] * Si[0][a] + PHt[i][1] * Si[1][a];
+    for (int i = 0; i < 6; ++i) p_out[i] = p[i] + K[i][0] * r[0] + K[i][1] * r[1];
+    p_out[4] = wrap_pi(p_out[4]);
+    /* Joseph form: (I - K H) P (I - K H)^T + K V K^T */
+    double A[6][6], T[6][6], Pn[6][6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j)
+            A[i][j] = (i == j ? 1.0 : 0.0) - (K[i][0] * H[0][j] + K[i][1] * H[1][j]);
+    mul66(A, P, T);
+    mul66t(T, A, Pn);
+    double v0 = hit[3] * hit[3], v1 = hit[4] * hit[4];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) Pn[i][j] += K[i][0] * v0 * K[j][0] + K[i][1] * v1 * K[j][1];
+    pack(Pn, P_out);
+    if (chi2_out) *chi2_out = chi2;
+    for (int i = 0; i < 6; ++i)
+        if (!isfinite(p_out[i])) return ORC_ST_NAN;
+    return ORC_ST_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* seed from three hits                                                 */
+/*
+ * Signed curvature of the circle through the three transverse points
+ * (Menger curvature, sign = sense of rotation 1 -> 2 -> 3), tangent
+ * direction at hit 1 = chord 1->3 direction minus half the turning angle,
+ * cot(theta) = dz / arc length between hits 1 and 3, position = hit 1.
+ * Prior covariance: diag(1, 1, 1, 4, 0.01, 0.01) (cm^2, GeV^-2, rad^2).
+ */
+void orc_seed(const double h1[3], const double h2[3], const double h3[3], double bz,
+              double p_out[6], double P_out[21])
+{
+    double ax = h2[0] - h1[0], ay = h2[1] - h1[1];
+    double bx = h3[0] - h1[0], by = h3[1] - h1[1];
+    double d12 = hypot(ax, ay);
+    double d13 = hypot(bx, by);
+    double d23 = hypot(h3[0] - h2[0], h3[1] - h2[1]);
+    double cross = ax * by - ay * bx;
+    double h = 2.0 * cross / (d12 * d23 * d13);
+    double w = 0.5 * h * d13;
+    if (w > 1.0) w = 1.0;
+    if (w < -1.0) w = -1.0;
+    double s13 = fabs(w) < 1e-8 ? d13 : d13 * asin(w) / w;
+    double phi = atan2(by, bx) - 0.5 * h * s13;
+    p_out[0] = h1[0];
+    p_out[1] = h1[1];
+    p_out[2] = h1[2];
+    p_out[3] = -h / (KAPPA * bz);
+    p_out[4] = wrap_pi(phi);
+    p_out[5] = atan2(s13, h3[2] - h1[2]);
+    double P[6][6];
+    memset(P, 0, sizeof(P));
+    P[0][0] = P[1][1] = P[2][2] = 1.0;
+    P[3][3] = 4.0;
+    P[4][4] = P[5][5] = 0.01;
+    pack(P, P_out);
+}
+
+/* ------------------------------------------------------------------ */
+/* fit                                                                 */
+
+typedef struct {
+    const orc_cfg* cfg;
+    long lo, hi;
+    int max_steps;
+    const double *hx, *hy, *hz, *hsu, *hsv;
+    const int *layer_seq, *hit_idx;
+    double *par, *cov, *chi2;
+    int *ndf, *status;
+} fit_job;
+
+static void fit_one(const fit_job* J, long t)
+{
+    const orc_cfg* cfg = J->cfg;
+    double p[6], Pk[21], chi2 = 0.0;
+    memcpy(p, J->par + 6 * t, sizeof(p));
+    memcpy(Pk, J->cov + 21 * t, sizeof(Pk));
+    int nh = 0, st = 0;
+    for (int k = 0; k < J->max_steps; ++k) {
+        int layer = J->layer_seq[(long)t * J->max_steps + k];
+        if (layer < 0) break;
+        double q[6], Q[21];
+        st |= orc_propagate(cfg, layer, p, Pk, q, Q, NULL, NULL, cfg->use_material);
+        if (st) break;
+        memcpy(p, q, sizeof(p));
+        memcpy(Pk, Q, sizeof(Pk));
+        int hi = J->hit_idx[(long)t * J->max_steps + k];
+        if (hi >= 0) {
+            double hit[5] = {J->hx[hi], J->hy[hi], J->hz[hi], J->hsu[hi], J->hsv[hi]};
+            double c2;
+            st |= orc_update(p, Pk, hit, cfg->layers[layer].kind, q, Q, &c2);
+            if (st) break;
+            memcpy(p, q, sizeof(p));
+            memcpy(Pk, Q, sizeof(Pk));
+            chi2 += c2;
+            nh++;
+        }
+    }
+    memcpy(J->par + 6 * t, p, sizeof(p));
+    memcpy(J->cov + 21 * t, Pk, sizeof(Pk));
+    J->chi2[t] = chi2;
+    J->ndf[t] = 2 * nh - 5;
+    J->status[t] = st;
+}
+
+static void* fit_worker(void* arg)
+{
+    fit_job* J = (fit_job*)arg;
+    for (long t = J->lo; t < J->hi; ++t) fit_one(J, t);
+    return NULL;
+}
+
+void orc_fit(const orc_cfg* cfg, long n, int max_steps,
+             const double* hx, const double* hy, const double* hz,
+             const double* hsu, const double* hsv,
+             const int* layer_seq, const int* hit_idx,
+             double* par_io, double* cov_io, double* chi2_out, int* ndf_out,
+             int* status_out, int n_threads)
+{
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    fit_job jobs[256];
+    pthread_t th[256];
+    for (int i = 0; i < n_threads; ++i) {
+        fit_job J = {cfg, n * i / n_threads, n * (i + 1) / n_threads, max_steps,
+                     hx, hy, hz, hsu, hsv, layer_seq, hit_idx,
+                     par_io, cov_io, chi2_out, ndf_out, status_out};
+        jobs[i] = J;
+    }
+    if (n_threads == 1) { fit_worker(&jobs[0]); return; }
+    for (int i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, fit_worker, &jobs[i]);
+    for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+}
+
+/* ------------------------------------------------------------------ */
+/* combinatorial finding                                                */
+
+typedef struct {
+    double p[6], P[21];
+    double chi2;
+    int nhits, misses, done, status;
+    int hits[MAXL];
+} cand_t;
+
+typedef struct {
+    int parent;      /* slot of the parent candidate */
+    int hit;         /* original hit index, NO_HIT for the no-hit / frozen child */
+    double chi2_hit;
+    double chi2_tot;
+    int nhits;
+} child_t;
+
+typedef struct {
+    /* hits of one event */
+    long n_hits;
+    const double *hx, *hy, *hz, *hsu, *hsv;
+    const int* hlayer;
+    /* per-layer hit lists (all-hits scan) and bins (binned scan) */
+    long* layer_off;     /* [n_layers+1] into layer_hits */
+    long* layer_hits;
+    long** bin_off;      /* per layer: [nbin_phi*nbin_2 + 1] into bin_hits[layer] */
+    long** bin_hits;
+} event_index;
+
+static int hit_phi_bin(double phi, int nb)
+{
+    int b = (int)floor((phi + PI) * nb / (2.0 * PI));
+    if (b < 0) b = 0;
+    if (b > nb - 1) b = nb - 1;
+    return b;
+}
+
+static int coord_bin(double v, double lo, double hi, int nb)
+{
+    double t = floor((v - lo) * nb / (hi - lo));
+    if (t < 0) t = 0;
+    if (t > nb - 1) t = nb - 1;
+    return (int)t;
+}
+
+static double hit_coord2(const event_index* E, const orc_layer* L, long i)
+{
+    return L->kind == 0 ? E->hz[i] : hypot(E->hx[i], E->hy[i]);
+}
+
+static void build_index(const orc_cfg* cfg, event_index* E)
+{
+    int nl = cfg->n_layers;
+    E->layer_off = (long*)calloc((size_t)(nl > 0 ? nl : 0) + 1, sizeof(long));
+    E->layer_hits = (long*)malloc(sizeof(long) * (E->n_hits > 0 ? E->n_hits : 1));
+    for (long i = 0; i < E->n_hits; ++i) E->layer_off[E->hlayer[i] + 1]++;
+    for (int l = 0; l < nl; ++l) E->layer_off[l + 1] += E->layer_off[l];
+    long* fill = (long*)calloc((size_t)(nl > 0 ? nl : 1), sizeof(long));
+    for (long i = 0; i < E->n_hits; ++i) {
+        int l = E->hlayer[i];
+        E->layer_hits[E->layer_off[l] + fill[l]++] = i;
+    }
+    free(fill);
+    E->bin_off = (long**)calloc((size_t)(nl > 0 ? nl : 1), sizeof(long*));
+    E->bin_hits = (long**)calloc((size_t)(nl > 0 ? nl : 1), sizeof(long*));
+    for (int l = 0; l < nl; ++l) {
+        const orc_layer* L = &cfg->layers[l];
+        int nb = L->nbin_phi * L->nbin_2;
+        long n = E->layer_off[l + 1] - E->layer_off[l];
+        long* off = (long*)calloc((size_t)(nb > 0 ? nb : 0) + 1, sizeof(long));
+        long* hits = (long*)malloc(sizeof(long) * (n > 0 ? n : 1));
+        int* bin_of = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+        for (long k = 0; k < n; ++k) {
+            long i = E->layer_hits[E->layer_off[l] + k];
+            int bp = hit_phi_bin(atan2(E->hy[i], E->hx[i]), L->nbin_phi);
+            int bv = coord_bin(hit_coord2(E, L, i), L->lo, L->hi, L->nbin_2);
+            bin_of[k] = bp * L->nbin_2 + bv;
+            off[bin_of[k] + 1]++;
+        }
+        for (int b = 0; b < nb; ++b) off[b + 1] += off[b];
+        long* f2 = (long*)calloc((size_t)(nb > 0 ? nb : 1), sizeof(long));
+        for (long k = 0; k < n; ++k) {
+            int b = bin_of[k];
+            hits[off[b] + f2[b]++] = E->layer_hits[E->layer_off[l] + k];
+        }
+        free(f2);
+        free(bin_of);
+        E->bin_off[l] = off;
+        E->bin_hits[l] = hits;
+    }
+}
+
+static void free_index(const orc_cfg* cfg, event_index* E)
+{
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        free(E->bin_off[l]);
+        free(E->bin_hits[l]);
+    }
+    free(E->bin_off);
+    free(E->bin_hits);
+    free(E->layer_off);
+    free(E->layer_hits);
+}
+
+/*
+ * Next surface (dynamic navigation): the candidate moves to whichever is
+ * reached first along the helix, the next barrel outward (smallest radius
+ * above the current one, reachable, crossing inside its z extent) or the
+ * first disk ahead in z whose crossing lies inside its radial extent.
+ * Returns the layer or -1 (no surface left); *stat gets NOCONV if the
+ * barrel solve failed.  *close is set when a decision had a relative
+ * margin below 1e-3.
+ */
+static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close)
+{
+    double rho = hypot(p[0], p[1]);
+    double best_s = INFINITY;
+    int best_l = -1;
+    int bl = -1;
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        const orc_layer* L = &cfg->layers[l];
+        if (L->kind != 0) continue;
+        if (L->r_or_z > rho + NEXT_BARREL_EPS && (bl < 0 || L->r_or_z < cfg->layers[bl].r_or_z))
+            bl = l;
+    }
+    double s_b = INFINITY;
+    if (bl >= 0) {
+        const orc_layer* L = &cfg->layers[bl];
+        double h = -KAPPA * cfg->bz * p[3];
+        if (h != 0.0) {
+            double cx = p[0] - sin(p[4]) / h, cy = p[1] + cos(p[4]) / h;
+            double rmax = hypot(cx, cy) + 1.0 / fabs(h);
+            if (fabs(rmax - L->r_or_z) < CLOSE_REL * L->r_or_z) *close = 1;
+        }
+        double s;
+        int st = orc_solve_barrel(cfg, p, L->r_or_z, -1.0, &s, NULL);
+        if (st == ORC_ST_NOCONV) {
+            *stat |= ORC_ST_NOCONV;
+            return -1;
+        }
+        if (st == ORC_ST_OK) {
+            double zc = p[2] + s * cos(p[5]) / sin(p[5]);
+            if (fabs(fabs(zc) - L->hi) < CLOSE_REL * L->hi) *close = 1;
+            if (fabs(zc) <= L->hi) {
+                best_s = s_b = s;
+                best_l = bl;
+            }
+        }
+    }
+    double cot = cos(p[5]) / sin(p[5]);
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        const orc_layer* L = &cfg->layers[l];
+        if (L->kind != 1) continue;
+        double dz = L->r_or_z - p[2];
+        if (!(dz * cot > 0.0) || fabs(dz) <= DISK_AHEAD_EPS) continue;
+        double s = dz / cot;
+        double q[6];
+        orc_helix(p, s, cfg->bz, q);
+        double r = hypot(q[0], q[1]);
+        if (fabs(r - L->lo) < CLOSE_REL * L->lo || fabs(r - L->hi) < CLOSE_REL * L->hi) *close = 1;
+        if (r < L->lo || r > L->hi) continue;
+        if (isfinite(s_b) && fabs(s - s_b) < CLOSE_REL * (s > s_b ? s : s_b)) *close = 1;
+        if (s < best_s) {
+            best_s = s;
+            best_l = l;
+        }
+    }
+    return best_l;
+}
+
+/* hits inside the window of a predicted state; returns count, writes (chi2, idx)
+ * of the accepted ones.  *close set when a tested hit's chi2 is within 1e-3
+ * relative of the cut. */
+typedef struct {
+    double chi2;
+    long idx;
+} hitsel_t;
+
+static int cmp_hitsel(const void* a, const void* b)
+{
+    const hitsel_t* x = (const hitsel_t*)a;
+    const hitsel_t* y = (const hitsel_t*)b;
+    if (x->chi2 < y->chi2) return -1;
+    if (x->chi2 > y->chi2) return 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+typedef struct {
+    double cos_dphi;   /* azimuthal half-width as a cosine; <= -1 means all */
+    double dphi;
+    double wv;         /* half-width along z (barrel) / r (disk) */
+    double vlo, vhi;   /* bin-enumeration range along the second coordinate */
+} window_t;
+
+static void make_window(const orc_cfg* cfg, const orc_layer* L, const double q[6],
+                        const double Pk[21], window_t* W)
+{
+    double cut = cfg->chi2_cut;
+    double pxx = Pk[pidx(0, 0)], pyy = Pk[pidx(1, 1)], pzz = Pk[pidx(2, 2)];
+    double rho = hypot(q[0], q[1]);
+    double wu = sqrt(cut * (pxx + pyy + L->win_su * L->win_su));
+    double t = WIN_REL * wu / rho;
+    double dphi = t >= 1.0 ? PI : asin(t) + WIN_ABS;
+    if (dphi > 0.5 * PI) dphi = PI;
+    W->dphi = dphi;
+    W->cos_dphi = dphi >= PI ? -2.0 : cos(dphi);
+    if (L->kind == 0) {
+        W->wv = WIN_REL * sqrt(cut * (pzz + L->win_sv * L->win_sv)) + WIN_ABS;
+        W->vlo = q[2] - W->wv;
+        W->vhi = q[2] + W->wv;
+    } else {
+        W->wv = WIN_REL * sqrt(cut * (pxx + pyy + L->win_sv * L->win_sv)) + WIN_ABS;
+        W->vlo = rho * (dphi >= PI ? -1.0 : cos(dphi)) - W->wv;
+        W->vhi = rho + W->wv;
+    }
+}
+
+/* test one hit: window predicate and chi2 cut */
+static int test_hit(const orc_cfg* cfg, const orc_layer* L, const event_index* E, long i,
+                    const double q[6], const double Pk[21], const window_t* W, double* chi2,
+                    int* close)
+{
+    double rho = hypot(q[0], q[1]);
+    double rh = hypot(E->hx[i], E->hy[i]);
+    if (W->cos_dphi > -1.5) {
+        double cd = (E->hx[i] * q[0] + E->hy[i] * q[1]) / (rh * rho);
+        if (cd < W->cos_dphi) return 0;
+    }
+    double hit[5] = {E->hx[i], E->hy[i], E->hz[i], E->hsu[i], E->hsv[i]};
+    double H[2][6], r[2];
+    measurement(q, hit, L->kind, H, r);
+    if (fabs(r[1]) > W->wv) return 0;
+    double c2 = orc_chi2(q, Pk, hit, L->kind);
+    if (fabs(c2 - cfg->chi2_cut) < CLOSE_REL * cfg->chi2_cut) *close = 1;
+    if (!(c2 < cfg->chi2_cut)) return 0;
+    *chi2 = c2;
+    return 1;
+}
+
+static int scan_hits(const orc_cfg* cfg, int layer, const event_index* E, int binned,
+                     const double q[6], const double Pk[21], hitsel_t** buf, int* cap,
+                     int* close)
+{
+    const orc_layer* L = &cfg->layers[layer];
+    window_t W;
+    make_window(cfg, L, q, Pk, &W);
+    int n = 0;
+#define ACCEPT(I)                                                           \
+    do {                                                                    \
+        double c2_;                                                         \
+        if (test_hit(cfg, L, E, (I), q, Pk, &W, &c2_, close)) {              \
+            if (n == *cap) {                                                \
+                *cap *= 2;                                                  \
+                *buf = (hitsel_t*)realloc(*buf, sizeof(hitsel_t) * *cap);   \
+            }                                                               \
+            (*buf)[n].chi2 = c2_;                                           \
+            (*buf)[n].idx = (I);                                            \
+            n++;                                                            \
+        }                                                                   \
+    } while (0)
+    if (!binned) {
+        for (long k = E->layer_off[layer]; k < E->layer_off[layer + 1]; ++k) ACCEPT(E->layer_hits[k]);
+    } else {
+        int np = L->nbin_phi;
+        double phi = atan2(q[1], q[0]);
+        long b_lo, b_hi;
+        if (W.dphi >= PI) {
+            b_lo = 0;
+            b_hi = np - 1;
+        } else {
+            b_lo = (long)floor((phi - W.dphi + PI) * np / (2.0 * PI));
+            b_hi = (long)floor((phi + W.dphi + PI) * np / (2.0 * PI));
+            if (b_hi - b_lo + 1 >= np) {
+                b_lo = 0;
+                b_hi = np - 1;
+            }
+        }
+        int v_lo = coord_bin(W.vlo, L->lo, L->hi, L->nbin_2);
+        int v_hi = coord_bin(W.vhi, L->lo, L->hi, L->nbin_2);
+        for (long bb = b_lo; bb <= b_hi; ++bb) {
+            int bp = (int)(((bb % np) + np) % np);
+            for (int bv = v_lo; bv <= v_hi; ++bv) {
+                int b = bp * L->nbin_2 + bv;
+                for (long k = E->bin_off[layer][b]; k < E->bin_off[layer][b + 1]; ++k)
+                    ACCEPT(E->bin_hits[layer][k]);
+            }
+        }
+    }
+#undef ACCEPT
+    qsort(*buf, n, sizeof(hitsel_t), cmp_hitsel);
+    return n;
+}
+
+static int cmp_child(const child_t* a, const child_t* b)
+{
+    if (a->nhits != b->nhits) return a->nhits > b->nhits ? -1 : 1;
+    if (a->chi2_tot != b->chi2_tot) return a->chi2_tot < b->chi2_tot ? -1 : 1;
+    if (a->parent != b->parent) return a->parent < b->parent ? -1 : 1;
+    return (a->hit > b->hit) - (a->hit < b->hit);
+}
+
+static int cmp_child_q(const void* a, const void* b)
+{
+    return cmp_child((const child_t*)a, (const child_t*)b);
+}
+
+static int near_tie(double a, double b)
+{
+    double m = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+    if (m < 1.0) m = 1.0;
+    return fabs(a - b) <= CLOSE_REL * m;
+}
+
+typedef struct {
+    const orc_cfg* cfg;
+    const event_index* E;
+    long lo, hi;
+    const int* seed_hits;
+    int binned;
+    int* out_hits;
+    double *out_par, *out_cov, *out_chi2;
+    int *out_ndf, *out_status, *out_tie;
+    long counters[2];
+} find_job;
+
+static void find_seed(find_job* J, long sd)
+{
+    const orc_cfg* cfg = J->cfg;
+    const event_index* E = J->E;
+    int nl = cfg->n_layers;
+    int mc = cfg->max_cands;
+    int cap_c = mc > 0 ? mc : 1;
+    cand_t* cands = (cand_t*)malloc(sizeof(cand_t) * cap_c);
+    cand_t* next = (cand_t*)malloc(sizeof(cand_t) * cap_c);
+    int cap_ch = 64, cap_h = 64;
+    child_t* ch = (child_t*)malloc(sizeof(child_t) * cap_ch);
+    hitsel_t* hs = (hitsel_t*)malloc(sizeof(hitsel_t) * cap_h);
+    double (*pred_p)[6] = malloc(sizeof(double) * 6 * cap_c);
+    double (*pred_P)[21] = malloc(sizeof(double) * 21 * cap_c);
+    int* pred_layer = (int*)malloc(sizeof(int) * cap_c);
+    int tie = -1;
+
+    /* seed: 3-hit circle, then the KF over the three seed hits */
+    const int* sh = J->seed_hits + 3 * sd;
+    cand_t* c0 = &cands[0];
+    memset(c0, 0, sizeof(cand_t));
+    for (int l = 0; l < nl; ++l) c0->hits[l] = -1;
+    double a[3] = {E->hx[sh[0]], E->hy[sh[0]], E->hz[sh[0]]};
+    double b[3] = {E->hx[sh[1]], E->hy[sh[1]], E->hz[sh[1]]};
+    double c[3] = {E->hx[sh[2]], E->hy[sh[2]], E->hz[sh[2]]};
+    orc_seed(a, b, c, cfg->bz, c0->p, c0->P);
+    for (int k = 0; k < 3 && !c0->status; ++k) {
+        long hi = sh[k];
+        int layer = E->hlayer[hi];
+        double q[6], Q[21], c2;
+        c0->status |= orc_propagate(cfg, layer, c0->p, c0->P, q, Q, NULL, NULL, cfg->use_material);
+        if (c0->status) break;
+        double hit[5] = {E->hx[hi], E->hy[hi], E->hz[hi], E->hsu[hi], E->hsv[hi]};
+        c0->status |= orc_update(q, Q, hit, cfg->layers[layer].kind, c0->p, c0->P, &c2);
+        c0->chi2 += c2;
+        c0->nhits++;
+        c0->hits[layer] = (int)hi;
+    }
+    c0->done = c0->status != 0;
+    int nc = 1;
+
+    for (int step = 0; step < nl; ++step) {
+        int any = 0;
+        for (int k = 0; k < nc; ++k) any |= !cands[k].done;
+        if (!any) break;
+        int close = 0, nch = 0;
+        for (int k = 0; k < nc; ++k) {
+            cand_t* cd = &cands[k];
+            if (nch + cap_c + 2 > cap_ch) {
+                cap_ch = 2 * (nch + cap_c + 2);
+                ch = (child_t*)realloc(ch, sizeof(child_t) * cap_ch);
+            }
+            pred_layer[k] = -1;
+            if (!cd->done) {
+                int st = 0;
+                int layer = navigate(cfg, cd->p, &st, &close);
+                if (layer < 0) {
+                    cd->done = 1;
+                    cd->status |= st;
+                } else {
+                    J->counters[0]++;
+                    st = orc_propagate(cfg, layer, cd->p, cd->P, pred_p[k], pred_P[k], NULL, NULL,
+                                       cfg->use_material);
+                    if (st) {
+                        cd->done = 1;
+                        cd->status |= st;
+                    } else {
+                        pred_layer[k] = layer;
+                    }
+                }
+            }
+            if (pred_layer[k] < 0) {
+                child_t x = {k, NO_HIT, 0.0, cd->chi2, cd->nhits};
+                ch[nch++] = x;
+                continue;
+            }
+            int nh = scan_hits(cfg, pred_layer[k], E, J->binned, pred_p[k], pred_P[k], &hs, &cap_h,
+                               &close);
+            int keep = nh < mc ? nh : mc;
+            if (nh > mc && near_tie(hs[mc - 1].chi2, hs[mc].chi2)) close = 1;
+            if (nch + keep + 1 > cap_ch) {
+                cap_ch = 2 * (nch + keep + 1);
+                ch = (child_t*)realloc(ch, sizeof(child_t) * cap_ch);
+            }
+            for (int j = 0; j < keep; ++j) {
+                child_t x = {k, (int)hs[j].idx, hs[j].chi2, cd->chi2 + hs[j].chi2, cd->nhits + 1};
+                ch[nch++] = x;
+            }
+            child_t x = {k, NO_HIT, 0.0, cd->chi2, cd->nhits};
+            ch[nch++] = x;
+        }
+        qsort(ch, nch, sizeof(child_t), cmp_child_q);
+        int nk = nch < mc ? nch : mc;
+        /* only the kept/dropped boundary changes which candidates survive */
+        if (nch > nk && ch[nk - 1].nhits == ch[nk].nhits &&
+            near_tie(ch[nk - 1].chi2_tot, ch[nk].chi2_tot))
+            close = 1;
+        if (close && tie < 0) tie = step;
+        for (int j = 0; j < nk; ++j) {
+            const child_t* x = &ch[j];
+            const cand_t* par = &cands[x->parent];
+            cand_t* nx = &next[j];
+            *nx = *par;
+            int layer = pred_layer[x->parent];
+            if (layer < 0) continue;              /* frozen: carried unchanged */
+            if (x->hit != NO_HIT) {
+                double hit[5] = {E->hx[x->hit], E->hy[x->hit], E->hz[x->hit], E->hsu[x->hit],
+                                 E->hsv[x->hit]};
+                double c2;
+                int st = orc_update(pred_p[x->parent], pred_P[x->parent], hit,
+                                    cfg->layers[layer].kind, nx->p, nx->P, &c2);
+                J->counters[1]++;
+                nx->status |= st;
+                if (st) nx->done = 1;
+                nx->chi2 = x->chi2_tot;
+                nx->nhits = x->nhits;
+                nx->misses = 0;
+                nx->hits[layer] = x->hit;
+            } else {
+                memcpy(nx->p, pred_p[x->parent], sizeof(nx->p));
+                memcpy(nx->P, pred_P[x->parent], sizeof(nx->P));
+                nx->misses = par->misses + 1;
+                if (nx->misses > cfg->max_miss) nx->done = 1;
+            }
+        }
+        cand_t* t = cands;
+        cands = next;
+        next = t;
+        nc = nk;
+    }
+    /* the final choice between the two best candidates */
+    if (nc > 1 && cands[0].nhits == cands[1].nhits && near_tie(cands[0].chi2, cands[1].chi2) &&
+        tie < 0)
+        tie = nl;
+    const cand_t* best = &cands[0];
+    for (int l = 0; l < nl; ++l) J->out_hits[sd * nl + l] = best->hits[l];
+    memcpy(J->out_par + 6 * sd, best->p, sizeof(best->p));
+    memcpy(J->out_cov + 21 * sd, best->P, sizeof(best->P));
+    J->out_chi2[sd] = best->chi2;
+    J->out_ndf[sd] = 2 * best->nhits - 5;
+    J->out_status[sd] = best->status;
+    J->out_tie[sd] = tie;
+    free(cands);
+    free(next);
+    free(ch);
+    free(hs);
+    free(pred_p);
+    free(pred_P);
+    free(pred_layer);
+}
+
+static void* find_worker(void* arg)
+{
+    find_job* J = (find_job*)arg;
+    for (long s = J->lo; s < J->hi; ++s) find_seed(J, s);
+    return NULL;
+}
+
+void orc_find(const orc_cfg* cfg, long n_hits,
+              const double* hx, const double* hy, const double* hz,
+              const double* hsu, const double* hsv, const int* hlayer,
+              long n_seeds, const int* seed_hits, int binned,
+              int* out_hits, double* out_par, double* out_cov, double* out_chi2,
+              int* out_ndf, int* out_status, int* out_tie_step, long* counters,
+              int n_threads)
+{
+    event_index E;
+    memset(&E, 0, sizeof(E));
+    E.n_hits = n_hits;
+    E.hx = hx; E.hy = hy; E.hz = hz; E.hsu = hsu; E.hsv = hsv; E.hlayer = hlayer;
+    build_index(cfg, &E);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    find_job* jobs = (find_job*)calloc(n_threads, sizeof(find_job));
+    pthread_t th[256];
+    for (int i = 0; i < n_threads; ++i) {
+        find_job J = {cfg, &E, n_seeds * i / n_threads, n_seeds * (i + 1) / n_threads,
+                      seed_hits, binned, out_hits, out_par, out_cov, out_chi2, out_ndf,
+                      out_status, out_tie_step, {0, 0}};
+        jobs[i] = J;
+    }
+    if (n_threads == 1) find_worker(&jobs[0]);
+    else {
+        for (int i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, find_worker, &jobs[i]);
+        for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+    }
+    counters[0] = counters[1] = 0;
+    for (int i = 0; i < n_threads; ++i) {
+        counters[0] += jobs[i].counters[0];
+        counters[1] += jobs[i].counters[1];
+    }
+    free(jobs);
+    free_index(cfg, &E);
+}
