@@ -1,0 +1,147 @@
+/*
+ * kf.h - C ABI of libkfmi.so, the MI355X (gfx950) Kalman-filter track fit and
+ * combinatorial track finding library.
+ *
+ * Method: the parallelised Kalman-filter tracking of arXiv:1906.02253
+ * (Sec. 2: vectorised KF fit and KF-based finding over many small matrices at
+ * once; Sec. 3.1: geometry as a vector of per-layer descriptions, layer-to-
+ * layer propagation, material per layer, constant field; Sec. 3.2: hits and
+ * seeds provided by the caller, found tracks handed back; Sec. 4: chi2-based
+ * hit selection inside search windows, candidate scoring).
+ *
+ * Conventions shared by every entry point
+ *   Units: cm, GeV, Tesla, radians.  Field along +z.
+ *   State p = (x, y, z, c = q/pT, phi, theta) at a point on the track.
+ *   Covariance: symmetric 6x6 stored as the packed upper triangle,
+ *   index(i <= j) = i*(11-i)/2 + j, 21 entries.
+ *   Track arrays are structure-of-arrays with leading dimension ld (elements):
+ *   element k of track i is at [k*ld + i]; ld is a multiple of 64 and >= n.
+ *   All array pointers are DEVICE pointers unless marked "host".  The caller
+ *   owns every array; the library never frees caller memory.  A context owns
+ *   its device workspace (allocated on first use of a given size, reused).
+ *   Calls are asynchronous on `stream` (a hipStream_t passed as void*, NULL =
+ *   the null stream); the caller synchronises before reading results.
+ *   Return value: KF_OK, or a negative kf_status for invalid arguments or a
+ *   HIP error (see kf_last_error).  Numerical trouble is never an error: it is
+ *   reported per track in `status` bits and the track is frozen from there on.
+ *   A context must not be used from two host threads at once.
+ */
+#ifndef KFMI_KF_H
+#define KFMI_KF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kf_ctx kf_ctx;
+
+enum kf_status {
+    KF_OK = 0,
+    KF_EINVAL = -1,        /* bad argument */
+    KF_EHIP = -2,          /* HIP runtime error (launch, copy, allocation) */
+    KF_ENOMEM = -3,        /* workspace allocation failed */
+    KF_EUNSUPPORTED = -4   /* valid but not supported by this build */
+};
+
+/* per-track status bits */
+enum {
+    KF_ST_OK = 0,
+    KF_ST_UNREACHABLE = 1, /* target surface not reachable (looper / behind) */
+    KF_ST_NOCONV = 2,      /* propagate-to-radius did not converge */
+    KF_ST_FALLBACK = 4,    /* learned initial guess rejected, exact solve used */
+    KF_ST_NONPD = 8,       /* innovation matrix not positive definite */
+    KF_ST_NAN = 16,        /* non-finite state */
+    KF_ST_BADINPUT = 32    /* out-of-range layer or hit index in the caller's arrays */
+};
+
+/* flags */
+enum {
+    KF_PREC_MIXED = 0,     /* FP32 storage and transport; update (S, S^-1, gain, Joseph) in FP64 */
+    KF_PREC_FP32 = 1,      /* everything FP32 (Joseph form kept) */
+    KF_PREC_FP64 = 2,      /* everything FP64, track arrays hold doubles */
+    KF_PREC_MASK = 3,
+    KF_INIT_MLP = 4,       /* start propagate-to-radius from the learned path-length guess */
+    KF_NO_MATERIAL = 8,    /* ignore the layers' material (no process noise) */
+    KF_PER_LAYER = 16      /* kf_fit: one launch per step, state through HBM between steps */
+};
+
+/* One detector layer (paper Sec. 3.1, the per-layer geometry record). */
+typedef struct {
+    int32_t kind;          /* 0 = barrel cylinder, 1 = disk */
+    float r_or_z;          /* barrel radius / disk z */
+    float lo, hi;          /* barrel: z extent [lo, hi]; disk: radial extent */
+    float x0;              /* material thickness in radiation lengths */
+    int32_t nbin_phi;      /* hit bins in phi over [-pi, pi) */
+    int32_t nbin_2;        /* hit bins in z (barrel) / r (disk) over [lo, hi] */
+    float win_su, win_sv;  /* largest hit sigma (u, v) on the layer, sizes the search window */
+} kf_layer;
+
+typedef struct {
+    float bz;              /* field [T] */
+    float chi2_cut;        /* hit acceptance chi2 (2 dof) */
+    int32_t max_cands;     /* candidates kept per seed, 1..8 */
+    int32_t max_newton;    /* propagate-to-radius iteration limit */
+    float newton_tol;      /* |r - r_layer| convergence threshold [cm] */
+    float mass;            /* particle mass for the scattering width [GeV] */
+    int32_t max_miss;      /* consecutive missed layers allowed */
+    int32_t mlp_max_iter;  /* iterations allowed from the learned guess before fallback */
+} kf_params;
+
+/* Track states, SoA with leading dimension ld.  par [6][ld], cov [21][ld],
+ * chi2 [ld] are float, or double with KF_PREC_FP64.  ndf = 2*hits - 5. */
+typedef struct {
+    int64_t n, ld;
+    void* par;
+    void* cov;
+    void* chi2;
+    int32_t* ndf;
+    uint32_t* status;
+} kf_tracks;
+
+/* Hits, SoA float32 (paper Sec. 3.2: provided externally). */
+typedef struct {
+    int64_t n;
+    const float *x, *y, *z;   /* global position */
+    const float *su, *sv;     /* sigma along r*phi and along z (barrel) / r (disk) */
+    const int32_t* layer;     /* layer index of each hit */
+} kf_hits;
+
+/* Create a context.  layers: host array of n_layers (<= 64) records, copied.
+ * params: host, copied; NULL = defaults (3.8 T, chi2 30, 6 candidates, 10
+ * Newton iterations, 1e-4 cm, pion mass, 2 misses, 3 learned iterations). */
+int kf_create(kf_ctx** ctx, const kf_layer* layers, int32_t n_layers, const kf_params* params);
+void kf_destroy(kf_ctx* ctx);
+/* Text of the last error on this context (valid until the next call). */
+const char* kf_last_error(const kf_ctx* ctx);
+/* Library-wide last error for failures without a context (kf_create). */
+const char* kf_last_error_global(void);
+
+/* Seed states from three hits per track (paper Sec. 3.2: seeds): circle
+ * through the transverse positions, tangent at hit 1, dip from the arc, prior
+ * covariance diag(1, 1, 1, 4, 0.01, 0.01).  seed_hits [3][ld] int32 hit
+ * indices.  Writes par, cov; chi2 = 0, ndf = -5, status = 0. */
+int kf_seed(kf_ctx* ctx, const kf_hits* hits, const int32_t* seed_hits, kf_tracks* out,
+            int flags, void* stream);
+
+/* Propagate every track to its target layer (target_layer [ld] int32, -1 =
+ * leave unchanged): helix transport, transport Jacobian with the path-length
+ * derivative, F P F^T plus the layer's scattering noise (unless
+ * KF_NO_MATERIAL).  Optional outputs (NULL to skip): path_len [ld] float
+ * transverse arc length, iters [ld] int32 evaluations of r(s). */
+int kf_propagate(kf_ctx* ctx, kf_tracks* t, const int32_t* target_layer, float* path_len,
+                 int32_t* iters, int flags, void* stream);
+
+/* Kalman fit (paper Sec. 2: KF track fitting).  In: t holds the starting
+ * state (e.g. from kf_seed).  Steps: layer_seq [max_steps][ld] (NULL = step k
+ * targets layer k; -1 ends the track) and hit_idx [max_steps][ld] (-1 = no
+ * hit at that step).  For each step: propagate, add the layer's noise,
+ * update with the hit.  Out: fitted state at the last step, chi2, ndf, status. */
+int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_seq,
+           const int32_t* hit_idx, int32_t max_steps, int flags, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,189 @@
+"""ctypes binding of libkfmi.so over torch device tensors.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libkfmi.so.  If the library is missing the import of this module raises; there
+is no fallback implementation.
+"""
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkfmi.so")
+
+KF_OK, KF_EINVAL, KF_EHIP, KF_ENOMEM, KF_EUNSUPPORTED = 0, -1, -2, -3, -4
+ST_OK, ST_UNREACHABLE, ST_NOCONV, ST_FALLBACK, ST_NONPD, ST_NAN, ST_BADINPUT = 0, 1, 2, 4, 8, 16, 32
+PREC_MIXED, PREC_FP32, PREC_FP64 = 0, 1, 2
+INIT_MLP, NO_MATERIAL, PER_LAYER = 4, 8, 16
+
+EXPORTED = ("kf_create", "kf_destroy", "kf_last_error", "kf_last_error_global", "kf_seed",
+            "kf_propagate", "kf_fit", "kf_find", "kf_find_batched", "kf_autotune",
+            "kf_mlp_load", "kf_mlp_train", "kf_mlp_forward", "kf_mlp_backward",
+            "kf_mlp_adam", "kf_mlp_features", "kf_find_workspace_bytes")
+
+
+class KfLayer(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("r_or_z", C.c_float), ("lo", C.c_float), ("hi", C.c_float),
+                ("x0", C.c_float), ("nbin_phi", C.c_int32), ("nbin_2", C.c_int32),
+                ("win_su", C.c_float), ("win_sv", C.c_float)]
+
+
+class KfParams(C.Structure):
+    _fields_ = [("bz", C.c_float), ("chi2_cut", C.c_float), ("max_cands", C.c_int32),
+                ("max_newton", C.c_int32), ("newton_tol", C.c_float), ("mass", C.c_float),
+                ("max_miss", C.c_int32), ("mlp_max_iter", C.c_int32)]
+
+
+class KfTracks(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ld", C.c_int64), ("par", C.c_void_p), ("cov", C.c_void_p),
+                ("chi2", C.c_void_p), ("ndf", C.c_void_p), ("status", C.c_void_p)]
+
+
+class KfHits(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("su", C.c_void_p), ("sv", C.c_void_p), ("layer", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build()); "
+                           "there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.kf_create.argtypes = [C.POINTER(vp), C.POINTER(KfLayer), i32, C.POINTER(KfParams)]
+    L.kf_create.restype = C.c_int
+    L.kf_destroy.argtypes = [vp]
+    L.kf_last_error.argtypes = [vp]
+    L.kf_last_error.restype = C.c_char_p
+    L.kf_last_error_global.restype = C.c_char_p
+    L.kf_seed.argtypes = [vp, C.POINTER(KfHits), vp, C.POINTER(KfTracks), C.c_int, vp]
+    L.kf_propagate.argtypes = [vp, C.POINTER(KfTracks), vp, vp, vp, C.c_int, vp]
+    L.kf_fit.argtypes = [vp, C.POINTER(KfTracks), C.POINTER(KfHits), vp, vp, i32, C.c_int, vp]
+    for f in ("kf_seed", "kf_propagate", "kf_fit"):
+        getattr(L, f).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def round_ld(n):
+    return max(64, (n + 63) // 64 * 64)
+
+
+class Tracks:
+    """SoA track states on the GPU: par [6, ld], cov [21, ld], chi2 [ld], ndf, status."""
+
+    def __init__(self, n, ld=None, dtype=torch.float32, device="cuda"):
+        self.n = int(n)
+        self.ld = int(ld or round_ld(n))
+        self.dtype = dtype
+        self.par = torch.zeros((6, self.ld), dtype=dtype, device=device)
+        self.cov = torch.zeros((21, self.ld), dtype=dtype, device=device)
+        self.chi2 = torch.zeros(self.ld, dtype=dtype, device=device)
+        self.ndf = torch.zeros(self.ld, dtype=torch.int32, device=device)
+        self.status = torch.zeros(self.ld, dtype=torch.int32, device=device)
+
+    def c(self):
+        return KfTracks(self.n, self.ld, _ptr(self.par), _ptr(self.cov), _ptr(self.chi2),
+                        _ptr(self.ndf), _ptr(self.status))
+
+    @staticmethod
+    def from_numpy(par, cov, dtype=torch.float32, ld=None):
+        n = par.shape[0]
+        t = Tracks(n, ld, dtype)
+        t.par[:, :n] = torch.as_tensor(par.T, dtype=dtype)
+        t.cov[:, :n] = torch.as_tensor(cov.T, dtype=dtype)
+        return t
+
+    def numpy(self):
+        n = self.n
+        return dict(par=self.par[:, :n].T.double().cpu().numpy(),
+                    cov=self.cov[:, :n].T.double().cpu().numpy(),
+                    chi2=self.chi2[:n].double().cpu().numpy(),
+                    ndf=self.ndf[:n].cpu().numpy(),
+                    status=self.status[:n].cpu().numpy())
+
+
+class Hits:
+    """SoA float32 hits on the GPU."""
+
+    def __init__(self, x, y, z, su, sv, layer, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32, device=device).contiguous()
+        self.x, self.y, self.z, self.su, self.sv = f(x), f(y), f(z), f(su), f(sv)
+        self.layer = torch.as_tensor(layer, dtype=torch.int32, device=device).contiguous()
+        self.n = int(self.x.shape[0])
+
+    @staticmethod
+    def from_event(ev, device="cuda"):
+        return Hits(ev.x, ev.y, ev.z, ev.su, ev.sv, ev.layer, device)
+
+    def c(self):
+        return KfHits(self.n, _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.su),
+                      _ptr(self.sv), _ptr(self.layer))
+
+
+class KFError(RuntimeError):
+    pass
+
+
+class Context:
+    """A kf_ctx: geometry + parameters (+ workspace) for one device."""
+
+    def __init__(self, geom, bz=3.8, chi2_cut=30.0, max_cands=6, max_newton=10, newton_tol=1e-4,
+                 mass=0.13957, max_miss=2, mlp_max_iter=3):
+        arr = (KfLayer * len(geom))()
+        for i, L in enumerate(geom):
+            arr[i] = KfLayer(int(L["kind"]), L["r_or_z"], L["lo"], L["hi"], L["x0"],
+                             int(L["nbin_phi"]), int(L["nbin_2"]), L["win_su"], L["win_sv"])
+        self.n_layers = len(geom)
+        prm = KfParams(bz, chi2_cut, max_cands, max_newton, newton_tol, mass, max_miss, mlp_max_iter)
+        h = C.c_void_p()
+        torch.cuda.current_device()          # make sure the runtime is up on this device
+        r = lib.kf_create(C.byref(h), arr, len(geom), C.byref(prm))
+        if r != KF_OK:
+            raise KFError(f"kf_create failed ({r}): {lib.kf_last_error_global().decode()}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.kf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, r, what):
+        if r != KF_OK:
+            raise KFError(f"{what} failed ({r}): {lib.kf_last_error(self.h).decode()}")
+
+    def seed(self, hits, seed_hits, out, flags=0):
+        """seed_hits: int32 [3, ld] hit indices."""
+        self._check(lib.kf_seed(self.h, C.byref(hits.c()), _ptr(seed_hits), C.byref(out.c()),
+                                flags, _stream()), "kf_seed")
+
+    def propagate(self, tracks, target, path_len=None, iters=None, flags=0):
+        self._check(lib.kf_propagate(self.h, C.byref(tracks.c()), _ptr(target), _ptr(path_len),
+                                     _ptr(iters), flags, _stream()), "kf_propagate")
+
+    def fit(self, tracks, hits, layer_seq, hit_idx, max_steps, flags=0):
+        self._check(lib.kf_fit(self.h, C.byref(tracks.c()), C.byref(hits.c()), _ptr(layer_seq),
+                               _ptr(hit_idx), int(max_steps), flags, _stream()), "kf_fit")

@@ -1,0 +1,319 @@
+// Seed, propagate and fit kernels: one lane per track, structure-of-arrays
+// state so that element k of consecutive tracks is one coalesced access.
+//
+// arXiv:1906.02253 Sec. 2 (vectorised KF track fitting over sets of small
+// matrices), Sec. 3.1 (layer-to-layer propagation with per-layer material in
+// a constant field), Sec. 3.2 (seeds provided externally).
+#include "kf_internal.hpp"
+#include "kf_math.hpp"
+
+namespace kfmi {
+
+template <typename TS, typename T>
+__device__ inline void load_state(const TS* par, const TS* cov, int64_t ld, int64_t i, T p[6],
+                                  T P[21])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = T(par[k * ld + i]);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) P[k] = T(cov[k * ld + i]);
+}
+
+template <typename TS, typename T>
+__device__ inline void store_state(TS* par, TS* cov, int64_t ld, int64_t i, const T p[6],
+                                   const T P[21])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) par[k * ld + i] = TS(p[k]);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) cov[k * ld + i] = TS(P[k]);
+}
+
+// Propagate (p, P) to layer L.  s_init < 0: straight-line start.
+template <typename T>
+__device__ inline int propagate_to(T p[6], T P[21], const kf_layer& L, const kf_params& prm,
+                                   bool material, T s_init, T* s_out, int* evals)
+{
+    const T kb = T(kKappa) * T(prm.bz);
+    T s;
+    if (L.kind == 0) {
+        const T h = -kb * p[3];
+        T sph, cph;
+        Tr<T>::sincos_(p[4], &sph, &cph);
+        const T r_l = T(L.r_or_z);
+        T s_hi;
+        if (!barrel_bracket(p[0], p[1], cph, sph, h, r_l, &s_hi)) return KF_ST_UNREACHABLE;
+        T s0 = s_init >= T(0) ? s_init : line_guess(p[0], p[1], cph, sph, r_l);
+        int st = newton_barrel(p[0], p[1], p[4], h, r_l, s0, T(0), s_hi, prm.max_newton,
+                               T(prm.newton_tol), &s, evals);
+        if (st) return st;
+    } else {
+        T st_, ct_;
+        Tr<T>::sincos_(p[5], &st_, &ct_);
+        if (ct_ == T(0)) return KF_ST_UNREACHABLE;
+        s = (T(L.r_or_z) - p[2]) * st_ / ct_;
+        *evals += 1;
+        if (s < T(0)) return KF_ST_UNREACHABLE;
+    }
+    transport(p, P, s, kb, L.kind, T(L.r_or_z));
+    if (material) add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
+    if (s_out) *s_out = s;
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) fin &= isfinite(p[k]);
+    return fin ? 0 : KF_ST_NAN;
+}
+
+// ---------------------------------------------------------------- seed
+template <typename TS, typename T>
+__global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_t n_hits,
+                                                   const float* __restrict__ hx,
+                                                   const float* __restrict__ hy,
+                                                   const float* __restrict__ hz,
+                                                   const int32_t* __restrict__ seed_hits, float bz,
+                                                   TS* __restrict__ par, TS* __restrict__ cov,
+                                                   TS* __restrict__ chi2, int32_t* __restrict__ ndf,
+                                                   uint32_t* __restrict__ status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t a = seed_hits[i], b = seed_hits[ld + i], c = seed_hits[2 * ld + i];
+    if (a < 0 || b < 0 || c < 0 || a >= n_hits || b >= n_hits || c >= n_hits) {
+        chi2[i] = TS(0);
+        ndf[i] = -5;
+        status[i] = KF_ST_BADINPUT;
+        return;
+    }
+    const T x1 = hx[a], y1 = hy[a], z1 = hz[a];
+    const T ax = T(hx[b]) - x1, ay = T(hy[b]) - y1;
+    const T bx = T(hx[c]) - x1, by = T(hy[c]) - y1;
+    const T d12 = Tr<T>::sqrt_(ax * ax + ay * ay);
+    const T d13 = Tr<T>::sqrt_(bx * bx + by * by);
+    const T ex = T(hx[c]) - T(hx[b]), ey = T(hy[c]) - T(hy[b]);
+    const T d23 = Tr<T>::sqrt_(ex * ex + ey * ey);
+    // signed curvature of the circle through the three points
+    const T h = T(2) * (ax * by - ay * bx) / (d12 * d23 * d13);
+    T w = T(0.5) * h * d13;
+    w = w > T(1) ? T(1) : (w < T(-1) ? T(-1) : w);
+    const T w2 = w * w;
+    const T s13 = Tr<T>::abs_(w) < T(1e-3) ? d13 * (T(1) + w2 * (T(1.0 / 6.0) + w2 * T(3.0 / 40.0)))
+                                           : d13 * Tr<T>::asin_(w) / w;
+    T p[6], P[21];
+    p[0] = x1;
+    p[1] = y1;
+    p[2] = z1;
+    p[3] = -h / (T(kKappa) * T(bz));
+    p[4] = wrap_phi(Tr<T>::atan2_(by, bx) - T(0.5) * h * s13);
+    p[5] = Tr<T>::atan2_(s13, T(hz[c]) - z1);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) P[k] = T(0);
+    P[pk(0, 0)] = P[pk(1, 1)] = P[pk(2, 2)] = T(1);
+    P[pk(3, 3)] = T(4);
+    P[pk(4, 4)] = P[pk(5, 5)] = T(0.01);
+    store_state(par, cov, ld, i, p, P);
+    chi2[i] = TS(0);
+    ndf[i] = -5;
+    status[i] = 0;
+}
+
+// ---------------------------------------------------------------- propagate
+template <typename TS, typename T>
+__global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, TS* __restrict__ par,
+                                                        TS* __restrict__ cov,
+                                                        uint32_t* __restrict__ status,
+                                                        const int32_t* __restrict__ target,
+                                                        const kf_layer* __restrict__ layers,
+                                                        int n_layers, kf_params prm, int material,
+                                                        float* __restrict__ path_len,
+                                                        int32_t* __restrict__ iters)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t l = target[i];
+    uint32_t st = status[i];
+    if (l >= n_layers) st |= KF_ST_BADINPUT;
+    if (l < 0 || st) {
+        status[i] = st;
+        if (path_len) path_len[i] = 0.0f;
+        if (iters) iters[i] = 0;
+        return;
+    }
+    T p[6], P[21];
+    load_state(par, cov, ld, i, p, P);
+    const kf_layer L = layers[l];
+    T s = T(0);
+    int ev = 0;
+    int r = propagate_to(p, P, L, prm, material != 0, T(-1), &s, &ev);
+    if (r) {
+        status[i] = st | (uint32_t)r;
+    } else {
+        store_state(par, cov, ld, i, p, P);
+    }
+    if (path_len) path_len[i] = float(s);
+    if (iters) iters[i] = ev;
+}
+
+// ---------------------------------------------------------------- fit
+struct FitArgs {
+    int64_t n, ld;
+    void* par;
+    void* cov;
+    void* chi2;
+    int32_t* ndf;
+    uint32_t* status;
+    const float *hx, *hy, *hz, *hsu, *hsv;
+    const int32_t* layer_seq;
+    const int32_t* hit_idx;
+    int64_t n_hits;
+    const kf_layer* layers;
+    int n_layers;
+    kf_params prm;
+    int material;
+};
+
+// Steps [k0, k1) of the fit.  init: start a fresh fit (chi2 = 0, ndf = -5).
+template <typename TS, typename T, typename U>
+__global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int init)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t ld = a.ld;
+    TS* par = (TS*)a.par;
+    TS* cov = (TS*)a.cov;
+    TS* chi2p = (TS*)a.chi2;
+    uint32_t st = init ? 0u : a.status[i];
+    int32_t ndf = init ? -5 : a.ndf[i];
+    U chi2 = init ? U(0) : U(chi2p[i]);
+    if (st) return;
+    T p[6], P[21];
+    load_state(par, cov, ld, i, p, P);
+    bool touched = false;
+    for (int k = k0; k < k1; ++k) {
+        const int32_t l = a.layer_seq ? a.layer_seq[(int64_t)k * ld + i] : k;
+        if (l < 0) break;
+        if (l >= a.n_layers) {
+            st |= KF_ST_BADINPUT;
+            break;
+        }
+        const kf_layer L = a.layers[l];
+        int ev = 0;
+        int r = propagate_to(p, P, L, a.prm, a.material != 0, T(-1), (T*)nullptr, &ev);
+        touched = true;
+        if (r) {
+            st |= (uint32_t)r;
+            break;
+        }
+        const int32_t hi = a.hit_idx[(int64_t)k * ld + i];
+        if (hi >= a.n_hits) {
+            st |= KF_ST_BADINPUT;
+            break;
+        }
+        if (hi >= 0) {
+            HitFrame<U> f = hit_frame<U>(a.hx[hi], a.hy[hi], a.hz[hi], a.hsu[hi], a.hsv[hi]);
+            U c2 = U(0);
+            r = kf_update<T, U>(p, P, f, L.kind, &c2);
+            if (r) {
+                st |= (uint32_t)r;
+                break;
+            }
+            // rounded to storage precision every step, so one launch per step
+            // and one launch for all steps give identical results
+            chi2 = U(TS(chi2 + c2));
+            ndf += 2;
+        }
+    }
+    // on failure the registers hold the last good state (a failed solve or
+    // update leaves them untouched)
+    if (touched) store_state(par, cov, ld, i, p, P);
+    chi2p[i] = TS(chi2);
+    a.ndf[i] = ndf;
+    a.status[i] = st;
+}
+
+// ---------------------------------------------------------------- launchers
+static inline dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
+
+hipError_t launch_seed(const kf_ctx* ctx, const kf_hits* h, const int32_t* seed_hits,
+                       kf_tracks* out, int flags, hipStream_t s)
+{
+    if (out->n == 0) return hipSuccess;
+    const int prec = flags & KF_PREC_MASK;
+    dim3 g = grid_for(out->n, 256);
+    if (prec == KF_PREC_FP64)
+        seed_kernel<double, double><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
+                                                      ctx->params.bz, (double*)out->par,
+                                                      (double*)out->cov, (double*)out->chi2,
+                                                      out->ndf, out->status);
+    else
+        seed_kernel<float, float><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
+                                                    ctx->params.bz, (float*)out->par,
+                                                    (float*)out->cov, (float*)out->chi2, out->ndf,
+                                                    out->status);
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* target, float* path_len,
+                            int32_t* iters, int flags, hipStream_t s)
+{
+    if (t->n == 0) return hipSuccess;
+    const int prec = flags & KF_PREC_MASK;
+    const int material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    dim3 g = grid_for(t->n, 256);
+    if (prec == KF_PREC_FP64)
+        propagate_kernel<double, double><<<g, 256, 0, s>>>(t->n, t->ld, (double*)t->par,
+                                                           (double*)t->cov, t->status, target,
+                                                           ctx->d_layers, ctx->n_layers, ctx->params,
+                                                           material, path_len, iters);
+    else
+        propagate_kernel<float, float><<<g, 256, 0, s>>>(t->n, t->ld, (float*)t->par,
+                                                         (float*)t->cov, t->status, target,
+                                                         ctx->d_layers, ctx->n_layers, ctx->params,
+                                                         material, path_len, iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const int32_t* layer_seq,
+                      const int32_t* hit_idx, int32_t max_steps, int flags, hipStream_t s)
+{
+    if (t->n == 0) return hipSuccess;
+    FitArgs a;
+    a.n = t->n;
+    a.ld = t->ld;
+    a.par = t->par;
+    a.cov = t->cov;
+    a.chi2 = t->chi2;
+    a.ndf = t->ndf;
+    a.status = t->status;
+    a.hx = h->x;
+    a.hy = h->y;
+    a.hz = h->z;
+    a.hsu = h->su;
+    a.hsv = h->sv;
+    a.layer_seq = layer_seq;
+    a.hit_idx = hit_idx;
+    a.n_hits = h->n;
+    a.layers = ctx->d_layers;
+    a.n_layers = ctx->n_layers;
+    a.prm = ctx->params;
+    a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    const int prec = flags & KF_PREC_MASK;
+    dim3 g = grid_for(t->n, 256);
+    const bool per_layer = (flags & KF_PER_LAYER) != 0;
+    const int nlaunch = per_layer ? max_steps : 1;
+    for (int k = 0; k < nlaunch; ++k) {
+        const int k0 = per_layer ? k : 0;
+        const int k1 = per_layer ? k + 1 : max_steps;
+        const int init = k == 0;
+        if (prec == KF_PREC_FP64)
+            fit_kernel<double, double, double><<<g, 256, 0, s>>>(a, k0, k1, init);
+        else if (prec == KF_PREC_FP32)
+            fit_kernel<float, float, float><<<g, 256, 0, s>>>(a, k0, k1, init);
+        else
+            fit_kernel<float, float, double><<<g, 256, 0, s>>>(a, k0, k1, init);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace kfmi

@@ -1,0 +1,46 @@
+// Internal declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/kf.h"
+
+namespace kfmi {
+
+constexpr int kMaxLayers = 64;
+
+// Device-resident workspace, grown on demand and reused between calls.
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    // returns nullptr on failure
+    void* get(size_t need);
+    void release();
+};
+
+}  // namespace kfmi
+
+struct kf_ctx {
+    int32_t n_layers = 0;
+    kf_layer layers[kfmi::kMaxLayers];
+    kf_params params;
+    kf_layer* d_layers = nullptr;     // device copy of the geometry
+    int device = 0;
+    std::string err;
+    kfmi::Workspace ws;               // general scratch of the find path
+};
+
+namespace kfmi {
+
+// Launchers (kernels in kf_fit.hip).  Return hipError_t.
+hipError_t launch_seed(const kf_ctx* ctx, const kf_hits* h, const int32_t* seed_hits,
+                       kf_tracks* out, int flags, hipStream_t s);
+hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* target,
+                            float* path_len, int32_t* iters, int flags, hipStream_t s);
+hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const int32_t* layer_seq,
+                      const int32_t* hit_idx, int32_t max_steps, int flags, hipStream_t s);
+
+}  // namespace kfmi

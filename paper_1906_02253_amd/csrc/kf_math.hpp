@@ -1,0 +1,402 @@
+// Device-side Kalman-filter arithmetic for gfx950: helix transport, the
+// propagate-to-surface solves, the transport Jacobian, scattering noise and
+// the 2D-hit update.  One lane owns one track (or candidate); matrices live
+// in registers.  T = transport precision, U = update precision.
+//
+// Method references (arXiv:1906.02253): Sec. 1 (traditional Kalman filter),
+// Sec. 2 (vectorised KF fit/find over many small matrices), Sec. 3.1
+// (layer-to-layer propagation, per-layer material, constant field).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kf.h"
+
+namespace kfmi {
+
+constexpr double kKappa = 0.00299792458;   // GeV / (T cm)
+constexpr double kPi = 3.14159265358979323846;
+constexpr float kNextBarrelEps = 0.05f;    // cm
+constexpr float kDiskAheadEps = 0.05f;     // cm
+
+// packed upper-triangle index of a symmetric 6x6
+__host__ __device__ constexpr int pk(int i, int j)
+{
+    return i <= j ? i * (11 - i) / 2 + j : j * (11 - j) / 2 + i;
+}
+
+template <typename T> struct Tr;
+template <> struct Tr<float> {
+    __device__ static inline void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
+    __device__ static inline float sqrt_(float x) { return sqrtf(x); }
+    __device__ static inline float abs_(float x) { return fabsf(x); }
+    __device__ static inline float atan2_(float y, float x) { return atan2f(y, x); }
+    __device__ static inline float log_(float x) { return logf(x); }
+    __device__ static inline float fmod_(float x, float y) { return fmodf(x, y); }
+    __device__ static inline float asin_(float x) { return asinf(x); }
+    __device__ static inline float cos_(float x) { return cosf(x); }
+    __device__ static inline float floor_(float x) { return floorf(x); }
+};
+template <> struct Tr<double> {
+    __device__ static inline void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+    __device__ static inline double sqrt_(double x) { return sqrt(x); }
+    __device__ static inline double abs_(double x) { return fabs(x); }
+    __device__ static inline double atan2_(double y, double x) { return atan2(y, x); }
+    __device__ static inline double log_(double x) { return log(x); }
+    __device__ static inline double fmod_(double x, double y) { return fmod(x, y); }
+    __device__ static inline double asin_(double x) { return asin(x); }
+    __device__ static inline double cos_(double x) { return cos(x); }
+    __device__ static inline double floor_(double x) { return floor(x); }
+};
+
+template <typename T>
+__device__ inline T wrap_phi(T a)
+{
+    const T pi = T(kPi), tpi = T(2.0 * kPi);
+    if (a > pi) a -= tpi;
+    if (a <= -pi) a += tpi;
+    return a;
+}
+
+// sin(u)/u given sin(u)
+template <typename T>
+__device__ inline T sinc_of(T u, T su)
+{
+    return Tr<T>::abs_(u) < T(1e-4) ? T(1) - u * u * T(1.0 / 6.0) : su / u;
+}
+
+// d/du [sin(u)/u]; Taylor series where the closed form cancels
+template <typename T>
+__device__ inline T dsinc_of(T u, T su, T cu)
+{
+    if (Tr<T>::abs_(u) < T(0.5)) {
+        T u2 = u * u;
+        return u * (T(-1.0 / 3.0) +
+                    u2 * (T(1.0 / 30.0) +
+                          u2 * (T(-1.0 / 840.0) + u2 * (T(1.0 / 45360.0) + u2 * T(-1.0 / 3991680.0)))));
+    }
+    return (u * cu - su) / (u * u);
+}
+
+// Helix point at transverse arc length s (sinc form, exact as h -> 0).
+template <typename T>
+struct HelixPoint {
+    T X, Y;          // transverse position
+    T cph, sph;      // direction cos/sin of phi(s)
+    T ca, sa;        // cos/sin(phi + h s / 2)
+    T sc, su, cu;    // sinc(u), sin(u), cos(u), u = h s / 2
+};
+
+template <typename T>
+__device__ inline HelixPoint<T> helix_at(T x, T y, T phi, T h, T s)
+{
+    HelixPoint<T> q;
+    T u = T(0.5) * h * s;
+    Tr<T>::sincos_(u, &q.su, &q.cu);
+    Tr<T>::sincos_(phi + u, &q.sa, &q.ca);
+    q.sc = sinc_of(u, q.su);
+    q.X = x + s * q.ca * q.sc;
+    q.Y = y + s * q.sa * q.sc;
+    q.cph = q.ca * q.cu - q.sa * q.su;
+    q.sph = q.sa * q.cu + q.ca * q.su;
+    return q;
+}
+
+// Straight-line (tangent) intersection with radius r_l: the plain initial guess.
+template <typename T>
+__device__ inline T line_guess(T x, T y, T cphi, T sphi, T r_l)
+{
+    T pu = x * cphi + y * sphi;
+    T disc = pu * pu - (x * x + y * y) + r_l * r_l;
+    return disc > T(0) ? -pu + Tr<T>::sqrt_(disc) : -pu;
+}
+
+// Bracket of the outward crossing: [0, arc length to the point of largest
+// radius].  Returns false when the circle never reaches r_l.
+template <typename T>
+__device__ inline bool barrel_bracket(T x, T y, T cphi, T sphi, T h, T r_l, T* s_hi)
+{
+    if (h == T(0)) {
+        *s_hi = T(1e30);
+        return true;
+    }
+    T inv = T(1) / h;
+    T cx = x - sphi * inv, cy = y + cphi * inv;
+    T R = Tr<T>::abs_(inv);
+    T dc = Tr<T>::sqrt_(cx * cx + cy * cy);
+    if (dc + R < r_l) return false;
+    T v0x = x - cx, v0y = y - cy;
+    T v1x = R * cx / dc, v1y = R * cy / dc;
+    T alpha = Tr<T>::atan2_(v0x * v1y - v0y * v1x, v0x * v1x + v0y * v1y);
+    T sw = Tr<T>::fmod_(h > T(0) ? alpha : -alpha, T(2.0 * kPi));
+    if (sw < T(0)) sw += T(2.0 * kPi);
+    *s_hi = sw * Tr<T>::abs_(inv);
+    return true;
+}
+
+// Bracketed Newton on r(s) = r_l from s0 within [s_lo, s_hi]; converged when
+// |r - r_l| < tol, then one more Newton step.  Returns 0 or KF_ST_NOCONV;
+// *evals counts evaluations of r(s).
+template <typename T>
+__device__ inline int newton_barrel(T x, T y, T phi, T h, T r_l, T s, T s_lo, T s_hi, int max_it,
+                                    T tol, T* s_out, int* evals)
+{
+    if (s < s_lo) s = s_lo;
+    if (s > s_hi) s = s_hi;
+    for (int it = 1; it <= max_it; ++it) {
+        HelixPoint<T> q = helix_at(x, y, phi, h, s);
+        T r = Tr<T>::sqrt_(q.X * q.X + q.Y * q.Y);
+        T res = r - r_l;
+        T drds = (q.X * q.cph + q.Y * q.sph) / r;
+        if (res < T(0)) {
+            if (s > s_lo) s_lo = s;
+        } else {
+            if (s < s_hi) s_hi = s;
+        }
+        if (Tr<T>::abs_(res) < tol) {
+            if (drds > T(0)) s -= res / drds;
+            *s_out = s;
+            *evals += it;
+            return 0;
+        }
+        T sn = s - res / drds;
+        if (!(drds > T(0)) || !(sn > s_lo && sn < s_hi)) sn = T(0.5) * (s_lo + s_hi);
+        s = sn;
+    }
+    *s_out = s;
+    *evals += max_it;
+    return KF_ST_NOCONV;
+}
+
+// Transport of (p, P) by arc length s to a surface: new state, F P F^T.
+// kind 0: barrel (path length from r(s) = r_l); 1: disk at z = zd.
+template <typename T>
+__device__ inline void transport(T p[6], T P[21], T s, T kb, int kind, T zd)
+{
+    const T x = p[0], y = p[1], z = p[2], c = p[3], phi = p[4], th = p[5];
+    const T h = -kb * c;
+    HelixPoint<T> q = helix_at(x, y, phi, h, s);
+    T st, ct;
+    Tr<T>::sincos_(th, &st, &ct);
+    const T cot = ct / st;
+    const T u = T(0.5) * h * s;
+    const T dsc = dsinc_of(u, q.su, q.cu);
+
+    // partial derivatives at fixed s
+    const T D03 = -kb * (T(0.5) * s * s * (q.ca * dsc - q.sa * q.sc));
+    const T D13 = -kb * (T(0.5) * s * s * (q.sa * dsc + q.ca * q.sc));
+    const T D04 = -s * q.sa * q.sc;
+    const T D14 = s * q.ca * q.sc;
+    const T D43 = -kb * s;
+    const T D25 = -s / (st * st);
+    // derivative of the state with respect to s
+    const T f0 = q.cph, f1 = q.sph, f2 = cot, f4 = h;
+    // derivative of s with respect to the starting state
+    T d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0;
+    if (kind == 0) {
+        T den = T(-1) / (q.X * f0 + q.Y * f1);
+        d0 = q.X * den;
+        d1 = q.Y * den;
+        d3 = (q.X * D03 + q.Y * D13) * den;
+        d4 = (q.X * D04 + q.Y * D14) * den;
+    } else {
+        d2 = -st / ct;
+        d5 = (zd - z) / (ct * ct);
+    }
+    T F[4][6] = {
+        {T(1) + f0 * d0, f0 * d1, f0 * d2, D03 + f0 * d3, D04 + f0 * d4, f0 * d5},
+        {f1 * d0, T(1) + f1 * d1, f1 * d2, D13 + f1 * d3, D14 + f1 * d4, f1 * d5},
+        {f2 * d0, f2 * d1, T(1) + f2 * d2, f2 * d3, f2 * d4, D25 + f2 * d5},
+        {f4 * d0, f4 * d1, f4 * d2, D43 + f4 * d3, T(1) + f4 * d4, f4 * d5},
+    };
+    // A = F P for the four general rows; rows 3 and 5 of F are unit rows
+    T A[4][6];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc += F[r][k] * P[pk(k, j)];
+            A[r][j] = acc;
+        }
+    // P' = A F^T (upper triangle).  Row of P' for F-row index: general rows use A,
+    // unit rows 3 and 5 use P itself.
+    T Pn[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            // pick row i of (F P): general or unit
+            const int ri = i == 0 ? 0 : i == 1 ? 1 : i == 2 ? 2 : i == 4 ? 3 : -1;
+            const int rj = j == 0 ? 0 : j == 1 ? 1 : j == 2 ? 2 : j == 4 ? 3 : -1;
+            T v;
+            if (rj < 0) {
+                // column j of F^T is e_j: (F P)_{i j}
+                v = ri >= 0 ? A[ri][j] : P[pk(i, j)];
+            } else {
+                T acc = T(0);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) acc += (ri >= 0 ? A[ri][k] : P[pk(i, k)]) * F[rj][k];
+                v = acc;
+            }
+            Pn[pk(i, j)] = v;
+        }
+#pragma unroll
+    for (int k = 0; k < 21; ++k) P[k] = Pn[k];
+    p[0] = q.X;
+    p[1] = q.Y;
+    p[2] = z + s * cot;
+    p[4] = wrap_phi(phi + h * s);
+}
+
+// Multiple-scattering process noise of a layer (PDG Highland width), added to
+// the (c, phi, theta) block at the propagated state.
+template <typename T>
+__device__ inline void add_scatter(const T p[6], T P[21], int kind, T x0, T mass)
+{
+    if (!(x0 > T(0))) return;
+    T st, ct;
+    Tr<T>::sincos_(p[5], &st, &ct);
+    T cosa;
+    if (kind == 0) {
+        T sph, cph;
+        Tr<T>::sincos_(p[4], &sph, &cph);
+        T r = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+        cosa = st * (cph * p[0] + sph * p[1]) / r;
+    } else {
+        cosa = ct;
+    }
+    cosa = Tr<T>::abs_(cosa);
+    if (cosa < T(1e-6)) cosa = T(1e-6);
+    const T t = x0 / cosa;
+    const T pm = T(1) / (Tr<T>::abs_(p[3]) * st);
+    const T b2 = pm * pm / (pm * pm + mass * mass);
+    const T beta = Tr<T>::sqrt_(b2);
+    const T th0 = T(0.0136) / (beta * pm) * Tr<T>::sqrt_(t) * (T(1) + T(0.038) * Tr<T>::log_(t / b2));
+    const T t2 = th0 * th0;
+    const T cot = ct / st;
+    P[pk(4, 4)] += t2 / (st * st);
+    P[pk(5, 5)] += t2;
+    P[pk(3, 5)] += -p[3] * cot * t2;
+    P[pk(3, 3)] += p[3] * p[3] * cot * cot * t2;
+}
+
+// Local frame of a hit: u along phi at the hit's azimuth, v along z (barrel)
+// or r (disk).  H has two rows with entries only in the x, y, z columns.
+template <typename U>
+struct HitFrame {
+    U c, s;          // cos/sin of the hit azimuth
+    U hx, hy, hz;
+    U vu, vv;        // sigma^2
+};
+
+template <typename U>
+__device__ inline HitFrame<U> hit_frame(float x, float y, float z, float su, float sv)
+{
+    HitFrame<U> f;
+    f.hx = U(x);
+    f.hy = U(y);
+    f.hz = U(z);
+    U rho = Tr<U>::sqrt_(f.hx * f.hx + f.hy * f.hy);
+    f.c = f.hx / rho;
+    f.s = f.hy / rho;
+    f.vu = U(su) * U(su);
+    f.vv = U(sv) * U(sv);
+    return f;
+}
+
+// chi2 of a hit against (p, P) without updating
+template <typename T, typename U>
+__device__ inline U hit_chi2(const T p[6], const T P[21], const HitFrame<U>& f, int kind)
+{
+    const U c = f.c, s = f.s;
+    U ru = -s * (f.hx - U(p[0])) + c * (f.hy - U(p[1]));
+    U rv;
+    U b0[3], b1[3];   // first three rows of P H^T (what S needs)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        b0[i] = -s * U(P[pk(i, 0)]) + c * U(P[pk(i, 1)]);
+        b1[i] = kind == 0 ? U(P[pk(i, 2)]) : c * U(P[pk(i, 0)]) + s * U(P[pk(i, 1)]);
+    }
+    U S00 = -s * b0[0] + c * b0[1] + f.vu;
+    U S01, S11;
+    if (kind == 0) {
+        rv = f.hz - U(p[2]);
+        S01 = -s * b1[0] + c * b1[1];
+        S11 = b1[2] + f.vv;
+    } else {
+        rv = c * (f.hx - U(p[0])) + s * (f.hy - U(p[1]));
+        S01 = -s * b1[0] + c * b1[1];
+        S11 = c * b1[0] + s * b1[1] + f.vv;
+    }
+    U det = S00 * S11 - S01 * S01;
+    if (!(det > U(0)) || !(S00 > U(0))) return U(1e30);
+    return (ru * ru * S11 - U(2) * ru * rv * S01 + rv * rv * S00) / det;
+}
+
+// Kalman update with a 2D hit.  Gain K = P H^T S^-1, state x + K r, covariance
+// in Joseph form (I - K H) P (I - K H)^T + K V K^T, evaluated as
+// M = P - K (H P), P+ = M - (M H^T) K^T + K V K^T.  Returns status bits.
+template <typename T, typename U>
+__device__ inline int kf_update(T p[6], T P[21], const HitFrame<U>& f, int kind, U* chi2_out)
+{
+    const U c = f.c, s = f.s;
+    U Pu[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Pu[k] = U(P[k]);
+    U ru = -s * (f.hx - U(p[0])) + c * (f.hy - U(p[1]));
+    U rv = kind == 0 ? f.hz - U(p[2]) : c * (f.hx - U(p[0])) + s * (f.hy - U(p[1]));
+    // B = P H^T (6x2)
+    U B0[6], B1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        B0[i] = -s * Pu[pk(i, 0)] + c * Pu[pk(i, 1)];
+        B1[i] = kind == 0 ? Pu[pk(i, 2)] : c * Pu[pk(i, 0)] + s * Pu[pk(i, 1)];
+    }
+    U S00 = -s * B0[0] + c * B0[1] + f.vu;
+    U S01 = -s * B1[0] + c * B1[1];
+    U S11 = (kind == 0 ? B1[2] : c * B1[0] + s * B1[1]) + f.vv;
+    U det = S00 * S11 - S01 * S01;
+    if (!(det > U(0)) || !(S00 > U(0))) return KF_ST_NONPD;
+    U idet = U(1) / det;
+    U I00 = S11 * idet, I01 = -S01 * idet, I11 = S00 * idet;
+    *chi2_out = ru * (I00 * ru + I01 * rv) + rv * (I01 * ru + I11 * rv);
+    U K0[6], K1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        K0[i] = B0[i] * I00 + B1[i] * I01;
+        K1[i] = B0[i] * I01 + B1[i] * I11;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p[i] = T(U(p[i]) + K0[i] * ru + K1[i] * rv);
+    p[4] = wrap_phi(p[4]);
+    // M = P - K B^T: needed in full for columns 0..2 and in the upper triangle
+    U Mc[6][3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Mc[i][j] = Pu[pk(i, j)] - K0[i] * B0[j] - K1[i] * B1[j];
+    // N = M H^T
+    U N0[6], N1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        N0[i] = -s * Mc[i][0] + c * Mc[i][1];
+        N1[i] = kind == 0 ? Mc[i][2] : c * Mc[i][0] + s * Mc[i][1];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            U m = j < 3 ? Mc[i][j] : Pu[pk(i, j)] - K0[i] * B0[j] - K1[i] * B1[j];
+            U v = m - N0[i] * K0[j] - N1[i] * K1[j] + f.vu * K0[i] * K0[j] + f.vv * K1[i] * K1[j];
+            P[pk(i, j)] = T(v);
+        }
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) fin &= isfinite(p[i]);
+    return fin ? 0 : KF_ST_NAN;
+}
+
+}  // namespace kfmi

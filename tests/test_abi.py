@@ -1,0 +1,50 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every function include/kf.h declares, and rejects bad arguments before any
+device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kf.h")
+LIB = os.path.join(ROOT, "paper_1906_02253_amd", "libkfmi.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(kf_[a-z0-9_]+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libkfmi.so is not built: run __graft_entry__.build()")
+    return C.CDLL(LIB)
+
+
+def test_header_declares_core_entry_points():
+    names = declared_functions()
+    for f in ("kf_create", "kf_destroy", "kf_propagate", "kf_fit", "kf_seed"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_argument_validation_without_device(lib):
+    lib.kf_create.restype = C.c_int
+    lib.kf_create.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    assert lib.kf_create(None, None, 0, None) == -1
+    out = C.c_void_p()
+    assert lib.kf_create(C.byref(out), None, 3, None) == -1
+    lib.kf_last_error_global.restype = C.c_char_p
+    assert b"layers" in lib.kf_last_error_global()
+    lib.kf_fit.restype = C.c_int
+    lib.kf_fit.argtypes = [C.c_void_p] * 6 + [C.c_int, C.c_void_p]
+    assert lib.kf_fit(None, None, None, None, None, 0, 0, None) == -1
