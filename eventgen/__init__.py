@@ -34,6 +34,32 @@ def concat_events(events):
     )
 
 
-__all__ = ["geometry", "Event", "fit_sample", "precision_sample", "find_events",
+def find_inputs(events, min_hits=3):
+    """Concatenated hits of several events plus one seed per track with at
+    least `min_hits` hits (its first three hits in crossing order).
+
+    Returns a dict: hits arrays (x, y, z, su, sv, layer, sim), event_off
+    [n_events+1], seed_event [n_seeds], seed_track [n_seeds] (track index
+    within its event), seed_hits [n_seeds, 3] global hit indices,
+    seed_hits_local [n_seeds, 3] event-local indices, seed_layers [n_seeds, 3].
+    """
+    cat = concat_events(events)
+    se, st, sh, shl, sl = [], [], [], [], []
+    for i, e in enumerate(events):
+        nh = e.n_track_hits()
+        sel = np.nonzero(nh >= min_hits)[0]
+        se.append(np.full(sel.shape[0], i, np.int32))
+        st.append(sel.astype(np.int32))
+        loc = e.seq_hit[sel, :3].astype(np.int64)
+        shl.append(loc.astype(np.int32))
+        sh.append((loc + cat["event_off"][i]).astype(np.int32))
+        sl.append(e.seq_layer[sel, :3].astype(np.int32))
+    cat.update(seed_event=np.concatenate(se), seed_track=np.concatenate(st),
+               seed_hits=np.concatenate(sh), seed_hits_local=np.concatenate(shl),
+               seed_layers=np.concatenate(sl))
+    return cat
+
+
+__all__ = ["find_inputs", "geometry", "Event", "fit_sample", "precision_sample", "find_events",
            "batch_events", "make_event", "concat_events", "pt_uniform",
            "pt_power2", "pt_two_values", "sig_loguniform", "KAPPA"]

@@ -141,6 +141,37 @@ int kf_propagate(kf_ctx* ctx, kf_tracks* t, const int32_t* target_layer, float* 
 int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_seq,
            const int32_t* hit_idx, int32_t max_steps, int flags, void* stream);
 
+/* Combinatorial track finding over one or many events (paper Sec. 2: KF-based
+ * track finding; Sec. 3.1: layer-to-layer propagation following the geometry;
+ * Sec. 3.2: seeds grouped close in eta-phi and processed in parallel; Sec. 4:
+ * hit-search windows, chi2 selection, candidate scoring).
+ *   hits        all events' hits concatenated (float32 SoA + layer id)
+ *   event_off   [n_events+1] int32: event e owns hits [event_off[e], event_off[e+1])
+ *   seeds       n_seeds states after the seed fit (kf_seed, then kf_fit over the
+ *               three seed hits); float storage (KF_PREC_MIXED or KF_PREC_FP32)
+ *   seed_event  [n_seeds] int32 event of each seed
+ *   seed_hits   [3][seeds->ld] int32 the seed's hits (copied to the hit list)
+ *   out_hits    [n_seeds][n_layers] int32: hit of the best candidate on each
+ *               layer (global hit index), -1 = none
+ *   out         n_seeds tracks, out->n == seeds->n: best candidate's state at its
+ *               last surface, chi2, ndf = 2*hits - 5, status
+ *   counters    optional [2] uint64, incremented by (propagations, updates)
+ * Per layer a candidate is propagated to its next surface (the first reached
+ * of the next barrel outward and the next disk ahead), every hit in the chi2
+ * window's bins passing chi2 < chi2_cut becomes a child (best max_cands per
+ * parent), plus one no-hit child; per seed the best max_cands children by
+ * (most hits, lowest chi2, parent rank, hit index) survive.  A candidate stops
+ * after max_miss + 1 consecutive missed layers or when no surface is left.
+ * Device scratch comes from the context workspace (grown on demand). */
+int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+            const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
+            int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream);
+
+/* Workgroup width of the finding kernel (32, 64, 128 or 256 lanes; a lane per
+ * candidate slot, width / max_cands seeds per tile) and tile order (0: seeds
+ * sorted by event, eta, phi; 1: largest events first).  Default 256, 1. */
+int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first);
+
 #ifdef __cplusplus
 }
 #endif

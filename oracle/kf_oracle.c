@@ -711,8 +711,8 @@ static int cmp_hitsel(const void* a, const void* b)
 }
 
 typedef struct {
-    double cos_dphi;   /* azimuthal half-width as a cosine; <= -1 means all */
-    double dphi;
+    double sin_dphi;   /* sine of the azimuthal half-width (unused when dphi >= pi) */
+    double dphi;       /* azimuthal half-width; pi means the whole circle */
     double wv;         /* half-width along z (barrel) / r (disk) */
     double vlo, vhi;   /* bin-enumeration range along the second coordinate */
 } window_t;
@@ -728,7 +728,7 @@ static void make_window(const orc_cfg* cfg, const orc_layer* L, const double q[6
     double dphi = t >= 1.0 ? PI : asin(t) + WIN_ABS;
     if (dphi > 0.5 * PI) dphi = PI;
     W->dphi = dphi;
-    W->cos_dphi = dphi >= PI ? -2.0 : cos(dphi);
+    W->sin_dphi = dphi >= PI ? 2.0 : sin(dphi);
     if (L->kind == 0) {
         W->wv = WIN_REL * sqrt(cut * (pzz + L->win_sv * L->win_sv)) + WIN_ABS;
         W->vlo = q[2] - W->wv;
@@ -747,9 +747,11 @@ static int test_hit(const orc_cfg* cfg, const orc_layer* L, const event_index* E
 {
     double rho = hypot(q[0], q[1]);
     double rh = hypot(E->hx[i], E->hy[i]);
-    if (W->cos_dphi > -1.5) {
+    if (W->dphi < PI) {
+        /* |azimuth difference| <= dphi (< pi/2): same half-plane and |sin| bounded */
         double cd = (E->hx[i] * q[0] + E->hy[i] * q[1]) / (rh * rho);
-        if (cd < W->cos_dphi) return 0;
+        double sd = (E->hy[i] * q[0] - E->hx[i] * q[1]) / (rh * rho);
+        if (!(cd > 0.0) || fabs(sd) > W->sin_dphi) return 0;
     }
     double hit[5] = {E->hx[i], E->hy[i], E->hz[i], E->hsu[i], E->hsv[i]};
     double H[2][6], r[2];

@@ -17,12 +17,6 @@ ST_OK, ST_UNREACHABLE, ST_NOCONV, ST_FALLBACK, ST_NONPD, ST_NAN, ST_BADINPUT = 0
 PREC_MIXED, PREC_FP32, PREC_FP64 = 0, 1, 2
 INIT_MLP, NO_MATERIAL, PER_LAYER = 4, 8, 16
 
-EXPORTED = ("kf_create", "kf_destroy", "kf_last_error", "kf_last_error_global", "kf_seed",
-            "kf_propagate", "kf_fit", "kf_find", "kf_find_batched", "kf_autotune",
-            "kf_mlp_load", "kf_mlp_train", "kf_mlp_forward", "kf_mlp_backward",
-            "kf_mlp_adam", "kf_mlp_features", "kf_find_workspace_bytes")
-
-
 class KfLayer(C.Structure):
     _fields_ = [("kind", C.c_int32), ("r_or_z", C.c_float), ("lo", C.c_float), ("hi", C.c_float),
                 ("x0", C.c_float), ("nbin_phi", C.c_int32), ("nbin_2", C.c_int32),
@@ -60,7 +54,10 @@ def _load():
     L.kf_seed.argtypes = [vp, C.POINTER(KfHits), vp, C.POINTER(KfTracks), C.c_int, vp]
     L.kf_propagate.argtypes = [vp, C.POINTER(KfTracks), vp, vp, vp, C.c_int, vp]
     L.kf_fit.argtypes = [vp, C.POINTER(KfTracks), C.POINTER(KfHits), vp, vp, i32, C.c_int, vp]
-    for f in ("kf_seed", "kf_propagate", "kf_fit"):
+    L.kf_find.argtypes = [vp, C.POINTER(KfHits), vp, i32, C.POINTER(KfTracks), vp, vp, vp,
+                          C.POINTER(KfTracks), vp, C.c_int, vp]
+    L.kf_set_find_config.argtypes = [vp, i32, i32]
+    for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_set_find_config"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -187,3 +184,18 @@ class Context:
     def fit(self, tracks, hits, layer_seq, hit_idx, max_steps, flags=0):
         self._check(lib.kf_fit(self.h, C.byref(tracks.c()), C.byref(hits.c()), _ptr(layer_seq),
                                _ptr(hit_idx), int(max_steps), flags, _stream()), "kf_fit")
+
+    def set_find_config(self, width=256, largest_first=True):
+        self._check(lib.kf_set_find_config(self.h, int(width), int(bool(largest_first))),
+                    "kf_set_find_config")
+
+    def find(self, hits, event_off, seeds, seed_event, seed_hits, out_hits, out, counters=None,
+             flags=0):
+        """event_off: int32 [n_events+1]; seed_event: int32 [n_seeds];
+        seed_hits: int32 [3, seeds.ld]; out_hits: int32 [n_seeds, n_layers];
+        counters: optional int64 [2] (propagations, updates), accumulated."""
+        n_events = int(event_off.shape[0]) - 1
+        self._check(lib.kf_find(self.h, C.byref(hits.c()), _ptr(event_off), n_events,
+                                C.byref(seeds.c()), _ptr(seed_event), _ptr(seed_hits),
+                                _ptr(out_hits), C.byref(out.c()), _ptr(counters), flags,
+                                _stream()), "kf_find")

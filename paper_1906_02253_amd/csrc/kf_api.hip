@@ -4,7 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
-#include "kf_internal.hpp"
+#include "kf_find.hpp"
 
 namespace {
 
@@ -121,6 +121,8 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
     memcpy(ctx->layers, layers, sizeof(kf_layer) * n_layers);
     ctx->params = p;
     hipError_t e = hipGetDevice(&ctx->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_layers, sizeof(kf_layer) * kfmi::kMaxLayers);
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_layers, ctx->layers, sizeof(kf_layer) * n_layers, hipMemcpyHostToDevice);
@@ -184,6 +186,115 @@ int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_
     hipError_t e = kfmi::launch_fit(ctx, t, hits, layer_seq, hit_idx, max_steps, flags,
                                     (hipStream_t)stream);
     return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_fit");
+}
+
+int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_set_find_config: null context");
+    if (width != 32 && width != 64 && width != 128 && width != 256)
+        return fail(ctx, KF_EINVAL, "kf_set_find_config: width must be 32, 64, 128 or 256");
+    if (width / ctx->params.max_cands < 1)
+        return fail(ctx, KF_EINVAL, "kf_set_find_config: width below max_cands");
+    ctx->find_width = width;
+    ctx->find_largest_first = largest_first ? 1 : 0;
+    return KF_OK;
+}
+
+int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+            const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
+            int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_find: null context");
+    int r = check_tracks(ctx, seeds, "kf_find seeds");
+    if (r) return r;
+    r = check_tracks(ctx, out, "kf_find out");
+    if (r) return r;
+    r = check_hits(ctx, hits, "kf_find");
+    if (r) return r;
+    const int prec = flags & KF_PREC_MASK;
+    if (prec == KF_PREC_FP64)
+        return fail(ctx, KF_EUNSUPPORTED, "kf_find: float storage only (MIXED or FP32)");
+    if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
+        return fail(ctx, KF_EINVAL, "kf_find: bad precision flag");
+    if (flags & KF_INIT_MLP) return fail(ctx, KF_EUNSUPPORTED, "kf_find: no learned model loaded");
+    if (out->n != seeds->n) return fail(ctx, KF_EINVAL, "kf_find: out->n must equal seeds->n");
+    if (n_events < 1 || !event_off) return fail(ctx, KF_EINVAL, "kf_find: need n_events >= 1 and event_off");
+    if (hits->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "kf_find: at most 2^31-1 hits");
+    if (seeds->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "kf_find: at most 2^31-1 seeds");
+    if (seeds->n > 0 && (!seed_event || !seed_hits || !out_hits))
+        return fail(ctx, KF_EINVAL, "kf_find: null seed_event, seed_hits or out_hits");
+    if (seeds->n == 0) return KF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int W = ctx->find_width;
+    const int MC = ctx->params.max_cands;
+    const int S = W / MC;
+    const int nl = ctx->n_layers;
+    kfmi::FindPlan pl;
+    int64_t per_event = 0;
+    for (int l = 0; l < nl; ++l) {
+        pl.bl.base[l] = (int32_t)per_event;
+        per_event += (int64_t)ctx->layers[l].nbin_phi * ctx->layers[l].nbin_2;
+    }
+    if ((int64_t)n_events * per_event >= 0x7fffffffLL)
+        return fail(ctx, KF_EINVAL, "kf_find: n_events x bins per event exceeds 2^31");
+    pl.bl.per_event = (int32_t)per_event;
+    int lw = 0;
+    while ((1 << lw) < W) ++lw;
+    const int pi = prec == KF_PREC_FP32 ? 1 : 0;
+    int& occ = ctx->occ_cache[pi][lw];
+    if (occ == 0) {
+        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, &occ);
+        if (e != hipSuccess) return hip_fail(ctx, e, "kf_find occupancy");
+        if (occ < 1) occ = 1;
+    }
+    const int64_t n_tiles = (seeds->n + S - 1) / S;
+    int64_t grid = (int64_t)occ * (ctx->n_cu > 0 ? ctx->n_cu : 1);
+    if (grid > n_tiles) grid = n_tiles;
+    const size_t bytes = kfmi::plan_find(&pl, nullptr, hits->n, n_events, seeds->n, nl, (int)grid, S);
+    void* base = ctx->ws.get(bytes);
+    if (!base) return fail(ctx, KF_ENOMEM, "kf_find: workspace of %zu bytes", bytes);
+    kfmi::plan_find(&pl, base, hits->n, n_events, seeds->n, nl, (int)grid, S);
+    hipError_t e = kfmi::launch_bin(pl, hits, event_off, n_events, ctx->d_layers, nl, s);
+    if (e == hipSuccess)
+        e = kfmi::launch_seed_order(pl, seeds, seed_event, event_off, n_events,
+                                    ctx->find_largest_first, s);
+    if (e == hipSuccess) e = kfmi::launch_fill(pl.tile_counter, 1, 0, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_find setup");
+    kfmi::FindArgs a;
+    a.bh = (const kfmi::BinnedHit*)pl.binned;
+    a.bin_off = pl.off;
+    a.bl = pl.bl;
+    a.n_hits = hits->n;
+    a.hit_layer = hits->layer;
+    a.n_seeds = seeds->n;
+    a.sld = seeds->ld;
+    a.spar = (const float*)seeds->par;
+    a.scov = (const float*)seeds->cov;
+    a.schi2 = (const float*)seeds->chi2;
+    a.sndf = seeds->ndf;
+    a.sstatus = seeds->status;
+    a.seed_event = seed_event;
+    a.n_events = n_events;
+    a.seed_hits = seed_hits;
+    a.order = pl.order;
+    a.out_hits = out_hits;
+    a.old = out->ld;
+    a.opar = (float*)out->par;
+    a.ocov = (float*)out->cov;
+    a.ochi2 = (float*)out->chi2;
+    a.ondf = out->ndf;
+    a.ostatus = out->status;
+    a.bp = pl.bp;
+    a.tile_counter = pl.tile_counter;
+    a.counters = (unsigned long long*)counters;
+    a.layers = ctx->d_layers;
+    a.n_layers = nl;
+    a.prm = ctx->params;
+    a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    a.n_tiles = (int)n_tiles;
+    a.seeds_per_tile = S;
+    e = kfmi::launch_find_kernel(a, W, (int)grid, prec, s);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_find");
 }
 
 }  // extern "C"

@@ -1,0 +1,707 @@
+// Combinatorial track finding on gfx950.
+//
+//   a1  bin hits per (event, layer, phi bin, z|r bin): count, scan, scatter
+//       into 32-byte records (paper Sec. 3.2: hits handed in by the caller;
+//       binning makes the per-layer hit search a contiguous range scan);
+//   a2  order seeds by (event size, eta bin, phi bin) so that a workgroup's
+//       seeds share hit bins (paper Sec. 3.2: seeds grouped close in eta and
+//       phi for cache reuse of hit data);
+//   a3-a7 one persistent kernel walks tiles of seeds through the detector
+//       layer by layer (paper Sec. 2: KF-based finding; Sec. 3.1: layer-to-
+//       layer propagation; Sec. 4: hit-search windows, candidate scoring):
+//       each lane owns one candidate slot (max_cands slots per seed), keeps
+//       its state in registers, propagates to its next surface, scans the
+//       window's bins for hits passing the chi2 cut, then the seed's slot-0
+//       lane merges the children of all its candidates (k-way merge of
+//       per-parent sorted lists) and the lanes materialise the survivors with
+//       the Kalman update.  Hit lists are recovered from per-step
+//       back-pointers at the end.
+#include <hipcub/hipcub.hpp>
+
+#include "kf_find.hpp"
+#include "kf_math.hpp"
+
+namespace kfmi {
+
+static_assert(sizeof(BinnedHit) == 32, "BinnedHit is two 16-byte loads");
+
+// ------------------------------------------------------------------ binning
+__device__ inline int phi_bin_of(float phi, int nb)
+{
+    int b = (int)floorf((phi + float(kPi)) * float(nb) / float(2.0 * kPi));
+    return b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
+}
+
+__device__ inline int coord_bin_of(float v, float lo, float hi, int nb)
+{
+    float t = floorf((v - lo) * float(nb) / (hi - lo));
+    if (!(t >= 0.0f)) t = 0.0f;
+    if (t > float(nb - 1)) t = float(nb - 1);
+    return (int)t;
+}
+
+__device__ inline int event_of(const int32_t* off, int n_events, int64_t i)
+{
+    int lo = 0, hi = n_events;            // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void bin_count_kernel(int64_t n_hits, const float* __restrict__ x,
+                                                        const float* __restrict__ y,
+                                                        const float* __restrict__ z,
+                                                        const int32_t* __restrict__ layer,
+                                                        const int32_t* __restrict__ event_off,
+                                                        int n_events, const kf_layer* __restrict__ layers,
+                                                        int n_layers, BinLayout bl,
+                                                        int32_t* __restrict__ cnt,
+                                                        int32_t* __restrict__ hit_key)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_hits) return;
+    const int l = layer[i];
+    if (l < 0 || l >= n_layers || i < event_off[0] || i >= event_off[n_events]) {
+        hit_key[i] = -1;
+        return;
+    }
+    const int e = event_of(event_off, n_events, i);
+    const kf_layer L = layers[l];
+    const float hx = x[i], hy = y[i];
+    const int bp = phi_bin_of(atan2f(hy, hx), L.nbin_phi);
+    const float v = L.kind == 0 ? z[i] : sqrtf(hx * hx + hy * hy);
+    const int bv = coord_bin_of(v, L.lo, L.hi, L.nbin_2);
+    const int key = e * bl.per_event + bl.base[l] + bp * L.nbin_2 + bv;
+    atomicAdd(&cnt[key], 1);
+    hit_key[i] = key;
+}
+
+__global__ __launch_bounds__(256) void bin_scatter_kernel(int64_t n_hits, const float* __restrict__ x,
+                                                          const float* __restrict__ y,
+                                                          const float* __restrict__ z,
+                                                          const float* __restrict__ su,
+                                                          const float* __restrict__ sv,
+                                                          const int32_t* __restrict__ hit_key,
+                                                          const int32_t* __restrict__ off,
+                                                          int32_t* __restrict__ cnt,
+                                                          BinnedHit* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_hits) return;
+    const int key = hit_key[i];
+    if (key < 0) return;
+    const int pos = off[key] + atomicSub(&cnt[key], 1) - 1;
+    BinnedHit h;
+    h.x = x[i];
+    h.y = y[i];
+    h.z = z[i];
+    h.su = su[i];
+    h.sv = sv[i];
+    const float rho = sqrtf(h.x * h.x + h.y * h.y);
+    h.cphi = h.x / rho;
+    h.sphi = h.y / rho;
+    h.idx = (int32_t)i;
+    out[pos] = h;
+}
+
+// ------------------------------------------------------------------ seed order
+__global__ __launch_bounds__(256) void seed_key_kernel(int64_t n, int64_t ld, const float* __restrict__ par,
+                                                       const int32_t* __restrict__ seed_event,
+                                                       const int32_t* __restrict__ event_off,
+                                                       int n_events, int largest_first,
+                                                       uint64_t* __restrict__ keys,
+                                                       int32_t* __restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float th = par[5 * ld + i], ph = par[4 * ld + i];
+    int e = seed_event[i];
+    e = e < 0 ? 0 : (e >= n_events ? n_events - 1 : e);
+    const float eta = -logf(tanf(0.5f * th));
+    int eb = (int)floorf((eta + 3.0f) * (64.0f / 6.0f));
+    eb = eb < 0 ? 0 : (eb > 63 ? 63 : eb);
+    int pb = (int)floorf((ph + float(kPi)) * (64.0f / float(2.0 * kPi)));
+    pb = pb < 0 ? 0 : (pb > 63 ? 63 : pb);
+    const uint32_t nh = (uint32_t)(event_off[e + 1] - event_off[e]);
+    const uint64_t hi = largest_first ? (uint64_t)(0x7fffffffu - (nh & 0x7fffffffu)) : 0ull;
+    keys[i] = (hi << 32) | ((uint64_t)e << 12) | ((uint64_t)eb << 6) | (uint64_t)pb;
+    vals[i] = (int32_t)i;
+}
+
+// ------------------------------------------------------------------ find
+// Next surface: whichever comes first along the helix, the next barrel
+// outward (smallest radius above the current one, reachable, crossing inside
+// its z extent) or the first disk ahead whose crossing is inside its radial
+// extent.  Returns the layer (or -1) and the path length.
+template <typename T>
+__device__ inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_params& prm, T kb,
+                               T* s_out, uint32_t* st)
+{
+    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+    int bl = -1;
+    T rbl = T(0);
+    for (int l = 0; l < nl; ++l) {
+        if (L[l].kind != 0) continue;
+        const T r = T(L[l].r_or_z);
+        if (r > rho + T(kNextBarrelEps) && (bl < 0 || r < rbl)) {
+            bl = l;
+            rbl = r;
+        }
+    }
+    T best_s = T(1e30);
+    int best_l = -1;
+    T sth, cth;
+    Tr<T>::sincos_(p[5], &sth, &cth);
+    if (bl >= 0) {
+        const T h = -kb * p[3];
+        T sph, cph;
+        Tr<T>::sincos_(p[4], &sph, &cph);
+        T s_hi;
+        if (barrel_bracket(p[0], p[1], cph, sph, h, rbl, &s_hi)) {
+            T s;
+            int ev = 0;
+            const T s0 = line_guess(p[0], p[1], cph, sph, rbl);
+            if (newton_barrel(p[0], p[1], p[4], h, rbl, s0, T(0), s_hi, prm.max_newton,
+                              T(prm.newton_tol), &s, &ev)) {
+                *st |= KF_ST_NOCONV;
+                return -1;
+            }
+            const T zc = p[2] + s * cth / sth;
+            if (Tr<T>::abs_(zc) <= T(L[bl].hi)) {
+                best_s = s;
+                best_l = bl;
+            }
+        }
+    }
+    const T cot = cth / sth;
+    for (int l = 0; l < nl; ++l) {
+        if (L[l].kind != 1) continue;
+        const T dz = T(L[l].r_or_z) - p[2];
+        if (!(dz * cot > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
+        const T s = dz / cot;
+        if (!(s < best_s)) continue;
+        const HelixPoint<T> q = helix_at(p[0], p[1], p[4], -kb * p[3], s);
+        const T r = Tr<T>::sqrt_(q.X * q.X + q.Y * q.Y);
+        if (r < T(L[l].lo) || r > T(L[l].hi)) continue;
+        best_s = s;
+        best_l = l;
+    }
+    *s_out = best_s;
+    return best_l;
+}
+
+// LDS layout of one workgroup (W lanes), all arrays lane-minor
+struct FindShared {
+    float* pred;        // [28][W]  predicted (or frozen) state: par 6, cov 21, chi2
+    int32_t* meta;      // [4][W]   nhits, misses, status, (done | (layer + 1) << 8)
+    float* cchi2;       // [kMaxCands][W]  accepted hit chi2, ascending
+    int32_t* cbidx;     // [kMaxCands][W]  binned index of those hits
+    int32_t* nchild;    // [W]
+    int8_t* sel;        // [S][kMaxCands][2]  (parent slot, child index)
+    int32_t* nsel;      // [S]
+    uint8_t* ptr;       // [S][kMaxCands] merge cursors
+    kf_layer* layers;   // [n_layers]
+    int32_t* misc;      // [4] tile id
+};
+
+__host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl)
+{
+    size_t b = 0;
+    b += sizeof(float) * 28 * W;
+    b += sizeof(int32_t) * 4 * W;
+    b += sizeof(float) * kMaxCands * W;
+    b += sizeof(int32_t) * kMaxCands * W;
+    b += sizeof(int32_t) * W;
+    b += sizeof(int32_t) * S;
+    b += sizeof(kf_layer) * nl;
+    b += sizeof(int32_t) * 4;
+    b += 2 * S * kMaxCands;
+    b += S * kMaxCands;
+    return (b + 15) & ~size_t(15);
+}
+
+template <typename T, typename U>
+__global__ __launch_bounds__(256) void find_kernel(FindArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int W = blockDim.x;
+    const int S = a.seeds_per_tile;
+    const int MC = a.prm.max_cands;
+    const int nl = a.n_layers;
+    FindShared sh;
+    {
+        unsigned char* q = smem;
+        sh.pred = (float*)q;
+        q += sizeof(float) * 28 * W;
+        sh.meta = (int32_t*)q;
+        q += sizeof(int32_t) * 4 * W;
+        sh.cchi2 = (float*)q;
+        q += sizeof(float) * kMaxCands * W;
+        sh.cbidx = (int32_t*)q;
+        q += sizeof(int32_t) * kMaxCands * W;
+        sh.nchild = (int32_t*)q;
+        q += sizeof(int32_t) * W;
+        sh.nsel = (int32_t*)q;
+        q += sizeof(int32_t) * S;
+        sh.layers = (kf_layer*)q;
+        q += sizeof(kf_layer) * nl;
+        sh.misc = (int32_t*)q;
+        q += sizeof(int32_t) * 4;
+        sh.sel = (int8_t*)q;
+        q += 2 * S * kMaxCands;
+        sh.ptr = (uint8_t*)q;
+    }
+    const int t = threadIdx.x;
+    for (int l = t; l < nl; l += W) sh.layers[l] = a.layers[l];
+    const int s_loc = t / MC;
+    const int slot = t - s_loc * MC;
+    const bool lane_ok = s_loc < S;
+    const T kb = T(kKappa) * T(a.prm.bz);
+    const float cut = a.prm.chi2_cut;
+    unsigned long long n_prop = 0, n_upd = 0;
+    int2* bp_base = a.bp + (size_t)blockIdx.x * nl * S * kMaxCands;
+
+    for (;;) {
+        __syncthreads();
+        if (t == 0) sh.misc[0] = atomicAdd(a.tile_counter, 1);
+        __syncthreads();
+        const int tile = sh.misc[0];
+        if (tile >= a.n_tiles) break;
+
+        const int64_t g = (int64_t)tile * S + s_loc;
+        const bool valid = lane_ok && g < a.n_seeds;
+        const int sid = valid ? a.order[g] : 0;
+        int ev = valid ? a.seed_event[sid] : 0;
+        const bool bad_event = ev < 0 || ev >= a.n_events;
+        if (bad_event) ev = 0;
+        // candidate registers
+        T p[6], P[21];
+        float chi2 = 0.0f;
+        int nhits = 0, misses = 0;
+        uint32_t status = 0;
+        bool occupied = valid && slot == 0;
+        bool done = true;
+        if (occupied) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) p[k] = T(a.spar[k * a.sld + sid]);
+#pragma unroll
+            for (int k = 0; k < 21; ++k) P[k] = T(a.scov[k * a.sld + sid]);
+            chi2 = a.schi2[sid];
+            nhits = (a.sndf[sid] + 5) / 2;
+            status = a.sstatus[sid] | (bad_event ? (uint32_t)KF_ST_BADINPUT : 0u);
+            done = status != 0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) p[k] = T(0);
+#pragma unroll
+            for (int k = 0; k < 21; ++k) P[k] = T(0);
+        }
+        int nsteps = 0;
+        for (int step = 0; step < nl; ++step) {
+            const bool live = occupied && !done;
+            if (!__syncthreads_or(live)) break;
+            // ---- a3: navigate and propagate
+            int pl = -1;
+            if (live) {
+                T s;
+                const int layer = navigate(p, sh.layers, nl, a.prm, kb, &s, &status);
+                if (layer < 0) {
+                    done = true;
+                } else {
+                    ++n_prop;
+                    const kf_layer L = sh.layers[layer];
+                    transport(p, P, s, kb, L.kind, T(L.r_or_z));
+                    if (a.material) add_scatter(p, P, L.kind, T(L.x0), T(a.prm.mass));
+                    bool fin = true;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) fin &= isfinite(p[k]);
+                    if (fin) {
+                        pl = layer;
+                    } else {
+                        status |= KF_ST_NAN;
+                        done = true;
+                    }
+                }
+            }
+            // ---- a4: window and chi2 scan over the window's bins
+            float lc2[kMaxCands];
+            int32_t lid[kMaxCands], lbi[kMaxCands];
+#pragma unroll
+            for (int k = 0; k < kMaxCands; ++k) {
+                lc2[k] = 3.0e38f;
+                lid[k] = 0x7fffffff;
+                lbi[k] = -1;
+            }
+            int nacc = 0;
+            if (pl >= 0) {
+                const kf_layer L = sh.layers[pl];
+                bool scan = true;
+                const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+                const T pxx = P[pk(0, 0)], pyy = P[pk(1, 1)], pzz = P[pk(2, 2)];
+                const T wu = Tr<T>::sqrt_(T(cut) * (pxx + pyy + T(L.win_su) * T(L.win_su)));
+                const T tt = T(1.001) * wu / rho;
+                T dphi = tt >= T(1) ? T(kPi) : Tr<T>::asin_(tt) + T(1e-4);
+                if (dphi > T(0.5 * kPi)) dphi = T(kPi);
+                const bool all_phi = dphi >= T(kPi);
+                const T cos_dphi = all_phi ? T(-1) : Tr<T>::cos_(dphi);
+                const T sin_dphi = all_phi ? T(2) : Tr<T>::sin_(dphi);
+                T wv, vlo, vhi;
+                if (L.kind == 0) {
+                    wv = T(1.001) * Tr<T>::sqrt_(T(cut) * (pzz + T(L.win_sv) * T(L.win_sv))) + T(1e-4);
+                    vlo = p[2] - wv;
+                    vhi = p[2] + wv;
+                } else {
+                    wv = T(1.001) * Tr<T>::sqrt_(T(cut) * (pxx + pyy + T(L.win_sv) * T(L.win_sv))) +
+                         T(1e-4);
+                    vlo = rho * cos_dphi - wv;
+                    vhi = rho + wv;
+                }
+                // a non-finite covariance gives no usable window: no hits tested
+                if (!(dphi >= T(0)) || !(wv >= T(0)) || !(wv < T(1e30)) || !(rho > T(0))) scan = false;
+                const int np = L.nbin_phi, n2 = L.nbin_2;
+                int b_lo = 0, b_hi = np - 1;
+                if (!scan) b_hi = -1;
+                if (scan && !all_phi) {
+                    const T phi = Tr<T>::atan2_(p[1], p[0]);
+                    b_lo = (int)Tr<T>::floor_((phi - dphi + T(kPi)) * T(np) / T(2.0 * kPi));
+                    b_hi = (int)Tr<T>::floor_((phi + dphi + T(kPi)) * T(np) / T(2.0 * kPi));
+                    if (b_hi - b_lo + 1 >= np || b_hi < b_lo) {
+                        b_lo = 0;
+                        b_hi = np - 1;
+                    }
+                }
+                const int v0 = coord_bin_of(float(vlo), L.lo, L.hi, n2);
+                const int v1 = coord_bin_of(float(vhi), L.lo, L.hi, n2);
+                const T cpp = p[0] / rho, spp = p[1] / rho;
+                const int row0 = ev * a.bl.per_event + a.bl.base[pl];
+                for (int bb = b_lo; bb <= b_hi; ++bb) {
+                    const int bphi = ((bb % np) + np) % np;
+                    const int rb = row0 + bphi * n2;
+                    const int h0 = a.bin_off[rb + v0], h1 = a.bin_off[rb + v1 + 1];
+                    for (int k = h0; k < h1; ++k) {
+                        const float4 r0 = *(const float4*)&a.bh[k].x;
+                        const float4 r1 = *(const float4*)&a.bh[k].sv;
+                        const float hcp = r1.y, hsp = r1.z;
+                        // |azimuth difference| <= dphi (< pi/2): same half-plane, |sin| bounded
+                        if (!all_phi && (!(T(hcp) * cpp + T(hsp) * spp > T(0)) ||
+                                         Tr<T>::abs_(T(hsp) * cpp - T(hcp) * spp) > sin_dphi))
+                            continue;
+                        T rv;
+                        if (L.kind == 0) rv = T(r0.z) - p[2];
+                        else rv = T(hcp) * (T(r0.x) - p[0]) + T(hsp) * (T(r0.y) - p[1]);
+                        if (Tr<T>::abs_(rv) > wv) continue;
+                        HitFrame<U> f;
+                        f.hx = U(r0.x);
+                        f.hy = U(r0.y);
+                        f.hz = U(r0.z);
+                        f.c = U(hcp);
+                        f.s = U(hsp);
+                        f.vu = U(r0.w) * U(r0.w);
+                        f.vv = U(r1.x) * U(r1.x);
+                        const U c2u = hit_chi2<T, U>(p, P, f, L.kind);
+                        if (!(c2u < U(cut))) continue;
+                        float c = float(c2u);
+                        int32_t id = __float_as_int(r1.w);
+                        int32_t bi = k;
+                        ++nacc;
+#pragma unroll
+                        for (int q = 0; q < kMaxCands; ++q) {
+                            const bool lt = c < lc2[q] || (c == lc2[q] && id < lid[q]);
+                            const float tc = lt ? lc2[q] : c;
+                            const int32_t ti = lt ? lid[q] : id;
+                            const int32_t tb = lt ? lbi[q] : bi;
+                            lc2[q] = lt ? c : lc2[q];
+                            lid[q] = lt ? id : lid[q];
+                            lbi[q] = lt ? bi : lbi[q];
+                            c = tc;
+                            id = ti;
+                            bi = tb;
+                        }
+                    }
+                }
+            }
+            // ---- publish this lane's predicted state and children
+            if (lane_ok) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) sh.pred[k * W + t] = float(p[k]);
+#pragma unroll
+                for (int k = 0; k < 21; ++k) sh.pred[(6 + k) * W + t] = float(P[k]);
+                sh.pred[27 * W + t] = chi2;
+                sh.meta[0 * W + t] = nhits;
+                sh.meta[1 * W + t] = misses;
+                sh.meta[2 * W + t] = (int32_t)status;
+                sh.meta[3 * W + t] = (done ? 1 : 0) | ((pl + 1) << 8);
+                const int nk = nacc < MC ? nacc : MC;
+                sh.nchild[t] = occupied ? nk : -1;
+#pragma unroll
+                for (int k = 0; k < kMaxCands; ++k) {
+                    sh.cchi2[k * W + t] = lc2[k];
+                    sh.cbidx[k * W + t] = lbi[k];
+                }
+            }
+            __syncthreads();
+            // ---- a5: per-seed selection (k-way merge of per-parent sorted children)
+            if (valid && slot == 0) {
+                const int base = s_loc * MC;
+                int npar = 0;
+                for (int j = 0; j < MC; ++j) {
+                    if (sh.nchild[base + j] < 0) break;
+                    ++npar;
+                }
+                uint8_t* cur = sh.ptr + s_loc * kMaxCands;
+                for (int j = 0; j < npar; ++j) cur[j] = 0;
+                int nsel = 0;
+                for (int r = 0; r < MC; ++r) {
+                    int bj = -1, bnh = 0;
+                    float bc = 0.0f;
+                    for (int j = 0; j < npar; ++j) {
+                        const int tj = base + j;
+                        const int nk = sh.nchild[tj];
+                        const int c = cur[j];
+                        if (c > nk) continue;          // list exhausted (hits + the extra child)
+                        const int nh0 = sh.meta[0 * W + tj];
+                        const float c0 = sh.pred[27 * W + tj];
+                        int knh;
+                        float kc;
+                        if (c < nk) {
+                            knh = nh0 + 1;
+                            kc = c0 + sh.cchi2[c * W + tj];
+                        } else {
+                            knh = nh0;
+                            kc = c0;
+                        }
+                        if (bj < 0 || knh > bnh || (knh == bnh && kc < bc)) {
+                            bj = j;
+                            bnh = knh;
+                            bc = kc;
+                        }
+                    }
+                    if (bj < 0) break;
+                    sh.sel[(s_loc * kMaxCands + r) * 2 + 0] = (int8_t)bj;
+                    sh.sel[(s_loc * kMaxCands + r) * 2 + 1] = (int8_t)cur[bj];
+                    cur[bj]++;
+                    ++nsel;
+                }
+                sh.nsel[s_loc] = nsel;
+            }
+            __syncthreads();
+            // ---- a6: materialise the surviving children (Kalman update for hit children)
+            if (valid) {
+                const int nsel = sh.nsel[s_loc];
+                occupied = slot < nsel;
+                int2 bpe = make_int2(-1, 0xFF00);
+                if (occupied) {
+                    const int j = sh.sel[(s_loc * kMaxCands + slot) * 2 + 0];
+                    const int c = sh.sel[(s_loc * kMaxCands + slot) * 2 + 1];
+                    const int tj = s_loc * MC + j;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) p[k] = T(sh.pred[k * W + tj]);
+#pragma unroll
+                    for (int k = 0; k < 21; ++k) P[k] = T(sh.pred[(6 + k) * W + tj]);
+                    chi2 = sh.pred[27 * W + tj];
+                    nhits = sh.meta[0 * W + tj];
+                    misses = sh.meta[1 * W + tj];
+                    status = (uint32_t)sh.meta[2 * W + tj];
+                    const int m3 = sh.meta[3 * W + tj];
+                    done = (m3 & 1) != 0;
+                    const int ppl = (m3 >> 8) - 1;
+                    const int nk = sh.nchild[tj];
+                    if (ppl >= 0) {
+                        if (c < nk) {
+                            const int bi = sh.cbidx[c * W + tj];
+                            const BinnedHit hh = a.bh[bi];
+                            HitFrame<U> f;
+                            f.hx = U(hh.x);
+                            f.hy = U(hh.y);
+                            f.hz = U(hh.z);
+                            f.c = U(hh.cphi);
+                            f.s = U(hh.sphi);
+                            f.vu = U(hh.su) * U(hh.su);
+                            f.vv = U(hh.sv) * U(hh.sv);
+                            U c2 = U(0);
+                            const int r = kf_update<T, U>(p, P, f, sh.layers[ppl].kind, &c2);
+                            ++n_upd;
+                            if (r) {
+                                status |= (uint32_t)r;
+                                done = true;
+                            }
+                            chi2 = chi2 + sh.cchi2[c * W + tj];
+                            nhits += 1;
+                            misses = 0;
+                            bpe = make_int2(hh.idx, j | (ppl << 8));
+                        } else {
+                            misses += 1;
+                            if (misses > a.prm.max_miss) done = true;
+                            bpe = make_int2(-1, j | (ppl << 8));
+                        }
+                    } else {
+                        bpe = make_int2(-1, j | 0xFF00);
+                    }
+                    bp_base[((size_t)step * S + s_loc) * kMaxCands + slot] = bpe;
+                }
+            }
+            ++nsteps;
+        }
+        // ---- a7: best candidate (slot 0, candidates are kept sorted) and its hit list
+        if (valid && slot == 0) {
+            const int64_t ol = a.n_layers;
+            int32_t* oh = a.out_hits + (int64_t)sid * ol;
+            for (int l = 0; l < nl; ++l) oh[l] = -1;
+            for (int k = 0; k < 3; ++k) {
+                const int hi = a.seed_hits[k * a.sld + sid];
+                if (hi >= 0 && hi < a.n_hits) {
+                    const int hl = a.hit_layer[hi];
+                    if (hl >= 0 && hl < nl) oh[hl] = hi;
+                }
+            }
+            int k = 0;
+            for (int st = nsteps - 1; st >= 0; --st) {
+                const int2 e = bp_base[((size_t)st * S + s_loc) * kMaxCands + k];
+                const int lay = (e.y >> 8) & 0xFF;
+                if (e.x >= 0 && lay < nl) oh[lay] = e.x;
+                k = e.y & 0xFF;
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) a.opar[q * a.old + sid] = float(p[q]);
+#pragma unroll
+            for (int q = 0; q < 21; ++q) a.ocov[q * a.old + sid] = float(P[q]);
+            a.ochi2[sid] = chi2;
+            a.ondf[sid] = 2 * nhits - 5;
+            a.ostatus[sid] = status;
+        }
+    }
+    if (a.counters) {
+        // wave-level reduction of the per-lane counts, one atomic per wave
+        for (int o = 32; o > 0; o >>= 1) {
+            n_prop += __shfl_xor(n_prop, o);
+            n_upd += __shfl_xor(n_upd, o);
+        }
+        if ((t & 63) == 0) {
+            atomicAdd(&a.counters[0], n_prop);
+            atomicAdd(&a.counters[1], n_upd);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+namespace {
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+}
+
+size_t find_shared_size(int W, int S, int nl) { return find_shared_bytes(W, S, nl); }
+
+hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, int* out)
+{
+    const size_t lds = find_shared_bytes(W, S, nl);
+    if (prec == KF_PREC_FP32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float>, W, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double>, W, lds);
+}
+
+hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    unsigned g = blocks_for(n, 256);
+    if (g > 4096) g = 4096;
+    fill_i32_kernel<<<g, 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event_off, int n_events,
+                      const kf_layer* d_layers, int n_layers, hipStream_t s)
+{
+    hipError_t e;
+    const int64_t total = (int64_t)n_events * pl.bl.per_event;
+    if ((e = launch_fill(pl.cnt, total + 1, 0, s)) != hipSuccess) return e;
+    if (h->n > 0) {
+        bin_count_kernel<<<blocks_for(h->n, 256), 256, 0, s>>>(h->n, h->x, h->y, h->z, h->layer,
+                                                               event_off, n_events, d_layers,
+                                                               n_layers, pl.bl, pl.cnt, pl.hit_key);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    size_t tb = pl.cub_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(pl.cub_tmp, tb, pl.cnt, pl.off, (int)(total + 1), s);
+    if (e != hipSuccess) return e;
+    if (h->n > 0) {
+        bin_scatter_kernel<<<blocks_for(h->n, 256), 256, 0, s>>>(h->n, h->x, h->y, h->z, h->su,
+                                                                 h->sv, pl.hit_key, pl.off, pl.cnt,
+                                                                 (BinnedHit*)pl.binned);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
+                             const int32_t* event_off, int n_events, int largest_first,
+                             hipStream_t s)
+{
+    if (seeds->n == 0) return hipSuccess;
+    seed_key_kernel<<<blocks_for(seeds->n, 256), 256, 0, s>>>(
+        seeds->n, seeds->ld, (const float*)seeds->par, seed_event, event_off, n_events,
+        largest_first, pl.keys_in, pl.vals_in);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t tb = pl.cub_bytes;
+    return hipcub::DeviceRadixSort::SortPairs(pl.cub_tmp, tb, pl.keys_in, pl.keys_out, pl.vals_in,
+                                              pl.order, (int)seeds->n, 0, 64, s);
+}
+
+size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t n_seeds,
+                 int n_layers, int grid, int seeds_per_tile)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? (void*)((char*)base + off) : nullptr;
+        off += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    const int64_t nb = (int64_t)n_events * pl->bl.per_event + 1;
+    const int64_t ns = n_seeds > 0 ? n_seeds : 1;
+    const int64_t nh = n_hits > 0 ? n_hits : 1;
+    pl->cnt = (int32_t*)take(sizeof(int32_t) * nb);
+    pl->off = (int32_t*)take(sizeof(int32_t) * nb);
+    pl->hit_key = (int32_t*)take(sizeof(int32_t) * nh);
+    pl->binned = take(sizeof(BinnedHit) * nh);
+    pl->keys_in = (uint64_t*)take(sizeof(uint64_t) * ns);
+    pl->keys_out = (uint64_t*)take(sizeof(uint64_t) * ns);
+    pl->vals_in = (int32_t*)take(sizeof(int32_t) * ns);
+    pl->order = (int32_t*)take(sizeof(int32_t) * ns);
+    pl->cub_bytes = cub_bytes_needed(nb, n_seeds);
+    pl->cub_tmp = take(pl->cub_bytes);
+    pl->bp = (int2*)take(sizeof(int2) * (size_t)grid * n_layers * seeds_per_tile * kMaxCands);
+    pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);
+    return off;
+}
+
+size_t cub_bytes_needed(int64_t n_bins_plus1, int64_t n_seeds)
+{
+    size_t a = 0, b = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, a, (int32_t*)nullptr, (int32_t*)nullptr,
+                                           (int)n_bins_plus1);
+    if (n_seeds > 0)
+        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                                 (int32_t*)nullptr, (int32_t*)nullptr, (int)n_seeds, 0,
+                                                 64);
+    return a > b ? a : b;
+}
+
+hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, hipStream_t s)
+{
+    const size_t lds = find_shared_bytes(W, a.seeds_per_tile, a.n_layers);
+    if (prec == KF_PREC_FP32)
+        find_kernel<float, float><<<grid, W, lds, s>>>(a);
+    else
+        find_kernel<float, double><<<grid, W, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace kfmi

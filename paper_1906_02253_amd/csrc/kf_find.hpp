@@ -1,0 +1,94 @@
+// Internal interface of the finding kernels (kf_find.hip) for the C-ABI layer.
+#pragma once
+
+#include "kf_internal.hpp"
+
+namespace kfmi {
+
+constexpr int kMaxCands = 8;    // candidate slots per seed the kernel is built for
+
+// One binned hit: position, sigmas, azimuth cos/sin and the caller's hit index.
+struct alignas(16) BinnedHit {
+    float x, y, z, su;
+    float sv, cphi, sphi;
+    int32_t idx;
+};
+
+// Bin layout of one event: layer l owns bins [base[l], base[l] + nbin_phi*nbin_2),
+// phi-major; events are per_event bins apart.
+struct BinLayout {
+    int32_t base[kMaxLayers];
+    int32_t per_event;
+};
+
+struct FindArgs {
+    // binned hits of all events
+    const BinnedHit* bh;
+    const int32_t* bin_off;
+    BinLayout bl;
+    int64_t n_hits;
+    const int32_t* hit_layer;
+    // seeds (par/cov/chi2/ndf/status after the seed fit), SoA with leading dim sld
+    int64_t n_seeds, sld;
+    const float* spar;
+    const float* scov;
+    const float* schi2;
+    const int32_t* sndf;
+    const uint32_t* sstatus;
+    const int32_t* seed_event;
+    int n_events;
+    const int32_t* seed_hits;     // [3][sld]
+    const int32_t* order;         // seeds in processing order
+    // outputs
+    int32_t* out_hits;            // [n_seeds][n_layers]
+    int64_t old;
+    float* opar;
+    float* ocov;
+    float* ochi2;
+    int32_t* ondf;
+    uint32_t* ostatus;
+    // scratch
+    int2* bp;                     // per workgroup: [n_layers][S][kMaxCands] back-pointers
+    int32_t* tile_counter;
+    unsigned long long* counters; // optional: [0] propagations, [1] updates
+    // geometry and parameters
+    const kf_layer* layers;
+    int n_layers;
+    kf_params prm;
+    int material;
+    int n_tiles;
+    int seeds_per_tile;
+};
+
+// Device scratch of one kf_find call, carved from the context workspace.
+struct FindPlan {
+    BinLayout bl;
+    int32_t* cnt;       // [n_events * per_event + 1]
+    int32_t* off;       // [n_events * per_event + 1]
+    int32_t* hit_key;   // [n_hits]
+    void* binned;       // [n_hits] records of 32 bytes
+    uint64_t* keys_in;  // [n_seeds]
+    uint64_t* keys_out;
+    int32_t* vals_in;
+    int32_t* order;
+    void* cub_tmp;
+    size_t cub_bytes;
+    int2* bp;
+    int32_t* tile_counter;
+};
+
+// Lays out the scratch of a call from `base` (nullptr: only sizes it); returns bytes.
+size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t n_seeds,
+                 int n_layers, int grid, int seeds_per_tile);
+size_t find_shared_size(int W, int S, int nl);
+hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, int* out);
+size_t cub_bytes_needed(int64_t n_bins_plus1, int64_t n_seeds);
+hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event_off, int n_events,
+                      const kf_layer* d_layers, int n_layers, hipStream_t s);
+hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
+                             const int32_t* event_off, int n_events, int largest_first,
+                             hipStream_t s);
+hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, hipStream_t s);
+
+}  // namespace kfmi

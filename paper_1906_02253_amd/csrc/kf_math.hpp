@@ -36,6 +36,7 @@ template <> struct Tr<float> {
     __device__ static inline float fmod_(float x, float y) { return fmodf(x, y); }
     __device__ static inline float asin_(float x) { return asinf(x); }
     __device__ static inline float cos_(float x) { return cosf(x); }
+    __device__ static inline float sin_(float x) { return sinf(x); }
     __device__ static inline float floor_(float x) { return floorf(x); }
 };
 template <> struct Tr<double> {
@@ -47,6 +48,7 @@ template <> struct Tr<double> {
     __device__ static inline double fmod_(double x, double y) { return fmod(x, y); }
     __device__ static inline double asin_(double x) { return asin(x); }
     __device__ static inline double cos_(double x) { return cos(x); }
+    __device__ static inline double sin_(double x) { return sin(x); }
     __device__ static inline double floor_(double x) { return floor(x); }
 };
 
