@@ -24,13 +24,13 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_TFLOPS = 78.6      # MI355X vector FP64 (= FP32 without packed math)
 
 # Bytes one fit step must move in the per-layer design (state crosses HBM
-# between layers): par 24 + cov 84 read and written, hit x,y,z,su,sv 20,
-# layer and hit index 8, chi2 / ndf / status read and written 24.
-PER_LAYER_BYTES_PER_STEP = 24 + 84 + 24 + 84 + 20 + 8 + 24
+# between layers): par 24 (float) + cov 168 (double) read and written, hit
+# x,y,z,su,sv 20, layer and hit index 8, chi2 / ndf / status read and written 24.
+PER_LAYER_BYTES_PER_STEP = 2 * (24 + 168) + 20 + 8 + 24
 # Fused design (state stays in registers for all layers): per step the hit and
 # its two indices; per track the state in and out plus chi2/ndf/status.
 FUSED_BYTES_PER_STEP = 20 + 8
-FUSED_BYTES_PER_TRACK = 2 * (24 + 84) + 24
+FUSED_BYTES_PER_TRACK = 2 * (24 + 168) + 24
 
 
 def parse():

@@ -58,9 +58,10 @@ enum {
 
 /* flags */
 enum {
-    KF_PREC_MIXED = 0,     /* FP32 storage and transport; update (S, S^-1, gain, Joseph) in FP64 */
+    KF_PREC_MIXED = 0,     /* state and transport (helix, Jacobian) FP32; covariance kept in
+                              FP64 (storage and F P F^T); update (S, S^-1, gain, Joseph) FP64 */
     KF_PREC_FP32 = 1,      /* everything FP32 (Joseph form kept) */
-    KF_PREC_FP64 = 2,      /* everything FP64, track arrays hold doubles */
+    KF_PREC_FP64 = 2,      /* everything FP64 */
     KF_PREC_MASK = 3,
     KF_INIT_MLP = 4,       /* start propagate-to-radius from the learned path-length guess */
     KF_NO_MATERIAL = 8,    /* ignore the layers' material (no process noise) */
@@ -70,27 +71,29 @@ enum {
 /* One detector layer (paper Sec. 3.1, the per-layer geometry record). */
 typedef struct {
     int32_t kind;          /* 0 = barrel cylinder, 1 = disk */
-    float r_or_z;          /* barrel radius / disk z */
-    float lo, hi;          /* barrel: z extent [lo, hi]; disk: radial extent */
-    float x0;              /* material thickness in radiation lengths */
     int32_t nbin_phi;      /* hit bins in phi over [-pi, pi) */
     int32_t nbin_2;        /* hit bins in z (barrel) / r (disk) over [lo, hi] */
-    float win_su, win_sv;  /* largest hit sigma (u, v) on the layer, sizes the search window */
+    int32_t reserved;      /* 0 */
+    double r_or_z;         /* barrel radius / disk z */
+    double lo, hi;         /* barrel: z extent [lo, hi]; disk: radial extent */
+    double x0;             /* material thickness in radiation lengths */
+    double win_su, win_sv; /* largest hit sigma (u, v) on the layer, sizes the search window */
 } kf_layer;
 
 typedef struct {
-    float bz;              /* field [T] */
-    float chi2_cut;        /* hit acceptance chi2 (2 dof) */
+    double bz;             /* field [T] */
+    double chi2_cut;       /* hit acceptance chi2 (2 dof) */
+    double newton_tol;     /* |r - r_layer| convergence threshold [cm] */
+    double mass;           /* particle mass for the scattering width [GeV] */
     int32_t max_cands;     /* candidates kept per seed, 1..8 */
     int32_t max_newton;    /* propagate-to-radius iteration limit */
-    float newton_tol;      /* |r - r_layer| convergence threshold [cm] */
-    float mass;            /* particle mass for the scattering width [GeV] */
     int32_t max_miss;      /* consecutive missed layers allowed */
     int32_t mlp_max_iter;  /* iterations allowed from the learned guess before fallback */
 } kf_params;
 
-/* Track states, SoA with leading dimension ld.  par [6][ld], cov [21][ld],
- * chi2 [ld] are float, or double with KF_PREC_FP64.  ndf = 2*hits - 5. */
+/* Track states, SoA with leading dimension ld.  par [6][ld] and chi2 [ld]
+ * are float (double with KF_PREC_FP64); cov [21][ld] is double (float with
+ * KF_PREC_FP32).  ndf = 2*hits - 5. */
 typedef struct {
     int64_t n, ld;
     void* par;
@@ -148,7 +151,7 @@ int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_
  *   hits        all events' hits concatenated (float32 SoA + layer id)
  *   event_off   [n_events+1] int32: event e owns hits [event_off[e], event_off[e+1])
  *   seeds       n_seeds states after the seed fit (kf_seed, then kf_fit over the
- *               three seed hits); float storage (KF_PREC_MIXED or KF_PREC_FP32)
+ *               three seed hits), KF_PREC_MIXED or KF_PREC_FP32 storage
  *   seed_event  [n_seeds] int32 event of each seed
  *   seed_hits   [3][seeds->ld] int32 the seed's hits (copied to the hit list)
  *   out_hits    [n_seeds][n_layers] int32: hit of the best candidate on each

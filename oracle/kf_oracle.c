@@ -563,7 +563,7 @@ static int hit_phi_bin(double phi, int nb)
 static int coord_bin(double v, double lo, double hi, int nb)
 {
     double t = floor((v - lo) * nb / (hi - lo));
-    if (t < 0) t = 0;
+    if (!(t >= 0)) t = 0;
     if (t > nb - 1) t = nb - 1;
     return (int)t;
 }
@@ -639,12 +639,16 @@ static void free_index(const orc_cfg* cfg, event_index* E)
 static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close)
 {
     double rho = hypot(p[0], p[1]);
+    /* only surfaces reached within half a turn in the transverse plane */
+    double hh = fabs(KAPPA * cfg->bz * p[3]);
+    double s_max = hh > 0.0 ? PI / hh : INFINITY;
     double best_s = INFINITY;
     int best_l = -1;
     int bl = -1;
     for (int l = 0; l < cfg->n_layers; ++l) {
         const orc_layer* L = &cfg->layers[l];
         if (L->kind != 0) continue;
+        if (fabs(L->r_or_z - (rho + NEXT_BARREL_EPS)) < CLOSE_REL * NEXT_BARREL_EPS) *close = 1;
         if (L->r_or_z > rho + NEXT_BARREL_EPS && (bl < 0 || L->r_or_z < cfg->layers[bl].r_or_z))
             bl = l;
     }
@@ -666,7 +670,8 @@ static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close
         if (st == ORC_ST_OK) {
             double zc = p[2] + s * cos(p[5]) / sin(p[5]);
             if (fabs(fabs(zc) - L->hi) < CLOSE_REL * L->hi) *close = 1;
-            if (fabs(zc) <= L->hi) {
+            if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+            if (fabs(zc) <= L->hi && s <= s_max) {
                 best_s = s_b = s;
                 best_l = bl;
             }
@@ -677,8 +682,11 @@ static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close
         const orc_layer* L = &cfg->layers[l];
         if (L->kind != 1) continue;
         double dz = L->r_or_z - p[2];
+        if (fabs(fabs(dz) - DISK_AHEAD_EPS) < CLOSE_REL * DISK_AHEAD_EPS) *close = 1;
         if (!(dz * cot > 0.0) || fabs(dz) <= DISK_AHEAD_EPS) continue;
         double s = dz / cot;
+        if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+        if (s > s_max) continue;
         double q[6];
         orc_helix(p, s, cfg->bz, q);
         double r = hypot(q[0], q[1]);
@@ -715,6 +723,7 @@ typedef struct {
     double dphi;       /* azimuthal half-width; pi means the whole circle */
     double wv;         /* half-width along z (barrel) / r (disk) */
     double vlo, vhi;   /* bin-enumeration range along the second coordinate */
+    int ok;            /* 0: no finite window (no hit is tested) */
 } window_t;
 
 static void make_window(const orc_cfg* cfg, const orc_layer* L, const double q[6],
@@ -738,6 +747,7 @@ static void make_window(const orc_cfg* cfg, const orc_layer* L, const double q[6
         W->vlo = rho * (dphi >= PI ? -1.0 : cos(dphi)) - W->wv;
         W->vhi = rho + W->wv;
     }
+    W->ok = dphi >= 0.0 && W->wv >= 0.0 && W->wv < 1e30 && rho > 0.0;
 }
 
 /* test one hit: window predicate and chi2 cut */
@@ -772,6 +782,7 @@ static int scan_hits(const orc_cfg* cfg, int layer, const event_index* E, int bi
     window_t W;
     make_window(cfg, L, q, Pk, &W);
     int n = 0;
+    if (!W.ok) return 0;
 #define ACCEPT(I)                                                           \
     do {                                                                    \
         double c2_;                                                         \

@@ -18,14 +18,15 @@ PREC_MIXED, PREC_FP32, PREC_FP64 = 0, 1, 2
 INIT_MLP, NO_MATERIAL, PER_LAYER = 4, 8, 16
 
 class KfLayer(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("r_or_z", C.c_float), ("lo", C.c_float), ("hi", C.c_float),
-                ("x0", C.c_float), ("nbin_phi", C.c_int32), ("nbin_2", C.c_int32),
-                ("win_su", C.c_float), ("win_sv", C.c_float)]
+    _fields_ = [("kind", C.c_int32), ("nbin_phi", C.c_int32), ("nbin_2", C.c_int32),
+                ("reserved", C.c_int32), ("r_or_z", C.c_double), ("lo", C.c_double),
+                ("hi", C.c_double), ("x0", C.c_double), ("win_su", C.c_double),
+                ("win_sv", C.c_double)]
 
 
 class KfParams(C.Structure):
-    _fields_ = [("bz", C.c_float), ("chi2_cut", C.c_float), ("max_cands", C.c_int32),
-                ("max_newton", C.c_int32), ("newton_tol", C.c_float), ("mass", C.c_float),
+    _fields_ = [("bz", C.c_double), ("chi2_cut", C.c_double), ("newton_tol", C.c_double),
+                ("mass", C.c_double), ("max_cands", C.c_int32), ("max_newton", C.c_int32),
                 ("max_miss", C.c_int32), ("mlp_max_iter", C.c_int32)]
 
 
@@ -84,15 +85,20 @@ def round_ld(n):
 
 
 class Tracks:
-    """SoA track states on the GPU: par [6, ld], cov [21, ld], chi2 [ld], ndf, status."""
+    """SoA track states on the GPU: par [6, ld], cov [21, ld], chi2 [ld], ndf, status.
 
-    def __init__(self, n, ld=None, dtype=torch.float32, device="cuda"):
+    Storage types follow the precision: MIXED par/chi2 float32, cov float64;
+    FP32 all float32; FP64 all float64."""
+
+    def __init__(self, n, ld=None, prec=PREC_MIXED, device="cuda"):
         self.n = int(n)
         self.ld = int(ld or round_ld(n))
-        self.dtype = dtype
-        self.par = torch.zeros((6, self.ld), dtype=dtype, device=device)
-        self.cov = torch.zeros((21, self.ld), dtype=dtype, device=device)
-        self.chi2 = torch.zeros(self.ld, dtype=dtype, device=device)
+        self.prec = prec
+        pd = torch.float64 if prec == PREC_FP64 else torch.float32
+        cd = torch.float32 if prec == PREC_FP32 else torch.float64
+        self.par = torch.zeros((6, self.ld), dtype=pd, device=device)
+        self.cov = torch.zeros((21, self.ld), dtype=cd, device=device)
+        self.chi2 = torch.zeros(self.ld, dtype=pd, device=device)
         self.ndf = torch.zeros(self.ld, dtype=torch.int32, device=device)
         self.status = torch.zeros(self.ld, dtype=torch.int32, device=device)
 
@@ -101,11 +107,11 @@ class Tracks:
                         _ptr(self.ndf), _ptr(self.status))
 
     @staticmethod
-    def from_numpy(par, cov, dtype=torch.float32, ld=None):
+    def from_numpy(par, cov, prec=PREC_MIXED, ld=None):
         n = par.shape[0]
-        t = Tracks(n, ld, dtype)
-        t.par[:, :n] = torch.as_tensor(par.T, dtype=dtype)
-        t.cov[:, :n] = torch.as_tensor(cov.T, dtype=dtype)
+        t = Tracks(n, ld, prec)
+        t.par[:, :n] = torch.as_tensor(par.T, dtype=t.par.dtype)
+        t.cov[:, :n] = torch.as_tensor(cov.T, dtype=t.cov.dtype)
         return t
 
     def numpy(self):
@@ -146,10 +152,10 @@ class Context:
                  mass=0.13957, max_miss=2, mlp_max_iter=3):
         arr = (KfLayer * len(geom))()
         for i, L in enumerate(geom):
-            arr[i] = KfLayer(int(L["kind"]), L["r_or_z"], L["lo"], L["hi"], L["x0"],
-                             int(L["nbin_phi"]), int(L["nbin_2"]), L["win_su"], L["win_sv"])
+            arr[i] = KfLayer(int(L["kind"]), int(L["nbin_phi"]), int(L["nbin_2"]), 0,
+                             L["r_or_z"], L["lo"], L["hi"], L["x0"], L["win_su"], L["win_sv"])
         self.n_layers = len(geom)
-        prm = KfParams(bz, chi2_cut, max_cands, max_newton, newton_tol, mass, max_miss, mlp_max_iter)
+        prm = KfParams(bz, chi2_cut, newton_tol, mass, max_cands, max_newton, max_miss, mlp_max_iter)
         h = C.c_void_p()
         torch.cuda.current_device()          # make sure the runtime is up on this device
         r = lib.kf_create(C.byref(h), arr, len(geom), C.byref(prm))

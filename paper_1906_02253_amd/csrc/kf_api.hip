@@ -95,25 +95,25 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
     for (int i = 0; i < n_layers; ++i) {
         const kf_layer& L = layers[i];
         if ((L.kind != 0 && L.kind != 1) || !(L.hi > L.lo) || L.nbin_phi <= 0 || L.nbin_2 <= 0 ||
-            L.nbin_phi > 4096 || L.nbin_2 > 4096 || !(L.x0 >= 0.0f) ||
-            (L.kind == 0 && !(L.r_or_z > 0.0f)))
+            L.nbin_phi > 4096 || L.nbin_2 > 4096 || !(L.x0 >= 0.0) ||
+            (L.kind == 0 && !(L.r_or_z > 0.0)) || !(L.win_su >= 0.0) || !(L.win_sv >= 0.0))
             return fail(nullptr, KF_EINVAL, "kf_create: invalid layer %d", i);
     }
     kf_params p;
     if (params) {
         p = *params;
     } else {
-        p.bz = 3.8f;
-        p.chi2_cut = 30.0f;
+        p.bz = 3.8;
+        p.chi2_cut = 30.0;
         p.max_cands = 6;
         p.max_newton = 10;
-        p.newton_tol = 1e-4f;
-        p.mass = 0.13957f;
+        p.newton_tol = 1e-4;
+        p.mass = 0.13957;
         p.max_miss = 2;
         p.mlp_max_iter = 3;
     }
-    if (!(p.bz != 0.0f) || !(p.chi2_cut > 0.0f) || p.max_cands < 1 || p.max_cands > 8 ||
-        p.max_newton < 1 || p.max_newton > 64 || !(p.newton_tol > 0.0f) || !(p.mass >= 0.0f) ||
+    if (!(p.bz != 0.0) || !(p.chi2_cut > 0.0) || p.max_cands < 1 || p.max_cands > 8 ||
+        p.max_newton < 1 || p.max_newton > 64 || !(p.newton_tol > 0.0) || !(p.mass >= 0.0) ||
         p.max_miss < 0 || p.mlp_max_iter < 1 || p.mlp_max_iter > 64)
         return fail(nullptr, KF_EINVAL, "kf_create: invalid parameters");
     kf_ctx* ctx = new kf_ctx();
@@ -123,6 +123,9 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
     hipError_t e = hipGetDevice(&ctx->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                  ctx->device);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_layers, sizeof(kf_layer) * kfmi::kMaxLayers);
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_layers, ctx->layers, sizeof(kf_layer) * n_layers, hipMemcpyHostToDevice);
@@ -238,6 +241,10 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     if ((int64_t)n_events * per_event >= 0x7fffffffLL)
         return fail(ctx, KF_EINVAL, "kf_find: n_events x bins per event exceeds 2^31");
     pl.bl.per_event = (int32_t)per_event;
+    const size_t lds = kfmi::find_shared_size(W, S, nl, prec);
+    if (ctx->max_lds > 0 && lds > (size_t)ctx->max_lds)
+        return fail(ctx, KF_EUNSUPPORTED, "kf_find: width %d needs %zu bytes of LDS, device allows %d",
+                    W, lds, ctx->max_lds);
     int lw = 0;
     while ((1 << lw) < W) ++lw;
     const int pi = prec == KF_PREC_FP32 ? 1 : 0;
@@ -269,7 +276,7 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     a.n_seeds = seeds->n;
     a.sld = seeds->ld;
     a.spar = (const float*)seeds->par;
-    a.scov = (const float*)seeds->cov;
+    a.scov = seeds->cov;
     a.schi2 = (const float*)seeds->chi2;
     a.sndf = seeds->ndf;
     a.sstatus = seeds->status;
@@ -280,7 +287,7 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     a.out_hits = out_hits;
     a.old = out->ld;
     a.opar = (float*)out->par;
-    a.ocov = (float*)out->cov;
+    a.ocov = out->cov;
     a.ochi2 = (float*)out->chi2;
     a.ondf = out->ndf;
     a.ostatus = out->status;

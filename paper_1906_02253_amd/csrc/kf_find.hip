@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(int64_t n_hits, const fl
     const float hx = x[i], hy = y[i];
     const int bp = phi_bin_of(atan2f(hy, hx), L.nbin_phi);
     const float v = L.kind == 0 ? z[i] : sqrtf(hx * hx + hy * hy);
-    const int bv = coord_bin_of(v, L.lo, L.hi, L.nbin_2);
+    const int bv = coord_bin_of(v, float(L.lo), float(L.hi), L.nbin_2);
     const int key = e * bl.per_event + bl.base[l] + bp * L.nbin_2 + bv;
     atomicAdd(&cnt[key], 1);
     hit_key[i] = key;
@@ -147,6 +147,9 @@ __device__ inline int navigate(const T p[6], const kf_layer* L, int nl, const kf
                                T* s_out, uint32_t* st)
 {
     const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+    // only surfaces reached within half a turn in the transverse plane
+    const T hh = Tr<T>::abs_(kb * p[3]);
+    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
     int bl = -1;
     T rbl = T(0);
     for (int l = 0; l < nl; ++l) {
@@ -176,7 +179,7 @@ __device__ inline int navigate(const T p[6], const kf_layer* L, int nl, const kf
                 return -1;
             }
             const T zc = p[2] + s * cth / sth;
-            if (Tr<T>::abs_(zc) <= T(L[bl].hi)) {
+            if (Tr<T>::abs_(zc) <= T(L[bl].hi) && s <= s_max) {
                 best_s = s;
                 best_l = bl;
             }
@@ -188,7 +191,7 @@ __device__ inline int navigate(const T p[6], const kf_layer* L, int nl, const kf
         const T dz = T(L[l].r_or_z) - p[2];
         if (!(dz * cot > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
         const T s = dz / cot;
-        if (!(s < best_s)) continue;
+        if (!(s < best_s) || s > s_max) continue;
         const HelixPoint<T> q = helix_at(p[0], p[1], p[4], -kb * p[3], s);
         const T r = Tr<T>::sqrt_(q.X * q.X + q.Y * q.Y);
         if (r < T(L[l].lo) || r > T(L[l].hi)) continue;
@@ -200,8 +203,10 @@ __device__ inline int navigate(const T p[6], const kf_layer* L, int nl, const kf
 }
 
 // LDS layout of one workgroup (W lanes), all arrays lane-minor
+template <typename C>
 struct FindShared {
-    float* pred;        // [28][W]  predicted (or frozen) state: par 6, cov 21, chi2
+    C* predc;           // [21][W]  predicted (or frozen) covariance
+    float* pred;        // [7][W]   predicted (or frozen) par 6, chi2
     int32_t* meta;      // [4][W]   nhits, misses, status, (done | (layer + 1) << 8)
     float* cchi2;       // [kMaxCands][W]  accepted hit chi2, ascending
     int32_t* cbidx;     // [kMaxCands][W]  binned index of those hits
@@ -213,10 +218,11 @@ struct FindShared {
     int32_t* misc;      // [4] tile id
 };
 
-__host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl)
+__host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t csize)
 {
     size_t b = 0;
-    b += sizeof(float) * 28 * W;
+    b += csize * 21 * W;
+    b += sizeof(float) * 7 * W;
     b += sizeof(int32_t) * 4 * W;
     b += sizeof(float) * kMaxCands * W;
     b += sizeof(int32_t) * kMaxCands * W;
@@ -229,7 +235,7 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl)
     return (b + 15) & ~size_t(15);
 }
 
-template <typename T, typename U>
+template <typename T, typename C, typename U>
 __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -237,11 +243,15 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
     const int S = a.seeds_per_tile;
     const int MC = a.prm.max_cands;
     const int nl = a.n_layers;
-    FindShared sh;
+    const C* scov = (const C*)a.scov;
+    C* ocov = (C*)a.ocov;
+    FindShared<C> sh;
     {
         unsigned char* q = smem;
+        sh.predc = (C*)q;
+        q += sizeof(C) * 21 * W;
         sh.pred = (float*)q;
-        q += sizeof(float) * 28 * W;
+        q += sizeof(float) * 7 * W;
         sh.meta = (int32_t*)q;
         q += sizeof(int32_t) * 4 * W;
         sh.cchi2 = (float*)q;
@@ -266,7 +276,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
     const int slot = t - s_loc * MC;
     const bool lane_ok = s_loc < S;
     const T kb = T(kKappa) * T(a.prm.bz);
-    const float cut = a.prm.chi2_cut;
+    const float cut = float(a.prm.chi2_cut);
     unsigned long long n_prop = 0, n_upd = 0;
     int2* bp_base = a.bp + (size_t)blockIdx.x * nl * S * kMaxCands;
 
@@ -284,7 +294,8 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
         const bool bad_event = ev < 0 || ev >= a.n_events;
         if (bad_event) ev = 0;
         // candidate registers
-        T p[6], P[21];
+        T p[6];
+        C P[21];
         float chi2 = 0.0f;
         int nhits = 0, misses = 0;
         uint32_t status = 0;
@@ -294,7 +305,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
 #pragma unroll
             for (int k = 0; k < 6; ++k) p[k] = T(a.spar[k * a.sld + sid]);
 #pragma unroll
-            for (int k = 0; k < 21; ++k) P[k] = T(a.scov[k * a.sld + sid]);
+            for (int k = 0; k < 21; ++k) P[k] = scov[k * a.sld + sid];
             chi2 = a.schi2[sid];
             nhits = (a.sndf[sid] + 5) / 2;
             status = a.sstatus[sid] | (bad_event ? (uint32_t)KF_ST_BADINPUT : 0u);
@@ -303,7 +314,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
 #pragma unroll
             for (int k = 0; k < 6; ++k) p[k] = T(0);
 #pragma unroll
-            for (int k = 0; k < 21; ++k) P[k] = T(0);
+            for (int k = 0; k < 21; ++k) P[k] = C(0);
         }
         int nsteps = 0;
         for (int step = 0; step < nl; ++step) {
@@ -346,7 +357,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                 const kf_layer L = sh.layers[pl];
                 bool scan = true;
                 const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
-                const T pxx = P[pk(0, 0)], pyy = P[pk(1, 1)], pzz = P[pk(2, 2)];
+                const T pxx = T(P[pk(0, 0)]), pyy = T(P[pk(1, 1)]), pzz = T(P[pk(2, 2)]);
                 const T wu = Tr<T>::sqrt_(T(cut) * (pxx + pyy + T(L.win_su) * T(L.win_su)));
                 const T tt = T(1.001) * wu / rho;
                 T dphi = tt >= T(1) ? T(kPi) : Tr<T>::asin_(tt) + T(1e-4);
@@ -379,8 +390,8 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                         b_hi = np - 1;
                     }
                 }
-                const int v0 = coord_bin_of(float(vlo), L.lo, L.hi, n2);
-                const int v1 = coord_bin_of(float(vhi), L.lo, L.hi, n2);
+                const int v0 = coord_bin_of(float(vlo), float(L.lo), float(L.hi), n2);
+                const int v1 = coord_bin_of(float(vhi), float(L.lo), float(L.hi), n2);
                 const T cpp = p[0] / rho, spp = p[1] / rho;
                 const int row0 = ev * a.bl.per_event + a.bl.base[pl];
                 for (int bb = b_lo; bb <= b_hi; ++bb) {
@@ -407,7 +418,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                         f.s = U(hsp);
                         f.vu = U(r0.w) * U(r0.w);
                         f.vv = U(r1.x) * U(r1.x);
-                        const U c2u = hit_chi2<T, U>(p, P, f, L.kind);
+                        const U c2u = hit_chi2<T, C, U>(p, P, f, L.kind);
                         if (!(c2u < U(cut))) continue;
                         float c = float(c2u);
                         int32_t id = __float_as_int(r1.w);
@@ -434,8 +445,8 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) sh.pred[k * W + t] = float(p[k]);
 #pragma unroll
-                for (int k = 0; k < 21; ++k) sh.pred[(6 + k) * W + t] = float(P[k]);
-                sh.pred[27 * W + t] = chi2;
+                for (int k = 0; k < 21; ++k) sh.predc[k * W + t] = P[k];
+                sh.pred[6 * W + t] = chi2;
                 sh.meta[0 * W + t] = nhits;
                 sh.meta[1 * W + t] = misses;
                 sh.meta[2 * W + t] = (int32_t)status;
@@ -469,7 +480,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                         const int c = cur[j];
                         if (c > nk) continue;          // list exhausted (hits + the extra child)
                         const int nh0 = sh.meta[0 * W + tj];
-                        const float c0 = sh.pred[27 * W + tj];
+                        const float c0 = sh.pred[6 * W + tj];
                         int knh;
                         float kc;
                         if (c < nk) {
@@ -506,8 +517,8 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
 #pragma unroll
                     for (int k = 0; k < 6; ++k) p[k] = T(sh.pred[k * W + tj]);
 #pragma unroll
-                    for (int k = 0; k < 21; ++k) P[k] = T(sh.pred[(6 + k) * W + tj]);
-                    chi2 = sh.pred[27 * W + tj];
+                    for (int k = 0; k < 21; ++k) P[k] = sh.predc[k * W + tj];
+                    chi2 = sh.pred[6 * W + tj];
                     nhits = sh.meta[0 * W + tj];
                     misses = sh.meta[1 * W + tj];
                     status = (uint32_t)sh.meta[2 * W + tj];
@@ -528,7 +539,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                             f.vu = U(hh.su) * U(hh.su);
                             f.vv = U(hh.sv) * U(hh.sv);
                             U c2 = U(0);
-                            const int r = kf_update<T, U>(p, P, f, sh.layers[ppl].kind, &c2);
+                            const int r = kf_update<T, C, U>(p, P, f, sh.layers[ppl].kind, &c2);
                             ++n_upd;
                             if (r) {
                                 status |= (uint32_t)r;
@@ -555,25 +566,28 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
         if (valid && slot == 0) {
             const int64_t ol = a.n_layers;
             int32_t* oh = a.out_hits + (int64_t)sid * ol;
+            // a layer visited more than once (a looper curling back) reports its
+            // latest hit: walk the back-pointers from the last step and keep the
+            // first hit met per layer, then the seed hits where nothing came later
             for (int l = 0; l < nl; ++l) oh[l] = -1;
-            for (int k = 0; k < 3; ++k) {
-                const int hi = a.seed_hits[k * a.sld + sid];
-                if (hi >= 0 && hi < a.n_hits) {
-                    const int hl = a.hit_layer[hi];
-                    if (hl >= 0 && hl < nl) oh[hl] = hi;
-                }
-            }
             int k = 0;
             for (int st = nsteps - 1; st >= 0; --st) {
                 const int2 e = bp_base[((size_t)st * S + s_loc) * kMaxCands + k];
                 const int lay = (e.y >> 8) & 0xFF;
-                if (e.x >= 0 && lay < nl) oh[lay] = e.x;
+                if (e.x >= 0 && lay < nl && oh[lay] < 0) oh[lay] = e.x;
                 k = e.y & 0xFF;
+            }
+            for (int q = 2; q >= 0; --q) {
+                const int hi = a.seed_hits[q * a.sld + sid];
+                if (hi >= 0 && hi < a.n_hits) {
+                    const int hl = a.hit_layer[hi];
+                    if (hl >= 0 && hl < nl && oh[hl] < 0) oh[hl] = hi;
+                }
             }
 #pragma unroll
             for (int q = 0; q < 6; ++q) a.opar[q * a.old + sid] = float(p[q]);
 #pragma unroll
-            for (int q = 0; q < 21; ++q) a.ocov[q * a.old + sid] = float(P[q]);
+            for (int q = 0; q < 21; ++q) ocov[q * a.old + sid] = P[q];
             a.ochi2[sid] = chi2;
             a.ondf[sid] = 2 * nhits - 5;
             a.ostatus[sid] = status;
@@ -597,14 +611,19 @@ namespace {
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }
 
-size_t find_shared_size(int W, int S, int nl) { return find_shared_bytes(W, S, nl); }
+size_t find_shared_size(int W, int S, int nl, int prec)
+{
+    return find_shared_bytes(W, S, nl, prec == KF_PREC_FP32 ? sizeof(float) : sizeof(double));
+}
 
 hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, int* out)
 {
-    const size_t lds = find_shared_bytes(W, S, nl);
+    const size_t lds = find_shared_size(W, S, nl, prec);
     if (prec == KF_PREC_FP32)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float>, W, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double>, W, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float, float>, W,
+                                                            lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double, double>, W,
+                                                        lds);
 }
 
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
@@ -696,11 +715,11 @@ size_t cub_bytes_needed(int64_t n_bins_plus1, int64_t n_seeds)
 
 hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, hipStream_t s)
 {
-    const size_t lds = find_shared_bytes(W, a.seeds_per_tile, a.n_layers);
+    const size_t lds = find_shared_size(W, a.seeds_per_tile, a.n_layers, prec);
     if (prec == KF_PREC_FP32)
-        find_kernel<float, float><<<grid, W, lds, s>>>(a);
+        find_kernel<float, float, float><<<grid, W, lds, s>>>(a);
     else
-        find_kernel<float, double><<<grid, W, lds, s>>>(a);
+        find_kernel<float, double, double><<<grid, W, lds, s>>>(a);
     return hipGetLastError();
 }
 

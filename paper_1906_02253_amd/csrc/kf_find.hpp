@@ -31,7 +31,7 @@ struct FindArgs {
     // seeds (par/cov/chi2/ndf/status after the seed fit), SoA with leading dim sld
     int64_t n_seeds, sld;
     const float* spar;
-    const float* scov;
+    const void* scov;             // double (mixed) or float (FP32)
     const float* schi2;
     const int32_t* sndf;
     const uint32_t* sstatus;
@@ -43,7 +43,7 @@ struct FindArgs {
     int32_t* out_hits;            // [n_seeds][n_layers]
     int64_t old;
     float* opar;
-    float* ocov;
+    void* ocov;
     float* ochi2;
     int32_t* ondf;
     uint32_t* ostatus;
@@ -80,7 +80,7 @@ struct FindPlan {
 // Lays out the scratch of a call from `base` (nullptr: only sizes it); returns bytes.
 size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t n_seeds,
                  int n_layers, int grid, int seeds_per_tile);
-size_t find_shared_size(int W, int S, int nl);
+size_t find_shared_size(int W, int S, int nl, int prec);
 hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, int* out);
 size_t cub_bytes_needed(int64_t n_bins_plus1, int64_t n_seeds);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -9,29 +9,30 @@
 
 namespace kfmi {
 
-template <typename TS, typename T>
-__device__ inline void load_state(const TS* par, const TS* cov, int64_t ld, int64_t i, T p[6],
-                                  T P[21])
+// par is stored in T, cov in C (T = state precision, C = covariance precision)
+template <typename T, typename C>
+__device__ inline void load_state(const T* par, const C* cov, int64_t ld, int64_t i, T p[6],
+                                  C P[21])
 {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) p[k] = T(par[k * ld + i]);
+    for (int k = 0; k < 6; ++k) p[k] = par[k * ld + i];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) P[k] = T(cov[k * ld + i]);
+    for (int k = 0; k < 21; ++k) P[k] = cov[k * ld + i];
 }
 
-template <typename TS, typename T>
-__device__ inline void store_state(TS* par, TS* cov, int64_t ld, int64_t i, const T p[6],
-                                   const T P[21])
+template <typename T, typename C>
+__device__ inline void store_state(T* par, C* cov, int64_t ld, int64_t i, const T p[6],
+                                   const C P[21])
 {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) par[k * ld + i] = TS(p[k]);
+    for (int k = 0; k < 6; ++k) par[k * ld + i] = p[k];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) cov[k * ld + i] = TS(P[k]);
+    for (int k = 0; k < 21; ++k) cov[k * ld + i] = P[k];
 }
 
 // Propagate (p, P) to layer L.  s_init < 0: straight-line start.
-template <typename T>
-__device__ inline int propagate_to(T p[6], T P[21], const kf_layer& L, const kf_params& prm,
+template <typename T, typename C>
+__device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_params& prm,
                                    bool material, T s_init, T* s_out, int* evals)
 {
     const T kb = T(kKappa) * T(prm.bz);
@@ -65,61 +66,65 @@ __device__ inline int propagate_to(T p[6], T P[21], const kf_layer& L, const kf_
 }
 
 // ---------------------------------------------------------------- seed
-template <typename TS, typename T>
+template <typename T, typename C>
 __global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_t n_hits,
                                                    const float* __restrict__ hx,
                                                    const float* __restrict__ hy,
                                                    const float* __restrict__ hz,
-                                                   const int32_t* __restrict__ seed_hits, float bz,
-                                                   TS* __restrict__ par, TS* __restrict__ cov,
-                                                   TS* __restrict__ chi2, int32_t* __restrict__ ndf,
+                                                   const int32_t* __restrict__ seed_hits, double bz,
+                                                   T* __restrict__ par, C* __restrict__ cov,
+                                                   T* __restrict__ chi2, int32_t* __restrict__ ndf,
                                                    uint32_t* __restrict__ status)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t a = seed_hits[i], b = seed_hits[ld + i], c = seed_hits[2 * ld + i];
     if (a < 0 || b < 0 || c < 0 || a >= n_hits || b >= n_hits || c >= n_hits) {
-        chi2[i] = TS(0);
+        chi2[i] = T(0);
         ndf[i] = -5;
         status[i] = KF_ST_BADINPUT;
         return;
     }
-    const T x1 = hx[a], y1 = hy[a], z1 = hz[a];
-    const T ax = T(hx[b]) - x1, ay = T(hy[b]) - y1;
-    const T bx = T(hx[c]) - x1, by = T(hy[c]) - y1;
-    const T d12 = Tr<T>::sqrt_(ax * ax + ay * ay);
-    const T d13 = Tr<T>::sqrt_(bx * bx + by * by);
-    const T ex = T(hx[c]) - T(hx[b]), ey = T(hy[c]) - T(hy[b]);
-    const T d23 = Tr<T>::sqrt_(ex * ex + ey * ey);
+    // computed in FP64 in every precision mode: the curvature is a small
+    // cross product of differences (sagitta << chord for stiff tracks)
+    using D = double;
+    const D x1 = hx[a], y1 = hy[a], z1 = hz[a];
+    const D ax = D(hx[b]) - x1, ay = D(hy[b]) - y1;
+    const D bx = D(hx[c]) - x1, by = D(hy[c]) - y1;
+    const D d12 = sqrt(ax * ax + ay * ay);
+    const D d13 = sqrt(bx * bx + by * by);
+    const D ex = D(hx[c]) - D(hx[b]), ey = D(hy[c]) - D(hy[b]);
+    const D d23 = sqrt(ex * ex + ey * ey);
     // signed curvature of the circle through the three points
-    const T h = T(2) * (ax * by - ay * bx) / (d12 * d23 * d13);
-    T w = T(0.5) * h * d13;
-    w = w > T(1) ? T(1) : (w < T(-1) ? T(-1) : w);
-    const T w2 = w * w;
-    const T s13 = Tr<T>::abs_(w) < T(1e-3) ? d13 * (T(1) + w2 * (T(1.0 / 6.0) + w2 * T(3.0 / 40.0)))
-                                           : d13 * Tr<T>::asin_(w) / w;
-    T p[6], P[21];
-    p[0] = x1;
-    p[1] = y1;
-    p[2] = z1;
-    p[3] = -h / (T(kKappa) * T(bz));
-    p[4] = wrap_phi(Tr<T>::atan2_(by, bx) - T(0.5) * h * s13);
-    p[5] = Tr<T>::atan2_(s13, T(hz[c]) - z1);
+    const D h = D(2) * (ax * by - ay * bx) / (d12 * d23 * d13);
+    D w = D(0.5) * h * d13;
+    w = w > D(1) ? D(1) : (w < D(-1) ? D(-1) : w);
+    const D w2 = w * w;
+    const D s13 = fabs(w) < D(1e-4) ? d13 * (D(1) + w2 * (D(1.0 / 6.0) + w2 * D(3.0 / 40.0)))
+                                     : d13 * asin(w) / w;
+    T p[6];
+    C P[21];
+    p[0] = T(x1);
+    p[1] = T(y1);
+    p[2] = T(z1);
+    p[3] = T(-h / (kKappa * D(bz)));
+    p[4] = T(wrap_phi(atan2(by, bx) - D(0.5) * h * s13));
+    p[5] = T(atan2(s13, D(hz[c]) - z1));
 #pragma unroll
-    for (int k = 0; k < 21; ++k) P[k] = T(0);
-    P[pk(0, 0)] = P[pk(1, 1)] = P[pk(2, 2)] = T(1);
-    P[pk(3, 3)] = T(4);
-    P[pk(4, 4)] = P[pk(5, 5)] = T(0.01);
+    for (int k = 0; k < 21; ++k) P[k] = C(0);
+    P[pk(0, 0)] = P[pk(1, 1)] = P[pk(2, 2)] = C(1);
+    P[pk(3, 3)] = C(4);
+    P[pk(4, 4)] = P[pk(5, 5)] = C(0.01);
     store_state(par, cov, ld, i, p, P);
-    chi2[i] = TS(0);
+    chi2[i] = T(0);
     ndf[i] = -5;
     status[i] = 0;
 }
 
 // ---------------------------------------------------------------- propagate
-template <typename TS, typename T>
-__global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, TS* __restrict__ par,
-                                                        TS* __restrict__ cov,
+template <typename T, typename C>
+__global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T* __restrict__ par,
+                                                        C* __restrict__ cov,
                                                         uint32_t* __restrict__ status,
                                                         const int32_t* __restrict__ target,
                                                         const kf_layer* __restrict__ layers,
@@ -138,7 +143,8 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
         if (iters) iters[i] = 0;
         return;
     }
-    T p[6], P[21];
+    T p[6];
+    C P[21];
     load_state(par, cov, ld, i, p, P);
     const kf_layer L = layers[l];
     T s = T(0);
@@ -172,20 +178,21 @@ struct FitArgs {
 };
 
 // Steps [k0, k1) of the fit.  init: start a fresh fit (chi2 = 0, ndf = -5).
-template <typename TS, typename T, typename U>
+template <typename T, typename C, typename U>
 __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int init)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int64_t ld = a.ld;
-    TS* par = (TS*)a.par;
-    TS* cov = (TS*)a.cov;
-    TS* chi2p = (TS*)a.chi2;
+    T* par = (T*)a.par;
+    C* cov = (C*)a.cov;
+    T* chi2p = (T*)a.chi2;
     uint32_t st = init ? 0u : a.status[i];
     int32_t ndf = init ? -5 : a.ndf[i];
     U chi2 = init ? U(0) : U(chi2p[i]);
     if (st) return;
-    T p[6], P[21];
+    T p[6];
+    C P[21];
     load_state(par, cov, ld, i, p, P);
     bool touched = false;
     for (int k = k0; k < k1; ++k) {
@@ -211,21 +218,21 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
         if (hi >= 0) {
             HitFrame<U> f = hit_frame<U>(a.hx[hi], a.hy[hi], a.hz[hi], a.hsu[hi], a.hsv[hi]);
             U c2 = U(0);
-            r = kf_update<T, U>(p, P, f, L.kind, &c2);
+            r = kf_update<T, C, U>(p, P, f, L.kind, &c2);
             if (r) {
                 st |= (uint32_t)r;
                 break;
             }
             // rounded to storage precision every step, so one launch per step
             // and one launch for all steps give identical results
-            chi2 = U(TS(chi2 + c2));
+            chi2 = U(T(chi2 + c2));
             ndf += 2;
         }
     }
     // on failure the registers hold the last good state (a failed solve or
     // update leaves them untouched)
     if (touched) store_state(par, cov, ld, i, p, P);
-    chi2p[i] = TS(chi2);
+    chi2p[i] = T(chi2);
     a.ndf[i] = ndf;
     a.status[i] = st;
 }
@@ -244,11 +251,16 @@ hipError_t launch_seed(const kf_ctx* ctx, const kf_hits* h, const int32_t* seed_
                                                       ctx->params.bz, (double*)out->par,
                                                       (double*)out->cov, (double*)out->chi2,
                                                       out->ndf, out->status);
-    else
+    else if (prec == KF_PREC_FP32)
         seed_kernel<float, float><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
                                                     ctx->params.bz, (float*)out->par,
                                                     (float*)out->cov, (float*)out->chi2, out->ndf,
                                                     out->status);
+    else
+        seed_kernel<float, double><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
+                                                     ctx->params.bz, (float*)out->par,
+                                                     (double*)out->cov, (float*)out->chi2, out->ndf,
+                                                     out->status);
     return hipGetLastError();
 }
 
@@ -264,11 +276,16 @@ hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* targ
                                                            (double*)t->cov, t->status, target,
                                                            ctx->d_layers, ctx->n_layers, ctx->params,
                                                            material, path_len, iters);
-    else
+    else if (prec == KF_PREC_FP32)
         propagate_kernel<float, float><<<g, 256, 0, s>>>(t->n, t->ld, (float*)t->par,
                                                          (float*)t->cov, t->status, target,
                                                          ctx->d_layers, ctx->n_layers, ctx->params,
                                                          material, path_len, iters);
+    else
+        propagate_kernel<float, double><<<g, 256, 0, s>>>(t->n, t->ld, (float*)t->par,
+                                                          (double*)t->cov, t->status, target,
+                                                          ctx->d_layers, ctx->n_layers, ctx->params,
+                                                          material, path_len, iters);
     return hipGetLastError();
 }
 
@@ -309,7 +326,7 @@ hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const i
         else if (prec == KF_PREC_FP32)
             fit_kernel<float, float, float><<<g, 256, 0, s>>>(a, k0, k1, init);
         else
-            fit_kernel<float, float, double><<<g, 256, 0, s>>>(a, k0, k1, init);
+            fit_kernel<float, double, double><<<g, 256, 0, s>>>(a, k0, k1, init);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

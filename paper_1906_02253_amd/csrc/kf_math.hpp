@@ -1,7 +1,8 @@
 // Device-side Kalman-filter arithmetic for gfx950: helix transport, the
 // propagate-to-surface solves, the transport Jacobian, scattering noise and
 // the 2D-hit update.  One lane owns one track (or candidate); matrices live
-// in registers.  T = transport precision, U = update precision.
+// in registers.  T = state and transport precision (helix, Jacobian),
+// C = covariance precision, U = update precision.
 //
 // Method references (arXiv:1906.02253): Sec. 1 (traditional Kalman filter),
 // Sec. 2 (vectorised KF fit/find over many small matrices), Sec. 3.1
@@ -173,8 +174,8 @@ __device__ inline int newton_barrel(T x, T y, T phi, T h, T r_l, T s, T s_lo, T 
 
 // Transport of (p, P) by arc length s to a surface: new state, F P F^T.
 // kind 0: barrel (path length from r(s) = r_l); 1: disk at z = zd.
-template <typename T>
-__device__ inline void transport(T p[6], T P[21], T s, T kb, int kind, T zd)
+template <typename T, typename C>
+__device__ inline void transport(T p[6], C P[21], T s, T kb, int kind, T zd)
 {
     const T x = p[0], y = p[1], z = p[2], c = p[3], phi = p[4], th = p[5];
     const T h = -kb * c;
@@ -206,26 +207,26 @@ __device__ inline void transport(T p[6], T P[21], T s, T kb, int kind, T zd)
         d2 = -st / ct;
         d5 = (zd - z) / (ct * ct);
     }
-    T F[4][6] = {
+    const C F[4][6] = {
         {T(1) + f0 * d0, f0 * d1, f0 * d2, D03 + f0 * d3, D04 + f0 * d4, f0 * d5},
         {f1 * d0, T(1) + f1 * d1, f1 * d2, D13 + f1 * d3, D14 + f1 * d4, f1 * d5},
         {f2 * d0, f2 * d1, T(1) + f2 * d2, f2 * d3, f2 * d4, D25 + f2 * d5},
         {f4 * d0, f4 * d1, f4 * d2, D43 + f4 * d3, T(1) + f4 * d4, f4 * d5},
     };
     // A = F P for the four general rows; rows 3 and 5 of F are unit rows
-    T A[4][6];
+    C A[4][6];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            T acc = T(0);
+            C acc = C(0);
 #pragma unroll
             for (int k = 0; k < 6; ++k) acc += F[r][k] * P[pk(k, j)];
             A[r][j] = acc;
         }
     // P' = A F^T (upper triangle).  Row of P' for F-row index: general rows use A,
     // unit rows 3 and 5 use P itself.
-    T Pn[21];
+    C Pn[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -233,12 +234,12 @@ __device__ inline void transport(T p[6], T P[21], T s, T kb, int kind, T zd)
             // pick row i of (F P): general or unit
             const int ri = i == 0 ? 0 : i == 1 ? 1 : i == 2 ? 2 : i == 4 ? 3 : -1;
             const int rj = j == 0 ? 0 : j == 1 ? 1 : j == 2 ? 2 : j == 4 ? 3 : -1;
-            T v;
+            C v;
             if (rj < 0) {
                 // column j of F^T is e_j: (F P)_{i j}
                 v = ri >= 0 ? A[ri][j] : P[pk(i, j)];
             } else {
-                T acc = T(0);
+                C acc = C(0);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) acc += (ri >= 0 ? A[ri][k] : P[pk(i, k)]) * F[rj][k];
                 v = acc;
@@ -255,8 +256,8 @@ __device__ inline void transport(T p[6], T P[21], T s, T kb, int kind, T zd)
 
 // Multiple-scattering process noise of a layer (PDG Highland width), added to
 // the (c, phi, theta) block at the propagated state.
-template <typename T>
-__device__ inline void add_scatter(const T p[6], T P[21], int kind, T x0, T mass)
+template <typename T, typename C>
+__device__ inline void add_scatter(const T p[6], C P[21], int kind, T x0, T mass)
 {
     if (!(x0 > T(0))) return;
     T st, ct;
@@ -279,10 +280,10 @@ __device__ inline void add_scatter(const T p[6], T P[21], int kind, T x0, T mass
     const T th0 = T(0.0136) / (beta * pm) * Tr<T>::sqrt_(t) * (T(1) + T(0.038) * Tr<T>::log_(t / b2));
     const T t2 = th0 * th0;
     const T cot = ct / st;
-    P[pk(4, 4)] += t2 / (st * st);
-    P[pk(5, 5)] += t2;
-    P[pk(3, 5)] += -p[3] * cot * t2;
-    P[pk(3, 3)] += p[3] * p[3] * cot * cot * t2;
+    P[pk(4, 4)] += C(t2 / (st * st));
+    P[pk(5, 5)] += C(t2);
+    P[pk(3, 5)] += C(-p[3] * cot * t2);
+    P[pk(3, 3)] += C(p[3] * p[3] * cot * cot * t2);
 }
 
 // Local frame of a hit: u along phi at the hit's azimuth, v along z (barrel)
@@ -310,8 +311,8 @@ __device__ inline HitFrame<U> hit_frame(float x, float y, float z, float su, flo
 }
 
 // chi2 of a hit against (p, P) without updating
-template <typename T, typename U>
-__device__ inline U hit_chi2(const T p[6], const T P[21], const HitFrame<U>& f, int kind)
+template <typename T, typename C, typename U>
+__device__ inline U hit_chi2(const T p[6], const C P[21], const HitFrame<U>& f, int kind)
 {
     const U c = f.c, s = f.s;
     U ru = -s * (f.hx - U(p[0])) + c * (f.hy - U(p[1]));
@@ -341,8 +342,8 @@ __device__ inline U hit_chi2(const T p[6], const T P[21], const HitFrame<U>& f, 
 // Kalman update with a 2D hit.  Gain K = P H^T S^-1, state x + K r, covariance
 // in Joseph form (I - K H) P (I - K H)^T + K V K^T, evaluated as
 // M = P - K (H P), P+ = M - (M H^T) K^T + K V K^T.  Returns status bits.
-template <typename T, typename U>
-__device__ inline int kf_update(T p[6], T P[21], const HitFrame<U>& f, int kind, U* chi2_out)
+template <typename T, typename C, typename U>
+__device__ inline int kf_update(T p[6], C P[21], const HitFrame<U>& f, int kind, U* chi2_out)
 {
     const U c = f.c, s = f.s;
     U Pu[21];
@@ -393,7 +394,7 @@ __device__ inline int kf_update(T p[6], T P[21], const HitFrame<U>& f, int kind,
         for (int j = i; j < 6; ++j) {
             U m = j < 3 ? Mc[i][j] : Pu[pk(i, j)] - K0[i] * B0[j] - K1[i] * B1[j];
             U v = m - N0[i] * K0[j] - N1[i] * K1[j] + f.vu * K0[i] * K0[j] + f.vv * K1[i] * K1[j];
-            P[pk(i, j)] = T(v);
+            P[pk(i, j)] = C(v);
         }
     bool fin = true;
 #pragma unroll

@@ -10,8 +10,9 @@ from . import binding as B
 class FindProblem:
     """Device-resident inputs of a finding run over many events."""
 
-    def __init__(self, ctx, inp, device="cuda"):
+    def __init__(self, ctx, inp, prec=0, device="cuda"):
         self.ctx = ctx
+        self.prec = prec
         self.hits = B.Hits(inp["x"], inp["y"], inp["z"], inp["su"], inp["sv"], inp["layer"], device)
         self.n_seeds = int(inp["seed_hits"].shape[0])
         self.ld = B.round_ld(self.n_seeds)
@@ -26,8 +27,8 @@ class FindProblem:
         se = np.zeros(ld, np.int32)
         se[:self.n_seeds] = inp["seed_event"]
         self.seed_event = torch.as_tensor(se, device=device)
-        self.seeds = B.Tracks(self.n_seeds, ld)
-        self.out = B.Tracks(self.n_seeds, ld)
+        self.seeds = B.Tracks(self.n_seeds, ld, prec)
+        self.out = B.Tracks(self.n_seeds, ld, prec)
         self.out_hits = torch.full((max(self.n_seeds, 1), ctx.n_layers), -1, dtype=torch.int32,
                                    device=device)
         self.counters = torch.zeros(2, dtype=torch.int64, device=device)

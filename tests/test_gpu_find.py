@@ -38,21 +38,25 @@ def _gpu_find(K, geom, inp, width=256, largest_first=True, flags=0):
     import torch
     ctx = K.Context(geom)
     ctx.set_find_config(width, largest_first)
-    fp = K.pipeline.FindProblem(ctx, inp)
+    fp = K.pipeline.FindProblem(ctx, inp, prec=flags & 3)
     fp.run(flags)
     torch.cuda.synchronize()
     return fp.results()
 
 
-def _check_parity(g, o, label):
+def _check_parity(g, o, label, outlier_frac=0.0):
+    """outlier_frac: fraction of seeds allowed between 1e-4 and 1e-3 relative
+    parameter error (FP32 state transport on long looper arcs)."""
     n_same, n_exc, bad = CM.compare_find(g, o)
     ns = g["hits"].shape[0]
     print(f"{label}: {n_same}/{ns} identical, {n_exc} excused (oracle ties), {len(bad)} unexplained")
     assert len(bad) == 0, (label, bad[:10], g["hits"][bad[:3]], o["hits"][bad[:3]])
     same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
     err = CM.par_error(g["par"][same], o["par"][same])
-    print(f"{label}: max rel par err {err.max(axis=0)}")
-    assert err.max() < 1.0
+    n_out = int((err.max(axis=1) >= CM.REL).sum())
+    print(f"{label}: max rel par err {err.max(axis=0)}; {n_out} seeds above 1e-4")
+    assert n_out <= outlier_frac * same.sum()
+    assert err.max() < 10 * CM.REL
     cerr = CM.chi2_error(g["chi2"][same], o["chi2"][same], o["ndf"][same])
     assert cerr.max() < CM.CHI2_REL, cerr.max()
     assert np.array_equal(g["ndf"][same], o["ndf"][same])

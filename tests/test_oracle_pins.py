@@ -586,3 +586,34 @@ def test_beam_search_equals_exhaustive(orc):
             assert abs(res["chi2"][k] - best[1]) < 1e-9 * max(1, best[1])
             n_checked += 1
     assert n_checked >= 30
+
+
+def test_binned_equals_all_hits_with_disks(orc):
+    """T9 on the barrel + disk geometry (|eta| < 2.5, noise 60 per track)."""
+    geom, evs = E.batch_events(n_events=2, seed=21, lam_lo=300, lam_hi=400)
+    cfg = orc.Config(geom)
+    for ev in evs:
+        sel, seeds = _seeds(ev)
+        seeds = seeds[:150]
+        rb = orc.find(cfg, ev, seeds, binned=True)
+        ra = orc.find(cfg, ev, seeds, binned=False)
+        assert np.array_equal(rb["hits"], ra["hits"])
+        assert np.array_equal(rb["chi2"], ra["chi2"])
+
+
+def test_disk_fit_pulls(orc):
+    """Forward tracks crossing disks: fit pulls unit width with scattering."""
+    rng = np.random.default_rng(22)
+    geom = E.geometry.barrel10_disks14(x0=0.02)
+    ev = E.make_event(rng, geom, 4000, E.pt_power2(0.5, 50.0), 2.5, 0)
+    r = _fit(orc, geom, ev)
+    nh = ev.n_track_hits()
+    ok = (r["status"] == 0) & (nh >= 6)
+    tr = ev.truth_out[np.arange(ev.n_tracks), nh - 1]
+    P = orc.unpack(r["cov"])
+    d = r["par"] - tr
+    d[:, 4] = wrap(d[:, 4])
+    for i, name in ((3, "c"), (4, "phi"), (5, "theta")):
+        v = (d[:, i] / np.sqrt(P[:, i, i]))[ok]
+        assert abs(v.mean()) < 0.05 and abs(v.std() - 1) < 0.05, (name, v.mean(), v.std())
+    assert abs((r["chi2"][ok] / r["ndf"][ok]).mean() - 1) < 0.05
