@@ -1,13 +1,21 @@
 """Throughput benchmark: KF propagate+update steps per second on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload fit]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-One timed step = one pass of the hot path over one batch of synthetic input
-already resident in HBM: seed every track from its first three hits, then the
-Kalman fit over all its layers (propagate to the layer, scattering noise,
-2D-hit update).  A KF step is one (track, layer) propagation with its update.
-Prints ONE JSON line (metric, value, roofline of the dominant kernel, CPU
-baseline of the FP64 oracle on a bounded sample).
+Workload: the uneven-multiplicity batch (64 events, track counts ~ Poisson
+with mean ~ U(200, 4000), 60 noise hits per track, ten barrel layers plus
+2 x 7 disks, |eta| < 2.5, 0.02 X0 per layer), synthetic.  One timed step is
+one pass of the whole finding path over the batch, inputs resident in HBM:
+seed every track from its first three hits (kf_seed), Kalman-fit the three
+seed hits (kf_fit), then kf_find (hit binning, seed ordering, the persistent
+finding kernel).  A KF step is one propagation of a track or candidate to a
+surface together with its update(s): the three seed-fit steps per seed plus
+the finding kernel's propagations (counted by the kernel itself).
+
+Prints ONE JSON line: metric, value, the roofline of the dominant kernel
+(the finding kernel, arithmetic-bound: algorithmic flops from the operation
+counts of its own code times its event counters, over its HIP-event time),
+the FP64 oracle timed on the host cores, and the fit kernels' figures.
 """
 import argparse
 import json
@@ -21,16 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_VECTOR_TFLOPS = 78.6      # MI355X vector FP64 (= FP32 without packed math)
+VECTOR_PEAK_TFLOPS = 78.6      # MI355X vector FP64, and FP32 without packed math
 
-# Bytes one fit step must move in the per-layer design (state crosses HBM
-# between layers): par 24 (float) + cov 168 (double) read and written, hit
-# x,y,z,su,sv 20, layer and hit index 8, chi2 / ndf / status read and written 24.
+# Per-layer fit design (state crosses HBM between layers): par 24 (float) and
+# cov 168 (double) read and written, hit x,y,z,su,sv 20, layer and hit index
+# 8, chi2 / ndf / status read and written 24.
 PER_LAYER_BYTES_PER_STEP = 2 * (24 + 168) + 20 + 8 + 24
-# Fused design (state stays in registers for all layers): per step the hit and
-# its two indices; per track the state in and out plus chi2/ndf/status.
-FUSED_BYTES_PER_STEP = 20 + 8
-FUSED_BYTES_PER_TRACK = 2 * (24 + 168) + 24
 
 
 def parse():
@@ -38,19 +42,28 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fit", choices=["fit"])
-    ap.add_argument("--tracks", type=int, default=4_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--width", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--fit-tracks", type=int, default=4_000_000)
     return ap.parse_args()
 
 
+def find_flops(cnt, oc):
+    """Algorithmic flops of the finding kernel from its event counters and the
+    operation counts of its arithmetic (special-function calls counted as one)."""
+    props, upd, chi2, newton, disk = [float(c) for c in cnt]
+    f = lambda k: oc[k]["ops"] + oc[k]["sfu"]
+    per_prop = f("nav_fixed") + f("barrel_setup") + f("transport_barrel") + f("window")
+    return (props * per_prop + newton * f("newton_eval") + disk * f("disk_eval")
+            + chi2 * f("hit_test") + upd * f("update"))
+
+
 def build_fit_set(n_total, n_unique=1_000_000, chunk=250_000, seed=3):
-    """Tracks of the precision workload's distribution (pT 0.3 / 100 GeV,
+    """Fit sample of the precision workload's distribution (pT 0.3 / 100 GeV,
     hit sigma_u log-uniform 0.002-0.01 cm, sigma_v = 5 sigma_u, ten barrel
     layers, no material): n_unique generated tracks replicated at distinct
-    addresses up to n_total.  Hits are laid out step-major, so step k of track
-    i is hit k*ld + i (coalesced gathers)."""
+    addresses up to n_total, hits step-major (step k of track i is hit k*ld+i)."""
     import eventgen as E
     ld = (n_total + 63) // 64 * 64
     ms = 10
@@ -92,77 +105,101 @@ def build_fit_set(n_total, n_unique=1_000_000, chunk=250_000, seed=3):
     return geom, ld, hits, lseq, hidx.astype(np.int32)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the KF path shards by event/track with no "
-              "exchange, and this build runs on a single MI355X; use --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    import paper_1906_02253_amd as K
-
-    torch.cuda.set_device(0)
-    t0 = time.time()
-    geom, ld, hits_np, lseq_np, hidx_np = build_fit_set(args.tracks)
-    n = args.tracks
-    print(f"# built {n} tracks in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-
-    dev = "cuda"
+def run_fit(K, torch, n, reps=5):
+    """Fused fit and per-layer fit of n tracks: kernel ms (HIP events) and rates."""
+    geom, ld, hits_np, lseq_np, hidx_np = build_fit_set(n)
     hits = K.Hits(hits_np["x"], hits_np["y"], hits_np["z"], hits_np["su"], hits_np["sv"],
                   hits_np["layer"])
-    lseq = torch.as_tensor(lseq_np, device=dev)
-    hidx = torch.as_tensor(hidx_np, device=dev)
+    lseq = torch.as_tensor(lseq_np, device="cuda")
+    hidx = torch.as_tensor(hidx_np, device="cuda")
     seed_hits = hidx[:3].contiguous()
     ctx = K.Context(geom)
     t = K.Tracks(n, ld)
     n_steps = int((lseq_np[:, :n] >= 0).sum())
-
     stream = torch.cuda.current_stream()
+    out = {}
+    for name, flags in (("fused", 0), ("per_layer", K.PER_LAYER)):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for r in range(-1, reps):
+            ctx.seed(hits, seed_hits, t)
+            if r >= 0:
+                ev[r][0].record(stream)
+            ctx.fit(t, hits, lseq, hidx, 10, flags=flags)
+            if r >= 0:
+                ev[r][1].record(stream)
+        torch.cuda.synchronize()
+        out[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    gbs = n_steps * PER_LAYER_BYTES_PER_STEP / (out["per_layer"] * 1e-3) / 1e9
+    return {"workload": f"fit of {n} tracks, precision-workload mix, 10 barrel layers, mixed precision",
+            "kf_steps": n_steps,
+            "fused_kernel_ms": out["fused"], "fused_steps_per_s": n_steps / (out["fused"] * 1e-3),
+            "per_layer_ms": out["per_layer"],
+            "per_layer_steps_per_s": n_steps / (out["per_layer"] * 1e-3),
+            "per_layer_hbm": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": gbs / HBM_PEAK_GBS,
+                              "bytes_per_step": PER_LAYER_BYTES_PER_STEP}}
 
-    def one_step(ev_pair=None):
-        ctx.seed(hits, seed_hits, t)
-        if ev_pair:
-            ev_pair[0].record(stream)
-        ctx.fit(t, hits, lseq, hidx, 10)
-        if ev_pair:
-            ev_pair[1].record(stream)
 
+def oracle_find_all(oracle, geom, evs, inp, threads):
+    """The FP64 oracle's seed fit + finding over every event; returns its
+    propagation count."""
+    cfg = oracle.Config(geom)
+    n_prop = 0
+    for e, ev in enumerate(evs):
+        m = np.nonzero(inp["seed_event"] == e)[0]
+        if m.size:
+            n_prop += oracle.find(cfg, ev, inp["seed_hits_local"][m], n_threads=threads)["n_prop"]
+    return n_prop
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: events are independent, the path shards by event "
+              "with no exchange, and this build runs on a single MI355X; use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import eventgen as E
+    import paper_1906_02253_amd as K
+    from paper_1906_02253_amd import pipeline
+    from paper_1906_02253_amd.build import OPCOUNT_JSON
+
+    with open(OPCOUNT_JSON) as f:
+        oc = json.load(f)
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    geom, evs = E.batch_events()
+    inp = E.find_inputs(evs)
+    n_seeds = int(inp["seed_hits"].shape[0])
+    print(f"# batch: {len(evs)} events, {n_seeds} seeds, {inp['x'].shape[0]} hits "
+          f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+
+    ctx = K.Context(geom)
+    ctx.set_find_config(args.width, True)
+    fp = pipeline.FindProblem(ctx, inp)
     for _ in range(args.warmup):
-        one_step()
+        fp.run()
     torch.cuda.synchronize()
-    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-             for _ in range(args.steps)]
+    c0 = fp.counters.clone()
+    ctx.set_timing(args.steps)
     torch.cuda.synchronize()
     start = time.perf_counter()
-    for k in range(args.steps):
-        one_step(pairs[k])
+    for _ in range(args.steps):
+        fp.run()
     torch.cuda.synchronize()
     wall = time.perf_counter() - start
-    fit_ms = float(np.mean([a.elapsed_time(b) for a, b in pairs]))
+    (ms_bin, ms_sort, ms_kernel), n_rec = ctx.timings()
+    cnt = ((fp.counters - c0).double() / args.steps).cpu().numpy()
     ms_per_step = wall * 1e3 / args.steps
-    value = n_steps / (ms_per_step * 1e-3)
-    st = t.status[:n].cpu().numpy()
-    print(f"# status nonzero: {(st != 0).sum()}", file=sys.stderr, flush=True)
-
-    # per-layer design of the same fit: one launch per layer, state through HBM
-    reps = 5
-    pl = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
-    for r in range(-1, reps):
-        ctx.seed(hits, seed_hits, t)
-        if r >= 0:
-            pl[r][0].record(stream)
-        ctx.fit(t, hits, lseq, hidx, 10, flags=K.PER_LAYER)
-        if r >= 0:
-            pl[r][1].record(stream)
-    torch.cuda.synchronize()
-    per_layer_ms = float(np.mean([a.elapsed_time(b) for a, b in pl]))
-    # every launch processes all n lanes (finished tracks return early): the
-    # algorithmic bytes count only live steps
-    per_layer_gbs = n_steps * PER_LAYER_BYTES_PER_STEP / (per_layer_ms * 1e-3) / 1e9
-
-    fused_bytes = n_steps * FUSED_BYTES_PER_STEP + n * FUSED_BYTES_PER_TRACK
-    fused_gbs = fused_bytes / (fit_ms * 1e-3) / 1e9
+    kf_steps = 3 * n_seeds + cnt[0]
+    value = kf_steps / (ms_per_step * 1e-3)
+    flops = find_flops(cnt, oc)
+    tflops = flops / (ms_kernel * 1e-3) / 1e12
+    print(f"# {ms_per_step:.3f} ms/step, find kernel {ms_kernel:.3f} ms, binning {ms_bin:.3f} ms, "
+          f"seed order {ms_sort:.3f} ms, {kf_steps:.0f} KF steps/pass", file=sys.stderr, flush=True)
 
     result = {
         "metric": "KF prop+update steps/s",
@@ -177,44 +214,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "fit: seed + Kalman fit, precision-config track mix "
-                               "(pT 0.3/100 GeV, sigma_u 0.002-0.01 cm), 10 barrel layers",
-                   "n_tracks": n, "kf_steps_per_pass": n_steps, "precision": "mixed",
+        "config": {"workload": "batched finding: 64 events, N ~ Poisson(U(200,4000)), 60 noise "
+                               "hits/track, 10 barrel layers + 2x7 disks, |eta|<2.5, 0.02 X0, "
+                               "chi2<30, <=6 candidates/seed; seed + seed fit + kf_find",
+                   "n_events": len(evs), "n_seeds": n_seeds, "n_hits": int(inp["x"].shape[0]),
+                   "kf_steps_per_pass": kf_steps, "width": args.width, "precision": "mixed",
                    "init": "plain"},
-        "roofline": {"bound": "hbm", "achieved": fused_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": fused_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "fit_kernel<float,float,double> (all layers in registers)",
-                     "kernel_ms": fit_ms},
-        "per_layer": {"kernel_ms_all_layers": per_layer_ms,
-                      "steps_per_s": n_steps / (per_layer_ms * 1e-3),
-                      "achieved_GBs": per_layer_gbs, "frac_hbm": per_layer_gbs / HBM_PEAK_GBS,
-                      "bytes_per_step": PER_LAYER_BYTES_PER_STEP},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "find_kernel<float,double,double>", "kernel_ms": ms_kernel,
+                     "flops_per_launch": flops, "events_per_launch": cnt.tolist()},
+        "phases_ms": {"binning": ms_bin, "seed_order": ms_sort, "find_kernel": ms_kernel},
     }
+
+    if not args.no_fit:
+        result["fit"] = run_fit(K, torch, args.fit_tracks)
+        print(f"# fit: {result['fit']['fused_steps_per_s']:.3e} steps/s fused", file=sys.stderr,
+              flush=True)
 
     if not args.no_cpu:
         import oracle
-        m = min(args.cpu_sample, n)
-        cols = np.arange(m)
-        cfg = oracle.Config(geom)
-        hx = {k: hits_np[k].astype(np.float64) for k in ("x", "y", "z", "su", "sv")}
-        # oracle seeds (3-hit circle + prior) for the sample, untimed setup
-        par0 = np.zeros((m, 6))
-        cov0 = np.zeros((m, 21))
-        for i in range(m):
-            h3 = [np.array([hx["x"][hidx_np[s, i]], hx["y"][hidx_np[s, i]],
-                            hx["z"][hidx_np[s, i]]]) for s in range(3)]
-            par0[i], cov0[i] = oracle.seed(*h3)
-        lq = np.ascontiguousarray(lseq_np[:, :m].T)
-        hq = np.ascontiguousarray(hidx_np[:, :m].T)
         threads = min(os.cpu_count() or 1, 16)
         c0 = time.perf_counter()
-        oracle.fit(cfg, hx, lq, hq, par0, cov0, n_threads=threads)
+        n_prop = oracle_find_all(oracle, geom, evs, inp, threads)
         cdt = time.perf_counter() - c0
-        csteps = int((lq >= 0).sum())
+        csteps = 3 * n_seeds + n_prop
         result["cpu_baseline"] = {"value": csteps / cdt, "unit": "steps/s", "cores": threads,
                                   "kind": "oracle",
-                                  "sample": f"FP64 oracle fit of the first {m} tracks "
-                                            f"({csteps} KF steps) in {cdt:.2f} s"}
+                                  "sample": f"FP64 oracle finding (seed fit + find) over the same "
+                                            f"64-event batch: {csteps} KF steps in {cdt:.2f} s"}
     print(json.dumps(result))
 
 

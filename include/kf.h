@@ -158,7 +158,8 @@ int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_
  *               layer (global hit index), -1 = none
  *   out         n_seeds tracks, out->n == seeds->n: best candidate's state at its
  *               last surface, chi2, ndf = 2*hits - 5, status
- *   counters    optional [2] uint64, incremented by (propagations, updates)
+ *   counters    optional [5] uint64, incremented by (propagations, updates,
+ *               chi2 tests, Newton evaluations, disk-crossing tests)
  * Per layer a candidate is propagated to its next surface (the first reached
  * of the next barrel outward and the next disk ahead), every hit in the chi2
  * window's bins passing chi2 < chi2_cut becomes a child (best max_cands per
@@ -174,6 +175,16 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
  * candidate slot, width / max_cands seeds per tile) and tile order (0: seeds
  * sorted by event, eta, phi; 1: largest events first).  Default 256, 1. */
 int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first);
+
+/* Kernel timing.  kf_set_timing(ctx, n) with 1 <= n <= 256 makes the next n
+ * kf_find calls record HIP events on their stream around their three phases
+ * (hit binning, seed ordering, finding kernel), one event set per call, with
+ * no host synchronisation; n = 0 turns it off.  kf_timings synchronises on
+ * the last recorded event and writes the mean milliseconds over the recorded
+ * calls: ms[0] binning, ms[1] seed ordering, ms[2] finding kernel, and
+ * ms[3] = number of calls recorded.  Returns KF_EINVAL if none was. */
+int kf_set_timing(kf_ctx* ctx, int32_t n);
+int kf_timings(kf_ctx* ctx, float ms[4]);
 
 #ifdef __cplusplus
 }

@@ -58,7 +58,10 @@ def _load():
     L.kf_find.argtypes = [vp, C.POINTER(KfHits), vp, i32, C.POINTER(KfTracks), vp, vp, vp,
                           C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_set_find_config.argtypes = [vp, i32, i32]
-    for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_set_find_config"):
+    L.kf_set_timing.argtypes = [vp, i32]
+    L.kf_timings.argtypes = [vp, C.POINTER(C.c_float)]
+    for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_set_find_config",
+              "kf_set_timing", "kf_timings"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -190,6 +193,17 @@ class Context:
     def fit(self, tracks, hits, layer_seq, hit_idx, max_steps, flags=0):
         self._check(lib.kf_fit(self.h, C.byref(tracks.c()), C.byref(hits.c()), _ptr(layer_seq),
                                _ptr(hit_idx), int(max_steps), flags, _stream()), "kf_fit")
+
+    def set_timing(self, n=1):
+        """Record kernel events for the next n kf_find calls (0: off)."""
+        self._check(lib.kf_set_timing(self.h, int(n)), "kf_set_timing")
+
+    def timings(self):
+        """Mean (binning, seed ordering, finding kernel) ms over the recorded calls,
+        and the number of calls recorded."""
+        ms = (C.c_float * 4)()
+        self._check(lib.kf_timings(self.h, ms), "kf_timings")
+        return tuple(ms[:3]), int(ms[3])
 
     def set_find_config(self, width=256, largest_first=True):
         self._check(lib.kf_set_find_config(self.h, int(width), int(bool(largest_first))),

@@ -31,6 +31,28 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+OPCOUNT_JSON = os.path.join(HERE, "opcount.json")
+
+
+def build_opcount(verbose=False):
+    """Compile the host operation counter of the device arithmetic and write
+    its per-unit operation counts to opcount.json."""
+    exe = os.path.join(HERE, "_opcount.bin")
+    cmd = [hipcc(), "-x", "hip", "--offload-host-only", "-O1", "-std=c++17", "-I", CSRC,
+           "-o", exe, os.path.join(CSRC, "opcount.cpp")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building the operation counter")
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    os.remove(exe)
+    with open(OPCOUNT_JSON, "w") as f:
+        f.write(out)
+    return OPCOUNT_JSON
+
+
 def build(verbose=False, extra=()):
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = LIB + ".tmp"
@@ -47,3 +69,4 @@ def build(verbose=False, extra=()):
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_opcount(verbose=True))

@@ -142,6 +142,8 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
 void kf_destroy(kf_ctx* ctx)
 {
     if (!ctx) return;
+    for (int k = 0; k < 4 * ctx->timing_cap; ++k) (void)hipEventDestroy(ctx->ev[k]);
+    delete[] ctx->ev;
     ctx->ws.release();
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
     delete ctx;
@@ -261,11 +263,17 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     void* base = ctx->ws.get(bytes);
     if (!base) return fail(ctx, KF_ENOMEM, "kf_find: workspace of %zu bytes", bytes);
     kfmi::plan_find(&pl, base, hits->n, n_events, seeds->n, nl, (int)grid, S);
-    hipError_t e = kfmi::launch_bin(pl, hits, event_off, n_events, ctx->d_layers, nl, s);
+    const bool tm = ctx->timing_used < ctx->timing_n;
+    hipEvent_t* ev = tm ? ctx->ev + 4 * ctx->timing_used : nullptr;
+    hipError_t e = hipSuccess;
+    if (tm) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = kfmi::launch_bin(pl, hits, event_off, n_events, ctx->d_layers, nl, s);
+    if (e == hipSuccess && tm) e = hipEventRecord(ev[1], s);
     if (e == hipSuccess)
         e = kfmi::launch_seed_order(pl, seeds, seed_event, event_off, n_events,
                                     ctx->find_largest_first, s);
     if (e == hipSuccess) e = kfmi::launch_fill(pl.tile_counter, 1, 0, s);
+    if (e == hipSuccess && tm) e = hipEventRecord(ev[2], s);
     if (e != hipSuccess) return hip_fail(ctx, e, "kf_find setup");
     kfmi::FindArgs a;
     a.bh = (const kfmi::BinnedHit*)pl.binned;
@@ -301,7 +309,56 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     a.n_tiles = (int)n_tiles;
     a.seeds_per_tile = S;
     e = kfmi::launch_find_kernel(a, W, (int)grid, prec, s);
+    if (e == hipSuccess && tm) {
+        e = hipEventRecord(ev[3], s);
+        if (e == hipSuccess) ctx->timing_used++;
+    }
     return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_find");
+}
+
+int kf_set_timing(kf_ctx* ctx, int32_t n)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_set_timing: null context");
+    if (n < 0 || n > 256) return fail(ctx, KF_EINVAL, "kf_set_timing: n must be in 0..256");
+    if (n > ctx->timing_cap) {
+        hipEvent_t* ev = new hipEvent_t[4 * n];
+        int k = 0;
+        for (; k < 4 * ctx->timing_cap; ++k) ev[k] = ctx->ev[k];
+        for (; k < 4 * n; ++k) {
+            hipError_t r = hipEventCreate(&ev[k]);
+            if (r != hipSuccess) {
+                for (int j = 4 * ctx->timing_cap; j < k; ++j) (void)hipEventDestroy(ev[j]);
+                delete[] ev;
+                return hip_fail(ctx, r, "kf_set_timing");
+            }
+        }
+        delete[] ctx->ev;
+        ctx->ev = ev;
+        ctx->timing_cap = n;
+    }
+    // the next n calls record into sets 0..n-1; later calls are not recorded
+    ctx->timing_used = 0;
+    ctx->timing_n = n;
+    return KF_OK;
+}
+
+int kf_timings(kf_ctx* ctx, float ms[4])
+{
+    if (!ctx || !ms) return fail(ctx, KF_EINVAL, "kf_timings: null argument");
+    const int first = 0, last = ctx->timing_used;
+    if (ctx->timing_n == 0 || last <= first) return fail(ctx, KF_EINVAL, "kf_timings: nothing recorded");
+    hipError_t e = hipEventSynchronize(ctx->ev[4 * (last - 1) + 3]);
+    double acc[3] = {0, 0, 0};
+    for (int c = first; c < last && e == hipSuccess; ++c)
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+            float t = 0.0f;
+            e = hipEventElapsedTime(&t, ctx->ev[4 * c + k], ctx->ev[4 * c + k + 1]);
+            acc[k] += t;
+        }
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_timings");
+    for (int k = 0; k < 3; ++k) ms[k] = float(acc[k] / (last - first));
+    ms[3] = float(last - first);
+    return KF_OK;
 }
 
 }  // extern "C"

@@ -138,70 +138,6 @@ __global__ __launch_bounds__(256) void seed_key_kernel(int64_t n, int64_t ld, co
 }
 
 // ------------------------------------------------------------------ find
-// Next surface: whichever comes first along the helix, the next barrel
-// outward (smallest radius above the current one, reachable, crossing inside
-// its z extent) or the first disk ahead whose crossing is inside its radial
-// extent.  Returns the layer (or -1) and the path length.
-template <typename T>
-__device__ inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_params& prm, T kb,
-                               T* s_out, uint32_t* st)
-{
-    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
-    // only surfaces reached within half a turn in the transverse plane
-    const T hh = Tr<T>::abs_(kb * p[3]);
-    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
-    int bl = -1;
-    T rbl = T(0);
-    for (int l = 0; l < nl; ++l) {
-        if (L[l].kind != 0) continue;
-        const T r = T(L[l].r_or_z);
-        if (r > rho + T(kNextBarrelEps) && (bl < 0 || r < rbl)) {
-            bl = l;
-            rbl = r;
-        }
-    }
-    T best_s = T(1e30);
-    int best_l = -1;
-    T sth, cth;
-    Tr<T>::sincos_(p[5], &sth, &cth);
-    if (bl >= 0) {
-        const T h = -kb * p[3];
-        T sph, cph;
-        Tr<T>::sincos_(p[4], &sph, &cph);
-        T s_hi;
-        if (barrel_bracket(p[0], p[1], cph, sph, h, rbl, &s_hi)) {
-            T s;
-            int ev = 0;
-            const T s0 = line_guess(p[0], p[1], cph, sph, rbl);
-            if (newton_barrel(p[0], p[1], p[4], h, rbl, s0, T(0), s_hi, prm.max_newton,
-                              T(prm.newton_tol), &s, &ev)) {
-                *st |= KF_ST_NOCONV;
-                return -1;
-            }
-            const T zc = p[2] + s * cth / sth;
-            if (Tr<T>::abs_(zc) <= T(L[bl].hi) && s <= s_max) {
-                best_s = s;
-                best_l = bl;
-            }
-        }
-    }
-    const T cot = cth / sth;
-    for (int l = 0; l < nl; ++l) {
-        if (L[l].kind != 1) continue;
-        const T dz = T(L[l].r_or_z) - p[2];
-        if (!(dz * cot > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
-        const T s = dz / cot;
-        if (!(s < best_s) || s > s_max) continue;
-        const HelixPoint<T> q = helix_at(p[0], p[1], p[4], -kb * p[3], s);
-        const T r = Tr<T>::sqrt_(q.X * q.X + q.Y * q.Y);
-        if (r < T(L[l].lo) || r > T(L[l].hi)) continue;
-        best_s = s;
-        best_l = l;
-    }
-    *s_out = best_s;
-    return best_l;
-}
-
 // LDS layout of one workgroup (W lanes), all arrays lane-minor
 template <typename C>
 struct FindShared {
@@ -277,7 +213,8 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
     const bool lane_ok = s_loc < S;
     const T kb = T(kKappa) * T(a.prm.bz);
     const float cut = float(a.prm.chi2_cut);
-    unsigned long long n_prop = 0, n_upd = 0;
+    unsigned long long n_prop = 0, n_upd = 0, n_chi2 = 0;
+    int n_newton = 0, n_disk = 0;
     int2* bp_base = a.bp + (size_t)blockIdx.x * nl * S * kMaxCands;
 
     for (;;) {
@@ -324,7 +261,8 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
             int pl = -1;
             if (live) {
                 T s;
-                const int layer = navigate(p, sh.layers, nl, a.prm, kb, &s, &status);
+                const int layer = navigate(p, sh.layers, nl, a.prm, kb, &s, &status, &n_newton,
+                                           &n_disk);
                 if (layer < 0) {
                     done = true;
                 } else {
@@ -355,29 +293,12 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
             int nacc = 0;
             if (pl >= 0) {
                 const kf_layer L = sh.layers[pl];
-                bool scan = true;
+                const Window<T> Wn = make_window<T, C>(p, P, L, T(cut));
+                const bool scan = Wn.ok;
+                const bool all_phi = Wn.all_phi;
+                const T dphi = Wn.dphi, sin_dphi = Wn.sin_dphi, wv = Wn.wv, vlo = Wn.vlo,
+                        vhi = Wn.vhi;
                 const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
-                const T pxx = T(P[pk(0, 0)]), pyy = T(P[pk(1, 1)]), pzz = T(P[pk(2, 2)]);
-                const T wu = Tr<T>::sqrt_(T(cut) * (pxx + pyy + T(L.win_su) * T(L.win_su)));
-                const T tt = T(1.001) * wu / rho;
-                T dphi = tt >= T(1) ? T(kPi) : Tr<T>::asin_(tt) + T(1e-4);
-                if (dphi > T(0.5 * kPi)) dphi = T(kPi);
-                const bool all_phi = dphi >= T(kPi);
-                const T cos_dphi = all_phi ? T(-1) : Tr<T>::cos_(dphi);
-                const T sin_dphi = all_phi ? T(2) : Tr<T>::sin_(dphi);
-                T wv, vlo, vhi;
-                if (L.kind == 0) {
-                    wv = T(1.001) * Tr<T>::sqrt_(T(cut) * (pzz + T(L.win_sv) * T(L.win_sv))) + T(1e-4);
-                    vlo = p[2] - wv;
-                    vhi = p[2] + wv;
-                } else {
-                    wv = T(1.001) * Tr<T>::sqrt_(T(cut) * (pxx + pyy + T(L.win_sv) * T(L.win_sv))) +
-                         T(1e-4);
-                    vlo = rho * cos_dphi - wv;
-                    vhi = rho + wv;
-                }
-                // a non-finite covariance gives no usable window: no hits tested
-                if (!(dphi >= T(0)) || !(wv >= T(0)) || !(wv < T(1e30)) || !(rho > T(0))) scan = false;
                 const int np = L.nbin_phi, n2 = L.nbin_2;
                 int b_lo = 0, b_hi = np - 1;
                 if (!scan) b_hi = -1;
@@ -419,6 +340,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                         f.vu = U(r0.w) * U(r0.w);
                         f.vv = U(r1.x) * U(r1.x);
                         const U c2u = hit_chi2<T, C, U>(p, P, f, L.kind);
+                        ++n_chi2;
                         if (!(c2u < U(cut))) continue;
                         float c = float(c2u);
                         int32_t id = __float_as_int(r1.w);
@@ -595,13 +517,12 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
     }
     if (a.counters) {
         // wave-level reduction of the per-lane counts, one atomic per wave
-        for (int o = 32; o > 0; o >>= 1) {
-            n_prop += __shfl_xor(n_prop, o);
-            n_upd += __shfl_xor(n_upd, o);
-        }
-        if ((t & 63) == 0) {
-            atomicAdd(&a.counters[0], n_prop);
-            atomicAdd(&a.counters[1], n_upd);
+        unsigned long long c[5] = {n_prop, n_upd, n_chi2, (unsigned long long)n_newton,
+                                   (unsigned long long)n_disk};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            for (int o = 32; o > 0; o >>= 1) c[q] += __shfl_xor(c[q], o);
+            if ((t & 63) == 0) atomicAdd(&a.counters[q], c[q]);
         }
     }
 }

@@ -36,6 +36,10 @@ struct kf_ctx {
     int find_width = 256;             // lanes per workgroup of the finding kernel
     int find_largest_first = 1;       // tile order
     int occ_cache[2][9] = {};         // resident workgroups per CU by (precision, log2 width)
+    int timing_cap = 0;               // event sets available (0: timing off)
+    int timing_used = 0;              // event sets recorded since kf_set_timing
+    int timing_n = 0;                 // sets requested by kf_set_timing
+    hipEvent_t* ev = nullptr;         // [timing_cap][4] phase boundaries
 };
 
 namespace kfmi {

@@ -14,6 +14,9 @@
 
 #include "../../include/kf.h"
 
+// Device functions that a host-side operation counter can also instantiate.
+#define KF_HD __host__ __device__
+
 namespace kfmi {
 
 constexpr double kKappa = 0.00299792458;   // GeV / (T cm)
@@ -29,32 +32,32 @@ __host__ __device__ constexpr int pk(int i, int j)
 
 template <typename T> struct Tr;
 template <> struct Tr<float> {
-    __device__ static inline void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
-    __device__ static inline float sqrt_(float x) { return sqrtf(x); }
-    __device__ static inline float abs_(float x) { return fabsf(x); }
-    __device__ static inline float atan2_(float y, float x) { return atan2f(y, x); }
-    __device__ static inline float log_(float x) { return logf(x); }
-    __device__ static inline float fmod_(float x, float y) { return fmodf(x, y); }
-    __device__ static inline float asin_(float x) { return asinf(x); }
-    __device__ static inline float cos_(float x) { return cosf(x); }
-    __device__ static inline float sin_(float x) { return sinf(x); }
-    __device__ static inline float floor_(float x) { return floorf(x); }
+    KF_HD static inline void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
+    KF_HD static inline float sqrt_(float x) { return sqrtf(x); }
+    KF_HD static inline float abs_(float x) { return fabsf(x); }
+    KF_HD static inline float atan2_(float y, float x) { return atan2f(y, x); }
+    KF_HD static inline float log_(float x) { return logf(x); }
+    KF_HD static inline float fmod_(float x, float y) { return fmodf(x, y); }
+    KF_HD static inline float asin_(float x) { return asinf(x); }
+    KF_HD static inline float cos_(float x) { return cosf(x); }
+    KF_HD static inline float sin_(float x) { return sinf(x); }
+    KF_HD static inline float floor_(float x) { return floorf(x); }
 };
 template <> struct Tr<double> {
-    __device__ static inline void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
-    __device__ static inline double sqrt_(double x) { return sqrt(x); }
-    __device__ static inline double abs_(double x) { return fabs(x); }
-    __device__ static inline double atan2_(double y, double x) { return atan2(y, x); }
-    __device__ static inline double log_(double x) { return log(x); }
-    __device__ static inline double fmod_(double x, double y) { return fmod(x, y); }
-    __device__ static inline double asin_(double x) { return asin(x); }
-    __device__ static inline double cos_(double x) { return cos(x); }
-    __device__ static inline double sin_(double x) { return sin(x); }
-    __device__ static inline double floor_(double x) { return floor(x); }
+    KF_HD static inline void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+    KF_HD static inline double sqrt_(double x) { return sqrt(x); }
+    KF_HD static inline double abs_(double x) { return fabs(x); }
+    KF_HD static inline double atan2_(double y, double x) { return atan2(y, x); }
+    KF_HD static inline double log_(double x) { return log(x); }
+    KF_HD static inline double fmod_(double x, double y) { return fmod(x, y); }
+    KF_HD static inline double asin_(double x) { return asin(x); }
+    KF_HD static inline double cos_(double x) { return cos(x); }
+    KF_HD static inline double sin_(double x) { return sin(x); }
+    KF_HD static inline double floor_(double x) { return floor(x); }
 };
 
 template <typename T>
-__device__ inline T wrap_phi(T a)
+KF_HD inline T wrap_phi(T a)
 {
     const T pi = T(kPi), tpi = T(2.0 * kPi);
     if (a > pi) a -= tpi;
@@ -64,14 +67,14 @@ __device__ inline T wrap_phi(T a)
 
 // sin(u)/u given sin(u)
 template <typename T>
-__device__ inline T sinc_of(T u, T su)
+KF_HD inline T sinc_of(T u, T su)
 {
     return Tr<T>::abs_(u) < T(1e-4) ? T(1) - u * u * T(1.0 / 6.0) : su / u;
 }
 
 // d/du [sin(u)/u]; Taylor series where the closed form cancels
 template <typename T>
-__device__ inline T dsinc_of(T u, T su, T cu)
+KF_HD inline T dsinc_of(T u, T su, T cu)
 {
     if (Tr<T>::abs_(u) < T(0.5)) {
         T u2 = u * u;
@@ -92,7 +95,7 @@ struct HelixPoint {
 };
 
 template <typename T>
-__device__ inline HelixPoint<T> helix_at(T x, T y, T phi, T h, T s)
+KF_HD inline HelixPoint<T> helix_at(T x, T y, T phi, T h, T s)
 {
     HelixPoint<T> q;
     T u = T(0.5) * h * s;
@@ -108,7 +111,7 @@ __device__ inline HelixPoint<T> helix_at(T x, T y, T phi, T h, T s)
 
 // Straight-line (tangent) intersection with radius r_l: the plain initial guess.
 template <typename T>
-__device__ inline T line_guess(T x, T y, T cphi, T sphi, T r_l)
+KF_HD inline T line_guess(T x, T y, T cphi, T sphi, T r_l)
 {
     T pu = x * cphi + y * sphi;
     T disc = pu * pu - (x * x + y * y) + r_l * r_l;
@@ -118,7 +121,7 @@ __device__ inline T line_guess(T x, T y, T cphi, T sphi, T r_l)
 // Bracket of the outward crossing: [0, arc length to the point of largest
 // radius].  Returns false when the circle never reaches r_l.
 template <typename T>
-__device__ inline bool barrel_bracket(T x, T y, T cphi, T sphi, T h, T r_l, T* s_hi)
+KF_HD inline bool barrel_bracket(T x, T y, T cphi, T sphi, T h, T r_l, T* s_hi)
 {
     if (h == T(0)) {
         *s_hi = T(1e30);
@@ -142,7 +145,7 @@ __device__ inline bool barrel_bracket(T x, T y, T cphi, T sphi, T h, T r_l, T* s
 // |r - r_l| < tol, then one more Newton step.  Returns 0 or KF_ST_NOCONV;
 // *evals counts evaluations of r(s).
 template <typename T>
-__device__ inline int newton_barrel(T x, T y, T phi, T h, T r_l, T s, T s_lo, T s_hi, int max_it,
+KF_HD inline int newton_barrel(T x, T y, T phi, T h, T r_l, T s, T s_lo, T s_hi, int max_it,
                                     T tol, T* s_out, int* evals)
 {
     if (s < s_lo) s = s_lo;
@@ -175,7 +178,7 @@ __device__ inline int newton_barrel(T x, T y, T phi, T h, T r_l, T s, T s_lo, T 
 // Transport of (p, P) by arc length s to a surface: new state, F P F^T.
 // kind 0: barrel (path length from r(s) = r_l); 1: disk at z = zd.
 template <typename T, typename C>
-__device__ inline void transport(T p[6], C P[21], T s, T kb, int kind, T zd)
+KF_HD inline void transport(T p[6], C P[21], T s, T kb, int kind, T zd)
 {
     const T x = p[0], y = p[1], z = p[2], c = p[3], phi = p[4], th = p[5];
     const T h = -kb * c;
@@ -257,7 +260,7 @@ __device__ inline void transport(T p[6], C P[21], T s, T kb, int kind, T zd)
 // Multiple-scattering process noise of a layer (PDG Highland width), added to
 // the (c, phi, theta) block at the propagated state.
 template <typename T, typename C>
-__device__ inline void add_scatter(const T p[6], C P[21], int kind, T x0, T mass)
+KF_HD inline void add_scatter(const T p[6], C P[21], int kind, T x0, T mass)
 {
     if (!(x0 > T(0))) return;
     T st, ct;
@@ -296,7 +299,7 @@ struct HitFrame {
 };
 
 template <typename U>
-__device__ inline HitFrame<U> hit_frame(float x, float y, float z, float su, float sv)
+KF_HD inline HitFrame<U> hit_frame(float x, float y, float z, float su, float sv)
 {
     HitFrame<U> f;
     f.hx = U(x);
@@ -312,7 +315,7 @@ __device__ inline HitFrame<U> hit_frame(float x, float y, float z, float su, flo
 
 // chi2 of a hit against (p, P) without updating
 template <typename T, typename C, typename U>
-__device__ inline U hit_chi2(const T p[6], const C P[21], const HitFrame<U>& f, int kind)
+KF_HD inline U hit_chi2(const T p[6], const C P[21], const HitFrame<U>& f, int kind)
 {
     const U c = f.c, s = f.s;
     U ru = -s * (f.hx - U(p[0])) + c * (f.hy - U(p[1]));
@@ -343,7 +346,7 @@ __device__ inline U hit_chi2(const T p[6], const C P[21], const HitFrame<U>& f, 
 // in Joseph form (I - K H) P (I - K H)^T + K V K^T, evaluated as
 // M = P - K (H P), P+ = M - (M H^T) K^T + K V K^T.  Returns status bits.
 template <typename T, typename C, typename U>
-__device__ inline int kf_update(T p[6], C P[21], const HitFrame<U>& f, int kind, U* chi2_out)
+KF_HD inline int kf_update(T p[6], C P[21], const HitFrame<U>& f, int kind, U* chi2_out)
 {
     const U c = f.c, s = f.s;
     U Pu[21];
@@ -400,6 +403,111 @@ __device__ inline int kf_update(T p[6], C P[21], const HitFrame<U>& f, int kind,
 #pragma unroll
     for (int i = 0; i < 6; ++i) fin &= isfinite(p[i]);
     return fin ? 0 : KF_ST_NAN;
+}
+
+// Next surface: whichever comes first along the helix, the next barrel
+// outward (smallest radius above the current one, reachable, crossing inside
+// its z extent) or the first disk ahead whose crossing is inside its radial
+// extent.  Returns the layer (or -1) and the path length.
+template <typename T>
+KF_HD inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_params& prm, T kb,
+                          T* s_out, uint32_t* st, int* newton_evals, int* disk_evals)
+{
+    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+    // only surfaces reached within half a turn in the transverse plane
+    const T hh = Tr<T>::abs_(kb * p[3]);
+    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
+    int bl = -1;
+    T rbl = T(0);
+    for (int l = 0; l < nl; ++l) {
+        if (L[l].kind != 0) continue;
+        const T r = T(L[l].r_or_z);
+        if (r > rho + T(kNextBarrelEps) && (bl < 0 || r < rbl)) {
+            bl = l;
+            rbl = r;
+        }
+    }
+    T best_s = T(1e30);
+    int best_l = -1;
+    T sth, cth;
+    Tr<T>::sincos_(p[5], &sth, &cth);
+    if (bl >= 0) {
+        const T h = -kb * p[3];
+        T sph, cph;
+        Tr<T>::sincos_(p[4], &sph, &cph);
+        T s_hi;
+        if (barrel_bracket(p[0], p[1], cph, sph, h, rbl, &s_hi)) {
+            T s;
+            const T s0 = line_guess(p[0], p[1], cph, sph, rbl);
+            if (newton_barrel(p[0], p[1], p[4], h, rbl, s0, T(0), s_hi, prm.max_newton,
+                              T(prm.newton_tol), &s, newton_evals)) {
+                *st |= KF_ST_NOCONV;
+                return -1;
+            }
+            const T zc = p[2] + s * cth / sth;
+            if (Tr<T>::abs_(zc) <= T(L[bl].hi) && s <= s_max) {
+                best_s = s;
+                best_l = bl;
+            }
+        }
+    }
+    const T cot = cth / sth;
+    for (int l = 0; l < nl; ++l) {
+        if (L[l].kind != 1) continue;
+        const T dz = T(L[l].r_or_z) - p[2];
+        if (!(dz * cot > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
+        const T s = dz / cot;
+        if (!(s < best_s) || s > s_max) continue;
+        ++*disk_evals;
+        const HelixPoint<T> q = helix_at(p[0], p[1], p[4], -kb * p[3], s);
+        const T r = Tr<T>::sqrt_(q.X * q.X + q.Y * q.Y);
+        if (r < T(L[l].lo) || r > T(L[l].hi)) continue;
+        best_s = s;
+        best_l = l;
+    }
+    *s_out = best_s;
+    return best_l;
+}
+
+
+// Hit-search window of a predicted state on a layer: the bounding box of the
+// chi2 < cut ellipse (half-widths from the position covariance plus the
+// layer's largest hit sigma) with a 1e-3 relative and 1e-4 absolute margin.
+// Azimuth: |d| <= dphi, tested as cos d > 0 and |sin d| <= sin dphi (dphi
+// below pi/2; wider windows take the whole circle).  Second coordinate: z
+// (barrel) or r (disk) range for the bin enumeration, |residual| <= wv.
+template <typename T>
+struct Window {
+    bool ok, all_phi;
+    T dphi, cos_dphi, sin_dphi, wv, vlo, vhi;
+};
+
+template <typename T, typename C>
+KF_HD inline Window<T> make_window(const T p[6], const C P[21], const kf_layer& L, T cut)
+{
+    Window<T> W;
+    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+    const T pxx = T(P[pk(0, 0)]), pyy = T(P[pk(1, 1)]), pzz = T(P[pk(2, 2)]);
+    const T wu = Tr<T>::sqrt_(cut * (pxx + pyy + T(L.win_su) * T(L.win_su)));
+    const T tt = T(1.001) * wu / rho;
+    T dphi = tt >= T(1) ? T(kPi) : Tr<T>::asin_(tt) + T(1e-4);
+    if (dphi > T(0.5 * kPi)) dphi = T(kPi);
+    W.dphi = dphi;
+    W.all_phi = dphi >= T(kPi);
+    W.cos_dphi = W.all_phi ? T(-1) : Tr<T>::cos_(dphi);
+    W.sin_dphi = W.all_phi ? T(2) : Tr<T>::sin_(dphi);
+    if (L.kind == 0) {
+        W.wv = T(1.001) * Tr<T>::sqrt_(cut * (pzz + T(L.win_sv) * T(L.win_sv))) + T(1e-4);
+        W.vlo = p[2] - W.wv;
+        W.vhi = p[2] + W.wv;
+    } else {
+        W.wv = T(1.001) * Tr<T>::sqrt_(cut * (pxx + pyy + T(L.win_sv) * T(L.win_sv))) + T(1e-4);
+        W.vlo = rho * W.cos_dphi - W.wv;
+        W.vhi = rho + W.wv;
+    }
+    // a non-finite covariance gives no usable window: no hits tested
+    W.ok = dphi >= T(0) && W.wv >= T(0) && W.wv < T(1e30) && rho > T(0);
+    return W;
 }
 
 }  // namespace kfmi
