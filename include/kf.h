@@ -173,7 +173,7 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
 
 /* Workgroup width of the finding kernel (32, 64, 128 or 256 lanes; a lane per
  * candidate slot, width / max_cands seeds per tile) and tile order (0: seeds
- * sorted by event, eta, phi; 1: largest events first).  Default 256, 1. */
+ * sorted by event, eta, phi; 1: largest events first).  Default 64, 1. */
 int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first);
 
 /* Kernel timing.  kf_set_timing(ctx, n) with 1 <= n <= 256 makes the next n

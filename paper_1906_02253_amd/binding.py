@@ -10,7 +10,8 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libkfmi.so")
+# KFMI_LIB selects another build of the same library (e.g. an instrumented one)
+LIB_PATH = os.environ.get("KFMI_LIB") or os.path.join(HERE, "libkfmi.so")
 
 KF_OK, KF_EINVAL, KF_EHIP, KF_ENOMEM, KF_EUNSUPPORTED = 0, -1, -2, -3, -4
 ST_OK, ST_UNREACHABLE, ST_NOCONV, ST_FALLBACK, ST_NONPD, ST_NAN, ST_BADINPUT = 0, 1, 2, 4, 8, 16, 32

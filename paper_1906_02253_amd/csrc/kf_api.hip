@@ -272,7 +272,7 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     if (e == hipSuccess)
         e = kfmi::launch_seed_order(pl, seeds, seed_event, event_off, n_events,
                                     ctx->find_largest_first, s);
-    if (e == hipSuccess) e = kfmi::launch_fill(pl.tile_counter, 1, 0, s);
+    if (e == hipSuccess) e = kfmi::launch_fill(pl.tile_counter, 64, 0, s);
     if (e == hipSuccess && tm) e = hipEventRecord(ev[2], s);
     if (e != hipSuccess) return hip_fail(ctx, e, "kf_find setup");
     kfmi::FindArgs a;

@@ -24,6 +24,7 @@
 namespace kfmi {
 
 static_assert(sizeof(BinnedHit) == 32, "BinnedHit is two 16-byte loads");
+constexpr int kQueues = 8;     // tile queues, one per XCD
 
 // ------------------------------------------------------------------ binning
 __device__ inline int phi_bin_of(float phi, int nb)
@@ -138,6 +139,14 @@ __global__ __launch_bounds__(256) void seed_key_kernel(int64_t n, int64_t ld, co
 }
 
 // ------------------------------------------------------------------ find
+// LDS writes of one wave made visible to that wave's other lanes
+__device__ inline void wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // LDS layout of one workgroup (W lanes), all arrays lane-minor
 template <typename C>
 struct FindShared {
@@ -152,7 +161,17 @@ struct FindShared {
     uint8_t* ptr;       // [S][kMaxCands] merge cursors
     kf_layer* layers;   // [n_layers]
     int32_t* misc;      // [4] tile id
+    // cooperative window scan, per lane (owner of a window) and per wave
+    float* own;         // [5][W] cos/sin of the predicted azimuth, sin(dphi), wv, flags
+    int32_t* seg;       // [n_waves][3][kSeg] queued phi rows: owner lane, first hit, count
+    int32_t* segpre;    // [n_waves][kSeg + 1] prefix of the rows' hit counts
+    int32_t* acc;       // [n_waves][3][kAcc] accepted hits: owner lane, hit index, binned index
+    float* accc2;       // [n_waves][kAcc] their chi2
 };
+
+constexpr int kSeg = 128;       // phi rows queued per wave per round
+constexpr int kScanBatch = 4;   // hits per lane in flight in the scan
+constexpr int kAcc = 64 * kScanBatch;
 
 __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t csize)
 {
@@ -164,15 +183,27 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
     b += sizeof(int32_t) * kMaxCands * W;
     b += sizeof(int32_t) * W;
     b += sizeof(int32_t) * S;
+    b = (b + 15) & ~size_t(15);
     b += sizeof(kf_layer) * nl;
     b += sizeof(int32_t) * 4;
     b += 2 * S * kMaxCands;
     b += S * kMaxCands;
+    b = (b + 15) & ~size_t(15);
+    const size_t nw = (W + 63) / 64;
+    b += sizeof(float) * 5 * W;
+    b += sizeof(int32_t) * nw * (3 * kSeg + kSeg + 1 + 3 * kAcc);
+    b += sizeof(float) * nw * kAcc;
     return (b + 15) & ~size_t(15);
 }
 
+// waves per SIMD the register allocation is held to (a build-time tuning knob)
+#ifndef KF_FIND_WAVES
+#define KF_FIND_WAVES 2
+#endif
+
 template <typename T, typename C, typename U>
-__global__ __launch_bounds__(256) void find_kernel(FindArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAVES))) void find_kernel(
+    FindArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int W = blockDim.x;
@@ -198,6 +229,7 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
         q += sizeof(int32_t) * W;
         sh.nsel = (int32_t*)q;
         q += sizeof(int32_t) * S;
+        q = smem + (((size_t)(q - smem) + 15) & ~size_t(15));
         sh.layers = (kf_layer*)q;
         q += sizeof(kf_layer) * nl;
         sh.misc = (int32_t*)q;
@@ -205,6 +237,18 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
         sh.sel = (int8_t*)q;
         q += 2 * S * kMaxCands;
         sh.ptr = (uint8_t*)q;
+        q += S * kMaxCands;
+        q = smem + (((size_t)(q - smem) + 15) & ~size_t(15));
+        const int nw = (W + 63) / 64;
+        sh.own = (float*)q;
+        q += sizeof(float) * 5 * W;
+        sh.seg = (int32_t*)q;
+        q += sizeof(int32_t) * nw * 3 * kSeg;
+        sh.segpre = (int32_t*)q;
+        q += sizeof(int32_t) * nw * (kSeg + 1);
+        sh.acc = (int32_t*)q;
+        q += sizeof(int32_t) * nw * 3 * kAcc;
+        sh.accc2 = (float*)q;
     }
     const int t = threadIdx.x;
     for (int l = t; l < nl; l += W) sh.layers[l] = a.layers[l];
@@ -219,7 +263,27 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
 
     for (;;) {
         __syncthreads();
-        if (t == 0) sh.misc[0] = atomicAdd(a.tile_counter, 1);
+        if (t == 0) {
+            // tiles are split into kQueues contiguous chunks, one per XCD
+            // (workgroups are dispatched to the XCDs round-robin), so that a
+            // chunk's neighbouring eta-phi tiles share that XCD's L2; a
+            // workgroup whose chunk is exhausted takes tiles from the others
+            const int chunk = (a.n_tiles + kQueues - 1) / kQueues;
+            const int home = blockIdx.x % kQueues;
+            int tile = a.n_tiles;
+            for (int d = 0; d < kQueues; ++d) {
+                const int q = (home + d) % kQueues;
+                const int lo = q * chunk;
+                const int hi = lo + chunk < a.n_tiles ? lo + chunk : a.n_tiles;
+                if (lo >= hi) continue;
+                const int i = atomicAdd(&a.tile_counter[q], 1);
+                if (lo + i < hi) {
+                    tile = lo + i;
+                    break;
+                }
+            }
+            sh.misc[0] = tile;
+        }
         __syncthreads();
         const int tile = sh.misc[0];
         if (tile >= a.n_tiles) break;
@@ -281,7 +345,19 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                     }
                 }
             }
-            // ---- a4: window and chi2 scan over the window's bins
+            // ---- a4: hit-search window, then the window's bins scanned by the
+            // whole wave together.  Per-candidate windows differ widely (a diffuse
+            // state can cover many rows of bins), so lanes queue their rows and
+            // the wave walks the flattened (row, hit) list 64 x kScanBatch hits at
+            // a time; accepted hits are compacted with a ballot and each owner
+            // lane inserts its own into its sorted list.
+            if (lane_ok) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) sh.pred[k * W + t] = float(p[k]);
+#pragma unroll
+                for (int k = 0; k < 21; ++k) sh.predc[k * W + t] = P[k];
+                sh.pred[6 * W + t] = chi2;
+            }
             float lc2[kMaxCands];
             int32_t lid[kMaxCands], lbi[kMaxCands];
 #pragma unroll
@@ -291,84 +367,200 @@ __global__ __launch_bounds__(256) void find_kernel(FindArgs a)
                 lbi[k] = -1;
             }
             int nacc = 0;
+            int nrow = 0, row_lo = 0, v0 = 0, v1 = 0, np = 1, n2 = 1, row0 = 0;
             if (pl >= 0) {
                 const kf_layer L = sh.layers[pl];
                 const Window<T> Wn = make_window<T, C>(p, P, L, T(cut));
-                const bool scan = Wn.ok;
-                const bool all_phi = Wn.all_phi;
-                const T dphi = Wn.dphi, sin_dphi = Wn.sin_dphi, wv = Wn.wv, vlo = Wn.vlo,
-                        vhi = Wn.vhi;
-                const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
-                const int np = L.nbin_phi, n2 = L.nbin_2;
-                int b_lo = 0, b_hi = np - 1;
-                if (!scan) b_hi = -1;
-                if (scan && !all_phi) {
-                    const T phi = Tr<T>::atan2_(p[1], p[0]);
-                    b_lo = (int)Tr<T>::floor_((phi - dphi + T(kPi)) * T(np) / T(2.0 * kPi));
-                    b_hi = (int)Tr<T>::floor_((phi + dphi + T(kPi)) * T(np) / T(2.0 * kPi));
-                    if (b_hi - b_lo + 1 >= np || b_hi < b_lo) {
-                        b_lo = 0;
-                        b_hi = np - 1;
-                    }
-                }
-                const int v0 = coord_bin_of(float(vlo), float(L.lo), float(L.hi), n2);
-                const int v1 = coord_bin_of(float(vhi), float(L.lo), float(L.hi), n2);
-                const T cpp = p[0] / rho, spp = p[1] / rho;
-                const int row0 = ev * a.bl.per_event + a.bl.base[pl];
-                for (int bb = b_lo; bb <= b_hi; ++bb) {
-                    const int bphi = ((bb % np) + np) % np;
-                    const int rb = row0 + bphi * n2;
-                    const int h0 = a.bin_off[rb + v0], h1 = a.bin_off[rb + v1 + 1];
-                    for (int k = h0; k < h1; ++k) {
-                        const float4 r0 = *(const float4*)&a.bh[k].x;
-                        const float4 r1 = *(const float4*)&a.bh[k].sv;
-                        const float hcp = r1.y, hsp = r1.z;
-                        // |azimuth difference| <= dphi (< pi/2): same half-plane, |sin| bounded
-                        if (!all_phi && (!(T(hcp) * cpp + T(hsp) * spp > T(0)) ||
-                                         Tr<T>::abs_(T(hsp) * cpp - T(hcp) * spp) > sin_dphi))
-                            continue;
-                        T rv;
-                        if (L.kind == 0) rv = T(r0.z) - p[2];
-                        else rv = T(hcp) * (T(r0.x) - p[0]) + T(hsp) * (T(r0.y) - p[1]);
-                        if (Tr<T>::abs_(rv) > wv) continue;
-                        HitFrame<U> f;
-                        f.hx = U(r0.x);
-                        f.hy = U(r0.y);
-                        f.hz = U(r0.z);
-                        f.c = U(hcp);
-                        f.s = U(hsp);
-                        f.vu = U(r0.w) * U(r0.w);
-                        f.vv = U(r1.x) * U(r1.x);
-                        const U c2u = hit_chi2<T, C, U>(p, P, f, L.kind);
-                        ++n_chi2;
-                        if (!(c2u < U(cut))) continue;
-                        float c = float(c2u);
-                        int32_t id = __float_as_int(r1.w);
-                        int32_t bi = k;
-                        ++nacc;
-#pragma unroll
-                        for (int q = 0; q < kMaxCands; ++q) {
-                            const bool lt = c < lc2[q] || (c == lc2[q] && id < lid[q]);
-                            const float tc = lt ? lc2[q] : c;
-                            const int32_t ti = lt ? lid[q] : id;
-                            const int32_t tb = lt ? lbi[q] : bi;
-                            lc2[q] = lt ? c : lc2[q];
-                            lid[q] = lt ? id : lid[q];
-                            lbi[q] = lt ? bi : lbi[q];
-                            c = tc;
-                            id = ti;
-                            bi = tb;
+                if (Wn.ok) {
+                    np = L.nbin_phi;
+                    n2 = L.nbin_2;
+                    int b_lo = 0, b_hi = np - 1;
+                    if (!Wn.all_phi) {
+                        const T phi = Tr<T>::atan2_(p[1], p[0]);
+                        b_lo = (int)Tr<T>::floor_((phi - Wn.dphi + T(kPi)) * T(np) / T(2.0 * kPi));
+                        b_hi = (int)Tr<T>::floor_((phi + Wn.dphi + T(kPi)) * T(np) / T(2.0 * kPi));
+                        if (b_hi - b_lo + 1 >= np || b_hi < b_lo) {
+                            b_lo = 0;
+                            b_hi = np - 1;
                         }
                     }
+                    nrow = b_hi - b_lo + 1;
+                    row_lo = b_lo;
+                    v0 = coord_bin_of(float(Wn.vlo), float(L.lo), float(L.hi), n2);
+                    v1 = coord_bin_of(float(Wn.vhi), float(L.lo), float(L.hi), n2);
+                    row0 = ev * a.bl.per_event + a.bl.base[pl];
+                    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+                    sh.own[0 * W + t] = float(p[0] / rho);
+                    sh.own[1 * W + t] = float(p[1] / rho);
+                    sh.own[2 * W + t] = float(Wn.sin_dphi);
+                    sh.own[3 * W + t] = float(Wn.wv);
+                    sh.own[4 * W + t] = __int_as_float((Wn.all_phi ? 1 : 0) | (L.kind << 1));
                 }
             }
-            // ---- publish this lane's predicted state and children
+            {
+                const int wave = t >> 6, ln = t & 63;
+                const int wlanes = (W - (wave << 6)) < 64 ? (W - (wave << 6)) : 64;
+                int32_t* sg_own = sh.seg + wave * 3 * kSeg;
+                int32_t* sg_h0 = sg_own + kSeg;
+                int32_t* sg_len = sg_h0 + kSeg;
+                int32_t* sg_pre = sh.segpre + wave * (kSeg + 1);
+                int32_t* ac_own = sh.acc + wave * 3 * kAcc;
+                int32_t* ac_id = ac_own + kAcc;
+                int32_t* ac_bi = ac_id + kAcc;
+                float* ac_c2 = sh.accc2 + wave * kAcc;
+                // wave-wide exclusive prefix sum (and total) of one int per lane
+                auto wave_scan = [&](int v, int* total) {
+                    int incl = v;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int u = __shfl_up(incl, o);
+                        if (ln >= o) incl += u;
+                    }
+                    *total = __shfl(incl, wlanes - 1);
+                    return incl - v;
+                };
+                int row_next = 0;
+                for (;;) {
+                    // (1) queue up to kRowsPerLane rows per lane, in lane order, as
+                    //     many as fit; their bin ranges are loaded together
+                    constexpr int kRowsPerLane = 4;
+                    const int want = nrow - row_next < kRowsPerLane ? nrow - row_next : kRowsPerLane;
+                    int total = 0;
+                    const int base = wave_scan(want, &total);
+                    // the prefix below covers two queued rows per active lane
+                    const int segcap = 2 * wlanes < kSeg ? 2 * wlanes : kSeg;
+                    int take = segcap - base < want ? segcap - base : want;
+                    if (take < 0) take = 0;
+#pragma unroll
+                    for (int r = 0; r < kRowsPerLane; ++r) {
+                        if (r < take) {
+                            const int bb = row_lo + row_next + r;
+                            const int rb = row0 + (((bb % np) + np) % np) * n2;
+                            const int h0 = a.bin_off[rb + v0];
+                            const int h1 = a.bin_off[rb + v1 + 1];
+                            sg_own[base + r] = ln;
+                            sg_h0[base + r] = h0;
+                            sg_len[base + r] = h1 - h0;
+                        }
+                    }
+                    row_next += take;
+                    const int nseg = total < segcap ? total : segcap;
+                    wave_fence();
+                    // (2) prefix of the queued rows' hit counts, two rows per lane
+                    const int la = 2 * ln < nseg ? sg_len[2 * ln] : 0;
+                    const int lb = 2 * ln + 1 < nseg ? sg_len[2 * ln + 1] : 0;
+                    int H = 0;
+                    const int pre = wave_scan(la + lb, &H);
+                    if (2 * ln < nseg) sg_pre[2 * ln] = pre;
+                    if (2 * ln + 1 < nseg) sg_pre[2 * ln + 1] = pre + la;
+                    if (ln == 0) sg_pre[nseg] = H;
+                    wave_fence();
+                    // (3) the flattened hits, 64 x kScanBatch per round
+                    int nacc_w = 0;
+                    for (int g0 = 0; g0 < H; g0 += wlanes * kScanBatch) {
+                        float4 r0[kScanBatch], r1[kScanBatch];
+                        int own[kScanBatch], bix[kScanBatch];
+#pragma unroll
+                        for (int q = 0; q < kScanBatch; ++q) {
+                            const int g = g0 + q * wlanes + ln;
+                            own[q] = -1;
+                            bix[q] = 0;
+                            if (g < H) {
+                                int lo = 0, hi = nseg;            // sg_pre[lo] <= g < sg_pre[hi]
+                                while (hi - lo > 1) {
+                                    const int mid = (lo + hi) >> 1;
+                                    if (sg_pre[mid] <= g) lo = mid;
+                                    else hi = mid;
+                                }
+                                own[q] = sg_own[lo];
+                                bix[q] = sg_h0[lo] + (g - sg_pre[lo]);
+                            }
+                            r0[q] = *(const float4*)&a.bh[bix[q]].x;
+                            r1[q] = *(const float4*)&a.bh[bix[q]].sv;
+                        }
+#pragma unroll
+                        for (int q = 0; q < kScanBatch; ++q) {
+                            bool ok = false;
+                            float c2f = 0.0f;
+                            const int o = own[q];
+                            if (o >= 0) {
+                                const int ot = (wave << 6) + o;
+                                const float hcp = r1[q].y, hsp = r1[q].z;
+                                const T cpp = T(sh.own[0 * W + ot]), spp = T(sh.own[1 * W + ot]);
+                                const T sin_dphi = T(sh.own[2 * W + ot]), wv = T(sh.own[3 * W + ot]);
+                                const int fl = __float_as_int(sh.own[4 * W + ot]);
+                                const int kind = fl >> 1;
+                                const T ox = T(sh.pred[0 * W + ot]), oy = T(sh.pred[1 * W + ot]),
+                                        oz = T(sh.pred[2 * W + ot]);
+                                // |azimuth difference| <= dphi (< pi/2): same half-plane, |sin| bounded
+                                bool pass = (fl & 1) || (T(hcp) * cpp + T(hsp) * spp > T(0) &&
+                                                         !(Tr<T>::abs_(T(hsp) * cpp - T(hcp) * spp) >
+                                                           sin_dphi));
+                                if (pass) {
+                                    const T rv = kind == 0 ? T(r0[q].z) - oz
+                                                           : T(hcp) * (T(r0[q].x) - ox) +
+                                                                 T(hsp) * (T(r0[q].y) - oy);
+                                    pass = !(Tr<T>::abs_(rv) > wv);
+                                }
+                                if (pass) {
+                                    HitFrame<U> f;
+                                    f.hx = U(r0[q].x);
+                                    f.hy = U(r0[q].y);
+                                    f.hz = U(r0[q].z);
+                                    f.c = U(hcp);
+                                    f.s = U(hsp);
+                                    f.vu = U(r0[q].w) * U(r0[q].w);
+                                    f.vv = U(r1[q].x) * U(r1[q].x);
+                                    const U c2u = hit_chi2_pos<U>(
+                                        U(ox), U(oy), U(oz), U(sh.predc[pk(0, 0) * W + ot]),
+                                        U(sh.predc[pk(0, 1) * W + ot]), U(sh.predc[pk(0, 2) * W + ot]),
+                                        U(sh.predc[pk(1, 1) * W + ot]), U(sh.predc[pk(1, 2) * W + ot]),
+                                        U(sh.predc[pk(2, 2) * W + ot]), f, kind);
+                                    ++n_chi2;
+                                    ok = c2u < U(cut);
+                                    c2f = float(c2u);
+                                }
+                            }
+                            const unsigned long long m = __ballot(ok);
+                            const int pos = nacc_w + __popcll(m & ((1ull << ln) - 1ull));
+                            if (ok) {
+                                ac_own[pos] = o;
+                                ac_id[pos] = __float_as_int(r1[q].w);
+                                ac_bi[pos] = bix[q];
+                                ac_c2[pos] = c2f;
+                            }
+                            nacc_w += __popcll(m);
+                        }
+                        wave_fence();
+                        // (4) owners take their accepted hits
+                        for (int j = 0; j < nacc_w; ++j) {
+                            if (ac_own[j] != ln) continue;
+                            float c = ac_c2[j];
+                            int32_t id = ac_id[j], bi = ac_bi[j];
+                            ++nacc;
+#pragma unroll
+                            for (int q = 0; q < kMaxCands; ++q) {
+                                const bool lt = c < lc2[q] || (c == lc2[q] && id < lid[q]);
+                                const float tc = lt ? lc2[q] : c;
+                                const int32_t ti = lt ? lid[q] : id;
+                                const int32_t tb = lt ? lbi[q] : bi;
+                                lc2[q] = lt ? c : lc2[q];
+                                lid[q] = lt ? id : lid[q];
+                                lbi[q] = lt ? bi : lbi[q];
+                                c = tc;
+                                id = ti;
+                                bi = tb;
+                            }
+                        }
+                        nacc_w = 0;
+                        wave_fence();
+                    }
+                    // the queue is rewritten next round: every lane is done reading it
+                    wave_fence();
+                    if (!__any(row_next < nrow)) break;
+                }
+            }
+            // ---- publish this lane's step outcome and children
             if (lane_ok) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) sh.pred[k * W + t] = float(p[k]);
-#pragma unroll
-                for (int k = 0; k < 21; ++k) sh.predc[k * W + t] = P[k];
-                sh.pred[6 * W + t] = chi2;
                 sh.meta[0 * W + t] = nhits;
                 sh.meta[1 * W + t] = misses;
                 sh.meta[2 * W + t] = (int32_t)status;

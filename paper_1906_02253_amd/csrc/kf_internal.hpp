@@ -33,7 +33,7 @@ struct kf_ctx {
     kfmi::Workspace ws;               // general scratch of the find path
     int n_cu = 0;                     // compute units of the device
     int max_lds = 0;                  // LDS bytes a workgroup may use
-    int find_width = 256;             // lanes per workgroup of the finding kernel
+    int find_width = 64;              // lanes per workgroup of the finding kernel
     int find_largest_first = 1;       // tile order
     int occ_cache[2][9] = {};         // resident workgroups per CU by (precision, log2 width)
     int timing_cap = 0;               // event sets available (0: timing off)

@@ -313,33 +313,38 @@ KF_HD inline HitFrame<U> hit_frame(float x, float y, float z, float su, float sv
     return f;
 }
 
-// chi2 of a hit against (p, P) without updating
+// chi2 of a hit against a predicted position (x, y, z) and the position
+// block of its covariance, without updating
+template <typename U>
+KF_HD inline U hit_chi2_pos(U x, U y, U z, U P00, U P01, U P02, U P11, U P12, U P22,
+                            const HitFrame<U>& f, int kind)
+{
+    const U c = f.c, s = f.s;
+    const U ru = -s * (f.hx - x) + c * (f.hy - y);
+    // first three rows of P H^T (what S needs)
+    const U b00 = -s * P00 + c * P01, b01 = -s * P01 + c * P11;
+    U S00 = -s * b00 + c * b01 + f.vu;
+    U rv, S01, S11;
+    if (kind == 0) {
+        rv = f.hz - z;
+        S01 = -s * P02 + c * P12;
+        S11 = P22 + f.vv;
+    } else {
+        rv = c * (f.hx - x) + s * (f.hy - y);
+        const U b10 = c * P00 + s * P01, b11 = c * P01 + s * P11;
+        S01 = -s * b10 + c * b11;
+        S11 = c * b10 + s * b11 + f.vv;
+    }
+    const U det = S00 * S11 - S01 * S01;
+    if (!(det > U(0)) || !(S00 > U(0))) return U(1e30);
+    return (ru * ru * S11 - U(2) * ru * rv * S01 + rv * rv * S00) / det;
+}
+
 template <typename T, typename C, typename U>
 KF_HD inline U hit_chi2(const T p[6], const C P[21], const HitFrame<U>& f, int kind)
 {
-    const U c = f.c, s = f.s;
-    U ru = -s * (f.hx - U(p[0])) + c * (f.hy - U(p[1]));
-    U rv;
-    U b0[3], b1[3];   // first three rows of P H^T (what S needs)
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        b0[i] = -s * U(P[pk(i, 0)]) + c * U(P[pk(i, 1)]);
-        b1[i] = kind == 0 ? U(P[pk(i, 2)]) : c * U(P[pk(i, 0)]) + s * U(P[pk(i, 1)]);
-    }
-    U S00 = -s * b0[0] + c * b0[1] + f.vu;
-    U S01, S11;
-    if (kind == 0) {
-        rv = f.hz - U(p[2]);
-        S01 = -s * b1[0] + c * b1[1];
-        S11 = b1[2] + f.vv;
-    } else {
-        rv = c * (f.hx - U(p[0])) + s * (f.hy - U(p[1]));
-        S01 = -s * b1[0] + c * b1[1];
-        S11 = c * b1[0] + s * b1[1] + f.vv;
-    }
-    U det = S00 * S11 - S01 * S01;
-    if (!(det > U(0)) || !(S00 > U(0))) return U(1e30);
-    return (ru * ru * S11 - U(2) * ru * rv * S01 + rv * rv * S00) / det;
+    return hit_chi2_pos<U>(U(p[0]), U(p[1]), U(p[2]), U(P[pk(0, 0)]), U(P[pk(0, 1)]),
+                           U(P[pk(0, 2)]), U(P[pk(1, 1)]), U(P[pk(1, 2)]), U(P[pk(2, 2)]), f, kind);
 }
 
 // Kalman update with a 2D hit.  Gain K = P H^T S^-1, state x + K r, covariance
