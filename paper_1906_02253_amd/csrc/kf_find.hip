@@ -165,8 +165,10 @@ struct FindShared {
     float* own;         // [5][W] cos/sin of the predicted azimuth, sin(dphi), wv, flags
     int32_t* seg;       // [n_waves][3][kSeg] queued phi rows: owner lane, first hit, count
     int32_t* segpre;    // [n_waves][kSeg + 1] prefix of the rows' hit counts
-    int32_t* acc;       // [n_waves][3][kAcc] accepted hits: owner lane, hit index, binned index
+    int32_t* acc;       // [n_waves][3][kAcc] accepted hits: next of the same owner, hit index, binned index
     float* accc2;       // [n_waves][kAcc] their chi2
+    int32_t* rowp;      // [n_waves][5][64] per owner lane: row prefix, first row, bins, base, sizes
+    int32_t* achead;    // [n_waves][64] per owner lane: first accepted hit of its list, -1 = none
 };
 
 constexpr int kSeg = 128;       // phi rows queued per wave per round
@@ -193,6 +195,8 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
     b += sizeof(float) * 5 * W;
     b += sizeof(int32_t) * nw * (3 * kSeg + kSeg + 1 + 3 * kAcc);
     b += sizeof(float) * nw * kAcc;
+    b += sizeof(int32_t) * nw * 5 * 64;
+    b += sizeof(int32_t) * nw * 64;
     return (b + 15) & ~size_t(15);
 }
 
@@ -249,6 +253,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         sh.acc = (int32_t*)q;
         q += sizeof(int32_t) * nw * 3 * kAcc;
         sh.accc2 = (float*)q;
+        q += sizeof(float) * nw * kAcc;
+        sh.rowp = (int32_t*)q;
+        q += sizeof(int32_t) * nw * 5 * 64;
+        sh.achead = (int32_t*)q;
     }
     const int t = threadIdx.x;
     for (int l = t; l < nl; l += W) sh.layers[l] = a.layers[l];
@@ -404,8 +412,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 int32_t* sg_h0 = sg_own + kSeg;
                 int32_t* sg_len = sg_h0 + kSeg;
                 int32_t* sg_pre = sh.segpre + wave * (kSeg + 1);
-                int32_t* ac_own = sh.acc + wave * 3 * kAcc;
-                int32_t* ac_id = ac_own + kAcc;
+                int32_t* ac_next = sh.acc + wave * 3 * kAcc;   // next accepted hit of the same owner
+                int32_t* ac_id = ac_next + kAcc;
                 int32_t* ac_bi = ac_id + kAcc;
                 float* ac_c2 = sh.accc2 + wave * kAcc;
                 // wave-wide exclusive prefix sum (and total) of one int per lane
@@ -418,32 +426,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     *total = __shfl(incl, wlanes - 1);
                     return incl - v;
                 };
-                int row_next = 0;
-                for (;;) {
-                    // (1) queue up to kRowsPerLane rows per lane, in lane order, as
-                    //     many as fit; their bin ranges are loaded together
-                    constexpr int kRowsPerLane = 4;
-                    const int want = nrow - row_next < kRowsPerLane ? nrow - row_next : kRowsPerLane;
-                    int total = 0;
-                    const int base = wave_scan(want, &total);
-                    // the prefix below covers two queued rows per active lane
-                    const int segcap = 2 * wlanes < kSeg ? 2 * wlanes : kSeg;
-                    int take = segcap - base < want ? segcap - base : want;
-                    if (take < 0) take = 0;
+                // rows of every lane, flattened: lane o owns rows [rowpre[o],
+                // rowpre[o] + nrow_o) of the wave's row list
+                int32_t* ac_head = sh.achead + wave * 64;
+                ac_head[ln] = -1;
+                int R = 0;
+                const int rpre = wave_scan(nrow, &R);
+                // the row parameters of each owner, for the lanes that expand its rows
+                int32_t* rw_par = sh.rowp + wave * 5 * 64;
+                rw_par[ln] = rpre;
+                rw_par[64 + ln] = row_lo;
+                rw_par[128 + ln] = v0 | (v1 << 16);
+                rw_par[192 + ln] = row0;
+                rw_par[256 + ln] = np | (n2 << 16);
+                wave_fence();
+                const int segcap = 2 * wlanes < kSeg ? 2 * wlanes : kSeg;
+                for (int rr0 = 0; rr0 < R; rr0 += segcap) {
+                    // (1) queue rows rr0 .. rr0 + segcap - 1, two per lane; their bin
+                    //     ranges are loaded together
+                    const int nseg = R - rr0 < segcap ? R - rr0 : segcap;
 #pragma unroll
-                    for (int r = 0; r < kRowsPerLane; ++r) {
-                        if (r < take) {
-                            const int bb = row_lo + row_next + r;
-                            const int rb = row0 + (((bb % np) + np) % np) * n2;
-                            const int h0 = a.bin_off[rb + v0];
-                            const int h1 = a.bin_off[rb + v1 + 1];
-                            sg_own[base + r] = ln;
-                            sg_h0[base + r] = h0;
-                            sg_len[base + r] = h1 - h0;
+                    for (int r = 0; r < 2; ++r) {
+                        const int j = r * wlanes + ln;
+                        if (j < nseg) {
+                            const int g = rr0 + j;
+                            int lo = 0, hi = wlanes;      // rowpre[lo] <= g < rowpre[hi]
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (rw_par[mid] <= g) lo = mid;
+                                else hi = mid;
+                            }
+                            const int o = lo;
+                            const int bb = rw_par[64 + o] + (g - rw_par[o]);
+                            const int vv = rw_par[128 + o], pp = rw_par[256 + o];
+                            const int onp = pp & 0xFFFF, on2 = pp >> 16;
+                            const int rb = rw_par[192 + o] + (((bb % onp) + onp) % onp) * on2;
+                            const int h0 = a.bin_off[rb + (vv & 0xFFFF)];
+                            const int h1 = a.bin_off[rb + (vv >> 16) + 1];
+                            sg_own[j] = o;
+                            sg_h0[j] = h0;
+                            sg_len[j] = h1 - h0;
                         }
                     }
-                    row_next += take;
-                    const int nseg = total < segcap ? total : segcap;
                     wave_fence();
                     // (2) prefix of the queued rows' hit counts, two rows per lane
                     const int la = 2 * ln < nseg ? sg_len[2 * ln] : 0;
@@ -523,17 +547,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                             const unsigned long long m = __ballot(ok);
                             const int pos = nacc_w + __popcll(m & ((1ull << ln) - 1ull));
                             if (ok) {
-                                ac_own[pos] = o;
                                 ac_id[pos] = __float_as_int(r1[q].w);
                                 ac_bi[pos] = bix[q];
                                 ac_c2[pos] = c2f;
+                                // thread it onto its owner's list
+                                ac_next[pos] = atomicExch(&ac_head[o], pos);
                             }
                             nacc_w += __popcll(m);
                         }
                         wave_fence();
-                        // (4) owners take their accepted hits
-                        for (int j = 0; j < nacc_w; ++j) {
-                            if (ac_own[j] != ln) continue;
+                        // (4) owners take their accepted hits from their own lists
+                        for (int j = ac_head[ln]; j >= 0; j = ac_next[j]) {
                             float c = ac_c2[j];
                             int32_t id = ac_id[j], bi = ac_bi[j];
                             ++nacc;
@@ -551,12 +575,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                                 bi = tb;
                             }
                         }
+                        ac_head[ln] = -1;
                         nacc_w = 0;
                         wave_fence();
                     }
                     // the queue is rewritten next round: every lane is done reading it
                     wave_fence();
-                    if (!__any(row_next < nrow)) break;
                 }
             }
             // ---- publish this lane's step outcome and children
