@@ -8,9 +8,11 @@ with mean ~ U(200, 4000), 60 noise hits per track, ten barrel layers plus
 one pass of the whole finding path over the batch, inputs resident in HBM:
 seed every track from its first three hits (kf_seed), Kalman-fit the three
 seed hits (kf_fit), then kf_find (hit binning, seed ordering, the persistent
-finding kernel).  A KF step is one propagation of a track or candidate to a
-surface together with its update(s): the three seed-fit steps per seed plus
-the finding kernel's propagations (counted by the kernel itself).
+finding kernel), replayed as one captured HIP graph (kf_find_batched) after
+the autotuner has picked the finding width and tile order.  A KF step is one
+propagation of a track or candidate to a surface together with its
+update(s): the three seed-fit steps per seed plus the finding kernel's
+propagations (counted by the kernel itself).
 
 Prints ONE JSON line: metric, value, the roofline of the dominant kernel
 (the finding kernel, arithmetic-bound: algorithmic flops from the operation
@@ -42,7 +44,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--width", type=int, default=256)
+    ap.add_argument("--width", type=int, default=0,
+                    help="finding workgroup width; 0 = autotune width and tile order")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--fit-tracks", type=int, default=4_000_000)
@@ -178,28 +181,40 @@ def main():
           f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
 
     ctx = K.Context(geom)
-    ctx.set_find_config(args.width, True)
     fp = pipeline.FindProblem(ctx, inp)
+    fp.run()
+    tune = None
+    if args.width:
+        ctx.set_find_config(args.width, False)
+    else:
+        tune = fp.autotune(reps=3)
+        print("# autotune (width, largest_first) -> ms: " +
+              ", ".join(f"{w}/{int(lf)}: {ms:.3f}" for (w, lf), ms in sorted(tune.items())),
+              file=sys.stderr, flush=True)
+    width, largest_first = ctx.find_config()
+    # the timed pass: seeding, seed fit, binning, seed order and the finding
+    # kernel replayed as one captured graph
     for _ in range(args.warmup):
-        fp.run()
+        fp.run_batched()
     torch.cuda.synchronize()
     c0 = fp.counters.clone()
     ctx.set_timing(args.steps)
     torch.cuda.synchronize()
     start = time.perf_counter()
     for _ in range(args.steps):
-        fp.run()
+        fp.run_batched()
     torch.cuda.synchronize()
     wall = time.perf_counter() - start
-    (ms_bin, ms_sort, ms_kernel), n_rec = ctx.timings()
+    (ms_seed, ms_bin, ms_sort, ms_kernel), n_rec = ctx.timings()
     cnt = ((fp.counters - c0).double() / args.steps).cpu().numpy()
     ms_per_step = wall * 1e3 / args.steps
     kf_steps = 3 * n_seeds + cnt[0]
     value = kf_steps / (ms_per_step * 1e-3)
     flops = find_flops(cnt, oc)
     tflops = flops / (ms_kernel * 1e-3) / 1e12
-    print(f"# {ms_per_step:.3f} ms/step, find kernel {ms_kernel:.3f} ms, binning {ms_bin:.3f} ms, "
-          f"seed order {ms_sort:.3f} ms, {kf_steps:.0f} KF steps/pass", file=sys.stderr, flush=True)
+    print(f"# {ms_per_step:.3f} ms/step, find kernel {ms_kernel:.3f} ms, seed+fit {ms_seed:.3f} ms, "
+          f"binning {ms_bin:.3f} ms, seed order {ms_sort:.3f} ms, {kf_steps:.0f} KF steps/pass",
+          file=sys.stderr, flush=True)
 
     result = {
         "metric": "KF prop+update steps/s",
@@ -218,13 +233,18 @@ def main():
                                "hits/track, 10 barrel layers + 2x7 disks, |eta|<2.5, 0.02 X0, "
                                "chi2<30, <=6 candidates/seed; seed + seed fit + kf_find",
                    "n_events": len(evs), "n_seeds": n_seeds, "n_hits": int(inp["x"].shape[0]),
-                   "kf_steps_per_pass": kf_steps, "width": args.width, "precision": "mixed",
+                   "kf_steps_per_pass": kf_steps, "width": width,
+                   "tile_order": "largest events first" if largest_first else "event, eta, phi",
+                   "autotune_ms": {f"{w}/{int(lf)}": ms for (w, lf), ms in sorted(tune.items())}
+                   if tune else None,
+                   "launch": "hipGraph replay (kf_find_batched)", "precision": "mixed",
                    "init": "plain"},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": "find_kernel<float,double,double>", "kernel_ms": ms_kernel,
                      "flops_per_launch": flops, "events_per_launch": cnt.tolist()},
-        "phases_ms": {"binning": ms_bin, "seed_order": ms_sort, "find_kernel": ms_kernel},
+        "phases_ms": {"seed_and_seed_fit": ms_seed, "binning": ms_bin, "seed_order": ms_sort,
+                      "find_kernel": ms_kernel},
     }
 
     if not args.no_fit:

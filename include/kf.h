@@ -72,7 +72,8 @@ enum {
 typedef struct {
     int32_t kind;          /* 0 = barrel cylinder, 1 = disk */
     int32_t nbin_phi;      /* hit bins in phi over [-pi, pi) */
-    int32_t nbin_2;        /* hit bins in z (barrel) / r (disk) over [lo, hi] */
+    int32_t nbin_2;        /* hit bins in z (barrel) / r (disk) over [lo, hi];
+                              nbin_phi * nbin_2 <= 16384 */
     int32_t reserved;      /* 0 */
     double r_or_z;         /* barrel radius / disk z */
     double lo, hi;         /* barrel: z extent [lo, hi]; disk: radial extent */
@@ -171,20 +172,54 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
             const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
             int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream);
 
+/* The whole finding pass over a batch of events as one captured HIP graph
+ * (paper Sec. 3.2: seeds processed in parallel; events of uneven size in one
+ * persistent launch): kf_seed of every seed from its three hits, kf_fit over
+ * those hits (layers seed_layers [3][seeds->ld] int32), then kf_find as above.
+ * seeds is caller-owned scratch for the seed states (n = number of seeds);
+ * the other arguments are those of kf_find.  The first call with a given set
+ * of pointers, sizes, flags and finding configuration captures the pass into
+ * a graph held by the context; later calls with the same set replay it, so
+ * the caller must keep those arrays alive and in place between calls (any
+ * change captures again).  The graph holds kernels and event records only.
+ * Results are identical to kf_seed + kf_fit + kf_find. */
+int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+                    const int32_t* seed_hits, const int32_t* seed_layers, const int32_t* seed_event,
+                    kf_tracks* seeds, int32_t* out_hits, kf_tracks* out, uint64_t* counters,
+                    int flags, void* stream);
+
 /* Workgroup width of the finding kernel (32, 64, 128 or 256 lanes; a lane per
  * candidate slot, width / max_cands seeds per tile) and tile order (0: seeds
- * sorted by event, eta, phi; 1: largest events first).  Default 64, 1. */
+ * sorted by event, eta, phi; 1: events largest first, then eta, phi).
+ * Default 64, 0.  Results do not depend on either; speed does. */
 int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first);
+/* The configuration in use (host outputs). */
+int kf_get_find_config(kf_ctx* ctx, int32_t* width, int32_t* largest_first);
+
+/* Autotuner: times kf_find on the caller's sample (arguments as kf_find, no
+ * counters) for every width in {32, 64, 128, 256} that fits the device's LDS
+ * and both tile orders: one untimed call per configuration, then reps rounds
+ * over all configurations with every call timed on its own; the fastest call
+ * of a configuration is its time, and the fastest configuration is kept in
+ * the context (kf_get_find_config reads it).  table: optional host float [8],
+ * ms at [2*w + order] for widths 32, 64, 128, 256 (-1 = not run).
+ * Synchronises on `stream` after every timed call.
+ * out_hits and out hold the results of the last configuration tried. */
+int kf_autotune(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+                const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
+                int32_t* out_hits, kf_tracks* out, int flags, int32_t reps, float* table,
+                void* stream);
 
 /* Kernel timing.  kf_set_timing(ctx, n) with 1 <= n <= 256 makes the next n
- * kf_find calls record HIP events on their stream around their three phases
- * (hit binning, seed ordering, finding kernel), one event set per call, with
- * no host synchronisation; n = 0 turns it off.  kf_timings synchronises on
- * the last recorded event and writes the mean milliseconds over the recorded
- * calls: ms[0] binning, ms[1] seed ordering, ms[2] finding kernel, and
- * ms[3] = number of calls recorded.  Returns KF_EINVAL if none was. */
+ * kf_find or kf_find_batched calls record HIP events on their stream at the
+ * boundaries of their phases (seed + seed fit, hit binning, seed ordering,
+ * finding kernel), one event set per call, with no host synchronisation;
+ * n = 0 turns it off.  kf_timings synchronises on the last recorded event and
+ * writes the mean milliseconds over the recorded calls: ms[0] seeding and
+ * seed fit (0 for kf_find), ms[1] binning, ms[2] seed ordering, ms[3] finding
+ * kernel, and ms[4] = number of calls recorded.  Returns KF_EINVAL if none was. */
 int kf_set_timing(kf_ctx* ctx, int32_t n);
-int kf_timings(kf_ctx* ctx, float ms[4]);
+int kf_timings(kf_ctx* ctx, float ms[5]);
 
 #ifdef __cplusplus
 }

@@ -58,11 +58,17 @@ def _load():
     L.kf_fit.argtypes = [vp, C.POINTER(KfTracks), C.POINTER(KfHits), vp, vp, i32, C.c_int, vp]
     L.kf_find.argtypes = [vp, C.POINTER(KfHits), vp, i32, C.POINTER(KfTracks), vp, vp, vp,
                           C.POINTER(KfTracks), vp, C.c_int, vp]
+    L.kf_find_batched.argtypes = [vp, C.POINTER(KfHits), vp, i32, vp, vp, vp, C.POINTER(KfTracks),
+                                  vp, C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_set_find_config.argtypes = [vp, i32, i32]
+    L.kf_get_find_config.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.kf_autotune.argtypes = [vp, C.POINTER(KfHits), vp, i32, C.POINTER(KfTracks), vp, vp, vp,
+                              C.POINTER(KfTracks), C.c_int, i32, C.POINTER(C.c_float), vp]
     L.kf_set_timing.argtypes = [vp, i32]
     L.kf_timings.argtypes = [vp, C.POINTER(C.c_float)]
-    for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_set_find_config",
-              "kf_set_timing", "kf_timings"):
+    for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_find_batched",
+              "kf_set_find_config", "kf_get_find_config", "kf_autotune", "kf_set_timing",
+              "kf_timings"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -196,27 +202,55 @@ class Context:
                                _ptr(hit_idx), int(max_steps), flags, _stream()), "kf_fit")
 
     def set_timing(self, n=1):
-        """Record kernel events for the next n kf_find calls (0: off)."""
+        """Record phase events for the next n kf_find / kf_find_batched calls (0: off)."""
         self._check(lib.kf_set_timing(self.h, int(n)), "kf_set_timing")
 
     def timings(self):
-        """Mean (binning, seed ordering, finding kernel) ms over the recorded calls,
-        and the number of calls recorded."""
-        ms = (C.c_float * 4)()
+        """Mean (seeding + seed fit, binning, seed ordering, finding kernel) ms
+        over the recorded calls, and the number of calls recorded."""
+        ms = (C.c_float * 5)()
         self._check(lib.kf_timings(self.h, ms), "kf_timings")
-        return tuple(ms[:3]), int(ms[3])
+        return tuple(ms[:4]), int(ms[4])
 
-    def set_find_config(self, width=256, largest_first=True):
+    def set_find_config(self, width=64, largest_first=False):
         self._check(lib.kf_set_find_config(self.h, int(width), int(bool(largest_first))),
                     "kf_set_find_config")
+
+    def find_config(self):
+        w, lf = C.c_int32(), C.c_int32()
+        self._check(lib.kf_get_find_config(self.h, C.byref(w), C.byref(lf)), "kf_get_find_config")
+        return int(w.value), bool(lf.value)
 
     def find(self, hits, event_off, seeds, seed_event, seed_hits, out_hits, out, counters=None,
              flags=0):
         """event_off: int32 [n_events+1]; seed_event: int32 [n_seeds];
         seed_hits: int32 [3, seeds.ld]; out_hits: int32 [n_seeds, n_layers];
-        counters: optional int64 [2] (propagations, updates), accumulated."""
+        counters: optional int64 [5], accumulated."""
         n_events = int(event_off.shape[0]) - 1
         self._check(lib.kf_find(self.h, C.byref(hits.c()), _ptr(event_off), n_events,
                                 C.byref(seeds.c()), _ptr(seed_event), _ptr(seed_hits),
                                 _ptr(out_hits), C.byref(out.c()), _ptr(counters), flags,
                                 _stream()), "kf_find")
+
+    def find_batched(self, hits, event_off, seed_hits, seed_layers, seed_event, seeds, out_hits,
+                     out, counters=None, flags=0):
+        """Seed, seed fit and find in one captured graph (replayed while the
+        arrays stay the same).  seeds: scratch Tracks for the seed states."""
+        n_events = int(event_off.shape[0]) - 1
+        self._check(lib.kf_find_batched(self.h, C.byref(hits.c()), _ptr(event_off), n_events,
+                                        _ptr(seed_hits), _ptr(seed_layers), _ptr(seed_event),
+                                        C.byref(seeds.c()), _ptr(out_hits), C.byref(out.c()),
+                                        _ptr(counters), flags, _stream()), "kf_find_batched")
+
+    def autotune(self, hits, event_off, seeds, seed_event, seed_hits, out_hits, out, flags=0,
+                 reps=3):
+        """Times every (width, tile order); keeps the fastest.  Returns
+        {(width, largest_first): ms}."""
+        n_events = int(event_off.shape[0]) - 1
+        tab = (C.c_float * 8)()
+        self._check(lib.kf_autotune(self.h, C.byref(hits.c()), _ptr(event_off), n_events,
+                                    C.byref(seeds.c()), _ptr(seed_event), _ptr(seed_hits),
+                                    _ptr(out_hits), C.byref(out.c()), flags, int(reps), tab,
+                                    _stream()), "kf_autotune")
+        return {(w, bool(lf)): tab[2 * i + lf] for i, w in enumerate((32, 64, 128, 256))
+                for lf in (0, 1) if tab[2 * i + lf] >= 0}

@@ -77,7 +77,181 @@ void Workspace::release()
     bytes = 0;
 }
 
+
+// Validated, laid-out finding pass: the phases enqueue from this.
+struct FindLaunch {
+    FindPlan pl;
+    FindArgs a;
+    int W = 0, grid = 0, prec = 0, largest_first = 0;
+    int64_t n_events = 0;
+    const int32_t* event_off = nullptr;
+    const int32_t* seed_event = nullptr;
+    const kf_hits* hits = nullptr;
+    const kf_tracks* seeds = nullptr;
+};
+
 }  // namespace kfmi
+
+namespace {
+
+// Checks the arguments of a finding pass, sizes and takes the workspace and
+// fills `L`.  Returns KF_OK or an error code (message set).
+int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+                 const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
+                 int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, const char* what,
+                 kfmi::FindLaunch* L)
+{
+    int r = check_tracks(ctx, seeds, what);
+    if (r) return r;
+    r = check_tracks(ctx, out, what);
+    if (r) return r;
+    r = check_hits(ctx, hits, what);
+    if (r) return r;
+    const int prec = flags & KF_PREC_MASK;
+    if (prec == KF_PREC_FP64)
+        return fail(ctx, KF_EUNSUPPORTED, "%s: float storage only (MIXED or FP32)", what);
+    if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
+        return fail(ctx, KF_EINVAL, "%s: bad precision flag", what);
+    if (flags & KF_INIT_MLP) return fail(ctx, KF_EUNSUPPORTED, "%s: no learned model loaded", what);
+    if (out->n != seeds->n) return fail(ctx, KF_EINVAL, "%s: out->n must equal seeds->n", what);
+    if (n_events < 1 || !event_off) return fail(ctx, KF_EINVAL, "%s: need n_events >= 1 and event_off", what);
+    if (hits->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "%s: at most 2^31-1 hits", what);
+    if (seeds->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "%s: at most 2^31-1 seeds", what);
+    if (seeds->n > 0 && (!seed_event || !seed_hits || !out_hits))
+        return fail(ctx, KF_EINVAL, "%s: null seed_event, seed_hits or out_hits", what);
+    const int W = ctx->find_width;
+    const int MC = ctx->params.max_cands;
+    const int S = W / MC;
+    const int nl = ctx->n_layers;
+    kfmi::FindPlan& pl = L->pl;
+    int64_t per_event = 0;
+    for (int l = 0; l < nl; ++l) {
+        pl.bl.base[l] = (int32_t)per_event;
+        per_event += (int64_t)ctx->layers[l].nbin_phi * ctx->layers[l].nbin_2;
+    }
+    if ((int64_t)n_events * per_event >= 0x7fffffffLL ||
+        (int64_t)n_events * 4096 >= 0x7fffffffLL)
+        return fail(ctx, KF_EINVAL, "%s: n_events x bins per event exceeds 2^31", what);
+    pl.bl.per_event = (int32_t)per_event;
+    const size_t lds = kfmi::find_shared_size(W, S, nl, prec);
+    if (ctx->max_lds > 0 && lds > (size_t)ctx->max_lds)
+        return fail(ctx, KF_EUNSUPPORTED, "%s: width %d needs %zu bytes of LDS, device allows %d",
+                    what, W, lds, ctx->max_lds);
+    int lw = 0;
+    while ((1 << lw) < W) ++lw;
+    const int pi = prec == KF_PREC_FP32 ? 1 : 0;
+    int& occ = ctx->occ_cache[pi][lw];
+    if (occ == 0) {
+        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, &occ);
+        if (e != hipSuccess) return hip_fail(ctx, e, "find occupancy");
+        if (occ < 1) occ = 1;
+    }
+    const int64_t n_tiles = (seeds->n + S - 1) / S;
+    int64_t grid = (int64_t)occ * (ctx->n_cu > 0 ? ctx->n_cu : 1);
+    if (grid > n_tiles) grid = n_tiles;
+    if (grid < 1) grid = 1;
+    const size_t bytes = kfmi::plan_find(&pl, nullptr, hits->n, n_events, seeds->n, nl, (int)grid, S);
+    void* base = ctx->ws.get(bytes);
+    if (!base) return fail(ctx, KF_ENOMEM, "%s: workspace of %zu bytes", what, bytes);
+    kfmi::plan_find(&pl, base, hits->n, n_events, seeds->n, nl, (int)grid, S);
+    kfmi::FindArgs& a = L->a;
+    a.bh = (const kfmi::BinnedHit*)pl.binned;
+    a.bin_off = pl.off;
+    a.bl = pl.bl;
+    a.n_hits = hits->n;
+    a.hit_layer = hits->layer;
+    a.n_seeds = seeds->n;
+    a.sld = seeds->ld;
+    a.spar = (const float*)seeds->par;
+    a.scov = seeds->cov;
+    a.schi2 = (const float*)seeds->chi2;
+    a.sndf = seeds->ndf;
+    a.sstatus = seeds->status;
+    a.seed_event = seed_event;
+    a.n_events = n_events;
+    a.seed_hits = seed_hits;
+    a.order = pl.order;
+    a.out_hits = out_hits;
+    a.old = out->ld;
+    a.opar = (float*)out->par;
+    a.ocov = out->cov;
+    a.ochi2 = (float*)out->chi2;
+    a.ondf = out->ndf;
+    a.ostatus = out->status;
+    a.bp = pl.bp;
+    a.tile_counter = pl.tile_counter;
+    a.counters = (unsigned long long*)counters;
+    a.layers = ctx->d_layers;
+    a.n_layers = nl;
+    a.prm = ctx->params;
+    a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    a.n_tiles = (int)n_tiles;
+    a.seeds_per_tile = S;
+    L->W = W;
+    L->grid = (int)grid;
+    L->prec = prec;
+    L->largest_first = ctx->find_largest_first;
+    L->n_events = n_events;
+    L->event_off = event_off;
+    L->seed_event = seed_event;
+    L->hits = hits;
+    L->seeds = seeds;
+    return KF_OK;
+}
+
+hipError_t phase_bin(const kf_ctx* ctx, const kfmi::FindLaunch& L, hipStream_t s)
+{
+    return kfmi::launch_bin(L.pl, L.hits, L.event_off, (int)L.n_events, ctx->d_layers,
+                            ctx->n_layers, s);
+}
+
+hipError_t phase_order(const kfmi::FindLaunch& L, hipStream_t s)
+{
+    hipError_t e = kfmi::launch_seed_order(L.pl, L.seeds, L.seed_event, L.event_off,
+                                           (int)L.n_events, L.largest_first, s);
+    if (e == hipSuccess) e = kfmi::launch_fill(L.pl.tile_counter, 64, 0, s);
+    return e;
+}
+
+hipError_t phase_find(const kfmi::FindLaunch& L, hipStream_t s)
+{
+    return kfmi::launch_find_kernel(L.a, L.W, L.grid, L.prec, s);
+}
+
+// Event set of the next timed call, or nullptr when timing is off.
+hipEvent_t* timing_set(kf_ctx* ctx)
+{
+    if (ctx->timing_used >= ctx->timing_n) return nullptr;
+    return ctx->ev + kfmi::kPhaseEvents * ctx->timing_used;
+}
+
+void release_graph(kf_ctx* ctx)
+{
+    kfmi::FindGraph& g = ctx->fg;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = kfmi::FindGraph();
+}
+
+// Captures what `f` enqueues on the context's capture stream into a new graph.
+template <typename F>
+hipError_t capture(kf_ctx* ctx, hipGraph_t* out, F f)
+{
+    *out = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = f(ctx->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le != hipSuccess ? le : e;
+    }
+    *out = g;
+    return hipSuccess;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -95,7 +269,7 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
     for (int i = 0; i < n_layers; ++i) {
         const kf_layer& L = layers[i];
         if ((L.kind != 0 && L.kind != 1) || !(L.hi > L.lo) || L.nbin_phi <= 0 || L.nbin_2 <= 0 ||
-            L.nbin_phi > 4096 || L.nbin_2 > 4096 || !(L.x0 >= 0.0) ||
+            L.nbin_phi * L.nbin_2 > kfmi::kMaxLayerBins || !(L.x0 >= 0.0) ||
             (L.kind == 0 && !(L.r_or_z > 0.0)) || !(L.win_su >= 0.0) || !(L.win_sv >= 0.0))
             return fail(nullptr, KF_EINVAL, "kf_create: invalid layer %d", i);
     }
@@ -142,8 +316,12 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
 void kf_destroy(kf_ctx* ctx)
 {
     if (!ctx) return;
-    for (int k = 0; k < 4 * ctx->timing_cap; ++k) (void)hipEventDestroy(ctx->ev[k]);
+    release_graph(ctx);
+    for (int k = 0; k < kfmi::kPhaseEvents * ctx->timing_cap; ++k) (void)hipEventDestroy(ctx->ev[k]);
     delete[] ctx->ev;
+    for (int k = 0; k < kfmi::kPhaseEvents; ++k)
+        if (ctx->idle_ev[k]) (void)hipEventDestroy(ctx->idle_ev[k]);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     ctx->ws.release();
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
     delete ctx;
@@ -205,132 +383,159 @@ int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first)
     return KF_OK;
 }
 
+int kf_get_find_config(kf_ctx* ctx, int32_t* width, int32_t* largest_first)
+{
+    if (!ctx || !width || !largest_first)
+        return fail(ctx, KF_EINVAL, "kf_get_find_config: null argument");
+    *width = ctx->find_width;
+    *largest_first = ctx->find_largest_first;
+    return KF_OK;
+}
+
 int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
             const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
             int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream)
 {
     if (!ctx) return fail(nullptr, KF_EINVAL, "kf_find: null context");
-    int r = check_tracks(ctx, seeds, "kf_find seeds");
+    kfmi::FindLaunch L;
+    int r = prepare_find(ctx, hits, event_off, n_events, seeds, seed_event, seed_hits, out_hits,
+                         out, counters, flags, "kf_find", &L);
     if (r) return r;
-    r = check_tracks(ctx, out, "kf_find out");
-    if (r) return r;
-    r = check_hits(ctx, hits, "kf_find");
-    if (r) return r;
-    const int prec = flags & KF_PREC_MASK;
-    if (prec == KF_PREC_FP64)
-        return fail(ctx, KF_EUNSUPPORTED, "kf_find: float storage only (MIXED or FP32)");
-    if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
-        return fail(ctx, KF_EINVAL, "kf_find: bad precision flag");
-    if (flags & KF_INIT_MLP) return fail(ctx, KF_EUNSUPPORTED, "kf_find: no learned model loaded");
-    if (out->n != seeds->n) return fail(ctx, KF_EINVAL, "kf_find: out->n must equal seeds->n");
-    if (n_events < 1 || !event_off) return fail(ctx, KF_EINVAL, "kf_find: need n_events >= 1 and event_off");
-    if (hits->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "kf_find: at most 2^31-1 hits");
-    if (seeds->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "kf_find: at most 2^31-1 seeds");
-    if (seeds->n > 0 && (!seed_event || !seed_hits || !out_hits))
-        return fail(ctx, KF_EINVAL, "kf_find: null seed_event, seed_hits or out_hits");
     if (seeds->n == 0) return KF_OK;
     hipStream_t s = (hipStream_t)stream;
-    const int W = ctx->find_width;
-    const int MC = ctx->params.max_cands;
-    const int S = W / MC;
-    const int nl = ctx->n_layers;
-    kfmi::FindPlan pl;
-    int64_t per_event = 0;
-    for (int l = 0; l < nl; ++l) {
-        pl.bl.base[l] = (int32_t)per_event;
-        per_event += (int64_t)ctx->layers[l].nbin_phi * ctx->layers[l].nbin_2;
-    }
-    if ((int64_t)n_events * per_event >= 0x7fffffffLL)
-        return fail(ctx, KF_EINVAL, "kf_find: n_events x bins per event exceeds 2^31");
-    pl.bl.per_event = (int32_t)per_event;
-    const size_t lds = kfmi::find_shared_size(W, S, nl, prec);
-    if (ctx->max_lds > 0 && lds > (size_t)ctx->max_lds)
-        return fail(ctx, KF_EUNSUPPORTED, "kf_find: width %d needs %zu bytes of LDS, device allows %d",
-                    W, lds, ctx->max_lds);
-    int lw = 0;
-    while ((1 << lw) < W) ++lw;
-    const int pi = prec == KF_PREC_FP32 ? 1 : 0;
-    int& occ = ctx->occ_cache[pi][lw];
-    if (occ == 0) {
-        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, &occ);
-        if (e != hipSuccess) return hip_fail(ctx, e, "kf_find occupancy");
-        if (occ < 1) occ = 1;
-    }
-    const int64_t n_tiles = (seeds->n + S - 1) / S;
-    int64_t grid = (int64_t)occ * (ctx->n_cu > 0 ? ctx->n_cu : 1);
-    if (grid > n_tiles) grid = n_tiles;
-    const size_t bytes = kfmi::plan_find(&pl, nullptr, hits->n, n_events, seeds->n, nl, (int)grid, S);
-    void* base = ctx->ws.get(bytes);
-    if (!base) return fail(ctx, KF_ENOMEM, "kf_find: workspace of %zu bytes", bytes);
-    kfmi::plan_find(&pl, base, hits->n, n_events, seeds->n, nl, (int)grid, S);
-    const bool tm = ctx->timing_used < ctx->timing_n;
-    hipEvent_t* ev = tm ? ctx->ev + 4 * ctx->timing_used : nullptr;
+    hipEvent_t* ev = timing_set(ctx);
     hipError_t e = hipSuccess;
-    if (tm) e = hipEventRecord(ev[0], s);
-    if (e == hipSuccess) e = kfmi::launch_bin(pl, hits, event_off, n_events, ctx->d_layers, nl, s);
-    if (e == hipSuccess && tm) e = hipEventRecord(ev[1], s);
-    if (e == hipSuccess)
-        e = kfmi::launch_seed_order(pl, seeds, seed_event, event_off, n_events,
-                                    ctx->find_largest_first, s);
-    if (e == hipSuccess) e = kfmi::launch_fill(pl.tile_counter, 64, 0, s);
-    if (e == hipSuccess && tm) e = hipEventRecord(ev[2], s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "kf_find setup");
-    kfmi::FindArgs a;
-    a.bh = (const kfmi::BinnedHit*)pl.binned;
-    a.bin_off = pl.off;
-    a.bl = pl.bl;
-    a.n_hits = hits->n;
-    a.hit_layer = hits->layer;
-    a.n_seeds = seeds->n;
-    a.sld = seeds->ld;
-    a.spar = (const float*)seeds->par;
-    a.scov = seeds->cov;
-    a.schi2 = (const float*)seeds->chi2;
-    a.sndf = seeds->ndf;
-    a.sstatus = seeds->status;
-    a.seed_event = seed_event;
-    a.n_events = n_events;
-    a.seed_hits = seed_hits;
-    a.order = pl.order;
-    a.out_hits = out_hits;
-    a.old = out->ld;
-    a.opar = (float*)out->par;
-    a.ocov = out->cov;
-    a.ochi2 = (float*)out->chi2;
-    a.ondf = out->ndf;
-    a.ostatus = out->status;
-    a.bp = pl.bp;
-    a.tile_counter = pl.tile_counter;
-    a.counters = (unsigned long long*)counters;
-    a.layers = ctx->d_layers;
-    a.n_layers = nl;
-    a.prm = ctx->params;
-    a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
-    a.n_tiles = (int)n_tiles;
-    a.seeds_per_tile = S;
-    e = kfmi::launch_find_kernel(a, W, (int)grid, prec, s);
-    if (e == hipSuccess && tm) {
-        e = hipEventRecord(ev[3], s);
+    // no seeding phase here: its two events coincide
+    if (ev) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = phase_bin(ctx, L, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
+    if (e == hipSuccess) e = phase_order(L, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
+    if (e == hipSuccess) e = phase_find(L, s);
+    if (e == hipSuccess && ev) {
+        e = hipEventRecord(ev[4], s);
         if (e == hipSuccess) ctx->timing_used++;
     }
     return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_find");
+}
+
+int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+                    const int32_t* seed_hits, const int32_t* seed_layers, const int32_t* seed_event,
+                    kf_tracks* seeds, int32_t* out_hits, kf_tracks* out, uint64_t* counters,
+                    int flags, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_find_batched: null context");
+    if (flags & KF_PER_LAYER) return fail(ctx, KF_EINVAL, "kf_find_batched: KF_PER_LAYER is a fit option");
+    kfmi::FindLaunch L;
+    int r = prepare_find(ctx, hits, event_off, n_events, seeds, seed_event, seed_hits, out_hits,
+                         out, counters, flags, "kf_find_batched", &L);
+    if (r) return r;
+    if (seeds->n > 0 && !seed_layers) return fail(ctx, KF_EINVAL, "kf_find_batched: null seed_layers");
+    if (seeds->n == 0) return KF_OK;
+    hipError_t e = hipSuccess;
+    if (!ctx->cap_stream) {
+        e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+        for (int k = 0; k < kfmi::kPhaseEvents && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&ctx->idle_ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(ctx, e, "kf_find_batched setup");
+    }
+    // everything the captured launches depend on: pointers, sizes, options
+    // and the workspace (a grown workspace moves every scratch array)
+    uint64_t key[40];
+    int nk = 0;
+    auto put = [&](uint64_t v) { key[nk++] = v; };
+    put((uint64_t)(uintptr_t)hits->x); put((uint64_t)(uintptr_t)hits->y);
+    put((uint64_t)(uintptr_t)hits->z); put((uint64_t)(uintptr_t)hits->su);
+    put((uint64_t)(uintptr_t)hits->sv); put((uint64_t)(uintptr_t)hits->layer);
+    put((uint64_t)hits->n); put((uint64_t)(uintptr_t)event_off); put((uint64_t)n_events);
+    put((uint64_t)(uintptr_t)seed_hits); put((uint64_t)(uintptr_t)seed_layers);
+    put((uint64_t)(uintptr_t)seed_event);
+    put((uint64_t)seeds->n); put((uint64_t)seeds->ld); put((uint64_t)(uintptr_t)seeds->par);
+    put((uint64_t)(uintptr_t)seeds->cov); put((uint64_t)(uintptr_t)seeds->chi2);
+    put((uint64_t)(uintptr_t)seeds->ndf); put((uint64_t)(uintptr_t)seeds->status);
+    put((uint64_t)out->ld); put((uint64_t)(uintptr_t)out->par); put((uint64_t)(uintptr_t)out->cov);
+    put((uint64_t)(uintptr_t)out->chi2); put((uint64_t)(uintptr_t)out->ndf);
+    put((uint64_t)(uintptr_t)out->status); put((uint64_t)(uintptr_t)out_hits);
+    put((uint64_t)(uintptr_t)counters); put((uint64_t)flags); put((uint64_t)L.W);
+    put((uint64_t)L.largest_first); put((uint64_t)L.grid);
+    put((uint64_t)(uintptr_t)ctx->ws.ptr); put((uint64_t)ctx->ws.bytes);
+    kfmi::FindGraph& g = ctx->fg;
+    const bool same = g.exec && g.nkey == nk && memcmp(g.key, key, sizeof(uint64_t) * nk) == 0;
+    if (!same) {
+        release_graph(ctx);
+        hipGraph_t sub[4] = {nullptr, nullptr, nullptr, nullptr};
+        kf_tracks* st = seeds;
+        const int fit_flags = flags & (KF_PREC_MASK | KF_NO_MATERIAL);
+        e = capture(ctx, &sub[0], [&](hipStream_t cs) {
+            hipError_t x = kfmi::launch_seed(ctx, hits, seed_hits, st, fit_flags, cs);
+            if (x == hipSuccess) x = kfmi::launch_fit(ctx, st, hits, seed_layers, seed_hits, 3, fit_flags, cs);
+            return x;
+        });
+        if (e == hipSuccess) e = capture(ctx, &sub[1], [&](hipStream_t cs) { return phase_bin(ctx, L, cs); });
+        if (e == hipSuccess) e = capture(ctx, &sub[2], [&](hipStream_t cs) { return phase_order(L, cs); });
+        if (e == hipSuccess) e = capture(ctx, &sub[3], [&](hipStream_t cs) { return phase_find(L, cs); });
+        if (e == hipSuccess) e = hipGraphCreate(&g.graph, 0);
+        // event 0 -> seed+fit -> event 1 -> binning -> event 2 -> order -> event 3 -> find -> event 4
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < kfmi::kPhaseEvents && e == hipSuccess; ++k) {
+            e = hipGraphAddEventRecordNode(&g.ev_node[k], g.graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                           ctx->idle_ev[k]);
+            prev = g.ev_node[k];
+            if (e == hipSuccess && k < 4) {
+                hipGraphNode_t child;
+                e = hipGraphAddChildGraphNode(&child, g.graph, &prev, 1, sub[k]);
+                prev = child;
+            }
+        }
+        for (int k = 0; k < 4; ++k)
+            if (sub[k]) (void)hipGraphDestroy(sub[k]);   // the child nodes hold copies
+        if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            release_graph(ctx);
+            return hip_fail(ctx, e, "kf_find_batched capture");
+        }
+        memcpy(g.key, key, sizeof(uint64_t) * nk);
+        g.nkey = nk;
+        g.timed = false;
+    }
+    hipEvent_t* ev = timing_set(ctx);
+    if (ev || g.timed) {
+        for (int k = 0; k < kfmi::kPhaseEvents && e == hipSuccess; ++k)
+            e = hipGraphExecEventRecordNodeSetEvent(g.exec, g.ev_node[k], ev ? ev[k] : ctx->idle_ev[k]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "kf_find_batched timing");
+        g.timed = ev != nullptr;
+    }
+    e = hipGraphLaunch(g.exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_find_batched launch");
+    if (ev) ctx->timing_used++;
+    return KF_OK;
 }
 
 int kf_set_timing(kf_ctx* ctx, int32_t n)
 {
     if (!ctx) return fail(nullptr, KF_EINVAL, "kf_set_timing: null context");
     if (n < 0 || n > 256) return fail(ctx, KF_EINVAL, "kf_set_timing: n must be in 0..256");
+    constexpr int E = kfmi::kPhaseEvents;
     if (n > ctx->timing_cap) {
-        hipEvent_t* ev = new hipEvent_t[4 * n];
+        hipEvent_t* ev = new hipEvent_t[E * n];
         int k = 0;
-        for (; k < 4 * ctx->timing_cap; ++k) ev[k] = ctx->ev[k];
-        for (; k < 4 * n; ++k) {
+        for (; k < E * ctx->timing_cap; ++k) ev[k] = ctx->ev[k];
+        for (; k < E * n; ++k) {
             hipError_t r = hipEventCreate(&ev[k]);
             if (r != hipSuccess) {
-                for (int j = 4 * ctx->timing_cap; j < k; ++j) (void)hipEventDestroy(ev[j]);
+                for (int j = E * ctx->timing_cap; j < k; ++j) (void)hipEventDestroy(ev[j]);
                 delete[] ev;
                 return hip_fail(ctx, r, "kf_set_timing");
             }
+        }
+        // a captured pass may still point at the old sets: point it back at
+        // the idle events before they go
+        if (ctx->fg.exec && ctx->fg.timed) {
+            for (int j = 0; j < E; ++j)
+                (void)hipGraphExecEventRecordNodeSetEvent(ctx->fg.exec, ctx->fg.ev_node[j],
+                                                          ctx->idle_ev[j]);
+            ctx->fg.timed = false;
         }
         delete[] ctx->ev;
         ctx->ev = ev;
@@ -342,22 +547,98 @@ int kf_set_timing(kf_ctx* ctx, int32_t n)
     return KF_OK;
 }
 
-int kf_timings(kf_ctx* ctx, float ms[4])
+int kf_timings(kf_ctx* ctx, float ms[5])
 {
     if (!ctx || !ms) return fail(ctx, KF_EINVAL, "kf_timings: null argument");
-    const int first = 0, last = ctx->timing_used;
-    if (ctx->timing_n == 0 || last <= first) return fail(ctx, KF_EINVAL, "kf_timings: nothing recorded");
-    hipError_t e = hipEventSynchronize(ctx->ev[4 * (last - 1) + 3]);
-    double acc[3] = {0, 0, 0};
-    for (int c = first; c < last && e == hipSuccess; ++c)
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    constexpr int E = kfmi::kPhaseEvents;
+    const int last = ctx->timing_used;
+    if (ctx->timing_n == 0 || last <= 0) return fail(ctx, KF_EINVAL, "kf_timings: nothing recorded");
+    hipError_t e = hipEventSynchronize(ctx->ev[E * (last - 1) + E - 1]);
+    double acc[E - 1] = {};
+    for (int c = 0; c < last && e == hipSuccess; ++c)
+        for (int k = 0; k < E - 1 && e == hipSuccess; ++k) {
             float t = 0.0f;
-            e = hipEventElapsedTime(&t, ctx->ev[4 * c + k], ctx->ev[4 * c + k + 1]);
+            e = hipEventElapsedTime(&t, ctx->ev[E * c + k], ctx->ev[E * c + k + 1]);
             acc[k] += t;
         }
     if (e != hipSuccess) return hip_fail(ctx, e, "kf_timings");
-    for (int k = 0; k < 3; ++k) ms[k] = float(acc[k] / (last - first));
-    ms[3] = float(last - first);
+    for (int k = 0; k < E - 1; ++k) ms[k] = float(acc[k] / last);
+    ms[E - 1] = float(last);
+    return KF_OK;
+}
+
+int kf_autotune(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+                const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
+                int32_t* out_hits, kf_tracks* out, int flags, int32_t reps, float* table,
+                void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_autotune: null context");
+    if (reps < 1 || reps > 100) return fail(ctx, KF_EINVAL, "kf_autotune: reps must be in 1..100");
+    hipStream_t s = (hipStream_t)stream;
+    constexpr int NW = 4, NC = 2 * NW;
+    static const int widths[NW] = {32, 64, 128, 256};
+    const int w0 = ctx->find_width, lf0 = ctx->find_largest_first;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return hip_fail(ctx, e, "kf_autotune");
+    }
+    const int saved_n = ctx->timing_n, saved_used = ctx->timing_used;
+    ctx->timing_n = ctx->timing_used = 0;       // tuning calls are not recorded
+    float best_ms[NC];
+    bool fits[NC];
+    for (int c = 0; c < NC; ++c) {
+        best_ms[c] = -1.0f;
+        const int w = widths[c / 2];
+        fits[c] = w / ctx->params.max_cands >= 1 &&
+                  kfmi::find_shared_size(w, w / ctx->params.max_cands, ctx->n_layers,
+                                         flags & KF_PREC_MASK) <= (size_t)ctx->max_lds;
+    }
+    // configurations are visited round-robin, reps rounds, each call timed
+    // on its own after one untimed call per configuration, and the fastest
+    // call counts: clock ramps and other drifts hit every configuration
+    int r = KF_OK;
+    for (int round = -1; round < reps && r == KF_OK; ++round)
+        for (int c = 0; c < NC && r == KF_OK; ++c) {
+            if (!fits[c]) continue;
+            ctx->find_width = widths[c / 2];
+            ctx->find_largest_first = c & 1;
+            if (round >= 0 && (e = hipEventRecord(ev[0], s)) != hipSuccess) r = hip_fail(ctx, e, "kf_autotune");
+            if (r == KF_OK)
+                r = kf_find(ctx, hits, event_off, n_events, seeds, seed_event, seed_hits, out_hits,
+                            out, nullptr, flags, stream);
+            if (r != KF_OK || round < 0) continue;
+            float ms = 0.0f;
+            if ((e = hipEventRecord(ev[1], s)) != hipSuccess || (e = hipEventSynchronize(ev[1])) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) {
+                r = hip_fail(ctx, e, "kf_autotune");
+                continue;
+            }
+            if (best_ms[c] < 0.0f || ms < best_ms[c]) best_ms[c] = ms;
+        }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    ctx->timing_n = saved_n;
+    ctx->timing_used = saved_used;
+    if (r != KF_OK) {
+        ctx->find_width = w0;
+        ctx->find_largest_first = lf0;
+        return r;
+    }
+    int best = -1;
+    for (int c = 0; c < NC; ++c) {
+        if (table) table[c] = best_ms[c];
+        if (best_ms[c] >= 0.0f && (best < 0 || best_ms[c] < best_ms[best])) best = c;
+    }
+    if (best < 0) {
+        ctx->find_width = w0;
+        ctx->find_largest_first = lf0;
+        return fail(ctx, KF_EUNSUPPORTED, "kf_autotune: no configuration fits the device");
+    }
+    ctx->find_width = widths[best / 2];
+    ctx->find_largest_first = best & 1;
     return KF_OK;
 }
 

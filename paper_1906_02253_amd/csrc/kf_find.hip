@@ -3,9 +3,10 @@
 //   a1  bin hits per (event, layer, phi bin, z|r bin): count, scan, scatter
 //       into 32-byte records (paper Sec. 3.2: hits handed in by the caller;
 //       binning makes the per-layer hit search a contiguous range scan);
-//   a2  order seeds by (event size, eta bin, phi bin) so that a workgroup's
-//       seeds share hit bins (paper Sec. 3.2: seeds grouped close in eta and
-//       phi for cache reuse of hit data);
+//   a2  order seeds by (event, eta bin, phi bin), events optionally largest
+//       first, with a counting sort, so that a workgroup's seeds share hit
+//       bins (paper Sec. 3.2: seeds grouped close in eta and phi for cache
+//       reuse of hit data);
 //   a3-a7 one persistent kernel walks tiles of seeds through the detector
 //       layer by layer (paper Sec. 2: KF-based finding; Sec. 3.1: layer-to-
 //       layer propagation; Sec. 4: hit-search windows, candidate scoring):
@@ -16,8 +17,6 @@
 //       per-parent sorted lists) and the lanes materialise the survivors with
 //       the Kalman update.  Hit lists are recovered from per-step
 //       back-pointers at the end.
-#include <hipcub/hipcub.hpp>
-
 #include "kf_find.hpp"
 #include "kf_math.hpp"
 
@@ -58,84 +57,327 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v)
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void bin_count_kernel(int64_t n_hits, const float* __restrict__ x,
-                                                        const float* __restrict__ y,
-                                                        const float* __restrict__ z,
-                                                        const int32_t* __restrict__ layer,
-                                                        const int32_t* __restrict__ event_off,
-                                                        int n_events, const kf_layer* __restrict__ layers,
-                                                        int n_layers, BinLayout bl,
-                                                        int32_t* __restrict__ cnt,
-                                                        int32_t* __restrict__ hit_key)
+// exclusive scan over the workgroup of one value per lane; lds holds one int
+// per wave
+__device__ inline int block_scan_excl(int v, int* total, int* lds)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_hits) return;
-    const int l = layer[i];
-    if (l < 0 || l >= n_layers || i < event_off[0] || i >= event_off[n_events]) {
-        hit_key[i] = -1;
-        return;
+    const int ln = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o);
+        if (ln >= o) incl += u;
     }
-    const int e = event_of(event_off, n_events, i);
-    const kf_layer L = layers[l];
-    const float hx = x[i], hy = y[i];
-    const int bp = phi_bin_of(atan2f(hy, hx), L.nbin_phi);
-    const float v = L.kind == 0 ? z[i] : sqrtf(hx * hx + hy * hy);
-    const int bv = coord_bin_of(v, float(L.lo), float(L.hi), L.nbin_2);
-    const int key = e * bl.per_event + bl.base[l] + bp * L.nbin_2 + bv;
-    atomicAdd(&cnt[key], 1);
-    hit_key[i] = key;
+    if (ln == 63) lds[w] = incl;
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int q = 0; q < nw; ++q) {
+        const int s = lds[q];
+        woff += q < w ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return woff + incl - v;
 }
 
-__global__ __launch_bounds__(256) void bin_scatter_kernel(int64_t n_hits, const float* __restrict__ x,
-                                                          const float* __restrict__ y,
-                                                          const float* __restrict__ z,
-                                                          const float* __restrict__ su,
-                                                          const float* __restrict__ sv,
-                                                          const int32_t* __restrict__ hit_key,
-                                                          const int32_t* __restrict__ off,
-                                                          int32_t* __restrict__ cnt,
-                                                          BinnedHit* __restrict__ out)
+// Hits are binned in two levels of counting sort, all hot counters in LDS:
+// (1) group hits by segment = (event, layer): a workgroup histograms a chunk
+//     of hits in LDS and reserves each segment's share with one global
+//     atomic, then scatters the hit indices;
+// (2) one workgroup per segment counts its hits per (phi, z|r) bin in LDS,
+//     scans the counts into the segment's bin offsets and writes the 32-byte
+//     records contiguously.
+constexpr int kSegChunk = 4096;      // hits per workgroup in level 1
+constexpr int kSegLocal = 2048;      // segments a level-1 workgroup counts in LDS
+
+__device__ inline int event_clamped(const int32_t* off, int n_events, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_hits) return;
-    const int key = hit_key[i];
-    if (key < 0) return;
-    const int pos = off[key] + atomicSub(&cnt[key], 1) - 1;
-    BinnedHit h;
-    h.x = x[i];
-    h.y = y[i];
-    h.z = z[i];
-    h.su = su[i];
-    h.sv = sv[i];
-    const float rho = sqrtf(h.x * h.x + h.y * h.y);
-    h.cphi = h.x / rho;
-    h.sphi = h.y / rho;
-    h.idx = (int32_t)i;
-    out[pos] = h;
+    if (i < off[0]) return 0;
+    if (i >= off[n_events]) return n_events - 1;
+    return event_of(off, n_events, i);
+}
+
+// segment of hit i, or -1 (layer out of range, hit outside every event)
+__device__ inline int segment_of(int64_t i, const int32_t* __restrict__ layer,
+                                 const int32_t* __restrict__ event_off, int n_events, int n_layers)
+{
+    const int l = layer[i];
+    if (l < 0 || l >= n_layers || i < event_off[0] || i >= event_off[n_events]) return -1;
+    return event_of(event_off, n_events, i) * n_layers + l;
+}
+
+__global__ __launch_bounds__(256) void seg_count_kernel(int64_t n_hits, const int32_t* __restrict__ layer,
+                                                        const int32_t* __restrict__ event_off,
+                                                        int n_events, int n_layers,
+                                                        int32_t* __restrict__ seg_key,
+                                                        int32_t* __restrict__ seg_cnt)
+{
+    __shared__ int h[kSegLocal];
+    const int64_t c0 = (int64_t)blockIdx.x * kSegChunk;
+    const int64_t c1 = c0 + kSegChunk < n_hits ? c0 + kSegChunk : n_hits;
+    const int s0 = event_clamped(event_off, n_events, c0) * n_layers;
+    const int ns = (event_clamped(event_off, n_events, c1 - 1) + 1) * n_layers - s0;
+    const bool local = ns <= kSegLocal;
+    if (local)
+        for (int b = threadIdx.x; b < ns; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+        const int key = segment_of(i, layer, event_off, n_events, n_layers);
+        seg_key[i] = key;
+        if (key >= 0) {
+            // (a decreasing event_off could put a hit outside the chunk's
+            // event range: such a hit takes the global counter)
+            if (local && (unsigned)(key - s0) < (unsigned)ns) atomicAdd(&h[key - s0], 1);
+            else atomicAdd(&seg_cnt[key], 1);
+        }
+    }
+    __syncthreads();
+    if (local)
+        for (int b = threadIdx.x; b < ns; b += blockDim.x)
+            if (h[b]) atomicAdd(&seg_cnt[s0 + b], h[b]);
+}
+
+__global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t n_hits, const int32_t* __restrict__ event_off,
+                                                          int n_events, int n_layers,
+                                                          const int32_t* __restrict__ seg_key,
+                                                          const int32_t* __restrict__ seg_off,
+                                                          int32_t* __restrict__ seg_fill,
+                                                          int32_t* __restrict__ seg_hits)
+{
+    __shared__ int h[kSegLocal];
+    __shared__ int base[kSegLocal];
+    const int64_t c0 = (int64_t)blockIdx.x * kSegChunk;
+    const int64_t c1 = c0 + kSegChunk < n_hits ? c0 + kSegChunk : n_hits;
+    const int s0 = event_clamped(event_off, n_events, c0) * n_layers;
+    const int ns = (event_clamped(event_off, n_events, c1 - 1) + 1) * n_layers - s0;
+    const bool local = ns <= kSegLocal;
+    if (local) {
+        for (int b = threadIdx.x; b < ns; b += blockDim.x) h[b] = 0;
+        __syncthreads();
+        for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+            const int key = seg_key[i];
+            if (key >= 0 && (unsigned)(key - s0) < (unsigned)ns) atomicAdd(&h[key - s0], 1);
+        }
+        __syncthreads();
+        // reserve this chunk's share of every segment it touches
+        for (int b = threadIdx.x; b < ns; b += blockDim.x) {
+            base[b] = h[b] ? seg_off[s0 + b] + atomicAdd(&seg_fill[s0 + b], h[b]) : 0;
+            h[b] = 0;
+        }
+        __syncthreads();
+    }
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+        const int key = seg_key[i];
+        if (key < 0) continue;
+        const int pos = local && (unsigned)(key - s0) < (unsigned)ns
+                            ? base[key - s0] + atomicAdd(&h[key - s0], 1)
+                            : seg_off[key] + atomicAdd(&seg_fill[key], 1);
+        seg_hits[pos] = (int32_t)i;
+    }
+}
+
+__device__ inline int hit_bin(const kf_layer& L, float hx, float hy, float hz)
+{
+    const int bp = phi_bin_of(atan2f(hy, hx), L.nbin_phi);
+    const float v = L.kind == 0 ? hz : sqrtf(hx * hx + hy * hy);
+    return bp * L.nbin_2 + coord_bin_of(v, float(L.lo), float(L.hi), L.nbin_2);
+}
+
+constexpr int kBinThreads = 1024;
+__global__ __launch_bounds__(kBinThreads) void bin_segment_kernel(
+    const int32_t* __restrict__ seg_off, const int32_t* __restrict__ seg_hits,
+    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const float* __restrict__ su, const float* __restrict__ sv, const kf_layer* __restrict__ layers,
+    int n_layers, int n_seg, BinLayout bl, int32_t* __restrict__ bin_off, BinnedHit* __restrict__ out)
+{
+    __shared__ int hist[kMaxLayerBins];
+    __shared__ int lds[kBinThreads / 64];
+    const int seg = blockIdx.x;
+    const int e = seg / n_layers, l = seg - e * n_layers;
+    const kf_layer L = layers[l];
+    const int nb = L.nbin_phi * L.nbin_2;
+    const int lo = seg_off[seg], hi = seg_off[seg + 1];
+    const int t = threadIdx.x;
+    for (int b = t; b < nb; b += kBinThreads) hist[b] = 0;
+    __syncthreads();
+    for (int i = lo + t; i < hi; i += kBinThreads) {
+        const int h = seg_hits[i];
+        atomicAdd(&hist[hit_bin(L, x[h], y[h], z[h])], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the bin counts: lane t takes bins [t*per, (t+1)*per)
+    const int per = (nb + kBinThreads - 1) / kBinThreads;
+    const int b0 = t * per;
+    int s = 0;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < nb) s += hist[b0 + q];
+    int tot;
+    int run = lo + block_scan_excl(s, &tot, lds);
+    int32_t* bo = bin_off + (int64_t)e * bl.per_event + bl.base[l];
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < nb) {
+            const int c = hist[b0 + q];
+            hist[b0 + q] = run;
+            bo[b0 + q] = run;
+            run += c;
+        }
+    if (seg == n_seg - 1 && t == 0) bin_off[(int64_t)(e + 1) * bl.per_event] = hi;
+    __syncthreads();
+    for (int i = lo + t; i < hi; i += kBinThreads) {
+        const int h = seg_hits[i];
+        BinnedHit r;
+        r.x = x[h];
+        r.y = y[h];
+        r.z = z[h];
+        r.su = su[h];
+        r.sv = sv[h];
+        const float rho = sqrtf(r.x * r.x + r.y * r.y);
+        r.cphi = r.x / rho;
+        r.sphi = r.y / rho;
+        r.idx = h;
+        out[atomicAdd(&hist[hit_bin(L, r.x, r.y, r.z)], 1)] = r;
+    }
+}
+
+// ------------------------------------------------------------------ prefix sums
+// Exclusive prefix sum of n int32 in three launches (no library scan, so that
+// the pass contains kernels only and can be captured into a graph): per-chunk
+// totals, an in-place scan of the totals by one workgroup, and a rescan of
+// each chunk from its offset.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const int32_t* __restrict__ in,
+                                                                   int64_t n,
+                                                                   int32_t* __restrict__ bsum)
+{
+    __shared__ int lds[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = base + (int64_t)q * kScanThreads;
+        s += i < n ? in[i] : 0;
+    }
+    int tot;
+    (void)block_scan_excl(s, &tot, lds);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void scan_top_kernel(int32_t* __restrict__ bsum, int nb)
+{
+    __shared__ int lds[1024 / 64];
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int i = b0 + (int)threadIdx.x;
+        const int v = i < nb ? bsum[i] : 0;
+        int tot;
+        const int ex = block_scan_excl(v, &tot, lds);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const int32_t* __restrict__ in,
+                                                                  int64_t n,
+                                                                  const int32_t* __restrict__ bsum,
+                                                                  int32_t* __restrict__ out)
+{
+    __shared__ int lds[kScanThreads / 64];
+    // lane t takes kScanItems consecutive values of the chunk
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = base + q < n ? in[base + q] : 0;
+        s += v[q];
+    }
+    int tot;
+    int run = bsum[blockIdx.x] + block_scan_excl(s, &tot, lds);
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
 }
 
 // ------------------------------------------------------------------ seed order
-__global__ __launch_bounds__(256) void seed_key_kernel(int64_t n, int64_t ld, const float* __restrict__ par,
-                                                       const int32_t* __restrict__ seed_event,
-                                                       const int32_t* __restrict__ event_off,
-                                                       int n_events, int largest_first,
-                                                       uint64_t* __restrict__ keys,
-                                                       int32_t* __restrict__ vals)
+constexpr int kSeedCells = 64 * 64;   // eta x phi cells per event
+
+// Position of each event in the processing order: by hit count, largest
+// first, ties by event index (a permutation of 0..n_events-1).
+__global__ __launch_bounds__(256) void event_rank_kernel(const int32_t* __restrict__ event_off,
+                                                         int n_events, int32_t* __restrict__ erank)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_events) return;
+    const int ne = event_off[e + 1] - event_off[e];
+    int r = 0;
+    for (int q = 0; q < n_events; ++q) {
+        const int nq = event_off[q + 1] - event_off[q];
+        r += (nq > ne || (nq == ne && q < e)) ? 1 : 0;
+    }
+    erank[e] = r;
+}
+
+__global__ __launch_bounds__(256) void seed_cell_kernel(int64_t n, int64_t ld, const float* __restrict__ par,
+                                                        const int32_t* __restrict__ seed_event,
+                                                        int n_events,
+                                                        const int32_t* __restrict__ erank,
+                                                        int32_t* __restrict__ cnt,
+                                                        int32_t* __restrict__ cell)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float th = par[5 * ld + i], ph = par[4 * ld + i];
     int e = seed_event[i];
     e = e < 0 ? 0 : (e >= n_events ? n_events - 1 : e);
+    if (erank) e = erank[e];
+    // eta over [-3, 3) and phi over [-pi, pi) in 64 bins each; a non-finite
+    // angle falls into bin 0
     const float eta = -logf(tanf(0.5f * th));
-    int eb = (int)floorf((eta + 3.0f) * (64.0f / 6.0f));
-    eb = eb < 0 ? 0 : (eb > 63 ? 63 : eb);
-    int pb = (int)floorf((ph + float(kPi)) * (64.0f / float(2.0 * kPi)));
-    pb = pb < 0 ? 0 : (pb > 63 ? 63 : pb);
-    const uint32_t nh = (uint32_t)(event_off[e + 1] - event_off[e]);
-    const uint64_t hi = largest_first ? (uint64_t)(0x7fffffffu - (nh & 0x7fffffffu)) : 0ull;
-    keys[i] = (hi << 32) | ((uint64_t)e << 12) | ((uint64_t)eb << 6) | (uint64_t)pb;
-    vals[i] = (int32_t)i;
+    float fe = floorf((eta + 3.0f) * (64.0f / 6.0f));
+    fe = fe >= 0.0f ? (fe < 63.0f ? fe : 63.0f) : 0.0f;
+    float fp = floorf((ph + float(kPi)) * (64.0f / float(2.0 * kPi)));
+    fp = fp >= 0.0f ? (fp < 63.0f ? fp : 63.0f) : 0.0f;
+    const int c = e * kSeedCells + (int)fe * 64 + (int)fp;
+    atomicAdd(&cnt[c], 1);
+    cell[i] = c;
+}
+
+__global__ __launch_bounds__(256) void seed_scatter_kernel(int64_t n, const int32_t* __restrict__ cell,
+                                                           const int32_t* __restrict__ off,
+                                                           int32_t* __restrict__ cnt,
+                                                           int32_t* __restrict__ order)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell[i];
+    order[off[c] + atomicSub(&cnt[c], 1) - 1] = (int32_t)i;
+}
+
+// The scatter leaves a cell's seeds in arbitrary order; sort each cell by
+// seed index so that tiles are the same from run to run.  Cells above
+// kCellSortMax seeds (only degenerate inputs pile up so) keep the scatter order.
+constexpr int kCellSortMax = 256;
+__global__ __launch_bounds__(256) void cell_sort_kernel(int64_t n_cells, const int32_t* __restrict__ off,
+                                                        int32_t* __restrict__ order)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int lo = off[c], hi = off[c + 1];
+    if (hi - lo < 2 || hi - lo > kCellSortMax) return;
+    for (int i = lo + 1; i < hi; ++i) {
+        const int32_t v = order[i];
+        int j = i - 1;
+        while (j >= lo && order[j] > v) {
+            order[j + 1] = order[j];
+            --j;
+        }
+        order[j + 1] = v;
+    }
 }
 
 // ------------------------------------------------------------------ find
@@ -772,28 +1014,38 @@ hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = blocks_for(n, kScanChunk);
+    scan_reduce_kernel<<<nb, kScanThreads, 0, s>>>(in, n, bsum);
+    scan_top_kernel<<<1, 1024, 0, s>>>(bsum, (int)nb);
+    scan_apply_kernel<<<nb, kScanThreads, 0, s>>>(in, n, bsum, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event_off, int n_events,
                       const kf_layer* d_layers, int n_layers, hipStream_t s)
 {
     hipError_t e;
-    const int64_t total = (int64_t)n_events * pl.bl.per_event;
-    if ((e = launch_fill(pl.cnt, total + 1, 0, s)) != hipSuccess) return e;
+    const int64_t n_seg = (int64_t)n_events * n_layers;
+    if ((e = launch_fill(pl.seg_cnt, 2 * (n_seg + 1), 0, s)) != hipSuccess) return e;   // cnt and fill
+    const unsigned nchunk = blocks_for(h->n, kSegChunk);
     if (h->n > 0) {
-        bin_count_kernel<<<blocks_for(h->n, 256), 256, 0, s>>>(h->n, h->x, h->y, h->z, h->layer,
-                                                               event_off, n_events, d_layers,
-                                                               n_layers, pl.bl, pl.cnt, pl.hit_key);
+        seg_count_kernel<<<nchunk, 256, 0, s>>>(h->n, h->layer, event_off, n_events, n_layers,
+                                                pl.hit_key, pl.seg_cnt);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    size_t tb = pl.cub_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(pl.cub_tmp, tb, pl.cnt, pl.off, (int)(total + 1), s);
-    if (e != hipSuccess) return e;
+    if ((e = launch_scan(pl.seg_cnt, pl.seg_off, n_seg + 1, pl.bsum, s)) != hipSuccess) return e;
     if (h->n > 0) {
-        bin_scatter_kernel<<<blocks_for(h->n, 256), 256, 0, s>>>(h->n, h->x, h->y, h->z, h->su,
-                                                                 h->sv, pl.hit_key, pl.off, pl.cnt,
-                                                                 (BinnedHit*)pl.binned);
+        seg_scatter_kernel<<<nchunk, 256, 0, s>>>(h->n, event_off, n_events, n_layers, pl.hit_key,
+                                                  pl.seg_off, pl.seg_fill, pl.seg_hits);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    return hipSuccess;
+    bin_segment_kernel<<<(unsigned)n_seg, kBinThreads, 0, s>>>(
+        pl.seg_off, pl.seg_hits, h->x, h->y, h->z, h->su, h->sv, d_layers, n_layers, (int)n_seg,
+        pl.bl, pl.off, (BinnedHit*)pl.binned);
+    return hipGetLastError();
 }
 
 hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
@@ -801,14 +1053,22 @@ hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const i
                              hipStream_t s)
 {
     if (seeds->n == 0) return hipSuccess;
-    seed_key_kernel<<<blocks_for(seeds->n, 256), 256, 0, s>>>(
-        seeds->n, seeds->ld, (const float*)seeds->par, seed_event, event_off, n_events,
-        largest_first, pl.keys_in, pl.vals_in);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    size_t tb = pl.cub_bytes;
-    return hipcub::DeviceRadixSort::SortPairs(pl.cub_tmp, tb, pl.keys_in, pl.keys_out, pl.vals_in,
-                                              pl.order, (int)seeds->n, 0, 64, s);
+    hipError_t e;
+    const int64_t total = (int64_t)n_events * kSeedCells;
+    if ((e = launch_fill(pl.scnt, total + 1, 0, s)) != hipSuccess) return e;
+    if (largest_first) {
+        event_rank_kernel<<<blocks_for(n_events, 256), 256, 0, s>>>(event_off, n_events, pl.erank);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    seed_cell_kernel<<<blocks_for(seeds->n, 256), 256, 0, s>>>(
+        seeds->n, seeds->ld, (const float*)seeds->par, seed_event, n_events,
+        largest_first ? pl.erank : nullptr, pl.scnt, pl.cell);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan(pl.scnt, pl.soff, total + 1, pl.bsum, s)) != hipSuccess) return e;
+    seed_scatter_kernel<<<blocks_for(seeds->n, 256), 256, 0, s>>>(seeds->n, pl.cell, pl.soff,
+                                                                  pl.scnt, pl.order);
+    cell_sort_kernel<<<blocks_for(total, 256), 256, 0, s>>>(total, pl.soff, pl.order);
+    return hipGetLastError();
 }
 
 size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t n_seeds,
@@ -821,33 +1081,27 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
         return p;
     };
     const int64_t nb = (int64_t)n_events * pl->bl.per_event + 1;
+    const int64_t nc = (int64_t)n_events * kSeedCells + 1;
     const int64_t ns = n_seeds > 0 ? n_seeds : 1;
     const int64_t nh = n_hits > 0 ? n_hits : 1;
-    pl->cnt = (int32_t*)take(sizeof(int32_t) * nb);
+    const int64_t nseg = (int64_t)n_events * n_layers + 1;
+    const int64_t nsum = ((nseg > nc ? nseg : nc) + kScanChunk - 1) / kScanChunk;
+    pl->seg_cnt = (int32_t*)take(sizeof(int32_t) * 2 * nseg);
+    pl->seg_fill = pl->seg_cnt + nseg;
+    pl->seg_off = (int32_t*)take(sizeof(int32_t) * nseg);
     pl->off = (int32_t*)take(sizeof(int32_t) * nb);
     pl->hit_key = (int32_t*)take(sizeof(int32_t) * nh);
+    pl->seg_hits = (int32_t*)take(sizeof(int32_t) * nh);
     pl->binned = take(sizeof(BinnedHit) * nh);
-    pl->keys_in = (uint64_t*)take(sizeof(uint64_t) * ns);
-    pl->keys_out = (uint64_t*)take(sizeof(uint64_t) * ns);
-    pl->vals_in = (int32_t*)take(sizeof(int32_t) * ns);
+    pl->scnt = (int32_t*)take(sizeof(int32_t) * nc);
+    pl->soff = (int32_t*)take(sizeof(int32_t) * nc);
+    pl->erank = (int32_t*)take(sizeof(int32_t) * n_events);
+    pl->cell = (int32_t*)take(sizeof(int32_t) * ns);
     pl->order = (int32_t*)take(sizeof(int32_t) * ns);
-    pl->cub_bytes = cub_bytes_needed(nb, n_seeds);
-    pl->cub_tmp = take(pl->cub_bytes);
+    pl->bsum = (int32_t*)take(sizeof(int32_t) * nsum);
     pl->bp = (int2*)take(sizeof(int2) * (size_t)grid * n_layers * seeds_per_tile * kMaxCands);
     pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);
     return off;
-}
-
-size_t cub_bytes_needed(int64_t n_bins_plus1, int64_t n_seeds)
-{
-    size_t a = 0, b = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, a, (int32_t*)nullptr, (int32_t*)nullptr,
-                                           (int)n_bins_plus1);
-    if (n_seeds > 0)
-        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                                 (int32_t*)nullptr, (int32_t*)nullptr, (int)n_seeds, 0,
-                                                 64);
-    return a > b ? a : b;
 }
 
 hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, hipStream_t s)

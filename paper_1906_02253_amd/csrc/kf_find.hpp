@@ -6,6 +6,7 @@
 namespace kfmi {
 
 constexpr int kMaxCands = 8;    // candidate slots per seed the kernel is built for
+constexpr int kMaxLayerBins = 16384;   // nbin_phi * nbin_2 of one layer (LDS histogram)
 
 // One binned hit: position, sigmas, azimuth cos/sin and the caller's hit index.
 struct alignas(16) BinnedHit {
@@ -63,16 +64,19 @@ struct FindArgs {
 // Device scratch of one kf_find call, carved from the context workspace.
 struct FindPlan {
     BinLayout bl;
-    int32_t* cnt;       // [n_events * per_event + 1]
-    int32_t* off;       // [n_events * per_event + 1]
-    int32_t* hit_key;   // [n_hits]
+    int32_t* seg_cnt;   // [n_events * n_layers + 1] hits per (event, layer) segment
+    int32_t* seg_fill;  // [n_events * n_layers + 1] hits placed per segment so far
+    int32_t* seg_off;   // [n_events * n_layers + 1] exclusive prefix sum of seg_cnt
+    int32_t* off;       // [n_events * per_event + 1] first binned hit of every bin
+    int32_t* hit_key;   // [n_hits] segment of each hit (-1: not binned)
+    int32_t* seg_hits;  // [n_hits] hit indices grouped by segment
     void* binned;       // [n_hits] records of 32 bytes
-    uint64_t* keys_in;  // [n_seeds]
-    uint64_t* keys_out;
-    int32_t* vals_in;
-    int32_t* order;
-    void* cub_tmp;
-    size_t cub_bytes;
+    int32_t* scnt;      // [n_events * cells + 1] seeds per (event, eta, phi) cell
+    int32_t* soff;      // [n_events * cells + 1] its exclusive prefix sum
+    int32_t* erank;     // [n_events] processing position of each event
+    int32_t* cell;      // [n_seeds] cell of each seed
+    int32_t* order;     // [n_seeds] seeds in processing order
+    int32_t* bsum;      // chunk totals of the prefix sums
     int2* bp;
     int32_t* tile_counter;
 };
@@ -82,7 +86,7 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
                  int n_layers, int grid, int seeds_per_tile);
 size_t find_shared_size(int W, int S, int nl, int prec);
 hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, int* out);
-size_t cub_bytes_needed(int64_t n_bins_plus1, int64_t n_seeds);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event_off, int n_events,
                       const kf_layer* d_layers, int n_layers, hipStream_t s);

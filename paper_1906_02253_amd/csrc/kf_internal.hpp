@@ -21,6 +21,19 @@ struct Workspace {
     void release();
 };
 
+// The captured finding pass of kf_find_batched: seeding, seed fit, binning,
+// seed order and the finding kernel as child graphs, separated by event-record
+// nodes whose events are swapped per launch (timing or not).
+constexpr int kPhaseEvents = 5;
+struct FindGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t ev_node[kPhaseEvents] = {};
+    uint64_t key[40] = {};          // everything the captured launches depend on
+    int nkey = 0;
+    bool timed = false;             // ev_node currently point at a timing set
+};
+
 }  // namespace kfmi
 
 struct kf_ctx {
@@ -34,12 +47,15 @@ struct kf_ctx {
     int n_cu = 0;                     // compute units of the device
     int max_lds = 0;                  // LDS bytes a workgroup may use
     int find_width = 64;              // lanes per workgroup of the finding kernel
-    int find_largest_first = 1;       // tile order
+    int find_largest_first = 0;       // tile order
     int occ_cache[2][9] = {};         // resident workgroups per CU by (precision, log2 width)
     int timing_cap = 0;               // event sets available (0: timing off)
     int timing_used = 0;              // event sets recorded since kf_set_timing
     int timing_n = 0;                 // sets requested by kf_set_timing
-    hipEvent_t* ev = nullptr;         // [timing_cap][4] phase boundaries
+    hipEvent_t* ev = nullptr;         // [timing_cap][kPhaseEvents] phase boundaries
+    hipStream_t cap_stream = nullptr; // private stream the batched pass is captured on
+    hipEvent_t idle_ev[kfmi::kPhaseEvents] = {};  // record targets of an untimed graph launch
+    kfmi::FindGraph fg;
 };
 
 namespace kfmi {

@@ -46,6 +46,16 @@ class FindProblem:
         self.seed_fit(flags)
         self.find(flags)
 
+    def run_batched(self, flags=0):
+        """The same pass as run(), as one captured graph (kf_find_batched)."""
+        self.ctx.find_batched(self.hits, self.event_off, self.seed_hits, self.seed_layers,
+                              self.seed_event, self.seeds, self.out_hits, self.out, self.counters,
+                              flags)
+
+    def autotune(self, flags=0, reps=3):
+        return self.ctx.autotune(self.hits, self.event_off, self.seeds, self.seed_event,
+                                 self.seed_hits, self.out_hits, self.out, flags, reps)
+
     def results(self):
         r = self.out.numpy()
         r["hits"] = self.out_hits[:self.n_seeds].cpu().numpy()

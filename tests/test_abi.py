@@ -48,3 +48,19 @@ def test_argument_validation_without_device(lib):
     lib.kf_fit.restype = C.c_int
     lib.kf_fit.argtypes = [C.c_void_p] * 6 + [C.c_int, C.c_void_p]
     assert lib.kf_fit(None, None, None, None, None, 0, 0, None) == -1
+
+
+def test_batched_and_autotune_validation_without_device(lib):
+    """The graph and autotuning entry points reject a null context before any
+    device work."""
+    for f, n in (("kf_find_batched", 13), ("kf_autotune", 13)):
+        fn = getattr(lib, f)
+        fn.restype = C.c_int
+        fn.argtypes = [C.c_void_p] * n
+        assert fn(*([None] * n)) == -1, f
+    lib.kf_get_find_config.restype = C.c_int
+    lib.kf_get_find_config.argtypes = [C.c_void_p] * 3
+    assert lib.kf_get_find_config(None, None, None) == -1
+    lib.kf_timings.restype = C.c_int
+    lib.kf_timings.argtypes = [C.c_void_p] * 2
+    assert lib.kf_timings(None, None) == -1

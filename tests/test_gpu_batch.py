@@ -33,3 +33,87 @@ def test_batch_widths_identical(K, cfg2):
         r = _gpu_find(K, geom, inp, w, lf)
         for k in ("hits", "par", "chi2", "ndf", "status"):
             assert np.array_equal(r[k], ref[k]), (w, lf, k)
+
+
+def _same(r, ref, label):
+    for k in ("hits", "par", "cov", "chi2", "ndf", "status"):
+        assert np.array_equal(r[k], ref[k]), (label, k)
+
+
+def test_batched_graph_replays_match_eager(K, cfg2):
+    """kf_find_batched (seed, seed fit, binning, seed order and the finding
+    kernel captured as one graph) gives the eager path's results on every
+    replay, with eager work and synchronisations between the replays; a
+    smaller input on the same context captures again and matches too."""
+    import torch
+    geom, evs, inp = cfg2
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run()
+    torch.cuda.synchronize()
+    ref = fp.results()
+    c_eager = ref["counters"].copy()
+    assert c_eager[0] > 0
+    for rep in range(4):
+        fp.out_hits.fill_(-7)
+        fp.out.par.zero_()
+        fp.counters.zero_()
+        fp.run_batched()
+        torch.cuda.synchronize()
+        r = fp.results()
+        _same(r, ref, f"replay {rep}")
+        assert np.array_equal(r["counters"], c_eager), rep
+        # eager work on the same context between replays
+        fp.find()
+        torch.cuda.synchronize()
+    # a smaller batch (the first 8 events) on the same context
+    small_inp = E.find_inputs(evs[:8])
+    fs = K.pipeline.FindProblem(ctx, small_inp)
+    fs.run()
+    torch.cuda.synchronize()
+    ref_s = fs.results()
+    for rep in range(2):
+        fs.out_hits.fill_(-7)
+        fs.run_batched()
+        torch.cuda.synchronize()
+        _same(fs.results(), ref_s, f"small replay {rep}")
+
+
+def test_batched_phase_timing(K, cfg2):
+    import torch
+    geom, evs, inp = cfg2
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run_batched()
+    ctx.set_timing(3)
+    for _ in range(3):
+        fp.run_batched()
+    fp.run_batched()          # beyond the requested sets: not recorded
+    torch.cuda.synchronize()
+    ms, n = ctx.timings()
+    assert n == 3
+    assert all(m > 0 for m in ms), ms
+    ctx.set_timing(0)
+    fp.run_batched()
+    torch.cuda.synchronize()
+
+
+def test_autotune_keeps_fastest_and_results(K, cfg2):
+    """The autotuner times every width and both tile orders, keeps the
+    fastest, and the tuned configuration gives the same results."""
+    import torch
+    geom, evs, inp = cfg2
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run()
+    torch.cuda.synchronize()
+    ref = fp.results()
+    tab = fp.autotune(reps=2)
+    print("autotune table (ms):", tab)
+    assert len(tab) == 8, tab
+    best = min(tab, key=tab.get)
+    assert ctx.find_config() == best
+    fp.out_hits.fill_(-7)
+    fp.run()
+    torch.cuda.synchronize()
+    _same(fp.results(), ref, "tuned")
