@@ -137,20 +137,39 @@ __global__ __launch_bounds__(256) void seg_count_kernel(int64_t n_hits, const in
             if (h[b]) atomicAdd(&seg_cnt[s0 + b], h[b]);
 }
 
-__global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t n_hits, const int32_t* __restrict__ event_off,
-                                                          int n_events, int n_layers,
+__device__ inline int hit_bin(const kf_layer& L, float hx, float hy, float hz)
+{
+    const int bp = phi_bin_of(atan2f(hy, hx), L.nbin_phi);
+    const float v = L.kind == 0 ? hz : sqrtf(hx * hx + hy * hy);
+    return bp * L.nbin_2 + coord_bin_of(v, float(L.lo), float(L.hi), L.nbin_2);
+}
+
+// Level 1, second pass: each hit's complete record and its bin within the
+// layer go to the hit's segment, so that level 2 streams contiguous records
+// (the caller's hits may come in any order within an event).
+__global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t n_hits, const float* __restrict__ x,
+                                                          const float* __restrict__ y,
+                                                          const float* __restrict__ z,
+                                                          const float* __restrict__ su,
+                                                          const float* __restrict__ sv,
+                                                          const int32_t* __restrict__ event_off,
+                                                          int n_events, const kf_layer* __restrict__ layers,
+                                                          int n_layers,
                                                           const int32_t* __restrict__ seg_key,
                                                           const int32_t* __restrict__ seg_off,
                                                           int32_t* __restrict__ seg_fill,
-                                                          int32_t* __restrict__ seg_hits)
+                                                          BinnedHit* __restrict__ seg_rec,
+                                                          int32_t* __restrict__ seg_bin)
 {
     __shared__ int h[kSegLocal];
     __shared__ int base[kSegLocal];
+    __shared__ kf_layer sl[kMaxLayers];
     const int64_t c0 = (int64_t)blockIdx.x * kSegChunk;
     const int64_t c1 = c0 + kSegChunk < n_hits ? c0 + kSegChunk : n_hits;
     const int s0 = event_clamped(event_off, n_events, c0) * n_layers;
     const int ns = (event_clamped(event_off, n_events, c1 - 1) + 1) * n_layers - s0;
     const bool local = ns <= kSegLocal;
+    for (int l = threadIdx.x; l < n_layers; l += blockDim.x) sl[l] = layers[l];
     if (local) {
         for (int b = threadIdx.x; b < ns; b += blockDim.x) h[b] = 0;
         __syncthreads();
@@ -164,46 +183,46 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t n_hits, const 
             base[b] = h[b] ? seg_off[s0 + b] + atomicAdd(&seg_fill[s0 + b], h[b]) : 0;
             h[b] = 0;
         }
-        __syncthreads();
     }
+    __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
         const int key = seg_key[i];
         if (key < 0) continue;
         const int pos = local && (unsigned)(key - s0) < (unsigned)ns
                             ? base[key - s0] + atomicAdd(&h[key - s0], 1)
                             : seg_off[key] + atomicAdd(&seg_fill[key], 1);
-        seg_hits[pos] = (int32_t)i;
+        BinnedHit r;
+        r.x = x[i];
+        r.y = y[i];
+        r.z = z[i];
+        r.su = su[i];
+        r.sv = sv[i];
+        const float rho = sqrtf(r.x * r.x + r.y * r.y);
+        r.cphi = r.x / rho;
+        r.sphi = r.y / rho;
+        r.idx = (int32_t)i;
+        seg_rec[pos] = r;
+        seg_bin[pos] = hit_bin(sl[key % n_layers], r.x, r.y, r.z);
     }
 }
 
-__device__ inline int hit_bin(const kf_layer& L, float hx, float hy, float hz)
-{
-    const int bp = phi_bin_of(atan2f(hy, hx), L.nbin_phi);
-    const float v = L.kind == 0 ? hz : sqrtf(hx * hx + hy * hy);
-    return bp * L.nbin_2 + coord_bin_of(v, float(L.lo), float(L.hi), L.nbin_2);
-}
-
+// Level 2: one workgroup per segment sorts its records by bin.
 constexpr int kBinThreads = 1024;
 __global__ __launch_bounds__(kBinThreads) void bin_segment_kernel(
-    const int32_t* __restrict__ seg_off, const int32_t* __restrict__ seg_hits,
-    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const float* __restrict__ su, const float* __restrict__ sv, const kf_layer* __restrict__ layers,
-    int n_layers, int n_seg, BinLayout bl, int32_t* __restrict__ bin_off, BinnedHit* __restrict__ out)
+    const int32_t* __restrict__ seg_off, const BinnedHit* __restrict__ seg_rec,
+    const int32_t* __restrict__ seg_bin, const kf_layer* __restrict__ layers, int n_layers,
+    int n_seg, BinLayout bl, int32_t* __restrict__ bin_off, BinnedHit* __restrict__ out)
 {
     __shared__ int hist[kMaxLayerBins];
     __shared__ int lds[kBinThreads / 64];
     const int seg = blockIdx.x;
     const int e = seg / n_layers, l = seg - e * n_layers;
-    const kf_layer L = layers[l];
-    const int nb = L.nbin_phi * L.nbin_2;
+    const int nb = layers[l].nbin_phi * layers[l].nbin_2;
     const int lo = seg_off[seg], hi = seg_off[seg + 1];
     const int t = threadIdx.x;
     for (int b = t; b < nb; b += kBinThreads) hist[b] = 0;
     __syncthreads();
-    for (int i = lo + t; i < hi; i += kBinThreads) {
-        const int h = seg_hits[i];
-        atomicAdd(&hist[hit_bin(L, x[h], y[h], z[h])], 1);
-    }
+    for (int i = lo + t; i < hi; i += kBinThreads) atomicAdd(&hist[seg_bin[i]], 1);
     __syncthreads();
     // exclusive scan of the bin counts: lane t takes bins [t*per, (t+1)*per)
     const int per = (nb + kBinThreads - 1) / kBinThreads;
@@ -223,20 +242,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_segment_kernel(
         }
     if (seg == n_seg - 1 && t == 0) bin_off[(int64_t)(e + 1) * bl.per_event] = hi;
     __syncthreads();
-    for (int i = lo + t; i < hi; i += kBinThreads) {
-        const int h = seg_hits[i];
-        BinnedHit r;
-        r.x = x[h];
-        r.y = y[h];
-        r.z = z[h];
-        r.su = su[h];
-        r.sv = sv[h];
-        const float rho = sqrtf(r.x * r.x + r.y * r.y);
-        r.cphi = r.x / rho;
-        r.sphi = r.y / rho;
-        r.idx = h;
-        out[atomicAdd(&hist[hit_bin(L, r.x, r.y, r.z)], 1)] = r;
-    }
+    for (int i = lo + t; i < hi; i += kBinThreads) out[atomicAdd(&hist[seg_bin[i]], 1)] = seg_rec[i];
 }
 
 // ------------------------------------------------------------------ prefix sums
@@ -1038,12 +1044,14 @@ hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event
     }
     if ((e = launch_scan(pl.seg_cnt, pl.seg_off, n_seg + 1, pl.bsum, s)) != hipSuccess) return e;
     if (h->n > 0) {
-        seg_scatter_kernel<<<nchunk, 256, 0, s>>>(h->n, event_off, n_events, n_layers, pl.hit_key,
-                                                  pl.seg_off, pl.seg_fill, pl.seg_hits);
+        seg_scatter_kernel<<<nchunk, 256, 0, s>>>(h->n, h->x, h->y, h->z, h->su, h->sv, event_off,
+                                                  n_events, d_layers, n_layers, pl.hit_key,
+                                                  pl.seg_off, pl.seg_fill, (BinnedHit*)pl.seg_rec,
+                                                  pl.seg_bin);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     bin_segment_kernel<<<(unsigned)n_seg, kBinThreads, 0, s>>>(
-        pl.seg_off, pl.seg_hits, h->x, h->y, h->z, h->su, h->sv, d_layers, n_layers, (int)n_seg,
+        pl.seg_off, (const BinnedHit*)pl.seg_rec, pl.seg_bin, d_layers, n_layers, (int)n_seg,
         pl.bl, pl.off, (BinnedHit*)pl.binned);
     return hipGetLastError();
 }
@@ -1091,7 +1099,8 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     pl->seg_off = (int32_t*)take(sizeof(int32_t) * nseg);
     pl->off = (int32_t*)take(sizeof(int32_t) * nb);
     pl->hit_key = (int32_t*)take(sizeof(int32_t) * nh);
-    pl->seg_hits = (int32_t*)take(sizeof(int32_t) * nh);
+    pl->seg_rec = take(sizeof(BinnedHit) * nh);
+    pl->seg_bin = (int32_t*)take(sizeof(int32_t) * nh);
     pl->binned = take(sizeof(BinnedHit) * nh);
     pl->scnt = (int32_t*)take(sizeof(int32_t) * nc);
     pl->soff = (int32_t*)take(sizeof(int32_t) * nc);

@@ -69,7 +69,8 @@ struct FindPlan {
     int32_t* seg_off;   // [n_events * n_layers + 1] exclusive prefix sum of seg_cnt
     int32_t* off;       // [n_events * per_event + 1] first binned hit of every bin
     int32_t* hit_key;   // [n_hits] segment of each hit (-1: not binned)
-    int32_t* seg_hits;  // [n_hits] hit indices grouped by segment
+    void* seg_rec;      // [n_hits] hit records grouped by segment (32 bytes each)
+    int32_t* seg_bin;   // [n_hits] bin of each grouped record within its layer
     void* binned;       // [n_hits] records of 32 bytes
     int32_t* scnt;      // [n_events * cells + 1] seeds per (event, eta, phi) cell
     int32_t* soff;      // [n_events * cells + 1] its exclusive prefix sum
