@@ -55,7 +55,7 @@ def parse():
 def find_flops(cnt, oc):
     """Algorithmic flops of the finding kernel from its event counters and the
     operation counts of its arithmetic (special-function calls counted as one)."""
-    props, upd, chi2, newton, disk = [float(c) for c in cnt]
+    props, upd, chi2, newton, disk = [float(c) for c in cnt[:5]]
     f = lambda k: oc[k]["ops"] + oc[k]["sfu"]
     per_prop = f("nav_fixed") + f("barrel_setup") + f("transport_barrel") + f("window")
     return (props * per_prop + newton * f("newton_eval") + disk * f("disk_eval")

@@ -356,3 +356,37 @@ def batch_events(n_events=64, seed=2, noise_per_track=60, lam_lo=200.0, lam_hi=4
         per_layer = noise_per_track * n // len(geom)
         evs.append(make_event(rng, geom, n, pt_power2(0.5, 50.0), 2.5, per_layer))
     return geom, evs
+
+
+def propagation_pairs(n_pairs=1_000_000, seed=4, n_tracks=200_000):
+    """Starting states and target layers for learning the propagation path
+    length at the precision workload's distribution (pT 0.3 / 100 GeV, ten
+    barrel layers, no material): every state a track passes through (its
+    vertex and each crossing but the last) paired with the next layer it
+    crosses, shuffled, the first n_pairs.  Returns (geom, state [n, 6] float64
+    = (x, y, z, c, phi, theta), target layer [n] int32)."""
+    geom, ev = precision_sample(n_tracks, seed=seed)
+    nh = ev.n_track_hits()
+    states = [ev.truth0]
+    targets = [ev.seq_layer[:, 0]]
+    for k in range(1, ev.seq_layer.shape[1]):
+        m = nh > k
+        states.append(ev.truth_out[m, k - 1])
+        targets.append(ev.seq_layer[m, k])
+    st = np.concatenate(states)
+    tg = np.concatenate(targets).astype(np.int32)
+    rng = np.random.default_rng(seed + 1000)
+    sel = rng.permutation(st.shape[0])[:n_pairs]
+    return geom, st[sel], tg[sel]
+
+
+def mlp_init(seed=4, n_in=8, n_hidden=64):
+    """Initial network parameters, flat float32 in the order W1[64][8], b1,
+    W2[64][64], b2, w3[64], b3: weights uniform in +-sqrt(6 / (fan_in +
+    fan_out)) (Glorot & Bengio 2010), biases zero."""
+    rng = np.random.default_rng(seed)
+    u = lambda fi, fo, shape: rng.uniform(-math.sqrt(6.0 / (fi + fo)), math.sqrt(6.0 / (fi + fo)), shape)
+    parts = [u(n_in, n_hidden, (n_hidden, n_in)), np.zeros(n_hidden),
+             u(n_hidden, n_hidden, (n_hidden, n_hidden)), np.zeros(n_hidden),
+             u(n_hidden, 1, n_hidden), np.zeros(1)]
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)

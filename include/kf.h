@@ -23,7 +23,8 @@
  *   the null stream); the caller synchronises before reading results.
  *   Return value: KF_OK, or a negative kf_status for invalid arguments or a
  *   HIP error (see kf_last_error).  Numerical trouble is never an error: it is
- *   reported per track in `status` bits and the track is frozen from there on.
+ *   reported per track in `status` bits and the track is frozen from there on
+ *   (KF_ST_FALLBACK excepted, which only informs).
  *   A context must not be used from two host threads at once.
  */
 #ifndef KFMI_KF_H
@@ -50,7 +51,9 @@ enum {
     KF_ST_OK = 0,
     KF_ST_UNREACHABLE = 1, /* target surface not reachable (looper / behind) */
     KF_ST_NOCONV = 2,      /* propagate-to-radius did not converge */
-    KF_ST_FALLBACK = 4,    /* learned initial guess rejected, exact solve used */
+    KF_ST_FALLBACK = 4,    /* informational, does not freeze the track: the learned
+                              initial guess did not converge within mlp_max_iter
+                              evaluations and the straight-line start was used */
     KF_ST_NONPD = 8,       /* innovation matrix not positive definite */
     KF_ST_NAN = 16,        /* non-finite state */
     KF_ST_BADINPUT = 32    /* out-of-range layer or hit index in the caller's arrays */
@@ -63,7 +66,8 @@ enum {
     KF_PREC_FP32 = 1,      /* everything FP32 (Joseph form kept) */
     KF_PREC_FP64 = 2,      /* everything FP64 */
     KF_PREC_MASK = 3,
-    KF_INIT_MLP = 4,       /* start propagate-to-radius from the learned path-length guess */
+    KF_INIT_MLP = 4,       /* start propagate-to-radius from the learned path-length guess
+                              (needs kf_mlp_load; kf_find needs a width >= 64) */
     KF_NO_MATERIAL = 8,    /* ignore the layers' material (no process noise) */
     KF_PER_LAYER = 16      /* kf_fit: one launch per step, state through HBM between steps */
 };
@@ -159,8 +163,9 @@ int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_
  *               layer (global hit index), -1 = none
  *   out         n_seeds tracks, out->n == seeds->n: best candidate's state at its
  *               last surface, chi2, ndf = 2*hits - 5, status
- *   counters    optional [5] uint64, incremented by (propagations, updates,
- *               chi2 tests, Newton evaluations, disk-crossing tests)
+ *   counters    optional [7] uint64, incremented by (propagations, updates,
+ *               chi2 tests, Newton evaluations, disk-crossing tests, learned
+ *               guesses evaluated, learned guesses that fell back)
  * Per layer a candidate is propagated to its next surface (the first reached
  * of the next barrel outward and the next disk ahead), every hit in the chi2
  * window's bins passing chi2 < chi2_cut becomes a child (best max_cands per
@@ -220,6 +225,55 @@ int kf_autotune(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int3
  * kernel, and ms[4] = number of calls recorded.  Returns KF_EINVAL if none was. */
 int kf_set_timing(kf_ctx* ctx, int32_t n);
 int kf_timings(kf_ctx* ctx, float ms[5]);
+
+
+/* ---- Learned initial guess of propagate-to-radius (not in the paper; the
+ * solve it starts stays exact).  Network 8 -> 64 (tanh) -> 64 (tanh) -> 1,
+ * evaluated on the matrix cores in bf16 with FP32 accumulation; trained on the
+ * device with FP32 master weights and Adam.  Parameters, flat FP32, 4801:
+ * W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3 (W row-major [out][in]).
+ * Inputs (8): rho/100, sin and cos of (phi - atan2(y, x)), h * (target radius,
+ * or 100 cm for a disk) with h = -0.00299792458 B c, target radius or disk z
+ * over 100, the straight-line path length s_line to the target over 100, cot
+ * theta, 1 for a disk.  Output: (transverse path length - s_line) / (h
+ * s_line^2).  With KF_INIT_MLP a barrel solve whose predicted correction
+ * exceeds 100 newton_tol starts from s_line + h s_line^2 * output with
+ * mlp_max_iter evaluations of r(s), and if those do not converge runs the
+ * plain solve (fallback); smaller corrections keep the straight-line start. */
+
+#define KF_MLP_NPARAM 4801
+#define KF_MLP_NIN 8
+
+typedef struct {
+    double lr;             /* Adam step size (default 1e-3) */
+    double beta1, beta2;   /* moment decays (0.9, 0.999) */
+    double eps;            /* 1e-8 */
+} kf_mlp_train_cfg;
+
+/* Loads the FP32 parameters w (host [4801]) as the master copy, resets the
+ * Adam moments and step count, and publishes the bf16 copies.  Synchronous;
+ * must not overlap calls that use the network. */
+int kf_mlp_load(kf_ctx* ctx, const float* w);
+/* Reads the FP32 master parameters into w (host [4801]); synchronises the device. */
+int kf_mlp_get(kf_ctx* ctx, float* w);
+/* Network inputs for propagating each track of t to target_layer [ld] int32
+ * (-1: zeros).  feats [8][t->ld] float32, device. */
+int kf_mlp_features(kf_ctx* ctx, const kf_tracks* t, const int32_t* target_layer, float* feats,
+                    int flags, void* stream);
+/* Network outputs out [n] for inputs feats [8][ld] (device). */
+int kf_mlp_forward(kf_ctx* ctx, const float* feats, int64_t n, int64_t ld, float* out, void* stream);
+/* Mean-squared-error loss and its gradient over the batch rows rows [batch]
+ * (int32 indices into the n columns of feats [8][ld] and target [ld]; rows
+ * outside [0, n) are skipped but still count in the mean).  grad: device
+ * float [4801]; loss: device float [1] or NULL.  Parameters unchanged. */
+int kf_mlp_grad(kf_ctx* ctx, const float* feats, const float* target, int64_t n, int64_t ld,
+                const int32_t* rows, int32_t batch, float* grad, float* loss, void* stream);
+/* n_steps Adam steps; step k uses the rows rows[k*batch .. (k+1)*batch) (the
+ * caller draws the shuffling).  cfg: host, NULL = defaults.  loss: optional
+ * device float [n_steps], the batch loss before each step. */
+int kf_mlp_train(kf_ctx* ctx, const float* feats, const float* target, int64_t n, int64_t ld,
+                 const int32_t* rows, int32_t batch, int32_t n_steps, const kf_mlp_train_cfg* cfg,
+                 float* loss, void* stream);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,9 @@ the next layer).  Reading taken for the unstated details:
     (disk), the target radius or disk z over 100, the straight-line path
     length to the target over 100 (tangent-line intersection for a barrel,
     the exact (z_D - z) tan theta for a disk), cot theta, and 1 for a disk;
-  * output: transverse arc length to the target over 100;
+  * output: the transverse arc length to the target minus the straight-line
+    one, in units of h s_line^2 (the leading order of that difference; the
+    guess is s_line + h s_line^2 * output);
   * 8 -> 64 (tanh) -> 64 (tanh) -> 1 (linear), mean squared error, Adam.
 Flat parameter order (4801 values): W1[64][8], b1[64], W2[64][64], b2[64],
 w3[64], b3.

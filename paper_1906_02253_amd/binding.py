@@ -41,6 +41,16 @@ class KfHits(C.Structure):
                 ("su", C.c_void_p), ("sv", C.c_void_p), ("layer", C.c_void_p)]
 
 
+class KfTrainCfg(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double)]
+
+
+MLP_NPARAM, MLP_NIN = 4801, 8
+N_COUNTERS = 7      # propagations, updates, chi2 tests, Newton evaluations, disk tests,
+                    # learned guesses, learned guesses that fell back
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build()); "
@@ -66,9 +76,17 @@ def _load():
                               C.POINTER(KfTracks), C.c_int, i32, C.POINTER(C.c_float), vp]
     L.kf_set_timing.argtypes = [vp, i32]
     L.kf_timings.argtypes = [vp, C.POINTER(C.c_float)]
+    fp = C.POINTER(C.c_float)
+    L.kf_mlp_load.argtypes = [vp, fp]
+    L.kf_mlp_get.argtypes = [vp, fp]
+    L.kf_mlp_features.argtypes = [vp, C.POINTER(KfTracks), vp, vp, C.c_int, vp]
+    L.kf_mlp_forward.argtypes = [vp, vp, i64, i64, vp, vp]
+    L.kf_mlp_grad.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp, vp, vp]
+    L.kf_mlp_train.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, C.POINTER(KfTrainCfg), vp, vp]
     for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_find_batched",
               "kf_set_find_config", "kf_get_find_config", "kf_autotune", "kf_set_timing",
-              "kf_timings"):
+              "kf_timings", "kf_mlp_load", "kf_mlp_get", "kf_mlp_features", "kf_mlp_forward",
+              "kf_mlp_grad", "kf_mlp_train"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -225,7 +243,7 @@ class Context:
              flags=0):
         """event_off: int32 [n_events+1]; seed_event: int32 [n_seeds];
         seed_hits: int32 [3, seeds.ld]; out_hits: int32 [n_seeds, n_layers];
-        counters: optional int64 [5], accumulated."""
+        counters: optional int64 [7], accumulated."""
         n_events = int(event_off.shape[0]) - 1
         self._check(lib.kf_find(self.h, C.byref(hits.c()), _ptr(event_off), n_events,
                                 C.byref(seeds.c()), _ptr(seed_event), _ptr(seed_hits),
@@ -254,3 +272,39 @@ class Context:
                                     _stream()), "kf_autotune")
         return {(w, bool(lf)): tab[2 * i + lf] for i, w in enumerate((32, 64, 128, 256))
                 for lf in (0, 1) if tab[2 * i + lf] >= 0}
+
+    # ---- learned initial guess
+    def mlp_load(self, w):
+        """w: numpy float32 [4801] (flat: W1, b1, W2, b2, w3, b3)."""
+        import numpy as np
+        a = np.ascontiguousarray(w, dtype=np.float32)
+        if a.shape != (MLP_NPARAM,):
+            raise ValueError("expected 4801 parameters")
+        self._check(lib.kf_mlp_load(self.h, a.ctypes.data_as(C.POINTER(C.c_float))), "kf_mlp_load")
+
+    def mlp_get(self):
+        import numpy as np
+        a = np.zeros(MLP_NPARAM, np.float32)
+        self._check(lib.kf_mlp_get(self.h, a.ctypes.data_as(C.POINTER(C.c_float))), "kf_mlp_get")
+        return a
+
+    def mlp_features(self, tracks, target, feats, flags=0):
+        """feats: float32 [8, tracks.ld] on the GPU."""
+        self._check(lib.kf_mlp_features(self.h, C.byref(tracks.c()), _ptr(target), _ptr(feats),
+                                        flags, _stream()), "kf_mlp_features")
+
+    def mlp_forward(self, feats, n, out):
+        self._check(lib.kf_mlp_forward(self.h, _ptr(feats), int(n), int(feats.shape[1]), _ptr(out),
+                                       _stream()), "kf_mlp_forward")
+
+    def mlp_grad(self, feats, target, n, rows, grad, loss=None):
+        self._check(lib.kf_mlp_grad(self.h, _ptr(feats), _ptr(target), int(n), int(feats.shape[1]),
+                                    _ptr(rows), int(rows.shape[0]), _ptr(grad), _ptr(loss),
+                                    _stream()), "kf_mlp_grad")
+
+    def mlp_train(self, feats, target, n, rows, batch, n_steps, lr=1e-3, beta1=0.9, beta2=0.999,
+                  eps=1e-8, loss=None):
+        cfg = KfTrainCfg(lr, beta1, beta2, eps)
+        self._check(lib.kf_mlp_train(self.h, _ptr(feats), _ptr(target), int(n), int(feats.shape[1]),
+                                     _ptr(rows), int(batch), int(n_steps), C.byref(cfg), _ptr(loss),
+                                     _stream()), "kf_mlp_train")

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkfmi.so")
-SOURCES = ["kf_api.hip", "kf_fit.hip", "kf_find.hip"]
+SOURCES = ["kf_api.hip", "kf_fit.hip", "kf_find.hip", "kf_mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

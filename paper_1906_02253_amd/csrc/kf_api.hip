@@ -1,10 +1,14 @@
 // C-ABI entry points of libkfmi.so: argument validation, context and
 // workspace management, dispatch to the kernel launchers.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
+
 #include "kf_find.hpp"
+#include "kf_mlp_api.hpp"
 
 namespace {
 
@@ -83,6 +87,7 @@ struct FindLaunch {
     FindPlan pl;
     FindArgs a;
     int W = 0, grid = 0, prec = 0, largest_first = 0;
+    bool learn = false;
     int64_t n_events = 0;
     const int32_t* event_off = nullptr;
     const int32_t* seed_event = nullptr;
@@ -112,7 +117,10 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
         return fail(ctx, KF_EUNSUPPORTED, "%s: float storage only (MIXED or FP32)", what);
     if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
         return fail(ctx, KF_EINVAL, "%s: bad precision flag", what);
-    if (flags & KF_INIT_MLP) return fail(ctx, KF_EUNSUPPORTED, "%s: no learned model loaded", what);
+    const bool learn = (flags & KF_INIT_MLP) != 0;
+    if (learn && !ctx->mlp_loaded) return fail(ctx, KF_EUNSUPPORTED, "%s: no learned model loaded", what);
+    if (learn && ctx->find_width < 64)
+        return fail(ctx, KF_EUNSUPPORTED, "%s: the learned guess needs a width of at least 64", what);
     if (out->n != seeds->n) return fail(ctx, KF_EINVAL, "%s: out->n must equal seeds->n", what);
     if (n_events < 1 || !event_off) return fail(ctx, KF_EINVAL, "%s: need n_events >= 1 and event_off", what);
     if (hits->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "%s: at most 2^31-1 hits", what);
@@ -140,9 +148,9 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     int lw = 0;
     while ((1 << lw) < W) ++lw;
     const int pi = prec == KF_PREC_FP32 ? 1 : 0;
-    int& occ = ctx->occ_cache[pi][lw];
+    int& occ = ctx->occ_cache[learn ? 1 : 0][pi][lw];
     if (occ == 0) {
-        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, &occ);
+        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, learn, &occ);
         if (e != hipSuccess) return hip_fail(ctx, e, "find occupancy");
         if (occ < 1) occ = 1;
     }
@@ -187,6 +195,8 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
     a.n_tiles = (int)n_tiles;
     a.seeds_per_tile = S;
+    a.mlp = ctx->mlp.dev();
+    L->learn = learn;
     L->W = W;
     L->grid = (int)grid;
     L->prec = prec;
@@ -215,7 +225,7 @@ hipError_t phase_order(const kfmi::FindLaunch& L, hipStream_t s)
 
 hipError_t phase_find(const kfmi::FindLaunch& L, hipStream_t s)
 {
-    return kfmi::launch_find_kernel(L.a, L.W, L.grid, L.prec, s);
+    return kfmi::launch_find_kernel(L.a, L.W, L.grid, L.prec, L.learn, s);
 }
 
 // Event set of the next timed call, or nullptr when timing is off.
@@ -322,6 +332,8 @@ void kf_destroy(kf_ctx* ctx)
     for (int k = 0; k < kfmi::kPhaseEvents; ++k)
         if (ctx->idle_ev[k]) (void)hipEventDestroy(ctx->idle_ev[k]);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    ctx->mlp_ws.release();
+    if (ctx->mlp_mem) (void)hipFree(ctx->mlp_mem);
     ctx->ws.release();
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
     delete ctx;
@@ -347,7 +359,8 @@ int kf_propagate(kf_ctx* ctx, kf_tracks* t, const int32_t* target_layer, float* 
     int r = check_tracks(ctx, t, "kf_propagate");
     if (r) return r;
     if (t->n > 0 && !target_layer) return fail(ctx, KF_EINVAL, "kf_propagate: null target_layer");
-    if (flags & KF_INIT_MLP) return fail(ctx, KF_EUNSUPPORTED, "kf_propagate: no learned model loaded");
+    if ((flags & KF_INIT_MLP) && !ctx->mlp_loaded)
+        return fail(ctx, KF_EUNSUPPORTED, "kf_propagate: no learned model loaded");
     hipError_t e = kfmi::launch_propagate(ctx, t, target_layer, path_len, iters, flags,
                                           (hipStream_t)stream);
     return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_propagate");
@@ -365,7 +378,8 @@ int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_
     if (!layer_seq && max_steps > ctx->n_layers)
         return fail(ctx, KF_EINVAL, "kf_fit: max_steps exceeds the layer count with implicit layers");
     if (t->n > 0 && max_steps > 0 && !hit_idx) return fail(ctx, KF_EINVAL, "kf_fit: null hit_idx");
-    if (flags & KF_INIT_MLP) return fail(ctx, KF_EUNSUPPORTED, "kf_fit: no learned model loaded");
+    if ((flags & KF_INIT_MLP) && !ctx->mlp_loaded)
+        return fail(ctx, KF_EUNSUPPORTED, "kf_fit: no learned model loaded");
     hipError_t e = kfmi::launch_fit(ctx, t, hits, layer_seq, hit_idx, max_steps, flags,
                                     (hipStream_t)stream);
     return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_fit");
@@ -466,7 +480,7 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
         release_graph(ctx);
         hipGraph_t sub[4] = {nullptr, nullptr, nullptr, nullptr};
         kf_tracks* st = seeds;
-        const int fit_flags = flags & (KF_PREC_MASK | KF_NO_MATERIAL);
+        const int fit_flags = flags & (KF_PREC_MASK | KF_NO_MATERIAL | KF_INIT_MLP);
         e = capture(ctx, &sub[0], [&](hipStream_t cs) {
             hipError_t x = kfmi::launch_seed(ctx, hits, seed_hits, st, fit_flags, cs);
             if (x == hipSuccess) x = kfmi::launch_fit(ctx, st, hits, seed_layers, seed_hits, 3, fit_flags, cs);
@@ -592,7 +606,7 @@ int kf_autotune(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int3
     for (int c = 0; c < NC; ++c) {
         best_ms[c] = -1.0f;
         const int w = widths[c / 2];
-        fits[c] = w / ctx->params.max_cands >= 1 &&
+        fits[c] = w / ctx->params.max_cands >= 1 && !((flags & KF_INIT_MLP) && w < 64) &&
                   kfmi::find_shared_size(w, w / ctx->params.max_cands, ctx->n_layers,
                                          flags & KF_PREC_MASK) <= (size_t)ctx->max_lds;
     }
@@ -640,6 +654,133 @@ int kf_autotune(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int3
     ctx->find_width = widths[best / 2];
     ctx->find_largest_first = best & 1;
     return KF_OK;
+}
+
+
+// ------------------------------------------------------------------ learned guess
+
+int kf_mlp_load(kf_ctx* ctx, const float* w)
+{
+    if (!ctx || !w) return fail(ctx, KF_EINVAL, "kf_mlp_load: null argument");
+    for (int p = 0; p < kfmi::kMlpParams; ++p)
+        if (!std::isfinite(w[p])) return fail(ctx, KF_EINVAL, "kf_mlp_load: parameter %d is not finite", p);
+    hipError_t e = hipSuccess;
+    constexpr size_t nf = 3 * kfmi::kMlpParams + 193;
+    constexpr size_t fbytes = (nf * sizeof(float) + 255) & ~size_t(255);
+    if (!ctx->mlp_mem) {
+        e = hipMalloc(&ctx->mlp_mem, fbytes + sizeof(uint16_t) * (64 * 16 + 2 * 64 * 64));
+        if (e != hipSuccess) {
+            ctx->mlp_mem = nullptr;
+            return hip_fail(ctx, e, "kf_mlp_load");
+        }
+        float* f = (float*)ctx->mlp_mem;
+        uint16_t* b = (uint16_t*)((char*)ctx->mlp_mem + fbytes);
+        ctx->mlp.master = f;
+        ctx->mlp.m = f + kfmi::kMlpParams;
+        ctx->mlp.v = f + 2 * kfmi::kMlpParams;
+        ctx->mlp.bias = f + 3 * kfmi::kMlpParams;
+        ctx->mlp.w1 = b;
+        ctx->mlp.w2 = b + 64 * 16;
+        ctx->mlp.w2t = b + 64 * 16 + 64 * 64;
+    }
+    e = hipMemcpy(ctx->mlp.master, w, sizeof(float) * kfmi::kMlpParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(ctx->mlp.m, 0, sizeof(float) * 2 * kfmi::kMlpParams);
+    if (e == hipSuccess) e = kfmi::launch_mlp_publish(ctx->mlp, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_mlp_load");
+    ctx->mlp_loaded = true;
+    ctx->mlp_step = 0;
+    return KF_OK;
+}
+
+int kf_mlp_get(kf_ctx* ctx, float* w)
+{
+    if (!ctx || !w) return fail(ctx, KF_EINVAL, "kf_mlp_get: null argument");
+    if (!ctx->mlp_loaded) return fail(ctx, KF_EINVAL, "kf_mlp_get: no learned model loaded");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(w, ctx->mlp.master, sizeof(float) * kfmi::kMlpParams, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_mlp_get");
+}
+
+int kf_mlp_features(kf_ctx* ctx, const kf_tracks* t, const int32_t* target_layer, float* feats,
+                    int flags, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_mlp_features: null context");
+    int r = check_tracks(ctx, t, "kf_mlp_features");
+    if (r) return r;
+    if (t->n > 0 && (!target_layer || !feats)) return fail(ctx, KF_EINVAL, "kf_mlp_features: null array");
+    hipError_t e = kfmi::launch_mlp_features(ctx, t, target_layer, feats, flags & KF_PREC_MASK,
+                                             (hipStream_t)stream);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_mlp_features");
+}
+
+int kf_mlp_forward(kf_ctx* ctx, const float* feats, int64_t n, int64_t ld, float* out, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_mlp_forward: null context");
+    if (!ctx->mlp_loaded) return fail(ctx, KF_EINVAL, "kf_mlp_forward: no learned model loaded");
+    if (n < 0 || ld < n) return fail(ctx, KF_EINVAL, "kf_mlp_forward: need 0 <= n <= ld");
+    if (n > 0 && (!feats || !out)) return fail(ctx, KF_EINVAL, "kf_mlp_forward: null array");
+    hipError_t e = kfmi::launch_mlp_forward(ctx->mlp.dev(), feats, n, ld, out, (hipStream_t)stream);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_mlp_forward");
+}
+
+namespace {
+int mlp_step_args(kf_ctx* ctx, const float* feats, const float* target, int64_t n, int64_t ld,
+                  const int32_t* rows, int32_t batch, const char* what)
+{
+    if (!ctx->mlp_loaded) return fail(ctx, KF_EINVAL, "%s: no learned model loaded", what);
+    if (n < 1 || ld < n) return fail(ctx, KF_EINVAL, "%s: need 1 <= n <= ld", what);
+    if (batch < 1 || batch > (1 << 20)) return fail(ctx, KF_EINVAL, "%s: batch must be in 1..2^20", what);
+    if (!feats || !target || !rows) return fail(ctx, KF_EINVAL, "%s: null array", what);
+    return KF_OK;
+}
+}  // namespace
+
+int kf_mlp_grad(kf_ctx* ctx, const float* feats, const float* target, int64_t n, int64_t ld,
+                const int32_t* rows, int32_t batch, float* grad, float* loss, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_mlp_grad: null context");
+    int r = mlp_step_args(ctx, feats, target, n, ld, rows, batch, "kf_mlp_grad");
+    if (r) return r;
+    if (!grad) return fail(ctx, KF_EINVAL, "kf_mlp_grad: null grad");
+    void* scratch = ctx->mlp_ws.get(kfmi::mlp_partial_bytes(batch));
+    if (!scratch) return fail(ctx, KF_ENOMEM, "kf_mlp_grad: scratch");
+    kfmi::AdamStep ad{};
+    hipError_t e = kfmi::launch_mlp_step(ctx->mlp, feats, target, n, ld, rows, batch, scratch, 0, ad,
+                                         grad, loss, (hipStream_t)stream);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_mlp_grad");
+}
+
+int kf_mlp_train(kf_ctx* ctx, const float* feats, const float* target, int64_t n, int64_t ld,
+                 const int32_t* rows, int32_t batch, int32_t n_steps, const kf_mlp_train_cfg* cfg,
+                 float* loss, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_mlp_train: null context");
+    int r = mlp_step_args(ctx, feats, target, n, ld, rows, batch, "kf_mlp_train");
+    if (r) return r;
+    if (n_steps < 0) return fail(ctx, KF_EINVAL, "kf_mlp_train: negative n_steps");
+    kf_mlp_train_cfg c{1e-3, 0.9, 0.999, 1e-8};
+    if (cfg) c = *cfg;
+    if (!(c.lr > 0) || !(c.beta1 >= 0 && c.beta1 < 1) || !(c.beta2 >= 0 && c.beta2 < 1) || !(c.eps > 0))
+        return fail(ctx, KF_EINVAL, "kf_mlp_train: bad optimiser settings");
+    void* scratch = ctx->mlp_ws.get(kfmi::mlp_partial_bytes(batch));
+    if (!scratch) return fail(ctx, KF_ENOMEM, "kf_mlp_train: scratch");
+    hipError_t e = hipSuccess;
+    for (int32_t k = 0; k < n_steps && e == hipSuccess; ++k) {
+        const int64_t t = ++ctx->mlp_step;
+        kfmi::AdamStep ad;
+        ad.lr = float(c.lr);
+        ad.beta1 = float(c.beta1);
+        ad.beta2 = float(c.beta2);
+        ad.eps = float(c.eps);
+        ad.c1 = float(1.0 / (1.0 - std::pow(c.beta1, double(t))));
+        ad.c2 = float(1.0 / (1.0 - std::pow(c.beta2, double(t))));
+        e = kfmi::launch_mlp_step(ctx->mlp, feats, target, n, ld, rows + (int64_t)k * batch, batch,
+                                  scratch, 1, ad, nullptr, loss ? loss + k : nullptr,
+                                  (hipStream_t)stream);
+    }
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_mlp_train");
 }
 
 }  // extern "C"

@@ -19,6 +19,7 @@
 //       back-pointers at the end.
 #include "kf_find.hpp"
 #include "kf_math.hpp"
+#include "kf_mlp.hpp"
 
 namespace kfmi {
 
@@ -453,7 +454,7 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
 #define KF_FIND_WAVES 2
 #endif
 
-template <typename T, typename C, typename U>
+template <typename T, typename C, typename U, bool LEARN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAVES))) void find_kernel(
     FindArgs a)
 {
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     const T kb = T(kKappa) * T(a.prm.bz);
     const float cut = float(a.prm.chi2_cut);
     unsigned long long n_prop = 0, n_upd = 0, n_chi2 = 0;
-    int n_newton = 0, n_disk = 0;
+    int n_newton = 0, n_disk = 0, n_guess = 0, n_fallback = 0;
     int2* bp_base = a.bp + (size_t)blockIdx.x * nl * S * kMaxCands;
 
     for (;;) {
@@ -566,7 +567,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             chi2 = a.schi2[sid];
             nhits = (a.sndf[sid] + 5) / 2;
             status = a.sstatus[sid] | (bad_event ? (uint32_t)KF_ST_BADINPUT : 0u);
-            done = status != 0;
+            done = (status & kFreezeMask) != 0;
         } else {
 #pragma unroll
             for (int k = 0; k < 6; ++k) p[k] = T(0);
@@ -577,12 +578,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         for (int step = 0; step < nl; ++step) {
             const bool live = occupied && !done;
             if (!__syncthreads_or(live)) break;
-            // ---- a3: navigate and propagate
+            // ---- a3: navigate and propagate (LEARN: the whole wave first
+            // evaluates the learned start of its candidates' barrel solves)
+            T s_guess = T(-1);
+            if (LEARN) {
+                float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
+                const int bl = live ? next_barrel(p, sh.layers, nl) : -1;
+                if (bl >= 0) mlp_features(p, sh.layers[bl], kb, f);
+                const float y = mlp_wave(a.mlp, f);
+                if (bl >= 0) {
+                    s_guess = T(mlp_guess(f, y));
+                    ++n_guess;
+                }
+            }
             int pl = -1;
             if (live) {
                 T s;
                 const int layer = navigate(p, sh.layers, nl, a.prm, kb, &s, &status, &n_newton,
-                                           &n_disk);
+                                           &n_disk, s_guess, LEARN ? a.prm.mlp_max_iter : 0,
+                                           &n_fallback);
                 if (layer < 0) {
                     done = true;
                 } else {
@@ -981,10 +995,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     }
     if (a.counters) {
         // wave-level reduction of the per-lane counts, one atomic per wave
-        unsigned long long c[5] = {n_prop, n_upd, n_chi2, (unsigned long long)n_newton,
-                                   (unsigned long long)n_disk};
+        unsigned long long c[kFindCounters] = {n_prop, n_upd, n_chi2, (unsigned long long)n_newton,
+                                               (unsigned long long)n_disk, (unsigned long long)n_guess,
+                                               (unsigned long long)n_fallback};
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
+        for (int q = 0; q < kFindCounters; ++q) {
             for (int o = 32; o > 0; o >>= 1) c[q] += __shfl_xor(c[q], o);
             if ((t & 63) == 0) atomicAdd(&a.counters[q], c[q]);
         }
@@ -1001,14 +1016,14 @@ size_t find_shared_size(int W, int S, int nl, int prec)
     return find_shared_bytes(W, S, nl, prec == KF_PREC_FP32 ? sizeof(float) : sizeof(double));
 }
 
-hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, int* out)
+hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, int* out)
 {
     const size_t lds = find_shared_size(W, S, nl, prec);
     if (prec == KF_PREC_FP32)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float, float>, W,
-                                                            lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double, double>, W,
-                                                        lds);
+        return learn ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float, float, true>, W, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float, float, false>, W, lds);
+    return learn ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double, double, true>, W, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double, double, false>, W, lds);
 }
 
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
@@ -1113,13 +1128,15 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     return off;
 }
 
-hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, hipStream_t s)
+hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, bool learn, hipStream_t s)
 {
     const size_t lds = find_shared_size(W, a.seeds_per_tile, a.n_layers, prec);
     if (prec == KF_PREC_FP32)
-        find_kernel<float, float, float><<<grid, W, lds, s>>>(a);
+        learn ? find_kernel<float, float, float, true><<<grid, W, lds, s>>>(a)
+              : find_kernel<float, float, float, false><<<grid, W, lds, s>>>(a);
     else
-        find_kernel<float, double, double><<<grid, W, lds, s>>>(a);
+        learn ? find_kernel<float, double, double, true><<<grid, W, lds, s>>>(a)
+              : find_kernel<float, double, double, false><<<grid, W, lds, s>>>(a);
     return hipGetLastError();
 }
 

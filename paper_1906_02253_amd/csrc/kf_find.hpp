@@ -7,6 +7,7 @@ namespace kfmi {
 
 constexpr int kMaxCands = 8;    // candidate slots per seed the kernel is built for
 constexpr int kMaxLayerBins = 16384;   // nbin_phi * nbin_2 of one layer (LDS histogram)
+constexpr int kFindCounters = 7;       // event counters of a finding call
 
 // One binned hit: position, sigmas, azimuth cos/sin and the caller's hit index.
 struct alignas(16) BinnedHit {
@@ -51,7 +52,8 @@ struct FindArgs {
     // scratch
     int2* bp;                     // per workgroup: [n_layers][S][kMaxCands] back-pointers
     int32_t* tile_counter;
-    unsigned long long* counters; // optional: [0] propagations, [1] updates
+    unsigned long long* counters; // optional [kFindCounters]: propagations, updates, chi2 tests,
+                                  // Newton evaluations, disk tests, learned guesses, fallbacks
     // geometry and parameters
     const kf_layer* layers;
     int n_layers;
@@ -59,6 +61,7 @@ struct FindArgs {
     int material;
     int n_tiles;
     int seeds_per_tile;
+    MlpDev mlp;                   // learned guess (KF_INIT_MLP)
 };
 
 // Device scratch of one kf_find call, carved from the context workspace.
@@ -86,7 +89,7 @@ struct FindPlan {
 size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t n_seeds,
                  int n_layers, int grid, int seeds_per_tile);
 size_t find_shared_size(int W, int S, int nl, int prec);
-hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, int* out);
+hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, int* out);
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event_off, int n_events,
@@ -94,6 +97,6 @@ hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event
 hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
                              const int32_t* event_off, int n_events, int largest_first,
                              hipStream_t s);
-hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, hipStream_t s);
+hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, bool learn, hipStream_t s);
 
 }  // namespace kfmi

@@ -6,6 +6,7 @@
 // a constant field), Sec. 3.2 (seeds provided externally).
 #include "kf_internal.hpp"
 #include "kf_math.hpp"
+#include "kf_mlp.hpp"
 
 namespace kfmi {
 
@@ -30,10 +31,12 @@ __device__ inline void store_state(T* par, C* cov, int64_t ld, int64_t i, const 
     for (int k = 0; k < 21; ++k) cov[k * ld + i] = P[k];
 }
 
-// Propagate (p, P) to layer L.  s_init < 0: straight-line start.
+// Propagate (p, P) to layer L.  s_init < 0: straight-line start; otherwise
+// the learned start with prm.mlp_max_iter evaluations before the fallback
+// to the straight-line start (counted in *fallbacks).
 template <typename T, typename C>
 __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_params& prm,
-                                   bool material, T s_init, T* s_out, int* evals)
+                                   bool material, T s_init, T* s_out, int* evals, int* fallbacks)
 {
     const T kb = T(kKappa) * T(prm.bz);
     T s;
@@ -44,9 +47,8 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
         const T r_l = T(L.r_or_z);
         T s_hi;
         if (!barrel_bracket(p[0], p[1], cph, sph, h, r_l, &s_hi)) return KF_ST_UNREACHABLE;
-        T s0 = s_init >= T(0) ? s_init : line_guess(p[0], p[1], cph, sph, r_l);
-        int st = newton_barrel(p[0], p[1], p[4], h, r_l, s0, T(0), s_hi, prm.max_newton,
-                               T(prm.newton_tol), &s, evals);
+        int st = solve_barrel(p, h, cph, sph, r_l, s_hi, prm, s_init, prm.mlp_max_iter, &s, evals,
+                              fallbacks);
         if (st) return st;
     } else {
         T st_, ct_;
@@ -122,7 +124,9 @@ __global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_
 }
 
 // ---------------------------------------------------------------- propagate
-template <typename T, typename C>
+// LEARN: every lane of the wave runs to the network call (uniform control
+// flow around the matrix-core instructions).
+template <typename T, typename C, bool LEARN>
 __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T* __restrict__ par,
                                                         C* __restrict__ cov,
                                                         uint32_t* __restrict__ status,
@@ -130,14 +134,16 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
                                                         const kf_layer* __restrict__ layers,
                                                         int n_layers, kf_params prm, int material,
                                                         float* __restrict__ path_len,
-                                                        int32_t* __restrict__ iters)
+                                                        int32_t* __restrict__ iters, MlpDev mlp)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t l = target[i];
-    uint32_t st = status[i];
+    if (!LEARN && i >= n) return;
+    const bool inb = i < n;
+    const int32_t l = inb ? target[i] : -1;
+    uint32_t st = inb ? status[i] : 0u;
     if (l >= n_layers) st |= KF_ST_BADINPUT;
-    if (l < 0 || st) {
+    const bool active = inb && l >= 0 && !(st & kFreezeMask);
+    if (!LEARN && !active) {
         status[i] = st;
         if (path_len) path_len[i] = 0.0f;
         if (iters) iters[i] = 0;
@@ -145,16 +151,36 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
     }
     T p[6];
     C P[21];
-    load_state(par, cov, ld, i, p, P);
-    const kf_layer L = layers[l];
+    kf_layer L;
+    if (active) {
+        load_state(par, cov, ld, i, p, P);
+        L = layers[l];
+    }
+    T s_init = T(-1);
+    if (LEARN) {
+        float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const bool want = active && L.kind == 0;
+        if (want) mlp_features(p, L, T(kKappa) * T(prm.bz), f);
+        const float y = mlp_wave(mlp, f);
+        if (want) s_init = T(mlp_guess(f, y));
+        if (!inb) return;
+        if (!active) {
+            status[i] = st;
+            if (path_len) path_len[i] = 0.0f;
+            if (iters) iters[i] = 0;
+            return;
+        }
+    }
     T s = T(0);
-    int ev = 0;
-    int r = propagate_to(p, P, L, prm, material != 0, T(-1), &s, &ev);
+    int ev = 0, fb = 0;
+    int r = propagate_to(p, P, L, prm, material != 0, s_init, &s, &ev, &fb);
+    if (fb) st |= KF_ST_FALLBACK;
     if (r) {
-        status[i] = st | (uint32_t)r;
+        st |= (uint32_t)r;
     } else {
         store_state(par, cov, ld, i, p, P);
     }
+    status[i] = st;
     if (path_len) path_len[i] = float(s);
     if (iters) iters[i] = ev;
 }
@@ -175,45 +201,70 @@ struct FitArgs {
     int n_layers;
     kf_params prm;
     int material;
+    MlpDev mlp;                  // learned guess (KF_INIT_MLP)
 };
 
 // Steps [k0, k1) of the fit.  init: start a fresh fit (chi2 = 0, ndf = -5).
-template <typename T, typename C, typename U>
+// LEARN: every lane of the wave walks all steps (finished lanes idle), so
+// that the network call at each step is in uniform control flow.
+template <typename T, typename C, typename U, bool LEARN>
 __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int init)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    if (!LEARN && i >= a.n) return;
+    const bool inb = i < a.n;
     const int64_t ld = a.ld;
     T* par = (T*)a.par;
     C* cov = (C*)a.cov;
     T* chi2p = (T*)a.chi2;
-    uint32_t st = init ? 0u : a.status[i];
-    int32_t ndf = init ? -5 : a.ndf[i];
-    U chi2 = init ? U(0) : U(chi2p[i]);
-    if (st) return;
+    uint32_t st = (init || !inb) ? 0u : a.status[i];
+    int32_t ndf = (init || !inb) ? -5 : a.ndf[i];
+    U chi2 = (init || !inb) ? U(0) : U(chi2p[i]);
+    bool alive = inb && !(st & kFreezeMask);
+    if (!LEARN && !alive) return;
+    const bool was_alive = alive;
     T p[6];
     C P[21];
-    load_state(par, cov, ld, i, p, P);
+    if (alive) load_state(par, cov, ld, i, p, P);
+    const T kb = T(kKappa) * T(a.prm.bz);
     bool touched = false;
     for (int k = k0; k < k1; ++k) {
-        const int32_t l = a.layer_seq ? a.layer_seq[(int64_t)k * ld + i] : k;
-        if (l < 0) break;
-        if (l >= a.n_layers) {
-            st |= KF_ST_BADINPUT;
-            break;
+        if (!LEARN && !alive) break;
+        int32_t l = -1;
+        if (alive) {
+            l = a.layer_seq ? a.layer_seq[(int64_t)k * ld + i] : k;
+            if (l < 0) {
+                alive = false;
+            } else if (l >= a.n_layers) {
+                st |= KF_ST_BADINPUT;
+                alive = false;
+            }
         }
-        const kf_layer L = a.layers[l];
-        int ev = 0;
-        int r = propagate_to(p, P, L, a.prm, a.material != 0, T(-1), (T*)nullptr, &ev);
+        kf_layer L;
+        if (alive) L = a.layers[l];
+        T s_init = T(-1);
+        if (LEARN) {
+            float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const bool want = alive && L.kind == 0;
+            if (want) mlp_features(p, L, kb, f);
+            const float y = mlp_wave(a.mlp, f);
+            if (want) s_init = T(mlp_guess(f, y));
+        }
+        if (!alive) continue;
+        int ev = 0, fb = 0;
+        int r = propagate_to(p, P, L, a.prm, a.material != 0, s_init, (T*)nullptr, &ev, &fb);
         touched = true;
+        if (fb) st |= KF_ST_FALLBACK;
         if (r) {
             st |= (uint32_t)r;
-            break;
+            alive = false;
+            continue;
         }
         const int32_t hi = a.hit_idx[(int64_t)k * ld + i];
         if (hi >= a.n_hits) {
             st |= KF_ST_BADINPUT;
-            break;
+            alive = false;
+            continue;
         }
         if (hi >= 0) {
             HitFrame<U> f = hit_frame<U>(a.hx[hi], a.hy[hi], a.hz[hi], a.hsu[hi], a.hsv[hi]);
@@ -221,7 +272,8 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
             r = kf_update<T, C, U>(p, P, f, L.kind, &c2);
             if (r) {
                 st |= (uint32_t)r;
-                break;
+                alive = false;
+                continue;
             }
             // rounded to storage precision every step, so one launch per step
             // and one launch for all steps give identical results
@@ -229,6 +281,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
             ndf += 2;
         }
     }
+    if (!was_alive) return;
     // on failure the registers hold the last good state (a failed solve or
     // update leaves them untouched)
     if (touched) store_state(par, cov, ld, i, p, P);
@@ -270,22 +323,24 @@ hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* targ
     if (t->n == 0) return hipSuccess;
     const int prec = flags & KF_PREC_MASK;
     const int material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    const bool learn = (flags & KF_INIT_MLP) != 0;
+    const MlpDev m = ctx->mlp.dev();
     dim3 g = grid_for(t->n, 256);
-    if (prec == KF_PREC_FP64)
-        propagate_kernel<double, double><<<g, 256, 0, s>>>(t->n, t->ld, (double*)t->par,
-                                                           (double*)t->cov, t->status, target,
-                                                           ctx->d_layers, ctx->n_layers, ctx->params,
-                                                           material, path_len, iters);
-    else if (prec == KF_PREC_FP32)
-        propagate_kernel<float, float><<<g, 256, 0, s>>>(t->n, t->ld, (float*)t->par,
-                                                         (float*)t->cov, t->status, target,
-                                                         ctx->d_layers, ctx->n_layers, ctx->params,
-                                                         material, path_len, iters);
-    else
-        propagate_kernel<float, double><<<g, 256, 0, s>>>(t->n, t->ld, (float*)t->par,
-                                                          (double*)t->cov, t->status, target,
-                                                          ctx->d_layers, ctx->n_layers, ctx->params,
-                                                          material, path_len, iters);
+#define KF_PROP(TT, CC, LL)                                                                       \
+    propagate_kernel<TT, CC, LL><<<g, 256, 0, s>>>(t->n, t->ld, (TT*)t->par, (CC*)t->cov, t->status, \
+                                                   target, ctx->d_layers, ctx->n_layers, ctx->params, \
+                                                   material, path_len, iters, m)
+    if (prec == KF_PREC_FP64) {
+        if (learn) KF_PROP(double, double, true);
+        else KF_PROP(double, double, false);
+    } else if (prec == KF_PREC_FP32) {
+        if (learn) KF_PROP(float, float, true);
+        else KF_PROP(float, float, false);
+    } else {
+        if (learn) KF_PROP(float, double, true);
+        else KF_PROP(float, double, false);
+    }
+#undef KF_PROP
     return hipGetLastError();
 }
 
@@ -313,6 +368,8 @@ hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const i
     a.n_layers = ctx->n_layers;
     a.prm = ctx->params;
     a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    a.mlp = ctx->mlp.dev();
+    const bool learn = (flags & KF_INIT_MLP) != 0;
     const int prec = flags & KF_PREC_MASK;
     dim3 g = grid_for(t->n, 256);
     const bool per_layer = (flags & KF_PER_LAYER) != 0;
@@ -321,12 +378,16 @@ hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const i
         const int k0 = per_layer ? k : 0;
         const int k1 = per_layer ? k + 1 : max_steps;
         const int init = k == 0;
-        if (prec == KF_PREC_FP64)
-            fit_kernel<double, double, double><<<g, 256, 0, s>>>(a, k0, k1, init);
-        else if (prec == KF_PREC_FP32)
-            fit_kernel<float, float, float><<<g, 256, 0, s>>>(a, k0, k1, init);
-        else
-            fit_kernel<float, double, double><<<g, 256, 0, s>>>(a, k0, k1, init);
+        if (prec == KF_PREC_FP64) {
+            if (learn) fit_kernel<double, double, double, true><<<g, 256, 0, s>>>(a, k0, k1, init);
+            else fit_kernel<double, double, double, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+        } else if (prec == KF_PREC_FP32) {
+            if (learn) fit_kernel<float, float, float, true><<<g, 256, 0, s>>>(a, k0, k1, init);
+            else fit_kernel<float, float, float, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+        } else {
+            if (learn) fit_kernel<float, double, double, true><<<g, 256, 0, s>>>(a, k0, k1, init);
+            else fit_kernel<float, double, double, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -21,6 +21,34 @@ struct Workspace {
     void release();
 };
 
+// Device copies of the learned guess's weights read by the forward pass
+// (rounded to bf16).
+struct MlpDev {
+    const uint16_t* w1;    // [64][16] W1 [out][in] twice along K (high and low input parts)
+    const uint16_t* w2;    // [64][64] W2 [out][in]
+    const uint16_t* w2t;   // [64][64] W2 transposed [in][out]
+    const float* bias;     // [193] b1 [0,64), b2 [64,128), w3 [128,192), b3 [192]
+};
+
+// Device state of the network: FP32 master weights and Adam moments (flat
+// parameter order), and the copies the forward pass reads.
+struct MlpBuffers {
+    float* master = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    float* bias = nullptr;
+    uint16_t* w1 = nullptr;
+    uint16_t* w2 = nullptr;
+    uint16_t* w2t = nullptr;
+    MlpDev dev() const { return MlpDev{w1, w2, w2t, bias}; }
+};
+
+// One Adam update: step size, moment decays, epsilon and the bias
+// corrections 1 / (1 - beta^t) of this step.
+struct AdamStep {
+    float lr, beta1, beta2, eps, c1, c2;
+};
+
 // The captured finding pass of kf_find_batched: seeding, seed fit, binning,
 // seed order and the finding kernel as child graphs, separated by event-record
 // nodes whose events are swapped per launch (timing or not).
@@ -48,7 +76,7 @@ struct kf_ctx {
     int max_lds = 0;                  // LDS bytes a workgroup may use
     int find_width = 64;              // lanes per workgroup of the finding kernel
     int find_largest_first = 0;       // tile order
-    int occ_cache[2][9] = {};         // resident workgroups per CU by (precision, log2 width)
+    int occ_cache[2][2][9] = {};      // resident workgroups per CU by (learned, precision, log2 width)
     int timing_cap = 0;               // event sets available (0: timing off)
     int timing_used = 0;              // event sets recorded since kf_set_timing
     int timing_n = 0;                 // sets requested by kf_set_timing
@@ -56,6 +84,11 @@ struct kf_ctx {
     hipStream_t cap_stream = nullptr; // private stream the batched pass is captured on
     hipEvent_t idle_ev[kfmi::kPhaseEvents] = {};  // record targets of an untimed graph launch
     kfmi::FindGraph fg;
+    void* mlp_mem = nullptr;          // device block holding the network buffers
+    kfmi::MlpBuffers mlp;             // views into mlp_mem
+    bool mlp_loaded = false;
+    int64_t mlp_step = 0;             // Adam steps taken since kf_mlp_load
+    kfmi::Workspace mlp_ws;           // partial gradients of a training step
 };
 
 namespace kfmi {

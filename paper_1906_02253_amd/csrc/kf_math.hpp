@@ -410,18 +410,15 @@ KF_HD inline int kf_update(T p[6], C P[21], const HitFrame<U>& f, int kind, U* c
     return fin ? 0 : KF_ST_NAN;
 }
 
-// Next surface: whichever comes first along the helix, the next barrel
-// outward (smallest radius above the current one, reachable, crossing inside
-// its z extent) or the first disk ahead whose crossing is inside its radial
-// extent.  Returns the layer (or -1) and the path length.
+// Status bits that freeze a track (everything except the informational
+// fallback bit of the learned guess).
+constexpr uint32_t kFreezeMask = ~(uint32_t)KF_ST_FALLBACK;
+
+// The next barrel outward: smallest radius above rho + kNextBarrelEps, or -1.
 template <typename T>
-KF_HD inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_params& prm, T kb,
-                          T* s_out, uint32_t* st, int* newton_evals, int* disk_evals)
+KF_HD inline int next_barrel(const T p[6], const kf_layer* L, int nl)
 {
     const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
-    // only surfaces reached within half a turn in the transverse plane
-    const T hh = Tr<T>::abs_(kb * p[3]);
-    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
     int bl = -1;
     T rbl = T(0);
     for (int l = 0; l < nl; ++l) {
@@ -432,6 +429,49 @@ KF_HD inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_para
             rbl = r;
         }
     }
+    return bl;
+}
+
+// Propagate-to-radius solve.  Plain: bracketed Newton from the straight-line
+// start s0.  With a learned guess s_guess >= 0 that differs from s0 by more
+// than kLearnedGate newton tolerances (the network predicts a curved path the
+// straight line misses), the solve starts at s_guess with learned_it
+// evaluations; if those do not converge it counts a fallback and runs the
+// plain solve.  Smaller predicted corrections keep the straight-line start,
+// exact for straight tracks.
+constexpr double kLearnedGate = 100.0;
+
+template <typename T>
+KF_HD inline int solve_barrel(const T p[6], T h, T cph, T sph, T r_l, T s_hi, const kf_params& prm,
+                              T s_guess, int learned_it, T* s, int* evals, int* fallbacks)
+{
+    const T s0 = line_guess(p[0], p[1], cph, sph, r_l);
+    if (s_guess >= T(0) && learned_it > 0 &&
+        Tr<T>::abs_(s_guess - s0) > T(kLearnedGate * prm.newton_tol)) {
+        if (!newton_barrel(p[0], p[1], p[4], h, r_l, s_guess, T(0), s_hi, learned_it,
+                           T(prm.newton_tol), s, evals))
+            return 0;
+        ++*fallbacks;
+    }
+    return newton_barrel(p[0], p[1], p[4], h, r_l, s0, T(0), s_hi, prm.max_newton,
+                         T(prm.newton_tol), s, evals);
+}
+
+// Next surface: whichever comes first along the helix, the next barrel
+// outward (smallest radius above the current one, reachable, crossing inside
+// its z extent) or the first disk ahead whose crossing is inside its radial
+// extent.  Returns the layer (or -1) and the path length.  s_guess >= 0: the
+// learned start of the barrel solve (learned_it evaluations, then fallback).
+template <typename T>
+KF_HD inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_params& prm, T kb,
+                          T* s_out, uint32_t* st, int* newton_evals, int* disk_evals,
+                          T s_guess = T(-1), int learned_it = 0, int* fallbacks = nullptr)
+{
+    // only surfaces reached within half a turn in the transverse plane
+    const T hh = Tr<T>::abs_(kb * p[3]);
+    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
+    const int bl = next_barrel(p, L, nl);
+    const T rbl = bl >= 0 ? T(L[bl].r_or_z) : T(0);
     T best_s = T(1e30);
     int best_l = -1;
     T sth, cth;
@@ -443,9 +483,11 @@ KF_HD inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_para
         T s_hi;
         if (barrel_bracket(p[0], p[1], cph, sph, h, rbl, &s_hi)) {
             T s;
-            const T s0 = line_guess(p[0], p[1], cph, sph, rbl);
-            if (newton_barrel(p[0], p[1], p[4], h, rbl, s0, T(0), s_hi, prm.max_newton,
-                              T(prm.newton_tol), &s, newton_evals)) {
+            int fb = 0;
+            const int r = solve_barrel(p, h, cph, sph, rbl, s_hi, prm, s_guess, learned_it, &s,
+                                       newton_evals, &fb);
+            if (fallbacks) *fallbacks += fb;
+            if (r) {
                 *st |= KF_ST_NOCONV;
                 return -1;
             }

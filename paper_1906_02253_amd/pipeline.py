@@ -31,8 +31,9 @@ class FindProblem:
         self.out = B.Tracks(self.n_seeds, ld, prec)
         self.out_hits = torch.full((max(self.n_seeds, 1), ctx.n_layers), -1, dtype=torch.int32,
                                    device=device)
-        # propagations, updates, chi2 tests, Newton evaluations, disk tests
-        self.counters = torch.zeros(5, dtype=torch.int64, device=device)
+        # propagations, updates, chi2 tests, Newton evaluations, disk tests,
+        # learned guesses, learned guesses that fell back
+        self.counters = torch.zeros(B.N_COUNTERS, dtype=torch.int64, device=device)
 
     def seed_fit(self, flags=0):
         self.ctx.seed(self.hits, self.seed_hits, self.seeds, flags)
