@@ -108,8 +108,9 @@ def build_fit_set(n_total, n_unique=1_000_000, chunk=250_000, seed=3):
     return geom, ld, hits, lseq, hidx.astype(np.int32)
 
 
-def run_fit(K, torch, n, reps=5):
-    """Fused fit and per-layer fit of n tracks: kernel ms (HIP events) and rates."""
+def run_fit(K, torch, n, w=None, reps=5):
+    """Fused fit (plain and, given weights w, learned start) and per-layer fit
+    of n tracks: kernel ms (HIP events) and rates."""
     geom, ld, hits_np, lseq_np, hidx_np = build_fit_set(n)
     hits = K.Hits(hits_np["x"], hits_np["y"], hits_np["z"], hits_np["su"], hits_np["sv"],
                   hits_np["layer"])
@@ -121,7 +122,11 @@ def run_fit(K, torch, n, reps=5):
     n_steps = int((lseq_np[:, :n] >= 0).sum())
     stream = torch.cuda.current_stream()
     out = {}
-    for name, flags in (("fused", 0), ("per_layer", K.PER_LAYER)):
+    legs = [("fused", 0), ("per_layer", K.PER_LAYER)]
+    if w is not None:
+        ctx.mlp_load(w)
+        legs.append(("fused_learned", K.INIT_MLP))
+    for name, flags in legs:
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(reps)]
         for r in range(-1, reps):
@@ -137,11 +142,71 @@ def run_fit(K, torch, n, reps=5):
     return {"workload": f"fit of {n} tracks, precision-workload mix, 10 barrel layers, mixed precision",
             "kf_steps": n_steps,
             "fused_kernel_ms": out["fused"], "fused_steps_per_s": n_steps / (out["fused"] * 1e-3),
+            "fused_learned_kernel_ms": out.get("fused_learned"),
+            "fused_learned_steps_per_s": n_steps / (out["fused_learned"] * 1e-3)
+            if "fused_learned" in out else None,
             "per_layer_ms": out["per_layer"],
             "per_layer_steps_per_s": n_steps / (out["per_layer"] * 1e-3),
             "per_layer_hbm": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": gbs / HBM_PEAK_GBS,
                               "bytes_per_step": PER_LAYER_BYTES_PER_STEP}}
+
+
+def timed_pass(torch, ctx, fp, flags, steps, warmup):
+    """Warm-up, then `steps` replays of the captured finding pass; returns
+    (wall ms per pass, mean phase ms (seed fit, binning, seed order, finding
+    kernel) from the HIP events inside the graph, counters per pass)."""
+    for _ in range(warmup):
+        fp.run_batched(flags)
+    torch.cuda.synchronize()
+    c0 = fp.counters.clone()
+    ctx.set_timing(steps)
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    for _ in range(steps):
+        fp.run_batched(flags)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - start
+    phases, _ = ctx.timings()
+    ctx.set_timing(0)
+    cnt = ((fp.counters - c0).double() / steps).cpu().numpy()
+    return wall * 1e3 / steps, phases, cnt
+
+
+def train_guess(K, torch, E):
+    """Trains the learned start on the device: 1e6 pairs from the plain
+    propagator at the precision workload's distribution, 20 epochs of batch
+    4096, Adam 1e-3.  Returns (weights, report)."""
+    from paper_1906_02253_amd import learned
+    t0 = time.time()
+    geom, states, tl = E.propagation_pairs(n_pairs=1_000_000, seed=4)
+    ctx = K.Context(geom)
+    ps = learned.PairSet(ctx, states, tl)
+    tr, va, te = learned.split_rows(ps.ok_rows, seed=4)
+    torch.cuda.synchronize()
+    t_data = time.time() - t0
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    losses = learned.train(ctx, ps, tr, E.mlp_init(4), epochs=20, batch=4096, lr=1e-3, seed=4)
+    b.record()
+    torch.cuda.synchronize()
+    train_ms = a.elapsed_time(b)
+    val = learned.eval_loss(ctx, ps, va)
+    r = learned.compare_starts(ctx, states[te], tl[te])
+    ok = r["plain"]["status"] == 0
+    it_p, it_l = r["plain"]["iters"][ok], r["learned"]["iters"][ok]
+    n_steps = losses.shape[0]
+    rep = {"pairs": int(ps.n), "train_rows": int(tr.size), "epochs": 20, "batch": 4096,
+           "adam_steps": int(n_steps), "train_ms": train_ms,
+           "train_rows_per_s": n_steps * 4096 / (train_ms * 1e-3),
+           "train_tflops": n_steps * 4096 * 3 * 2 * 4672 / (train_ms * 1e-3) / 1e12,
+           "final_train_loss": float(losses[-50:].mean()), "validation_loss": val,
+           "held_out_propagations": int(ok.sum()),
+           "r_evals_plain_mean": float(it_p.mean()), "r_evals_plain_p99": float(np.percentile(it_p, 99)),
+           "r_evals_learned_mean": float(it_l.mean()),
+           "r_evals_learned_p99": float(np.percentile(it_l, 99)),
+           "data_prep_s": t_data}
+    return ctx.mlp_get(), rep
 
 
 def oracle_find_all(oracle, geom, evs, inp, threads):
@@ -194,20 +259,8 @@ def main():
     width, largest_first = ctx.find_config()
     # the timed pass: seeding, seed fit, binning, seed order and the finding
     # kernel replayed as one captured graph
-    for _ in range(args.warmup):
-        fp.run_batched()
-    torch.cuda.synchronize()
-    c0 = fp.counters.clone()
-    ctx.set_timing(args.steps)
-    torch.cuda.synchronize()
-    start = time.perf_counter()
-    for _ in range(args.steps):
-        fp.run_batched()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - start
-    (ms_seed, ms_bin, ms_sort, ms_kernel), n_rec = ctx.timings()
-    cnt = ((fp.counters - c0).double() / args.steps).cpu().numpy()
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step, (ms_seed, ms_bin, ms_sort, ms_kernel), cnt = timed_pass(
+        torch, ctx, fp, 0, args.steps, args.warmup)
     kf_steps = 3 * n_seeds + cnt[0]
     value = kf_steps / (ms_per_step * 1e-3)
     flops = find_flops(cnt, oc)
@@ -247,8 +300,28 @@ def main():
                       "find_kernel": ms_kernel},
     }
 
+    # learned start: train on the device, then the same timed pass
+    w, rep = train_guess(K, torch, E)
+    ctx.mlp_load(w)
+    if width < 64:
+        ctx.set_find_config(64, largest_first)
+    ms_l, ph_l, cnt_l = timed_pass(torch, ctx, fp, K.INIT_MLP, args.steps, args.warmup)
+    steps_l = 3 * n_seeds + cnt_l[0]
+    rep.update({"steps_per_s": steps_l / (ms_l * 1e-3), "ms_per_step": ms_l,
+                "find_kernel_ms": ph_l[3], "kf_steps_per_pass": steps_l,
+                "r_evals_per_propagation_plain": cnt[3] / cnt[0],
+                "r_evals_per_propagation_learned": cnt_l[3] / cnt_l[0],
+                "guesses_per_pass": cnt_l[5], "fallbacks_per_pass": cnt_l[6],
+                "fallback_rate": cnt_l[6] / max(cnt_l[5], 1.0),
+                "mlp_tflops_in_find": cnt_l[5] * 2 * 4672 / (ph_l[3] * 1e-3) / 1e12})
+    result["learned_init"] = rep
+    print(f"# learned start: {ms_l:.3f} ms/step ({rep['steps_per_s']:.3e} steps/s), find kernel "
+          f"{ph_l[3]:.3f} ms; r(s) evaluations per propagation {cnt[3] / cnt[0]:.3f} plain, "
+          f"{cnt_l[3] / cnt_l[0]:.3f} learned; training {rep['train_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
+
     if not args.no_fit:
-        result["fit"] = run_fit(K, torch, args.fit_tracks)
+        result["fit"] = run_fit(K, torch, args.fit_tracks, w)
         print(f"# fit: {result['fit']['fused_steps_per_s']:.3e} steps/s fused", file=sys.stderr,
               flush=True)
 
