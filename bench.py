@@ -52,6 +52,29 @@ def parse():
     return ap.parse_args()
 
 
+# HBM bytes per launch from the committed rocprofv3 counter summary, used
+# only while the finding kernel's sources are the ones it was measured on
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "find_pass_batch64_hbm_counters.json")
+KERNEL_SOURCES = ["kf_find.hip", "kf_find.hpp", "kf_math.hpp", "kf_mlp.hpp", "kf_internal.hpp"]
+
+
+def measured_traffic(kernel):
+    import hashlib
+    try:
+        with open(TRAFFIC_JSON) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1906_02253_amd", "csrc", s), "rb") as f:
+            h.update(f.read())
+    if d.get("kernel_source_hash") != h.hexdigest()[:16]:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return k["hbm_bytes"] if k else None
+
+
 def find_flops(cnt, oc):
     """Algorithmic flops of the finding kernel from its event counters and the
     operation counts of its arithmetic (special-function calls counted as one)."""
@@ -152,6 +175,22 @@ def run_fit(K, torch, n, w=None, reps=5):
                               "bytes_per_step": PER_LAYER_BYTES_PER_STEP}}
 
 
+def copy_probe(torch, mib=1024, reps=5):
+    """A plain streaming kernel of known size (read mib MiB, write mib MiB):
+    its bandwidth, and the reference the HBM byte counters are scaled by."""
+    x = torch.ones(mib * 2 ** 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 2.0, out=y)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.mul(x, 2.0, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"bytes": 2 * mib * 2 ** 20, "ms": ms, "gbs": 2 * mib * 2 ** 20 / (ms * 1e-3) / 1e9}
+
+
 def timed_pass(torch, ctx, fp, flags, steps, warmup):
     """Warm-up, then `steps` replays of the captured finding pass; returns
     (wall ms per pass, mean phase ms (seed fit, binning, seed order, finding
@@ -245,6 +284,7 @@ def main():
     print(f"# batch: {len(evs)} events, {n_seeds} seeds, {inp['x'].shape[0]} hits "
           f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
 
+    probe = copy_probe(torch)
     ctx = K.Context(geom)
     fp = pipeline.FindProblem(ctx, inp)
     fp.run()
@@ -293,11 +333,13 @@ def main():
                    "launch": "hipGraph replay (kf_find_batched)", "precision": "mixed",
                    "init": "plain"},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": tflops / VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic("kfmi::find_kernel<float, double, double, false>"),
                      "kernel": "find_kernel<float,double,double>", "kernel_ms": ms_kernel,
                      "flops_per_launch": flops, "events_per_launch": cnt.tolist()},
         "phases_ms": {"seed_and_seed_fit": ms_seed, "binning": ms_bin, "seed_order": ms_sort,
                       "find_kernel": ms_kernel},
+        "copy_probe": probe,
     }
 
     # learned start: train on the device, then the same timed pass

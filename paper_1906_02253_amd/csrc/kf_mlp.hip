@@ -202,22 +202,31 @@ __device__ inline void publish_param(int p, float w, uint16_t* w1, uint16_t* w2,
 
 // mode 0: write the summed gradient to grad_out and the loss to loss_out[0];
 // mode 1: Adam step on the master weights and republish the bf16 copies.
+// A workgroup takes 64 consecutive parameters; its four waves sum every
+// fourth partial (coalesced across the parameters), then combine in LDS.
+constexpr int kReduceParams = 64;
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int n_waves,
                                                          const float* __restrict__ loss_part, int batch,
                                                          int mode, MlpBuffers mb, AdamStep ad,
                                                          float* __restrict__ grad_out,
                                                          float* __restrict__ loss_out)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x < 64 && loss_out) {
+    __shared__ float part[4][kReduceParams];
+    const int ln = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && grp == 0 && loss_out) {
         float s = 0.0f;
-        for (int w = threadIdx.x; w < n_waves; w += 64) s += loss_part[w];
+        for (int w = ln; w < n_waves; w += 64) s += loss_part[w];
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (threadIdx.x == 0) loss_out[0] = s / float(batch);
+        if (ln == 0) loss_out[0] = s / float(batch);
     }
-    if (p >= kMlpParams) return;
-    float gsum = 0.0f;
-    for (int w = 0; w < n_waves; ++w) gsum += partial[(size_t)w * kMlpParams + p];
+    const int p = blockIdx.x * kReduceParams + ln;
+    float gs = 0.0f;
+    if (p < kMlpParams)
+        for (int w = grp; w < n_waves; w += 4) gs += partial[(size_t)w * kMlpParams + p];
+    part[grp][ln] = gs;
+    __syncthreads();
+    if (grp != 0 || p >= kMlpParams) return;
+    const float gsum = part[0][ln] + part[1][ln] + part[2][ln] + part[3][ln];
     if (mode == 0) {
         grad_out[p] = gsum;
         return;
@@ -281,8 +290,9 @@ hipError_t launch_mlp_step(const MlpBuffers& mb, const float* feats, const float
                                                    partial, loss_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    mlp_reduce_kernel<<<nblk(kMlpParams, 256), 256, 0, s>>>(partial, n_waves, loss_part, batch, mode,
-                                                             mb, ad, grad_out, loss_out);
+    mlp_reduce_kernel<<<nblk(kMlpParams, kReduceParams), 256, 0, s>>>(partial, n_waves, loss_part,
+                                                                       batch, mode, mb, ad, grad_out,
+                                                                       loss_out);
     return hipGetLastError();
 }
 
