@@ -407,7 +407,6 @@ struct FindShared {
     int32_t* nchild;    // [W]
     int8_t* sel;        // [S][kMaxCands][2]  (parent slot, child index)
     int32_t* nsel;      // [S]
-    uint8_t* ptr;       // [S][kMaxCands] merge cursors
     kf_layer* layers;   // [n_layers]
     int32_t* misc;      // [4] tile id
     // cooperative window scan, per lane (owner of a window) and per wave
@@ -438,7 +437,6 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
     b += sizeof(kf_layer) * nl;
     b += sizeof(int32_t) * 4;
     b += 2 * S * kMaxCands;
-    b += S * kMaxCands;
     b = (b + 15) & ~size_t(15);
     const size_t nw = (W + 63) / 64;
     b += sizeof(float) * 5 * W;
@@ -489,8 +487,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         q += sizeof(int32_t) * 4;
         sh.sel = (int8_t*)q;
         q += 2 * S * kMaxCands;
-        sh.ptr = (uint8_t*)q;
-        q += S * kMaxCands;
         q = smem + (((size_t)(q - smem) + 15) & ~size_t(15));
         const int nw = (W + 63) / 64;
         sh.own = (float*)q;
@@ -861,46 +857,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             }
             __syncthreads();
             // ---- a5: per-seed selection (k-way merge of per-parent sorted children)
+            // by the seed's slot-0 lane, the parents' list heads held in
+            // registers: one LDS read per pick after the initial loads
             if (valid && slot == 0) {
                 const int base = s_loc * MC;
-                int npar = 0;
-                for (int j = 0; j < MC; ++j) {
-                    if (sh.nchild[base + j] < 0) break;
-                    ++npar;
+                int nk[kMaxCands], nh0[kMaxCands], cur[kMaxCands], hnh[kMaxCands];
+                float c0[kMaxCands], hc[kMaxCands];
+#pragma unroll
+                for (int j = 0; j < kMaxCands; ++j) {
+                    nk[j] = j < MC ? sh.nchild[base + j] : -1;
+                    nh0[j] = j < MC ? sh.meta[0 * W + base + j] : 0;
+                    c0[j] = j < MC ? sh.pred[6 * W + base + j] : 0.0f;
+                    cur[j] = 0;
                 }
-                uint8_t* cur = sh.ptr + s_loc * kMaxCands;
-                for (int j = 0; j < npar; ++j) cur[j] = 0;
+                // parents fill slots 0, 1, ...: the first empty slot ends them
+                bool stop = false;
+#pragma unroll
+                for (int j = 0; j < kMaxCands; ++j) {
+                    stop = stop || nk[j] < 0;
+                    if (stop) nk[j] = -1;
+                    // head: the best child (nk == 0: the child without a hit)
+                    hnh[j] = nk[j] > 0 ? nh0[j] + 1 : nh0[j];
+                    hc[j] = nk[j] > 0 ? c0[j] + sh.cchi2[0 * W + base + (j < MC ? j : 0)] : c0[j];
+                }
                 int nsel = 0;
                 for (int r = 0; r < MC; ++r) {
                     int bj = -1, bnh = 0;
                     float bc = 0.0f;
-                    for (int j = 0; j < npar; ++j) {
-                        const int tj = base + j;
-                        const int nk = sh.nchild[tj];
-                        const int c = cur[j];
-                        if (c > nk) continue;          // list exhausted (hits + the extra child)
-                        const int nh0 = sh.meta[0 * W + tj];
-                        const float c0 = sh.pred[6 * W + tj];
-                        int knh;
-                        float kc;
-                        if (c < nk) {
-                            knh = nh0 + 1;
-                            kc = c0 + sh.cchi2[c * W + tj];
-                        } else {
-                            knh = nh0;
-                            kc = c0;
-                        }
-                        if (bj < 0 || knh > bnh || (knh == bnh && kc < bc)) {
+#pragma unroll
+                    for (int j = 0; j < kMaxCands; ++j) {
+                        const bool live_j = nk[j] >= 0 && cur[j] <= nk[j];
+                        if (live_j && (bj < 0 || hnh[j] > bnh || (hnh[j] == bnh && hc[j] < bc))) {
                             bj = j;
-                            bnh = knh;
-                            bc = kc;
+                            bnh = hnh[j];
+                            bc = hc[j];
                         }
                     }
                     if (bj < 0) break;
+                    int c = 0, n = 0, h0 = 0;
+                    float cc0 = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < kMaxCands; ++j)
+                        if (j == bj) {
+                            c = cur[j];
+                            n = nk[j];
+                            h0 = nh0[j];
+                            cc0 = c0[j];
+                        }
                     sh.sel[(s_loc * kMaxCands + r) * 2 + 0] = (int8_t)bj;
-                    sh.sel[(s_loc * kMaxCands + r) * 2 + 1] = (int8_t)cur[bj];
-                    cur[bj]++;
+                    sh.sel[(s_loc * kMaxCands + r) * 2 + 1] = (int8_t)c;
                     ++nsel;
+                    // advance the winner's list and load its next head
+                    const int cn = c + 1;
+                    const int nnh = cn < n ? h0 + 1 : h0;
+                    const float nc = cn < n ? cc0 + sh.cchi2[cn * W + base + bj] : cc0;
+#pragma unroll
+                    for (int j = 0; j < kMaxCands; ++j)
+                        if (j == bj) {
+                            cur[j] = cn;
+                            hnh[j] = nnh;
+                            hc[j] = nc;
+                        }
                 }
                 sh.nsel[s_loc] = nsel;
             }
