@@ -129,7 +129,7 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
         return fail(ctx, KF_EINVAL, "%s: null seed_event, seed_hits or out_hits", what);
     const int W = ctx->find_width;
     const int MC = ctx->params.max_cands;
-    const int S = W / MC;
+    const int S = kfmi::seeds_per_wg(W, MC);
     const int nl = ctx->n_layers;
     kfmi::FindPlan& pl = L->pl;
     int64_t per_event = 0;
@@ -390,7 +390,7 @@ int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first)
     if (!ctx) return fail(nullptr, KF_EINVAL, "kf_set_find_config: null context");
     if (width != 32 && width != 64 && width != 128 && width != 256)
         return fail(ctx, KF_EINVAL, "kf_set_find_config: width must be 32, 64, 128 or 256");
-    if (width / ctx->params.max_cands < 1)
+    if (kfmi::seeds_per_wg(width, ctx->params.max_cands) < 1)
         return fail(ctx, KF_EINVAL, "kf_set_find_config: width below max_cands");
     ctx->find_width = width;
     ctx->find_largest_first = largest_first ? 1 : 0;
@@ -606,8 +606,9 @@ int kf_autotune(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int3
     for (int c = 0; c < NC; ++c) {
         best_ms[c] = -1.0f;
         const int w = widths[c / 2];
-        fits[c] = w / ctx->params.max_cands >= 1 && !((flags & KF_INIT_MLP) && w < 64) &&
-                  kfmi::find_shared_size(w, w / ctx->params.max_cands, ctx->n_layers,
+        fits[c] = kfmi::seeds_per_wg(w, ctx->params.max_cands) >= 1 &&
+                  !((flags & KF_INIT_MLP) && w < 64) &&
+                  kfmi::find_shared_size(w, kfmi::seeds_per_wg(w, ctx->params.max_cands), ctx->n_layers,
                                          flags & KF_PREC_MASK) <= (size_t)ctx->max_lds;
     }
     // configurations are visited round-robin, reps rounds, each call timed

@@ -399,8 +399,8 @@ __device__ inline void wave_fence()
 // LDS layout of one workgroup (W lanes), all arrays lane-minor
 template <typename C>
 struct FindShared {
-    C* predc;           // [21][W]  predicted (or frozen) covariance
-    float* pred;        // [7][W]   predicted (or frozen) par 6, chi2
+    C* posc;            // [6][W]   predicted position covariance P00 P01 P02 P11 P12 P22
+    float* pred;        // [4][W]   predicted (or frozen) x, y, z and chi2
     int32_t* meta;      // [4][W]   nhits, misses, status, (done | (layer + 1) << 8)
     float* cchi2;       // [kMaxCands][W]  accepted hit chi2, ascending
     int32_t* cbidx;     // [kMaxCands][W]  binned index of those hits
@@ -426,8 +426,8 @@ constexpr int kAcc = 64 * kScanBatch;
 __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t csize)
 {
     size_t b = 0;
-    b += csize * 21 * W;
-    b += sizeof(float) * 7 * W;
+    b += csize * 6 * W;
+    b += sizeof(float) * 4 * W;
     b += sizeof(int32_t) * 4 * W;
     b += sizeof(float) * kMaxCands * W;
     b += sizeof(int32_t) * kMaxCands * W;
@@ -466,10 +466,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     FindShared<C> sh;
     {
         unsigned char* q = smem;
-        sh.predc = (C*)q;
-        q += sizeof(C) * 21 * W;
+        sh.posc = (C*)q;
+        q += sizeof(C) * 6 * W;
         sh.pred = (float*)q;
-        q += sizeof(float) * 7 * W;
+        q += sizeof(float) * 4 * W;
         sh.meta = (int32_t*)q;
         q += sizeof(int32_t) * 4 * W;
         sh.cchi2 = (float*)q;
@@ -505,9 +505,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     }
     const int t = threadIdx.x;
     for (int l = t; l < nl; l += W) sh.layers[l] = a.layers[l];
-    const int s_loc = t / MC;
-    const int slot = t - s_loc * MC;
-    const bool lane_ok = s_loc < S;
+    // seeds never straddle waves: wave w holds seeds w*SPW .. w*SPW + SPW - 1
+    const int SPW = seeds_per_wave(W, MC);
+    const int ln64 = t & 63;
+    const int s_loc = (t >> 6) * SPW + ln64 / MC;
+    const int slot = ln64 % MC;
+    const bool lane_ok = ln64 / MC < SPW && s_loc < S;
+    const int lbase = t - slot;             // lane of this seed's slot 0
     const T kb = T(kKappa) * T(a.prm.bz);
     const float cut = float(a.prm.chi2_cut);
     unsigned long long n_prop = 0, n_upd = 0, n_chi2 = 0;
@@ -619,10 +623,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             // lane inserts its own into its sorted list.
             if (lane_ok) {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) sh.pred[k * W + t] = float(p[k]);
-#pragma unroll
-                for (int k = 0; k < 21; ++k) sh.predc[k * W + t] = P[k];
-                sh.pred[6 * W + t] = chi2;
+                for (int k = 0; k < 3; ++k) sh.pred[k * W + t] = float(p[k]);
+                sh.pred[3 * W + t] = chi2;
+                sh.posc[0 * W + t] = P[pk(0, 0)];
+                sh.posc[1 * W + t] = P[pk(0, 1)];
+                sh.posc[2 * W + t] = P[pk(0, 2)];
+                sh.posc[3 * W + t] = P[pk(1, 1)];
+                sh.posc[4 * W + t] = P[pk(1, 2)];
+                sh.posc[5 * W + t] = P[pk(2, 2)];
             }
             float lc2[kMaxCands];
             int32_t lid[kMaxCands], lbi[kMaxCands];
@@ -793,10 +801,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                                     f.vu = U(r0[q].w) * U(r0[q].w);
                                     f.vv = U(r1[q].x) * U(r1[q].x);
                                     const U c2u = hit_chi2_pos<U>(
-                                        U(ox), U(oy), U(oz), U(sh.predc[pk(0, 0) * W + ot]),
-                                        U(sh.predc[pk(0, 1) * W + ot]), U(sh.predc[pk(0, 2) * W + ot]),
-                                        U(sh.predc[pk(1, 1) * W + ot]), U(sh.predc[pk(1, 2) * W + ot]),
-                                        U(sh.predc[pk(2, 2) * W + ot]), f, kind);
+                                        U(ox), U(oy), U(oz), U(sh.posc[0 * W + ot]),
+                                        U(sh.posc[1 * W + ot]), U(sh.posc[2 * W + ot]),
+                                        U(sh.posc[3 * W + ot]), U(sh.posc[4 * W + ot]),
+                                        U(sh.posc[5 * W + ot]), f, kind);
                                     ++n_chi2;
                                     ok = c2u < U(cut);
                                     c2f = float(c2u);
@@ -860,14 +868,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             // by the seed's slot-0 lane, the parents' list heads held in
             // registers: one LDS read per pick after the initial loads
             if (valid && slot == 0) {
-                const int base = s_loc * MC;
+                const int base = lbase;
                 int nk[kMaxCands], nh0[kMaxCands], cur[kMaxCands], hnh[kMaxCands];
                 float c0[kMaxCands], hc[kMaxCands];
 #pragma unroll
                 for (int j = 0; j < kMaxCands; ++j) {
                     nk[j] = j < MC ? sh.nchild[base + j] : -1;
                     nh0[j] = j < MC ? sh.meta[0 * W + base + j] : 0;
-                    c0[j] = j < MC ? sh.pred[6 * W + base + j] : 0.0f;
+                    c0[j] = j < MC ? sh.pred[3 * W + base + j] : 0.0f;
                     cur[j] = 0;
                 }
                 // parents fill slots 0, 1, ...: the first empty slot ends them
@@ -922,20 +930,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 sh.nsel[s_loc] = nsel;
             }
             __syncthreads();
-            // ---- a6: materialise the surviving children (Kalman update for hit children)
+            // ---- a6: materialise the surviving children (Kalman update for hit
+            // children).  A child copies its parent's predicted state from the
+            // parent's registers (same wave); every lane takes part in the copy.
+            int sel_j = 0, sel_c = 0, src = ln64;
+            bool occ_new = false;
             if (valid) {
-                const int nsel = sh.nsel[s_loc];
-                occupied = slot < nsel;
+                occ_new = slot < sh.nsel[s_loc];
+                if (occ_new) {
+                    sel_j = sh.sel[(s_loc * kMaxCands + slot) * 2 + 0];
+                    sel_c = sh.sel[(s_loc * kMaxCands + slot) * 2 + 1];
+                    src = (lbase + sel_j) & 63;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) p[k] = __shfl(p[k], src);
+#pragma unroll
+            for (int k = 0; k < 21; ++k) P[k] = __shfl(P[k], src);
+            if (valid) {
+                occupied = occ_new;
                 int2 bpe = make_int2(-1, 0xFF00);
                 if (occupied) {
-                    const int j = sh.sel[(s_loc * kMaxCands + slot) * 2 + 0];
-                    const int c = sh.sel[(s_loc * kMaxCands + slot) * 2 + 1];
-                    const int tj = s_loc * MC + j;
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) p[k] = T(sh.pred[k * W + tj]);
-#pragma unroll
-                    for (int k = 0; k < 21; ++k) P[k] = sh.predc[k * W + tj];
-                    chi2 = sh.pred[6 * W + tj];
+                    const int j = sel_j;
+                    const int c = sel_c;
+                    const int tj = lbase + j;
+                    chi2 = sh.pred[3 * W + tj];
                     nhits = sh.meta[0 * W + tj];
                     misses = sh.meta[1 * W + tj];
                     status = (uint32_t)sh.meta[2 * W + tj];

@@ -9,6 +9,14 @@ constexpr int kMaxCands = 8;    // candidate slots per seed the kernel is built 
 constexpr int kMaxLayerBins = 16384;   // nbin_phi * nbin_2 of one layer (LDS histogram)
 constexpr int kFindCounters = 7;       // event counters of a finding call
 
+// Seeds per workgroup of the finding kernel: max_cands lanes per seed, and a
+// seed never straddles two waves (its candidates exchange state by shuffles).
+__host__ __device__ inline int seeds_per_wave(int W, int MC) { return (W < 64 ? W : 64) / MC; }
+__host__ __device__ inline int seeds_per_wg(int W, int MC)
+{
+    return W < 64 ? W / MC : (W / 64) * (64 / MC);
+}
+
 // One binned hit: position, sigmas, azimuth cos/sin and the caller's hit index.
 struct alignas(16) BinnedHit {
     float x, y, z, su;
