@@ -749,20 +749,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     for (int g0 = 0; g0 < H; g0 += wlanes * kScanBatch) {
                         float4 r0[kScanBatch], r1[kScanBatch];
                         int own[kScanBatch], bix[kScanBatch];
+                        // lane ln takes kScanBatch consecutive hits: one search for
+                        // the row of the first, then step over row ends
+                        const int gb = g0 + ln * kScanBatch;
+                        int row = 0;
+                        if (gb < H) {
+                            int hi = nseg;                        // sg_pre[row] <= gb < sg_pre[hi]
+                            while (hi - row > 1) {
+                                const int mid = (row + hi) >> 1;
+                                if (sg_pre[mid] <= gb) row = mid;
+                                else hi = mid;
+                            }
+                        }
 #pragma unroll
                         for (int q = 0; q < kScanBatch; ++q) {
-                            const int g = g0 + q * wlanes + ln;
+                            const int g = gb + q;
                             own[q] = -1;
                             bix[q] = 0;
                             if (g < H) {
-                                int lo = 0, hi = nseg;            // sg_pre[lo] <= g < sg_pre[hi]
-                                while (hi - lo > 1) {
-                                    const int mid = (lo + hi) >> 1;
-                                    if (sg_pre[mid] <= g) lo = mid;
-                                    else hi = mid;
-                                }
-                                own[q] = sg_own[lo];
-                                bix[q] = sg_h0[lo] + (g - sg_pre[lo]);
+                                while (sg_pre[row + 1] <= g) ++row;   // sg_pre[nseg] = H > g
+                                own[q] = sg_own[row];
+                                bix[q] = sg_h0[row] + (g - sg_pre[row]);
                             }
                             r0[q] = *(const float4*)&a.bh[bix[q]].x;
                             r1[q] = *(const float4*)&a.bh[bix[q]].sv;
