@@ -64,3 +64,12 @@ def test_batched_and_autotune_validation_without_device(lib):
     lib.kf_timings.restype = C.c_int
     lib.kf_timings.argtypes = [C.c_void_p] * 2
     assert lib.kf_timings(None, None) == -1
+
+
+def test_mlp_entry_points_validate_without_device(lib):
+    for f, n in (("kf_mlp_load", 2), ("kf_mlp_get", 2), ("kf_mlp_features", 6),
+                 ("kf_mlp_forward", 6), ("kf_mlp_grad", 10), ("kf_mlp_train", 11)):
+        fn = getattr(lib, f)
+        fn.restype = C.c_int
+        fn.argtypes = [C.c_void_p] * n
+        assert fn(*([None] * n)) == -1, f

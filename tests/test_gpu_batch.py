@@ -117,3 +117,33 @@ def test_autotune_keeps_fastest_and_results(K, cfg2):
     fp.run()
     torch.cuda.synchronize()
     _same(fp.results(), ref, "tuned")
+
+
+def test_batched_edge_cases(K):
+    """A single small event through the graph, and an empty seed list."""
+    import torch
+    rng = np.random.default_rng(91)
+    geom = E.geometry.barrel10_disks14(x0=0.02)
+    ev = E.make_event(rng, geom, 7, E.pt_power2(0.5, 50.0), 2.5, 20)
+    inp = E.find_inputs([ev])
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run()
+    torch.cuda.synchronize()
+    ref = fp.results()
+    fp.out_hits.fill_(-7)
+    fp.run_batched()
+    fp.run_batched()
+    torch.cuda.synchronize()
+    _same(fp.results(), ref, "one event")
+    # no seeds: nothing to do, no error
+    empty = dict(inp)
+    for key in ("seed_event", "seed_track"):
+        empty[key] = inp[key][:0]
+    for key in ("seed_hits", "seed_hits_local", "seed_layers"):
+        empty[key] = inp[key][:0]
+    fe = K.pipeline.FindProblem(ctx, empty)
+    fe.run()
+    fe.run_batched()
+    torch.cuda.synchronize()
+    assert int(fe.counters[0].item()) == 0

@@ -268,3 +268,32 @@ def test_learned_find_matches_oracle(K, orc, trained):
     assert g["counters"][5] > 0
     o = CM.oracle_find_events(orc, geom, evs, inp)
     _check_parity(g, o, "learned find")
+
+
+def test_learned_find_needs_width_64(K, trained):
+    """The learned start runs a whole wave per guess: width 32 is refused,
+    and the autotuner skips it under the learned flag."""
+    import torch
+    geom, evs = E.find_events(n_events=1, n_tracks=100, n_noise=2_000, seed=1)
+    inp = E.find_inputs(evs)
+    ctx = K.Context(geom)
+    ctx.mlp_load(trained["ctx"].mlp_get())
+    fp = K.pipeline.FindProblem(ctx, inp)
+    ctx.set_find_config(32, False)
+    with pytest.raises(K.KFError):
+        fp.run(K.INIT_MLP)
+    fp.run()                                  # the plain path accepts 32
+    tab = fp.autotune(flags=K.INIT_MLP, reps=1)
+    assert all(w >= 64 for (w, _) in tab), tab
+    assert ctx.find_config()[0] >= 64
+    torch.cuda.synchronize()
+
+
+def test_learned_requires_loaded_model(K):
+    geom, ev = E.fit_sample(n_tracks=10, seed=0)
+    ctx = K.Context(geom)
+    t = K.Tracks(10)
+    import torch
+    tl = torch.zeros(t.ld, dtype=torch.int32, device="cuda")
+    with pytest.raises(K.KFError):
+        ctx.propagate(t, tl, flags=K.INIT_MLP)
