@@ -35,8 +35,10 @@ VECTOR_PEAK_TFLOPS = 78.6      # MI355X vector FP64, and FP32 without packed mat
 
 # Per-layer fit design (state crosses HBM between layers): par 24 (float) and
 # cov 168 (double) read and written, hit x,y,z,su,sv 20, layer and hit index
-# 8, chi2 / ndf / status read and written 24.
+# 8, chi2 / ndf / status read and written 24.  With FP32 storage the
+# covariance is 84 bytes.
 PER_LAYER_BYTES_PER_STEP = 2 * (24 + 168) + 20 + 8 + 24
+PER_LAYER_BYTES_PER_STEP_FP32 = 2 * (24 + 84) + 20 + 8 + 24
 
 
 def parse():
@@ -141,19 +143,21 @@ def run_fit(K, torch, n, w=None, reps=5):
     hidx = torch.as_tensor(hidx_np, device="cuda")
     seed_hits = hidx[:3].contiguous()
     ctx = K.Context(geom)
-    t = K.Tracks(n, ld)
+    tm = K.Tracks(n, ld)
+    t32 = K.Tracks(n, ld, K.PREC_FP32)
     n_steps = int((lseq_np[:, :n] >= 0).sum())
     stream = torch.cuda.current_stream()
     out = {}
-    legs = [("fused", 0), ("per_layer", K.PER_LAYER)]
+    legs = [("fused", 0), ("per_layer", K.PER_LAYER), ("per_layer_fp32", K.PER_LAYER | K.PREC_FP32)]
     if w is not None:
         ctx.mlp_load(w)
         legs.append(("fused_learned", K.INIT_MLP))
     for name, flags in legs:
+        t = t32 if flags & K.PREC_FP32 else tm
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(reps)]
         for r in range(-1, reps):
-            ctx.seed(hits, seed_hits, t)
+            ctx.seed(hits, seed_hits, t, flags & 3)
             if r >= 0:
                 ev[r][0].record(stream)
             ctx.fit(t, hits, lseq, hidx, 10, flags=flags)
@@ -162,6 +166,7 @@ def run_fit(K, torch, n, w=None, reps=5):
         torch.cuda.synchronize()
         out[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     gbs = n_steps * PER_LAYER_BYTES_PER_STEP / (out["per_layer"] * 1e-3) / 1e9
+    gbs32 = n_steps * PER_LAYER_BYTES_PER_STEP_FP32 / (out["per_layer_fp32"] * 1e-3) / 1e9
     return {"workload": f"fit of {n} tracks, precision-workload mix, 10 barrel layers, mixed precision",
             "kf_steps": n_steps,
             "fused_kernel_ms": out["fused"], "fused_steps_per_s": n_steps / (out["fused"] * 1e-3),
@@ -172,7 +177,12 @@ def run_fit(K, torch, n, w=None, reps=5):
             "per_layer_steps_per_s": n_steps / (out["per_layer"] * 1e-3),
             "per_layer_hbm": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": gbs / HBM_PEAK_GBS,
-                              "bytes_per_step": PER_LAYER_BYTES_PER_STEP}}
+                              "bytes_per_step": PER_LAYER_BYTES_PER_STEP},
+            "per_layer_fp32_ms": out["per_layer_fp32"],
+            "per_layer_fp32_steps_per_s": n_steps / (out["per_layer_fp32"] * 1e-3),
+            "per_layer_fp32_hbm": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": gbs32 / HBM_PEAK_GBS,
+                                   "bytes_per_step": PER_LAYER_BYTES_PER_STEP_FP32}}
 
 
 def copy_probe(torch, mib=1024, reps=5):
