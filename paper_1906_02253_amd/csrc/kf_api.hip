@@ -449,10 +449,20 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
     if (seeds->n == 0) return KF_OK;
     hipError_t e = hipSuccess;
     if (!ctx->cap_stream) {
-        e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+        // created together: kept only if all succeed
+        hipStream_t cs = nullptr;
+        hipEvent_t ie[kfmi::kPhaseEvents] = {};
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         for (int k = 0; k < kfmi::kPhaseEvents && e == hipSuccess; ++k)
-            e = hipEventCreateWithFlags(&ctx->idle_ev[k], hipEventDisableTiming);
-        if (e != hipSuccess) return hip_fail(ctx, e, "kf_find_batched setup");
+            e = hipEventCreateWithFlags(&ie[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (int k = 0; k < kfmi::kPhaseEvents; ++k)
+                if (ie[k]) (void)hipEventDestroy(ie[k]);
+            if (cs) (void)hipStreamDestroy(cs);
+            return hip_fail(ctx, e, "kf_find_batched setup");
+        }
+        ctx->cap_stream = cs;
+        for (int k = 0; k < kfmi::kPhaseEvents; ++k) ctx->idle_ev[k] = ie[k];
     }
     // everything the captured launches depend on: pointers, sizes, options
     // and the workspace (a grown workspace moves every scratch array)

@@ -312,6 +312,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const int32_t*
 
 // ------------------------------------------------------------------ seed order
 constexpr int kSeedCells = 64 * 64;   // eta x phi cells per event
+constexpr int kRankMaxEvents = 16384; // events ranked by size for the largest-first order
 
 // Position of each event in the processing order: by hit count, largest
 // first, ties by event index (a permutation of 0..n_events-1).
@@ -1122,6 +1123,9 @@ hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const i
     hipError_t e;
     const int64_t total = (int64_t)n_events * kSeedCells;
     if ((e = launch_fill(pl.scnt, total + 1, 0, s)) != hipSuccess) return e;
+    // the ranking compares every pair of events: beyond kRankMaxEvents the
+    // events keep their input order
+    if (n_events > kRankMaxEvents) largest_first = 0;
     if (largest_first) {
         event_rank_kernel<<<blocks_for(n_events, 256), 256, 0, s>>>(event_off, n_events, pl.erank);
         if ((e = hipGetLastError()) != hipSuccess) return e;
