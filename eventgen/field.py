@@ -1,0 +1,147 @@
+"""Tracks in the parametrised solenoid-like field (synthetic): the field
+model's parameters and a fine-step tracer that produces the true crossings of
+barrel layers.  Input generation only: the tracer integrates with its own
+small fixed step (default 0.05 cm), far below the reconstruction's.
+
+Field: Bz = B0 / (1 + (z/Z0)^2), Br = -(r/2) dBz/dz, no azimuthal component
+(divergence free, axially symmetric)."""
+import numpy as np
+
+from . import geometry as G
+from .generate import Event, KAPPA, pt_uniform
+
+Z0_DEFAULT = 300.0       # cm
+
+
+def field(x, y, z, b0=G.BZ_TESLA, z0=Z0_DEFAULT):
+    u = z / z0
+    g = 1.0 / (1.0 + u * u)
+    dbz = -2.0 * b0 * z / (z0 * z0) * g * g
+    return -0.5 * dbz * x, -0.5 * dbz * y, b0 * g
+
+
+def _deriv(Y, kq, b0, z0):
+    bx, by, bz = field(Y[0], Y[1], Y[2], b0, z0)
+    tx, ty, tz = Y[3], Y[4], Y[5]
+    return np.stack([tx, ty, tz, kq * (ty * bz - tz * by), kq * (tz * bx - tx * bz),
+                     kq * (tx * by - ty * bx)])
+
+
+def _rk4(Y, h, kq, b0, z0):
+    k1 = _deriv(Y, kq, b0, z0)
+    k2 = _deriv(Y + 0.5 * h * k1, kq, b0, z0)
+    k3 = _deriv(Y + 0.5 * h * k2, kq, b0, z0)
+    k4 = _deriv(Y + h * k3, kq, b0, z0)
+    return Y + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+
+
+def to_state(Y, kq):
+    """(position, direction) columns -> (x, y, z, c, phi, theta) rows."""
+    tt = np.hypot(Y[3], Y[4])
+    th = np.arctan2(tt, Y[5])
+    return np.stack([Y[0], Y[1], Y[2], kq / KAPPA / np.sin(th), np.arctan2(Y[4], Y[3]), th],
+                    axis=1)
+
+
+def from_state(s):
+    st = np.sin(s[:, 5])
+    Y = np.stack([s[:, 0], s[:, 1], s[:, 2], st * np.cos(s[:, 4]), st * np.sin(s[:, 4]),
+                  np.cos(s[:, 5])])
+    return Y, KAPPA * s[:, 3] * st
+
+
+def trace_to_radii(states, radii, zmax, b0=G.BZ_TESLA, z0=Z0_DEFAULT, step=0.05,
+                   max_len=400.0):
+    """Outward crossings of the cylinders `radii` (ascending) by tracks
+    starting at `states` [n, 6].  Returns (crossing states [n, nl, 6] and a
+    mask [n, nl]: crossed inside |z| <= zmax[l], before turning back)."""
+    n, nl = states.shape[0], len(radii)
+    Y, kq = from_state(states)
+    out = np.zeros((n, nl, 6))
+    hit = np.zeros((n, nl), bool)
+    nxt = np.zeros(n, int)                  # next layer to cross
+    alive = np.ones(n, bool)
+    steps = int(max_len / step)
+    for _ in range(steps):
+        if not alive.any():
+            break
+        Yn = _rk4(Y, step, kq, b0, z0)
+        r0, r1 = np.hypot(Y[0], Y[1]), np.hypot(Yn[0], Yn[1])
+        # a track turning back inwards (away from the vertex region) or past
+        # the last layer is done
+        alive &= ~((r1 < r0 - 1e-9) & (r0 > 1.0))
+        for _inner in range(3):                # at most a few layers per step
+            idx = np.nonzero(alive & (nxt < nl))[0]
+            if idx.size == 0:
+                break
+            rl = np.asarray(radii)[nxt[idx]]
+            cross = (r0[idx] < rl) & (r1[idx] >= rl)
+            if not cross.any():
+                break
+            ci = idx[cross]
+            rc = rl[cross]
+            # bisection on the step fraction, each trial a single RK4 sub-step
+            lo, hi = np.zeros(ci.size), np.full(ci.size, step)
+            for _b in range(40):
+                mid = 0.5 * (lo + hi)
+                Ym = _rk4(Y[:, ci], mid, kq[ci], b0, z0)
+                inside = np.hypot(Ym[0], Ym[1]) < rc
+                lo = np.where(inside, mid, lo)
+                hi = np.where(inside, hi, mid)
+            Yc = _rk4(Y[:, ci], 0.5 * (lo + hi), kq[ci], b0, z0)
+            lay = nxt[ci]
+            ok = np.abs(Yc[2]) <= np.asarray(zmax)[lay]
+            out[ci, lay] = to_state(Yc, kq[ci])
+            hit[ci, lay] = ok
+            alive[ci[~ok]] = False
+            nxt[ci] += 1
+        alive &= nxt < nl
+        Y = Yn
+    return out, hit
+
+
+def field_sample(n_tracks=2000, seed=5, z0=Z0_DEFAULT, su=0.01, sv=0.05):
+    """Fit workload in the parametrised field: pT U(0.5, 10) GeV, |eta| < 1,
+    vertex sigma 0.01 cm, ten barrel layers, no material, hits smeared by
+    (su, sv) on the surface.  Returns (geom, Event)."""
+    rng = np.random.default_rng(seed)
+    geom = G.barrel10(x0=0.0, su=su, sv=sv)
+    radii = [L["r_or_z"] for L in geom]
+    zmax = [L["hi"] for L in geom]
+    n = n_tracks
+    pt = pt_uniform(0.5, 10.0)(rng, n)
+    eta = rng.uniform(-1.0, 1.0, n)
+    th = 2.0 * np.arctan(np.exp(-eta))
+    phi = rng.uniform(-np.pi, np.pi, n)
+    q = rng.choice([-1.0, 1.0], n)
+    v = rng.normal(0.0, 0.01, (n, 3))
+    st0 = np.stack([v[:, 0], v[:, 1], v[:, 2], q / pt, phi, th], axis=1)
+    cr, ok = trace_to_radii(st0, radii, zmax, z0=z0)
+    # consecutive crossings from the first layer only
+    nh = np.argmin(np.concatenate([ok, np.zeros((n, 1), bool)], axis=1), axis=1)
+    xs, ys, zs, sus, svs, lay, sim = [], [], [], [], [], [], []
+    seq_hit = np.full((n, len(geom)), -1, np.int32)
+    seq_layer = np.full((n, len(geom)), -1, np.int32)
+    truth_at = np.zeros((n, len(geom), 6))
+    k = 0
+    for t in range(n):
+        for l in range(nh[t]):
+            s = cr[t, l]
+            r = np.hypot(s[0], s[1])
+            ph = np.arctan2(s[1], s[0]) + rng.normal(0.0, su) / r
+            xs.append(r * np.cos(ph))
+            ys.append(r * np.sin(ph))
+            zs.append(s[2] + rng.normal(0.0, sv))
+            sus.append(su)
+            svs.append(sv)
+            lay.append(l)
+            sim.append(t)
+            seq_hit[t, l] = k
+            seq_layer[t, l] = l
+            truth_at[t, l] = s
+            k += 1
+    f32 = lambda a: np.asarray(a, np.float32)
+    ev = Event(x=f32(xs), y=f32(ys), z=f32(zs), su=f32(sus), sv=f32(svs),
+               layer=np.asarray(lay, np.int32), sim=np.asarray(sim, np.int32), truth0=st0,
+               seq_hit=seq_hit, seq_layer=seq_layer, truth_at=truth_at, truth_out=truth_at.copy())
+    return geom, ev

@@ -41,7 +41,7 @@ class _Cfg(C.Structure):
     _fields_ = [("n_layers", C.c_int), ("layers", C.POINTER(_Layer)), ("bz", C.c_double),
                 ("chi2_cut", C.c_double), ("max_cands", C.c_int), ("max_newton", C.c_int),
                 ("newton_tol", C.c_double), ("mass", C.c_double), ("max_miss", C.c_int),
-                ("use_material", C.c_int)]
+                ("use_material", C.c_int), ("field_z0", C.c_double), ("field_step", C.c_double)]
 
 
 _lib = None
@@ -58,6 +58,8 @@ def lib():
         lp = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
         cfgp = C.POINTER(_Cfg)
         L.orc_helix.argtypes = [dp, C.c_double, C.c_double, dp]
+        L.orc_field.argtypes = [cfgp, dp, dp]
+        L.orc_rk_path.argtypes = [cfgp, dp, C.c_double, dp]
         L.orc_propagate.argtypes = [cfgp, C.c_int, dp, dp, dp, dp, C.POINTER(C.c_double),
                                     C.POINTER(C.c_int), C.c_int]
         L.orc_propagate.restype = C.c_int
@@ -83,7 +85,8 @@ class Config:
     """Geometry + filter parameters, held alive for the C side."""
 
     def __init__(self, geom, bz=3.8, chi2_cut=30.0, max_cands=6, max_newton=10,
-                 newton_tol=1e-4, mass=0.13957, max_miss=2, material=None):
+                 newton_tol=1e-4, mass=0.13957, max_miss=2, material=None, field_z0=0.0,
+                 field_step=2.0):
         self.geom = geom
         arr = (_Layer * len(geom))()
         for i, L in enumerate(geom):
@@ -93,7 +96,7 @@ class Config:
         if material is None:
             material = any(L["x0"] > 0 for L in geom)
         self.c = _Cfg(len(geom), arr, bz, chi2_cut, max_cands, max_newton, newton_tol, mass,
-                      max_miss, int(bool(material)))
+                      max_miss, int(bool(material)), field_z0, field_step)
         self.ref = C.byref(self.c)
 
 
@@ -214,3 +217,17 @@ def find(cfg, ev, seed_hits, binned=True, n_threads=1):
                par, cov, c2, ndf, st, tie, cnt, int(n_threads))
     return dict(hits=out_hits, par=par, cov=cov, chi2=c2, ndf=ndf, status=st, tie=tie,
                 n_prop=int(cnt[0]), n_upd=int(cnt[1]))
+
+
+def field(cfg, x):
+    """Parametrised field at x (cm) [3] -> B [3] (T)."""
+    B = np.zeros(3)
+    lib().orc_field(cfg.ref, np.ascontiguousarray(x, np.float64), B)
+    return B
+
+
+def rk_path(cfg, p, l):
+    """State after 3D path length l through the parametrised field."""
+    out = np.zeros(6)
+    lib().orc_rk_path(cfg.ref, np.ascontiguousarray(p, np.float64), float(l), out)
+    return out

@@ -19,7 +19,15 @@
  *     Joseph-form covariance (the traditional KF of the paper's Sec. 1);
  *   - layer-by-layer combinatorial finding (paper Sec. 2 and Sec. 4: hit
  *     search windows, chi2 selection, candidate scoring, bounded candidate
- *     count per seed).
+ *     count per seed);
+ *   - optionally a parametrised (non-uniform) field (paper Sec. 3.1: constant
+ *     or parametrised fields): an axially symmetric solenoid-like field,
+ *     Bz = B0 / (1 + (z/Z0)^2) and Br = -(r/2) dBz/dz (divergence free),
+ *     tracks integrated in 3D path length by fourth-order Runge-Kutta with
+ *     equal steps of at most field_step; the propagate-to-radius solve is
+ *     the same bracketed Newton iteration on the integrated radius, and the
+ *     transport Jacobian is the helix one in the field at the start point.
+ *     Barrel targets only.
  */
 #include "kf_oracle.h"
 
@@ -190,10 +198,143 @@ int orc_solve_barrel(const orc_cfg* cfg, const double p[6], double r_l, double s
     return ORC_ST_NOCONV;
 }
 
+/* ------------------------------------------------------------------ */
+/* parametrised field and Runge-Kutta transport                         */
+
+void orc_field(const orc_cfg* cfg, const double x[3], double B[3])
+{
+    double u = x[2] / cfg->field_z0;
+    double g = 1.0 / (1.0 + u * u);
+    double bz = cfg->bz * g;
+    /* dBz/dz = bz * (-2 z / Z0^2) * g; Br = -(r/2) dBz/dz */
+    double dbz = -2.0 * cfg->bz * x[2] / (cfg->field_z0 * cfg->field_z0) * g * g;
+    double br_over_r = -0.5 * dbz;
+    B[0] = br_over_r * x[0];
+    B[1] = br_over_r * x[1];
+    B[2] = bz;
+}
+
+/* d/dl of (position, direction) for a charge with kq = kappa * q / p */
+static void eom(const orc_cfg* cfg, double kq, const double y[6], double dy[6])
+{
+    double B[3];
+    orc_field(cfg, y, B);
+    dy[0] = y[3];
+    dy[1] = y[4];
+    dy[2] = y[5];
+    dy[3] = kq * (y[4] * B[2] - y[5] * B[1]);
+    dy[4] = kq * (y[5] * B[0] - y[3] * B[2]);
+    dy[5] = kq * (y[3] * B[1] - y[4] * B[0]);
+}
+
+void orc_rk_path(const orc_cfg* cfg, const double p[6], double l, double out[6])
+{
+    double st = sin(p[5]);
+    double y[6] = {p[0], p[1], p[2], st * cos(p[4]), st * sin(p[4]), cos(p[5])};
+    double kq = KAPPA * p[3] * st;          /* q/p = c sin(theta) */
+    int n = (int)ceil(fabs(l) / cfg->field_step);
+    double h = n > 0 ? l / n : 0.0;
+    for (int i = 0; i < n; ++i) {
+        double k1[6], k2[6], k3[6], k4[6], t[6];
+        eom(cfg, kq, y, k1);
+        for (int j = 0; j < 6; ++j) t[j] = y[j] + 0.5 * h * k1[j];
+        eom(cfg, kq, t, k2);
+        for (int j = 0; j < 6; ++j) t[j] = y[j] + 0.5 * h * k2[j];
+        eom(cfg, kq, t, k3);
+        for (int j = 0; j < 6; ++j) t[j] = y[j] + h * k3[j];
+        eom(cfg, kq, t, k4);
+        for (int j = 0; j < 6; ++j) y[j] += h / 6.0 * (k1[j] + 2.0 * k2[j] + 2.0 * k3[j] + k4[j]);
+    }
+    double tt = hypot(y[3], y[4]);
+    out[0] = y[0];
+    out[1] = y[1];
+    out[2] = y[2];
+    out[5] = atan2(tt, y[5]);
+    out[4] = atan2(y[4], y[3]);
+    out[3] = p[3] * st / sin(out[5]);       /* q/p is conserved */
+}
+
+/* Propagate-to-radius in the parametrised field: bracketed Newton on the 3D
+ * path length l with r(l) from the Runge-Kutta transport.  Start: the
+ * straight-line intersection (l_init < 0) or l_init.  Bracket: the helix of
+ * the start point's field (its apex), as in the uniform case. */
+static int solve_barrel_field(const orc_cfg* cfg, const double p[6], double r_l, double l_init,
+                              double* l_out, int* iters_out)
+{
+    double x0[3] = {p[0], p[1], p[2]}, B0[3];
+    orc_field(cfg, x0, B0);
+    orc_cfg loc = *cfg;
+    loc.bz = B0[2];
+    double st = sin(p[5]);
+    double s_br, s_hi;
+    /* reuse the uniform solve for the bracket: unreachable there is unreachable here */
+    int it0 = 0;
+    loc.max_newton = 1;
+    int r0 = orc_solve_barrel(&loc, p, r_l, -1.0, &s_br, &it0);
+    if (r0 == ORC_ST_UNREACHABLE) {
+        if (iters_out) *iters_out = 0;
+        return ORC_ST_UNREACHABLE;
+    }
+    double h = -KAPPA * loc.bz * p[3];
+    s_hi = 1e30;
+    if (h != 0.0) {
+        double cphi = cos(p[4]), sphi = sin(p[4]);
+        double cx = p[0] - sphi / h, cy = p[1] + cphi / h;
+        double R = 1.0 / fabs(h), dc = hypot(cx, cy);
+        double v0x = p[0] - cx, v0y = p[1] - cy;
+        double v1x = R * cx / dc, v1y = R * cy / dc;
+        double alpha = atan2(v0x * v1y - v0y * v1x, v0x * v1x + v0y * v1y);
+        double sw = fmod((h > 0 ? alpha : -alpha), 2.0 * PI);
+        if (sw < 0) sw += 2.0 * PI;
+        s_hi = sw / fabs(h);
+    }
+    double l_lo = 0.0, l_hi = s_hi / st;
+    double l;
+    if (l_init >= 0.0) {
+        l = l_init;
+    } else {
+        double cphi = cos(p[4]), sphi = sin(p[4]);
+        double pu = p[0] * cphi + p[1] * sphi;
+        double disc = pu * pu - (p[0] * p[0] + p[1] * p[1]) + r_l * r_l;
+        l = (disc > 0.0 ? -pu + sqrt(disc) : -pu) / st;
+    }
+    if (l < l_lo) l = l_lo;
+    if (l > l_hi) l = l_hi;
+    for (int it = 1; it <= cfg->max_newton; ++it) {
+        double q[6];
+        orc_rk_path(cfg, p, l, q);
+        double r = hypot(q[0], q[1]);
+        double res = r - r_l;
+        double drdl = sin(q[5]) * (q[0] * cos(q[4]) + q[1] * sin(q[4])) / r;
+        if (res < 0.0) { if (l > l_lo) l_lo = l; }
+        else { if (l < l_hi) l_hi = l; }
+        if (fabs(res) < cfg->newton_tol) {
+            if (drdl > 0.0) l -= res / drdl;
+            *l_out = l;
+            if (iters_out) *iters_out = it;
+            return ORC_ST_OK;
+        }
+        double ln = l - res / drdl;
+        if (!(drdl > 0.0) || !(ln > l_lo && ln < l_hi)) ln = 0.5 * (l_lo + l_hi);
+        l = ln;
+    }
+    *l_out = l;
+    if (iters_out) *iters_out = cfg->max_newton;
+    return ORC_ST_NOCONV;
+}
+
 /* path length to a layer, no covariance */
 static int path_to_layer(const orc_cfg* cfg, int layer, const double p[6], double* s, int* iters)
 {
     const orc_layer* L = &cfg->layers[layer];
+    if (cfg->field_z0 > 0.0) {
+        /* parametrised field: barrels only; s is the 3D path length here */
+        if (L->kind != 0) {
+            if (iters) *iters = 0;
+            return ORC_ST_UNREACHABLE;
+        }
+        return solve_barrel_field(cfg, p, L->r_or_z, -1.0, s, iters);
+    }
     if (L->kind == 0) return orc_solve_barrel(cfg, p, L->r_or_z, -1.0, s, iters);
     double ct = cos(p[5]);
     if (ct == 0.0) return ORC_ST_UNREACHABLE;
@@ -205,10 +346,10 @@ static int path_to_layer(const orc_cfg* cfg, int layer, const double p[6], doubl
 /* ------------------------------------------------------------------ */
 /* transport Jacobian at path length s                                 */
 
-static void jacobian_at(const orc_cfg* cfg, const orc_layer* L, const double p[6], double s,
-                        double F[6][6])
+static void jacobian_at_bz(double bz, const orc_layer* L, const double p[6], double s,
+                           double F[6][6])
 {
-    double kb = KAPPA * cfg->bz;
+    double kb = KAPPA * bz;
     double h = -kb * p[3];
     double u = 0.5 * h * s;
     double a = p[4] + u;
@@ -216,7 +357,7 @@ static void jacobian_at(const orc_cfg* cfg, const orc_layer* L, const double p[6
     double ca = cos(a), sa = sin(a);
     double st = sin(p[5]), ct = cos(p[5]);
     double q[6];
-    orc_helix(p, s, cfg->bz, q);
+    orc_helix(p, s, bz, q);
 
     /* partial derivatives at fixed s */
     double D[6][6];
@@ -248,13 +389,36 @@ static void jacobian_at(const orc_cfg* cfg, const orc_layer* L, const double p[6
         for (int j = 0; j < 6; ++j) F[i][j] = D[i][j] + fs[i] * dsdp[j];
 }
 
+static void jacobian_at(const orc_cfg* cfg, const orc_layer* L, const double p[6], double s,
+                        double F[6][6])
+{
+    jacobian_at_bz(cfg->bz, L, p, s, F);
+}
+
+/* Field-dependent parts of a propagation over path s (transverse arc in the
+ * uniform field, 3D length in the parametrised one): end state and Jacobian. */
+static void transport_parts(const orc_cfg* cfg, const orc_layer* L, const double p[6], double s,
+                            double q[6], double F[6][6])
+{
+    if (cfg->field_z0 > 0.0) {
+        double x0[3] = {p[0], p[1], p[2]}, B0[3];
+        orc_field(cfg, x0, B0);
+        orc_rk_path(cfg, p, s, q);
+        /* the helix Jacobian in the start point's field, over the transverse path */
+        jacobian_at_bz(B0[2], L, p, s * sin(p[5]), F);
+    } else {
+        orc_helix(p, s, cfg->bz, q);
+        jacobian_at(cfg, L, p, s, F);
+    }
+}
+
 int orc_jacobian(const orc_cfg* cfg, int layer, const double p[6], double Fo[36])
 {
     double s;
     int st = path_to_layer(cfg, layer, p, &s, NULL);
     if (st) return st;
-    double F[6][6];
-    jacobian_at(cfg, &cfg->layers[layer], p, s, F);
+    double F[6][6], q[6];
+    transport_parts(cfg, &cfg->layers[layer], p, s, q, F);
     memcpy(Fo, F, sizeof(F));
     return 0;
 }
@@ -295,8 +459,7 @@ int orc_propagate(const orc_cfg* cfg, int layer, const double p[6], const double
     if (st) return st;
     const orc_layer* L = &cfg->layers[layer];
     double q[6], F[6][6], P[6][6], T[6][6], Pn[6][6];
-    orc_helix(p, s, cfg->bz, q);
-    jacobian_at(cfg, L, p, s, F);
+    transport_parts(cfg, L, p, s, q, F);
     unpack(Pk, P);
     mul66(F, P, T);
     mul66t(T, F, Pn);

@@ -57,10 +57,16 @@ typedef struct {
     double mass;        /* GeV, for beta in the scattering formula */
     int max_miss;       /* consecutive missed layers allowed */
     int use_material;   /* add process noise */
+    double field_z0;    /* > 0: parametrised field (see orc_field), Bz = bz / (1 + (z/field_z0)^2) */
+    double field_step;  /* largest integration step in the parametrised field [cm] */
 } orc_cfg;
 
 /* helix transport by transverse arc length s */
 void orc_helix(const double p[6], double s, double bz, double out[6]);
+/* parametrised field at x[3] (cm): B[3] in T (Bx, By, Bz) */
+void orc_field(const orc_cfg* cfg, const double x[3], double B[3]);
+/* state after 3D path length l through the parametrised field (RK4) */
+void orc_rk_path(const orc_cfg* cfg, const double p[6], double l, double out[6]);
 
 /* propagate state+cov to layer `layer`; returns status bits.
  * s_out / iters_out may be NULL. add_noise: add scattering noise of the layer. */

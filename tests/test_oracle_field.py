@@ -1,0 +1,154 @@
+"""Pins of the oracle's parametrised-field propagation (solenoid-like field,
+Runge-Kutta transport, propagate-to-radius) against facts outside its own
+code: Maxwell's divergence-free condition, the field formula as the input
+generator implements it, the closed-form helix in the uniform limit, a
+high-accuracy adaptive integration of the equations of motion by scipy, the
+fourth-order convergence of the integrator, and fit pulls on tracks traced by
+the generator's independent fine-step integrator."""
+import numpy as np
+import pytest
+
+import eventgen as E
+import eventgen.field as EF
+
+KAPPA = 0.00299792458
+
+
+def _cfg(orc, z0=300.0, step=2.0, geom=None):
+    return orc.Config(geom or E.geometry.barrel10(x0=0.0), field_z0=z0, field_step=step)
+
+
+def _tracks(rng, n, pt_lo=0.5, pt_hi=10.0):
+    pt = rng.uniform(pt_lo, pt_hi, n)
+    th = rng.uniform(0.7, 2.4, n)
+    return np.stack([rng.normal(0, 1, n), rng.normal(0, 1, n), rng.uniform(-40, 40, n),
+                     rng.choice([-1, 1], n) / pt, rng.uniform(-np.pi, np.pi, n), th], axis=1)
+
+
+def _ref_path(p, l, z0, b0=3.8):
+    """The equations of motion integrated by scipy's DOP853 at rtol 1e-12."""
+    from scipy.integrate import solve_ivp
+    st = np.sin(p[5])
+    kq = KAPPA * p[3] * st
+
+    def f(_, y):
+        u = y[2] / z0
+        g = 1.0 / (1.0 + u * u)
+        dbz = -2.0 * b0 * y[2] / z0 ** 2 * g * g
+        bx, by, bz = -0.5 * dbz * y[0], -0.5 * dbz * y[1], b0 * g
+        return [y[3], y[4], y[5], kq * (y[4] * bz - y[5] * by), kq * (y[5] * bx - y[3] * bz),
+                kq * (y[3] * by - y[4] * bx)]
+
+    y0 = [p[0], p[1], p[2], st * np.cos(p[4]), st * np.sin(p[4]), np.cos(p[5])]
+    r = solve_ivp(f, (0.0, l), y0, method="DOP853", rtol=1e-12, atol=1e-12)
+    return r.y[:, -1]
+
+
+def test_field_divergence_free_and_symmetric(orc):
+    cfg = _cfg(orc)
+    rng = np.random.default_rng(100)
+    for _ in range(20):
+        x = rng.uniform(-100, 100, 3)
+        x[2] = rng.uniform(-250, 250)
+        d = 1e-3
+        div = 0.0
+        for i in range(3):
+            a, b = x.copy(), x.copy()
+            a[i] += d
+            b[i] -= d
+            div += (orc.field(cfg, a)[i] - orc.field(cfg, b)[i]) / (2 * d)
+        assert abs(div) < 1e-9
+        B = orc.field(cfg, x)
+        xm = x.copy()
+        xm[2] = -x[2]
+        Bm = orc.field(cfg, xm)
+        assert np.allclose([Bm[0], Bm[1], Bm[2]], [-B[0], -B[1], B[2]], rtol=1e-14, atol=1e-16)
+        # the input generator's own implementation of the same formula
+        g = EF.field(x[0], x[1], x[2], 3.8, 300.0)
+        assert np.allclose(B, g, rtol=1e-13, atol=1e-15)
+    assert orc.field(cfg, np.zeros(3))[2] == pytest.approx(3.8)
+    assert orc.field(cfg, np.array([0.0, 0.0, 300.0]))[2] == pytest.approx(1.9)
+
+
+def test_rk_uniform_limit_is_the_helix(orc):
+    cfg = _cfg(orc, z0=1e15, step=1.0)
+    rng = np.random.default_rng(101)
+    for p in _tracks(rng, 30, 0.5, 10.0):
+        for l in (5.0, 40.0, 100.0):
+            q = orc.rk_path(cfg, p, l)
+            h = orc.helix(p, l * np.sin(p[5]))
+            assert np.allclose(q[:3], h[:3], atol=2e-6), (p, l)
+            assert np.allclose(q[3], h[3], rtol=1e-9)
+            assert np.allclose(q[5], h[5], atol=1e-9)
+
+
+def test_rk_matches_adaptive_integration(orc):
+    cfg = _cfg(orc)
+    rng = np.random.default_rng(102)
+    for p in _tracks(rng, 12):
+        ref = _ref_path(p, 80.0, 300.0)
+        q = orc.rk_path(cfg, p, 80.0)
+        assert np.allclose(q[:3], ref[:3], atol=2e-5), (p, q[:3] - ref[:3])
+        th = np.arctan2(np.hypot(ref[3], ref[4]), ref[5])
+        assert q[5] == pytest.approx(th, abs=1e-6)
+
+
+def test_rk_is_fourth_order(orc):
+    rng = np.random.default_rng(103)
+    p = _tracks(rng, 1, 0.5, 0.6)[0]
+    ref = _ref_path(p, 60.0, 300.0)
+    err = []
+    for step in (4.0, 2.0, 1.0):
+        q = orc.rk_path(_cfg(orc, step=step), p, 60.0)
+        err.append(np.linalg.norm(q[:3] - ref[:3]))
+    r1, r2 = err[0] / err[1], err[1] / err[2]
+    assert 12 < r1 < 20 and 12 < r2 < 20, (err, r1, r2)
+
+
+def test_field_propagation_to_radius(orc):
+    """The converged crossing lies on the cylinder, at the place the
+    adaptive integration of the same trajectory crosses it."""
+    from scipy.integrate import solve_ivp
+    cfg = _cfg(orc)
+    geom = cfg.geom
+    rng = np.random.default_rng(104)
+    P0 = np.zeros(21)
+    n_ok = 0
+    for p in _tracks(rng, 20, 1.0, 10.0):
+        p[0] = p[1] = 0.0
+        layer = 7                                  # r = 65 cm
+        st, q, _, l, it = orc.propagate(cfg, layer, p, P0, noise=False)
+        if st:
+            continue
+        n_ok += 1
+        r_l = geom[layer]["r_or_z"]
+        assert np.hypot(q[0], q[1]) == pytest.approx(r_l, abs=1e-5)
+        ref = _ref_path(p, l, 300.0)
+        assert np.allclose(q[:3], ref[:3], atol=5e-5)
+        assert 1 <= it <= 10
+    assert n_ok >= 15
+
+
+def test_field_fit_pulls(orc):
+    """Fit in the parametrised field of tracks traced by the generator's
+    fine-step integrator: unit pulls at the last layer and chi2/ndf near 1
+    (the transport Jacobian is the helix one in the start point's field, an
+    approximation the pulls must tolerate)."""
+    geom, ev = EF.field_sample(n_tracks=1500, seed=5)
+    cfg = _cfg(orc, geom=geom)
+    par0, cov0 = orc.seeds_for_event(ev)
+    r = orc.fit(cfg, dict(x=ev.x, y=ev.y, z=ev.z, su=ev.su, sv=ev.sv), ev.seq_layer, ev.seq_hit,
+                par0, cov0, n_threads=8)
+    nh = ev.n_track_hits()
+    ok = (r["status"] == 0) & (nh == 10)
+    assert ok.sum() > 1200
+    truth = ev.truth_at[ok, 9]
+    P = orc.unpack(r["cov"][ok])
+    d = r["par"][ok] - truth
+    d[:, 4] = (d[:, 4] + np.pi) % (2 * np.pi) - np.pi
+    for k in (2, 3, 4, 5):
+        pull = d[:, k] / np.sqrt(P[:, k, k])
+        assert abs(pull.mean()) < 0.1, (k, pull.mean())
+        assert 0.9 < pull.std() < 1.1, (k, pull.std())
+    c2 = r["chi2"][ok] / r["ndf"][ok]
+    assert 0.9 < c2.mean() < 1.1
