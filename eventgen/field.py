@@ -100,7 +100,18 @@ def trace_to_radii(states, radii, zmax, b0=G.BZ_TESLA, z0=Z0_DEFAULT, step=0.05,
     return out, hit
 
 
-def field_sample(n_tracks=2000, seed=5, z0=Z0_DEFAULT, su=0.01, sv=0.05):
+def _vertex_states(rng, n):
+    """pT U(0.5, 10) GeV, |eta| < 1, both charges, vertex sigma 0.01 cm."""
+    pt = pt_uniform(0.5, 10.0)(rng, n)
+    eta = rng.uniform(-1.0, 1.0, n)
+    th = 2.0 * np.arctan(np.exp(-eta))
+    phi = rng.uniform(-np.pi, np.pi, n)
+    q = rng.choice([-1.0, 1.0], n)
+    v = rng.normal(0.0, 0.01, (n, 3))
+    return np.stack([v[:, 0], v[:, 1], v[:, 2], q / pt, phi, th], axis=1)
+
+
+def field_sample(n_tracks=2000, seed=5, z0=Z0_DEFAULT, su=0.01, sv=0.05, step=0.05):
     """Fit workload in the parametrised field: pT U(0.5, 10) GeV, |eta| < 1,
     vertex sigma 0.01 cm, ten barrel layers, no material, hits smeared by
     (su, sv) on the surface.  Returns (geom, Event)."""
@@ -109,14 +120,8 @@ def field_sample(n_tracks=2000, seed=5, z0=Z0_DEFAULT, su=0.01, sv=0.05):
     radii = [L["r_or_z"] for L in geom]
     zmax = [L["hi"] for L in geom]
     n = n_tracks
-    pt = pt_uniform(0.5, 10.0)(rng, n)
-    eta = rng.uniform(-1.0, 1.0, n)
-    th = 2.0 * np.arctan(np.exp(-eta))
-    phi = rng.uniform(-np.pi, np.pi, n)
-    q = rng.choice([-1.0, 1.0], n)
-    v = rng.normal(0.0, 0.01, (n, 3))
-    st0 = np.stack([v[:, 0], v[:, 1], v[:, 2], q / pt, phi, th], axis=1)
-    cr, ok = trace_to_radii(st0, radii, zmax, z0=z0)
+    st0 = _vertex_states(rng, n)
+    cr, ok = trace_to_radii(st0, radii, zmax, z0=z0, step=step)
     # consecutive crossings from the first layer only
     nh = np.argmin(np.concatenate([ok, np.zeros((n, 1), bool)], axis=1), axis=1)
     xs, ys, zs, sus, svs, lay, sim = [], [], [], [], [], [], []
@@ -145,3 +150,29 @@ def field_sample(n_tracks=2000, seed=5, z0=Z0_DEFAULT, su=0.01, sv=0.05):
                layer=np.asarray(lay, np.int32), sim=np.asarray(sim, np.int32), truth0=st0,
                seq_hit=seq_hit, seq_layer=seq_layer, truth_at=truth_at, truth_out=truth_at.copy())
     return geom, ev
+
+
+def field_pairs(n_tracks=100_000, seed=6, z0=Z0_DEFAULT, step=0.5):
+    """Starting states and target layers for learning the propagation path
+    length in the parametrised field: tracks of the field workload's
+    distribution traced (RK4, `step` cm) through the ten barrel layers; every
+    state a track passes through (its vertex and each crossing but the last)
+    paired with the next layer, shuffled.  Returns (geom, state [n, 6]
+    float64, target layer [n] int32)."""
+    rng = np.random.default_rng(seed)
+    geom = G.barrel10(x0=0.0)
+    radii = [L["r_or_z"] for L in geom]
+    zmax = [L["hi"] for L in geom]
+    st0 = _vertex_states(rng, n_tracks)
+    cr, ok = trace_to_radii(st0, radii, zmax, z0=z0, step=step)
+    nh = np.argmin(np.concatenate([ok, np.zeros((n_tracks, 1), bool)], axis=1), axis=1)
+    states = [st0[nh > 0]]
+    targets = [np.zeros(int((nh > 0).sum()), np.int32)]
+    for k in range(1, len(geom)):
+        m = nh > k
+        states.append(cr[m, k - 1])
+        targets.append(np.full(int(m.sum()), k, np.int32))
+    st = np.concatenate(states)
+    tg = np.concatenate(targets)
+    sel = rng.permutation(st.shape[0])
+    return geom, st[sel], tg[sel]

@@ -94,6 +94,11 @@ typedef struct {
     int32_t max_newton;    /* propagate-to-radius iteration limit */
     int32_t max_miss;      /* consecutive missed layers allowed */
     int32_t mlp_max_iter;  /* iterations allowed from the learned guess before fallback */
+    double field_z0;       /* 0: uniform field bz along z.  > 0: parametrised solenoid-like
+                              field Bz = bz / (1 + (z/field_z0)^2), Br = -(r/2) dBz/dz, tracks
+                              integrated by fourth-order Runge-Kutta (kf_propagate, kf_fit;
+                              barrel targets only, disks report UNREACHABLE; kf_find refuses it) */
+    double field_step;     /* largest Runge-Kutta step [cm] in the parametrised field (> 0) */
 } kf_params;
 
 /* Track states, SoA with leading dimension ld.  par [6][ld] and chi2 [ld]
@@ -117,8 +122,9 @@ typedef struct {
 } kf_hits;
 
 /* Create a context.  layers: host array of n_layers (<= 64) records, copied.
- * params: host, copied; NULL = defaults (3.8 T, chi2 30, 6 candidates, 10
- * Newton iterations, 1e-4 cm, pion mass, 2 misses, 3 learned iterations). */
+ * params: host, copied; NULL = defaults (3.8 T uniform, chi2 30, 6
+ * candidates, 10 Newton iterations, 1e-4 cm, pion mass, 2 misses, 3 learned
+ * iterations, Runge-Kutta step 2 cm). */
 int kf_create(kf_ctx** ctx, const kf_layer* layers, int32_t n_layers, const kf_params* params);
 void kf_destroy(kf_ctx* ctx);
 /* Text of the last error on this context (valid until the next call). */
@@ -234,10 +240,12 @@ int kf_timings(kf_ctx* ctx, float ms[5]);
  * device with FP32 master weights and Adam.  Parameters, flat FP32, 4801:
  * W1[64][8], b1[64], W2[64][64], b2[64], w3[64], b3 (W row-major [out][in]).
  * Inputs (8): rho/100, sin and cos of (phi - atan2(y, x)), h * (target radius,
- * or 100 cm for a disk) with h = -0.00299792458 B c, target radius or disk z
+ * or 100 cm for a disk) with h = -0.00299792458 Bz c (Bz at the start point),
+ * target radius or disk z
  * over 100, the straight-line path length s_line to the target over 100, cot
- * theta, 1 for a disk.  Output: (transverse path length - s_line) / (h
- * s_line^2).  With KF_INIT_MLP a barrel solve whose predicted correction
+ * theta, z/100.  Output: (transverse path length - s_line) / (h s_line^2); in
+ * the parametrised field the transverse path length is the 3D one times sin
+ * theta at the start.  With KF_INIT_MLP a barrel solve whose predicted correction
  * exceeds 100 newton_tol starts from s_line + h s_line^2 * output with
  * mlp_max_iter evaluations of r(s), and if those do not converge runs the
  * plain solve (fallback); smaller corrections keep the straight-line start. */

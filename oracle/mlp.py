@@ -9,10 +9,11 @@ The network is not part of the paper; it is the learned initial guess for
 the iterative propagate-to-radius solve (the paper's Sec. 3.1 propagation to
 the next layer).  Reading taken for the unstated details:
   * inputs (8): rho/100, sin psi, cos psi with psi = phi - atan2(y, x), the
-    signed curvature h times the target radius (barrel) or times 100 cm
-    (disk), the target radius or disk z over 100, the straight-line path
-    length to the target over 100 (tangent-line intersection for a barrel,
-    the exact (z_D - z) tan theta for a disk), cot theta, and 1 for a disk;
+    signed curvature h (in the field at the start point) times the target
+    radius (barrel) or times 100 cm (disk), the target radius or disk z over
+    100, the straight-line path length to the target over 100 (tangent-line
+    intersection for a barrel, the exact (z_D - z) tan theta for a disk),
+    cot theta, and z/100 (the parametrised field depends on z);
   * output: the transverse arc length to the target minus the straight-line
     one, in units of h s_line^2 (the leading order of that difference; the
     guess is s_line + h s_line^2 * output);
@@ -102,10 +103,11 @@ def train(theta, X, t, perm, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta, np.array(losses)
 
 
-def features(state, kind, target, bz=3.8):
+def features(state, kind, target, bz=3.8, field_z0=0.0):
     """Network inputs for propagating `state` [n, 6] = (x, y, z, c, phi,
     theta) to a barrel of radius `target` (kind 0) or a disk at z = `target`
-    (kind 1).  Returns [n, 8] (FP64)."""
+    (kind 1); field_z0 > 0: the parametrised field Bz = bz / (1 + (z/z0)^2).
+    Returns [n, 8] (FP64)."""
     s = np.atleast_2d(np.asarray(state, np.float64))
     kind = np.broadcast_to(np.asarray(kind), (s.shape[0],))
     target = np.broadcast_to(np.asarray(target, np.float64), (s.shape[0],))
@@ -115,7 +117,8 @@ def features(state, kind, target, bz=3.8):
     psi = phi - alpha
     sin_psi = np.where(rho > 0, np.sin(psi), 0.0)
     cos_psi = np.where(rho > 0, np.cos(psi), 1.0)
-    h = -KAPPA * bz * c
+    bz_here = bz / (1.0 + (z / field_z0) ** 2) if field_z0 > 0 else bz
+    h = -KAPPA * bz_here * c
     disk = kind == 1
     # tangent line from (x, y) along phi to the circle of radius target
     pu = x * np.cos(phi) + y * np.sin(phi)
@@ -130,7 +133,7 @@ def features(state, kind, target, bz=3.8):
     f[:, 4] = target / 100.0
     f[:, 5] = np.where(disk, s_disk, s_line_barrel) / 100.0
     f[:, 6] = np.cos(th) / np.sin(th)
-    f[:, 7] = disk.astype(np.float64)
+    f[:, 7] = z / 100.0
     return f
 
 

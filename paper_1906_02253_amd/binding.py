@@ -28,7 +28,8 @@ class KfLayer(C.Structure):
 class KfParams(C.Structure):
     _fields_ = [("bz", C.c_double), ("chi2_cut", C.c_double), ("newton_tol", C.c_double),
                 ("mass", C.c_double), ("max_cands", C.c_int32), ("max_newton", C.c_int32),
-                ("max_miss", C.c_int32), ("mlp_max_iter", C.c_int32)]
+                ("max_miss", C.c_int32), ("mlp_max_iter", C.c_int32), ("field_z0", C.c_double),
+                ("field_step", C.c_double)]
 
 
 class KfTracks(C.Structure):
@@ -177,13 +178,14 @@ class Context:
     """A kf_ctx: geometry + parameters (+ workspace) for one device."""
 
     def __init__(self, geom, bz=3.8, chi2_cut=30.0, max_cands=6, max_newton=10, newton_tol=1e-4,
-                 mass=0.13957, max_miss=2, mlp_max_iter=3):
+                 mass=0.13957, max_miss=2, mlp_max_iter=3, field_z0=0.0, field_step=2.0):
         arr = (KfLayer * len(geom))()
         for i, L in enumerate(geom):
             arr[i] = KfLayer(int(L["kind"]), int(L["nbin_phi"]), int(L["nbin_2"]), 0,
                              L["r_or_z"], L["lo"], L["hi"], L["x0"], L["win_su"], L["win_sv"])
         self.n_layers = len(geom)
-        prm = KfParams(bz, chi2_cut, newton_tol, mass, max_cands, max_newton, max_miss, mlp_max_iter)
+        prm = KfParams(bz, chi2_cut, newton_tol, mass, max_cands, max_newton, max_miss, mlp_max_iter,
+                       field_z0, field_step)
         h = C.c_void_p()
         torch.cuda.current_device()          # make sure the runtime is up on this device
         r = lib.kf_create(C.byref(h), arr, len(geom), C.byref(prm))

@@ -117,6 +117,8 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
         return fail(ctx, KF_EUNSUPPORTED, "%s: float storage only (MIXED or FP32)", what);
     if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
         return fail(ctx, KF_EINVAL, "%s: bad precision flag", what);
+    if (ctx->params.field_z0 > 0.0)
+        return fail(ctx, KF_EUNSUPPORTED, "%s: finding runs in the uniform field only", what);
     const bool learn = (flags & KF_INIT_MLP) != 0;
     if (learn && !ctx->mlp_loaded) return fail(ctx, KF_EUNSUPPORTED, "%s: no learned model loaded", what);
     if (learn && ctx->find_width < 64)
@@ -295,10 +297,13 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
         p.mass = 0.13957;
         p.max_miss = 2;
         p.mlp_max_iter = 3;
+        p.field_z0 = 0.0;
+        p.field_step = 2.0;
     }
     if (!(p.bz != 0.0) || !(p.chi2_cut > 0.0) || p.max_cands < 1 || p.max_cands > 8 ||
         p.max_newton < 1 || p.max_newton > 64 || !(p.newton_tol > 0.0) || !(p.mass >= 0.0) ||
-        p.max_miss < 0 || p.mlp_max_iter < 1 || p.mlp_max_iter > 64)
+        p.max_miss < 0 || p.mlp_max_iter < 1 || p.mlp_max_iter > 64 || !(p.field_z0 >= 0.0) ||
+        (p.field_z0 > 0.0 && !(p.field_step > 0.0 && p.field_step <= 1000.0)))
         return fail(nullptr, KF_EINVAL, "kf_create: invalid parameters");
     kf_ctx* ctx = new kf_ctx();
     ctx->n_layers = n_layers;

@@ -585,7 +585,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             if (LEARN) {
                 float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
                 const int bl = live ? next_barrel(p, sh.layers, nl) : -1;
-                if (bl >= 0) mlp_features(p, sh.layers[bl], kb, f);
+                if (bl >= 0) mlp_features(p, sh.layers[bl], a.prm, f);
                 const float y = mlp_wave(a.mlp, f);
                 if (bl >= 0) {
                     s_guess = T(mlp_guess(f, y));

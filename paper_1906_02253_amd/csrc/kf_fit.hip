@@ -40,6 +40,34 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
 {
     const T kb = T(kKappa) * T(prm.bz);
     T s;
+    if (prm.field_z0 > 0.0) {
+        // parametrised field: Runge-Kutta transport to a barrel; the covariance
+        // is carried by the helix Jacobian in the start point's field
+        if (L.kind != 0) return KF_ST_UNREACHABLE;
+        T bx, by, bz0;
+        field_at(T(prm.bz), T(prm.field_z0), p[0], p[1], p[2], &bx, &by, &bz0);
+        const T kb0 = T(kKappa) * bz0;
+        const T sth = Tr<T>::sin_(p[5]);
+        T l;
+        int st = solve_barrel_field(p, T(L.r_or_z), prm, kb0, s_init >= T(0) ? s_init / sth : T(-1),
+                                    prm.mlp_max_iter, &l, evals, fallbacks);
+        if (st) return st;
+        T q[6];
+        rk_path(p, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
+        T pc[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pc[k] = p[k];
+        transport(pc, P, l * sth, kb0, 0, T(L.r_or_z));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) p[k] = q[k];
+        p[4] = wrap_phi(p[4]);
+        if (material) add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
+        if (s_out) *s_out = l * sth;
+        bool fin = true;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fin &= isfinite(p[k]);
+        return fin ? 0 : KF_ST_NAN;
+    }
     if (L.kind == 0) {
         const T h = -kb * p[3];
         T sph, cph;
@@ -160,7 +188,7 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
     if (LEARN) {
         float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
         const bool want = active && L.kind == 0;
-        if (want) mlp_features(p, L, T(kKappa) * T(prm.bz), f);
+        if (want) mlp_features(p, L, prm, f);
         const float y = mlp_wave(mlp, f);
         if (want) s_init = T(mlp_guess(f, y));
         if (!inb) return;
@@ -246,7 +274,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
         if (LEARN) {
             float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
             const bool want = alive && L.kind == 0;
-            if (want) mlp_features(p, L, kb, f);
+            if (want) mlp_features(p, L, a.prm, f);
             const float y = mlp_wave(a.mlp, f);
             if (want) s_init = T(mlp_guess(f, y));
         }

@@ -410,6 +410,74 @@ KF_HD inline int kf_update(T p[6], C P[21], const HitFrame<U>& f, int kind, U* c
     return fin ? 0 : KF_ST_NAN;
 }
 
+// ---------------------------------------------------------------- parametrised field
+// Solenoid-like, axially symmetric and divergence free: Bz = B0 / (1 +
+// (z/Z0)^2) and Br = -(r/2) dBz/dz (paper Sec. 3.1 supports parametrised
+// fields; the model is ours).
+template <typename T>
+KF_HD inline void field_at(T B0, T Z0, T x, T y, T z, T* bx, T* by, T* bz)
+{
+    const T u = z / Z0;
+    const T g = T(1) / (T(1) + u * u);
+    const T k = B0 * z / (Z0 * Z0) * g * g;    // -(1/2) dBz/dz
+    *bx = k * x;
+    *by = k * y;
+    *bz = B0 * g;
+}
+
+// State after 3D path length l: fourth-order Runge-Kutta on (position,
+// direction) with q/p = c sin(theta) conserved, n = ceil(|l| / step) equal
+// steps (backwards for l < 0: the polish step of the radius solve can end a
+// hair behind the start).  Output in the state parametrisation (x, y, z, c,
+// phi, theta).
+template <typename T>
+KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
+{
+    T st, ct, sp, cp;
+    Tr<T>::sincos_(p[5], &st, &ct);
+    Tr<T>::sincos_(p[4], &sp, &cp);
+    const T kq = T(kKappa) * p[3] * st;
+    T y0 = p[0], y1 = p[1], y2 = p[2], t0 = st * cp, t1 = st * sp, t2 = ct;
+    const int n = (int)ceil(double(Tr<T>::abs_(l) / step));
+    const T h = n > 0 ? l / T(n) : T(0);
+    // derivative of (position, direction) at (x, t)
+    auto der = [&](T x0, T x1, T x2, T u0, T u1, T u2, T d[6]) {
+        T bx, by, bz;
+        field_at(B0, Z0, x0, x1, x2, &bx, &by, &bz);
+        d[0] = u0;
+        d[1] = u1;
+        d[2] = u2;
+        d[3] = kq * (u1 * bz - u2 * by);
+        d[4] = kq * (u2 * bx - u0 * bz);
+        d[5] = kq * (u0 * by - u1 * bx);
+    };
+    for (int i = 0; i < n; ++i) {
+        T a[6], b[6], c[6], d[6];
+        der(y0, y1, y2, t0, t1, t2, a);
+        const T hh = T(0.5) * h;
+        der(y0 + hh * a[0], y1 + hh * a[1], y2 + hh * a[2], t0 + hh * a[3], t1 + hh * a[4],
+            t2 + hh * a[5], b);
+        der(y0 + hh * b[0], y1 + hh * b[1], y2 + hh * b[2], t0 + hh * b[3], t1 + hh * b[4],
+            t2 + hh * b[5], c);
+        der(y0 + h * c[0], y1 + h * c[1], y2 + h * c[2], t0 + h * c[3], t1 + h * c[4],
+            t2 + h * c[5], d);
+        const T w = h / T(6);
+        y0 += w * (a[0] + T(2) * b[0] + T(2) * c[0] + d[0]);
+        y1 += w * (a[1] + T(2) * b[1] + T(2) * c[1] + d[1]);
+        y2 += w * (a[2] + T(2) * b[2] + T(2) * c[2] + d[2]);
+        t0 += w * (a[3] + T(2) * b[3] + T(2) * c[3] + d[3]);
+        t1 += w * (a[4] + T(2) * b[4] + T(2) * c[4] + d[4]);
+        t2 += w * (a[5] + T(2) * b[5] + T(2) * c[5] + d[5]);
+    }
+    const T tt = Tr<T>::sqrt_(t0 * t0 + t1 * t1);
+    out[0] = y0;
+    out[1] = y1;
+    out[2] = y2;
+    out[5] = Tr<T>::atan2_(tt, t2);
+    out[4] = Tr<T>::atan2_(t1, t0);
+    out[3] = p[3] * st / Tr<T>::sin_(out[5]);
+}
+
 // Status bits that freeze a track (everything except the informational
 // fallback bit of the learned guess).
 constexpr uint32_t kFreezeMask = ~(uint32_t)KF_ST_FALLBACK;
@@ -455,6 +523,65 @@ KF_HD inline int solve_barrel(const T p[6], T h, T cph, T sph, T r_l, T s_hi, co
     }
     return newton_barrel(p[0], p[1], p[4], h, r_l, s0, T(0), s_hi, prm.max_newton,
                          T(prm.newton_tol), s, evals);
+}
+
+// Propagate-to-radius in the parametrised field: bracketed Newton on the 3D
+// path length l, r(l) from rk_path.  The bracket and reachability come from
+// the helix in the start point's field (kb0 = kappa Bz(start)); the start is
+// the straight line, or l_guess >= 0 with learned_it evaluations before the
+// fallback to the straight line (counted in *fallbacks).
+template <typename T>
+KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T kb0, T l_guess,
+                                    int learned_it, T* l_out, int* evals, int* fallbacks)
+{
+    T sph, cph, sth, cth;
+    Tr<T>::sincos_(p[4], &sph, &cph);
+    Tr<T>::sincos_(p[5], &sth, &cth);
+    const T h = -kb0 * p[3];
+    T s_hi;
+    if (!barrel_bracket(p[0], p[1], cph, sph, h, r_l, &s_hi)) return KF_ST_UNREACHABLE;
+    const T l_top = s_hi / sth;
+    const T B0 = T(prm.bz), Z0 = T(prm.field_z0), step = T(prm.field_step);
+    const T tol = T(prm.newton_tol);
+    const T l_line = line_guess(p[0], p[1], cph, sph, r_l) / sth;
+    // bracketed Newton from l within [0, l_top] with at most max_it evaluations
+    auto newton = [&](T l, int max_it) -> int {
+        T lo = T(0), hi = l_top;
+        if (l < lo) l = lo;
+        if (l > hi) l = hi;
+        for (int it = 1; it <= max_it; ++it) {
+            T q[6];
+            rk_path(p, l, B0, Z0, step, q);
+            T sq, cq, sq5, cq5;
+            Tr<T>::sincos_(q[4], &sq, &cq);
+            Tr<T>::sincos_(q[5], &sq5, &cq5);
+            const T r = Tr<T>::sqrt_(q[0] * q[0] + q[1] * q[1]);
+            const T res = r - r_l;
+            const T drdl = sq5 * (q[0] * cq + q[1] * sq) / r;
+            ++*evals;
+            if (res < T(0)) {
+                if (l > lo) lo = l;
+            } else {
+                if (l < hi) hi = l;
+            }
+            if (Tr<T>::abs_(res) < tol) {
+                if (drdl > T(0)) l -= res / drdl;
+                *l_out = l;
+                return 0;
+            }
+            T ln = l - res / drdl;
+            if (!(drdl > T(0)) || !(ln > lo && ln < hi)) ln = T(0.5) * (lo + hi);
+            l = ln;
+        }
+        *l_out = l;
+        return (int)KF_ST_NOCONV;
+    };
+    if (l_guess >= T(0) && learned_it > 0 &&
+        Tr<T>::abs_(l_guess - l_line) * sth > T(kLearnedGate * prm.newton_tol)) {
+        if (!newton(l_guess, learned_it)) return 0;
+        ++*fallbacks;
+    }
+    return newton(l_line, prm.max_newton);
 }
 
 // Next surface: whichever comes first along the helix, the next barrel

@@ -19,7 +19,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void mlp_features_kernel(int64_t n, int64_t ld, const T* __restrict__ par,
                                                            const int32_t* __restrict__ target,
                                                            const kf_layer* __restrict__ layers,
-                                                           int n_layers, double bz,
+                                                           int n_layers, kf_params prm,
                                                            float* __restrict__ feats)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(int64_t n, int64_t ld
         T p[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) p[k] = par[k * ld + i];
-        mlp_features(p, layers[l], T(kKappa) * T(bz), f);
+        mlp_features(p, layers[l], prm, f);
     }
 #pragma unroll
     for (int k = 0; k < kMlpIn; ++k) feats[k * ld + i] = f[k];
@@ -257,10 +257,10 @@ hipError_t launch_mlp_features(const kf_ctx* ctx, const kf_tracks* t, const int3
     if (t->n == 0) return hipSuccess;
     if (prec == KF_PREC_FP64)
         mlp_features_kernel<double><<<nblk(t->n, 256), 256, 0, s>>>(
-            t->n, t->ld, (const double*)t->par, target, ctx->d_layers, ctx->n_layers, ctx->params.bz, feats);
+            t->n, t->ld, (const double*)t->par, target, ctx->d_layers, ctx->n_layers, ctx->params, feats);
     else
         mlp_features_kernel<float><<<nblk(t->n, 256), 256, 0, s>>>(
-            t->n, t->ld, (const float*)t->par, target, ctx->d_layers, ctx->n_layers, ctx->params.bz, feats);
+            t->n, t->ld, (const float*)t->par, target, ctx->d_layers, ctx->n_layers, ctx->params, feats);
     return hipGetLastError();
 }
 

@@ -167,13 +167,21 @@ __device__ inline float mlp_guess(const float f[kMlpIn], float y)
     return 100.0f * (f[5] + k * y);
 }
 
-// Network inputs for propagating state p to layer L (kb = kappa * B):
-// rho/100, sin and cos of (phi - atan2(y, x)), h * (target radius, or 100 cm
-// for a disk), target radius or disk z over 100, straight-line path length
-// over 100 (tangent-line intersection / exact disk path), cot theta, is_disk.
+// Network inputs for propagating state p to layer L: rho/100, sin and cos
+// of (phi - atan2(y, x)), h * (target radius, or 100 cm for a disk) with h the
+// curvature in the field at the start point, target radius or disk z over
+// 100, straight-line path length over 100 (tangent-line intersection / exact
+// disk path), cot theta, z/100.
 template <typename T>
-__device__ inline void mlp_features(const T p[6], const kf_layer& L, T kb, float f[kMlpIn])
+__device__ inline void mlp_features(const T p[6], const kf_layer& L, const kf_params& prm,
+                                    float f[kMlpIn])
 {
+    T bz = T(prm.bz);
+    if (prm.field_z0 > 0.0) {
+        T bx, by;
+        field_at(T(prm.bz), T(prm.field_z0), p[0], p[1], p[2], &bx, &by, &bz);
+    }
+    const T kb = T(kKappa) * bz;
     const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
     T sph, cph, sth, cth;
     Tr<T>::sincos_(p[4], &sph, &cph);
@@ -189,7 +197,7 @@ __device__ inline void mlp_features(const T p[6], const kf_layer& L, T kb, float
     const T sl = disk ? (tgt - p[2]) * sth / cth : line_guess(p[0], p[1], cph, sph, tgt);
     f[5] = float(sl / T(100));
     f[6] = float(cth / sth);
-    f[7] = disk ? 1.0f : 0.0f;
+    f[7] = float(p[2] / T(100));
 }
 
 }  // namespace kfmi

@@ -98,6 +98,8 @@ int main()
     prm.max_newton = 10;
     prm.max_miss = 2;
     prm.mlp_max_iter = 3;
+    prm.field_z0 = 0.0;
+    prm.field_step = 2.0;
     const T kb = T(kKappa * prm.bz);
     kf_layer barrel{0, 128, 32, 0, 50.0, -60.0, 60.0, 0.02, 0.01, 0.05};
     kf_layer disk{1, 128, 32, 0, 110.0, 20.0, 100.0, 0.02, 0.01, 0.05};

@@ -1,0 +1,266 @@
+"""GPU parity in the parametrised solenoid-like field (Bz = B0 / (1 +
+(z/Z0)^2), Br = -(r/2) dBz/dz): Runge-Kutta propagate-to-radius, the fit and
+the learned start, against the FP64 oracle's field extension on tracks traced
+by the input generator's fine-step integrator.
+
+Tolerances as in tests/common.py (parameters 1e-4 relative with floors, chi2
+1e-3 of max(chi2, ndf)); the all-FP64 path within 1e-9."""
+import numpy as np
+import pytest
+
+import eventgen as E
+import eventgen.field as EF
+from tests import common as CM
+
+pytestmark = pytest.mark.gpu
+
+Z0, STEP = 300.0, 2.0
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1906_02253_amd as K
+    from paper_1906_02253_amd import learned, pipeline
+    K.learned = learned
+    K.pipeline = pipeline
+    return K
+
+
+@pytest.fixture(scope="module")
+def sample():
+    return EF.field_sample(n_tracks=1500, seed=5)
+
+
+def _ctx(K, geom, **kw):
+    return K.Context(geom, field_z0=Z0, field_step=STEP, **kw)
+
+
+def _cfg(orc, geom):
+    return orc.Config(geom, field_z0=Z0, field_step=STEP)
+
+
+def _fit(K, ctx, ev, flags=0):
+    import torch
+    n = ev.n_tracks
+    ld = CM.ld_of(n)
+    hits = K.Hits.from_event(ev)
+    sh = torch.as_tensor(CM.soa_int(ev.seq_hit[:, :3], ld), device="cuda")
+    lseq = torch.as_tensor(CM.soa_int(ev.seq_layer, ld), device="cuda")
+    hidx = torch.as_tensor(CM.soa_int(ev.seq_hit, ld), device="cuda")
+    t = K.Tracks(n, ld, flags & 3)
+    ctx.seed(hits, sh, t, flags)
+    ctx.fit(t, hits, lseq, hidx, ev.seq_layer.shape[1], flags)
+    torch.cuda.synchronize()
+    return t.numpy()
+
+
+def _oracle_fit(orc, geom, ev):
+    par0, cov0 = orc.seeds_for_event(ev)
+    return orc.fit(_cfg(orc, geom), dict(x=ev.x, y=ev.y, z=ev.z, su=ev.su, sv=ev.sv),
+                   ev.seq_layer, ev.seq_hit, par0, cov0, n_threads=8)
+
+
+def _crossing_rows(ev, seed):
+    """(state at the crossing of layer k, layer k+1) for one random k per track."""
+    rng = np.random.default_rng(seed)
+    nh = ev.n_track_hits()
+    st, tg = [], []
+    for t in range(ev.n_tracks):
+        if nh[t] < 2:
+            continue
+        k = rng.integers(0, nh[t] - 1)
+        st.append(ev.truth_at[t, k])
+        tg.append(ev.seq_layer[t, k + 1])
+    return np.array(st), np.array(tg, np.int32)
+
+
+def _propagate(K, ctx, par, cov, tgt, prec, flags=0):
+    import torch
+    n = par.shape[0]
+    ld = CM.ld_of(n)
+    t = K.Tracks.from_numpy(par, cov, prec=prec, ld=ld)
+    target = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
+    target[:n] = torch.as_tensor(tgt, device="cuda")
+    plen = torch.zeros(ld, device="cuda")
+    its = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    ctx.propagate(t, target, plen, its, flags=prec | flags)
+    torch.cuda.synchronize()
+    return t.numpy(), plen.cpu().numpy()[:n], its.cpu().numpy()[:n]
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_field_propagate_parity(K, orc, sample, prec):
+    """States at their crossing of layer k propagated to layer k+1 (with
+    material noise): end state, transverse-equivalent path length l sin(theta0),
+    covariance and, in FP64, the number of Runge-Kutta evaluations."""
+    geom, ev = sample
+    geom = [dict(L, x0=0.02) for L in geom]
+    par, tgt = _crossing_rows(ev, 3)
+    n = par.shape[0]
+    P = np.diag([1e-4, 1e-4, 2e-3, 1e-4, 1e-5, 1e-5])
+    cov = np.tile(orc.pack(P), (n, 1))
+    pflag = K.PREC_FP64 if prec == "fp64" else K.PREC_MIXED
+    g, plen, its = _propagate(K, _ctx(K, geom), par, cov, tgt, pflag)
+    cfg = _cfg(orc, geom)
+    op, oc = np.zeros((n, 6)), np.zeros((n, 21))
+    ol, oit = np.zeros(n), np.zeros(n, int)
+    for i in range(n):
+        st, op[i], oc[i], ol[i], oit[i] = orc.propagate(cfg, tgt[i], par[i], cov[i], noise=True)
+        assert st == 0
+    assert (g["status"] == 0).all()
+    err = CM.par_error(g["par"], op)
+    sl = ol * np.sin(par[:, 5])
+    rel = 1e-9 if prec == "fp64" else CM.REL
+    print(f"{prec}: {n} propagations, max rel par err {err.max():.2e}, "
+          f"max |dl| {np.abs(plen - sl).max():.2e}, evaluations mean {its.mean():.3f}")
+    assert err.max() < rel, err.max(axis=0)
+    assert np.abs(plen - sl).max() < (1e-5 if prec == "fp64" else 1e-3)
+    crel = 1e-9 if prec == "fp64" else 1e-3
+    for idx in (0, 6, 11, 15, 18, 20):
+        assert np.abs(g["cov"][:, idx] / oc[:, idx] - 1).max() < crel, idx
+    if prec == "fp64":
+        assert (its == oit).mean() > 0.999
+
+
+def test_field_fit_parity(K, orc, sample):
+    """1,500 tracks traced through the field, ten barrel layers: the
+    mixed-precision GPU fit against the FP64 oracle (statuses, ndf, parameters,
+    chi2, covariance diagonal), and the all-FP64 one to rounding."""
+    geom, ev = sample
+    o = _oracle_fit(orc, geom, ev)
+    ctx = _ctx(K, geom)
+    g = _fit(K, ctx, ev)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["ndf"], o["ndf"])
+    ok = o["status"] == 0
+    assert ok.sum() > 1200
+    err = CM.par_error(g["par"][ok], o["par"][ok])
+    cerr = CM.chi2_error(g["chi2"][ok], o["chi2"][ok], o["ndf"][ok])
+    print(f"mixed: max rel par err {err.max():.2e}, chi2 err / tol {cerr.max() / CM.CHI2_REL:.3f}")
+    assert err.max() < CM.REL, err.max(axis=0)
+    assert cerr.max() < CM.CHI2_REL
+    for i in range(6):
+        idx = i * (11 - i) // 2 + i
+        rel = np.abs(g["cov"][ok, idx] / o["cov"][ok, idx] - 1)
+        assert np.quantile(rel, 0.999) < 1e-3, (i, rel.max())
+    g64 = _fit(K, ctx, ev, K.PREC_FP64)
+    assert np.array_equal(g64["status"], o["status"])
+    e64 = CM.par_error(g64["par"][ok], o["par"][ok])
+    print(f"fp64: max rel par err {e64.max():.2e}")
+    assert e64.max() < 1e-9
+    assert np.abs(g64["chi2"][ok] - o["chi2"][ok]).max() < 1e-7 * max(1, o["chi2"].max())
+
+
+def test_field_fit_per_layer_equals_fused(K, sample):
+    geom, ev = sample
+    ctx = _ctx(K, geom)
+    a = _fit(K, ctx, ev)
+    b = _fit(K, ctx, ev, K.PER_LAYER)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_field_uniform_limit_matches_helix(K, sample):
+    """Z0 far beyond the detector: the Runge-Kutta fit agrees with the
+    uniform-field (closed-form helix) fit of the same tracks."""
+    import torch
+    geom, ev = sample
+    a = _fit(K, K.Context(geom, field_z0=1e12, field_step=STEP), ev)
+    b = _fit(K, K.Context(geom), ev)
+    assert np.array_equal(a["status"], b["status"])
+    ok = a["status"] == 0
+    assert CM.par_error(a["par"][ok], b["par"][ok]).max() < CM.REL
+    assert CM.chi2_error(a["chi2"][ok], b["chi2"][ok], a["ndf"][ok]).max() < CM.CHI2_REL
+
+
+def test_field_disks_unreachable(K, orc):
+    """Only barrels are targets in the parametrised field: a disk target
+    leaves the track unreachable, on the GPU as in the oracle."""
+    geom = E.geometry.barrel10_disks14(x0=0.0)
+    par = np.array([[0.0, 0.0, 0.0, 0.5, 0.3, 0.3]] * 3)
+    cov = np.tile(orc.pack(np.eye(6) * 1e-4), (3, 1))
+    tgt = np.array([0, 10, 12], np.int32)
+    g, _, _ = _propagate(K, _ctx(K, geom), par, cov, tgt, K.PREC_MIXED)
+    cfg = _cfg(orc, geom)
+    for i in range(3):
+        st = orc.propagate(cfg, tgt[i], par[i], cov[i], noise=False)[0]
+        assert (st == 0) == (g["status"][i] == 0)
+    assert g["status"][0] == 0
+    assert g["status"][1] & K.ST_UNREACHABLE and g["status"][2] & K.ST_UNREACHABLE
+
+
+def test_field_find_refused(K):
+    import torch
+    geom, evs = E.find_events(n_events=1, n_tracks=50, n_noise=0, seed=1)
+    p = K.pipeline.FindProblem(_ctx(K, geom), E.find_inputs(evs))
+    p.seed_fit()
+    with pytest.raises(K.KFError, match="uniform field"):
+        p.find()
+    with pytest.raises(K.KFError, match="uniform field"):
+        p.run_batched()
+    torch.cuda.synchronize()
+
+
+def test_field_bad_params_rejected(K, sample):
+    geom, _ = sample
+    for kw in (dict(field_z0=-1.0), dict(field_z0=300.0, field_step=0.0),
+               dict(field_z0=300.0, field_step=5000.0)):
+        with pytest.raises(K.KFError):
+            K.Context(geom, **kw)
+
+
+@pytest.fixture(scope="module")
+def trained_field(K):
+    """Network trained on the device on the field workload's propagations
+    (50,000 traced tracks, about 500,000 pairs; 20 epochs of batch 4096, Adam
+    lr 1e-3), inputs taking Bz at the start point."""
+    geom, states, tl = EF.field_pairs(n_tracks=50_000, seed=6)
+    ctx = _ctx(K, geom)
+    ps = K.learned.PairSet(ctx, states, tl)
+    tr, va, te = K.learned.split_rows(ps.ok_rows, seed=6)
+    w0 = E.mlp_init(6)
+    ctx.mlp_load(w0)
+    l0 = K.learned.eval_loss(ctx, ps, va)
+    K.learned.train(ctx, ps, tr, w0, epochs=20, batch=4096, lr=1e-3, seed=6)
+    lv = K.learned.eval_loss(ctx, ps, va)
+    print(f"field pairs {ps.n}, ok {ps.ok_rows.size}; val loss {l0:.3e} -> {lv:.3e}")
+    return dict(ctx=ctx, geom=geom, states=states, tl=tl, test=te, l0=l0, lv=lv)
+
+
+def test_field_learned_start(K, trained_field):
+    """The learned start in the field: same crossings as the straight-line
+    start, fewer Runge-Kutta evaluations on average."""
+    tf = trained_field
+    assert tf["lv"] < 0.01 * tf["l0"]
+    te = tf["test"]
+    r = K.learned.compare_starts(tf["ctx"], tf["states"][te], tf["tl"][te])
+    p, l = r["plain"], r["learned"]
+    frozen = lambda s: s & ~K.ST_FALLBACK
+    assert np.array_equal(frozen(p["status"]), frozen(l["status"]))
+    ok = p["status"] == 0
+    assert ok.mean() > 0.99
+    ds = np.abs(l["path"][ok] - p["path"][ok])
+    err = CM.par_error(l["par"][ok], p["par"][ok])
+    fb = (l["status"] & K.ST_FALLBACK) != 0
+    it_p, it_l = p["iters"][ok], l["iters"][ok]
+    print(f"{ok.sum()} field propagations: evaluations plain mean {it_p.mean():.3f}, learned "
+          f"mean {it_l.mean():.3f}; fallback rate {fb[ok].mean():.4f}; max |ds| {ds.max():.2e} cm")
+    assert ds.max() < 1e-4
+    assert err.max() < CM.REL
+    assert it_l.mean() < it_p.mean()
+    assert fb[ok].mean() < 0.05
+
+
+def test_field_learned_fit_matches_oracle(K, orc, sample, trained_field):
+    geom, ev = sample
+    ctx = _ctx(K, geom)
+    ctx.mlp_load(trained_field["ctx"].mlp_get())
+    g = _fit(K, ctx, ev, K.INIT_MLP)
+    o = _oracle_fit(orc, geom, ev)
+    assert np.array_equal(g["status"] & ~K.ST_FALLBACK, o["status"])
+    ok = o["status"] == 0
+    assert CM.par_error(g["par"][ok], o["par"][ok]).max() < CM.REL
+    assert CM.chi2_error(g["chi2"][ok], o["chi2"][ok], o["ndf"][ok]).max() < CM.CHI2_REL
