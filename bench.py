@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--fit-tracks", type=int, default=4_000_000)
+    ap.add_argument("--field-tracks", type=int, default=1_000_000)
     return ap.parse_args()
 
 
@@ -183,6 +184,122 @@ def run_fit(K, torch, n, w=None, reps=5):
             "per_layer_fp32_hbm": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": gbs32 / HBM_PEAK_GBS,
                                    "bytes_per_step": PER_LAYER_BYTES_PER_STEP_FP32}}
+
+
+FIELD_Z0, FIELD_STEP = 300.0, 2.0
+
+
+def build_field_fit_set(n_total, n_unique=100_000, seed=7):
+    """Fit sample in the parametrised field Bz = 3.8 T / (1 + (z/300 cm)^2)
+    (pT U(0.5, 10) GeV, |eta| < 1, ten barrel layers, no material), traced
+    with 0.5 cm Runge-Kutta steps: n_unique tracks replicated at distinct
+    addresses up to n_total, hits step-major.  Also returns the unique
+    tracks' layer-to-layer propagations (state at the crossing of layer k,
+    layer k+1) for the evaluation counts."""
+    import eventgen.field as EF
+    geom, ev = EF.field_sample(n_tracks=n_unique, seed=seed, step=0.5)
+    ld = (n_total + 63) // 64 * 64
+    ms = 10
+    m = n_unique
+    bx = np.zeros((ms, m), np.float32)
+    by, bz_ = np.zeros_like(bx), np.zeros_like(bx)
+    bsu, bsv = np.full_like(bx, 0.01), np.full_like(bx, 0.05)
+    bl = np.zeros((ms, m), np.int32)
+    blseq = np.full((ms, m), -1, np.int32)
+    for s in range(ms):
+        hi = ev.seq_hit[:, s]
+        msk = hi >= 0
+        src = hi[msk]
+        bx[s, msk], by[s, msk], bz_[s, msk] = ev.x[src], ev.y[src], ev.z[src]
+        bsu[s, msk], bsv[s, msk], bl[s, msk] = ev.su[src], ev.sv[src], ev.layer[src]
+        blseq[s, msk] = ev.seq_layer[msk, s]
+    reps = (n_total + m - 1) // m
+
+    def tile(a, fill):
+        out = np.full((ms, ld), fill, a.dtype)
+        out[:, :n_total] = np.tile(a, (1, reps))[:, :n_total]
+        return out
+    lseq = tile(blseq, -1)
+    hits = dict(x=tile(bx, 0).reshape(-1), y=tile(by, 0).reshape(-1), z=tile(bz_, 0).reshape(-1),
+                su=tile(bsu, 0.01).reshape(-1), sv=tile(bsv, 0.05).reshape(-1),
+                layer=tile(bl, 0).reshape(-1))
+    hidx = np.where(lseq >= 0, (np.arange(ms)[:, None] * ld + np.arange(ld)[None, :]), -1)
+    nh = ev.n_track_hits()
+    st, tg = [], []
+    for k in range(ms - 1):
+        msk = nh > k + 1
+        st.append(ev.truth_at[msk, k])
+        tg.append(np.full(int(msk.sum()), k + 1, np.int32))
+    return geom, ld, hits, lseq, hidx.astype(np.int32), np.concatenate(st), np.concatenate(tg)
+
+
+def field_flops_per_step(oc, evals, lengths):
+    """Operations of one field propagation and update: the solve's set-up,
+    each evaluation (its Runge-Kutta transport over the path taken as the
+    converged one), the final transport, the covariance transport and the
+    update; special-function calls counted as one.  evals and lengths are
+    per-propagation arrays (3D path, cm)."""
+    f = lambda k: oc[k]["ops"] + oc[k]["sfu"]
+    n = np.ceil(np.abs(lengths) / FIELD_STEP)
+    per = (f("field_setup") + f("field_at") + evals * (f("field_eval") + f("rk_fixed"))
+           + (evals + 1) * n * f("rk_step") + f("rk_fixed") + f("transport_barrel") + f("update"))
+    return float(per.mean())
+
+
+def run_field_fit(K, torch, n, oc, reps=5):
+    """Fused fit of n tracks in the parametrised field, plain and learned
+    start (network trained on the device on the field workload's
+    propagations): kernel ms (HIP events), rates, Runge-Kutta evaluations per
+    propagation, and the arithmetic roofline estimate."""
+    import eventgen as E
+    import eventgen.field as EF
+    from paper_1906_02253_amd import learned
+    geom, ld, hits_np, lseq_np, hidx_np, pst, ptg = build_field_fit_set(n)
+    ctx = K.Context(geom, field_z0=FIELD_Z0, field_step=FIELD_STEP)
+    g2, states, tl = EF.field_pairs(n_tracks=20_000, seed=6)
+    ps = learned.PairSet(ctx, states, tl)
+    tr, va, _ = learned.split_rows(ps.ok_rows, seed=6)
+    learned.train(ctx, ps, tr, E.mlp_init(6), epochs=20, batch=4096, lr=1e-3, seed=6)
+    val = learned.eval_loss(ctx, ps, va)
+    hits = K.Hits(hits_np["x"], hits_np["y"], hits_np["z"], hits_np["su"], hits_np["sv"],
+                  hits_np["layer"])
+    lseq = torch.as_tensor(lseq_np, device="cuda")
+    hidx = torch.as_tensor(hidx_np, device="cuda")
+    seed_hits = hidx[:3].contiguous()
+    t = K.Tracks(n, ld)
+    n_steps = int((lseq_np[:, :n] >= 0).sum())
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, flags in (("plain", 0), ("learned", K.INIT_MLP)):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for r in range(-1, reps):
+            ctx.seed(hits, seed_hits, t)
+            if r >= 0:
+                ev[r][0].record(stream)
+            ctx.fit(t, hits, lseq, hidx, 10, flags=flags)
+            if r >= 0:
+                ev[r][1].record(stream)
+        torch.cuda.synchronize()
+        out[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    cs = learned.compare_starts(ctx, pst, ptg)
+    ok = cs["plain"]["status"] == 0
+    l3 = cs["plain"]["path"][ok] / np.sin(pst[ok, 5])
+    rep = {"workload": f"fit of {n} tracks in the field Bz = 3.8 T / (1 + (z/300 cm)^2), "
+                       f"pT U(0.5,10) GeV, |eta|<1, 10 barrel layers, RK4 step <= 2 cm, mixed "
+                       f"precision",
+           "kf_steps": n_steps, "network_validation_loss": val}
+    for name in ("plain", "learned"):
+        it = cs[name]["iters"][ok].astype(np.float64)
+        fl = field_flops_per_step(oc, it, l3) * n_steps
+        tf = fl / (out[name] * 1e-3) / 1e12
+        rep[name] = {"kernel_ms": out[name], "steps_per_s": n_steps / (out[name] * 1e-3),
+                     "rk_evals_per_propagation": float(it.mean()),
+                     "roofline_estimate": {"bound": "alu", "achieved": tf,
+                                           "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                           "frac": tf / VECTOR_PEAK_TFLOPS,
+                                           "flops_per_launch": fl}}
+    return rep
 
 
 def copy_probe(torch, mib=1024, reps=5):
@@ -376,6 +493,14 @@ def main():
         result["fit"] = run_fit(K, torch, args.fit_tracks, w)
         print(f"# fit: {result['fit']['fused_steps_per_s']:.3e} steps/s fused", file=sys.stderr,
               flush=True)
+
+    if not args.no_fit:
+        result["field_fit"] = run_field_fit(K, torch, args.field_tracks, oc)
+        ff = result["field_fit"]
+        print(f"# field fit: {ff['plain']['steps_per_s']:.3e} steps/s plain, "
+              f"{ff['learned']['steps_per_s']:.3e} learned; RK evaluations per propagation "
+              f"{ff['plain']['rk_evals_per_propagation']:.3f} / "
+              f"{ff['learned']['rk_evals_per_propagation']:.3f}", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         import oracle

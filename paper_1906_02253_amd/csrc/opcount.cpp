@@ -181,6 +181,36 @@ int main()
         p[2] + T(25.0) * ct / st;
         ct / st;
     });
+    // parametrised field: one fourth-order Runge-Kutta step, the fixed part
+    // of a transport (state in and out), and one evaluation of the radius
+    // solve besides its transport (a step longer than any path makes every
+    // transport a single step)
+    Tally rk_fixed = count([&] {
+        T q[6];
+        rk_path(p, T(0.0), T(3.8), T(300.0), T(2.0), q);
+    });
+    Tally rk_one = count([&] {
+        T q[6];
+        rk_path(p, T(1.5), T(3.8), T(300.0), T(2.0), q);
+    });
+    Tally rk_step{rk_one.ops - rk_fixed.ops, rk_one.sfu - rk_fixed.sfu};
+    kf_params fp = prm;
+    fp.field_z0 = 300.0;
+    fp.field_step = 1e6;
+    int fe = 0, ffb = 0;
+    T lo;
+    const T kb0 = T(kKappa * 3.8);
+    fp.max_newton = 1;
+    Tally f1 = count([&] { solve_barrel_field(p, T(50.0), fp, kb0, T(-1.0), 0, &lo, &fe, &ffb); });
+    fp.max_newton = 2;
+    fp.newton_tol = 1e-300;
+    Tally f2 = count([&] { solve_barrel_field(p, T(50.0), fp, kb0, T(-1.0), 0, &lo, &fe, &ffb); });
+    Tally field_eval{f2.ops - f1.ops - rk_one.ops, f2.sfu - f1.sfu - rk_one.sfu};
+    Tally field_setup{f1.ops - (f2.ops - f1.ops), f1.sfu - (f2.sfu - f1.sfu)};
+    Tally field_at_t = count([&] {
+        T bx, by, bz;
+        field_at(T(3.8), T(300.0), p[0], p[1], p[2], &bx, &by, &bz);
+    });
     printf("{\n");
     auto pr = [](const char* k, Tally t, bool last = false) {
         printf("  \"%s\": {\"ops\": %ld, \"sfu\": %ld}%s\n", k, t.ops, t.sfu, last ? "" : ",");
@@ -193,7 +223,12 @@ int main()
     pr("window", window);
     pr("hit_test", hit_test);
     pr("update", update);
-    pr("nav_fixed", nav_fixed, true);
+    pr("nav_fixed", nav_fixed);
+    pr("rk_step", rk_step);
+    pr("rk_fixed", rk_fixed);
+    pr("field_eval", field_eval);
+    pr("field_setup", field_setup);
+    pr("field_at", field_at_t, true);
     printf("}\n");
     return 0;
 }
