@@ -77,6 +77,8 @@ def lib():
                               ip, ip, C.c_int]
         L.orc_find.argtypes = [cfgp, C.c_long, dp, dp, dp, dp, dp, ip, C.c_long, ip, C.c_int,
                                ip, dp, dp, dp, ip, ip, ip, lp, C.c_int]
+        L.orc_clean_seeds.argtypes = [C.c_long, dp, dp, ip, ip, ip, C.c_double, C.c_double,
+                                      C.c_double, ip, ip]
         _lib = L
     return _lib
 
@@ -231,3 +233,19 @@ def rk_path(cfg, p, l):
     out = np.zeros(6)
     lib().orc_rk_path(cfg.ref, np.ascontiguousarray(p, np.float64), float(l), out)
     return out
+
+
+def clean_seeds(par, chi2, status, event, hits, deta=0.01, dphi=0.01, dc=0.05):
+    """Seed cleaning (paper Sec. 3.2) by its definition, pairwise within each
+    event.  par [n, 6], chi2 [n], status [n] (0 = takes part), event [n],
+    hits [n, 3].  Returns (keep [n] bool, tie [n] bool)."""
+    n = int(np.asarray(chi2).shape[0])
+    keep = np.zeros(n, np.int32)
+    tie = np.zeros(n, np.int32)
+    lib().orc_clean_seeds(n, np.ascontiguousarray(par, np.float64).reshape(-1),
+                          np.ascontiguousarray(chi2, np.float64),
+                          np.ascontiguousarray(status, np.int32),
+                          np.ascontiguousarray(event, np.int32),
+                          np.ascontiguousarray(hits, np.int32).reshape(-1), float(deta), float(dphi),
+                          float(dc), keep, tie)
+    return keep.astype(bool), tie.astype(bool)

@@ -1218,3 +1218,75 @@ void orc_find(const orc_cfg* cfg, long n_hits,
     free(jobs);
     free_index(cfg, &E);
 }
+
+/* ------------------------------------------------------------------ */
+/* Seed cleaning (paper Sec. 3.2: before finding, seeds that probably come
+ * from the same particle are removed, judged by shared hits and by the
+ * seeds' pT, eta and phi; the paper leaves the rule open).  Reading taken:
+ *   two seeds of the same event are duplicates if they share a hit, or if
+ *   |d eta| < deta, |d phi| (modulo 2 pi) < dphi and |d c| < dc all hold;
+ *   seed i is better than seed j if (float) chi2_i < (float) chi2_j, equal
+ *   chi2 going to the lower index;
+ *   a seed is removed iff some better seed is its duplicate (whether or not
+ *   that seed is itself removed: the order-free form, so every seed is
+ *   decided independently of the others' fate).
+ * Only seeds with status 0 take part; the others are kept (keep = 1) and
+ * neither remove nor are removed.  tie[j] = 1 marks a seed in a pair whose
+ * decision lies within 1e-3 relative of a threshold (parameters) or 1e-4
+ * relative in chi2. */
+static double seed_eta(double th) { return -log(tan(0.5 * th)); }
+
+void orc_clean_seeds(long n, const double* par, const double* chi2, const int* status,
+                     const int* event, const int* hits, double deta, double dphi, double dc,
+                     int* keep, int* tie)
+{
+    /* group seed indices by event (counting sort; events are small ints) */
+    int ev_max = -1;
+    for (long i = 0; i < n; ++i) if (event[i] > ev_max) ev_max = event[i];
+    long* cnt = (long*)calloc((size_t)ev_max + 2, sizeof(long));
+    long* idx = (long*)malloc((size_t)(n > 0 ? n : 1) * sizeof(long));
+    for (long i = 0; i < n; ++i) cnt[event[i] + 1]++;
+    for (int e = 0; e <= ev_max; ++e) cnt[e + 1] += cnt[e];
+    long* fill = (long*)calloc((size_t)ev_max + 1, sizeof(long));
+    for (long i = 0; i < n; ++i) idx[cnt[event[i]] + fill[event[i]]++] = i;
+    for (long i = 0; i < n; ++i) {
+        keep[i] = 1;
+        tie[i] = 0;
+    }
+    for (int e = 0; e <= ev_max; ++e) {
+        for (long a = cnt[e]; a < cnt[e + 1]; ++a) {
+            long j = idx[a];
+            if (status[j] != 0) continue;
+            float fj = (float)chi2[j];
+            for (long b = cnt[e]; b < cnt[e + 1]; ++b) {
+                long i = idx[b];
+                if (i == j || status[i] != 0) continue;
+                int share = 0;
+                for (int u = 0; u < 3; ++u)
+                    for (int v = 0; v < 3; ++v)
+                        if (hits[3 * i + u] >= 0 && hits[3 * i + u] == hits[3 * j + v]) share = 1;
+                double de = fabs(seed_eta(par[6 * i + 5]) - seed_eta(par[6 * j + 5]));
+                double dp = fabs(wrap_pi(par[6 * i + 4] - par[6 * j + 4]));
+                double dq = fabs(par[6 * i + 3] - par[6 * j + 3]);
+                int close = de < deta && dp < dphi && dq < dc;
+                int dup = share || close;
+                float fi = (float)chi2[i];
+                int better = fi < fj || (fi == fj && i < j);
+                if (dup && better) keep[j] = 0;
+                /* near-threshold decisions */
+                if (!share) {
+                    const double t = 1e-3;
+                    int all_in = de < deta * (1 + t) && dp < dphi * (1 + t) && dq < dc * (1 + t);
+                    int any_edge = fabs(de - deta) <= t * deta || fabs(dp - dphi) <= t * dphi ||
+                                   fabs(dq - dc) <= t * dc;
+                    if (all_in && any_edge) tie[i] = tie[j] = 1;
+                }
+                if (dup && fabs((double)fi - (double)fj) <= 1e-4 * fmax(fabs(fi), fabs(fj)))
+                    tie[i] = tie[j] = 1;
+            }
+        }
+    }
+    free(cnt);
+    free(fill);
+    free(idx);
+}

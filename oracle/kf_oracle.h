@@ -119,6 +119,13 @@ void orc_find(const orc_cfg* cfg, long n_hits,
               int* out_ndf, int* out_status, int* out_tie_step, long* counters,
               int n_threads);
 
+/* Seed cleaning within each event (see kf_oracle.c).  par [n][6], chi2 [n],
+ * status [n] (only 0 takes part), event [n], hits [n][3] (-1 none).
+ * keep [n] = 1 kept, 0 removed; tie [n] = 1 near a threshold. */
+void orc_clean_seeds(long n, const double* par, const double* chi2, const int* status,
+                     const int* event, const int* hits, double deta, double dphi, double dc,
+                     int* keep, int* tie);
+
 #ifdef __cplusplus
 }
 #endif
