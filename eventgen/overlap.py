@@ -83,4 +83,38 @@ def overlap_batch(seed=9, p_barrel=0.1, p_disk=0.3, **kw):
     return geom, [o[0] for o in out], [o[1] for o in out]
 
 
-__all__ = ["add_overlaps", "overlap_inputs", "overlap_find_events", "overlap_batch", "G"]
+def seed_set(n=6000, n_events=3, seed=11, n_hits=20_000):
+    """Synthetic seed collection for the cleaning alone: dense clusters of
+    seeds (so that duplicates chain) placed across eta-phi cell edges and the
+    phi = +-pi seam, hits drawn from a small pool (shared hits), chi2 on a
+    coarse grid (equal values occur), a few seeds with a failed-fit status;
+    n_events * n_hits hits in all.  Returns dict: par [n, 6] float32, chi2 [n] float32, status [n] uint32,
+    event [n] int32, hits [n, 3] int32."""
+    rng = np.random.default_rng(seed)
+    n_cl = n // 6
+    ce = rng.uniform(-2.9, 2.9, n_cl)
+    cp = np.where(rng.random(n_cl) < 0.2, np.pi - 0.003, rng.uniform(-np.pi, np.pi, n_cl))
+    cc = rng.uniform(-2.0, 2.0, n_cl)
+    which = rng.integers(0, n_cl, n)
+    eta = ce[which] + rng.normal(0, 0.006, n)
+    phi = cp[which] + rng.normal(0, 0.006, n)
+    phi = (phi + np.pi) % (2 * np.pi) - np.pi
+    c = cc[which] + rng.normal(0, 0.03, n)
+    par = np.zeros((n, 6), np.float32)
+    par[:, 0] = rng.normal(0, 5, n)
+    par[:, 1] = rng.normal(0, 5, n)
+    par[:, 2] = rng.normal(0, 5, n)
+    par[:, 3] = c
+    par[:, 4] = phi
+    par[:, 5] = 2 * np.arctan(np.exp(-eta))
+    chi2 = (rng.integers(0, 400, n) * 0.05).astype(np.float32)
+    status = np.where(rng.random(n) < 0.02, 2, 0).astype(np.uint32)
+    event = rng.integers(0, n_events, n).astype(np.int32)
+    # hit indices are global: event e owns [e n_hits, (e + 1) n_hits)
+    hits = (rng.integers(0, n_hits, (n, 3)) + event[:, None] * n_hits).astype(np.int32)
+    hits[rng.random((n, 3)) < 0.05] = -1
+    return dict(par=par, chi2=chi2, status=status, event=event, hits=hits)
+
+
+__all__ = ["add_overlaps", "overlap_inputs", "overlap_find_events", "overlap_batch", "seed_set",
+           "G"]

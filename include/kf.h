@@ -56,7 +56,8 @@ enum {
                               evaluations and the straight-line start was used */
     KF_ST_NONPD = 8,       /* innovation matrix not positive definite */
     KF_ST_NAN = 16,        /* non-finite state */
-    KF_ST_BADINPUT = 32    /* out-of-range layer or hit index in the caller's arrays */
+    KF_ST_BADINPUT = 32,   /* out-of-range layer or hit index in the caller's arrays */
+    KF_ST_DUPLICATE = 64   /* seed removed by seed cleaning (kf_clean_seeds, KF_CLEAN_SEEDS) */
 };
 
 /* flags */
@@ -69,7 +70,9 @@ enum {
     KF_INIT_MLP = 4,       /* start propagate-to-radius from the learned path-length guess
                               (needs kf_mlp_load; kf_find needs a width >= 64) */
     KF_NO_MATERIAL = 8,    /* ignore the layers' material (no process noise) */
-    KF_PER_LAYER = 16      /* kf_fit: one launch per step, state through HBM between steps */
+    KF_PER_LAYER = 16,     /* kf_fit: one launch per step, state through HBM between steps */
+    KF_CLEAN_SEEDS = 32    /* kf_find, kf_find_batched: seed cleaning (kf_clean_seeds) after
+                              the seed order, before the finding kernel */
 };
 
 /* One detector layer (paper Sec. 3.1, the per-layer geometry record). */
@@ -99,6 +102,10 @@ typedef struct {
                               integrated by fourth-order Runge-Kutta (kf_propagate, kf_fit;
                               barrel targets only, disks report UNREACHABLE; kf_find refuses it) */
     double field_step;     /* largest Runge-Kutta step [cm] in the parametrised field (> 0) */
+    double clean_deta;     /* seed cleaning: |d eta| below which two seeds may be duplicates,
+                              0 .. 0.09375 (the width of a seed cell in eta) */
+    double clean_dphi;     /* seed cleaning: |d phi| [rad], 0 .. 2 pi / 64 (a seed cell in phi) */
+    double clean_dc;       /* seed cleaning: |d (q/pT)| [1/GeV], >= 0 */
 } kf_params;
 
 /* Track states, SoA with leading dimension ld.  par [6][ld] and chi2 [ld]
@@ -124,7 +131,8 @@ typedef struct {
 /* Create a context.  layers: host array of n_layers (<= 64) records, copied.
  * params: host, copied; NULL = defaults (3.8 T uniform, chi2 30, 6
  * candidates, 10 Newton iterations, 1e-4 cm, pion mass, 2 misses, 3 learned
- * iterations, Runge-Kutta step 2 cm). */
+ * iterations, Runge-Kutta step 2 cm, seed cleaning 0.01 / 0.01 rad / 0.05
+ * 1/GeV). */
 int kf_create(kf_ctx** ctx, const kf_layer* layers, int32_t n_layers, const kf_params* params);
 void kf_destroy(kf_ctx* ctx);
 /* Text of the last error on this context (valid until the next call). */
@@ -155,6 +163,29 @@ int kf_propagate(kf_ctx* ctx, kf_tracks* t, const int32_t* target_layer, float* 
 int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_seq,
            const int32_t* hit_idx, int32_t max_steps, int flags, void* stream);
 
+/* Seed cleaning (paper Sec. 3.2: before finding, seeds that probably stem
+ * from the same particle are removed using hit identity and the seeds' pT,
+ * eta and phi).  Two seeds of one event are duplicates if they share a hit,
+ * or if |d eta| < clean_deta, |d phi| < clean_dphi (modulo 2 pi) and
+ * |d c| < clean_dc all hold (eta = -ln tan(theta/2), differences in double
+ * precision from the stored floats).  A seed is better than another if its
+ * chi2 (float) is lower, equal chi2 going to the lower index.  A seed is
+ * removed iff some better seed is its duplicate, whether or not that seed is
+ * removed itself (every seed is decided independently).
+ *   hits        only hits->n is used (seed hit indices outside [0, n) match nothing)
+ *   seeds       in: par, chi2, status after the seed fit (KF_PREC_MIXED or
+ *               KF_PREC_FP32 storage); out: status gets KF_ST_DUPLICATE set on
+ *               removed seeds and cleared on kept ones.  Seeds with any other
+ *               freezing bit, or with seed_event outside [0, n_events), take no
+ *               part: they are neither removed nor remove others.
+ *   seed_event  [n_seeds] int32, seed_hits [3][seeds->ld] int32 global hit
+ *               indices (an index belongs to one event, as in kf_find)
+ * kf_find skips seeds with KF_ST_DUPLICATE like any frozen seed (their output
+ * is the seed state with the seed's own hits).  The result is the same on
+ * every call with the same inputs. */
+int kf_clean_seeds(kf_ctx* ctx, const kf_hits* hits, int32_t n_events, kf_tracks* seeds,
+                   const int32_t* seed_event, const int32_t* seed_hits, int flags, void* stream);
+
 /* Combinatorial track finding over one or many events (paper Sec. 2: KF-based
  * track finding; Sec. 3.1: layer-to-layer propagation following the geometry;
  * Sec. 3.2: seeds grouped close in eta-phi and processed in parallel; Sec. 4:
@@ -178,6 +209,8 @@ int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_
  * parent), plus one no-hit child; per seed the best max_cands children by
  * (most hits, lowest chi2, parent rank, hit index) survive.  A candidate stops
  * after max_miss + 1 consecutive missed layers or when no surface is left.
+ * With KF_CLEAN_SEEDS the seeds are cleaned first (kf_clean_seeds; it writes
+ * the seeds' status).
  * Device scratch comes from the context workspace (grown on demand). */
 int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
             const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,

@@ -15,8 +15,9 @@ LIB_PATH = os.environ.get("KFMI_LIB") or os.path.join(HERE, "libkfmi.so")
 
 KF_OK, KF_EINVAL, KF_EHIP, KF_ENOMEM, KF_EUNSUPPORTED = 0, -1, -2, -3, -4
 ST_OK, ST_UNREACHABLE, ST_NOCONV, ST_FALLBACK, ST_NONPD, ST_NAN, ST_BADINPUT = 0, 1, 2, 4, 8, 16, 32
+ST_DUPLICATE = 64
 PREC_MIXED, PREC_FP32, PREC_FP64 = 0, 1, 2
-INIT_MLP, NO_MATERIAL, PER_LAYER = 4, 8, 16
+INIT_MLP, NO_MATERIAL, PER_LAYER, CLEAN_SEEDS = 4, 8, 16, 32
 
 class KfLayer(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nbin_phi", C.c_int32), ("nbin_2", C.c_int32),
@@ -29,7 +30,8 @@ class KfParams(C.Structure):
     _fields_ = [("bz", C.c_double), ("chi2_cut", C.c_double), ("newton_tol", C.c_double),
                 ("mass", C.c_double), ("max_cands", C.c_int32), ("max_newton", C.c_int32),
                 ("max_miss", C.c_int32), ("mlp_max_iter", C.c_int32), ("field_z0", C.c_double),
-                ("field_step", C.c_double)]
+                ("field_step", C.c_double), ("clean_deta", C.c_double), ("clean_dphi", C.c_double),
+                ("clean_dc", C.c_double)]
 
 
 class KfTracks(C.Structure):
@@ -71,6 +73,8 @@ def _load():
                           C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_find_batched.argtypes = [vp, C.POINTER(KfHits), vp, i32, vp, vp, vp, C.POINTER(KfTracks),
                                   vp, C.POINTER(KfTracks), vp, C.c_int, vp]
+    L.kf_clean_seeds.argtypes = [vp, C.POINTER(KfHits), i32, C.POINTER(KfTracks), vp, vp, C.c_int,
+                                 vp]
     L.kf_set_find_config.argtypes = [vp, i32, i32]
     L.kf_get_find_config.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.kf_autotune.argtypes = [vp, C.POINTER(KfHits), vp, i32, C.POINTER(KfTracks), vp, vp, vp,
@@ -178,14 +182,15 @@ class Context:
     """A kf_ctx: geometry + parameters (+ workspace) for one device."""
 
     def __init__(self, geom, bz=3.8, chi2_cut=30.0, max_cands=6, max_newton=10, newton_tol=1e-4,
-                 mass=0.13957, max_miss=2, mlp_max_iter=3, field_z0=0.0, field_step=2.0):
+                 mass=0.13957, max_miss=2, mlp_max_iter=3, field_z0=0.0, field_step=2.0,
+                 clean_deta=0.01, clean_dphi=0.01, clean_dc=0.05):
         arr = (KfLayer * len(geom))()
         for i, L in enumerate(geom):
             arr[i] = KfLayer(int(L["kind"]), int(L["nbin_phi"]), int(L["nbin_2"]), 0,
                              L["r_or_z"], L["lo"], L["hi"], L["x0"], L["win_su"], L["win_sv"])
         self.n_layers = len(geom)
         prm = KfParams(bz, chi2_cut, newton_tol, mass, max_cands, max_newton, max_miss, mlp_max_iter,
-                       field_z0, field_step)
+                       field_z0, field_step, clean_deta, clean_dphi, clean_dc)
         h = C.c_void_p()
         torch.cuda.current_device()          # make sure the runtime is up on this device
         r = lib.kf_create(C.byref(h), arr, len(geom), C.byref(prm))
@@ -240,6 +245,13 @@ class Context:
         w, lf = C.c_int32(), C.c_int32()
         self._check(lib.kf_get_find_config(self.h, C.byref(w), C.byref(lf)), "kf_get_find_config")
         return int(w.value), bool(lf.value)
+
+    def clean_seeds(self, hits, n_events, seeds, seed_event, seed_hits, flags=0):
+        """Seed cleaning: sets ST_DUPLICATE in seeds.status on removed seeds.
+        seed_event int32 [ld]; seed_hits int32 [3, ld]."""
+        self._check(lib.kf_clean_seeds(self.h, C.byref(hits.c()), int(n_events), C.byref(seeds.c()),
+                                       _ptr(seed_event), _ptr(seed_hits), flags, _stream()),
+                    "kf_clean_seeds")
 
     def find(self, hits, event_off, seeds, seed_event, seed_hits, out_hits, out, counters=None,
              flags=0):

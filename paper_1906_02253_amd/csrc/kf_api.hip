@@ -88,7 +88,9 @@ struct FindLaunch {
     FindArgs a;
     int W = 0, grid = 0, prec = 0, largest_first = 0;
     bool learn = false;
+    bool clean = false;
     int64_t n_events = 0;
+    const int32_t* seed_hits = nullptr;
     const int32_t* event_off = nullptr;
     const int32_t* seed_event = nullptr;
     const kf_hits* hits = nullptr;
@@ -199,6 +201,8 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.seeds_per_tile = S;
     a.mlp = ctx->mlp.dev();
     L->learn = learn;
+    L->clean = (flags & KF_CLEAN_SEEDS) != 0;
+    L->seed_hits = seed_hits;
     L->W = W;
     L->grid = (int)grid;
     L->prec = prec;
@@ -217,10 +221,13 @@ hipError_t phase_bin(const kf_ctx* ctx, const kfmi::FindLaunch& L, hipStream_t s
                             ctx->n_layers, s);
 }
 
-hipError_t phase_order(const kfmi::FindLaunch& L, hipStream_t s)
+hipError_t phase_order(const kf_ctx* ctx, const kfmi::FindLaunch& L, hipStream_t s)
 {
     hipError_t e = kfmi::launch_seed_order(L.pl, L.seeds, L.seed_event, L.event_off,
                                            (int)L.n_events, L.largest_first, s);
+    if (e == hipSuccess && L.clean)
+        e = kfmi::launch_clean(L.pl, L.seeds, L.seed_event, (int)L.n_events, L.seed_hits,
+                               L.hits->n, ctx->params, s);
     if (e == hipSuccess) e = kfmi::launch_fill(L.pl.tile_counter, 64, 0, s);
     return e;
 }
@@ -299,11 +306,17 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
         p.mlp_max_iter = 3;
         p.field_z0 = 0.0;
         p.field_step = 2.0;
+        p.clean_deta = 0.01;
+        p.clean_dphi = 0.01;
+        p.clean_dc = 0.05;
     }
     if (!(p.bz != 0.0) || !(p.chi2_cut > 0.0) || p.max_cands < 1 || p.max_cands > 8 ||
         p.max_newton < 1 || p.max_newton > 64 || !(p.newton_tol > 0.0) || !(p.mass >= 0.0) ||
         p.max_miss < 0 || p.mlp_max_iter < 1 || p.mlp_max_iter > 64 || !(p.field_z0 >= 0.0) ||
-        (p.field_z0 > 0.0 && !(p.field_step > 0.0 && p.field_step <= 1000.0)))
+        (p.field_z0 > 0.0 && !(p.field_step > 0.0 && p.field_step <= 1000.0)) ||
+        !(p.clean_deta >= 0.0 && p.clean_deta <= 6.0 / 64.0) ||
+        !(p.clean_dphi >= 0.0 && p.clean_dphi <= 2.0 * kfmi::kPi / 64.0) ||
+        !(p.clean_dc >= 0.0 && p.clean_dc < 1e30))
         return fail(nullptr, KF_EINVAL, "kf_create: invalid parameters");
     kf_ctx* ctx = new kf_ctx();
     ctx->n_layers = n_layers;
@@ -411,6 +424,35 @@ int kf_get_find_config(kf_ctx* ctx, int32_t* width, int32_t* largest_first)
     return KF_OK;
 }
 
+int kf_clean_seeds(kf_ctx* ctx, const kf_hits* hits, int32_t n_events, kf_tracks* seeds,
+                   const int32_t* seed_event, const int32_t* seed_hits, int flags, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_clean_seeds: null context");
+    int r = check_tracks(ctx, seeds, "kf_clean_seeds");
+    if (r) return r;
+    if (!hits || hits->n < 0) return fail(ctx, KF_EINVAL, "kf_clean_seeds: bad hits");
+    const int prec = flags & KF_PREC_MASK;
+    if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
+        return fail(ctx, KF_EUNSUPPORTED, "kf_clean_seeds: float storage only (MIXED or FP32)");
+    if (n_events < 1) return fail(ctx, KF_EINVAL, "kf_clean_seeds: need n_events >= 1");
+    if ((int64_t)n_events * 4096 >= 0x7fffffffLL)
+        return fail(ctx, KF_EINVAL, "kf_clean_seeds: too many events");
+    if (seeds->n > 0x7fffffffLL) return fail(ctx, KF_EINVAL, "kf_clean_seeds: at most 2^31-1 seeds");
+    if (seeds->n == 0) return KF_OK;
+    if (!seed_event || !seed_hits) return fail(ctx, KF_EINVAL, "kf_clean_seeds: null seed_event or seed_hits");
+    kfmi::FindPlan pl{};
+    pl.bl.per_event = 0;
+    const size_t bytes = kfmi::plan_find(&pl, nullptr, hits->n, n_events, seeds->n, 0, 1, 1);
+    void* base = ctx->ws.get(bytes);
+    if (!base) return fail(ctx, KF_ENOMEM, "kf_clean_seeds: workspace of %zu bytes", bytes);
+    kfmi::plan_find(&pl, base, hits->n, n_events, seeds->n, 0, 1, 1);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = kfmi::launch_seed_order(pl, seeds, seed_event, nullptr, n_events, 0, s);
+    if (e == hipSuccess) e = kfmi::launch_clean(pl, seeds, seed_event, n_events, seed_hits, hits->n,
+                                                ctx->params, s);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_clean_seeds");
+}
+
 int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
             const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
             int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream)
@@ -429,7 +471,7 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
     if (e == hipSuccess) e = phase_bin(ctx, L, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
-    if (e == hipSuccess) e = phase_order(L, s);
+    if (e == hipSuccess) e = phase_order(ctx, L, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
     if (e == hipSuccess) e = phase_find(L, s);
     if (e == hipSuccess && ev) {
@@ -502,7 +544,7 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
             return x;
         });
         if (e == hipSuccess) e = capture(ctx, &sub[1], [&](hipStream_t cs) { return phase_bin(ctx, L, cs); });
-        if (e == hipSuccess) e = capture(ctx, &sub[2], [&](hipStream_t cs) { return phase_order(L, cs); });
+        if (e == hipSuccess) e = capture(ctx, &sub[2], [&](hipStream_t cs) { return phase_order(ctx, L, cs); });
         if (e == hipSuccess) e = capture(ctx, &sub[3], [&](hipStream_t cs) { return phase_find(L, cs); });
         if (e == hipSuccess) e = hipGraphCreate(&g.graph, 0);
         // event 0 -> seed+fit -> event 1 -> binning -> event 2 -> order -> event 3 -> find -> event 4

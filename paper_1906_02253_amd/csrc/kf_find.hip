@@ -1141,6 +1141,132 @@ hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const i
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- seed cleaning
+// Duplicate seeds (same event; a shared hit, or eta, phi and q/pT all within
+// the thresholds) and the order-free rule: a seed is removed iff a better
+// duplicate exists.  Three passes over the seeds: clear the claim slot of
+// every hit a taking-part seed holds; every such seed claims its hits with an
+// atomic minimum of its key; then each seed checks its hits' claims (a lower
+// key there is a better seed sharing that hit) and the seeds of its own and
+// the eight neighbouring (eta, phi) cells (the thresholds are below a cell's
+// width, so every parameter duplicate is there).
+
+// (chi2 as float, then index), ascending = better
+__device__ inline unsigned long long clean_key(float chi2, int64_t i)
+{
+    uint32_t u = __float_as_uint(chi2);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((unsigned long long)u << 32) | (unsigned long long)(uint32_t)i;
+}
+
+__device__ inline bool clean_part(uint32_t st, int32_t e, int n_events)
+{
+    return (st & kFreezeMask & ~(uint32_t)KF_ST_DUPLICATE) == 0 && e >= 0 && e < n_events;
+}
+
+__global__ __launch_bounds__(256) void clean_reset_kernel(int64_t n, int64_t ld,
+                                                          const uint32_t* __restrict__ status,
+                                                          const int32_t* __restrict__ seed_event,
+                                                          int n_events,
+                                                          const int32_t* __restrict__ seed_hits,
+                                                          int64_t n_hits,
+                                                          unsigned long long* __restrict__ best)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !clean_part(status[i], seed_event[i], n_events)) return;
+    for (int k = 0; k < 3; ++k) {
+        const int32_t h = seed_hits[k * ld + i];
+        if (h >= 0 && h < n_hits) best[h] = ~0ull;
+    }
+}
+
+__global__ __launch_bounds__(256) void clean_claim_kernel(int64_t n, int64_t ld,
+                                                          const float* __restrict__ chi2,
+                                                          const uint32_t* __restrict__ status,
+                                                          const int32_t* __restrict__ seed_event,
+                                                          int n_events,
+                                                          const int32_t* __restrict__ seed_hits,
+                                                          int64_t n_hits,
+                                                          unsigned long long* __restrict__ best)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !clean_part(status[i], seed_event[i], n_events)) return;
+    const unsigned long long key = clean_key(chi2[i], i);
+    for (int k = 0; k < 3; ++k) {
+        const int32_t h = seed_hits[k * ld + i];
+        if (h >= 0 && h < n_hits) atomicMin(&best[h], key);
+    }
+}
+
+__device__ inline double seed_eta(float th) { return -log(tan(0.5 * (double)th)); }
+
+__global__ __launch_bounds__(256) void clean_mark_kernel(
+    int64_t n, int64_t ld, const float* __restrict__ par, const float* __restrict__ chi2,
+    uint32_t* __restrict__ status, const int32_t* __restrict__ seed_event, int n_events,
+    const int32_t* __restrict__ seed_hits, int64_t n_hits,
+    const unsigned long long* __restrict__ best, const int32_t* __restrict__ cell,
+    const int32_t* __restrict__ soff, const int32_t* __restrict__ order, double deta, double dphi,
+    double dc)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t st = status[j];
+    if (!clean_part(st, seed_event[j], n_events)) return;
+    const unsigned long long kj = clean_key(chi2[j], j);
+    bool dup = false;
+    for (int k = 0; k < 3; ++k) {
+        const int32_t h = seed_hits[k * ld + j];
+        if (h >= 0 && h < n_hits && best[h] < kj) dup = true;
+    }
+    if (!dup) {
+        const double ej = seed_eta(par[5 * ld + j]);
+        const double pj = par[4 * ld + j], cj = par[3 * ld + j];
+        const int c = cell[j];
+        const int base = c - c % kSeedCells;
+        const int fe = (c % kSeedCells) / 64, fp = c % 64;
+        for (int de = -1; de <= 1 && !dup; ++de) {
+            const int e2 = fe + de;
+            if (e2 < 0 || e2 > 63) continue;
+            for (int dp = -1; dp <= 1 && !dup; ++dp) {
+                const int cc = base + e2 * 64 + ((fp + dp + 64) & 63);
+                for (int q = soff[cc]; q < soff[cc + 1]; ++q) {
+                    const int32_t i = order[q];
+                    if (i == j || !clean_part(status[i], seed_event[i], n_events)) continue;
+                    if (clean_key(chi2[i], i) >= kj) continue;
+                    double d = (double)par[4 * ld + i] - pj;
+                    if (d > kPi) d -= 2.0 * kPi;
+                    if (d < -kPi) d += 2.0 * kPi;
+                    if (fabs(seed_eta(par[5 * ld + i]) - ej) < deta && fabs(d) < dphi &&
+                        fabs((double)par[3 * ld + i] - cj) < dc) {
+                        dup = true;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    status[j] = dup ? (st | (uint32_t)KF_ST_DUPLICATE) : (st & ~(uint32_t)KF_ST_DUPLICATE);
+}
+
+hipError_t launch_clean(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
+                        int n_events, const int32_t* seed_hits, int64_t n_hits,
+                        const kf_params& prm, hipStream_t s)
+{
+    if (seeds->n == 0) return hipSuccess;
+    const unsigned nb = blocks_for(seeds->n, 256);
+    clean_reset_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, seeds->status, seed_event, n_events,
+                                          seed_hits, n_hits, pl.clean_best);
+    clean_claim_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->chi2,
+                                          seeds->status, seed_event, n_events, seed_hits, n_hits,
+                                          pl.clean_best);
+    clean_mark_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
+                                         (const float*)seeds->chi2, seeds->status, seed_event,
+                                         n_events, seed_hits, n_hits, pl.clean_best, pl.cell,
+                                         pl.soff, pl.order, prm.clean_deta, prm.clean_dphi,
+                                         prm.clean_dc);
+    return hipGetLastError();
+}
+
 size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t n_seeds,
                  int n_layers, int grid, int seeds_per_tile)
 {
@@ -1172,6 +1298,7 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     pl->bsum = (int32_t*)take(sizeof(int32_t) * nsum);
     pl->bp = (int2*)take(sizeof(int2) * (size_t)grid * n_layers * seeds_per_tile * kMaxCands);
     pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);
+    pl->clean_best = (unsigned long long*)take(sizeof(unsigned long long) * nh);
     return off;
 }
 

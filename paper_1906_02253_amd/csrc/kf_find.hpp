@@ -91,6 +91,7 @@ struct FindPlan {
     int32_t* bsum;      // chunk totals of the prefix sums
     int2* bp;
     int32_t* tile_counter;
+    unsigned long long* clean_best;  // [n_hits] best seed claiming each hit (seed cleaning)
 };
 
 // Lays out the scratch of a call from `base` (nullptr: only sizes it); returns bytes.
@@ -102,6 +103,11 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event_off, int n_events,
                       const kf_layer* d_layers, int n_layers, hipStream_t s);
+// Seed cleaning over the cells the seed order just built (pl.cell, pl.soff,
+// pl.order): marks or clears KF_ST_DUPLICATE in seeds->status.
+hipError_t launch_clean(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
+                        int n_events, const int32_t* seed_hits, int64_t n_hits,
+                        const kf_params& prm, hipStream_t s);
 hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
                              const int32_t* event_off, int n_events, int largest_first,
                              hipStream_t s);

@@ -53,7 +53,7 @@ def test_argument_validation_without_device(lib):
 def test_batched_and_autotune_validation_without_device(lib):
     """The graph and autotuning entry points reject a null context before any
     device work."""
-    for f, n in (("kf_find_batched", 13), ("kf_autotune", 13)):
+    for f, n in (("kf_find_batched", 13), ("kf_autotune", 13), ("kf_clean_seeds", 8)):
         fn = getattr(lib, f)
         fn.restype = C.c_int
         fn.argtypes = [C.c_void_p] * n
@@ -73,3 +73,21 @@ def test_mlp_entry_points_validate_without_device(lib):
         fn.restype = C.c_int
         fn.argtypes = [C.c_void_p] * n
         assert fn(*([None] * n)) == -1, f
+
+
+def test_cleaning_thresholds_validated_without_device(lib):
+    """kf_create rejects seed-cleaning thresholds wider than a seed cell (or
+    negative) before touching the device."""
+    from paper_1906_02253_amd.binding import KfLayer, KfParams
+    lib.kf_create.restype = C.c_int
+    lib.kf_create.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    lay = (KfLayer * 1)()
+    lay[0] = KfLayer(0, 128, 32, 0, 10.0, -20.0, 20.0, 0.0, 0.01, 0.05)
+    for bad in (dict(clean_deta=0.1), dict(clean_dphi=0.1), dict(clean_dc=-1.0),
+                dict(clean_deta=-0.01)):
+        kw = dict(clean_deta=0.01, clean_dphi=0.01, clean_dc=0.05)
+        kw.update(bad)
+        prm = KfParams(3.8, 30.0, 1e-4, 0.13957, 6, 10, 2, 3, 0.0, 2.0, kw["clean_deta"],
+                       kw["clean_dphi"], kw["clean_dc"])
+        out = C.c_void_p()
+        assert lib.kf_create(C.byref(out), lay, 1, C.byref(prm)) == -1, bad

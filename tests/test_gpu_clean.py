@@ -1,0 +1,176 @@
+"""GPU parity of seed cleaning (Sec. 3.2) against the FP64 oracle: the
+cleaning alone on a dense synthetic seed collection, and the finding pass
+with cleaning on module-overlap events (seed fit, cleaning, finding), eager
+and as the captured graph.
+
+Bars: the keep decisions are bit-exact except seeds the oracle marks as
+within 1e-3 of a parameter threshold or 1e-4 in chi2 (none expected on the
+synthetic set, whose inputs both sides read as the same floats); hit lists
+of seeds kept on both sides follow the finding tests' rules."""
+import numpy as np
+import pytest
+
+import eventgen.overlap as EO
+from tests import common as CM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1906_02253_amd as K
+    from paper_1906_02253_amd import pipeline
+    K.pipeline = pipeline
+    return K
+
+
+def _gpu_clean(K, geom, s, n_hits, n_events, calls=1, **kw):
+    import torch
+    n = s["par"].shape[0]
+    ld = CM.ld_of(n)
+    t = K.Tracks.from_numpy(s["par"].astype(np.float64), np.zeros((n, 21)), ld=ld)
+    t.chi2[:n] = torch.as_tensor(s["chi2"], device="cuda")
+    t.status[:n] = torch.as_tensor(s["status"].astype(np.int32), device="cuda")
+    ev = torch.zeros(ld, dtype=torch.int32, device="cuda")
+    ev[:n] = torch.as_tensor(s["event"], device="cuda")
+    sh = torch.as_tensor(CM.soa_int(s["hits"], ld), device="cuda")
+    hits = K.Hits(*(np.zeros(n_hits, np.float32) for _ in range(5)), np.zeros(n_hits, np.int32))
+    ctx = K.Context(geom, **kw)
+    for _ in range(calls):
+        ctx.clean_seeds(hits, n_events, t, ev, sh)
+    torch.cuda.synchronize()
+    return t.status[:n].cpu().numpy().astype(np.int64)
+
+
+def test_clean_parity_synthetic(K, orc):
+    """6,000 seeds in 3 events, clustered so that duplicates chain, across
+    cell edges and the phi seam, shared hits, equal chi2 values, failed
+    seeds: GPU keep decisions == oracle's, seed by seed."""
+    import eventgen as E
+    geom = E.geometry.barrel10(x0=0.0)
+    s = EO.seed_set(n=6000, n_events=3, seed=11, n_hits=20_000)
+    st = _gpu_clean(K, geom, s, 60_000, 3)
+    keep, tie = orc.clean_seeds(s["par"].astype(np.float64), s["chi2"].astype(np.float64),
+                                s["status"].astype(np.int32), s["event"], s["hits"])
+    g_keep = (st & K.ST_DUPLICATE) == 0
+    print(f"kept {keep.sum()} of {keep.size}; ties {tie.sum()}; "
+          f"mismatches {(g_keep != keep).sum()}")
+    assert 0.2 * keep.size < keep.sum() < 0.9 * keep.size
+    assert np.array_equal(g_keep[~tie], keep[~tie])
+    assert tie.sum() < 0.01 * keep.size
+    # failed seeds untouched
+    bad = s["status"] != 0
+    assert np.array_equal(st[bad], s["status"][bad].astype(np.int64))
+
+
+def test_clean_repeatable_and_thresholds(K, orc):
+    """Cleaning twice gives the same statuses (the duplicate bit of the first
+    call is recomputed, not taken as a failure); other thresholds agree with
+    the oracle too; zero thresholds leave only shared hits."""
+    import eventgen as E
+    geom = E.geometry.barrel10(x0=0.0)
+    s = EO.seed_set(n=3000, n_events=2, seed=12, n_hits=8000)
+    a = _gpu_clean(K, geom, s, 16_000, 2, calls=1)
+    b = _gpu_clean(K, geom, s, 16_000, 2, calls=2)
+    assert np.array_equal(a, b)
+    for kw in (dict(clean_deta=0.005, clean_dphi=0.02, clean_dc=0.2),
+               dict(clean_deta=0.0, clean_dphi=0.0, clean_dc=0.0)):
+        st = _gpu_clean(K, geom, s, 16_000, 2, **kw)
+        keep, tie = orc.clean_seeds(s["par"].astype(np.float64), s["chi2"].astype(np.float64),
+                                    s["status"].astype(np.int32), s["event"], s["hits"],
+                                    deta=kw["clean_deta"], dphi=kw["clean_dphi"], dc=kw["clean_dc"])
+        g_keep = (st & K.ST_DUPLICATE) == 0
+        assert np.array_equal(g_keep[~tie], keep[~tie]), kw
+
+
+def _oracle_clean_find(orc, geom, evs, inp):
+    """Oracle pipeline: seed and fit every seed over its three hits, clean,
+    then find from the kept seeds only."""
+    ns = inp["seed_hits"].shape[0]
+    cfg = orc.Config(geom)
+    par, chi2, st = np.zeros((ns, 6)), np.zeros(ns), np.zeros(ns, np.int32)
+    for e, ev in enumerate(evs):
+        m = np.nonzero(inp["seed_event"] == e)[0]
+        shl = inp["seed_hits_local"][m]
+        p0, c0 = np.zeros((m.size, 6)), np.zeros((m.size, 21))
+        for k in range(m.size):
+            p0[k], c0[k] = orc.seed(*[np.array([ev.x[h], ev.y[h], ev.z[h]]) for h in shl[k]])
+        r = orc.fit(cfg, dict(x=ev.x, y=ev.y, z=ev.z, su=ev.su, sv=ev.sv), inp["seed_layers"][m],
+                    shl, p0, c0, n_threads=8)
+        par[m], chi2[m], st[m] = r["par"], r["chi2"], r["status"]
+    keep, tie = orc.clean_seeds(par, chi2, st, inp["seed_event"], inp["seed_hits"])
+    kept = np.nonzero(keep)[0]
+    sub = {k: v[kept] for k, v in inp.items()
+           if k in ("seed_event", "seed_hits", "seed_hits_local", "seed_layers")}
+    sub["event_off"] = inp["event_off"]
+    o = CM.oracle_find_events(orc, geom, evs, sub)
+    return keep, tie, kept, o
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_find_with_cleaning_matches_oracle(K, orc, batched):
+    """Module-overlap events (3 x 800 tracks, 30% overlap per layer, 50,000
+    noise hits): seeds removed on the GPU == oracle (up to its near-threshold
+    seeds), removed seeds carry ST_DUPLICATE and their own hits only, and the
+    kept seeds' hit lists match the oracle's."""
+    import torch
+    geom, evs, ovls = EO.overlap_find_events(n_events=3, n_tracks=800, n_noise=50_000)
+    inp = EO.overlap_inputs(evs, ovls)
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    if batched:
+        for _ in range(2):
+            fp.run_batched(K.CLEAN_SEEDS)
+    else:
+        fp.seed_fit()
+        fp.find(K.CLEAN_SEEDS)
+    torch.cuda.synchronize()
+    g = fp.results()
+    keep, tie, kept, o = _oracle_clean_find(orc, geom, evs, inp)
+    g_keep = (g["status"] & K.ST_DUPLICATE) == 0
+    ns = keep.size
+    print(f"{ns} seeds, oracle keeps {keep.sum()}, GPU keeps {g_keep.sum()}, ties {tie.sum()}, "
+          f"mismatches {(g_keep != keep).sum()}")
+    assert ns > 2 * keep.sum() * 0.95
+    assert np.array_equal(g_keep[~tie], keep[~tie])
+    rem = np.nonzero(~g_keep)[0]
+    assert (g["hits"][rem] >= 0).sum(axis=1).max() <= 3
+    both = np.nonzero(keep & g_keep)[0]
+    pos = np.searchsorted(kept, both)
+    gsub = dict(hits=g["hits"][both])
+    osub = dict(hits=o["hits"][pos], tie=o["tie"][pos])
+    n_same, n_exc, bad = CM.compare_find(gsub, osub)
+    print(f"kept on both: {both.size}, identical {n_same}, excused {n_exc}, unexplained {bad.size}")
+    assert bad.size == 0
+    ok = (o["status"][pos] == 0) & (g["status"][both] == 0)
+    same = (gsub["hits"] == osub["hits"]).all(axis=1) & ok
+    err = CM.par_error(g["par"][both][same], o["par"][pos][same])
+    assert err.max() < CM.REL
+
+
+def test_clean_edge_cases(K, orc):
+    """No seeds; one seed; all seeds identical (one survives, the lowest
+    index at equal chi2); seeds with out-of-range events take no part."""
+    import eventgen as E
+    geom = E.geometry.barrel10(x0=0.0)
+    one = dict(par=np.array([[0, 0, 0, 1.0, 0.5, 1.2]], np.float32), chi2=np.array([3.0], np.float32),
+               status=np.zeros(1, np.uint32), event=np.zeros(1, np.int32),
+               hits=np.array([[0, 1, 2]], np.int32))
+    assert _gpu_clean(K, geom, one, 10, 1).tolist() == [0]
+    same = {k: np.repeat(v, 5, axis=0) for k, v in one.items()}
+    same["hits"] = np.arange(15, dtype=np.int32).reshape(5, 3)
+    st = _gpu_clean(K, geom, same, 20, 1)
+    assert ((st & K.ST_DUPLICATE) == 0).tolist() == [True, False, False, False, False]
+    same["event"] = np.array([0, 0, 7, -1, 0], np.int32)
+    st = _gpu_clean(K, geom, same, 20, 1)
+    assert ((st & K.ST_DUPLICATE) == 0).tolist() == [True, False, True, True, False]
+    import torch
+    ctx = K.Context(geom)
+    t = K.Tracks(0, 64)
+    z = torch.zeros((3, 64), dtype=torch.int32, device="cuda")
+    ctx.clean_seeds(K.Hits(*(np.zeros(1, np.float32) for _ in range(5)), np.zeros(1, np.int32)),
+                    1, t, z[0], z)
+    torch.cuda.synchronize()
