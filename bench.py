@@ -50,6 +50,7 @@ def parse():
                     help="finding workgroup width; 0 = autotune width and tile order")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--no-clean", action="store_true")
     ap.add_argument("--fit-tracks", type=int, default=4_000_000)
     ap.add_argument("--field-tracks", type=int, default=1_000_000)
     return ap.parse_args()
@@ -302,6 +303,40 @@ def run_field_fit(K, torch, n, oc, reps=5):
     return rep
 
 
+def run_clean_pass(K, torch, steps, warmup, width, largest_first):
+    """The batched pass on the 64-event batch with module-overlap duplicate
+    seeds (overlap hits at 10% per barrel and 30% per disk crossing on each
+    track's first three layers, one seed per hit combination), without and
+    with seed cleaning: ms per pass, the phases, seeds kept."""
+    import eventgen.overlap as EO
+    from paper_1906_02253_amd import pipeline
+    geom, evs, ovls = EO.overlap_batch(seed=9)
+    inp = EO.overlap_inputs(evs, ovls)
+    n_seeds = int(inp["seed_hits"].shape[0])
+    n_particles = int(np.unique(inp["seed_event"].astype(np.int64) * 1_000_000
+                                + inp["seed_track"]).size)
+    ctx = K.Context(geom)
+    ctx.set_find_config(width, largest_first)
+    fp = pipeline.FindProblem(ctx, inp)
+    out = {"workload": "64-event batch (seed 9) with module-overlap duplicate seeds: overlap hits "
+                       "at 10% per barrel and 30% per disk crossing on the first three layers, one "
+                       "seed per combination of those hits",
+           "n_seeds": n_seeds, "n_particles_seeded": n_particles, "width": width}
+    for name, flags in (("no_cleaning", 0), ("cleaning", K.CLEAN_SEEDS)):
+        ms, (ms_seed, ms_bin, ms_order, ms_kernel), cnt = timed_pass(torch, ctx, fp, flags, steps,
+                                                                     warmup)
+        st = fp.out.status[:n_seeds].cpu().numpy()
+        out[name] = {"ms_per_pass": ms, "seeds_per_s": n_seeds / (ms * 1e-3),
+                     "phases_ms": {"seed_and_seed_fit": ms_seed, "binning": ms_bin,
+                                   "seed_order_and_cleaning": ms_order, "find_kernel": ms_kernel},
+                     "seeds_searched": int(((st & K.ST_DUPLICATE) == 0).sum()),
+                     "kf_steps_per_pass": 3 * n_seeds + float(cnt[0])}
+    out["cleaning_ms"] = (out["cleaning"]["phases_ms"]["seed_order_and_cleaning"]
+                          - out["no_cleaning"]["phases_ms"]["seed_order_and_cleaning"])
+    out["speedup"] = out["no_cleaning"]["ms_per_pass"] / out["cleaning"]["ms_per_pass"]
+    return out
+
+
 def copy_probe(torch, mib=1024, reps=5):
     """A plain streaming kernel of known size (read mib MiB, write mib MiB):
     its bandwidth, and the reference the HBM byte counters are scaled by."""
@@ -501,6 +536,15 @@ def main():
               f"{ff['learned']['steps_per_s']:.3e} learned; RK evaluations per propagation "
               f"{ff['plain']['rk_evals_per_propagation']:.3f} / "
               f"{ff['learned']['rk_evals_per_propagation']:.3f}", file=sys.stderr, flush=True)
+
+    if not args.no_clean:
+        result["seed_cleaning"] = run_clean_pass(K, torch, args.steps, args.warmup, width,
+                                                 largest_first)
+        sc = result["seed_cleaning"]
+        print(f"# seed cleaning: {sc['n_seeds']} seeds -> {sc['cleaning']['seeds_searched']} "
+              f"searched; pass {sc['no_cleaning']['ms_per_pass']:.3f} -> "
+              f"{sc['cleaning']['ms_per_pass']:.3f} ms (cleaning {sc['cleaning_ms']:.3f} ms)",
+              file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         import oracle

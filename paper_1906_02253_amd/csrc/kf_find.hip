@@ -1144,14 +1144,16 @@ hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const i
 // ---------------------------------------------------------------- seed cleaning
 // Duplicate seeds (same event; a shared hit, or eta, phi and q/pT all within
 // the thresholds) and the order-free rule: a seed is removed iff a better
-// duplicate exists.  Three passes over the seeds: clear the claim slot of
-// every hit a taking-part seed holds; every such seed claims its hits with an
-// atomic minimum of its key; then each seed checks its hits' claims (a lower
-// key there is a better seed sharing that hit) and the seeds of its own and
-// the eight neighbouring (eta, phi) cells (the thresholds are below a cell's
-// width, so every parameter duplicate is there).
+// duplicate exists.  Three passes: clear the claim slot of every hit a
+// taking-part seed holds; in cell order, every seed writes a compact record
+// (key, eta, phi, q/pT) at its position and claims its hits with an atomic
+// minimum of its key; then, again in cell order, each seed checks its hits'
+// claims (a lower key there is a better seed sharing that hit) and the
+// records of its own and the eight neighbouring (eta, phi) cells, which are
+// contiguous ranges (the thresholds are below a cell's width, so every
+// parameter duplicate is there).
 
-// (chi2 as float, then index), ascending = better
+// (chi2 as float, then index), ascending = better; ~0 = takes no part
 __device__ inline unsigned long long clean_key(float chi2, int64_t i)
 {
     uint32_t u = __float_as_uint(chi2);
@@ -1180,47 +1182,53 @@ __global__ __launch_bounds__(256) void clean_reset_kernel(int64_t n, int64_t ld,
     }
 }
 
-__global__ __launch_bounds__(256) void clean_claim_kernel(int64_t n, int64_t ld,
-                                                          const float* __restrict__ chi2,
-                                                          const uint32_t* __restrict__ status,
-                                                          const int32_t* __restrict__ seed_event,
-                                                          int n_events,
-                                                          const int32_t* __restrict__ seed_hits,
-                                                          int64_t n_hits,
-                                                          unsigned long long* __restrict__ best)
+__global__ __launch_bounds__(256) void clean_claim_kernel(
+    int64_t n, int64_t ld, const float* __restrict__ par, const float* __restrict__ chi2,
+    const uint32_t* __restrict__ status, const int32_t* __restrict__ seed_event, int n_events,
+    const int32_t* __restrict__ seed_hits, int64_t n_hits, const int32_t* __restrict__ order,
+    unsigned long long* __restrict__ best, CleanRec* __restrict__ rec)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !clean_part(status[i], seed_event[i], n_events)) return;
-    const unsigned long long key = clean_key(chi2[i], i);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t i = order[t];
+    CleanRec r;
+    if (!clean_part(status[i], seed_event[i], n_events)) {
+        r.key = ~0ull;
+        r.eta = 0.0;
+        r.phi = 0.0f;
+        r.c = 0.0f;
+        rec[t] = r;
+        return;
+    }
+    r.key = clean_key(chi2[i], i);
+    r.eta = -log(tan(0.5 * (double)par[5 * ld + i]));
+    r.phi = par[4 * ld + i];
+    r.c = par[3 * ld + i];
+    rec[t] = r;
     for (int k = 0; k < 3; ++k) {
         const int32_t h = seed_hits[k * ld + i];
-        if (h >= 0 && h < n_hits) atomicMin(&best[h], key);
+        if (h >= 0 && h < n_hits) atomicMin(&best[h], r.key);
     }
 }
 
-__device__ inline double seed_eta(float th) { return -log(tan(0.5 * (double)th)); }
-
 __global__ __launch_bounds__(256) void clean_mark_kernel(
-    int64_t n, int64_t ld, const float* __restrict__ par, const float* __restrict__ chi2,
-    uint32_t* __restrict__ status, const int32_t* __restrict__ seed_event, int n_events,
-    const int32_t* __restrict__ seed_hits, int64_t n_hits,
-    const unsigned long long* __restrict__ best, const int32_t* __restrict__ cell,
-    const int32_t* __restrict__ soff, const int32_t* __restrict__ order, double deta, double dphi,
-    double dc)
+    int64_t n, int64_t ld, uint32_t* __restrict__ status, const int32_t* __restrict__ seed_hits,
+    int64_t n_hits, const unsigned long long* __restrict__ best, const CleanRec* __restrict__ rec,
+    const int32_t* __restrict__ cell, const int32_t* __restrict__ soff,
+    const int32_t* __restrict__ order, double deta, double dphi, double dc)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const uint32_t st = status[j];
-    if (!clean_part(st, seed_event[j], n_events)) return;
-    const unsigned long long kj = clean_key(chi2[j], j);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const CleanRec me = rec[t];
+    if (me.key == ~0ull) return;
+    const int32_t j = order[t];
     bool dup = false;
     for (int k = 0; k < 3; ++k) {
         const int32_t h = seed_hits[k * ld + j];
-        if (h >= 0 && h < n_hits && best[h] < kj) dup = true;
+        if (h >= 0 && h < n_hits && best[h] < me.key) dup = true;
     }
     if (!dup) {
-        const double ej = seed_eta(par[5 * ld + j]);
-        const double pj = par[4 * ld + j], cj = par[3 * ld + j];
+        const double ej = me.eta, pj = me.phi, cj = me.c;
         const int c = cell[j];
         const int base = c - c % kSeedCells;
         const int fe = (c % kSeedCells) / 64, fp = c % 64;
@@ -1229,15 +1237,14 @@ __global__ __launch_bounds__(256) void clean_mark_kernel(
             if (e2 < 0 || e2 > 63) continue;
             for (int dp = -1; dp <= 1 && !dup; ++dp) {
                 const int cc = base + e2 * 64 + ((fp + dp + 64) & 63);
-                for (int q = soff[cc]; q < soff[cc + 1]; ++q) {
-                    const int32_t i = order[q];
-                    if (i == j || !clean_part(status[i], seed_event[i], n_events)) continue;
-                    if (clean_key(chi2[i], i) >= kj) continue;
-                    double d = (double)par[4 * ld + i] - pj;
+                const int q1 = soff[cc + 1];
+                for (int q = soff[cc]; q < q1; ++q) {
+                    const CleanRec o = rec[q];
+                    if (o.key >= me.key) continue;     // not better, itself, or no part
+                    double d = (double)o.phi - pj;
                     if (d > kPi) d -= 2.0 * kPi;
                     if (d < -kPi) d += 2.0 * kPi;
-                    if (fabs(seed_eta(par[5 * ld + i]) - ej) < deta && fabs(d) < dphi &&
-                        fabs((double)par[3 * ld + i] - cj) < dc) {
+                    if (fabs(o.eta - ej) < deta && fabs(d) < dphi && fabs((double)o.c - cj) < dc) {
                         dup = true;
                         break;
                     }
@@ -1245,6 +1252,7 @@ __global__ __launch_bounds__(256) void clean_mark_kernel(
             }
         }
     }
+    const uint32_t st = status[j];
     status[j] = dup ? (st | (uint32_t)KF_ST_DUPLICATE) : (st & ~(uint32_t)KF_ST_DUPLICATE);
 }
 
@@ -1256,14 +1264,13 @@ hipError_t launch_clean(const FindPlan& pl, const kf_tracks* seeds, const int32_
     const unsigned nb = blocks_for(seeds->n, 256);
     clean_reset_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, seeds->status, seed_event, n_events,
                                           seed_hits, n_hits, pl.clean_best);
-    clean_claim_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->chi2,
-                                          seeds->status, seed_event, n_events, seed_hits, n_hits,
-                                          pl.clean_best);
-    clean_mark_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
-                                         (const float*)seeds->chi2, seeds->status, seed_event,
-                                         n_events, seed_hits, n_hits, pl.clean_best, pl.cell,
-                                         pl.soff, pl.order, prm.clean_deta, prm.clean_dphi,
-                                         prm.clean_dc);
+    clean_claim_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
+                                          (const float*)seeds->chi2, seeds->status, seed_event,
+                                          n_events, seed_hits, n_hits, pl.order, pl.clean_best,
+                                          pl.clean_rec);
+    clean_mark_kernel<<<nb, 256, 0, s>>>(seeds->n, seeds->ld, seeds->status, seed_hits, n_hits,
+                                         pl.clean_best, pl.clean_rec, pl.cell, pl.soff, pl.order,
+                                         prm.clean_deta, prm.clean_dphi, prm.clean_dc);
     return hipGetLastError();
 }
 
@@ -1299,6 +1306,7 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     pl->bp = (int2*)take(sizeof(int2) * (size_t)grid * n_layers * seeds_per_tile * kMaxCands);
     pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);
     pl->clean_best = (unsigned long long*)take(sizeof(unsigned long long) * nh);
+    pl->clean_rec = (CleanRec*)take(sizeof(CleanRec) * ns);
     return off;
 }
 

@@ -73,6 +73,14 @@ struct FindArgs {
 };
 
 // Device scratch of one kf_find call, carved from the context workspace.
+// A seed as the cleaning compares it, stored at its position in cell order:
+// key = (chi2 as float, index), ~0 when the seed takes no part.
+struct CleanRec {
+    unsigned long long key;
+    double eta;
+    float phi, c;
+};
+
 struct FindPlan {
     BinLayout bl;
     int32_t* seg_cnt;   // [n_events * n_layers + 1] hits per (event, layer) segment
@@ -92,6 +100,7 @@ struct FindPlan {
     int2* bp;
     int32_t* tile_counter;
     unsigned long long* clean_best;  // [n_hits] best seed claiming each hit (seed cleaning)
+    CleanRec* clean_rec;      // [n_seeds] cleaning records in seed (cell) order
 };
 
 // Lays out the scratch of a call from `base` (nullptr: only sizes it); returns bytes.
