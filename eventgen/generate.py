@@ -96,7 +96,30 @@ def _highland(c, theta, t):
     return 0.0136 / (beta * p) * np.sqrt(t) * (1.0 + 0.038 * np.log(t / (beta * beta)))
 
 
-def transport(rng, st, q, geom, bz, smear_fn, max_steps=None):
+def _bethe_si(p, m):
+    """Mean ionisation loss in silicon [MeV cm^2/g] (Bethe formula with the
+    maximum energy transfer, no density effect): the truth simulation's
+    energy loss."""
+    me, K, za, I = 0.51099895, 0.307075, 0.49848, 173e-6
+    M = m * 1e3
+    E = np.sqrt((p * 1e3) ** 2 + M * M)
+    beta = p * 1e3 / E
+    gam = E / M
+    bg2 = (beta * gam) ** 2
+    tmax = 2 * me * bg2 / (1 + 2 * gam * me / M + (me / M) ** 2)
+    return K * za / beta ** 2 * (0.5 * np.log(2 * me * bg2 * tmax / I ** 2) - beta ** 2)
+
+
+def map_cell(mat, x, y, z):
+    """Cell values (x0, xi) of a material map at points (x, y, z)."""
+    nr, nz = mat["x0"].shape
+    ir = np.clip(np.floor(np.hypot(x, y) / (mat["r_max"] / nr)).astype(np.int64), 0, nr - 1)
+    iz = np.clip(np.floor((z - mat["z_min"]) / ((mat["z_max"] - mat["z_min"]) / nz)).astype(np.int64),
+                 0, nz - 1)
+    return mat["x0"][ir, iz].astype(np.float64), mat["xi"][ir, iz].astype(np.float64)
+
+
+def transport(rng, st, q, geom, bz, smear_fn, max_steps=None, material=None):
     """Walk every track through the detector.
 
     st: dict of float64 arrays x, y, z, c, phi, theta (production point).
@@ -104,7 +127,10 @@ def transport(rng, st, q, geom, bz, smear_fn, max_steps=None):
     transverse arc length) among the next barrel outward (radius above the
     current one, crossing within its z extent) and the first disk ahead in z
     whose crossing lies within its radial extent.  Tracks stop after half a
-    turn in the transverse plane or when no surface is left.
+    turn in the transverse plane or when no surface is left.  With a material
+    map (dict r_max, z_min, z_max, x0 [nr, nz], xi [nr, nz]) the thickness at
+    each crossing is the map's cell, and the particle also loses its mean
+    ionisation energy there (momentum magnitude only).
     Returns per-track lists of crossings: (layer, state6 at crossing, s).
     """
     n = st["x"].shape[0]
@@ -177,11 +203,25 @@ def transport(rng, st, q, geom, bz, smear_fn, max_steps=None):
         out_layer[go, step] = best_l[go]
         out_state[go, step] = np.stack([x, y, z, c, phi, th], axis=1)[go]
         # multiple scattering at the crossed surface
-        x0 = np.array([geom[i]["x0"] for i in range(nl)])[lay]
+        kind = np.array([geom[i]["kind"] for i in range(nl)])[lay]
+        if material is None:
+            x0 = np.array([geom[i]["x0"] for i in range(nl)])[lay]
+            xi = np.zeros(n)
+        else:
+            x0, xi = map_cell(material, x, y, z)
         mat = go & (x0 > 0)
         if mat.any():
-            kind = np.array([geom[i]["kind"] for i in range(nl)])[lay]
             c, phi, th = scatter_kick(rng, x, y, c, phi, th, kind, np.where(mat, x0, 0.0))
+        el = go & (xi > 0)
+        if el.any():
+            pos_phi = np.arctan2(y, x)
+            cosa = np.maximum(np.abs(np.where(kind == 0, np.sin(th) * np.cos(phi - pos_phi),
+                                              np.cos(th))), 1e-6)
+            p = 1.0 / (np.abs(c) * np.sin(th))
+            E = np.sqrt(p * p + PION_MASS ** 2)
+            dE = np.minimum(_bethe_si(p, PION_MASS) * xi / cosa * 1e-3, 0.5 * (E - PION_MASS))
+            p1 = np.sqrt((E - dE) ** 2 - PION_MASS ** 2)
+            c = np.where(el, c * p / p1, c)
         out_after[go, step] = np.stack([x, y, z, c, phi, th], axis=1)[go]
     return out_layer, out_state, out_after
 
@@ -253,7 +293,7 @@ def _layer_sigmas(geom):
 
 
 def make_event(rng, geom, n_tracks, pt_sampler, eta_max, n_noise_per_layer=0,
-               bz=G.BZ_TESLA, sig_fn=None, vertex_sigma=0.01):
+               bz=G.BZ_TESLA, sig_fn=None, vertex_sigma=0.01, material=None):
     """Generate one event: tracks from a Gaussian vertex, hits, noise, shuffle."""
     n = int(n_tracks)
     vx = rng.normal(0.0, vertex_sigma, n)
@@ -267,7 +307,7 @@ def make_event(rng, geom, n_tracks, pt_sampler, eta_max, n_noise_per_layer=0,
     c = q / pt
     st = dict(x=vx, y=vy, z=vz, c=c, phi=phi, theta=theta)
     truth0 = np.stack([vx, vy, vz, c, phi, theta], axis=1)
-    layers, states, after = transport(rng, st, q, geom, bz, None)
+    layers, states, after = transport(rng, st, q, geom, bz, None, material=material)
     if sig_fn is None:
         sig_fn = _layer_sigmas(geom)
     ti, si, lay, hx, hy, hz, hsu, hsv = _make_hits(rng, geom, layers, states, sig_fn)

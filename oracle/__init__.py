@@ -41,7 +41,10 @@ class _Cfg(C.Structure):
     _fields_ = [("n_layers", C.c_int), ("layers", C.POINTER(_Layer)), ("bz", C.c_double),
                 ("chi2_cut", C.c_double), ("max_cands", C.c_int), ("max_newton", C.c_int),
                 ("newton_tol", C.c_double), ("mass", C.c_double), ("max_miss", C.c_int),
-                ("use_material", C.c_int), ("field_z0", C.c_double), ("field_step", C.c_double)]
+                ("use_material", C.c_int), ("field_z0", C.c_double), ("field_step", C.c_double),
+                ("mat_nr", C.c_int), ("mat_nz", C.c_int), ("mat_rmax", C.c_double),
+                ("mat_zmin", C.c_double), ("mat_zmax", C.c_double),
+                ("mat_x0", C.POINTER(C.c_double)), ("mat_xi", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -77,6 +80,9 @@ def lib():
                               ip, ip, C.c_int]
         L.orc_find.argtypes = [cfgp, C.c_long, dp, dp, dp, dp, dp, ip, C.c_long, ip, C.c_int,
                                ip, dp, dp, dp, ip, ip, ip, lp, C.c_int]
+        L.orc_dedx.argtypes = [C.c_double, C.c_double]
+        L.orc_dedx.restype = C.c_double
+        L.orc_material.argtypes = [cfgp, C.c_int, dp, dp]
         L.orc_clean_seeds.argtypes = [C.c_long, dp, dp, ip, ip, ip, C.c_double, C.c_double,
                                       C.c_double, ip, ip]
         _lib = L
@@ -88,7 +94,7 @@ class Config:
 
     def __init__(self, geom, bz=3.8, chi2_cut=30.0, max_cands=6, max_newton=10,
                  newton_tol=1e-4, mass=0.13957, max_miss=2, material=None, field_z0=0.0,
-                 field_step=2.0):
+                 field_step=2.0, material_map=None):
         self.geom = geom
         arr = (_Layer * len(geom))()
         for i, L in enumerate(geom):
@@ -96,9 +102,19 @@ class Config:
                             int(L["nbin_phi"]), int(L["nbin_2"]), L["win_su"], L["win_sv"])
         self._arr = arr
         if material is None:
-            material = any(L["x0"] > 0 for L in geom)
+            material = any(L["x0"] > 0 for L in geom) or material_map is not None
         self.c = _Cfg(len(geom), arr, bz, chi2_cut, max_cands, max_newton, newton_tol, mass,
                       max_miss, int(bool(material)), field_z0, field_step)
+        if material_map is not None:
+            # dict(r_max, z_min, z_max, x0 [nr, nz], xi [nr, nz])
+            m = material_map
+            self._mx0 = np.ascontiguousarray(m["x0"], np.float64)
+            self._mxi = np.ascontiguousarray(m["xi"], np.float64)
+            self.c.mat_nr, self.c.mat_nz = self._mx0.shape
+            self.c.mat_rmax, self.c.mat_zmin, self.c.mat_zmax = m["r_max"], m["z_min"], m["z_max"]
+            dpp = C.POINTER(C.c_double)
+            self.c.mat_x0 = self._mx0.ctypes.data_as(dpp)
+            self.c.mat_xi = self._mxi.ctypes.data_as(dpp)
         self.ref = C.byref(self.c)
 
 
@@ -249,3 +265,17 @@ def clean_seeds(par, chi2, status, event, hits, deta=0.01, dphi=0.01, dc=0.05):
                           np.ascontiguousarray(hits, np.int32).reshape(-1), float(deta), float(dphi),
                           float(dc), keep, tie)
     return keep.astype(bool), tie.astype(bool)
+
+
+def dedx(p, m=0.13957):
+    """Mean ionisation loss in silicon [MeV cm^2/g] (Bethe, no density effect)."""
+    return lib().orc_dedx(float(p), float(m))
+
+
+def material(cfg, layer, q, Pk):
+    """Material effects (scattering noise, mean energy loss) at a crossing of
+    `layer` by state q: returns (q', Pk')."""
+    q = np.ascontiguousarray(q, np.float64).copy()
+    Pk = np.ascontiguousarray(Pk, np.float64).copy()
+    lib().orc_material(cfg.ref, int(layer), q, Pk)
+    return q, Pk

@@ -426,16 +426,24 @@ int orc_jacobian(const orc_cfg* cfg, int layer, const double p[6], double Fo[36]
 /* ------------------------------------------------------------------ */
 /* multiple-scattering process noise at a layer (PDG Highland formula)  */
 
-static void add_scatter(const orc_cfg* cfg, const orc_layer* L, const double q[6], double P[6][6])
+/* |cos| of the angle between the track and the surface normal */
+static double incidence(const orc_layer* L, const double q[6])
 {
-    if (!(L->x0 > 0.0)) return;
     double st = sin(q[5]), ct = cos(q[5]);
     double cosa;
     if (L->kind == 0) cosa = st * cos(q[4] - atan2(q[1], q[0]));
     else cosa = ct;
     cosa = fabs(cosa);
     if (cosa < 1e-6) cosa = 1e-6;
-    double t = L->x0 / cosa;
+    return cosa;
+}
+
+static void add_scatter(const orc_cfg* cfg, const orc_layer* L, double x0, const double q[6],
+                        double P[6][6])
+{
+    if (!(x0 > 0.0)) return;
+    double st = sin(q[5]), ct = cos(q[5]);
+    double t = x0 / incidence(L, q);
     double pmom = 1.0 / (fabs(q[3]) * st);
     double beta = pmom / sqrt(pmom * pmom + cfg->mass * cfg->mass);
     double th0 = 0.0136 / (beta * pmom) * sqrt(t) * (1.0 + 0.038 * log(t / (beta * beta)));
@@ -446,6 +454,84 @@ static void add_scatter(const orc_cfg* cfg, const orc_layer* L, const double q[6
     P[3][5] += -q[3] * cot * t2;
     P[5][3] += -q[3] * cot * t2;
     P[3][3] += q[3] * q[3] * cot * cot * t2;
+}
+
+/* Mean ionisation energy loss per unit areal density (PDG "Passage of
+ * particles through matter": the Bethe formula with the maximum energy
+ * transfer to an electron, without density-effect or shell corrections), for
+ * silicon: Z/A = 0.49848, I = 173 eV.  Units MeV cm^2 / g. */
+double orc_dedx(double p, double m)
+{
+    const double K = 0.307075, ZA = 0.49848, I = 173e-6, me = 0.51099895;  /* MeV */
+    double M = m * 1e3;
+    double pm = p * 1e3;
+    double E = sqrt(pm * pm + M * M);
+    double beta = pm / E, gamma = E / M;
+    double bg2 = beta * beta * gamma * gamma;
+    double tmax = 2.0 * me * bg2 / (1.0 + 2.0 * gamma * me / M + (me / M) * (me / M));
+    return K * ZA / (beta * beta) * (0.5 * log(2.0 * me * bg2 * tmax / (I * I)) - beta * beta);
+}
+
+/* Material at a crossing: the map's cell at the crossing point, else the
+ * layer's own thickness and no energy loss. */
+static void material_at(const orc_cfg* cfg, const orc_layer* L, const double q[6], double* x0,
+                        double* xi)
+{
+    if (!cfg->mat_x0) {
+        *x0 = L->x0;
+        *xi = 0.0;
+        return;
+    }
+    double r = hypot(q[0], q[1]);
+    int ir = (int)floor(r / (cfg->mat_rmax / cfg->mat_nr));
+    int iz = (int)floor((q[2] - cfg->mat_zmin) / ((cfg->mat_zmax - cfg->mat_zmin) / cfg->mat_nz));
+    if (ir < 0) ir = 0;
+    if (ir >= cfg->mat_nr) ir = cfg->mat_nr - 1;
+    if (iz < 0) iz = 0;
+    if (iz >= cfg->mat_nz) iz = cfg->mat_nz - 1;
+    *x0 = cfg->mat_x0[ir * cfg->mat_nz + iz];
+    *xi = cfg->mat_xi[ir * cfg->mat_nz + iz];
+}
+
+/* Mean energy loss over the crossed thickness xi / cos(alpha): the momentum
+ * magnitude drops to p' with E' = E - dE (the loss capped at half the
+ * kinetic energy: a track that would stop keeps a finite state), direction
+ * kept, so c' = c p / p'; the covariance follows the Jacobian
+ * dc'/dc = (p/p')^3 E'/E of the loss at fixed dE. */
+static void energy_loss(const orc_cfg* cfg, const orc_layer* L, double xi, double q[6],
+                        double P[6][6])
+{
+    if (!(xi > 0.0)) return;
+    double st = sin(q[5]);
+    double p = 1.0 / (fabs(q[3]) * st);
+    double m = cfg->mass;
+    double E = sqrt(p * p + m * m);
+    double dE = orc_dedx(p, m) * xi / incidence(L, q) * 1e-3;     /* GeV */
+    if (dE > 0.5 * (E - m)) dE = 0.5 * (E - m);
+    double E1 = E - dE;
+    double p1 = sqrt(E1 * E1 - m * m);
+    double J = (p / p1) * (p / p1) * (p / p1) * (E1 / E);
+    q[3] *= p / p1;
+    for (int k = 0; k < 6; ++k) {
+        P[3][k] *= J;
+        P[k][3] *= J;
+    }
+}
+
+static void material_effects(const orc_cfg* cfg, const orc_layer* L, double q[6], double P[6][6])
+{
+    double x0, xi;
+    material_at(cfg, L, q, &x0, &xi);
+    add_scatter(cfg, L, x0, q, P);
+    energy_loss(cfg, L, xi, q, P);
+}
+
+void orc_material(const orc_cfg* cfg, int layer, double q[6], double Pk[21])
+{
+    double P[6][6];
+    unpack(Pk, P);
+    material_effects(cfg, &cfg->layers[layer], q, P);
+    pack(P, Pk);
 }
 
 int orc_propagate(const orc_cfg* cfg, int layer, const double p[6], const double Pk[21],
@@ -463,7 +549,7 @@ int orc_propagate(const orc_cfg* cfg, int layer, const double p[6], const double
     unpack(Pk, P);
     mul66(F, P, T);
     mul66t(T, F, Pn);
-    if (add_noise) add_scatter(cfg, L, q, Pn);
+    if (add_noise) material_effects(cfg, L, q, Pn);
     memcpy(p_out, q, sizeof(q));
     pack(Pn, P_out);
     if (s_out) *s_out = s;

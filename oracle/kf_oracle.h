@@ -59,6 +59,15 @@ typedef struct {
     int use_material;   /* add process noise */
     double field_z0;    /* > 0: parametrised field (see orc_field), Bz = bz / (1 + (z/field_z0)^2) */
     double field_step;  /* largest integration step in the parametrised field [cm] */
+    /* optional r-z material map (mat_x0 NULL: the layers' own x0, no energy
+     * loss): cell (ir, iz) with ir = floor(r / (mat_rmax / mat_nr)) and
+     * iz = floor((z - mat_zmin) / ((mat_zmax - mat_zmin) / mat_nz)), clamped;
+     * x0 = radiation-length fraction, xi = areal density [g/cm^2] for the
+     * ionisation loss, both at normal incidence, arrays [mat_nr][mat_nz] */
+    int mat_nr, mat_nz;
+    double mat_rmax, mat_zmin, mat_zmax;
+    const double* mat_x0;
+    const double* mat_xi;
 } orc_cfg;
 
 /* helix transport by transverse arc length s */
@@ -118,6 +127,14 @@ void orc_find(const orc_cfg* cfg, long n_hits,
               int* out_hits, double* out_par, double* out_cov, double* out_chi2,
               int* out_ndf, int* out_status, int* out_tie_step, long* counters,
               int n_threads);
+
+/* Mean ionisation loss (Bethe, no density effect) in silicon [MeV cm^2/g]
+ * of a particle of momentum p and mass m [GeV]. */
+double orc_dedx(double p, double m);
+
+/* Material effects at a crossing of `layer` by state q (in place): the
+ * scattering noise and the mean energy loss, as in propagation. */
+void orc_material(const orc_cfg* cfg, int layer, double q[6], double Pk[21]);
 
 /* Seed cleaning within each event (see kf_oracle.c).  par [n][6], chi2 [n],
  * status [n] (only 0 takes part), event [n], hits [n][3] (-1 none).
