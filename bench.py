@@ -59,7 +59,8 @@ def parse():
 # HBM bytes per launch from the committed rocprofv3 counter summary, used
 # only while the finding kernel's sources are the ones it was measured on
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "find_pass_batch64_hbm_counters.json")
-KERNEL_SOURCES = ["kf_find.hip", "kf_find.hpp", "kf_math.hpp", "kf_mlp.hpp", "kf_internal.hpp"]
+KERNEL_SOURCES = ["kf_find.hip", "kf_find.hpp", "kf_math.hpp", "kf_mlp.hpp", "kf_internal.hpp",
+                  "kf_matmap.hpp"]
 
 
 def measured_traffic(kernel):

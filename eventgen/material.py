@@ -49,4 +49,19 @@ def eloss_sample(n_tracks=3000, seed=22, base=0.05, pt=(0.5, 1.0)):
     return geom, mat, ev
 
 
-__all__ = ["material_map", "eloss_sample", "X0_SI"]
+def eloss_find_events(n_events=3, n_tracks=800, n_noise=50_000, seed=23, base=0.03):
+    """The finding workload's shape (ten barrels, pT^-2 on 0.5-50 GeV, |eta|
+    < 1, uniform noise) with all material from an r-z map around `base` X0,
+    tracks simulated with scattering and energy loss.  Returns (geom, map,
+    events)."""
+    from .generate import pt_power2
+    rng = np.random.default_rng(seed)
+    geom = G.barrel10(x0=0.0)
+    mat = material_map(geom, base=base, seed=seed)
+    per_layer = n_noise // len(geom)
+    evs = [make_event(rng, geom, n_tracks, pt_power2(0.5, 50.0), 1.0, per_layer, material=mat)
+           for _ in range(n_events)]
+    return geom, mat, evs
+
+
+__all__ = ["material_map", "eloss_sample", "eloss_find_events", "X0_SI"]

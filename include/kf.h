@@ -128,6 +128,20 @@ typedef struct {
     const int32_t* layer;     /* layer index of each hit */
 } kf_hits;
 
+/* r-z material map (paper Sec. 3.1: scattering and energy loss from
+ * two-dimensional material arrays indexed in r-z).  Cell (ir, iz) with
+ * ir = floor(r / (r_max / nr)) and iz = floor((z - z_min) / ((z_max - z_min) /
+ * nz)), clamped to the grid, holds the radiation-length fraction x0 and the
+ * areal density xi [g/cm^2] of the surface crossing it, both at normal
+ * incidence.  Host arrays [nr][nz] float, copied. */
+typedef struct {
+    int32_t nr, nz;        /* 1 <= nr, nz; nr * nz <= 2^22 */
+    double r_max;          /* > 0 [cm] */
+    double z_min, z_max;   /* z_min < z_max [cm] */
+    const float* x0;       /* [nr][nz] >= 0 */
+    const float* xi;       /* [nr][nz] >= 0 */
+} kf_material;
+
 /* Create a context.  layers: host array of n_layers (<= 64) records, copied.
  * params: host, copied; NULL = defaults (3.8 T uniform, chi2 30, 6
  * candidates, 10 Newton iterations, 1e-4 cm, pion mass, 2 misses, 3 learned
@@ -139,6 +153,18 @@ void kf_destroy(kf_ctx* ctx);
 const char* kf_last_error(const kf_ctx* ctx);
 /* Library-wide last error for failures without a context (kf_create). */
 const char* kf_last_error_global(void);
+
+/* Sets (map != NULL) or removes (NULL) the context's r-z material map.  With
+ * a map, the material at each layer crossing (unless KF_NO_MATERIAL) comes
+ * from the map's cell at the crossing point instead of the layer's x0: the
+ * Highland scattering noise of x0 / cos(alpha), then the mean ionisation
+ * loss (Bethe formula with the maximum energy transfer, no density effect,
+ * silicon Z/A = 0.49848 and I = 173 eV, the context's mass) over
+ * xi / cos(alpha): |p| drops to p' with E' = E - dE (dE capped at half the
+ * kinetic energy), the direction is kept, c' = c p / p', and the covariance
+ * row and column of c are scaled by dc'/dc = (p/p')^3 E'/E.  Synchronous;
+ * do not call while work that uses the context is in flight. */
+int kf_set_material(kf_ctx* ctx, const kf_material* map);
 
 /* Seed states from three hits per track (paper Sec. 3.2: seeds): circle
  * through the transverse positions, tangent at hit 1, dip from the arc, prior

@@ -5,6 +5,7 @@ libkfmi.so.  If the library is missing the import of this module raises; there
 is no fallback implementation.
 """
 import ctypes as C
+import numpy as np
 import os
 
 import torch
@@ -32,6 +33,11 @@ class KfParams(C.Structure):
                 ("max_miss", C.c_int32), ("mlp_max_iter", C.c_int32), ("field_z0", C.c_double),
                 ("field_step", C.c_double), ("clean_deta", C.c_double), ("clean_dphi", C.c_double),
                 ("clean_dc", C.c_double)]
+
+
+class KfMaterial(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("r_max", C.c_double), ("z_min", C.c_double),
+                ("z_max", C.c_double), ("x0", C.c_void_p), ("xi", C.c_void_p)]
 
 
 class KfTracks(C.Structure):
@@ -73,6 +79,7 @@ def _load():
                           C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_find_batched.argtypes = [vp, C.POINTER(KfHits), vp, i32, vp, vp, vp, C.POINTER(KfTracks),
                                   vp, C.POINTER(KfTracks), vp, C.c_int, vp]
+    L.kf_set_material.argtypes = [vp, C.POINTER(KfMaterial)]
     L.kf_clean_seeds.argtypes = [vp, C.POINTER(KfHits), i32, C.POINTER(KfTracks), vp, vp, C.c_int,
                                  vp]
     L.kf_set_find_config.argtypes = [vp, i32, i32]
@@ -245,6 +252,20 @@ class Context:
         w, lf = C.c_int32(), C.c_int32()
         self._check(lib.kf_get_find_config(self.h, C.byref(w), C.byref(lf)), "kf_get_find_config")
         return int(w.value), bool(lf.value)
+
+    def set_material(self, m):
+        """r-z material map: dict(r_max, z_min, z_max, x0 [nr, nz], xi [nr, nz])
+        (host arrays, copied), or None to remove it."""
+        if m is None:
+            self._check(lib.kf_set_material(self.h, None), "kf_set_material")
+            return
+        x0 = np.ascontiguousarray(m["x0"], np.float32)
+        xi = np.ascontiguousarray(m["xi"], np.float32)
+        if x0.shape != xi.shape or x0.ndim != 2:
+            raise KFError("set_material: x0 and xi must be 2-D arrays of one shape")
+        km = KfMaterial(x0.shape[0], x0.shape[1], m["r_max"], m["z_min"], m["z_max"],
+                        x0.ctypes.data, xi.ctypes.data)
+        self._check(lib.kf_set_material(self.h, C.byref(km)), "kf_set_material")
 
     def clean_seeds(self, hits, n_events, seeds, seed_event, seed_hits, flags=0):
         """Seed cleaning: sets ST_DUPLICATE in seeds.status on removed seeds.

@@ -152,9 +152,10 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     int lw = 0;
     while ((1 << lw) < W) ++lw;
     const int pi = prec == KF_PREC_FP32 ? 1 : 0;
-    int& occ = ctx->occ_cache[learn ? 1 : 0][pi][lw];
+    const bool mat = ctx->mat.x0 != nullptr;
+    int& occ = ctx->occ_cache[mat ? 1 : 0][learn ? 1 : 0][pi][lw];
     if (occ == 0) {
-        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, learn, &occ);
+        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, learn, mat, &occ);
         if (e != hipSuccess) return hip_fail(ctx, e, "find occupancy");
         if (occ < 1) occ = 1;
     }
@@ -197,6 +198,7 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.n_layers = nl;
     a.prm = ctx->params;
     a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    a.mat = ctx->mat;
     a.n_tiles = (int)n_tiles;
     a.seeds_per_tile = S;
     a.mlp = ctx->mlp.dev();
@@ -354,6 +356,7 @@ void kf_destroy(kf_ctx* ctx)
     if (ctx->mlp_mem) (void)hipFree(ctx->mlp_mem);
     ctx->ws.release();
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
+    if (ctx->d_mat) (void)hipFree(ctx->d_mat);
     delete ctx;
 }
 
@@ -421,6 +424,51 @@ int kf_get_find_config(kf_ctx* ctx, int32_t* width, int32_t* largest_first)
         return fail(ctx, KF_EINVAL, "kf_get_find_config: null argument");
     *width = ctx->find_width;
     *largest_first = ctx->find_largest_first;
+    return KF_OK;
+}
+
+int kf_set_material(kf_ctx* ctx, const kf_material* m)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_set_material: null context");
+    if (m) {
+        if (m->nr < 1 || m->nz < 1 || (int64_t)m->nr * m->nz > (1LL << 22) || !(m->r_max > 0.0) ||
+            !(m->z_max > m->z_min) || !std::isfinite(m->r_max) || !std::isfinite(m->z_min) ||
+            !std::isfinite(m->z_max) || !m->x0 || !m->xi)
+            return fail(ctx, KF_EINVAL, "kf_set_material: bad map dimensions or null arrays");
+        const int64_t nc = (int64_t)m->nr * m->nz;
+        for (int64_t i = 0; i < nc; ++i)
+            if (!(m->x0[i] >= 0.0f) || !(m->xi[i] >= 0.0f) || !std::isfinite(m->x0[i]) ||
+                !std::isfinite(m->xi[i]))
+                return fail(ctx, KF_EINVAL, "kf_set_material: cell %lld is negative or not finite",
+                            (long long)i);
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_material");
+    if (ctx->d_mat) {
+        e = hipFree(ctx->d_mat);
+        ctx->d_mat = nullptr;
+        ctx->mat = kfmi::MatMap{};
+        if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_material free");
+    }
+    if (!m) return KF_OK;
+    const size_t nc = (size_t)m->nr * m->nz;
+    float* d = nullptr;
+    e = hipMalloc(&d, 2 * nc * sizeof(float));
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_material alloc");
+    e = hipMemcpy(d, m->x0, nc * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d + nc, m->xi, nc * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(ctx, e, "kf_set_material copy");
+    }
+    ctx->d_mat = d;
+    ctx->mat.x0 = d;
+    ctx->mat.xi = d + nc;
+    ctx->mat.nr = m->nr;
+    ctx->mat.nz = m->nz;
+    ctx->mat.r_max = m->r_max;
+    ctx->mat.z_min = m->z_min;
+    ctx->mat.z_max = m->z_max;
     return KF_OK;
 }
 
@@ -531,6 +579,7 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
     put((uint64_t)(uintptr_t)counters); put((uint64_t)flags); put((uint64_t)L.W);
     put((uint64_t)L.largest_first); put((uint64_t)L.grid);
     put((uint64_t)(uintptr_t)ctx->ws.ptr); put((uint64_t)ctx->ws.bytes);
+    put((uint64_t)(uintptr_t)ctx->mat.x0);
     kfmi::FindGraph& g = ctx->fg;
     const bool same = g.exec && g.nkey == nk && memcmp(g.key, key, sizeof(uint64_t) * nk) == 0;
     if (!same) {

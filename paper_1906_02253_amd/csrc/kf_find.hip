@@ -453,7 +453,7 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
 #define KF_FIND_WAVES 2
 #endif
 
-template <typename T, typename C, typename U, bool LEARN>
+template <typename T, typename C, typename U, bool LEARN, bool MAT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAVES))) void find_kernel(
     FindArgs a)
 {
@@ -604,7 +604,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     ++n_prop;
                     const kf_layer L = sh.layers[layer];
                     transport(p, P, s, kb, L.kind, T(L.r_or_z));
-                    if (a.material) add_scatter(p, P, L.kind, T(L.x0), T(a.prm.mass));
+                    if (a.material) {
+                        if constexpr (MAT)
+                            add_material(p, P, L, a.mat, T(a.prm.mass));
+                        else
+                            add_scatter(p, P, L.kind, T(L.x0), T(a.prm.mass));
+                    }
                     bool fin = true;
 #pragma unroll
                     for (int k = 0; k < 6; ++k) fin &= isfinite(p[k]);
@@ -1060,14 +1065,21 @@ size_t find_shared_size(int W, int S, int nl, int prec)
     return find_shared_bytes(W, S, nl, prec == KF_PREC_FP32 ? sizeof(float) : sizeof(double));
 }
 
-hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, int* out)
+template <typename T, typename C, typename U, bool LEARN>
+static hipError_t find_occ(bool mat, int W, size_t lds, int* out)
+{
+    return mat ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, true>, W, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, false>, W, lds);
+}
+
+hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, bool mat, int* out)
 {
     const size_t lds = find_shared_size(W, S, nl, prec);
     if (prec == KF_PREC_FP32)
-        return learn ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float, float, true>, W, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, float, float, false>, W, lds);
-    return learn ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double, double, true>, W, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<float, double, double, false>, W, lds);
+        return learn ? find_occ<float, float, float, true>(mat, W, lds, out)
+                     : find_occ<float, float, float, false>(mat, W, lds, out);
+    return learn ? find_occ<float, double, double, true>(mat, W, lds, out)
+                 : find_occ<float, double, double, false>(mat, W, lds, out);
 }
 
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
@@ -1310,15 +1322,24 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     return off;
 }
 
+template <typename T, typename C, typename U, bool LEARN>
+static void find_launch(const FindArgs& a, int W, int grid, size_t lds, hipStream_t s)
+{
+    if (a.mat.x0)
+        find_kernel<T, C, U, LEARN, true><<<grid, W, lds, s>>>(a);
+    else
+        find_kernel<T, C, U, LEARN, false><<<grid, W, lds, s>>>(a);
+}
+
 hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, bool learn, hipStream_t s)
 {
     const size_t lds = find_shared_size(W, a.seeds_per_tile, a.n_layers, prec);
     if (prec == KF_PREC_FP32)
-        learn ? find_kernel<float, float, float, true><<<grid, W, lds, s>>>(a)
-              : find_kernel<float, float, float, false><<<grid, W, lds, s>>>(a);
+        learn ? find_launch<float, float, float, true>(a, W, grid, lds, s)
+              : find_launch<float, float, float, false>(a, W, grid, lds, s);
     else
-        learn ? find_kernel<float, double, double, true><<<grid, W, lds, s>>>(a)
-              : find_kernel<float, double, double, false><<<grid, W, lds, s>>>(a);
+        learn ? find_launch<float, double, double, true>(a, W, grid, lds, s)
+              : find_launch<float, double, double, false>(a, W, grid, lds, s);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ __device__ inline void store_state(T* par, C* cov, int64_t ld, int64_t i, const 
 // to the straight-line start (counted in *fallbacks).
 template <typename T, typename C>
 __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_params& prm,
-                                   bool material, T s_init, T* s_out, int* evals, int* fallbacks)
+                                   bool material, const MatMap& mat, T s_init, T* s_out, int* evals,
+                                   int* fallbacks)
 {
     const T kb = T(kKappa) * T(prm.bz);
     T s;
@@ -61,7 +62,7 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
 #pragma unroll
         for (int k = 0; k < 6; ++k) p[k] = q[k];
         p[4] = wrap_phi(p[4]);
-        if (material) add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
+        if (material) add_material(p, P, L, mat, T(prm.mass));
         if (s_out) *s_out = l * sth;
         bool fin = true;
 #pragma unroll
@@ -87,7 +88,7 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
         if (s < T(0)) return KF_ST_UNREACHABLE;
     }
     transport(p, P, s, kb, L.kind, T(L.r_or_z));
-    if (material) add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
+    if (material) add_material(p, P, L, mat, T(prm.mass));
     if (s_out) *s_out = s;
     bool fin = true;
 #pragma unroll
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
                                                         const int32_t* __restrict__ target,
                                                         const kf_layer* __restrict__ layers,
                                                         int n_layers, kf_params prm, int material,
-                                                        float* __restrict__ path_len,
+                                                        MatMap mat, float* __restrict__ path_len,
                                                         int32_t* __restrict__ iters, MlpDev mlp)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
     }
     T s = T(0);
     int ev = 0, fb = 0;
-    int r = propagate_to(p, P, L, prm, material != 0, s_init, &s, &ev, &fb);
+    int r = propagate_to(p, P, L, prm, material != 0, mat, s_init, &s, &ev, &fb);
     if (fb) st |= KF_ST_FALLBACK;
     if (r) {
         st |= (uint32_t)r;
@@ -229,6 +230,7 @@ struct FitArgs {
     int n_layers;
     kf_params prm;
     int material;
+    MatMap mat;                  // r-z material map (x0 == nullptr: none)
     MlpDev mlp;                  // learned guess (KF_INIT_MLP)
 };
 
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
         }
         if (!alive) continue;
         int ev = 0, fb = 0;
-        int r = propagate_to(p, P, L, a.prm, a.material != 0, s_init, (T*)nullptr, &ev, &fb);
+        int r = propagate_to(p, P, L, a.prm, a.material != 0, a.mat, s_init, (T*)nullptr, &ev, &fb);
         touched = true;
         if (fb) st |= KF_ST_FALLBACK;
         if (r) {
@@ -357,7 +359,7 @@ hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* targ
 #define KF_PROP(TT, CC, LL)                                                                       \
     propagate_kernel<TT, CC, LL><<<g, 256, 0, s>>>(t->n, t->ld, (TT*)t->par, (CC*)t->cov, t->status, \
                                                    target, ctx->d_layers, ctx->n_layers, ctx->params, \
-                                                   material, path_len, iters, m)
+                                                   material, ctx->mat, path_len, iters, m)
     if (prec == KF_PREC_FP64) {
         if (learn) KF_PROP(double, double, true);
         else KF_PROP(double, double, false);
@@ -396,6 +398,7 @@ hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const i
     a.n_layers = ctx->n_layers;
     a.prm = ctx->params;
     a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
+    a.mat = ctx->mat;
     a.mlp = ctx->mlp.dev();
     const bool learn = (flags & KF_INIT_MLP) != 0;
     const int prec = flags & KF_PREC_MASK;

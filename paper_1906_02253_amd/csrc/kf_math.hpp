@@ -13,6 +13,7 @@
 #include <stdint.h>
 
 #include "../../include/kf.h"
+#include "kf_matmap.hpp"
 
 // Device functions that a host-side operation counter can also instantiate.
 #define KF_HD __host__ __device__
@@ -287,6 +288,71 @@ KF_HD inline void add_scatter(const T p[6], C P[21], int kind, T x0, T mass)
     P[pk(5, 5)] += C(t2);
     P[pk(3, 5)] += C(-p[3] * cot * t2);
     P[pk(3, 3)] += C(p[3] * p[3] * cot * cot * t2);
+}
+
+// Mean ionisation loss in silicon [MeV cm^2/g]: the Bethe formula with the
+// maximum energy transfer to an electron, no density effect (PDG, passage of
+// particles through matter); Z/A = 0.49848, I = 173 eV.  p, m in GeV.
+template <typename T>
+KF_HD inline T bethe_si(T p, T m)
+{
+    const T me = T(0.51099895), K = T(0.307075), za = T(0.49848), I = T(173e-6);
+    const T M = m * T(1e3), pm = p * T(1e3);
+    const T E = Tr<T>::sqrt_(pm * pm + M * M);
+    const T beta = pm / E, gam = E / M;
+    const T b2 = beta * beta;
+    const T bg2 = b2 * gam * gam;
+    const T r = me / M;
+    const T tmax = T(2) * me * bg2 / (T(1) + T(2) * gam * r + r * r);
+    return K * za / b2 * (T(0.5) * Tr<T>::log_(T(2) * me * bg2 * tmax / (I * I)) - b2);
+}
+
+// Material effects at the crossing of layer L by the propagated state:
+// without a map, the layer's scattering noise; with one, the cell at the
+// crossing point gives the thickness for the noise and the areal density for
+// the mean energy loss (|p| lowered at fixed direction, c' = c p/p', the
+// covariance's c row and column scaled by dc'/dc = (p/p')^3 E'/E).
+template <typename T, typename C>
+KF_HD inline void add_material(T p[6], C P[21], const kf_layer& L, const MatMap& m, T mass)
+{
+    if (!m.x0) {
+        add_scatter(p, P, L.kind, T(L.x0), mass);
+        return;
+    }
+    const double r = sqrt((double)p[0] * (double)p[0] + (double)p[1] * (double)p[1]);
+    int ir = (int)floor(r / (m.r_max / m.nr));
+    int iz = (int)floor(((double)p[2] - m.z_min) / ((m.z_max - m.z_min) / m.nz));
+    ir = ir < 0 ? 0 : (ir >= m.nr ? m.nr - 1 : ir);
+    iz = iz < 0 ? 0 : (iz >= m.nz ? m.nz - 1 : iz);
+    const T x0 = T(m.x0[ir * m.nz + iz]), xi = T(m.xi[ir * m.nz + iz]);
+    add_scatter(p, P, L.kind, x0, mass);
+    if (!(xi > T(0))) return;
+    T st, ct;
+    Tr<T>::sincos_(p[5], &st, &ct);
+    T cosa;
+    if (L.kind == 0) {
+        T sph, cph;
+        Tr<T>::sincos_(p[4], &sph, &cph);
+        const T rr = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+        cosa = st * (cph * p[0] + sph * p[1]) / rr;
+    } else {
+        cosa = ct;
+    }
+    cosa = Tr<T>::abs_(cosa);
+    if (cosa < T(1e-6)) cosa = T(1e-6);
+    const T pm = T(1) / (Tr<T>::abs_(p[3]) * st);
+    const T E = Tr<T>::sqrt_(pm * pm + mass * mass);
+    T dE = bethe_si(pm, mass) * xi / cosa * T(1e-3);
+    const T cap = T(0.5) * (E - mass);
+    if (dE > cap) dE = cap;
+    const T E1 = E - dE;
+    const T p1 = Tr<T>::sqrt_(E1 * E1 - mass * mass);
+    const T ratio = pm / p1;
+    const C J = C(ratio * ratio * ratio * (E1 / E));
+    p[3] *= ratio;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) P[pk(3, k)] *= J;
+    P[pk(3, 3)] *= J;
 }
 
 // Local frame of a hit: u along phi at the hit's azimuth, v along z (barrel)

@@ -1,0 +1,168 @@
+"""GPU parity with an r-z material map (scattering from the map's cell at
+each crossing, mean ionisation energy loss) against the FP64 oracle:
+propagation, the fit and finding, on tracks simulated with scattering and
+energy loss from the same map.  Tolerances as in tests/common.py; the
+all-FP64 path to rounding."""
+import numpy as np
+import pytest
+
+import eventgen as E
+import eventgen.material as EM
+from tests import common as CM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1906_02253_amd as K
+    from paper_1906_02253_amd import pipeline
+    K.pipeline = pipeline
+    return K
+
+
+@pytest.fixture(scope="module")
+def sample():
+    return EM.eloss_sample(n_tracks=3000, seed=22)
+
+
+def _fit(K, ctx, ev, flags=0):
+    import torch
+    n = ev.n_tracks
+    ld = CM.ld_of(n)
+    hits = K.Hits.from_event(ev)
+    sh = torch.as_tensor(CM.soa_int(ev.seq_hit[:, :3], ld), device="cuda")
+    lseq = torch.as_tensor(CM.soa_int(ev.seq_layer, ld), device="cuda")
+    hidx = torch.as_tensor(CM.soa_int(ev.seq_hit, ld), device="cuda")
+    t = K.Tracks(n, ld, flags & 3)
+    ctx.seed(hits, sh, t, flags)
+    ctx.fit(t, hits, lseq, hidx, ev.seq_layer.shape[1], flags)
+    torch.cuda.synchronize()
+    return t.numpy()
+
+
+def _oracle_fit(orc, geom, mat, ev):
+    par0, cov0 = orc.seeds_for_event(ev)
+    cfg = orc.Config(geom, material_map=mat)
+    return orc.fit(cfg, dict(x=ev.x, y=ev.y, z=ev.z, su=ev.su, sv=ev.sv), ev.seq_layer, ev.seq_hit,
+                   par0, cov0, n_threads=8)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_map_propagate_parity(K, orc, sample, prec):
+    """States at their crossing of layer k (after that layer's material)
+    propagated to layer k+1 with the map's scattering and energy loss."""
+    import torch
+    geom, mat, ev = sample
+    rng = np.random.default_rng(5)
+    nh = ev.n_track_hits()
+    rows = [(t, rng.integers(0, nh[t] - 1)) for t in range(ev.n_tracks) if nh[t] >= 2]
+    par = np.array([ev.truth_out[t, k] for t, k in rows])
+    tgt = np.array([ev.seq_layer[t, k + 1] for t, k in rows], np.int32)
+    n = par.shape[0]
+    cov = np.tile(orc.pack(np.diag([1e-4, 1e-4, 2e-3, 1e-4, 1e-5, 1e-5])), (n, 1))
+    ld = CM.ld_of(n)
+    pflag = K.PREC_FP64 if prec == "fp64" else K.PREC_MIXED
+    ctx = K.Context(geom)
+    ctx.set_material(mat)
+    t = K.Tracks.from_numpy(par, cov, prec=pflag, ld=ld)
+    target = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
+    target[:n] = torch.as_tensor(tgt, device="cuda")
+    ctx.propagate(t, target, flags=pflag)
+    torch.cuda.synchronize()
+    g = t.numpy()
+    cfg = orc.Config(geom, material_map=mat)
+    op, oc = np.zeros((n, 6)), np.zeros((n, 21))
+    for i in range(n):
+        st, op[i], oc[i], _, _ = orc.propagate(cfg, tgt[i], par[i], cov[i], noise=True)
+        assert st == 0
+    assert (g["status"] == 0).all()
+    err = CM.par_error(g["par"], op)
+    # energy loss changed c by a visible amount relative to the tolerance
+    assert np.abs(op[:, 3] / par[:, 3] - 1).mean() > 10 * CM.REL
+    rel = 1e-9 if prec == "fp64" else CM.REL
+    print(f"{prec}: {n} propagations, max rel par err {err.max():.2e}")
+    assert err.max() < rel, err.max(axis=0)
+    crel = 1e-9 if prec == "fp64" else 1e-3
+    for idx in (0, 6, 11, 15, 18, 20):
+        assert np.quantile(np.abs(g["cov"][:, idx] / oc[:, idx] - 1), 0.999) < crel, idx
+
+
+def test_map_fit_parity(K, orc, sample):
+    geom, mat, ev = sample
+    o = _oracle_fit(orc, geom, mat, ev)
+    ctx = K.Context(geom)
+    ctx.set_material(mat)
+    g = _fit(K, ctx, ev)
+    assert np.array_equal(g["status"], o["status"])
+    ok = o["status"] == 0
+    err = CM.par_error(g["par"][ok], o["par"][ok])
+    cerr = CM.chi2_error(g["chi2"][ok], o["chi2"][ok], o["ndf"][ok])
+    print(f"mixed: max rel par err {err.max():.2e}, chi2 err / tol {cerr.max() / CM.CHI2_REL:.3f}")
+    assert err.max() < CM.REL, err.max(axis=0)
+    assert cerr.max() < CM.CHI2_REL
+    g64 = _fit(K, ctx, ev, K.PREC_FP64)
+    e64 = CM.par_error(g64["par"][ok], o["par"][ok])
+    print(f"fp64: max rel par err {e64.max():.2e}")
+    assert e64.max() < 1e-9
+    # per layer = fused with the map too
+    b = _fit(K, ctx, ev, K.PER_LAYER)
+    for k in g:
+        assert np.array_equal(g[k], b[k]), k
+
+
+def test_map_removed_restores_plain(K, sample):
+    """set_material(None) gives back exactly the results of a context that
+    never had a map (the layers' own x0, no energy loss)."""
+    geom, mat, ev = sample
+    geom2 = [dict(L, x0=0.03) for L in geom]
+    a = _fit(K, K.Context(geom2), ev)
+    ctx = K.Context(geom2)
+    ctx.set_material(mat)
+    m = _fit(K, ctx, ev)
+    ctx.set_material(None)
+    b = _fit(K, ctx, ev)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert not np.array_equal(a["par"], m["par"])
+
+
+def test_bad_map_rejected(K, sample):
+    geom, mat, _ = sample
+    ctx = K.Context(geom)
+    for bad in (dict(mat, r_max=-1.0), dict(mat, z_min=400.0), dict(mat, x0=-mat["x0"] - 1),
+                dict(mat, xi=np.full_like(mat["xi"], np.nan))):
+        with pytest.raises(K.KFError):
+            ctx.set_material(bad)
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_map_find_matches_oracle(K, orc, batched):
+    """Finding on 3 events of 800 tracks and 50,000 noise hits, material and
+    energy loss from the map: hit lists against the FP64 oracle under the
+    finding tests' tie rules; eager and as the captured graph (recaptured
+    when the map changes)."""
+    import torch
+    geom, mat, evs = EM.eloss_find_events(n_events=3, n_tracks=800, n_noise=50_000)
+    inp = E.find_inputs(evs)
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    if batched:
+        fp.run_batched()                 # captured without a map, then with it
+        ctx.set_material(mat)
+        fp.run_batched()
+    else:
+        ctx.set_material(mat)
+        fp.run()
+    torch.cuda.synchronize()
+    g = fp.results()
+    o = CM.oracle_find_events(orc, geom, evs, inp, material_map=mat)
+    n_same, n_exc, bad = CM.compare_find(g, o)
+    print(f"map find: {n_same}/{g['hits'].shape[0]} identical, {n_exc} excused, {bad.size} unexplained")
+    assert bad.size == 0
+    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+    err = CM.par_error(g["par"][same], o["par"][same])
+    assert (err.max(axis=1) < CM.REL).mean() > 0.999
