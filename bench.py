@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--no-clean", action="store_true")
+    ap.add_argument("--no-material", action="store_true")
     ap.add_argument("--fit-tracks", type=int, default=4_000_000)
     ap.add_argument("--field-tracks", type=int, default=1_000_000)
     return ap.parse_args()
@@ -189,6 +190,97 @@ def run_fit(K, torch, n, w=None, reps=5):
 
 
 FIELD_Z0, FIELD_STEP = 300.0, 2.0
+
+
+def tile_fit_set(ev, n_total, ms=10):
+    """Step-major fit arrays of an event's tracks replicated at distinct
+    addresses up to n_total (step k of track i is hit k*ld+i)."""
+    ld = (n_total + 63) // 64 * 64
+    m = ev.n_tracks
+    bx = np.zeros((ms, m), np.float32)
+    by, bz_ = np.zeros_like(bx), np.zeros_like(bx)
+    bsu, bsv = np.full_like(bx, 0.01), np.full_like(bx, 0.05)
+    bl = np.zeros((ms, m), np.int32)
+    blseq = np.full((ms, m), -1, np.int32)
+    for s in range(ms):
+        hi = ev.seq_hit[:, s]
+        msk = hi >= 0
+        src = hi[msk]
+        bx[s, msk], by[s, msk], bz_[s, msk] = ev.x[src], ev.y[src], ev.z[src]
+        bsu[s, msk], bsv[s, msk], bl[s, msk] = ev.su[src], ev.sv[src], ev.layer[src]
+        blseq[s, msk] = ev.seq_layer[msk, s]
+    reps = (n_total + m - 1) // m
+
+    def tile(a, fill):
+        out = np.full((ms, ld), fill, a.dtype)
+        out[:, :n_total] = np.tile(a, (1, reps))[:, :n_total]
+        return out
+    lseq = tile(blseq, -1)
+    hits = dict(x=tile(bx, 0).reshape(-1), y=tile(by, 0).reshape(-1), z=tile(bz_, 0).reshape(-1),
+                su=tile(bsu, 0.01).reshape(-1), sv=tile(bsv, 0.05).reshape(-1),
+                layer=tile(bl, 0).reshape(-1))
+    hidx = np.where(lseq >= 0, (np.arange(ms)[:, None] * ld + np.arange(ld)[None, :]), -1)
+    return ld, hits, lseq, hidx.astype(np.int32)
+
+
+def time_fused_fit(K, torch, ctx, ld, hits_np, lseq_np, hidx_np, n, flags=0, reps=5):
+    """Mean kernel ms of kf_fit over n tracks (HIP events), seeding untimed."""
+    hits = K.Hits(hits_np["x"], hits_np["y"], hits_np["z"], hits_np["su"], hits_np["sv"],
+                  hits_np["layer"])
+    lseq = torch.as_tensor(lseq_np, device="cuda")
+    hidx = torch.as_tensor(hidx_np, device="cuda")
+    seed_hits = hidx[:3].contiguous()
+    t = K.Tracks(n, ld, flags & 3)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for r in range(-1, reps):
+        ctx.seed(hits, seed_hits, t, flags & 3)
+        if r >= 0:
+            ev[r][0].record(stream)
+        ctx.fit(t, hits, lseq, hidx, 10, flags=flags)
+        if r >= 0:
+            ev[r][1].record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def run_material(K, torch, steps, warmup, width, largest_first, n_fit):
+    """The r-z material map with energy loss against constant per-layer
+    material: the batched finding pass on a 64-event batch simulated with the
+    map (scattering and energy loss), and the fused fit of n_fit tracks."""
+    import eventgen as E
+    import eventgen.material as EM
+    from paper_1906_02253_amd import pipeline
+    geom, mat, evs = EM.eloss_batch(seed=2)
+    inp = E.find_inputs(evs)
+    n_seeds = int(inp["seed_hits"].shape[0])
+    out = {"workload": "64-event batch (seed 2) simulated with scattering and energy loss from an "
+                       "r-z map (250 x 250 cells, ~0.02 X0 per surface); finding pass with the map "
+                       "vs constant 0.02 X0 per layer without energy loss; fused fit of "
+                       f"{n_fit} tracks (pT 0.5-1 GeV, ~0.05 X0) likewise",
+           "n_seeds": n_seeds}
+    for name, g, m in (("layer_x0", [dict(L, x0=0.02) for L in geom], None), ("map", geom, mat)):
+        ctx = K.Context(g)
+        ctx.set_find_config(width, largest_first)
+        if m is not None:
+            ctx.set_material(m)
+        fp = pipeline.FindProblem(ctx, inp)
+        ms, ph, cnt = timed_pass(torch, ctx, fp, 0, steps, warmup)
+        kf = 3 * n_seeds + float(cnt[0])
+        out["find_" + name] = {"ms_per_pass": ms, "steps_per_s": kf / (ms * 1e-3),
+                               "find_kernel_ms": ph[3], "kf_steps_per_pass": kf}
+    fgeom, fmat, fev = EM.eloss_sample(n_tracks=100_000, seed=24)
+    ld, hits, lseq, hidx = tile_fit_set(fev, n_fit)
+    n_steps = int((lseq[:, :n_fit] >= 0).sum())
+    for name, g, m in (("layer_x0", [dict(L, x0=0.05) for L in fgeom], None), ("map", fgeom, fmat)):
+        ctx = K.Context(g)
+        if m is not None:
+            ctx.set_material(m)
+        ms = time_fused_fit(K, torch, ctx, ld, hits, lseq, hidx, n_fit)
+        out["fit_" + name] = {"kernel_ms": ms, "steps_per_s": n_steps / (ms * 1e-3),
+                              "kf_steps": n_steps}
+    return out
 
 
 def build_field_fit_set(n_total, n_unique=100_000, seed=7):
@@ -546,6 +638,14 @@ def main():
               f"searched; pass {sc['no_cleaning']['ms_per_pass']:.3f} -> "
               f"{sc['cleaning']['ms_per_pass']:.3f} ms (cleaning {sc['cleaning_ms']:.3f} ms)",
               file=sys.stderr, flush=True)
+
+    if not args.no_material:
+        result["material_map"] = run_material(K, torch, args.steps, args.warmup, width,
+                                              largest_first, 1_000_000)
+        mm = result["material_map"]
+        print(f"# material map: find pass {mm['find_layer_x0']['ms_per_pass']:.3f} -> "
+              f"{mm['find_map']['ms_per_pass']:.3f} ms; fit {mm['fit_layer_x0']['steps_per_s']:.3e} "
+              f"-> {mm['fit_map']['steps_per_s']:.3e} steps/s", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         import oracle

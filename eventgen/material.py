@@ -64,4 +64,23 @@ def eloss_find_events(n_events=3, n_tracks=800, n_noise=50_000, seed=23, base=0.
     return geom, mat, evs
 
 
-__all__ = ["material_map", "eloss_sample", "eloss_find_events", "X0_SI"]
+def eloss_batch(seed=2, base=0.02, noise_per_track=60, lam_lo=200.0, lam_hi=4000.0,
+                n_events=64):
+    """The uneven-multiplicity batch's shape (64 events, N ~ Poisson(U(200,
+    4000)), 60 noise hits per track, ten barrels + 2 x 7 disks, |eta| < 2.5)
+    with all material from an r-z map around `base` X0 and tracks simulated
+    with scattering and energy loss.  Returns (geom, map, events)."""
+    from .generate import pt_power2
+    rng = np.random.default_rng(seed)
+    geom = G.barrel10_disks14(x0=0.0)
+    mat = material_map(geom, base=base, seed=seed)
+    evs = []
+    for _ in range(n_events):
+        lam = rng.uniform(lam_lo, lam_hi)
+        n = max(1, int(rng.poisson(lam)))
+        per_layer = noise_per_track * n // len(geom)
+        evs.append(make_event(rng, geom, n, pt_power2(0.5, 50.0), 2.5, per_layer, material=mat))
+    return geom, mat, evs
+
+
+__all__ = ["material_map", "eloss_sample", "eloss_find_events", "eloss_batch", "X0_SI"]
