@@ -59,3 +59,33 @@ def barrel10_disks14(x0=0.02, su=0.01, sv=0.05):
 
 LAYER_FIELDS = ("kind", "r_or_z", "lo", "hi", "x0", "nbin_phi", "nbin_2",
                 "win_su", "win_sv")
+
+
+def steering_plans(geom, edges=(0.8, 1.6, 2.5), n_eta=41):
+    """Tracking regions and their layer plans: five regions in eta (barrel
+    |eta| < edges[0], transitions up to edges[1], endcaps up to edges[2], both
+    signs).  A region's plan lists every layer a straight line from the origin
+    crosses (inside the layer's extent) for some eta sampled in the region,
+    ordered by the median path length to it over those etas.  Returns a list
+    of dict(eta_lo, eta_hi, layers)."""
+    import numpy as np
+    e0, e1, e2 = edges
+    bounds = [(-e2, -e1), (-e1, -e0), (-e0, e0), (e0, e1), (e1, e2)]
+    out = []
+    for lo, hi in bounds:
+        etas = np.linspace(lo, hi, n_eta)[1:-1]
+        paths = {}
+        for eta in etas:
+            sh, ch = np.sinh(eta), np.cosh(eta)
+            for i, L in enumerate(geom):
+                if L["kind"] == 0:
+                    z = L["r_or_z"] * sh
+                    if L["lo"] <= z <= L["hi"]:
+                        paths.setdefault(i, []).append(L["r_or_z"] * ch)
+                elif sh != 0 and np.sign(L["r_or_z"]) == np.sign(sh):
+                    r = L["r_or_z"] / sh
+                    if L["lo"] <= r <= L["hi"]:
+                        paths.setdefault(i, []).append(abs(L["r_or_z"]) * ch / abs(sh))
+        plan = sorted(paths, key=lambda i: float(np.median(paths[i])))
+        out.append(dict(eta_lo=float(lo), eta_hi=float(hi), layers=[int(i) for i in plan]))
+    return out

@@ -37,6 +37,11 @@ class _Layer(C.Structure):
                 ("nbin_2", C.c_int), ("win_su", C.c_double), ("win_sv", C.c_double)]
 
 
+class _Region(C.Structure):
+    _fields_ = [("eta_lo", C.c_double), ("eta_hi", C.c_double), ("n", C.c_int),
+                ("layers", C.c_int * 64)]
+
+
 class _Cfg(C.Structure):
     _fields_ = [("n_layers", C.c_int), ("layers", C.POINTER(_Layer)), ("bz", C.c_double),
                 ("chi2_cut", C.c_double), ("max_cands", C.c_int), ("max_newton", C.c_int),
@@ -44,7 +49,8 @@ class _Cfg(C.Structure):
                 ("use_material", C.c_int), ("field_z0", C.c_double), ("field_step", C.c_double),
                 ("mat_nr", C.c_int), ("mat_nz", C.c_int), ("mat_rmax", C.c_double),
                 ("mat_zmin", C.c_double), ("mat_zmax", C.c_double),
-                ("mat_x0", C.POINTER(C.c_double)), ("mat_xi", C.POINTER(C.c_double))]
+                ("mat_x0", C.POINTER(C.c_double)), ("mat_xi", C.POINTER(C.c_double)),
+                ("n_regions", C.c_int), ("regions", C.POINTER(_Region))]
 
 
 _lib = None
@@ -94,7 +100,7 @@ class Config:
 
     def __init__(self, geom, bz=3.8, chi2_cut=30.0, max_cands=6, max_newton=10,
                  newton_tol=1e-4, mass=0.13957, max_miss=2, material=None, field_z0=0.0,
-                 field_step=2.0, material_map=None):
+                 field_step=2.0, material_map=None, steering=None):
         self.geom = geom
         arr = (_Layer * len(geom))()
         for i, L in enumerate(geom):
@@ -105,6 +111,16 @@ class Config:
             material = any(L["x0"] > 0 for L in geom) or material_map is not None
         self.c = _Cfg(len(geom), arr, bz, chi2_cut, max_cands, max_newton, newton_tol, mass,
                       max_miss, int(bool(material)), field_z0, field_step)
+        if steering:
+            # [dict(eta_lo, eta_hi, layers=[...]), ...]: tracking regions and plans
+            self._reg = (_Region * len(steering))()
+            for g, R in enumerate(steering):
+                self._reg[g].eta_lo, self._reg[g].eta_hi = R["eta_lo"], R["eta_hi"]
+                self._reg[g].n = len(R["layers"])
+                for q, l in enumerate(R["layers"]):
+                    self._reg[g].layers[q] = int(l)
+            self.c.n_regions = len(steering)
+            self.c.regions = self._reg
         if material_map is not None:
             # dict(r_max, z_min, z_max, x0 [nr, nz], xi [nr, nz])
             m = material_map

@@ -778,6 +778,7 @@ typedef struct {
     double p[6], P[21];
     double chi2;
     int nhits, misses, done, status;
+    int pos;                 /* steering: next plan entry */
     int hits[MAXL];
 } cand_t;
 
@@ -948,6 +949,78 @@ static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close
         }
     }
     return best_l;
+}
+
+/*
+ * Steering (Sec. 3.1: a tracking region's list of layers to traverse).  From
+ * plan entry *pos on, the first layer the candidate actually reaches: a
+ * barrel outside rho + NEXT_BARREL_EPS whose outward crossing lies within
+ * half a turn and inside |z| <= hi, or a disk ahead (|dz| > DISK_AHEAD_EPS)
+ * crossed within half a turn inside its radial extent.  Entries not reached
+ * are passed over.  Returns the layer (and sets *pos past it) or -1 when the
+ * plan is exhausted; a failed barrel solve sets NOCONV and returns -1.
+ */
+static int steer(const orc_cfg* cfg, const orc_region* R, int* pos, const double p[6], int* stat,
+                 int* close)
+{
+    double rho = hypot(p[0], p[1]);
+    double hh = fabs(KAPPA * cfg->bz * p[3]);
+    double s_max = hh > 0.0 ? PI / hh : INFINITY;
+    double cot = cos(p[5]) / sin(p[5]);
+    for (; *pos < R->n; ++*pos) {
+        int l = R->layers[*pos];
+        const orc_layer* L = &cfg->layers[l];
+        if (L->kind == 0) {
+            if (fabs(L->r_or_z - (rho + NEXT_BARREL_EPS)) < CLOSE_REL * NEXT_BARREL_EPS) *close = 1;
+            if (!(L->r_or_z > rho + NEXT_BARREL_EPS)) continue;
+            double h = -KAPPA * cfg->bz * p[3];
+            if (h != 0.0) {
+                double cx = p[0] - sin(p[4]) / h, cy = p[1] + cos(p[4]) / h;
+                double rmax = hypot(cx, cy) + 1.0 / fabs(h);
+                if (fabs(rmax - L->r_or_z) < CLOSE_REL * L->r_or_z) *close = 1;
+            }
+            double s;
+            int st = orc_solve_barrel(cfg, p, L->r_or_z, -1.0, &s, NULL);
+            if (st == ORC_ST_NOCONV) {
+                *stat |= ORC_ST_NOCONV;
+                return -1;
+            }
+            if (st != ORC_ST_OK) continue;
+            double zc = p[2] + s * cot;
+            if (fabs(fabs(zc) - L->hi) < CLOSE_REL * L->hi) *close = 1;
+            if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+            if (fabs(zc) > L->hi || s > s_max) continue;
+        } else {
+            double dz = L->r_or_z - p[2];
+            if (fabs(fabs(dz) - DISK_AHEAD_EPS) < CLOSE_REL * DISK_AHEAD_EPS) *close = 1;
+            if (!(dz * cot > 0.0) || fabs(dz) <= DISK_AHEAD_EPS) continue;
+            double s = dz / cot;
+            if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+            if (s > s_max) continue;
+            double q[6];
+            orc_helix(p, s, cfg->bz, q);
+            double r = hypot(q[0], q[1]);
+            if (fabs(r - L->lo) < CLOSE_REL * L->lo || fabs(r - L->hi) < CLOSE_REL * L->hi) *close = 1;
+            if (r < L->lo || r > L->hi) continue;
+        }
+        ++*pos;
+        return l;
+    }
+    return -1;
+}
+
+/* The region of a seed state (first containing its eta), or -1; *close when
+ * eta lies within 1e-3 of a region edge. */
+static int seed_region(const orc_cfg* cfg, const double p[6], int* close)
+{
+    double eta = -log(tan(0.5 * p[5]));
+    for (int g = 0; g < cfg->n_regions; ++g) {
+        const orc_region* R = &cfg->regions[g];
+        if (fabs(eta - R->eta_lo) < 1e-3 || fabs(eta - R->eta_hi) < 1e-3) *close = 1;
+    }
+    for (int g = 0; g < cfg->n_regions; ++g)
+        if (eta >= cfg->regions[g].eta_lo && eta < cfg->regions[g].eta_hi) return g;
+    return -1;
 }
 
 /* hits inside the window of a predicted state; returns count, writes (chi2, idx)
@@ -1149,6 +1222,27 @@ static void find_seed(find_job* J, long sd)
         c0->hits[layer] = (int)hi;
     }
     c0->done = c0->status != 0;
+    /* steering: the seed's region, and the plan entry after its last seed layer */
+    const orc_region* R = NULL;
+    c0->pos = 0;
+    if (cfg->n_regions > 0 && !c0->done) {
+        int close0 = 0;
+        int g = seed_region(cfg, c0->p, &close0);
+        if (close0) tie = 0;
+        int start = -1;
+        if (g >= 0) {
+            R = &cfg->regions[g];
+            for (int k = 0; k < 3; ++k)
+                for (int q = 0; q < R->n; ++q)
+                    if (R->layers[q] == E->hlayer[sh[k]] && q + 1 > start) start = q + 1;
+        }
+        if (start < 0) {
+            c0->status |= ORC_ST_UNREACHABLE;
+            c0->done = 1;
+        } else {
+            c0->pos = start;
+        }
+    }
     int nc = 1;
 
     for (int step = 0; step < nl; ++step) {
@@ -1165,7 +1259,8 @@ static void find_seed(find_job* J, long sd)
             pred_layer[k] = -1;
             if (!cd->done) {
                 int st = 0;
-                int layer = navigate(cfg, cd->p, &st, &close);
+                int layer = R ? steer(cfg, R, &cd->pos, cd->p, &st, &close)
+                              : navigate(cfg, cd->p, &st, &close);
                 if (layer < 0) {
                     cd->done = 1;
                     cd->status |= st;

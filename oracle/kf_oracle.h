@@ -46,6 +46,14 @@ typedef struct {
     double win_su, win_sv;
 } orc_layer;
 
+/* A tracking region and its layer plan (Sec. 3.1 steering): seeds with eta
+ * in [eta_lo, eta_hi) follow `layers` in this order. */
+typedef struct {
+    double eta_lo, eta_hi;
+    int n;
+    int layers[64];
+} orc_region;
+
 typedef struct {
     int n_layers;
     const orc_layer* layers;
@@ -68,6 +76,9 @@ typedef struct {
     double mat_rmax, mat_zmin, mat_zmax;
     const double* mat_x0;
     const double* mat_xi;
+    /* optional steering (n_regions 0: dynamic navigation) */
+    int n_regions;
+    const orc_region* regions;
 } orc_cfg;
 
 /* helix transport by transverse arc length s */
