@@ -154,6 +154,30 @@ const char* kf_last_error(const kf_ctx* ctx);
 /* Library-wide last error for failures without a context (kf_create). */
 const char* kf_last_error_global(void);
 
+/* Tracking regions with layer plans (paper Sec. 3.1: regions in eta with
+ * steering parameters that list the layers finding traverses; the finder
+ * follows them without knowing the detector's structure). */
+#define KF_MAX_REGIONS 8
+typedef struct {
+    double eta_lo, eta_hi;   /* seeds with eta = -ln tan(theta/2) in [eta_lo, eta_hi) */
+    int32_t n_layers;        /* plan length, 1..64 */
+    int32_t layers[64];      /* layer indices in traversal order, each at most once */
+} kf_region;
+
+/* Sets (n_regions >= 1) or removes (regions NULL or n_regions 0) steering
+ * for kf_find / kf_find_batched.  With steering a seed takes the first
+ * region containing its eta (none: KF_ST_UNREACHABLE, not searched); its
+ * search starts after the last plan entry that is one of its seed hits'
+ * layers (none: KF_ST_UNREACHABLE); at each step a candidate takes, from its
+ * plan position on, the first layer it actually reaches - a barrel outside
+ * rho + 0.05 cm crossed outward within half a turn inside |z| <= hi, or a
+ * disk ahead (|dz| > 0.05 cm) crossed within half a turn inside its radial
+ * extent - passing over entries it does not reach.  Without steering the
+ * next surface is found dynamically (the first reached of the next barrel
+ * outward and the next disk ahead).  Steering excludes KF_INIT_MLP.
+ * Synchronous; do not call while work that uses the context is in flight. */
+int kf_set_steering(kf_ctx* ctx, const kf_region* regions, int32_t n_regions);
+
 /* Sets (map != NULL) or removes (NULL) the context's r-z material map.  With
  * a map, the material at each layer crossing (unless KF_NO_MATERIAL) comes
  * from the map's cell at the crossing point instead of the layer's x0: the

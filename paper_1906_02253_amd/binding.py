@@ -40,6 +40,11 @@ class KfMaterial(C.Structure):
                 ("z_max", C.c_double), ("x0", C.c_void_p), ("xi", C.c_void_p)]
 
 
+class KfRegion(C.Structure):
+    _fields_ = [("eta_lo", C.c_double), ("eta_hi", C.c_double), ("n_layers", C.c_int32),
+                ("layers", C.c_int32 * 64)]
+
+
 class KfTracks(C.Structure):
     _fields_ = [("n", C.c_int64), ("ld", C.c_int64), ("par", C.c_void_p), ("cov", C.c_void_p),
                 ("chi2", C.c_void_p), ("ndf", C.c_void_p), ("status", C.c_void_p)]
@@ -80,6 +85,7 @@ def _load():
     L.kf_find_batched.argtypes = [vp, C.POINTER(KfHits), vp, i32, vp, vp, vp, C.POINTER(KfTracks),
                                   vp, C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_set_material.argtypes = [vp, C.POINTER(KfMaterial)]
+    L.kf_set_steering.argtypes = [vp, C.POINTER(KfRegion), i32]
     L.kf_clean_seeds.argtypes = [vp, C.POINTER(KfHits), i32, C.POINTER(KfTracks), vp, vp, C.c_int,
                                  vp]
     L.kf_set_find_config.argtypes = [vp, i32, i32]
@@ -252,6 +258,23 @@ class Context:
         w, lf = C.c_int32(), C.c_int32()
         self._check(lib.kf_get_find_config(self.h, C.byref(w), C.byref(lf)), "kf_get_find_config")
         return int(w.value), bool(lf.value)
+
+    def set_steering(self, regions):
+        """Tracking regions and layer plans: [dict(eta_lo, eta_hi, layers=[...]),
+        ...] (at most 8, plans of at most 64 layers), or None for dynamic
+        navigation."""
+        if not regions:
+            self._check(lib.kf_set_steering(self.h, None, 0), "kf_set_steering")
+            return
+        arr = (KfRegion * len(regions))()
+        for g, R in enumerate(regions):
+            lay = list(R["layers"])
+            if len(lay) > 64:
+                raise KFError("set_steering: a plan holds at most 64 layers")
+            arr[g].eta_lo, arr[g].eta_hi, arr[g].n_layers = R["eta_lo"], R["eta_hi"], len(lay)
+            for q, l in enumerate(lay):
+                arr[g].layers[q] = int(l)
+        self._check(lib.kf_set_steering(self.h, arr, len(regions)), "kf_set_steering")
 
     def set_material(self, m):
         """r-z material map: dict(r_max, z_min, z_max, x0 [nr, nz], xi [nr, nz])

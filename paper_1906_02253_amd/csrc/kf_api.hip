@@ -123,6 +123,8 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
         return fail(ctx, KF_EUNSUPPORTED, "%s: finding runs in the uniform field only", what);
     const bool learn = (flags & KF_INIT_MLP) != 0;
     if (learn && !ctx->mlp_loaded) return fail(ctx, KF_EUNSUPPORTED, "%s: no learned model loaded", what);
+    if (learn && ctx->d_steer)
+        return fail(ctx, KF_EUNSUPPORTED, "%s: steering and the learned guess exclude each other", what);
     if (learn && ctx->find_width < 64)
         return fail(ctx, KF_EUNSUPPORTED, "%s: the learned guess needs a width of at least 64", what);
     if (out->n != seeds->n) return fail(ctx, KF_EINVAL, "%s: out->n must equal seeds->n", what);
@@ -153,9 +155,10 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     while ((1 << lw) < W) ++lw;
     const int pi = prec == KF_PREC_FP32 ? 1 : 0;
     const bool mat = ctx->mat.x0 != nullptr;
-    int& occ = ctx->occ_cache[mat ? 1 : 0][learn ? 1 : 0][pi][lw];
+    const bool steer = ctx->d_steer != nullptr;
+    int& occ = ctx->occ_cache[steer ? 1 : 0][mat ? 1 : 0][learn ? 1 : 0][pi][lw];
     if (occ == 0) {
-        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, learn, mat, &occ);
+        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, learn, mat, steer, &occ);
         if (e != hipSuccess) return hip_fail(ctx, e, "find occupancy");
         if (occ < 1) occ = 1;
     }
@@ -199,6 +202,7 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.prm = ctx->params;
     a.material = (flags & KF_NO_MATERIAL) ? 0 : 1;
     a.mat = ctx->mat;
+    a.steer = ctx->d_steer;
     a.n_tiles = (int)n_tiles;
     a.seeds_per_tile = S;
     a.mlp = ctx->mlp.dev();
@@ -357,6 +361,7 @@ void kf_destroy(kf_ctx* ctx)
     ctx->ws.release();
     if (ctx->d_layers) (void)hipFree(ctx->d_layers);
     if (ctx->d_mat) (void)hipFree(ctx->d_mat);
+    if (ctx->d_steer) (void)hipFree(ctx->d_steer);
     delete ctx;
 }
 
@@ -424,6 +429,53 @@ int kf_get_find_config(kf_ctx* ctx, int32_t* width, int32_t* largest_first)
         return fail(ctx, KF_EINVAL, "kf_get_find_config: null argument");
     *width = ctx->find_width;
     *largest_first = ctx->find_largest_first;
+    return KF_OK;
+}
+
+int kf_set_steering(kf_ctx* ctx, const kf_region* regions, int32_t n_regions)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_set_steering: null context");
+    const bool set = regions && n_regions > 0;
+    kfmi::SteerDev h{};
+    if (set) {
+        if (n_regions > kfmi::kMaxRegions)
+            return fail(ctx, KF_EINVAL, "kf_set_steering: at most %d regions", kfmi::kMaxRegions);
+        h.n = n_regions;
+        for (int g = 0; g < n_regions; ++g) {
+            const kf_region& R = regions[g];
+            if (!(R.eta_lo < R.eta_hi) || R.n_layers < 1 || R.n_layers > kfmi::kMaxPlan)
+                return fail(ctx, KF_EINVAL, "kf_set_steering: region %d has a bad eta range or length", g);
+            bool seen[kfmi::kMaxLayers] = {};
+            for (int q = 0; q < R.n_layers; ++q) {
+                const int l = R.layers[q];
+                if (l < 0 || l >= ctx->n_layers || seen[l])
+                    return fail(ctx, KF_EINVAL, "kf_set_steering: region %d entry %d: bad or repeated layer",
+                                g, q);
+                seen[l] = true;
+                h.layers[g][q] = (uint8_t)l;
+            }
+            h.len[g] = R.n_layers;
+            h.eta_lo[g] = R.eta_lo;
+            h.eta_hi[g] = R.eta_hi;
+        }
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_steering");
+    if (ctx->d_steer) {
+        e = hipFree(ctx->d_steer);
+        ctx->d_steer = nullptr;
+        if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_steering free");
+    }
+    if (!set) return KF_OK;
+    kfmi::SteerDev* d = nullptr;
+    e = hipMalloc(&d, sizeof(kfmi::SteerDev));
+    if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_steering alloc");
+    e = hipMemcpy(d, &h, sizeof(h), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(ctx, e, "kf_set_steering copy");
+    }
+    ctx->d_steer = d;
     return KF_OK;
 }
 
@@ -580,6 +632,7 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
     put((uint64_t)L.largest_first); put((uint64_t)L.grid);
     put((uint64_t)(uintptr_t)ctx->ws.ptr); put((uint64_t)ctx->ws.bytes);
     put((uint64_t)(uintptr_t)ctx->mat.x0);
+    put((uint64_t)(uintptr_t)ctx->d_steer);
     kfmi::FindGraph& g = ctx->fg;
     const bool same = g.exec && g.nkey == nk && memcmp(g.key, key, sizeof(uint64_t) * nk) == 0;
     if (!same) {

@@ -453,7 +453,7 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
 #define KF_FIND_WAVES 2
 #endif
 
-template <typename T, typename C, typename U, bool LEARN, bool MAT>
+template <typename T, typename C, typename U, bool LEARN, bool MAT, bool STEER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAVES))) void find_kernel(
     FindArgs a)
 {
@@ -575,6 +575,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
 #pragma unroll
             for (int k = 0; k < 21; ++k) P[k] = C(0);
         }
+        // steering: the seed's region and the plan entry after its last seed
+        // layer (every lane of the seed computes the same)
+        int rg = 0, pos = 0;
+        if constexpr (STEER) {
+            if (valid) {
+                const double eta = -log(tan(0.5 * (double)a.spar[5 * a.sld + sid]));
+                rg = -1;
+                for (int g = 0; g < a.steer->n; ++g)
+                    if (eta >= a.steer->eta_lo[g] && eta < a.steer->eta_hi[g]) {
+                        rg = g;
+                        break;
+                    }
+                int start = -1;
+                if (rg >= 0) {
+                    for (int q = 0; q < 3; ++q) {
+                        const int hi = a.seed_hits[q * a.sld + sid];
+                        if (hi < 0 || hi >= a.n_hits) continue;
+                        const int hl = a.hit_layer[hi];
+                        for (int j = 0; j < a.steer->len[rg]; ++j)
+                            if (a.steer->layers[rg][j] == hl && j + 1 > start) start = j + 1;
+                    }
+                }
+                if (start < 0) {
+                    if (occupied && !done) {
+                        status |= KF_ST_UNREACHABLE;
+                        done = true;
+                    }
+                    rg = 0;
+                    start = 0;
+                }
+                pos = start;
+            }
+        }
         int nsteps = 0;
         for (int step = 0; step < nl; ++step) {
             const bool live = occupied && !done;
@@ -595,9 +628,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             int pl = -1;
             if (live) {
                 T s;
-                const int layer = navigate(p, sh.layers, nl, a.prm, kb, &s, &status, &n_newton,
-                                           &n_disk, s_guess, LEARN ? a.prm.mlp_max_iter : 0,
-                                           &n_fallback);
+                int layer;
+                if constexpr (STEER)
+                    layer = steer_next(p, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
+                                       a.prm, kb, &s, &status, &n_newton, &n_disk);
+                else
+                    layer = navigate(p, sh.layers, nl, a.prm, kb, &s, &status, &n_newton, &n_disk,
+                                     s_guess, LEARN ? a.prm.mlp_max_iter : 0, &n_fallback);
                 if (layer < 0) {
                     done = true;
                 } else {
@@ -867,7 +904,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 sh.meta[0 * W + t] = nhits;
                 sh.meta[1 * W + t] = misses;
                 sh.meta[2 * W + t] = (int32_t)status;
-                sh.meta[3 * W + t] = (done ? 1 : 0) | ((pl + 1) << 8);
+                sh.meta[3 * W + t] = (done ? 1 : 0) | ((pl + 1) << 8) | (pos << 16);
                 const int nk = nacc < MC ? nacc : MC;
                 sh.nchild[t] = occupied ? nk : -1;
 #pragma unroll
@@ -973,7 +1010,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     status = (uint32_t)sh.meta[2 * W + tj];
                     const int m3 = sh.meta[3 * W + tj];
                     done = (m3 & 1) != 0;
-                    const int ppl = (m3 >> 8) - 1;
+                    const int ppl = ((m3 >> 8) & 0xFF) - 1;
+                    if constexpr (STEER) pos = (m3 >> 16) & 0xFF;
                     const int nk = sh.nchild[tj];
                     if (ppl >= 0) {
                         if (c < nk) {
@@ -1065,21 +1103,36 @@ size_t find_shared_size(int W, int S, int nl, int prec)
     return find_shared_bytes(W, S, nl, prec == KF_PREC_FP32 ? sizeof(float) : sizeof(double));
 }
 
-template <typename T, typename C, typename U, bool LEARN>
-static hipError_t find_occ(bool mat, int W, size_t lds, int* out)
+// Instantiations: (precision) x (plain, learned, steered) x (material map);
+// learned and steered exclude each other.
+template <typename T, typename C, typename U, bool LEARN, bool MAT>
+static hipError_t find_occ2(bool steer, int W, size_t lds, int* out)
 {
-    return mat ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, true>, W, lds)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, false>, W, lds);
+    if constexpr (!LEARN) {
+        if (steer)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, false, MAT, true>,
+                                                                W, lds);
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, MAT, false>, W,
+                                                        lds);
 }
 
-hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, bool mat, int* out)
+template <typename T, typename C, typename U, bool LEARN>
+static hipError_t find_occ(bool mat, bool steer, int W, size_t lds, int* out)
+{
+    return mat ? find_occ2<T, C, U, LEARN, true>(steer, W, lds, out)
+               : find_occ2<T, C, U, LEARN, false>(steer, W, lds, out);
+}
+
+hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, bool mat, bool steer,
+                                  int* out)
 {
     const size_t lds = find_shared_size(W, S, nl, prec);
     if (prec == KF_PREC_FP32)
-        return learn ? find_occ<float, float, float, true>(mat, W, lds, out)
-                     : find_occ<float, float, float, false>(mat, W, lds, out);
-    return learn ? find_occ<float, double, double, true>(mat, W, lds, out)
-                 : find_occ<float, double, double, false>(mat, W, lds, out);
+        return learn ? find_occ<float, float, float, true>(mat, steer, W, lds, out)
+                     : find_occ<float, float, float, false>(mat, steer, W, lds, out);
+    return learn ? find_occ<float, double, double, true>(mat, steer, W, lds, out)
+                 : find_occ<float, double, double, false>(mat, steer, W, lds, out);
 }
 
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
@@ -1322,13 +1375,25 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     return off;
 }
 
+template <typename T, typename C, typename U, bool LEARN, bool MAT>
+static void find_launch2(const FindArgs& a, int W, int grid, size_t lds, hipStream_t s)
+{
+    if constexpr (!LEARN) {
+        if (a.steer) {
+            find_kernel<T, C, U, false, MAT, true><<<grid, W, lds, s>>>(a);
+            return;
+        }
+    }
+    find_kernel<T, C, U, LEARN, MAT, false><<<grid, W, lds, s>>>(a);
+}
+
 template <typename T, typename C, typename U, bool LEARN>
 static void find_launch(const FindArgs& a, int W, int grid, size_t lds, hipStream_t s)
 {
     if (a.mat.x0)
-        find_kernel<T, C, U, LEARN, true><<<grid, W, lds, s>>>(a);
+        find_launch2<T, C, U, LEARN, true>(a, W, grid, lds, s);
     else
-        find_kernel<T, C, U, LEARN, false><<<grid, W, lds, s>>>(a);
+        find_launch2<T, C, U, LEARN, false>(a, W, grid, lds, s);
 }
 
 hipError_t launch_find_kernel(const FindArgs& a, int W, int grid, int prec, bool learn, hipStream_t s)

@@ -8,6 +8,7 @@
 
 #include "../../include/kf.h"
 #include "kf_matmap.hpp"
+#include "kf_steer.hpp"
 
 namespace kfmi {
 
@@ -72,6 +73,7 @@ struct kf_ctx {
     kf_layer* d_layers = nullptr;     // device copy of the geometry
     float* d_mat = nullptr;           // device copy of the material map (x0 then xi)
     kfmi::MatMap mat{};               // its view (x0 == nullptr: no map)
+    kfmi::SteerDev* d_steer = nullptr;  // device copy of the tracking regions (nullptr: none)
     int device = 0;
     std::string err;
     kfmi::Workspace ws;               // general scratch of the find path
@@ -79,8 +81,8 @@ struct kf_ctx {
     int max_lds = 0;                  // LDS bytes a workgroup may use
     int find_width = 64;              // lanes per workgroup of the finding kernel
     int find_largest_first = 0;       // tile order
-    int occ_cache[2][2][2][9] = {};   // resident workgroups per CU by (material map, learned,
-                                      // precision, log2 width)
+    int occ_cache[2][2][2][2][9] = {};  // resident workgroups per CU by (steering, material map,
+                                        // learned, precision, log2 width)
     int timing_cap = 0;               // event sets available (0: timing off)
     int timing_used = 0;              // event sets recorded since kf_set_timing
     int timing_n = 0;                 // sets requested by kf_set_timing

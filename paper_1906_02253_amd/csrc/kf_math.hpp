@@ -14,6 +14,7 @@
 
 #include "../../include/kf.h"
 #include "kf_matmap.hpp"
+#include "kf_steer.hpp"
 
 // Device functions that a host-side operation counter can also instantiate.
 #define KF_HD __host__ __device__
@@ -648,6 +649,60 @@ KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T
         ++*fallbacks;
     }
     return newton(l_line, prm.max_newton);
+}
+
+// Steering: from plan entry *pos on, the first layer the candidate reaches
+// (a barrel outside rho + kNextBarrelEps crossed outward within half a turn
+// inside |z| <= hi, or a disk ahead crossed within half a turn inside its
+// radial extent); entries not reached are passed over.  Returns the layer,
+// its path length and *pos past it, or -1 when the plan is exhausted (a
+// failed barrel solve sets NOCONV and returns -1).
+template <typename T>
+KF_HD inline int steer_next(const T p[6], const kf_layer* L, const uint8_t* plan, int n_plan,
+                            int* pos, const kf_params& prm, T kb, T* s_out, uint32_t* st,
+                            int* newton_evals, int* disk_evals)
+{
+    const T hh = Tr<T>::abs_(kb * p[3]);
+    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
+    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+    T sth, cth, sph, cph;
+    Tr<T>::sincos_(p[5], &sth, &cth);
+    Tr<T>::sincos_(p[4], &sph, &cph);
+    const T cot = cth / sth;
+    const T h = -kb * p[3];
+    for (int q = *pos; q < n_plan; ++q) {
+        const int l = plan[q];
+        const kf_layer& Ly = L[l];
+        T s;
+        if (Ly.kind == 0) {
+            const T r_l = T(Ly.r_or_z);
+            if (!(r_l > rho + T(kNextBarrelEps))) continue;
+            T s_hi;
+            if (!barrel_bracket(p[0], p[1], cph, sph, h, r_l, &s_hi)) continue;
+            int fb = 0;
+            if (solve_barrel(p, h, cph, sph, r_l, s_hi, prm, T(-1), 0, &s, newton_evals, &fb)) {
+                *st |= KF_ST_NOCONV;
+                *pos = q + 1;
+                return -1;
+            }
+            const T zc = p[2] + s * cot;
+            if (Tr<T>::abs_(zc) > T(Ly.hi) || s > s_max) continue;
+        } else {
+            const T dz = T(Ly.r_or_z) - p[2];
+            if (!(dz * cot > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
+            s = dz / cot;
+            if (s > s_max) continue;
+            ++*disk_evals;
+            const HelixPoint<T> hp = helix_at(p[0], p[1], p[4], h, s);
+            const T r = Tr<T>::sqrt_(hp.X * hp.X + hp.Y * hp.Y);
+            if (r < T(Ly.lo) || r > T(Ly.hi)) continue;
+        }
+        *s_out = s;
+        *pos = q + 1;
+        return l;
+    }
+    *pos = n_plan;
+    return -1;
 }
 
 // Next surface: whichever comes first along the helix, the next barrel
