@@ -61,7 +61,8 @@ def parse():
 # only while the finding kernel's sources are the ones it was measured on
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "find_pass_batch64_hbm_counters.json")
 KERNEL_SOURCES = ["kf_find.hip", "kf_find.hpp", "kf_math.hpp", "kf_mlp.hpp", "kf_internal.hpp",
-                  "kf_matmap.hpp"]
+                  "kf_matmap.hpp", "kf_steer.hpp"]
+FIND_KERNEL = "kfmi::find_kernel<float, double, double, false, false, false>"
 
 
 def measured_traffic(kernel):
@@ -589,8 +590,8 @@ def main():
                    "init": "plain"},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic("kfmi::find_kernel<float, double, double, false>"),
-                     "kernel": "find_kernel<float,double,double>", "kernel_ms": ms_kernel,
+                     "traffic": measured_traffic(FIND_KERNEL),
+                     "kernel": FIND_KERNEL, "kernel_ms": ms_kernel,
                      "flops_per_launch": flops, "events_per_launch": cnt.tolist()},
         "phases_ms": {"seed_and_seed_fit": ms_seed, "binning": ms_bin, "seed_order": ms_sort,
                       "find_kernel": ms_kernel},
@@ -616,6 +617,28 @@ def main():
           f"{ph_l[3]:.3f} ms; r(s) evaluations per propagation {cnt[3] / cnt[0]:.3f} plain, "
           f"{cnt_l[3] / cnt_l[0]:.3f} learned; training {rep['train_ms']:.1f} ms",
           file=sys.stderr, flush=True)
+
+    # steering: the same batch and pass following the five-region layer plans
+    sctx = K.Context(geom)
+    sctx.set_find_config(width, largest_first)
+    sctx.set_steering(E.geometry.steering_plans(geom))
+    sfp = pipeline.FindProblem(sctx, inp)
+    ms_s, ph_s, cnt_s = timed_pass(torch, sctx, sfp, 0, args.steps, args.warmup)
+    fp.run_batched(0)                   # the dynamic navigation's hit lists, plain start
+    torch.cuda.synchronize()
+    fp_hits = fp.out_hits[:n_seeds].cpu().numpy()
+    s_hits = sfp.out_hits[:n_seeds].cpu().numpy()
+    result["steering"] = {
+        "plans": "five eta regions (|eta| < 0.8, 0.8-1.6, 1.6-2.5, both signs), each the layers a "
+                 "straight line from the origin crosses, ordered by path length",
+        "ms_per_step": ms_s, "steps_per_s": (3 * n_seeds + cnt_s[0]) / (ms_s * 1e-3),
+        "find_kernel_ms": ph_s[3], "kf_steps_per_pass": 3 * n_seeds + float(cnt_s[0]),
+        "hits_found": int((s_hits >= 0).sum()), "hits_found_dynamic": int((fp_hits >= 0).sum()),
+        "identical_hit_lists": float((s_hits == fp_hits).all(axis=1).mean())}
+    print(f"# steering: {ms_s:.3f} ms/step, find kernel {ph_s[3]:.3f} ms; hits found "
+          f"{result['steering']['hits_found']} vs {result['steering']['hits_found_dynamic']} dynamic",
+          file=sys.stderr, flush=True)
+    del sfp, sctx
 
     if not args.no_fit:
         result["fit"] = run_fit(K, torch, args.fit_tracks, w)

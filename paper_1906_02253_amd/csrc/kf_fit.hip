@@ -34,14 +34,17 @@ __device__ inline void store_state(T* par, C* cov, int64_t ld, int64_t i, const 
 // Propagate (p, P) to layer L.  s_init < 0: straight-line start; otherwise
 // the learned start with prm.mlp_max_iter evaluations before the fallback
 // to the straight-line start (counted in *fallbacks).
-template <typename T, typename C>
+// FIELD: the parametrised field (kf_params.field_z0 > 0); MAT: the r-z material
+// map.  Both are compile-time variants so that the uniform-field, per-layer
+// material instantiation keeps its register budget.
+template <typename T, typename C, bool FIELD, bool MAT>
 __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_params& prm,
                                    bool material, const MatMap& mat, T s_init, T* s_out, int* evals,
                                    int* fallbacks)
 {
     const T kb = T(kKappa) * T(prm.bz);
     T s;
-    if (prm.field_z0 > 0.0) {
+    if constexpr (FIELD) {
         // parametrised field: Runge-Kutta transport to a barrel; the covariance
         // is carried by the helix Jacobian in the start point's field
         if (L.kind != 0) return KF_ST_UNREACHABLE;
@@ -62,7 +65,12 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
 #pragma unroll
         for (int k = 0; k < 6; ++k) p[k] = q[k];
         p[4] = wrap_phi(p[4]);
-        if (material) add_material(p, P, L, mat, T(prm.mass));
+        if (material) {
+            if constexpr (MAT)
+                add_material(p, P, L, mat, T(prm.mass));
+            else
+                add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
+        }
         if (s_out) *s_out = l * sth;
         bool fin = true;
 #pragma unroll
@@ -88,7 +96,12 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
         if (s < T(0)) return KF_ST_UNREACHABLE;
     }
     transport(p, P, s, kb, L.kind, T(L.r_or_z));
-    if (material) add_material(p, P, L, mat, T(prm.mass));
+    if (material) {
+            if constexpr (MAT)
+                add_material(p, P, L, mat, T(prm.mass));
+            else
+                add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
+        }
     if (s_out) *s_out = s;
     bool fin = true;
 #pragma unroll
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_
 // ---------------------------------------------------------------- propagate
 // LEARN: every lane of the wave runs to the network call (uniform control
 // flow around the matrix-core instructions).
-template <typename T, typename C, bool LEARN>
+template <typename T, typename C, bool LEARN, bool FIELD, bool MAT>
 __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T* __restrict__ par,
                                                         C* __restrict__ cov,
                                                         uint32_t* __restrict__ status,
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
     }
     T s = T(0);
     int ev = 0, fb = 0;
-    int r = propagate_to(p, P, L, prm, material != 0, mat, s_init, &s, &ev, &fb);
+    int r = propagate_to<T, C, FIELD, MAT>(p, P, L, prm, material != 0, mat, s_init, &s, &ev, &fb);
     if (fb) st |= KF_ST_FALLBACK;
     if (r) {
         st |= (uint32_t)r;
@@ -237,7 +250,7 @@ struct FitArgs {
 // Steps [k0, k1) of the fit.  init: start a fresh fit (chi2 = 0, ndf = -5).
 // LEARN: every lane of the wave walks all steps (finished lanes idle), so
 // that the network call at each step is in uniform control flow.
-template <typename T, typename C, typename U, bool LEARN>
+template <typename T, typename C, typename U, bool LEARN, bool FIELD, bool MAT>
 __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int init)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -282,7 +295,8 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
         }
         if (!alive) continue;
         int ev = 0, fb = 0;
-        int r = propagate_to(p, P, L, a.prm, a.material != 0, a.mat, s_init, (T*)nullptr, &ev, &fb);
+        int r = propagate_to<T, C, FIELD, MAT>(p, P, L, a.prm, a.material != 0, a.mat, s_init, (T*)nullptr,
+                                                &ev, &fb);
         touched = true;
         if (fb) st |= KF_ST_FALLBACK;
         if (r) {
@@ -356,10 +370,22 @@ hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* targ
     const bool learn = (flags & KF_INIT_MLP) != 0;
     const MlpDev m = ctx->mlp.dev();
     dim3 g = grid_for(t->n, 256);
-#define KF_PROP(TT, CC, LL)                                                                       \
-    propagate_kernel<TT, CC, LL><<<g, 256, 0, s>>>(t->n, t->ld, (TT*)t->par, (CC*)t->cov, t->status, \
-                                                   target, ctx->d_layers, ctx->n_layers, ctx->params, \
-                                                   material, ctx->mat, path_len, iters, m)
+    const bool field = ctx->params.field_z0 > 0.0, map = ctx->mat.x0 != nullptr;
+#define KF_PROP1(TT, CC, LL, FF, MM)                                                                 \
+    propagate_kernel<TT, CC, LL, FF, MM><<<g, 256, 0, s>>>(t->n, t->ld, (TT*)t->par, (CC*)t->cov,  \
+                                                           t->status, target, ctx->d_layers,       \
+                                                           ctx->n_layers, ctx->params, material,   \
+                                                           ctx->mat, path_len, iters, m)
+#define KF_PROP(TT, CC, LL)                                                                          \
+    do {                                                                                             \
+        if (field) {                                                                                 \
+            if (map) KF_PROP1(TT, CC, LL, true, true);                                               \
+            else KF_PROP1(TT, CC, LL, true, false);                                                  \
+        } else {                                                                                     \
+            if (map) KF_PROP1(TT, CC, LL, false, true);                                              \
+            else KF_PROP1(TT, CC, LL, false, false);                                                 \
+        }                                                                                            \
+    } while (0)
     if (prec == KF_PREC_FP64) {
         if (learn) KF_PROP(double, double, true);
         else KF_PROP(double, double, false);
@@ -371,7 +397,21 @@ hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* targ
         else KF_PROP(float, double, false);
     }
 #undef KF_PROP
+#undef KF_PROP1
     return hipGetLastError();
+}
+
+template <typename T, typename C, typename U, bool LEARN>
+static void fit_launch(const FitArgs& a, dim3 g, int k0, int k1, int init, bool field, bool map,
+                       hipStream_t s)
+{
+    if (field) {
+        if (map) fit_kernel<T, C, U, LEARN, true, true><<<g, 256, 0, s>>>(a, k0, k1, init);
+        else fit_kernel<T, C, U, LEARN, true, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+    } else {
+        if (map) fit_kernel<T, C, U, LEARN, false, true><<<g, 256, 0, s>>>(a, k0, k1, init);
+        else fit_kernel<T, C, U, LEARN, false, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+    }
 }
 
 hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const int32_t* layer_seq,
@@ -404,20 +444,21 @@ hipError_t launch_fit(const kf_ctx* ctx, kf_tracks* t, const kf_hits* h, const i
     const int prec = flags & KF_PREC_MASK;
     dim3 g = grid_for(t->n, 256);
     const bool per_layer = (flags & KF_PER_LAYER) != 0;
+    const bool field = ctx->params.field_z0 > 0.0, map = ctx->mat.x0 != nullptr;
     const int nlaunch = per_layer ? max_steps : 1;
     for (int k = 0; k < nlaunch; ++k) {
         const int k0 = per_layer ? k : 0;
         const int k1 = per_layer ? k + 1 : max_steps;
         const int init = k == 0;
         if (prec == KF_PREC_FP64) {
-            if (learn) fit_kernel<double, double, double, true><<<g, 256, 0, s>>>(a, k0, k1, init);
-            else fit_kernel<double, double, double, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+            if (learn) fit_launch<double, double, double, true>(a, g, k0, k1, init, field, map, s);
+            else fit_launch<double, double, double, false>(a, g, k0, k1, init, field, map, s);
         } else if (prec == KF_PREC_FP32) {
-            if (learn) fit_kernel<float, float, float, true><<<g, 256, 0, s>>>(a, k0, k1, init);
-            else fit_kernel<float, float, float, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+            if (learn) fit_launch<float, float, float, true>(a, g, k0, k1, init, field, map, s);
+            else fit_launch<float, float, float, false>(a, g, k0, k1, init, field, map, s);
         } else {
-            if (learn) fit_kernel<float, double, double, true><<<g, 256, 0, s>>>(a, k0, k1, init);
-            else fit_kernel<float, double, double, false><<<g, 256, 0, s>>>(a, k0, k1, init);
+            if (learn) fit_launch<float, double, double, true>(a, g, k0, k1, init, field, map, s);
+            else fit_launch<float, double, double, false>(a, g, k0, k1, init, field, map, s);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
