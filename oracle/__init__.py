@@ -86,6 +86,7 @@ def lib():
                               ip, ip, C.c_int]
         L.orc_find.argtypes = [cfgp, C.c_long, dp, dp, dp, dp, dp, ip, C.c_long, ip, C.c_int,
                                ip, dp, dp, dp, ip, ip, ip, lp, C.c_int]
+        L.orc_dedup.argtypes = [C.c_long, C.c_int, ip, dp, ip, ip, C.c_double, ip]
         L.orc_dedx.argtypes = [C.c_double, C.c_double]
         L.orc_dedx.restype = C.c_double
         L.orc_material.argtypes = [cfgp, C.c_int, dp, dp]
@@ -295,3 +296,15 @@ def material(cfg, layer, q, Pk):
     Pk = np.ascontiguousarray(Pk, np.float64).copy()
     lib().orc_material(cfg.ref, int(layer), q, Pk)
     return q, Pk
+
+
+def dedup(hits, chi2, status, event, frac=0.5):
+    """Duplicate removal of found tracks by its definition, pairwise within
+    each event.  hits [n, nl] (-1 none).  Returns keep [n] bool."""
+    hits = np.ascontiguousarray(hits, np.int32)
+    n, nl = hits.shape
+    keep = np.zeros(n, np.int32)
+    lib().orc_dedup(n, nl, hits.reshape(-1), np.ascontiguousarray(chi2, np.float64),
+                    np.ascontiguousarray(status, np.int32), np.ascontiguousarray(event, np.int32),
+                    float(frac), keep)
+    return keep.astype(bool)

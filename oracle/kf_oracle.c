@@ -1471,3 +1471,74 @@ void orc_clean_seeds(long n, const double* par, const double* chi2, const int* s
     free(fill);
     free(idx);
 }
+
+/* ------------------------------------------------------------------ */
+/* Duplicate removal of found tracks (the paper's Sec. 4 names removing
+ * duplicate tracks from several seeds of one particle as the cleaning of the
+ * final collection; it gives no rule).  Reading taken: two found tracks of
+ * one event are duplicates if the hits they share number at least
+ * frac * min(n_i, n_j), n = hits in a track's list; track i is better than
+ * track j by (more hits, lower chi2 compared in float, lower index); a track
+ * is removed iff a better duplicate exists.  Tracks with status != 0 take no
+ * part.  hits [n][nl] (-1 none). */
+void orc_dedup(long n, int nl, const int* hits, const double* chi2, const int* status,
+               const int* event, double frac, int* keep)
+{
+    /* hit -> tracks using it, so that only pairs sharing a hit are counted */
+    long hmax = -1;
+    for (long i = 0; i < n * nl; ++i) if (hits[i] > hmax) hmax = hits[i];
+    long* off = (long*)calloc((size_t)(hmax + 2), sizeof(long));
+    for (long i = 0; i < n * nl; ++i) if (hits[i] >= 0) off[hits[i] + 1]++;
+    for (long h = 0; h <= hmax; ++h) off[h + 1] += off[h];
+    long* fill = (long*)calloc((size_t)(hmax + 1 > 0 ? hmax + 1 : 1), sizeof(long));
+    long* users = (long*)malloc((size_t)(off[hmax + 1] > 0 ? off[hmax + 1] : 1) * sizeof(long));
+    int* nh = (int*)calloc((size_t)(n > 0 ? n : 1), sizeof(int));
+    for (long i = 0; i < n; ++i)
+        for (int l = 0; l < nl; ++l) {
+            int h = hits[i * nl + l];
+            if (h < 0) continue;
+            nh[i]++;
+            users[off[h] + fill[h]++] = i;
+        }
+    long* part = (long*)malloc(sizeof(long) * (size_t)(n > 0 ? n : 1));
+    int* cnt = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (long j = 0; j < n; ++j) {
+        keep[j] = 1;
+        if (status[j] != 0) continue;
+        /* shared-hit counts with every track meeting j in some hit */
+        long np = 0;
+        for (int l = 0; l < nl; ++l) {
+            int h = hits[j * nl + l];
+            if (h < 0) continue;
+            for (long u = off[h]; u < off[h + 1]; ++u) {
+                long i = users[u];
+                if (i == j) continue;
+                long q = 0;
+                while (q < np && part[q] != i) ++q;
+                if (q == np) {
+                    part[np] = i;
+                    cnt[np++] = 0;
+                }
+                cnt[q]++;
+            }
+        }
+        for (long q = 0; q < np; ++q) {
+            long i = part[q];
+            if (status[i] != 0 || event[i] != event[j]) continue;
+            int mn = nh[i] < nh[j] ? nh[i] : nh[j];
+            if (mn == 0 || !(cnt[q] >= frac * mn)) continue;
+            float fi = (float)chi2[i], fj = (float)chi2[j];
+            int better = nh[i] > nh[j] || (nh[i] == nh[j] && (fi < fj || (fi == fj && i < j)));
+            if (better) {
+                keep[j] = 0;
+                break;
+            }
+        }
+    }
+    free(off);
+    free(fill);
+    free(users);
+    free(nh);
+    free(part);
+    free(cnt);
+}

@@ -154,6 +154,10 @@ void orc_clean_seeds(long n, const double* par, const double* chi2, const int* s
                      const int* event, const int* hits, double deta, double dphi, double dc,
                      int* keep, int* tie);
 
+/* Duplicate removal of found tracks (see kf_oracle.c): keep [n] = 1 kept. */
+void orc_dedup(long n, int nl, const int* hits, const double* chi2, const int* status,
+               const int* event, double frac, int* keep);
+
 #ifdef __cplusplus
 }
 #endif
