@@ -116,5 +116,36 @@ def seed_set(n=6000, n_events=3, seed=11, n_hits=20_000):
     return dict(par=par, chi2=chi2, status=status, event=event, hits=hits)
 
 
-__all__ = ["add_overlaps", "overlap_inputs", "overlap_find_events", "overlap_batch", "seed_set",
+def track_set(n=5000, n_events=3, nl=10, seed=13, pool=400):
+    """Synthetic found-track collection for duplicate removal alone: groups
+    of 1-6 tracks derived from a base hit list (each entry kept, replaced or
+    dropped at random), so that shared fractions fall on both sides of the
+    usual thresholds; chi2 on a coarse grid (equal values occur); 2% with a
+    failed status.  Hit indices are global: layer l of event e draws from its
+    own range.  Returns dict: hits [n, nl] int32, chi2 [n] float32, status
+    [n] uint32, event [n] int32, n_hits."""
+    rng = np.random.default_rng(seed)
+    hits = np.full((n, nl), -1, np.int32)
+    event = np.zeros(n, np.int32)
+    i = 0
+    while i < n:
+        e = int(rng.integers(0, n_events))
+        base = rng.integers(0, pool, nl)
+        nb = int(rng.integers(3, nl + 1))
+        for _ in range(int(rng.integers(1, 7))):
+            if i >= n:
+                break
+            row = np.where(rng.random(nl) < 0.75, base, rng.integers(0, pool, nl))
+            row = np.where(rng.random(nl) < 0.15, -1, row)
+            row[nb:] = -1
+            ok = row >= 0
+            hits[i] = np.where(ok, row + (e * nl + np.arange(nl)) * pool, -1)
+            event[i] = e
+            i += 1
+    chi2 = (rng.integers(0, 50, n) * 0.5).astype(np.float32)
+    status = np.where(rng.random(n) < 0.02, 8, 0).astype(np.uint32)
+    return dict(hits=hits, chi2=chi2, status=status, event=event, n_hits=n_events * nl * pool)
+
+
+__all__ = ["track_set", "add_overlaps", "overlap_inputs", "overlap_find_events", "overlap_batch", "seed_set",
            "G"]

@@ -57,7 +57,9 @@ enum {
     KF_ST_NONPD = 8,       /* innovation matrix not positive definite */
     KF_ST_NAN = 16,        /* non-finite state */
     KF_ST_BADINPUT = 32,   /* out-of-range layer or hit index in the caller's arrays */
-    KF_ST_DUPLICATE = 64   /* seed removed by seed cleaning (kf_clean_seeds, KF_CLEAN_SEEDS) */
+    KF_ST_DUPLICATE = 64,  /* seed removed by seed cleaning (kf_clean_seeds, KF_CLEAN_SEEDS) */
+    KF_ST_DUPTRACK = 128   /* found track removed as a duplicate (kf_remove_duplicates,
+                              KF_REMOVE_DUPLICATES) */
 };
 
 /* flags */
@@ -71,8 +73,10 @@ enum {
                               (needs kf_mlp_load; kf_find needs a width >= 64) */
     KF_NO_MATERIAL = 8,    /* ignore the layers' material (no process noise) */
     KF_PER_LAYER = 16,     /* kf_fit: one launch per step, state through HBM between steps */
-    KF_CLEAN_SEEDS = 32    /* kf_find, kf_find_batched: seed cleaning (kf_clean_seeds) after
+    KF_CLEAN_SEEDS = 32,   /* kf_find, kf_find_batched: seed cleaning (kf_clean_seeds) after
                               the seed order, before the finding kernel */
+    KF_REMOVE_DUPLICATES = 64  /* kf_find, kf_find_batched: duplicate removal of the found
+                                  tracks (kf_remove_duplicates) after the finding kernel */
 };
 
 /* One detector layer (paper Sec. 3.1, the per-layer geometry record). */
@@ -106,6 +110,8 @@ typedef struct {
                               0 .. 0.09375 (the width of a seed cell in eta) */
     double clean_dphi;     /* seed cleaning: |d phi| [rad], 0 .. 2 pi / 64 (a seed cell in phi) */
     double clean_dc;       /* seed cleaning: |d (q/pT)| [1/GeV], >= 0 */
+    double dup_frac;       /* duplicate removal: shared fraction of the shorter track's hits,
+                              0 < dup_frac <= 1 */
 } kf_params;
 
 /* Track states, SoA with leading dimension ld.  par [6][ld] and chi2 [ld]
@@ -146,7 +152,7 @@ typedef struct {
  * params: host, copied; NULL = defaults (3.8 T uniform, chi2 30, 6
  * candidates, 10 Newton iterations, 1e-4 cm, pion mass, 2 misses, 3 learned
  * iterations, Runge-Kutta step 2 cm, seed cleaning 0.01 / 0.01 rad / 0.05
- * 1/GeV). */
+ * 1/GeV, duplicate fraction 0.5). */
 int kf_create(kf_ctx** ctx, const kf_layer* layers, int32_t n_layers, const kf_params* params);
 void kf_destroy(kf_ctx* ctx);
 /* Text of the last error on this context (valid until the next call). */
@@ -236,6 +242,26 @@ int kf_fit(kf_ctx* ctx, kf_tracks* t, const kf_hits* hits, const int32_t* layer_
 int kf_clean_seeds(kf_ctx* ctx, const kf_hits* hits, int32_t n_events, kf_tracks* seeds,
                    const int32_t* seed_event, const int32_t* seed_hits, int flags, void* stream);
 
+/* Duplicate removal of found tracks (paper Sec. 4: several seeds of one
+ * particle give the same track; removing them is the cleaning of the final
+ * collection).  Two tracks of one event are duplicates if the hits they
+ * share number at least dup_frac * min(n_i, n_j), n = hits in a track's
+ * list.  A track is better than another by (more hits, lower chi2 as float,
+ * lower index); a track is removed iff a better duplicate exists (each track
+ * decided independently).
+ *   hits         only hits->n is used (hit indices outside [0, n) are ignored)
+ *   tracks       in: chi2, status (KF_PREC_MIXED or KF_PREC_FP32 storage);
+ *                out: KF_ST_DUPTRACK set on removed tracks, cleared on kept
+ *                ones.  Tracks with any other freezing bit take no part.
+ *   track_hits   [tracks->n][n_layers] int32, the hit of each track on each
+ *                layer, -1 = none (kf_find's out_hits); a hit index may appear
+ *                only in its own layer's column
+ *   track_event  [tracks->n] int32 event of each track
+ * The result is the same on every call with the same inputs. */
+int kf_remove_duplicates(kf_ctx* ctx, const kf_hits* hits, kf_tracks* tracks,
+                         const int32_t* track_hits, const int32_t* track_event, int flags,
+                         void* stream);
+
 /* Combinatorial track finding over one or many events (paper Sec. 2: KF-based
  * track finding; Sec. 3.1: layer-to-layer propagation following the geometry;
  * Sec. 3.2: seeds grouped close in eta-phi and processed in parallel; Sec. 4:
@@ -260,7 +286,8 @@ int kf_clean_seeds(kf_ctx* ctx, const kf_hits* hits, int32_t n_events, kf_tracks
  * (most hits, lowest chi2, parent rank, hit index) survive.  A candidate stops
  * after max_miss + 1 consecutive missed layers or when no surface is left.
  * With KF_CLEAN_SEEDS the seeds are cleaned first (kf_clean_seeds; it writes
- * the seeds' status).
+ * the seeds' status); with KF_REMOVE_DUPLICATES the found tracks are
+ * deduplicated last (kf_remove_duplicates on out, out_hits and seed_event).
  * Device scratch comes from the context workspace (grown on demand). */
 int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
             const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,

@@ -16,9 +16,9 @@ LIB_PATH = os.environ.get("KFMI_LIB") or os.path.join(HERE, "libkfmi.so")
 
 KF_OK, KF_EINVAL, KF_EHIP, KF_ENOMEM, KF_EUNSUPPORTED = 0, -1, -2, -3, -4
 ST_OK, ST_UNREACHABLE, ST_NOCONV, ST_FALLBACK, ST_NONPD, ST_NAN, ST_BADINPUT = 0, 1, 2, 4, 8, 16, 32
-ST_DUPLICATE = 64
+ST_DUPLICATE, ST_DUPTRACK = 64, 128
 PREC_MIXED, PREC_FP32, PREC_FP64 = 0, 1, 2
-INIT_MLP, NO_MATERIAL, PER_LAYER, CLEAN_SEEDS = 4, 8, 16, 32
+INIT_MLP, NO_MATERIAL, PER_LAYER, CLEAN_SEEDS, REMOVE_DUPLICATES = 4, 8, 16, 32, 64
 
 class KfLayer(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nbin_phi", C.c_int32), ("nbin_2", C.c_int32),
@@ -32,7 +32,7 @@ class KfParams(C.Structure):
                 ("mass", C.c_double), ("max_cands", C.c_int32), ("max_newton", C.c_int32),
                 ("max_miss", C.c_int32), ("mlp_max_iter", C.c_int32), ("field_z0", C.c_double),
                 ("field_step", C.c_double), ("clean_deta", C.c_double), ("clean_dphi", C.c_double),
-                ("clean_dc", C.c_double)]
+                ("clean_dc", C.c_double), ("dup_frac", C.c_double)]
 
 
 class KfMaterial(C.Structure):
@@ -86,6 +86,8 @@ def _load():
                                   vp, C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_set_material.argtypes = [vp, C.POINTER(KfMaterial)]
     L.kf_set_steering.argtypes = [vp, C.POINTER(KfRegion), i32]
+    L.kf_remove_duplicates.argtypes = [vp, C.POINTER(KfHits), C.POINTER(KfTracks), vp, vp, C.c_int,
+                                       vp]
     L.kf_clean_seeds.argtypes = [vp, C.POINTER(KfHits), i32, C.POINTER(KfTracks), vp, vp, C.c_int,
                                  vp]
     L.kf_set_find_config.argtypes = [vp, i32, i32]
@@ -196,14 +198,14 @@ class Context:
 
     def __init__(self, geom, bz=3.8, chi2_cut=30.0, max_cands=6, max_newton=10, newton_tol=1e-4,
                  mass=0.13957, max_miss=2, mlp_max_iter=3, field_z0=0.0, field_step=2.0,
-                 clean_deta=0.01, clean_dphi=0.01, clean_dc=0.05):
+                 clean_deta=0.01, clean_dphi=0.01, clean_dc=0.05, dup_frac=0.5):
         arr = (KfLayer * len(geom))()
         for i, L in enumerate(geom):
             arr[i] = KfLayer(int(L["kind"]), int(L["nbin_phi"]), int(L["nbin_2"]), 0,
                              L["r_or_z"], L["lo"], L["hi"], L["x0"], L["win_su"], L["win_sv"])
         self.n_layers = len(geom)
         prm = KfParams(bz, chi2_cut, newton_tol, mass, max_cands, max_newton, max_miss, mlp_max_iter,
-                       field_z0, field_step, clean_deta, clean_dphi, clean_dc)
+                       field_z0, field_step, clean_deta, clean_dphi, clean_dc, dup_frac)
         h = C.c_void_p()
         torch.cuda.current_device()          # make sure the runtime is up on this device
         r = lib.kf_create(C.byref(h), arr, len(geom), C.byref(prm))
@@ -289,6 +291,13 @@ class Context:
         km = KfMaterial(x0.shape[0], x0.shape[1], m["r_max"], m["z_min"], m["z_max"],
                         x0.ctypes.data, xi.ctypes.data)
         self._check(lib.kf_set_material(self.h, C.byref(km)), "kf_set_material")
+
+    def remove_duplicates(self, hits, tracks, track_hits, track_event, flags=0):
+        """Duplicate removal of found tracks: sets ST_DUPTRACK in tracks.status on
+        removed tracks.  track_hits int32 [n, n_layers]; track_event int32 [n]."""
+        self._check(lib.kf_remove_duplicates(self.h, C.byref(hits.c()), C.byref(tracks.c()),
+                                             _ptr(track_hits), _ptr(track_event), flags, _stream()),
+                    "kf_remove_duplicates")
 
     def clean_seeds(self, hits, n_events, seeds, seed_event, seed_hits, flags=0):
         """Seed cleaning: sets ST_DUPLICATE in seeds.status on removed seeds.

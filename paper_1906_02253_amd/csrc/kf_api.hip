@@ -89,6 +89,9 @@ struct FindLaunch {
     int W = 0, grid = 0, prec = 0, largest_first = 0;
     bool learn = false;
     bool clean = false;
+    bool dedup = false;
+    int32_t* out_hits = nullptr;
+    kf_tracks* out = nullptr;
     int64_t n_events = 0;
     const int32_t* seed_hits = nullptr;
     const int32_t* event_off = nullptr;
@@ -208,6 +211,9 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.mlp = ctx->mlp.dev();
     L->learn = learn;
     L->clean = (flags & KF_CLEAN_SEEDS) != 0;
+    L->dedup = (flags & KF_REMOVE_DUPLICATES) != 0;
+    L->out_hits = out_hits;
+    L->out = out;
     L->seed_hits = seed_hits;
     L->W = W;
     L->grid = (int)grid;
@@ -238,9 +244,13 @@ hipError_t phase_order(const kf_ctx* ctx, const kfmi::FindLaunch& L, hipStream_t
     return e;
 }
 
-hipError_t phase_find(const kfmi::FindLaunch& L, hipStream_t s)
+hipError_t phase_find(const kf_ctx* ctx, const kfmi::FindLaunch& L, hipStream_t s)
 {
-    return kfmi::launch_find_kernel(L.a, L.W, L.grid, L.prec, L.learn, s);
+    hipError_t e = kfmi::launch_find_kernel(L.a, L.W, L.grid, L.prec, L.learn, s);
+    if (e == hipSuccess && L.dedup)
+        e = kfmi::launch_dedup(L.pl, L.out->n, ctx->n_layers, L.out_hits, (const float*)L.out->chi2,
+                               L.out->status, L.seed_event, L.hits->n, ctx->params.dup_frac, s);
+    return e;
 }
 
 // Event set of the next timed call, or nullptr when timing is off.
@@ -315,6 +325,7 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
         p.clean_deta = 0.01;
         p.clean_dphi = 0.01;
         p.clean_dc = 0.05;
+        p.dup_frac = 0.5;
     }
     if (!(p.bz != 0.0) || !(p.chi2_cut > 0.0) || p.max_cands < 1 || p.max_cands > 8 ||
         p.max_newton < 1 || p.max_newton > 64 || !(p.newton_tol > 0.0) || !(p.mass >= 0.0) ||
@@ -322,7 +333,7 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
         (p.field_z0 > 0.0 && !(p.field_step > 0.0 && p.field_step <= 1000.0)) ||
         !(p.clean_deta >= 0.0 && p.clean_deta <= 6.0 / 64.0) ||
         !(p.clean_dphi >= 0.0 && p.clean_dphi <= 2.0 * kfmi::kPi / 64.0) ||
-        !(p.clean_dc >= 0.0 && p.clean_dc < 1e30))
+        !(p.clean_dc >= 0.0 && p.clean_dc < 1e30) || !(p.dup_frac > 0.0 && p.dup_frac <= 1.0))
         return fail(nullptr, KF_EINVAL, "kf_create: invalid parameters");
     kf_ctx* ctx = new kf_ctx();
     ctx->n_layers = n_layers;
@@ -524,6 +535,35 @@ int kf_set_material(kf_ctx* ctx, const kf_material* m)
     return KF_OK;
 }
 
+int kf_remove_duplicates(kf_ctx* ctx, const kf_hits* hits, kf_tracks* tracks,
+                         const int32_t* track_hits, const int32_t* track_event, int flags,
+                         void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_remove_duplicates: null context");
+    int r = check_tracks(ctx, tracks, "kf_remove_duplicates");
+    if (r) return r;
+    if (!hits || hits->n < 0) return fail(ctx, KF_EINVAL, "kf_remove_duplicates: bad hits");
+    const int prec = flags & KF_PREC_MASK;
+    if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
+        return fail(ctx, KF_EUNSUPPORTED, "kf_remove_duplicates: float storage only (MIXED or FP32)");
+    if (hits->n > 0x7ffffffeLL) return fail(ctx, KF_EINVAL, "kf_remove_duplicates: at most 2^31-2 hits");
+    if (tracks->n * (int64_t)ctx->n_layers > 0x7fffffffLL)
+        return fail(ctx, KF_EINVAL, "kf_remove_duplicates: too many tracks");
+    if (tracks->n == 0) return KF_OK;
+    if (!track_hits || !track_event)
+        return fail(ctx, KF_EINVAL, "kf_remove_duplicates: null track_hits or track_event");
+    kfmi::FindPlan pl{};
+    pl.bl.per_event = 0;
+    const size_t bytes = kfmi::plan_find(&pl, nullptr, hits->n, 1, tracks->n, ctx->n_layers, 1, 1);
+    void* base = ctx->ws.get(bytes);
+    if (!base) return fail(ctx, KF_ENOMEM, "kf_remove_duplicates: workspace of %zu bytes", bytes);
+    kfmi::plan_find(&pl, base, hits->n, 1, tracks->n, ctx->n_layers, 1, 1);
+    hipError_t e = kfmi::launch_dedup(pl, tracks->n, ctx->n_layers, track_hits,
+                                      (const float*)tracks->chi2, tracks->status, track_event,
+                                      hits->n, ctx->params.dup_frac, (hipStream_t)stream);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_remove_duplicates");
+}
+
 int kf_clean_seeds(kf_ctx* ctx, const kf_hits* hits, int32_t n_events, kf_tracks* seeds,
                    const int32_t* seed_event, const int32_t* seed_hits, int flags, void* stream)
 {
@@ -573,7 +613,7 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
     if (e == hipSuccess) e = phase_order(ctx, L, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
-    if (e == hipSuccess) e = phase_find(L, s);
+    if (e == hipSuccess) e = phase_find(ctx, L, s);
     if (e == hipSuccess && ev) {
         e = hipEventRecord(ev[4], s);
         if (e == hipSuccess) ctx->timing_used++;
@@ -647,7 +687,7 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
         });
         if (e == hipSuccess) e = capture(ctx, &sub[1], [&](hipStream_t cs) { return phase_bin(ctx, L, cs); });
         if (e == hipSuccess) e = capture(ctx, &sub[2], [&](hipStream_t cs) { return phase_order(ctx, L, cs); });
-        if (e == hipSuccess) e = capture(ctx, &sub[3], [&](hipStream_t cs) { return phase_find(L, cs); });
+        if (e == hipSuccess) e = capture(ctx, &sub[3], [&](hipStream_t cs) { return phase_find(ctx, L, cs); });
         if (e == hipSuccess) e = hipGraphCreate(&g.graph, 0);
         // event 0 -> seed+fit -> event 1 -> binning -> event 2 -> order -> event 3 -> find -> event 4
         hipGraphNode_t prev = nullptr;

@@ -1339,6 +1339,119 @@ hipError_t launch_clean(const FindPlan& pl, const kf_tracks* seeds, const int32_
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- duplicate removal
+// Found tracks sharing at least frac of the shorter one's hits; the better by
+// (more hits, lower float chi2, lower index) removes the other, each track
+// decided independently.  A hit -> tracks index (count, prefix, scatter)
+// limits the comparisons to tracks that meet in a hit; a pair's shared hits
+// are counted layer by layer (a hit sits only in its own layer's column).
+
+__device__ inline bool dedup_part(uint32_t st)
+{
+    return (st & kFreezeMask & ~(uint32_t)KF_ST_DUPTRACK) == 0;
+}
+
+__global__ __launch_bounds__(256) void dedup_count_kernel(int64_t n, int nl,
+                                                          const int32_t* __restrict__ rows,
+                                                          const uint32_t* __restrict__ status,
+                                                          int64_t n_hits, int32_t* __restrict__ cnt,
+                                                          int32_t* __restrict__ nh)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (!dedup_part(status[j])) {
+        nh[j] = -1;
+        return;
+    }
+    int c = 0;
+    for (int l = 0; l < nl; ++l) {
+        const int32_t h = rows[j * nl + l];
+        if (h >= 0 && h < n_hits) {
+            atomicAdd(&cnt[h], 1);
+            ++c;
+        }
+    }
+    nh[j] = c;
+}
+
+__global__ __launch_bounds__(256) void dedup_fill_kernel(int64_t n, int nl,
+                                                         const int32_t* __restrict__ rows,
+                                                         const int32_t* __restrict__ nh,
+                                                         int64_t n_hits,
+                                                         const int32_t* __restrict__ off,
+                                                         int32_t* __restrict__ cnt,
+                                                         int32_t* __restrict__ users)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n || nh[j] < 0) return;
+    for (int l = 0; l < nl; ++l) {
+        const int32_t h = rows[j * nl + l];
+        if (h >= 0 && h < n_hits) users[off[h] + atomicSub(&cnt[h], 1) - 1] = (int32_t)j;
+    }
+}
+
+__global__ __launch_bounds__(256) void dedup_mark_kernel(int64_t n, int nl,
+                                                         const int32_t* __restrict__ rows,
+                                                         const float* __restrict__ chi2,
+                                                         uint32_t* __restrict__ status,
+                                                         const int32_t* __restrict__ event,
+                                                         const int32_t* __restrict__ nh,
+                                                         int64_t n_hits,
+                                                         const int32_t* __restrict__ off,
+                                                         const int32_t* __restrict__ users,
+                                                         double frac)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int nj = nh[j];
+    if (nj < 0) return;
+    const float fj = chi2[j];
+    const int32_t ej = event[j];
+    bool dup = false;
+    for (int l = 0; l < nl && !dup; ++l) {
+        const int32_t h = rows[j * nl + l];
+        if (h < 0 || h >= n_hits) continue;
+        for (int u = off[h]; u < off[h + 1]; ++u) {
+            const int32_t i = users[u];
+            if (i == j || event[i] != ej) continue;
+            const int ni = nh[i];
+            const float fi = chi2[i];
+            const bool better = ni > nj || (ni == nj && (fi < fj || (fi == fj && i < j)));
+            if (!better) continue;
+            int shared = 0;
+            for (int m = 0; m < nl; ++m) {
+                const int32_t hj = rows[j * nl + m];
+                shared += (hj >= 0 && hj < n_hits && rows[(int64_t)i * nl + m] == hj) ? 1 : 0;
+            }
+            const int mn = ni < nj ? ni : nj;
+            if (mn > 0 && (double)shared >= frac * (double)mn) {
+                dup = true;
+                break;
+            }
+        }
+    }
+    const uint32_t st = status[j];
+    status[j] = dup ? (st | (uint32_t)KF_ST_DUPTRACK) : (st & ~(uint32_t)KF_ST_DUPTRACK);
+}
+
+hipError_t launch_dedup(const FindPlan& pl, int64_t n, int nl, const int32_t* rows,
+                        const float* chi2, uint32_t* status, const int32_t* event, int64_t n_hits,
+                        double frac, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipError_t e;
+    if ((e = launch_fill(pl.dup_cnt, n_hits + 1, 0, s)) != hipSuccess) return e;
+    const unsigned nb = blocks_for(n, 256);
+    dedup_count_kernel<<<nb, 256, 0, s>>>(n, nl, rows, status, n_hits, pl.dup_cnt, pl.dup_nh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan(pl.dup_cnt, pl.dup_off, n_hits + 1, pl.bsum, s)) != hipSuccess) return e;
+    dedup_fill_kernel<<<nb, 256, 0, s>>>(n, nl, rows, pl.dup_nh, n_hits, pl.dup_off, pl.dup_cnt,
+                                         pl.dup_users);
+    dedup_mark_kernel<<<nb, 256, 0, s>>>(n, nl, rows, chi2, status, event, pl.dup_nh, n_hits,
+                                         pl.dup_off, pl.dup_users, frac);
+    return hipGetLastError();
+}
+
 size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t n_seeds,
                  int n_layers, int grid, int seeds_per_tile)
 {
@@ -1353,7 +1466,9 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     const int64_t ns = n_seeds > 0 ? n_seeds : 1;
     const int64_t nh = n_hits > 0 ? n_hits : 1;
     const int64_t nseg = (int64_t)n_events * n_layers + 1;
-    const int64_t nsum = ((nseg > nc ? nseg : nc) + kScanChunk - 1) / kScanChunk;
+    int64_t nsmax = nseg > nc ? nseg : nc;
+    if (nh + 1 > nsmax) nsmax = nh + 1;
+    const int64_t nsum = (nsmax + kScanChunk - 1) / kScanChunk;
     pl->seg_cnt = (int32_t*)take(sizeof(int32_t) * 2 * nseg);
     pl->seg_fill = pl->seg_cnt + nseg;
     pl->seg_off = (int32_t*)take(sizeof(int32_t) * nseg);
@@ -1372,6 +1487,10 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);
     pl->clean_best = (unsigned long long*)take(sizeof(unsigned long long) * nh);
     pl->clean_rec = (CleanRec*)take(sizeof(CleanRec) * ns);
+    pl->dup_cnt = (int32_t*)take(sizeof(int32_t) * (nh + 1));
+    pl->dup_off = (int32_t*)take(sizeof(int32_t) * (nh + 1));
+    pl->dup_users = (int32_t*)take(sizeof(int32_t) * ns * (n_layers > 0 ? n_layers : 1));
+    pl->dup_nh = (int32_t*)take(sizeof(int32_t) * ns);
     return off;
 }
 

@@ -103,6 +103,10 @@ struct FindPlan {
     int32_t* tile_counter;
     unsigned long long* clean_best;  // [n_hits] best seed claiming each hit (seed cleaning)
     CleanRec* clean_rec;      // [n_seeds] cleaning records in seed (cell) order
+    int32_t* dup_cnt;         // [n_hits + 1] tracks per hit (duplicate removal)
+    int32_t* dup_off;         // [n_hits + 1] its exclusive prefix sum
+    int32_t* dup_users;       // [n_seeds * n_layers] tracks of each hit, grouped by hit
+    int32_t* dup_nh;          // [n_seeds] hits per taking-part track, -1 = no part
 };
 
 // Lays out the scratch of a call from `base` (nullptr: only sizes it); returns bytes.
@@ -120,6 +124,10 @@ hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event
 hipError_t launch_clean(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
                         int n_events, const int32_t* seed_hits, int64_t n_hits,
                         const kf_params& prm, hipStream_t s);
+// Duplicate removal of found tracks: marks or clears KF_ST_DUPTRACK in status.
+hipError_t launch_dedup(const FindPlan& pl, int64_t n, int nl, const int32_t* rows,
+                        const float* chi2, uint32_t* status, const int32_t* event, int64_t n_hits,
+                        double frac, hipStream_t s);
 hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
                              const int32_t* event_off, int n_events, int largest_first,
                              hipStream_t s);

@@ -53,7 +53,8 @@ def test_argument_validation_without_device(lib):
 def test_batched_and_autotune_validation_without_device(lib):
     """The graph and autotuning entry points reject a null context before any
     device work."""
-    for f, n in (("kf_find_batched", 13), ("kf_autotune", 13), ("kf_clean_seeds", 8)):
+    for f, n in (("kf_find_batched", 13), ("kf_autotune", 13), ("kf_clean_seeds", 8),
+                 ("kf_remove_duplicates", 7)):
         fn = getattr(lib, f)
         fn.restype = C.c_int
         fn.argtypes = [C.c_void_p] * n
@@ -88,6 +89,6 @@ def test_cleaning_thresholds_validated_without_device(lib):
         kw = dict(clean_deta=0.01, clean_dphi=0.01, clean_dc=0.05)
         kw.update(bad)
         prm = KfParams(3.8, 30.0, 1e-4, 0.13957, 6, 10, 2, 3, 0.0, 2.0, kw["clean_deta"],
-                       kw["clean_dphi"], kw["clean_dc"])
+                       kw["clean_dphi"], kw["clean_dc"], 0.5)
         out = C.c_void_p()
         assert lib.kf_create(C.byref(out), lay, 1, C.byref(prm)) == -1, bad

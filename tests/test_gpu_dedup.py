@@ -1,0 +1,107 @@
+"""GPU parity of duplicate removal of found tracks against the FP64 oracle:
+the removal alone on synthetic collections (bit-exact keep decisions: the
+rule takes integer counts and float chi2 comparisons that both sides make
+alike), and finding with removal on module-overlap events, eager and as the
+captured graph, with and without seed cleaning."""
+import numpy as np
+import pytest
+
+import eventgen.overlap as EO
+from tests import common as CM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1906_02253_amd as K
+    from paper_1906_02253_amd import pipeline
+    K.pipeline = pipeline
+    return K
+
+
+def _gpu_dedup(K, s, calls=1, frac=0.5):
+    import torch
+    import eventgen as E
+    n, nl = s["hits"].shape
+    geom = E.geometry.barrel10(x0=0.0)[:nl]
+    ld = CM.ld_of(n)
+    t = K.Tracks(n, ld)
+    t.chi2[:n] = torch.as_tensor(s["chi2"], device="cuda")
+    t.status[:n] = torch.as_tensor(s["status"].astype(np.int32), device="cuda")
+    rows = torch.as_tensor(s["hits"], device="cuda")
+    ev = torch.as_tensor(s["event"], device="cuda")
+    nh = s["n_hits"]
+    hits = K.Hits(*(np.zeros(nh, np.float32) for _ in range(5)), np.zeros(nh, np.int32))
+    ctx = K.Context(geom, dup_frac=frac)
+    for _ in range(calls):
+        ctx.remove_duplicates(hits, t, rows, ev)
+    torch.cuda.synchronize()
+    return t.status[:n].cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("frac", [0.5, 0.3, 0.8])
+def test_dedup_parity_synthetic(K, orc, frac):
+    s = EO.track_set(n=5000, n_events=3, seed=13)
+    st = _gpu_dedup(K, s, frac=frac)
+    keep = orc.dedup(s["hits"], s["chi2"].astype(np.float64), s["status"].astype(np.int32),
+                     s["event"], frac=frac)
+    g_keep = (st & K.ST_DUPTRACK) == 0
+    print(f"frac {frac}: kept {keep.sum()} of {keep.size}, mismatches {(g_keep != keep).sum()}")
+    assert 0.2 * keep.size < keep.sum() < 0.9 * keep.size
+    assert np.array_equal(g_keep, keep)
+    bad = s["status"] != 0
+    assert np.array_equal(st[bad], s["status"][bad].astype(np.int64))
+
+
+def test_dedup_repeatable(K):
+    s = EO.track_set(n=3000, n_events=2, seed=14)
+    assert np.array_equal(_gpu_dedup(K, s, calls=1), _gpu_dedup(K, s, calls=3))
+
+
+@pytest.mark.parametrize("mode", ["eager", "graph", "graph+clean"])
+def test_find_with_dedup_matches_oracle(K, orc, mode):
+    """Overlap events (3 x 800 tracks, 30% overlaps, 50,000 noise hits):
+    found tracks removed on the GPU == oracle (its finder's lists, then its
+    removal), the kept tracks one per particle almost always."""
+    import torch
+    geom, evs, ovls = EO.overlap_find_events(n_events=3, n_tracks=800, n_noise=50_000)
+    inp = EO.overlap_inputs(evs, ovls)
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    flags = K.REMOVE_DUPLICATES | (K.CLEAN_SEEDS if mode == "graph+clean" else 0)
+    if mode == "eager":
+        fp.seed_fit()
+        fp.find(flags)
+    else:
+        fp.run_batched(flags)
+        fp.run_batched(flags)
+    torch.cuda.synchronize()
+    g = fp.results()
+    if mode == "graph+clean":
+        from tests.test_gpu_clean import _oracle_clean_find
+        ckeep, _, kept, o_sub = _oracle_clean_find(orc, geom, evs, inp)
+        o = {k: np.zeros((ckeep.size,) + v.shape[1:], v.dtype) for k, v in o_sub.items()
+             if isinstance(v, np.ndarray)}
+        for k in o:
+            o[k][kept] = o_sub[k]
+        o["status"][~ckeep] = K.ST_DUPLICATE
+        o["hits"][~ckeep] = -1
+    else:
+        o = CM.oracle_find_events(orc, geom, evs, inp)
+    same = (g["hits"] == o["hits"]).all(axis=1) | (o["status"] != 0)
+    assert same.mean() > 0.99
+    keep = orc.dedup(o["hits"], o["chi2"], o["status"], inp["seed_event"])
+    part = o["status"] == 0
+    g_keep = (g["status"] & K.ST_DUPTRACK) == 0
+    mism = np.nonzero(part & (g_keep != keep))[0]
+    print(f"{mode}: {part.sum()} taking part, oracle keeps {keep[part].sum()}, GPU keeps "
+          f"{g_keep[part].sum()}, mismatches {mism.size}")
+    assert mism.size <= (~same).sum()
+    key = inp["seed_event"].astype(np.int64) * 100_000 + inp["seed_track"]
+    _, inv = np.unique(key, return_inverse=True)
+    kept_pp = np.bincount(inv[part], weights=(g_keep & part)[part])
+    assert (kept_pp >= 1).mean() > 0.99 and kept_pp.mean() < 1.05
