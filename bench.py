@@ -401,7 +401,9 @@ def run_clean_pass(K, torch, steps, warmup, width, largest_first):
     """The batched pass on the 64-event batch with module-overlap duplicate
     seeds (overlap hits at 10% per barrel and 30% per disk crossing on each
     track's first three layers, one seed per hit combination), without and
-    with seed cleaning: ms per pass, the phases, seeds kept."""
+    with seed cleaning and duplicate removal of the found tracks (its time is
+    inside the finding phase): ms per pass, the phases, seeds searched and
+    tracks kept."""
     import eventgen.overlap as EO
     from paper_1906_02253_amd import pipeline
     geom, evs, ovls = EO.overlap_batch(seed=9)
@@ -416,18 +418,24 @@ def run_clean_pass(K, torch, steps, warmup, width, largest_first):
                        "at 10% per barrel and 30% per disk crossing on the first three layers, one "
                        "seed per combination of those hits",
            "n_seeds": n_seeds, "n_particles_seeded": n_particles, "width": width}
-    for name, flags in (("no_cleaning", 0), ("cleaning", K.CLEAN_SEEDS)):
+    for name, flags in (("no_cleaning", 0), ("cleaning", K.CLEAN_SEEDS),
+                        ("duplicate_removal", K.REMOVE_DUPLICATES),
+                        ("cleaning_and_duplicate_removal", K.CLEAN_SEEDS | K.REMOVE_DUPLICATES)):
         ms, (ms_seed, ms_bin, ms_order, ms_kernel), cnt = timed_pass(torch, ctx, fp, flags, steps,
                                                                      warmup)
         st = fp.out.status[:n_seeds].cpu().numpy()
         out[name] = {"ms_per_pass": ms, "seeds_per_s": n_seeds / (ms * 1e-3),
                      "phases_ms": {"seed_and_seed_fit": ms_seed, "binning": ms_bin,
-                                   "seed_order_and_cleaning": ms_order, "find_kernel": ms_kernel},
+                                   "seed_order_and_cleaning": ms_order,
+                                   "find_kernel": ms_kernel},
                      "seeds_searched": int(((st & K.ST_DUPLICATE) == 0).sum()),
+                     "tracks_kept": int(((st & (K.ST_DUPLICATE | K.ST_DUPTRACK)) == 0).sum()),
                      "kf_steps_per_pass": 3 * n_seeds + float(cnt[0])}
     out["cleaning_ms"] = (out["cleaning"]["phases_ms"]["seed_order_and_cleaning"]
                           - out["no_cleaning"]["phases_ms"]["seed_order_and_cleaning"])
     out["speedup"] = out["no_cleaning"]["ms_per_pass"] / out["cleaning"]["ms_per_pass"]
+    out["duplicate_removal_ms"] = (out["duplicate_removal"]["phases_ms"]["find_kernel"]
+                                   - out["no_cleaning"]["phases_ms"]["find_kernel"])
     return out
 
 
