@@ -1413,8 +1413,8 @@ void orc_find(const orc_cfg* cfg, long n_hits,
  *   decided independently of the others' fate).
  * Only seeds with status 0 take part; the others are kept (keep = 1) and
  * neither remove nor are removed.  tie[j] = 1 marks a seed in a pair whose
- * decision lies within 1e-3 relative of a threshold (parameters) or 1e-4
- * relative in chi2. */
+ * decision lies within the bands stated below of a threshold or of a chi2
+ * equality. */
 static double seed_eta(double th) { return -log(tan(0.5 * th)); }
 
 void orc_clean_seeds(long n, const double* par, const double* chi2, const int* status,
@@ -1454,15 +1454,22 @@ void orc_clean_seeds(long n, const double* par, const double* chi2, const int* s
                 float fi = (float)chi2[i];
                 int better = fi < fj || (fi == fj && i < j);
                 if (dup && better) keep[j] = 0;
-                /* near-threshold decisions */
+                /* near-threshold decisions: within 1e-3 of a threshold, the band
+                 * for q/pT also 1e-3 of |q/pT| and the one for chi2 2e-3 of
+                 * max(chi2, 1) (ten times the parity bars of a seed fit's
+                 * parameters and twice that of its chi2, so that a fit of the
+                 * same seed within those bars cannot flip an unmarked decision) */
                 if (!share) {
                     const double t = 1e-3;
-                    int all_in = de < deta * (1 + t) && dp < dphi * (1 + t) && dq < dc * (1 + t);
+                    double bq = t * dc;
+                    double cm = fmax(fabs(par[6 * i + 3]), fabs(par[6 * j + 3]));
+                    if (t * cm > bq) bq = t * cm;
+                    int all_in = de < deta * (1 + t) && dp < dphi * (1 + t) && dq < dc + bq;
                     int any_edge = fabs(de - deta) <= t * deta || fabs(dp - dphi) <= t * dphi ||
-                                   fabs(dq - dc) <= t * dc;
+                                   fabs(dq - dc) <= bq;
                     if (all_in && any_edge) tie[i] = tie[j] = 1;
                 }
-                if (dup && fabs((double)fi - (double)fj) <= 1e-4 * fmax(fabs(fi), fabs(fj)))
+                if (dup && fabs((double)fi - (double)fj) <= 2e-3 * fmax(1.0, fmax(fabs(fi), fabs(fj))))
                     tie[i] = tie[j] = 1;
             }
         }

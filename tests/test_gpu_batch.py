@@ -147,3 +147,22 @@ def test_batched_edge_cases(K):
     fe.run_batched()
     torch.cuda.synchronize()
     assert int(fe.counters[0].item()) == 0
+
+
+def test_batch_steered_full(K, orc, cfg2):
+    """The full batch following the five-region layer plans, as the bench's
+    steered pass runs it (graph replays), against the FP64 oracle with the
+    same plans."""
+    import torch
+    geom, evs, inp = cfg2
+    plans = E.geometry.steering_plans(geom)
+    ctx = K.Context(geom)
+    ctx.set_find_config(64, False)
+    ctx.set_steering(plans)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run_batched()
+    fp.run_batched()
+    torch.cuda.synchronize()
+    g = fp.results()
+    o = CM.oracle_find_events(orc, geom, evs, inp, steering=plans)
+    _check_parity(g, o, "batch steered", outlier_frac=1e-4)

@@ -59,8 +59,9 @@ def test_clean_parity_synthetic(K, orc):
     print(f"kept {keep.sum()} of {keep.size}; ties {tie.sum()}; "
           f"mismatches {(g_keep != keep).sum()}")
     assert 0.2 * keep.size < keep.sum() < 0.9 * keep.size
-    assert np.array_equal(g_keep[~tie], keep[~tie])
-    assert tie.sum() < 0.01 * keep.size
+    # the same float inputs on both sides: every decision agrees, ties included
+    assert np.array_equal(g_keep, keep)
+    assert tie.sum() < 0.05 * keep.size
     # failed seeds untouched
     bad = s["status"] != 0
     assert np.array_equal(st[bad], s["status"][bad].astype(np.int64))

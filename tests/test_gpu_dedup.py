@@ -105,3 +105,46 @@ def test_find_with_dedup_matches_oracle(K, orc, mode):
     _, inv = np.unique(key, return_inverse=True)
     kept_pp = np.bincount(inv[part], weights=(g_keep & part)[part])
     assert (kept_pp >= 1).mean() > 0.99 and kept_pp.mean() < 1.05
+
+
+def test_overlap_batch_full(K, orc):
+    """The bench's overlap batch at full size (64 events, 247,857 seeds) with
+    seed cleaning and duplicate removal in the captured pass: seeds removed,
+    hit lists of the searched seeds and found tracks removed, against the
+    oracle's seed fit, cleaning, finding and removal."""
+    import torch
+    from tests.test_gpu_clean import _oracle_clean_find
+    geom, evs, ovls = EO.overlap_batch(seed=9)
+    inp = EO.overlap_inputs(evs, ovls)
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    flags = K.CLEAN_SEEDS | K.REMOVE_DUPLICATES
+    fp.run_batched(flags)
+    fp.run_batched(flags)
+    torch.cuda.synchronize()
+    g = fp.results()
+    ckeep, ctie, kept, o_sub = _oracle_clean_find(orc, geom, evs, inp)
+    g_ckeep = (g["status"] & K.ST_DUPLICATE) == 0
+    print(f"cleaning: {ckeep.size} seeds, oracle keeps {ckeep.sum()}, GPU keeps {g_ckeep.sum()}, "
+          f"ties {ctie.sum()}, mismatches {(g_ckeep != ckeep).sum()}")
+    assert np.array_equal(g_ckeep[~ctie], ckeep[~ctie])
+    both = np.nonzero(ckeep & g_ckeep)[0]
+    pos = np.searchsorted(kept, both)
+    n_same, n_exc, bad = CM.compare_find(dict(hits=g["hits"][both]),
+                                         dict(hits=o_sub["hits"][pos], tie=o_sub["tie"][pos]))
+    print(f"searched on both: {both.size}, identical {n_same}, excused {n_exc}, unexplained {bad.size}")
+    assert bad.size == 0
+    # removal on the oracle's own collection (seeds it removed take no part)
+    n = ckeep.size
+    o_hits = np.full((n, len(geom)), -1, np.int64)
+    o_chi2, o_st = np.zeros(n), np.full(n, K.ST_DUPLICATE, np.int64)
+    o_hits[kept], o_chi2[kept], o_st[kept] = o_sub["hits"], o_sub["chi2"], o_sub["status"]
+    dkeep = orc.dedup(o_hits, o_chi2, o_st, inp["seed_event"])
+    part = o_st == 0
+    g_keep = (g["status"] & K.ST_DUPTRACK) == 0
+    same = np.zeros(n, bool)
+    same[both] = (g["hits"][both] == o_sub["hits"][pos]).all(axis=1)
+    mism = np.nonzero(part & (g_keep != dkeep))[0]
+    print(f"removal: {part.sum()} taking part, oracle keeps {dkeep[part].sum()}, GPU keeps "
+          f"{g_keep[part & g_ckeep].sum()}, mismatches {mism.size}")
+    assert mism.size <= (part & ~same).sum() + (g_ckeep != ckeep).sum()
