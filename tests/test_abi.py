@@ -92,3 +92,13 @@ def test_cleaning_thresholds_validated_without_device(lib):
                        kw["clean_dphi"], kw["clean_dc"], 0.5)
         out = C.c_void_p()
         assert lib.kf_create(C.byref(out), lay, 1, C.byref(prm)) == -1, bad
+
+
+def test_steering_material_entry_points_validate_without_device(lib):
+    """kf_set_steering and kf_set_material reject a null context before any
+    device work."""
+    for f, n in (("kf_set_steering", 3), ("kf_set_material", 2)):
+        fn = getattr(lib, f)
+        fn.restype = C.c_int
+        fn.argtypes = [C.c_void_p] * n
+        assert fn(*([None] * n)) == -1, f
