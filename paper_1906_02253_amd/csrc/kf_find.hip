@@ -1390,6 +1390,12 @@ __global__ __launch_bounds__(256) void dedup_fill_kernel(int64_t n, int nl,
     }
 }
 
+// A track's shared-hit count with each partner is accumulated while walking
+// its hits' user lists (a partner appears once per hit it shares); up to
+// kDedupPartners better partners are tracked in registers, and a track with
+// more falls back to counting each pair's shared hits layer by layer.
+constexpr int kDedupPartners = 8;
+
 __global__ __launch_bounds__(256) void dedup_mark_kernel(int64_t n, int nl,
                                                          const int32_t* __restrict__ rows,
                                                          const float* __restrict__ chi2,
@@ -1407,26 +1413,65 @@ __global__ __launch_bounds__(256) void dedup_mark_kernel(int64_t n, int nl,
     if (nj < 0) return;
     const float fj = chi2[j];
     const int32_t ej = event[j];
-    bool dup = false;
-    for (int l = 0; l < nl && !dup; ++l) {
+    auto better = [&](int32_t i) {
+        const int ni = nh[i];
+        const float fi = chi2[i];
+        return event[i] == ej && (ni > nj || (ni == nj && (fi < fj || (fi == fj && i < j))));
+    };
+    auto is_dup = [&](int32_t i, int shared) {
+        const int ni = nh[i];
+        const int mn = ni < nj ? ni : nj;
+        return mn > 0 && (double)shared >= frac * (double)mn;
+    };
+    int32_t pid[kDedupPartners];
+    int pcnt[kDedupPartners];
+    int np = 0;
+    bool overflow = false;
+    for (int l = 0; l < nl; ++l) {
         const int32_t h = rows[j * nl + l];
         if (h < 0 || h >= n_hits) continue;
         for (int u = off[h]; u < off[h + 1]; ++u) {
             const int32_t i = users[u];
-            if (i == j || event[i] != ej) continue;
-            const int ni = nh[i];
-            const float fi = chi2[i];
-            const bool better = ni > nj || (ni == nj && (fi < fj || (fi == fj && i < j)));
-            if (!better) continue;
-            int shared = 0;
-            for (int m = 0; m < nl; ++m) {
-                const int32_t hj = rows[j * nl + m];
-                shared += (hj >= 0 && hj < n_hits && rows[(int64_t)i * nl + m] == hj) ? 1 : 0;
+            if (i == j || !better(i)) continue;
+            int q = 0;
+#pragma unroll
+            for (int r = 0; r < kDedupPartners; ++r)
+                if (r < np && pid[r] == i) q = r + 1;
+            if (q > 0) {
+#pragma unroll
+                for (int r = 0; r < kDedupPartners; ++r)
+                    if (r == q - 1) ++pcnt[r];
+            } else if (np < kDedupPartners) {
+#pragma unroll
+                for (int r = 0; r < kDedupPartners; ++r)
+                    if (r == np) {
+                        pid[r] = i;
+                        pcnt[r] = 1;
+                    }
+                ++np;
+            } else {
+                overflow = true;
             }
-            const int mn = ni < nj ? ni : nj;
-            if (mn > 0 && (double)shared >= frac * (double)mn) {
-                dup = true;
-                break;
+        }
+    }
+    bool dup = false;
+#pragma unroll
+    for (int r = 0; r < kDedupPartners; ++r)
+        if (r < np && is_dup(pid[r], pcnt[r])) dup = true;
+    if (!dup && overflow) {
+        // more better partners than tracked: count every pair directly
+        for (int l = 0; l < nl && !dup; ++l) {
+            const int32_t h = rows[j * nl + l];
+            if (h < 0 || h >= n_hits) continue;
+            for (int u = off[h]; u < off[h + 1] && !dup; ++u) {
+                const int32_t i = users[u];
+                if (i == j || !better(i)) continue;
+                int shared = 0;
+                for (int m = 0; m < nl; ++m) {
+                    const int32_t hj = rows[j * nl + m];
+                    shared += (hj >= 0 && hj < n_hits && rows[(int64_t)i * nl + m] == hj) ? 1 : 0;
+                }
+                dup = is_dup(i, shared);
             }
         }
     }
