@@ -148,3 +148,22 @@ def test_overlap_batch_full(K, orc):
     print(f"removal: {part.sum()} taking part, oracle keeps {dkeep[part].sum()}, GPU keeps "
           f"{g_keep[part & g_ckeep].sum()}, mismatches {mism.size}")
     assert mism.size <= (part & ~same).sum() + (g_ckeep != ckeep).sum()
+
+
+def test_dedup_edge_cases(K):
+    """No tracks; a single track; tracks without hits (never duplicates)."""
+    import torch
+    import eventgen as E
+    geom = E.geometry.barrel10(x0=0.0)
+    ctx = K.Context(geom)
+    hits = K.Hits(*(np.zeros(10, np.float32) for _ in range(5)), np.zeros(10, np.int32))
+    t = K.Tracks(0, 64)
+    z = torch.zeros((64, 10), dtype=torch.int32, device="cuda")
+    ctx.remove_duplicates(hits, t, z, z[:, 0].contiguous())
+    one = dict(hits=np.array([[0, 1, 2, -1, -1, -1, -1, -1, -1, -1]], np.int32),
+               chi2=np.array([1.0], np.float32), status=np.zeros(1, np.uint32),
+               event=np.zeros(1, np.int32), n_hits=10)
+    assert _gpu_dedup(K, one).tolist() == [0]
+    empty = dict(hits=np.full((3, 10), -1, np.int32), chi2=np.ones(3, np.float32),
+                 status=np.zeros(3, np.uint32), event=np.zeros(3, np.int32), n_hits=10)
+    assert _gpu_dedup(K, empty).tolist() == [0, 0, 0]

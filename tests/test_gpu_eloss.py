@@ -166,3 +166,34 @@ def test_map_find_matches_oracle(K, orc, batched):
     same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
     err = CM.par_error(g["par"][same], o["par"][same])
     assert (err.max(axis=1) < CM.REL).mean() > 0.999
+
+
+def test_map_energy_loss_cap(K, orc):
+    """A cell far thicker than any detector (xi ~ 2 kg/cm^2): the loss is capped
+    at half the kinetic energy on both sides and the state stays finite."""
+    import torch
+    geom = [dict(kind=0, r_or_z=50.0, lo=-100.0, hi=100.0, x0=0.0, nbin_phi=64, nbin_2=16,
+                 win_su=0.01, win_sv=0.05)]
+    x0 = np.full((250, 250), 0.05, np.float32)
+    mat = dict(r_max=120.0, z_min=-300.0, z_max=300.0, x0=x0,
+               xi=np.full((250, 250), 2000.0, np.float32))
+    par = np.array([[0.0, 0.0, 0.0, 1 / 0.4, 0.3, 1.3], [0.0, 0.0, 0.0, -1 / 2.0, -1.0, 1.7]])
+    cov = np.tile(orc.pack(np.eye(6) * 1e-5), (2, 1))
+    ctx = K.Context(geom)
+    ctx.set_material(mat)
+    t = K.Tracks.from_numpy(par, cov, prec=K.PREC_FP64, ld=64)
+    target = torch.full((64,), -1, dtype=torch.int32, device="cuda")
+    target[:2] = 0
+    ctx.propagate(t, target, flags=K.PREC_FP64)
+    torch.cuda.synchronize()
+    g = t.numpy()
+    cfg = orc.Config(geom, material_map=mat)
+    for i in range(2):
+        st, q, Q, _, _ = orc.propagate(cfg, 0, par[i], cov[i], noise=True)
+        assert st == 0 and g["status"][i] == 0
+        assert np.all(np.isfinite(g["par"][i]))
+        p0 = 1 / (abs(par[i, 3]) * np.sin(par[i, 5]))
+        p1 = 1 / (abs(q[3]) * np.sin(q[5]))
+        E0, E1 = np.hypot(p0, 0.13957), np.hypot(p1, 0.13957)
+        assert E1 == pytest.approx(E0 - 0.5 * (E0 - 0.13957), rel=1e-12)   # the cap
+        assert CM.par_error(g["par"][i:i + 1], q[None])[0].max() < 1e-9

@@ -264,3 +264,21 @@ def test_field_learned_fit_matches_oracle(K, orc, sample, trained_field):
     ok = o["status"] == 0
     assert CM.par_error(g["par"][ok], o["par"][ok]).max() < CM.REL
     assert CM.chi2_error(g["chi2"][ok], o["chi2"][ok], o["ndf"][ok]).max() < CM.CHI2_REL
+
+
+def test_field_looper_unreachable(K, orc):
+    """A 0.3 GeV track from the origin turns back near r = 2R ~ 53 cm: the
+    layers beyond are unreachable in the field on both sides, the inner ones
+    are reached."""
+    import eventgen as E
+    geom = E.geometry.barrel10(x0=0.0)
+    par = np.array([[0.0, 0.0, 0.0, 1 / 0.3, 0.4, 1.2]] * 4)
+    cov = np.tile(orc.pack(np.eye(6) * 1e-4), (4, 1))
+    tgt = np.array([2, 6, 8, 9], np.int32)        # r = 11, 50, 80, 100 cm
+    g, _, _ = _propagate(K, _ctx(K, geom), par, cov, tgt, K.PREC_MIXED)
+    cfg = _cfg(orc, geom)
+    for i in range(4):
+        st = orc.propagate(cfg, tgt[i], par[i], cov[i], noise=False)[0]
+        assert bool(st & orc.ST_UNREACHABLE) == bool(g["status"][i] & K.ST_UNREACHABLE), i
+    assert g["status"][0] == 0 and g["status"][1] == 0
+    assert g["status"][2] & K.ST_UNREACHABLE and g["status"][3] & K.ST_UNREACHABLE
