@@ -528,7 +528,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: events are independent, the path shards by event "
-              "with no exchange, and this build runs on a single MI355X; use --gpus 1.",
+              "with no exchange, and the library drives one GPU per process; use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -43,7 +43,7 @@ enum kf_status {
     KF_EINVAL = -1,        /* bad argument */
     KF_EHIP = -2,          /* HIP runtime error (launch, copy, allocation) */
     KF_ENOMEM = -3,        /* workspace allocation failed */
-    KF_EUNSUPPORTED = -4   /* valid but not supported by this build */
+    KF_EUNSUPPORTED = -4   /* valid but not supported by this library */
 };
 
 /* per-track status bits */

@@ -2,7 +2,7 @@
 // 8 -> 64 (tanh) -> 64 (tanh) -> 1 network evaluated by a whole wavefront on
 // bf16 matrix cores (FP32 accumulate).  Not part of the paper; it supplies a
 // start for the iterative solve that the paper's layer-to-layer propagation
-// (Sec. 3.1) needs, the exact solve staying the judge.  The output is the
+// (Sec. 3.1) needs, the exact solve staying the arbiter.  The output is the
 // correction to the straight-line path length in units of h s_line^2 (see
 // mlp_guess): the straight line is exact for straight tracks, and the
 // network's error then scales with the correction, not with the path.
