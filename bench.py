@@ -62,7 +62,7 @@ def parse():
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "find_pass_batch64_hbm_counters.json")
 KERNEL_SOURCES = ["kf_find.hip", "kf_find.hpp", "kf_math.hpp", "kf_mlp.hpp", "kf_internal.hpp",
                   "kf_matmap.hpp", "kf_steer.hpp"]
-FIND_KERNEL = "kfmi::find_kernel<float, double, double, false, false, false>"
+FIND_KERNEL = "kfmi::find_kernel<float, double, double, false, false, false, false>"
 
 
 def measured_traffic(kernel):

@@ -176,3 +176,52 @@ def field_pairs(n_tracks=100_000, seed=6, z0=Z0_DEFAULT, step=0.5):
     tg = np.concatenate(targets)
     sel = rng.permutation(st.shape[0])
     return geom, st[sel], tg[sel]
+
+
+def field_find_events(n_events=3, n_tracks=600, n_noise=30_000, seed=25, z0=Z0_DEFAULT, step=0.2,
+                      su=0.01, sv=0.05):
+    """Finding workload in the parametrised field: per event n_tracks of the
+    field workload's distribution traced (RK4, `step` cm) through the ten
+    barrels (no material), hits smeared by (su, sv), plus n_noise uniform
+    noise hits spread over the layers; hits shuffled.  Returns (geom,
+    events)."""
+    from .generate import Event, _noise
+    rng = np.random.default_rng(seed)
+    geom = G.barrel10(x0=0.0, su=su, sv=sv)
+    radii = [L["r_or_z"] for L in geom]
+    zmax = [L["hi"] for L in geom]
+    evs = []
+    for _ in range(n_events):
+        n = n_tracks
+        st0 = _vertex_states(rng, n)
+        cr, ok = trace_to_radii(st0, radii, zmax, z0=z0, step=step)
+        nh = np.argmin(np.concatenate([ok, np.zeros((n, 1), bool)], axis=1), axis=1)
+        ti, si = np.nonzero(np.arange(len(geom))[None, :] < nh[:, None])
+        s = cr[ti, si]
+        r = np.hypot(s[:, 0], s[:, 1])
+        ph = np.arctan2(s[:, 1], s[:, 0]) + rng.normal(0.0, su, ti.size) / r
+        hx, hy = r * np.cos(ph), r * np.sin(ph)
+        hz = s[:, 2] + rng.normal(0.0, sv, ti.size)
+        nx, ny, nz, nl, nsu, nsv = _noise(rng, geom, n_noise // len(geom))
+        allx = np.concatenate([hx, nx])
+        ally = np.concatenate([hy, ny])
+        allz = np.concatenate([hz, nz])
+        alll = np.concatenate([si, nl])
+        allsu = np.concatenate([np.full(ti.size, su), nsu])
+        allsv = np.concatenate([np.full(ti.size, sv), nsv])
+        sim = np.concatenate([ti, np.full(nx.shape[0], -1)])
+        perm = rng.permutation(allx.shape[0])
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(perm.shape[0])
+        seq_hit = np.full((n, len(geom)), -1, np.int32)
+        seq_hit[ti, si] = inv[np.arange(ti.size)]
+        seq_layer = np.where(seq_hit >= 0, np.arange(len(geom))[None, :], -1).astype(np.int32)
+        truth_at = np.zeros((n, len(geom), 6))
+        truth_at[ti, si] = s
+        f32 = lambda a: np.asarray(a, np.float32)
+        evs.append(Event(x=f32(allx[perm]), y=f32(ally[perm]), z=f32(allz[perm]),
+                         su=f32(allsu[perm]), sv=f32(allsv[perm]),
+                         layer=alll[perm].astype(np.int32), sim=sim[perm].astype(np.int32),
+                         truth0=st0, seq_hit=seq_hit, seq_layer=seq_layer, truth_at=truth_at,
+                         truth_out=truth_at.copy()))
+    return geom, evs

@@ -103,8 +103,9 @@ typedef struct {
     int32_t mlp_max_iter;  /* iterations allowed from the learned guess before fallback */
     double field_z0;       /* 0: uniform field bz along z.  > 0: parametrised solenoid-like
                               field Bz = bz / (1 + (z/field_z0)^2), Br = -(r/2) dBz/dz, tracks
-                              integrated by fourth-order Runge-Kutta (kf_propagate, kf_fit;
-                              barrel targets only, disks report UNREACHABLE; kf_find refuses it) */
+                              integrated by fourth-order Runge-Kutta (kf_propagate, kf_fit,
+                              kf_find; barrels are the only surfaces, disks report UNREACHABLE;
+                              finding in this field takes neither KF_INIT_MLP nor steering) */
     double field_step;     /* largest Runge-Kutta step [cm] in the parametrised field (> 0) */
     double clean_deta;     /* seed cleaning: |d eta| below which two seeds may be duplicates,
                               0 .. 0.09375 (the width of a seed cell in eta) */
@@ -180,7 +181,8 @@ typedef struct {
  * disk ahead (|dz| > 0.05 cm) crossed within half a turn inside its radial
  * extent - passing over entries it does not reach.  Without steering the
  * next surface is found dynamically (the first reached of the next barrel
- * outward and the next disk ahead).  Steering excludes KF_INIT_MLP.
+ * outward and the next disk ahead).  Steering excludes KF_INIT_MLP and the
+ * parametrised field.
  * Synchronous; do not call while work that uses the context is in flight. */
 int kf_set_steering(kf_ctx* ctx, const kf_region* regions, int32_t n_regions);
 
@@ -280,7 +282,8 @@ int kf_remove_duplicates(kf_ctx* ctx, const kf_hits* hits, kf_tracks* tracks,
  *               chi2 tests, Newton evaluations, disk-crossing tests, learned
  *               guesses evaluated, learned guesses that fell back)
  * Per layer a candidate is propagated to its next surface (the first reached
- * of the next barrel outward and the next disk ahead), every hit in the chi2
+ * of the next barrel outward and the next disk ahead; in the parametrised
+ * field the next barrel outward, by the Runge-Kutta radius solve), every hit in the chi2
  * window's bins passing chi2 < chi2_cut becomes a child (best max_cands per
  * parent), plus one no-hit child; per seed the best max_cands children by
  * (most hits, lowest chi2, parent rank, hit index) survive.  A candidate stops

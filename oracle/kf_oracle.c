@@ -886,8 +886,55 @@ static void free_index(const orc_cfg* cfg, event_index* E)
  * barrel solve failed.  *close is set when a decision had a relative
  * margin below 1e-3.
  */
+/*
+ * Next surface in the parametrised field (only barrels are surfaces there):
+ * the next barrel outward (radius above rho + NEXT_BARREL_EPS), reached by
+ * the Runge-Kutta radius solve, crossing inside |z| <= hi, within half a turn
+ * of the start point's curvature in the transverse plane.
+ */
+static int navigate_field(const orc_cfg* cfg, const double p[6], int* stat, int* close)
+{
+    double rho = hypot(p[0], p[1]);
+    int bl = -1;
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        const orc_layer* L = &cfg->layers[l];
+        if (L->kind != 0) continue;
+        if (fabs(L->r_or_z - (rho + NEXT_BARREL_EPS)) < CLOSE_REL * NEXT_BARREL_EPS) *close = 1;
+        if (L->r_or_z > rho + NEXT_BARREL_EPS && (bl < 0 || L->r_or_z < cfg->layers[bl].r_or_z))
+            bl = l;
+    }
+    if (bl < 0) return -1;
+    const orc_layer* L = &cfg->layers[bl];
+    double x0[3] = {p[0], p[1], p[2]}, B0[3];
+    orc_field(cfg, x0, B0);
+    double hh = fabs(KAPPA * B0[2] * p[3]);
+    double s_max = hh > 0.0 ? PI / hh : INFINITY;
+    double h0 = -KAPPA * B0[2] * p[3];
+    if (h0 != 0.0) {
+        /* reachability comes from the start point's helix: its farthest radius */
+        double cx = p[0] - sin(p[4]) / h0, cy = p[1] + cos(p[4]) / h0;
+        double rmax = hypot(cx, cy) + 1.0 / fabs(h0);
+        if (fabs(rmax - L->r_or_z) < CLOSE_REL * L->r_or_z) *close = 1;
+    }
+    double l;
+    int st = solve_barrel_field(cfg, p, L->r_or_z, -1.0, &l, NULL);
+    if (st == ORC_ST_NOCONV) {
+        *stat |= ORC_ST_NOCONV;
+        return -1;
+    }
+    if (st != ORC_ST_OK) return -1;
+    double q[6];
+    orc_rk_path(cfg, p, l, q);
+    double s = l * sin(p[5]);
+    if (fabs(fabs(q[2]) - L->hi) < CLOSE_REL * L->hi) *close = 1;
+    if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+    if (fabs(q[2]) > L->hi || s > s_max) return -1;
+    return bl;
+}
+
 static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close)
 {
+    if (cfg->field_z0 > 0.0) return navigate_field(cfg, p, stat, close);
     double rho = hypot(p[0], p[1]);
     /* only surfaces reached within half a turn in the transverse plane */
     double hh = fabs(KAPPA * cfg->bz * p[3]);

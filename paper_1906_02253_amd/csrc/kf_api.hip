@@ -122,12 +122,15 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
         return fail(ctx, KF_EUNSUPPORTED, "%s: float storage only (MIXED or FP32)", what);
     if (prec != KF_PREC_MIXED && prec != KF_PREC_FP32)
         return fail(ctx, KF_EINVAL, "%s: bad precision flag", what);
-    if (ctx->params.field_z0 > 0.0)
-        return fail(ctx, KF_EUNSUPPORTED, "%s: finding runs in the uniform field only", what);
+    const bool field = ctx->params.field_z0 > 0.0;
     const bool learn = (flags & KF_INIT_MLP) != 0;
     if (learn && !ctx->mlp_loaded) return fail(ctx, KF_EUNSUPPORTED, "%s: no learned model loaded", what);
     if (learn && ctx->d_steer)
         return fail(ctx, KF_EUNSUPPORTED, "%s: steering and the learned guess exclude each other", what);
+    if (field && (learn || ctx->d_steer))
+        return fail(ctx, KF_EUNSUPPORTED,
+                    "%s: finding in the parametrised field takes neither the learned guess nor steering",
+                    what);
     if (learn && ctx->find_width < 64)
         return fail(ctx, KF_EUNSUPPORTED, "%s: the learned guess needs a width of at least 64", what);
     if (out->n != seeds->n) return fail(ctx, KF_EINVAL, "%s: out->n must equal seeds->n", what);
@@ -159,9 +162,9 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     const int pi = prec == KF_PREC_FP32 ? 1 : 0;
     const bool mat = ctx->mat.x0 != nullptr;
     const bool steer = ctx->d_steer != nullptr;
-    int& occ = ctx->occ_cache[steer ? 1 : 0][mat ? 1 : 0][learn ? 1 : 0][pi][lw];
+    int& occ = ctx->occ_cache[field ? 1 : 0][steer ? 1 : 0][mat ? 1 : 0][learn ? 1 : 0][pi][lw];
     if (occ == 0) {
-        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, learn, mat, steer, &occ);
+        hipError_t e = kfmi::find_max_blocks_per_cu(W, S, nl, prec, learn, mat, steer, field, &occ);
         if (e != hipSuccess) return hip_fail(ctx, e, "find occupancy");
         if (occ < 1) occ = 1;
     }

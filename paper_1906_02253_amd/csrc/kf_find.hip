@@ -453,7 +453,7 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
 #define KF_FIND_WAVES 2
 #endif
 
-template <typename T, typename C, typename U, bool LEARN, bool MAT, bool STEER>
+template <typename T, typename C, typename U, bool LEARN, bool MAT, bool STEER, bool FIELD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAVES))) void find_kernel(
     FindArgs a)
 {
@@ -629,7 +629,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             if (live) {
                 T s;
                 int layer;
-                if constexpr (STEER)
+                T fl = T(0), fkb = T(0);
+                T fq[6];
+                if constexpr (FIELD)
+                    layer = navigate_field(p, sh.layers, nl, a.prm, &fl, fq, &fkb, &status,
+                                           &n_newton);
+                else if constexpr (STEER)
                     layer = steer_next(p, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
                                        a.prm, kb, &s, &status, &n_newton, &n_disk);
                 else
@@ -640,7 +645,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 } else {
                     ++n_prop;
                     const kf_layer L = sh.layers[layer];
-                    transport(p, P, s, kb, L.kind, T(L.r_or_z));
+                    if constexpr (FIELD)
+                        field_transport(p, P, fq, fl, fkb, T(L.r_or_z));
+                    else
+                        transport(p, P, s, kb, L.kind, T(L.r_or_z));
                     if (a.material) {
                         if constexpr (MAT)
                             add_material(p, P, L, a.mat, T(a.prm.mass));
@@ -1103,36 +1111,39 @@ size_t find_shared_size(int W, int S, int nl, int prec)
     return find_shared_bytes(W, S, nl, prec == KF_PREC_FP32 ? sizeof(float) : sizeof(double));
 }
 
-// Instantiations: (precision) x (plain, learned, steered) x (material map);
-// learned and steered exclude each other.
+// Instantiations: (precision) x (plain, learned, steered, parametrised field)
+// x (material map); learned, steered and field exclude each other.
 template <typename T, typename C, typename U, bool LEARN, bool MAT>
-static hipError_t find_occ2(bool steer, int W, size_t lds, int* out)
+static hipError_t find_occ2(bool steer, bool field, int W, size_t lds, int* out)
 {
     if constexpr (!LEARN) {
+        if (field)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                out, find_kernel<T, C, U, false, MAT, false, true>, W, lds);
         if (steer)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, false, MAT, true>,
-                                                                W, lds);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                out, find_kernel<T, C, U, false, MAT, true, false>, W, lds);
     }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, MAT, false>, W,
-                                                        lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, MAT, false, false>,
+                                                        W, lds);
 }
 
 template <typename T, typename C, typename U, bool LEARN>
-static hipError_t find_occ(bool mat, bool steer, int W, size_t lds, int* out)
+static hipError_t find_occ(bool mat, bool steer, bool field, int W, size_t lds, int* out)
 {
-    return mat ? find_occ2<T, C, U, LEARN, true>(steer, W, lds, out)
-               : find_occ2<T, C, U, LEARN, false>(steer, W, lds, out);
+    return mat ? find_occ2<T, C, U, LEARN, true>(steer, field, W, lds, out)
+               : find_occ2<T, C, U, LEARN, false>(steer, field, W, lds, out);
 }
 
 hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, bool mat, bool steer,
-                                  int* out)
+                                  bool field, int* out)
 {
     const size_t lds = find_shared_size(W, S, nl, prec);
     if (prec == KF_PREC_FP32)
-        return learn ? find_occ<float, float, float, true>(mat, steer, W, lds, out)
-                     : find_occ<float, float, float, false>(mat, steer, W, lds, out);
-    return learn ? find_occ<float, double, double, true>(mat, steer, W, lds, out)
-                 : find_occ<float, double, double, false>(mat, steer, W, lds, out);
+        return learn ? find_occ<float, float, float, true>(mat, steer, field, W, lds, out)
+                     : find_occ<float, float, float, false>(mat, steer, field, W, lds, out);
+    return learn ? find_occ<float, double, double, true>(mat, steer, field, W, lds, out)
+                 : find_occ<float, double, double, false>(mat, steer, field, W, lds, out);
 }
 
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s)
@@ -1543,12 +1554,16 @@ template <typename T, typename C, typename U, bool LEARN, bool MAT>
 static void find_launch2(const FindArgs& a, int W, int grid, size_t lds, hipStream_t s)
 {
     if constexpr (!LEARN) {
+        if (a.prm.field_z0 > 0.0) {
+            find_kernel<T, C, U, false, MAT, false, true><<<grid, W, lds, s>>>(a);
+            return;
+        }
         if (a.steer) {
-            find_kernel<T, C, U, false, MAT, true><<<grid, W, lds, s>>>(a);
+            find_kernel<T, C, U, false, MAT, true, false><<<grid, W, lds, s>>>(a);
             return;
         }
     }
-    find_kernel<T, C, U, LEARN, MAT, false><<<grid, W, lds, s>>>(a);
+    find_kernel<T, C, U, LEARN, MAT, false, false><<<grid, W, lds, s>>>(a);
 }
 
 template <typename T, typename C, typename U, bool LEARN>

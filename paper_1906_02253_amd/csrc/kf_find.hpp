@@ -114,7 +114,7 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
                  int n_layers, int grid, int seeds_per_tile);
 size_t find_shared_size(int W, int S, int nl, int prec);
 hipError_t find_max_blocks_per_cu(int W, int S, int nl, int prec, bool learn, bool mat, bool steer,
-                                  int* out);
+                                  bool field, int* out);
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* bsum, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event_off, int n_events,

@@ -58,13 +58,7 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
         if (st) return st;
         T q[6];
         rk_path(p, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
-        T pc[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) pc[k] = p[k];
-        transport(pc, P, l * sth, kb0, 0, T(L.r_or_z));
-#pragma unroll
-        for (int k = 0; k < 6; ++k) p[k] = q[k];
-        p[4] = wrap_phi(p[4]);
+        field_transport(p, P, q, l, kb0, T(L.r_or_z));
         if (material) {
             if constexpr (MAT)
                 add_material(p, P, L, mat, T(prm.mass));

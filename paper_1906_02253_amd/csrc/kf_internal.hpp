@@ -81,8 +81,8 @@ struct kf_ctx {
     int max_lds = 0;                  // LDS bytes a workgroup may use
     int find_width = 64;              // lanes per workgroup of the finding kernel
     int find_largest_first = 0;       // tile order
-    int occ_cache[2][2][2][2][9] = {};  // resident workgroups per CU by (steering, material map,
-                                        // learned, precision, log2 width)
+    int occ_cache[2][2][2][2][2][9] = {};  // resident workgroups per CU by (field, steering,
+                                           // material map, learned, precision, log2 width)
     int timing_cap = 0;               // event sets available (0: timing off)
     int timing_used = 0;              // event sets recorded since kf_set_timing
     int timing_n = 0;                 // sets requested by kf_set_timing

@@ -545,6 +545,23 @@ KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
     out[3] = p[3] * st / Tr<T>::sin_(out[5]);
 }
 
+// Propagation along the 3D path l in the parametrised field whose end state q
+// (rk_path) is known: the covariance by the helix Jacobian (with ds/dp) in
+// the start point's field (kb0) over the transverse length l sin(theta0),
+// then the state becomes q.  Barrels only.
+template <typename T, typename C>
+KF_HD inline void field_transport(T p[6], C P[21], const T q[6], T l, T kb0, T r_l)
+{
+    const T sth = Tr<T>::sin_(p[5]);
+    T pc[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pc[k] = p[k];
+    transport(pc, P, l * sth, kb0, 0, r_l);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = q[k];
+    p[4] = wrap_phi(p[4]);
+}
+
 // Status bits that freeze a track (everything except the informational
 // fallback bit of the learned guess).
 constexpr uint32_t kFreezeMask = ~(uint32_t)KF_ST_FALLBACK;
@@ -649,6 +666,37 @@ KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T
         ++*fallbacks;
     }
     return newton(l_line, prm.max_newton);
+}
+
+// Next surface in the parametrised field, where only barrels are surfaces:
+// the next barrel outward (next_barrel), reached by the Runge-Kutta radius
+// solve, crossing inside |z| <= hi within half a turn of the start point's
+// curvature.  Returns the layer with the 3D path, the end state and kb0 =
+// kappa Bz(start), or -1 (a failed solve sets NOCONV).
+template <typename T>
+KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const kf_params& prm,
+                                T* l_out, T q[6], T* kb0_out, uint32_t* st, int* newton_evals)
+{
+    const int bl = next_barrel(p, L, nl);
+    if (bl < 0) return -1;
+    T bx, by, bz0;
+    field_at(T(prm.bz), T(prm.field_z0), p[0], p[1], p[2], &bx, &by, &bz0);
+    const T kb0 = T(kKappa) * bz0;
+    const T hh = Tr<T>::abs_(kb0 * p[3]);
+    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
+    T l;
+    int fb = 0;
+    const int r = solve_barrel_field(p, T(L[bl].r_or_z), prm, kb0, T(-1), 0, &l, newton_evals, &fb);
+    if (r == (int)KF_ST_NOCONV) {
+        *st |= KF_ST_NOCONV;
+        return -1;
+    }
+    if (r) return -1;
+    rk_path(p, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
+    if (Tr<T>::abs_(q[2]) > T(L[bl].hi) || l * Tr<T>::sin_(p[5]) > s_max) return -1;
+    *l_out = l;
+    *kb0_out = kb0;
+    return bl;
 }
 
 // Steering: from plan entry *pos on, the first layer the candidate reaches

@@ -192,15 +192,56 @@ def test_field_disks_unreachable(K, orc):
     assert g["status"][1] & K.ST_UNREACHABLE and g["status"][2] & K.ST_UNREACHABLE
 
 
-def test_field_find_refused(K):
+@pytest.mark.parametrize("batched", [False, True])
+def test_field_find_matches_oracle(K, orc, batched):
+    """Finding in the parametrised field: 3 events of 600 tracks traced
+    through the field and 30,000 noise hits each; the next surface is the next
+    barrel by the Runge-Kutta radius solve.  Hit lists against the FP64
+    oracle's finder in the same field under the finding tests' tie rules,
+    eager and as the captured graph."""
+    import torch
+    geom, evs = EF.field_find_events(n_events=3, n_tracks=600, n_noise=30_000, seed=25)
+    inp = E.find_inputs(evs)
+    fp = K.pipeline.FindProblem(_ctx(K, geom), inp)
+    if batched:
+        fp.run_batched()
+        fp.run_batched()
+    else:
+        fp.run()
+    torch.cuda.synchronize()
+    g = fp.results()
+    o = CM.oracle_find_events(orc, geom, evs, inp, field_z0=Z0, field_step=STEP)
+    n_same, n_exc, bad = CM.compare_find(g, o)
+    ns = g["hits"].shape[0]
+    print(f"field find: {n_same}/{ns} identical, {n_exc} excused, {bad.size} unexplained; "
+          f"counters {g['counters'][:5].tolist()}")
+    assert bad.size == 0
+    assert n_same > 0.98 * ns
+    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+    err = CM.par_error(g["par"][same], o["par"][same])
+    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    # most tracks are found with all their crossings
+    nh_true = np.concatenate([(e.seq_hit[e.n_track_hits() >= 3] >= 0).sum(axis=1) for e in evs])
+    nh_found = (g["hits"] >= 0).sum(axis=1)
+    assert (nh_found >= nh_true).mean() > 0.9
+
+
+def test_field_find_refusals(K):
+    """Finding in the parametrised field takes neither the learned guess nor
+    steering."""
     import torch
     geom, evs = E.find_events(n_events=1, n_tracks=50, n_noise=0, seed=1)
-    p = K.pipeline.FindProblem(_ctx(K, geom), E.find_inputs(evs))
+    ctx = _ctx(K, geom)
+    ctx.set_steering([dict(eta_lo=-10.0, eta_hi=10.0, layers=list(range(10)))])
+    p = K.pipeline.FindProblem(ctx, E.find_inputs(evs))
     p.seed_fit()
-    with pytest.raises(K.KFError, match="uniform field"):
+    with pytest.raises(K.KFError, match="parametrised field"):
         p.find()
-    with pytest.raises(K.KFError, match="uniform field"):
-        p.run_batched()
+    ctx.set_steering(None)
+    ctx.mlp_load(E.mlp_init(1))
+    with pytest.raises(K.KFError, match="parametrised field"):
+        p.find(K.INIT_MLP)
+    p.find()
     torch.cuda.synchronize()
 
 

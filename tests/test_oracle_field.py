@@ -152,3 +152,38 @@ def test_field_fit_pulls(orc):
         assert 0.9 < pull.std() < 1.1, (k, pull.std())
     c2 = r["chi2"][ok] / r["ndf"][ok]
     assert 0.9 < c2.mean() < 1.1
+
+
+def test_field_find_follows_the_field(orc):
+    """Finding in the parametrised field (next surface = next barrel by the
+    Runge-Kutta radius solve) on tracks traced by the generator's fine-step
+    integrator among uniform noise: it recovers nearly every true hit beyond
+    the seed, with chi2/ndf near 1; the same finder in the uniform field of
+    the central value loses hits and its chi2 is inflated (the field falls by
+    up to a third over the barrels' length)."""
+    from tests import common as CM
+    geom, evs = EF.field_find_events(n_events=2, n_tracks=500, n_noise=20_000, seed=26)
+    inp = E.find_inputs(evs)
+
+    def eff(r):
+        found = tot = 0
+        for s in range(inp["seed_hits"].shape[0]):
+            e, t = inp["seed_event"][s], inp["seed_track"][s]
+            true = evs[e].seq_hit[t]
+            true = set((true[true >= 0][3:] + inp["event_off"][e]).tolist())
+            got = set(r["hits"][s][r["hits"][s] >= 0].tolist())
+            found += len(true & got)
+            tot += len(true)
+        return found / tot
+
+    f = CM.oracle_find_events(orc, geom, evs, inp, field_z0=300.0, field_step=2.0)
+    u = CM.oracle_find_events(orc, geom, evs, inp)
+    ef, eu = eff(f), eff(u)
+    c2f = np.median(f["chi2"] / np.maximum(f["ndf"], 1))
+    c2u = np.median(u["chi2"] / np.maximum(u["ndf"], 1))
+    print(f"hit efficiency: field {ef:.4f}, uniform {eu:.4f}; median chi2/ndf {c2f:.3f} vs {c2u:.3f}")
+    assert (f["status"] == 0).mean() > 0.99
+    assert ef > 0.99
+    assert eu < ef - 0.01
+    assert 0.8 < c2f < 1.1
+    assert c2u > c2f + 0.15
