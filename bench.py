@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--no-clean", action="store_true")
     ap.add_argument("--no-material", action="store_true")
+    ap.add_argument("--no-field-find", action="store_true")
     ap.add_argument("--fit-tracks", type=int, default=4_000_000)
     ap.add_argument("--field-tracks", type=int, default=1_000_000)
     return ap.parse_args()
@@ -397,6 +398,37 @@ def run_field_fit(K, torch, n, oc, reps=5):
     return rep
 
 
+def run_field_find(K, torch, steps, warmup, width, largest_first):
+    """The batched finding pass on field-traced events (16 events, N ~
+    Poisson(U(200, 4000)) tracks, 60 noise hits per track, ten barrels) in the
+    parametrised field, next surface by the Runge-Kutta radius solve; beside
+    it the same events found with the uniform central field (the closed-form
+    helix): ms per pass, KF steps/s, the finding kernel, solve evaluations per
+    propagation and the hits found."""
+    import eventgen as E
+    import eventgen.field as EF
+    from paper_1906_02253_amd import pipeline
+    geom, evs = EF.field_find_batch()
+    inp = E.find_inputs(evs)
+    n_seeds = int(inp["seed_hits"].shape[0])
+    out = {"workload": "16 events traced in Bz = 3.8 T / (1 + (z/300 cm)^2) (0.5 cm RK4 steps), "
+                       "N ~ Poisson(U(200,4000)), pT U(0.5,10) GeV, |eta|<1, 60 noise hits/track, "
+                       "10 barrel layers, no material; RK4 step <= 2 cm in the finder",
+           "n_seeds": n_seeds, "n_hits": int(inp["x"].shape[0]), "width": width}
+    for name, kw in (("field", dict(field_z0=FIELD_Z0, field_step=FIELD_STEP)), ("uniform", {})):
+        ctx = K.Context(geom, **kw)
+        ctx.set_find_config(width, largest_first)
+        fp = pipeline.FindProblem(ctx, inp)
+        ms, ph, cnt = timed_pass(torch, ctx, fp, 0, steps, warmup)
+        h = fp.out_hits[:n_seeds].cpu().numpy()
+        out[name] = {"ms_per_pass": ms, "steps_per_s": (3 * n_seeds + cnt[0]) / (ms * 1e-3),
+                     "find_kernel_ms": ph[3], "kf_steps_per_pass": 3 * n_seeds + float(cnt[0]),
+                     "solve_evals_per_propagation": float(cnt[3] / max(cnt[0], 1.0)),
+                     "hits_found": int((h >= 0).sum())}
+        del fp, ctx
+    return out
+
+
 def run_clean_pass(K, torch, steps, warmup, width, largest_first):
     """The batched pass on the 64-event batch with module-overlap duplicate
     seeds (overlap hits at 10% per barrel and 30% per disk crossing on each
@@ -660,6 +692,15 @@ def main():
               f"{ff['learned']['steps_per_s']:.3e} learned; RK evaluations per propagation "
               f"{ff['plain']['rk_evals_per_propagation']:.3f} / "
               f"{ff['learned']['rk_evals_per_propagation']:.3f}", file=sys.stderr, flush=True)
+
+    if not args.no_field_find:
+        result["field_find"] = run_field_find(K, torch, args.steps, args.warmup, width,
+                                              largest_first)
+        ff = result["field_find"]
+        print(f"# field find: {ff['field']['ms_per_pass']:.3f} ms/pass "
+              f"({ff['field']['steps_per_s']:.3e} steps/s), uniform field "
+              f"{ff['uniform']['ms_per_pass']:.3f} ms; hits found {ff['field']['hits_found']} vs "
+              f"{ff['uniform']['hits_found']}", file=sys.stderr, flush=True)
 
     if not args.no_clean:
         result["seed_cleaning"] = run_clean_pass(K, torch, args.steps, args.warmup, width,

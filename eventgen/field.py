@@ -180,43 +180,50 @@ def field_pairs(n_tracks=100_000, seed=6, z0=Z0_DEFAULT, step=0.5):
 
 def field_find_events(n_events=3, n_tracks=600, n_noise=30_000, seed=25, z0=Z0_DEFAULT, step=0.2,
                       su=0.01, sv=0.05):
-    """Finding workload in the parametrised field: per event n_tracks of the
-    field workload's distribution traced (RK4, `step` cm) through the ten
-    barrels (no material), hits smeared by (su, sv), plus n_noise uniform
-    noise hits spread over the layers; hits shuffled.  Returns (geom,
-    events)."""
+    """Finding workload in the parametrised field: per event n_tracks (an int,
+    or one count per event) of the field workload's distribution traced (RK4,
+    `step` cm, every event's tracks in one vectorised pass) through the ten
+    barrels (no material), hits smeared by (su, sv), plus n_noise (an int, or
+    one count per event) uniform noise hits spread over the layers; hits
+    shuffled.  Returns (geom, events)."""
     from .generate import Event, _noise
     rng = np.random.default_rng(seed)
     geom = G.barrel10(x0=0.0, su=su, sv=sv)
+    nl = len(geom)
     radii = [L["r_or_z"] for L in geom]
     zmax = [L["hi"] for L in geom]
+    nt = np.broadcast_to(np.asarray(n_tracks, np.int64), (n_events,))
+    nn = np.broadcast_to(np.asarray(n_noise, np.int64), (n_events,))
+    st_all = _vertex_states(rng, int(nt.sum()))
+    cr_all, ok_all = trace_to_radii(st_all, radii, zmax, z0=z0, step=step)
+    bounds = np.concatenate([[0], np.cumsum(nt)])
     evs = []
-    for _ in range(n_events):
-        n = n_tracks
-        st0 = _vertex_states(rng, n)
-        cr, ok = trace_to_radii(st0, radii, zmax, z0=z0, step=step)
+    for e in range(n_events):
+        n = int(nt[e])
+        st0 = st_all[bounds[e]:bounds[e + 1]]
+        cr, ok = cr_all[bounds[e]:bounds[e + 1]], ok_all[bounds[e]:bounds[e + 1]]
         nh = np.argmin(np.concatenate([ok, np.zeros((n, 1), bool)], axis=1), axis=1)
-        ti, si = np.nonzero(np.arange(len(geom))[None, :] < nh[:, None])
+        ti, si = np.nonzero(np.arange(nl)[None, :] < nh[:, None])
         s = cr[ti, si]
         r = np.hypot(s[:, 0], s[:, 1])
         ph = np.arctan2(s[:, 1], s[:, 0]) + rng.normal(0.0, su, ti.size) / r
         hx, hy = r * np.cos(ph), r * np.sin(ph)
         hz = s[:, 2] + rng.normal(0.0, sv, ti.size)
-        nx, ny, nz, nl, nsu, nsv = _noise(rng, geom, n_noise // len(geom))
+        nx, ny, nz, nlay, nsu, nsv = _noise(rng, geom, int(nn[e]) // nl)
         allx = np.concatenate([hx, nx])
         ally = np.concatenate([hy, ny])
         allz = np.concatenate([hz, nz])
-        alll = np.concatenate([si, nl])
+        alll = np.concatenate([si, nlay])
         allsu = np.concatenate([np.full(ti.size, su), nsu])
         allsv = np.concatenate([np.full(ti.size, sv), nsv])
         sim = np.concatenate([ti, np.full(nx.shape[0], -1)])
         perm = rng.permutation(allx.shape[0])
         inv = np.empty_like(perm)
         inv[perm] = np.arange(perm.shape[0])
-        seq_hit = np.full((n, len(geom)), -1, np.int32)
+        seq_hit = np.full((n, nl), -1, np.int32)
         seq_hit[ti, si] = inv[np.arange(ti.size)]
-        seq_layer = np.where(seq_hit >= 0, np.arange(len(geom))[None, :], -1).astype(np.int32)
-        truth_at = np.zeros((n, len(geom), 6))
+        seq_layer = np.where(seq_hit >= 0, np.arange(nl)[None, :], -1).astype(np.int32)
+        truth_at = np.zeros((n, nl, 6))
         truth_at[ti, si] = s
         f32 = lambda a: np.asarray(a, np.float32)
         evs.append(Event(x=f32(allx[perm]), y=f32(ally[perm]), z=f32(allz[perm]),
@@ -225,3 +232,14 @@ def field_find_events(n_events=3, n_tracks=600, n_noise=30_000, seed=25, z0=Z0_D
                          truth0=st0, seq_hit=seq_hit, seq_layer=seq_layer, truth_at=truth_at,
                          truth_out=truth_at.copy()))
     return geom, evs
+
+
+def field_find_batch(n_events=16, seed=27):
+    """The finding batch in the parametrised field: n_events events with
+    N ~ Poisson(U(200, 4000)) tracks of the field workload's distribution and
+    60 noise hits per track (the batched workload's multiplicity and noise
+    recipe, on the ten barrels), traced in 0.5 cm steps.  Returns (geom,
+    events)."""
+    rng = np.random.default_rng(seed)
+    nt = np.maximum(rng.poisson(rng.uniform(200, 4000, n_events)), 1)
+    return field_find_events(n_events=n_events, n_tracks=nt, n_noise=60 * nt, seed=seed + 1, step=0.5)
