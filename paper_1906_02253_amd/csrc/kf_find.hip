@@ -90,21 +90,14 @@ __device__ inline int block_scan_excl(int v, int* total, int* lds)
 //     records contiguously.
 constexpr int kSegChunk = 4096;      // hits per workgroup in level 1
 constexpr int kSegLocal = 2048;      // segments a level-1 workgroup counts in LDS
+constexpr int kChunkEvents = 64;    // events of a chunk whose boundaries level 1 keeps in LDS
+constexpr int kScatterBatch = 4;    // hits per lane whose loads the scatter issues together
 
 __device__ inline int event_clamped(const int32_t* off, int n_events, int64_t i)
 {
     if (i < off[0]) return 0;
     if (i >= off[n_events]) return n_events - 1;
     return event_of(off, n_events, i);
-}
-
-// segment of hit i, or -1 (layer out of range, hit outside every event)
-__device__ inline int segment_of(int64_t i, const int32_t* __restrict__ layer,
-                                 const int32_t* __restrict__ event_off, int n_events, int n_layers)
-{
-    const int l = layer[i];
-    if (l < 0 || l >= n_layers || i < event_off[0] || i >= event_off[n_events]) return -1;
-    return event_of(event_off, n_events, i) * n_layers + l;
 }
 
 __global__ __launch_bounds__(256) void seg_count_kernel(int64_t n_hits, const int32_t* __restrict__ layer,
@@ -114,16 +107,40 @@ __global__ __launch_bounds__(256) void seg_count_kernel(int64_t n_hits, const in
                                                         int32_t* __restrict__ seg_cnt)
 {
     __shared__ int h[kSegLocal];
+    __shared__ int eoff[kChunkEvents + 2];
     const int64_t c0 = (int64_t)blockIdx.x * kSegChunk;
     const int64_t c1 = c0 + kSegChunk < n_hits ? c0 + kSegChunk : n_hits;
-    const int s0 = event_clamped(event_off, n_events, c0) * n_layers;
-    const int ns = (event_clamped(event_off, n_events, c1 - 1) + 1) * n_layers - s0;
-    const bool local = ns <= kSegLocal;
+    const int e0 = event_clamped(event_off, n_events, c0);
+    const int e1 = event_clamped(event_off, n_events, c1 - 1);
+    const int s0 = e0 * n_layers;
+    const int ns = (e1 + 1) * n_layers - s0;
+    const bool local = ns > 0 && ns <= kSegLocal;   // ns <= 0 only for a decreasing event_off
+    // the chunk's event boundaries in LDS: each hit's event by a short search there
+    const bool near = e1 >= e0 && e1 - e0 < kChunkEvents;
+    if (near)
+        for (int k = threadIdx.x; k <= e1 - e0 + 1; k += blockDim.x) eoff[k] = event_off[e0 + k];
+    const int64_t all_lo = event_off[0], all_hi = event_off[n_events];
     if (local)
         for (int b = threadIdx.x; b < ns; b += blockDim.x) h[b] = 0;
     __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-        const int key = segment_of(i, layer, event_off, n_events, n_layers);
+        const int l = layer[i];
+        int key = -1;
+        if (l >= 0 && l < n_layers && i >= all_lo && i < all_hi) {
+            int e;
+            if (near) {
+                int lo = 0, hi = e1 - e0 + 1;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (eoff[mid] <= i) lo = mid;
+                    else hi = mid;
+                }
+                e = e0 + lo;
+            } else {
+                e = event_of(event_off, n_events, i);
+            }
+            key = e * n_layers + l;
+        }
         seg_key[i] = key;
         if (key >= 0) {
             // (a decreasing event_off could put a hit outside the chunk's
@@ -169,7 +186,7 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t n_hits, const 
     const int64_t c1 = c0 + kSegChunk < n_hits ? c0 + kSegChunk : n_hits;
     const int s0 = event_clamped(event_off, n_events, c0) * n_layers;
     const int ns = (event_clamped(event_off, n_events, c1 - 1) + 1) * n_layers - s0;
-    const bool local = ns <= kSegLocal;
+    const bool local = ns > 0 && ns <= kSegLocal;   // ns <= 0 only for a decreasing event_off
     for (int l = threadIdx.x; l < n_layers; l += blockDim.x) sl[l] = layers[l];
     if (local) {
         for (int b = threadIdx.x; b < ns; b += blockDim.x) h[b] = 0;
@@ -186,24 +203,36 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t n_hits, const 
         }
     }
     __syncthreads();
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-        const int key = seg_key[i];
-        if (key < 0) continue;
-        const int pos = local && (unsigned)(key - s0) < (unsigned)ns
-                            ? base[key - s0] + atomicAdd(&h[key - s0], 1)
-                            : seg_off[key] + atomicAdd(&seg_fill[key], 1);
-        BinnedHit r;
-        r.x = x[i];
-        r.y = y[i];
-        r.z = z[i];
-        r.su = su[i];
-        r.sv = sv[i];
-        const float rho = sqrtf(r.x * r.x + r.y * r.y);
-        r.cphi = r.x / rho;
-        r.sphi = r.y / rho;
-        r.idx = (int32_t)i;
-        seg_rec[pos] = r;
-        seg_bin[pos] = hit_bin(sl[key % n_layers], r.x, r.y, r.z);
+    // kScatterBatch hits per lane per round: their loads are issued together
+    for (int64_t i0 = c0 + threadIdx.x; i0 < c1; i0 += (int64_t)kScatterBatch * blockDim.x) {
+        int key[kScatterBatch];
+        BinnedHit r[kScatterBatch];
+#pragma unroll
+        for (int q = 0; q < kScatterBatch; ++q) {
+            const int64_t i = i0 + (int64_t)q * blockDim.x;
+            key[q] = i < c1 ? seg_key[i] : -1;
+            if (key[q] >= 0) {
+                r[q].x = x[i];
+                r[q].y = y[i];
+                r[q].z = z[i];
+                r[q].su = su[i];
+                r[q].sv = sv[i];
+                r[q].idx = (int32_t)i;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kScatterBatch; ++q) {
+            if (key[q] < 0) continue;
+            const int k = key[q];
+            const int pos = local && (unsigned)(k - s0) < (unsigned)ns
+                                ? base[k - s0] + atomicAdd(&h[k - s0], 1)
+                                : seg_off[k] + atomicAdd(&seg_fill[k], 1);
+            const float rho = sqrtf(r[q].x * r[q].x + r[q].y * r[q].y);
+            r[q].cphi = r[q].x / rho;
+            r[q].sphi = r[q].y / rho;
+            seg_rec[pos] = r[q];
+            seg_bin[pos] = hit_bin(sl[k % n_layers], r[q].x, r[q].y, r[q].z);
+        }
     }
 }
 
