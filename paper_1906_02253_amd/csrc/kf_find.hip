@@ -443,10 +443,10 @@ struct FindShared {
     float* own;         // [5][W] cos/sin of the predicted azimuth, sin(dphi), wv, flags
     int32_t* seg;       // [n_waves][3][kSeg] queued phi rows: owner lane, first hit, count
     int32_t* segpre;    // [n_waves][kSeg + 1] prefix of the rows' hit counts
-    int32_t* acc;       // [n_waves][3][kAcc] accepted hits: next of the same owner, hit index, binned index
+    int32_t* acc;       // [n_waves][3][kAcc] per owner lane its accepted hits' first and last
+                        // entry ([0, 64), [64, 128)); the entries' hit index; their binned index
     float* accc2;       // [n_waves][kAcc] their chi2
     int32_t* rowp;      // [n_waves][5][64] per owner lane: row prefix, first row, bins, base, sizes
-    int32_t* achead;    // [n_waves][64] per owner lane: first accepted hit of its list, -1 = none
 };
 
 constexpr int kSeg = 128;       // phi rows queued per wave per round
@@ -473,7 +473,6 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
     b += sizeof(int32_t) * nw * (3 * kSeg + kSeg + 1 + 3 * kAcc);
     b += sizeof(float) * nw * kAcc;
     b += sizeof(int32_t) * nw * 5 * 64;
-    b += sizeof(int32_t) * nw * 64;
     return (b + 15) & ~size_t(15);
 }
 
@@ -530,8 +529,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         sh.accc2 = (float*)q;
         q += sizeof(float) * nw * kAcc;
         sh.rowp = (int32_t*)q;
-        q += sizeof(int32_t) * nw * 5 * 64;
-        sh.achead = (int32_t*)q;
     }
     const int t = threadIdx.x;
     for (int l = t; l < nl; l += W) sh.layers[l] = a.layers[l];
@@ -758,8 +755,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 int32_t* sg_h0 = sg_own + kSeg;
                 int32_t* sg_len = sg_h0 + kSeg;
                 int32_t* sg_pre = sh.segpre + wave * (kSeg + 1);
-                int32_t* ac_next = sh.acc + wave * 3 * kAcc;   // next accepted hit of the same owner
-                int32_t* ac_id = ac_next + kAcc;
+                // accepted hits are compacted in hit order, and the flattened hits
+                // run owner by owner, so each owner's accepted hits of a round form
+                // one range [ac_first, ac_last]
+                int32_t* ac_first = sh.acc + wave * 3 * kAcc;
+                int32_t* ac_last = ac_first + 64;
+                int32_t* ac_id = ac_first + kAcc;
                 int32_t* ac_bi = ac_id + kAcc;
                 float* ac_c2 = sh.accc2 + wave * kAcc;
                 // wave-wide exclusive prefix sum (and total) of one int per lane
@@ -774,8 +775,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 };
                 // rows of every lane, flattened: lane o owns rows [rowpre[o],
                 // rowpre[o] + nrow_o) of the wave's row list
-                int32_t* ac_head = sh.achead + wave * 64;
-                ac_head[ln] = -1;
+                ac_first[ln] = 0x7fffffff;
+                ac_last[ln] = -1;
                 int R = 0;
                 const int rpre = wave_scan(nrow, &R);
                 // the row parameters of each owner, for the lanes that expand its rows
@@ -825,7 +826,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     if (ln == 0) sg_pre[nseg] = H;
                     wave_fence();
                     // (3) the flattened hits, 64 x kScanBatch per round
-                    int nacc_w = 0;
                     for (int g0 = 0; g0 < H; g0 += wlanes * kScanBatch) {
                         float4 r0[kScanBatch], r1[kScanBatch];
                         int own[kScanBatch], bix[kScanBatch];
@@ -854,6 +854,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                             r0[q] = *(const float4*)&a.bh[bix[q]].x;
                             r1[q] = *(const float4*)&a.bh[bix[q]].sv;
                         }
+                        bool okq[kScanBatch];
+                        float c2q[kScanBatch];
 #pragma unroll
                         for (int q = 0; q < kScanBatch; ++q) {
                             bool ok = false;
@@ -897,23 +899,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                                     c2f = float(c2u);
                                 }
                             }
-                            const unsigned long long m = __ballot(ok);
-                            const int pos = nacc_w + __popcll(m & ((1ull << ln) - 1ull));
-                            if (ok) {
+                            okq[q] = ok;
+                            c2q[q] = c2f;
+                        }
+                        // compaction in hit order (lane-major: a lane's hits are
+                        // consecutive), each entry widening its owner's range
+                        int nok = 0;
+#pragma unroll
+                        for (int q = 0; q < kScanBatch; ++q) nok += okq[q] ? 1 : 0;
+                        int n_round = 0;
+                        int pos = wave_scan(nok, &n_round);
+#pragma unroll
+                        for (int q = 0; q < kScanBatch; ++q)
+                            if (okq[q]) {
                                 ac_id[pos] = __float_as_int(r1[q].w);
                                 ac_bi[pos] = bix[q];
-                                ac_c2[pos] = c2f;
-                                // thread it onto its owner's list
-                                ac_next[pos] = atomicExch(&ac_head[o], pos);
+                                ac_c2[pos] = c2q[q];
+                                atomicMin(&ac_first[own[q]], pos);
+                                atomicMax(&ac_last[own[q]], pos);
+                                ++pos;
                             }
-                            nacc_w += __popcll(m);
-                        }
                         wave_fence();
-                        // (4) owners take their accepted hits from their own lists
-                        for (int j = ac_head[ln]; j >= 0; j = ac_next[j]) {
+                        // (4) owners take their accepted hits; one that cannot enter
+                        // the sorted list (not below its last entry) is only counted
+                        const int j1 = ac_last[ln];
+                        for (int j = ac_first[ln]; j <= j1; ++j) {
                             float c = ac_c2[j];
                             int32_t id = ac_id[j], bi = ac_bi[j];
                             ++nacc;
+                            if (!(c < lc2[kMaxCands - 1] ||
+                                  (c == lc2[kMaxCands - 1] && id < lid[kMaxCands - 1])))
+                                continue;
 #pragma unroll
                             for (int q = 0; q < kMaxCands; ++q) {
                                 const bool lt = c < lc2[q] || (c == lc2[q] && id < lid[q]);
@@ -928,8 +944,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                                 bi = tb;
                             }
                         }
-                        ac_head[ln] = -1;
-                        nacc_w = 0;
+                        ac_first[ln] = 0x7fffffff;
+                        ac_last[ln] = -1;
                         wave_fence();
                     }
                     // the queue is rewritten next round: every lane is done reading it
