@@ -426,6 +426,23 @@ __device__ inline void wave_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A hit's place in a candidate's child list, (chi2, hit index) ascending, as
+// one unsigned key: the float's bits made monotone (-0 taken as +0) above
+// the non-negative index.
+__device__ inline uint64_t child_key(float c2, int32_t id)
+{
+    uint32_t u = __float_as_uint(c2);
+    if (u == 0x80000000u) u = 0u;
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)u << 32) | (uint32_t)id;
+}
+
+__device__ inline float child_key_chi2(uint64_t key)
+{
+    const uint32_t u = (uint32_t)(key >> 32);
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
 // LDS layout of one workgroup (W lanes), all arrays lane-minor
 template <typename C>
 struct FindShared {
@@ -452,6 +469,7 @@ struct FindShared {
 constexpr int kSeg = 128;       // phi rows queued per wave per round
 constexpr int kScanBatch = 4;   // hits per lane in flight in the scan
 constexpr int kAcc = 64 * kScanBatch;
+constexpr int kInsBatch = 4;    // accepted hits an owner loads together
 
 __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t csize)
 {
@@ -709,12 +727,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 sh.posc[4 * W + t] = P[pk(1, 2)];
                 sh.posc[5 * W + t] = P[pk(2, 2)];
             }
-            float lc2[kMaxCands];
-            int32_t lid[kMaxCands], lbi[kMaxCands];
+            // this candidate's accepted hits, best first: key and binned index
+            uint64_t lk[kMaxCands];
+            int32_t lbi[kMaxCands];
 #pragma unroll
             for (int k = 0; k < kMaxCands; ++k) {
-                lc2[k] = 3.0e38f;
-                lid[k] = 0x7fffffff;
+                lk[k] = ~0ull;
                 lbi[k] = -1;
             }
             int nacc = 0;
@@ -923,25 +941,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                         // (4) owners take their accepted hits; one that cannot enter
                         // the sorted list (not below its last entry) is only counted
                         const int j1 = ac_last[ln];
-                        for (int j = ac_first[ln]; j <= j1; ++j) {
-                            float c = ac_c2[j];
-                            int32_t id = ac_id[j], bi = ac_bi[j];
-                            ++nacc;
-                            if (!(c < lc2[kMaxCands - 1] ||
-                                  (c == lc2[kMaxCands - 1] && id < lid[kMaxCands - 1])))
-                                continue;
+                        for (int jb = ac_first[ln]; jb <= j1; jb += kInsBatch) {
+                            // the batch's entries are loaded together
+                            float cb[kInsBatch];
+                            int32_t ib[kInsBatch], bb[kInsBatch];
 #pragma unroll
-                            for (int q = 0; q < kMaxCands; ++q) {
-                                const bool lt = c < lc2[q] || (c == lc2[q] && id < lid[q]);
-                                const float tc = lt ? lc2[q] : c;
-                                const int32_t ti = lt ? lid[q] : id;
-                                const int32_t tb = lt ? lbi[q] : bi;
-                                lc2[q] = lt ? c : lc2[q];
-                                lid[q] = lt ? id : lid[q];
-                                lbi[q] = lt ? bi : lbi[q];
-                                c = tc;
-                                id = ti;
-                                bi = tb;
+                            for (int u = 0; u < kInsBatch; ++u) {
+                                const int j = jb + u <= j1 ? jb + u : j1;
+                                cb[u] = ac_c2[j];
+                                ib[u] = ac_id[j];
+                                bb[u] = ac_bi[j];
+                            }
+#pragma unroll
+                            for (int u = 0; u < kInsBatch; ++u) {
+                                if (jb + u > j1) break;
+                                uint64_t e = child_key(cb[u], ib[u]);
+                                int32_t bi = bb[u];
+                                ++nacc;
+                                if (!(e < lk[kMaxCands - 1])) continue;
+#pragma unroll
+                                for (int q = 0; q < kMaxCands; ++q) {
+                                    const bool lt = e < lk[q];
+                                    const uint64_t te = lt ? lk[q] : e;
+                                    const int32_t tb = lt ? lbi[q] : bi;
+                                    lk[q] = lt ? e : lk[q];
+                                    lbi[q] = lt ? bi : lbi[q];
+                                    e = te;
+                                    bi = tb;
+                                }
                             }
                         }
                         ac_first[ln] = 0x7fffffff;
@@ -962,7 +989,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 sh.nchild[t] = occupied ? nk : -1;
 #pragma unroll
                 for (int k = 0; k < kMaxCands; ++k) {
-                    sh.cchi2[k * W + t] = lc2[k];
+                    sh.cchi2[k * W + t] = lk[k] == ~0ull ? 3.0e38f : child_key_chi2(lk[k]);
                     sh.cbidx[k * W + t] = lbi[k];
                 }
             }
