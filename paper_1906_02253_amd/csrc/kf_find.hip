@@ -443,6 +443,18 @@ __device__ inline float child_key_chi2(uint64_t key)
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
 }
 
+// A child's place in its seed's selection: more hits first, then lower chi2
+// (as child_key's bits), then parent slot j and child c.
+__device__ inline uint64_t merge_key(int nhits, float c2, int j, int c)
+{
+    uint32_t u = __float_as_uint(c2);
+    if (u == 0x80000000u) u = 0u;
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    const uint32_t nh = nhits < 0 ? 0u : nhits > 255 ? 255u : (uint32_t)nhits;
+    return ((uint64_t)(255u - nh) << 56) | ((uint64_t)u << 24) | ((uint64_t)j << 16) |
+           ((uint64_t)c << 8);
+}
+
 // LDS layout of one workgroup (W lanes), all arrays lane-minor
 template <typename C>
 struct FindShared {
@@ -999,63 +1011,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             // registers: one LDS read per pick after the initial loads
             if (valid && slot == 0) {
                 const int base = lbase;
-                int nk[kMaxCands], nh0[kMaxCands], cur[kMaxCands], hnh[kMaxCands];
-                float c0[kMaxCands], hc[kMaxCands];
-#pragma unroll
-                for (int j = 0; j < kMaxCands; ++j) {
-                    nk[j] = j < MC ? sh.nchild[base + j] : -1;
-                    nh0[j] = j < MC ? sh.meta[0 * W + base + j] : 0;
-                    c0[j] = j < MC ? sh.pred[3 * W + base + j] : 0.0f;
-                    cur[j] = 0;
-                }
-                // parents fill slots 0, 1, ...: the first empty slot ends them
+                // list heads as merge keys; parents fill slots 0, 1, ...: the
+                // first empty slot ends them
+                uint64_t K[kMaxCands];
                 bool stop = false;
 #pragma unroll
                 for (int j = 0; j < kMaxCands; ++j) {
-                    stop = stop || nk[j] < 0;
-                    if (stop) nk[j] = -1;
-                    // head: the best child (nk == 0: the child without a hit)
-                    hnh[j] = nk[j] > 0 ? nh0[j] + 1 : nh0[j];
-                    hc[j] = nk[j] > 0 ? c0[j] + sh.cchi2[0 * W + base + (j < MC ? j : 0)] : c0[j];
+                    const int nkj = j < MC ? sh.nchild[base + j] : -1;
+                    stop = stop || nkj < 0;
+                    K[j] = ~0ull;
+                    if (!stop) {
+                        // head: the best child (nk == 0: the child without a hit)
+                        const int nh = sh.meta[0 * W + base + j];
+                        const float c0 = sh.pred[3 * W + base + j];
+                        K[j] = nkj > 0 ? merge_key(nh + 1, c0 + sh.cchi2[0 * W + base + j], j, 0)
+                                       : merge_key(nh, c0, j, 0);
+                    }
                 }
                 int nsel = 0;
                 for (int r = 0; r < MC; ++r) {
-                    int bj = -1, bnh = 0;
-                    float bc = 0.0f;
+                    uint64_t best = K[0];
 #pragma unroll
-                    for (int j = 0; j < kMaxCands; ++j) {
-                        const bool live_j = nk[j] >= 0 && cur[j] <= nk[j];
-                        if (live_j && (bj < 0 || hnh[j] > bnh || (hnh[j] == bnh && hc[j] < bc))) {
-                            bj = j;
-                            bnh = hnh[j];
-                            bc = hc[j];
-                        }
-                    }
-                    if (bj < 0) break;
-                    int c = 0, n = 0, h0 = 0;
-                    float cc0 = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < kMaxCands; ++j)
-                        if (j == bj) {
-                            c = cur[j];
-                            n = nk[j];
-                            h0 = nh0[j];
-                            cc0 = c0[j];
-                        }
+                    for (int j = 1; j < kMaxCands; ++j) best = K[j] < best ? K[j] : best;
+                    if (best == ~0ull) break;
+                    const int bj = (int)(best >> 16) & 0xFF, c = (int)(best >> 8) & 0xFF;
                     sh.sel[(s_loc * kMaxCands + r) * 2 + 0] = (int8_t)bj;
                     sh.sel[(s_loc * kMaxCands + r) * 2 + 1] = (int8_t)c;
                     ++nsel;
-                    // advance the winner's list and load its next head
-                    const int cn = c + 1;
-                    const int nnh = cn < n ? h0 + 1 : h0;
-                    const float nc = cn < n ? cc0 + sh.cchi2[cn * W + base + bj] : cc0;
+                    // advance the winner's list: its next hit child, then the
+                    // child without a hit, then nothing
+                    const int tj = base + bj, cn = c + 1;
+                    const int n = sh.nchild[tj], h0 = sh.meta[0 * W + tj];
+                    const float cc0 = sh.pred[3 * W + tj];
+                    const float cx = sh.cchi2[(cn < kMaxCands ? cn : kMaxCands - 1) * W + tj];
+                    const uint64_t nkey = cn < n    ? merge_key(h0 + 1, cc0 + cx, bj, cn)
+                                          : cn == n ? merge_key(h0, cc0, bj, cn)
+                                                    : ~0ull;
 #pragma unroll
-                    for (int j = 0; j < kMaxCands; ++j)
-                        if (j == bj) {
-                            cur[j] = cn;
-                            hnh[j] = nnh;
-                            hc[j] = nc;
-                        }
+                    for (int j = 0; j < kMaxCands; ++j) K[j] = j == bj ? nkey : K[j];
                 }
                 sh.nsel[s_loc] = nsel;
             }
