@@ -467,6 +467,7 @@ struct FindShared {
     int8_t* sel;        // [S][kMaxCands][2]  (parent slot, child index)
     int32_t* nsel;      // [S]
     kf_layer* layers;   // [n_layers]
+    NavOrder* nav;      // surface orders of the dynamic navigation
     int32_t* misc;      // [4] tile id
     // cooperative window scan, per lane (owner of a window) and per wave
     float* own;         // [5][W] cos/sin of the predicted azimuth, sin(dphi), wv, flags
@@ -495,6 +496,7 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
     b += sizeof(int32_t) * S;
     b = (b + 15) & ~size_t(15);
     b += sizeof(kf_layer) * nl;
+    b += sizeof(NavOrder);
     b += sizeof(int32_t) * 4;
     b += 2 * S * kMaxCands;
     b = (b + 15) & ~size_t(15);
@@ -542,6 +544,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         q = smem + (((size_t)(q - smem) + 15) & ~size_t(15));
         sh.layers = (kf_layer*)q;
         q += sizeof(kf_layer) * nl;
+        sh.nav = (NavOrder*)q;
+        q += sizeof(NavOrder);
         sh.misc = (int32_t*)q;
         q += sizeof(int32_t) * 4;
         sh.sel = (int8_t*)q;
@@ -562,6 +566,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     }
     const int t = threadIdx.x;
     for (int l = t; l < nl; l += W) sh.layers[l] = a.layers[l];
+    if (t == 0) build_nav_order(a.layers, nl, sh.nav);   // read after the tile loop's barrier
     // seeds never straddle waves: wave w holds seeds w*SPW .. w*SPW + SPW - 1
     const int SPW = seeds_per_wave(W, MC);
     const int ln64 = t & 63;
@@ -673,7 +678,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             T s_guess = T(-1);
             if (LEARN) {
                 float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
-                const int bl = live ? next_barrel(p, sh.layers, nl) : -1;
+                const int bl = live ? next_barrel(p, sh.layers, *sh.nav) : -1;
                 if (bl >= 0) mlp_features(p, sh.layers[bl], a.prm, f);
                 const float y = mlp_wave(a.mlp, f);
                 if (bl >= 0) {
@@ -694,7 +699,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     layer = steer_next(p, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
                                        a.prm, kb, &s, &status, &n_newton, &n_disk);
                 else
-                    layer = navigate(p, sh.layers, nl, a.prm, kb, &s, &status, &n_newton, &n_disk,
+                    layer = navigate(p, sh.layers, *sh.nav, a.prm, kb, &s, &status, &n_newton, &n_disk,
                                      s_guess, LEARN ? a.prm.mlp_max_iter : 0, &n_fallback);
                 if (layer < 0) {
                     done = true;

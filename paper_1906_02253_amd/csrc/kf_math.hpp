@@ -566,6 +566,46 @@ KF_HD inline void field_transport(T p[6], C P[21], const T q[6], T l, T kb0, T r
 // fallback bit of the learned guess).
 constexpr uint32_t kFreezeMask = ~(uint32_t)KF_ST_FALLBACK;
 
+// Surface orders for the dynamic navigation, built once per workgroup:
+// barrel indices by radius (ascending, ties by index) and disk indices in
+// layer order.
+struct NavOrder {
+    int8_t barrel[64];
+    int8_t disk[64];
+    int32_t nb, nd;
+};
+
+KF_HD inline void build_nav_order(const kf_layer* L, int nl, NavOrder* nv)
+{
+    nv->nb = nv->nd = 0;
+    for (int l = 0; l < nl; ++l) {
+        if (L[l].kind == 0) {
+            // stable insertion by radius
+            int k = nv->nb++;
+            while (k > 0 && L[nv->barrel[k - 1]].r_or_z > L[l].r_or_z) {
+                nv->barrel[k] = nv->barrel[k - 1];
+                --k;
+            }
+            nv->barrel[k] = (int8_t)l;
+        } else {
+            nv->disk[nv->nd++] = (int8_t)l;
+        }
+    }
+}
+
+// The next barrel outward from the radius-ordered list: the first above
+// rho + kNextBarrelEps (the same layer as next_barrel below), or -1.
+template <typename T>
+KF_HD inline int next_barrel(const T p[6], const kf_layer* L, const NavOrder& nv)
+{
+    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+    for (int k = 0; k < nv.nb; ++k) {
+        const int l = nv.barrel[k];
+        if (T(L[l].r_or_z) > rho + T(kNextBarrelEps)) return l;
+    }
+    return -1;
+}
+
 // The next barrel outward: smallest radius above rho + kNextBarrelEps, or -1.
 template <typename T>
 KF_HD inline int next_barrel(const T p[6], const kf_layer* L, int nl)
@@ -759,14 +799,14 @@ KF_HD inline int steer_next(const T p[6], const kf_layer* L, const uint8_t* plan
 // extent.  Returns the layer (or -1) and the path length.  s_guess >= 0: the
 // learned start of the barrel solve (learned_it evaluations, then fallback).
 template <typename T>
-KF_HD inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_params& prm, T kb,
+KF_HD inline int navigate(const T p[6], const kf_layer* L, const NavOrder& nv, const kf_params& prm, T kb,
                           T* s_out, uint32_t* st, int* newton_evals, int* disk_evals,
                           T s_guess = T(-1), int learned_it = 0, int* fallbacks = nullptr)
 {
     // only surfaces reached within half a turn in the transverse plane
     const T hh = Tr<T>::abs_(kb * p[3]);
     const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
-    const int bl = next_barrel(p, L, nl);
+    const int bl = next_barrel(p, L, nv);
     const T rbl = bl >= 0 ? T(L[bl].r_or_z) : T(0);
     T best_s = T(1e30);
     int best_l = -1;
@@ -795,8 +835,8 @@ KF_HD inline int navigate(const T p[6], const kf_layer* L, int nl, const kf_para
         }
     }
     const T cot = cth / sth;
-    for (int l = 0; l < nl; ++l) {
-        if (L[l].kind != 1) continue;
+    for (int k = 0; k < nv.nd; ++k) {
+        const int l = nv.disk[k];
         const T dz = T(L[l].r_or_z) - p[2];
         if (!(dz * cot > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
         const T s = dz / cot;
