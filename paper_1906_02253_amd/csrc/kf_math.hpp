@@ -137,7 +137,9 @@ KF_HD inline bool barrel_bracket(T x, T y, T cphi, T sphi, T h, T r_l, T* s_hi)
     T v0x = x - cx, v0y = y - cy;
     T v1x = R * cx / dc, v1y = R * cy / dc;
     T alpha = Tr<T>::atan2_(v0x * v1y - v0y * v1x, v0x * v1x + v0y * v1y);
-    T sw = Tr<T>::fmod_(h > T(0) ? alpha : -alpha, T(2.0 * kPi));
+    // |alpha| <= pi, so the sweep in the direction of motion reduced to
+    // [0, 2 pi) needs no remainder
+    T sw = h > T(0) ? alpha : -alpha;
     if (sw < T(0)) sw += T(2.0 * kPi);
     *s_hi = sw * Tr<T>::abs_(inv);
     return true;
