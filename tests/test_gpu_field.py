@@ -226,6 +226,33 @@ def test_field_find_matches_oracle(K, orc, batched):
     assert (nh_found >= nh_true).mean() > 0.9
 
 
+def test_field_find_bench_batch(K, orc):
+    """Parity at the size the bench times: the 16 field-traced events of the
+    field-finding bench leg (N ~ Poisson(U(200, 4000)) tracks, 60 noise hits
+    per track), built as bench.py builds them and found as it finds them
+    (width 64, the captured graph), every seed against the FP64 oracle in the
+    same field."""
+    import torch
+    geom, evs = EF.field_find_batch()
+    inp = E.find_inputs(evs)
+    ctx = _ctx(K, geom)
+    ctx.set_find_config(64, False)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run_batched()
+    torch.cuda.synchronize()
+    g = fp.results()
+    o = CM.oracle_find_events(orc, geom, evs, inp, n_threads=16, field_z0=Z0, field_step=STEP)
+    n_same, n_exc, bad = CM.compare_find(g, o)
+    ns = g["hits"].shape[0]
+    print(f"field bench batch: {n_same}/{ns} identical, {n_exc} excused, {bad.size} unexplained")
+    assert bad.size == 0
+    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+    assert same.mean() > 0.98
+    err = CM.par_error(g["par"][same], o["par"][same])
+    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    assert abs(int(g["counters"][0]) - o["n_prop"]) <= 0.01 * o["n_prop"]
+
+
 def test_field_find_refusals(K):
     """Finding in the parametrised field takes neither the learned guess nor
     steering."""
