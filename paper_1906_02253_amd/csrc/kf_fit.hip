@@ -263,7 +263,6 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
     T p[6];
     C P[21];
     if (alive) load_state(par, cov, ld, i, p, P);
-    const T kb = T(kKappa) * T(a.prm.bz);
     bool touched = false;
     for (int k = k0; k < k1; ++k) {
         if (!LEARN && !alive) break;
