@@ -253,6 +253,28 @@ def test_field_find_bench_batch(K, orc):
     assert abs(int(g["counters"][0]) - o["n_prop"]) <= 0.01 * o["n_prop"]
 
 
+def test_field_find_uniform_limit_matches_oracle(K, orc):
+    """The kernel's field path with Z0 = 1e9 cm (a uniform field over the
+    detector, Runge-Kutta transport in 0.5 cm steps) against the oracle's
+    closed-form helix finder on the same events: the finding tests' parity."""
+    import torch
+    geom, evs = E.find_events(n_events=2, n_tracks=300, n_noise=20_000, seed=41)
+    inp = E.find_inputs(evs)
+    ctx = K.Context(geom, field_z0=1e9, field_step=0.5)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run()
+    torch.cuda.synchronize()
+    g = fp.results()
+    o = CM.oracle_find_events(orc, geom, evs, inp)
+    n_same, n_exc, bad = CM.compare_find(g, o)
+    print(f"field uniform limit: {n_same}/{g['hits'].shape[0]} identical, {n_exc} excused")
+    assert bad.size == 0
+    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+    assert same.mean() > 0.98
+    err = CM.par_error(g["par"][same], o["par"][same])
+    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+
+
 def test_field_find_refusals(K):
     """Finding in the parametrised field takes neither the learned guess nor
     steering."""

@@ -187,3 +187,22 @@ def test_field_find_follows_the_field(orc):
     assert eu < ef - 0.01
     assert 0.8 < c2f < 1.1
     assert c2u > c2f + 0.15
+
+
+def test_field_find_uniform_limit_equals_helix_finder(orc):
+    """With Z0 = 1e9 cm the parametrised field is uniform over the detector:
+    finding with Runge-Kutta transport (0.5 cm steps) reproduces the
+    closed-form helix finder on the same events hit for hit, with the same
+    propagations, states to 1e-9 relative and chi2 to 1e-8."""
+    from tests import common as CM
+    geom, evs = E.find_events(n_events=2, n_tracks=300, n_noise=20_000, seed=41)
+    inp = E.find_inputs(evs)
+    u = CM.oracle_find_events(orc, geom, evs, inp)
+    f = CM.oracle_find_events(orc, geom, evs, inp, field_z0=1e9, field_step=0.5)
+    assert np.array_equal(u["hits"], f["hits"])
+    assert np.array_equal(u["status"], f["status"])
+    assert u["n_prop"] == f["n_prop"]
+    ok = u["status"] == 0
+    assert ok.mean() > 0.99
+    assert CM.par_error(f["par"][ok], u["par"][ok]).max() < 1e-9
+    assert np.max(np.abs(f["chi2"][ok] - u["chi2"][ok]) / np.maximum(u["chi2"][ok], 1.0)) < 1e-8
