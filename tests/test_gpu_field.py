@@ -275,6 +275,37 @@ def test_field_find_uniform_limit_matches_oracle(K, orc):
     assert (err.max(axis=1) < CM.REL).mean() > 0.999
 
 
+def test_field_find_with_material_map(K, orc):
+    """Finding in the parametrised field with the r-z material map (its own
+    kernel instance: Runge-Kutta navigation and transport, then the map's
+    scattering and mean energy loss at each crossing) against the FP64 oracle
+    with the same field and map, eager and as the captured graph."""
+    import torch
+    import eventgen.material as EM
+    geom, evs = EF.field_find_events(n_events=2, n_tracks=500, n_noise=20_000, seed=28)
+    mat = EM.material_map(geom, base=0.02, seed=21)
+    inp = E.find_inputs(evs)
+    ctx = _ctx(K, geom)
+    ctx.set_material(mat)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    o = CM.oracle_find_events(orc, geom, evs, inp, field_z0=Z0, field_step=STEP, material_map=mat)
+    for batched in (False, True):
+        if batched:
+            fp.run_batched()
+        else:
+            fp.run()
+        torch.cuda.synchronize()
+        g = fp.results()
+        n_same, n_exc, bad = CM.compare_find(g, o)
+        print(f"field + map ({'graph' if batched else 'eager'}): {n_same}/{g['hits'].shape[0]} "
+              f"identical, {n_exc} excused")
+        assert bad.size == 0
+        same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+        assert same.mean() > 0.98
+        err = CM.par_error(g["par"][same], o["par"][same])
+        assert (err.max(axis=1) < CM.REL).mean() > 0.999
+
+
 def test_field_find_refusals(K):
     """Finding in the parametrised field takes neither the learned guess nor
     steering."""
