@@ -168,6 +168,33 @@ def test_map_find_matches_oracle(K, orc, batched):
     assert (err.max(axis=1) < CM.REL).mean() > 0.999
 
 
+def test_map_find_learned_start_matches_oracle(K, orc):
+    """Finding with the map and the learned start of the barrel solves (its
+    own kernel instance; a freshly initialised network, so most guesses fall
+    back to the straight line): the solve stays exact, so the hit lists match
+    the FP64 oracle's plain finder with the same map."""
+    import torch
+    geom, mat, evs = EM.eloss_find_events(n_events=2, n_tracks=600, n_noise=30_000)
+    inp = E.find_inputs(evs)
+    ctx = K.Context(geom)
+    ctx.set_find_config(64, False)
+    ctx.set_material(mat)
+    ctx.mlp_load(E.mlp_init(5))
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run(K.INIT_MLP)
+    torch.cuda.synchronize()
+    g = fp.results()
+    assert g["counters"][5] > 0                  # guesses were made
+    o = CM.oracle_find_events(orc, geom, evs, inp, material_map=mat)
+    n_same, n_exc, bad = CM.compare_find(g, o)
+    print(f"learned map find: {n_same}/{g['hits'].shape[0]} identical, {n_exc} excused, "
+          f"{bad.size} unexplained; guesses {g['counters'][5]}, fallbacks {g['counters'][6]}")
+    assert bad.size == 0
+    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & ((g["status"] & ~K.ST_FALLBACK) == 0)
+    err = CM.par_error(g["par"][same], o["par"][same])
+    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+
+
 def test_map_energy_loss_cap(K, orc):
     """A cell far thicker than any detector (xi ~ 2 kg/cm^2): the loss is capped
     at half the kinetic energy on both sides and the state stays finite."""

@@ -110,3 +110,33 @@ def test_unreachable_seeds_and_validation(K):
     fp = K.pipeline.FindProblem(ctx, inp)
     with pytest.raises(K.KFError, match="exclude"):
         fp.run(K.INIT_MLP)
+
+
+def test_steered_find_with_material_map(K, orc):
+    """Steered finding with the r-z material map (its own kernel instance):
+    the five-region plans on two barrel + endcap events, scattering and mean
+    energy loss from a map around 0.02 X0, against the FP64 oracle with the
+    same plans and map."""
+    import torch
+    import eventgen.material as EM
+    geom, evs = _events(seed=42, n_events=2, n_tracks=500)
+    inp = E.find_inputs(evs)
+    plans = E.geometry.steering_plans(geom)
+    mat = EM.material_map(geom, base=0.02, seed=21)
+    ctx = K.Context(geom)
+    ctx.set_find_config(64, False)
+    ctx.set_steering(plans)
+    ctx.set_material(mat)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    fp.run()
+    torch.cuda.synchronize()
+    g = fp.results()
+    o = CM.oracle_find_events(orc, geom, evs, inp, steering=plans, material_map=mat)
+    n_same, n_exc, bad = CM.compare_find(g, o)
+    ns = g["hits"].shape[0]
+    print(f"steered find with map: {n_same}/{ns} identical, {n_exc} excused, {bad.size} unexplained")
+    assert bad.size == 0
+    assert n_same > 0.95 * ns
+    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+    err = CM.par_error(g["par"][same], o["par"][same])
+    assert (err.max(axis=1) < CM.REL).mean() > 0.999
