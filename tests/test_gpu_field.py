@@ -154,6 +154,35 @@ def test_field_fit_parity(K, orc, sample):
     assert np.abs(g64["chi2"][ok] - o["chi2"][ok]).max() < 1e-7 * max(1, o["chi2"].max())
 
 
+def test_field_fit_with_material_map(K, orc, sample):
+    """The fit in the parametrised field with the r-z material map (its own
+    kernel instance): the 1,500 field-traced tracks against the FP64 oracle
+    with the same field and map, mixed precision and all-FP64."""
+    import eventgen.material as EM
+    geom, ev = sample
+    mat = EM.material_map(geom, base=0.02, seed=21)
+    par0, cov0 = orc.seeds_for_event(ev)
+    cfg = orc.Config(geom, field_z0=Z0, field_step=STEP, material_map=mat)
+    o = orc.fit(cfg, dict(x=ev.x, y=ev.y, z=ev.z, su=ev.su, sv=ev.sv), ev.seq_layer, ev.seq_hit,
+                par0, cov0, n_threads=8)
+    ctx = _ctx(K, geom)
+    ctx.set_material(mat)
+    g = _fit(K, ctx, ev)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.array_equal(g["ndf"], o["ndf"])
+    ok = o["status"] == 0
+    assert ok.sum() > 1200
+    err = CM.par_error(g["par"][ok], o["par"][ok])
+    cerr = CM.chi2_error(g["chi2"][ok], o["chi2"][ok], o["ndf"][ok])
+    print(f"field + map fit: max rel par err {err.max():.2e}, chi2 err / tol {cerr.max() / CM.CHI2_REL:.3f}")
+    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    assert err.max() < 10 * CM.REL
+    assert cerr.max() < CM.CHI2_REL
+    g64 = _fit(K, ctx, ev, K.PREC_FP64)
+    assert np.array_equal(g64["status"], o["status"])
+    assert CM.par_error(g64["par"][ok], o["par"][ok]).max() < 1e-9
+
+
 def test_field_fit_per_layer_equals_fused(K, sample):
     geom, ev = sample
     ctx = _ctx(K, geom)
