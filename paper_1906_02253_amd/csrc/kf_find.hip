@@ -576,7 +576,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     const int lbase = t - slot;             // lane of this seed's slot 0
     const T kb = T(kKappa) * T(a.prm.bz);
     const float cut = float(a.prm.chi2_cut);
-    unsigned long long n_prop = 0, n_upd = 0, n_chi2 = 0;
+    unsigned n_prop = 0, n_upd = 0, n_chi2 = 0;   // per lane: far below 2^32
     int n_newton = 0, n_disk = 0, n_guess = 0, n_fallback = 0;
     int2* bp_base = a.bp + (size_t)blockIdx.x * nl * S * kMaxCands;
 
@@ -1160,7 +1160,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     }
     if (a.counters) {
         // wave-level reduction of the per-lane counts, one atomic per wave
-        unsigned long long c[kFindCounters] = {n_prop, n_upd, n_chi2, (unsigned long long)n_newton,
+        unsigned long long c[kFindCounters] = {(unsigned long long)n_prop, (unsigned long long)n_upd,
+                                               (unsigned long long)n_chi2, (unsigned long long)n_newton,
                                                (unsigned long long)n_disk, (unsigned long long)n_guess,
                                                (unsigned long long)n_fallback};
 #pragma unroll
