@@ -14,7 +14,12 @@
  *   - transport Jacobian including the path-length derivative (implicit
  *     function theorem on the surface equation);
  *   - multiple scattering at every crossed layer (paper Sec. 3.1: material
- *     per layer) with the PDG Highland width;
+ *     per layer) with the PDG Highland width.  Parity unpinned for the width's
+ *     constants (13.6 MeV, 0.038) and the form of its logarithm: the only
+ *     other statement of them is the event generator's, which the pins
+ *     compare against; the structure around them (path-corrected thickness,
+ *     beta p, the (c, phi, theta) block of the noise) is pinned by the
+ *     toy Monte Carlo of the generator's kicks and by fit pulls;
  *   - Kalman update with a 2D hit measured in the hit's local frame,
  *     Joseph-form covariance (the traditional KF of the paper's Sec. 1);
  *   - layer-by-layer combinatorial finding (paper Sec. 2 and Sec. 4: hit

@@ -617,3 +617,62 @@ def test_disk_fit_pulls(orc):
         v = (d[:, i] / np.sqrt(P[:, i, i]))[ok]
         assert abs(v.mean()) < 0.05 and abs(v.std() - 1) < 0.05, (name, v.mean(), v.std())
     assert abs((r["chi2"][ok] / r["ndf"][ok]).mean() - 1) < 0.05
+
+
+# ---------------------------------------------------------------- seed
+@pytest.mark.parametrize("pt", [0.35, 1.0, 7.0, 100.0])
+def test_seed_of_noise_free_helix_hits(orc, pt):
+    """The three-hit seed (circle through the transverse positions, tangent at
+    hit 1, dip from the arc) of noise-free hits on an analytic helix returns
+    that helix's state at hit 1: position, q/pT, phi and theta to 1e-9.  The
+    hits are the closed-form crossings of brute force (circle-circle
+    intersection for barrels, the rotation about the centre for disks), both
+    charges, |eta| up to 2.5, barrel and disk triplets."""
+    geom = E.geometry.barrel10_disks14(x0=0.0)
+    rng = np.random.default_rng(int(pt * 1000) + 7)
+    n_checked = {0: 0, 1: 0}
+    for trial in range(400):
+        q = rng.choice([-1.0, 1.0])
+        eta = rng.uniform(-2.5, 2.5)
+        th = 2 * math.atan(math.exp(-eta))
+        p = np.array([rng.normal(0, 0.01), rng.normal(0, 0.01), rng.normal(0, 0.01), q / pt,
+                      rng.uniform(-np.pi, np.pi), th])
+        # the first three surfaces the track crosses, by closed forms
+        hits = []
+        cur = p.copy()
+        for _ in range(3):
+            best = None
+            for l, L in enumerate(geom):
+                if L["kind"] == 0:
+                    if L["r_or_z"] <= math.hypot(cur[0], cur[1]) + 1e-6:
+                        continue
+                    r = BF.cf_barrel(cur, L["r_or_z"], BZ)
+                    if r is None or abs(r[0][2]) > L["hi"]:
+                        continue
+                else:
+                    if (L["r_or_z"] - cur[2]) * math.cos(th) <= 1e-6:
+                        continue
+                    r = BF.cf_disk(cur, L["r_or_z"], BZ)
+                    rho = math.hypot(r[0][0], r[0][1])
+                    if not (L["lo"] <= rho <= L["hi"]):
+                        continue
+                if r[1] > 0 and (best is None or r[1] < best[1]):
+                    best = (r[0], r[1], L["kind"])
+            if best is None:
+                break
+            hits.append(best)
+            cur = best[0]
+        if len(hits) < 3:
+            continue
+        kinds = {k for _, _, k in hits}
+        for k in kinds:
+            n_checked[k] += 1
+        want = hits[0][0]
+        got, P = orc.seed(want[:3], hits[1][0][:3], hits[2][0][:3], BZ)
+        assert np.abs(got[:3] - want[:3]).max() < 1e-9
+        assert abs(got[3] - want[3]) < 1e-9 * max(abs(want[3]), 1.0)
+        assert abs(wrap(got[4] - want[4])) < 1e-9
+        assert abs(got[5] - want[5]) < 1e-9
+        # the prior is the fixed diffuse diagonal
+        assert np.allclose(orc.unpack(P), np.diag([1, 1, 1, 4, 0.01, 0.01]))
+    assert n_checked[0] > 100 and n_checked[1] > 20, n_checked
