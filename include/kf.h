@@ -64,8 +64,10 @@ enum {
 
 /* flags */
 enum {
-    KF_PREC_MIXED = 0,     /* state and transport (helix, Jacobian) FP32; covariance kept in
-                              FP64 (storage and F P F^T); update (S, S^-1, gain, Joseph) FP64 */
+    KF_PREC_MIXED = 0,     /* FP32 storage of state and covariance; surface solves, helix,
+                              transport Jacobian, navigation and search windows FP32; F P F^T,
+                              the process noise and the update (S, S^-1, gain, Joseph) FP64,
+                              with the state held in FP64 between its FP32 loads and stores */
     KF_PREC_FP32 = 1,      /* everything FP32 (Joseph form kept) */
     KF_PREC_FP64 = 2,      /* everything FP64 */
     KF_PREC_MASK = 3,
@@ -115,9 +117,8 @@ typedef struct {
                               0 < dup_frac <= 1 */
 } kf_params;
 
-/* Track states, SoA with leading dimension ld.  par [6][ld] and chi2 [ld]
- * are float (double with KF_PREC_FP64); cov [21][ld] is double (float with
- * KF_PREC_FP32).  ndf = 2*hits - 5. */
+/* Track states, SoA with leading dimension ld.  par [6][ld], cov [21][ld]
+ * and chi2 [ld] are float (double with KF_PREC_FP64).  ndf = 2*hits - 5. */
 typedef struct {
     int64_t n, ld;
     void* par;
@@ -382,6 +383,15 @@ int kf_mlp_get(kf_ctx* ctx, float* w);
  * (-1: zeros).  feats [8][t->ld] float32, device. */
 int kf_mlp_features(kf_ctx* ctx, const kf_tracks* t, const int32_t* target_layer, float* feats,
                     int flags, void* stream);
+/* Training targets: for n propagations with inputs feats [8][ld] (from
+ * kf_mlp_features) and transverse path lengths path_len [ld] [cm] (from the
+ * plain kf_propagate), target [ld] = the network output that makes the guess
+ * equal the path, (path_len - s_line) / (h s_line^2) in the inputs' units
+ * (s_line = 100 feats[5], h s_line^2 = 100 feats[3] feats[5]^2 / feats[4]);
+ * 0 where |feats[3] feats[5]^2 / feats[4]| <= 1e-9 (no curvature term).
+ * Device float arrays; rows beyond n untouched. */
+int kf_mlp_targets(kf_ctx* ctx, const float* feats, const float* path_len, int64_t n, int64_t ld,
+                   float* target, void* stream);
 /* Network outputs out [n] for inputs feats [8][ld] (device). */
 int kf_mlp_forward(kf_ctx* ctx, const float* feats, int64_t n, int64_t ld, float* out, void* stream);
 /* Mean-squared-error loss and its gradient over the batch rows rows [batch]

@@ -85,7 +85,7 @@ def lib():
         L.orc_fit.argtypes = [cfgp, C.c_long, C.c_int, dp, dp, dp, dp, dp, ip, ip, dp, dp, dp,
                               ip, ip, C.c_int]
         L.orc_find.argtypes = [cfgp, C.c_long, dp, dp, dp, dp, dp, ip, C.c_long, ip, C.c_int,
-                               ip, dp, dp, dp, ip, ip, ip, lp, C.c_int]
+                               ip, dp, dp, dp, ip, ip, ip, ip, lp, C.c_int]
         L.orc_dedup.argtypes = [C.c_long, C.c_int, ip, dp, ip, ip, C.c_double, ip]
         L.orc_dedx.argtypes = [C.c_double, C.c_double]
         L.orc_dedx.restype = C.c_double
@@ -233,7 +233,12 @@ def fit(cfg, hits, layer_seq, hit_idx, par0, cov0, n_threads=1):
 
 
 def find(cfg, ev, seed_hits, binned=True, n_threads=1):
-    """Combinatorial finding on one event; seed_hits [n_seeds, 3] event-local indices."""
+    """Combinatorial finding on one event; seed_hits [n_seeds, 3] event-local
+    indices.  Per seed: the best candidate's hit list, state, chi2, ndf and
+    status; tie = the walk step of the first decision taken within 1e-3 of its
+    threshold (nl: only the final choice was close; -1: none); visit [n_seeds,
+    n_layers] = the walk step at which the best candidate last reached each
+    layer (-1: never; the seed's own layers precede the walk)."""
     L = lib()
     f64 = lambda a: np.ascontiguousarray(a, np.float64)
     seed_hits = np.ascontiguousarray(seed_hits, np.int32)
@@ -246,12 +251,13 @@ def find(cfg, ev, seed_hits, binned=True, n_threads=1):
     ndf = np.zeros(ns, np.int32)
     st = np.zeros(ns, np.int32)
     tie = np.zeros(ns, np.int32)
+    visit = np.zeros((ns, nl), np.int32)
     cnt = np.zeros(2, np.int64)
     L.orc_find(cfg.ref, ev.n_hits, f64(ev.x), f64(ev.y), f64(ev.z), f64(ev.su), f64(ev.sv),
                np.ascontiguousarray(ev.layer, np.int32), ns, seed_hits, int(binned), out_hits,
-               par, cov, c2, ndf, st, tie, cnt, int(n_threads))
+               par, cov, c2, ndf, st, tie, visit, cnt, int(n_threads))
     return dict(hits=out_hits, par=par, cov=cov, chi2=c2, ndf=ndf, status=st, tie=tie,
-                n_prop=int(cnt[0]), n_upd=int(cnt[1]))
+                visit=visit, n_prop=int(cnt[0]), n_upd=int(cnt[1]))
 
 
 def field(cfg, x):

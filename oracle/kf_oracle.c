@@ -785,6 +785,7 @@ typedef struct {
     int nhits, misses, done, status;
     int pos;                 /* steering: next plan entry */
     int hits[MAXL];
+    int visit[MAXL];         /* walk step at which each layer was last reached (-1: never) */
 } cand_t;
 
 typedef struct {
@@ -1231,7 +1232,7 @@ typedef struct {
     int binned;
     int* out_hits;
     double *out_par, *out_cov, *out_chi2;
-    int *out_ndf, *out_status, *out_tie;
+    int *out_ndf, *out_status, *out_tie, *out_visit;
     long counters[2];
 } find_job;
 
@@ -1257,6 +1258,7 @@ static void find_seed(find_job* J, long sd)
     cand_t* c0 = &cands[0];
     memset(c0, 0, sizeof(cand_t));
     for (int l = 0; l < nl; ++l) c0->hits[l] = -1;
+    for (int l = 0; l < nl; ++l) c0->visit[l] = -1;
     double a[3] = {E->hx[sh[0]], E->hy[sh[0]], E->hz[sh[0]]};
     double b[3] = {E->hx[sh[1]], E->hy[sh[1]], E->hz[sh[1]]};
     double c[3] = {E->hx[sh[2]], E->hy[sh[2]], E->hz[sh[2]]};
@@ -1362,6 +1364,7 @@ static void find_seed(find_job* J, long sd)
             *nx = *par;
             int layer = pred_layer[x->parent];
             if (layer < 0) continue;              /* frozen: carried unchanged */
+            nx->visit[layer] = step;
             if (x->hit != NO_HIT) {
                 double hit[5] = {E->hx[x->hit], E->hy[x->hit], E->hz[x->hit], E->hsu[x->hit],
                                  E->hsv[x->hit]};
@@ -1393,6 +1396,8 @@ static void find_seed(find_job* J, long sd)
         tie = nl;
     const cand_t* best = &cands[0];
     for (int l = 0; l < nl; ++l) J->out_hits[sd * nl + l] = best->hits[l];
+    if (J->out_visit)
+        for (int l = 0; l < nl; ++l) J->out_visit[sd * nl + l] = best->visit[l];
     memcpy(J->out_par + 6 * sd, best->p, sizeof(best->p));
     memcpy(J->out_cov + 21 * sd, best->P, sizeof(best->P));
     J->out_chi2[sd] = best->chi2;
@@ -1420,7 +1425,7 @@ void orc_find(const orc_cfg* cfg, long n_hits,
               const double* hsu, const double* hsv, const int* hlayer,
               long n_seeds, const int* seed_hits, int binned,
               int* out_hits, double* out_par, double* out_cov, double* out_chi2,
-              int* out_ndf, int* out_status, int* out_tie_step, long* counters,
+              int* out_ndf, int* out_status, int* out_tie_step, int* out_visit, long* counters,
               int n_threads)
 {
     event_index E;
@@ -1435,7 +1440,7 @@ void orc_find(const orc_cfg* cfg, long n_hits,
     for (int i = 0; i < n_threads; ++i) {
         find_job J = {cfg, &E, n_seeds * i / n_threads, n_seeds * (i + 1) / n_threads,
                       seed_hits, binned, out_hits, out_par, out_cov, out_chi2, out_ndf,
-                      out_status, out_tie_step, {0, 0}};
+                      out_status, out_tie_step, out_visit, {0, 0}};
         jobs[i] = J;
     }
     if (n_threads == 1) find_worker(&jobs[0]);

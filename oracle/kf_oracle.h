@@ -136,8 +136,8 @@ void orc_find(const orc_cfg* cfg, long n_hits,
               const double* hsu, const double* hsv, const int* hlayer,
               long n_seeds, const int* seed_hits, int binned,
               int* out_hits, double* out_par, double* out_cov, double* out_chi2,
-              int* out_ndf, int* out_status, int* out_tie_step, long* counters,
-              int n_threads);
+              int* out_ndf, int* out_status, int* out_tie_step, int* out_visit,
+              long* counters, int n_threads);
 
 /* Mean ionisation loss (Bethe, no density effect) in silicon [MeV cm^2/g]
  * of a particle of momentum p and mass m [GeV]. */

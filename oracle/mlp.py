@@ -137,6 +137,19 @@ def features(state, kind, target, bz=3.8, field_z0=0.0):
     return f
 
 
+def target(f, path):
+    """Training target of one propagation with inputs f [n, 8] (features())
+    and transverse path length `path` [n] [cm]: the output y for which the
+    guess s_line + h s_line^2 y equals the path, written in the inputs'
+    units (s_line = 100 f5, h s_line^2 = 100 f3 f5^2 / f4); 0 where that
+    scale is at most 1e-9 (no curvature term)."""
+    f = np.atleast_2d(np.asarray(f, np.float64))
+    path = np.asarray(path, np.float64)
+    k = np.where(f[:, 4] != 0, f[:, 3] * f[:, 5] ** 2 / np.where(f[:, 4] != 0, f[:, 4], 1.0), 0.0)
+    big = np.abs(k) > 1e-9
+    return np.where(big, (path / 100.0 - f[:, 5]) / np.where(big, k, 1.0), 0.0)
+
+
 def bf16_round(a):
     """Round float64 values to the nearest bfloat16 (ties to even), returned
     as float64: the precision the network's weights and inputs take on the

@@ -101,11 +101,13 @@ def _load():
     L.kf_mlp_get.argtypes = [vp, fp]
     L.kf_mlp_features.argtypes = [vp, C.POINTER(KfTracks), vp, vp, C.c_int, vp]
     L.kf_mlp_forward.argtypes = [vp, vp, i64, i64, vp, vp]
+    L.kf_mlp_targets.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.kf_mlp_grad.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp, vp, vp]
     L.kf_mlp_train.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, C.POINTER(KfTrainCfg), vp, vp]
     for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_find_batched",
               "kf_set_find_config", "kf_get_find_config", "kf_autotune", "kf_set_timing",
               "kf_timings", "kf_mlp_load", "kf_mlp_get", "kf_mlp_features", "kf_mlp_forward",
+              "kf_mlp_targets",
               "kf_mlp_grad", "kf_mlp_train"):
         getattr(L, f).restype = C.c_int
     return L
@@ -135,15 +137,14 @@ def round_ld(n):
 class Tracks:
     """SoA track states on the GPU: par [6, ld], cov [21, ld], chi2 [ld], ndf, status.
 
-    Storage types follow the precision: MIXED par/chi2 float32, cov float64;
-    FP32 all float32; FP64 all float64."""
+    Storage types follow the precision: MIXED and FP32 float32, FP64 float64."""
 
     def __init__(self, n, ld=None, prec=PREC_MIXED, device="cuda"):
         self.n = int(n)
         self.ld = int(ld or round_ld(n))
         self.prec = prec
         pd = torch.float64 if prec == PREC_FP64 else torch.float32
-        cd = torch.float32 if prec == PREC_FP32 else torch.float64
+        cd = pd
         self.par = torch.zeros((6, self.ld), dtype=pd, device=device)
         self.cov = torch.zeros((21, self.ld), dtype=cd, device=device)
         self.chi2 = torch.zeros(self.ld, dtype=pd, device=device)
@@ -359,6 +360,12 @@ class Context:
         """feats: float32 [8, tracks.ld] on the GPU."""
         self._check(lib.kf_mlp_features(self.h, C.byref(tracks.c()), _ptr(target), _ptr(feats),
                                         flags, _stream()), "kf_mlp_features")
+
+    def mlp_targets(self, feats, path_len, n, target):
+        """Training targets [ld] from inputs feats [8, ld] and path lengths [ld]."""
+        self._check(lib.kf_mlp_targets(self.h, _ptr(feats), _ptr(path_len), int(n),
+                                       int(feats.shape[1]), _ptr(target), _stream()),
+                    "kf_mlp_targets")
 
     def mlp_forward(self, feats, n, out):
         self._check(lib.kf_mlp_forward(self.h, _ptr(feats), int(n), int(feats.shape[1]), _ptr(out),

@@ -185,7 +185,7 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.n_seeds = seeds->n;
     a.sld = seeds->ld;
     a.spar = (const float*)seeds->par;
-    a.scov = seeds->cov;
+    a.scov = (const float*)seeds->cov;
     a.schi2 = (const float*)seeds->chi2;
     a.sndf = seeds->ndf;
     a.sstatus = seeds->status;
@@ -196,7 +196,7 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.out_hits = out_hits;
     a.old = out->ld;
     a.opar = (float*)out->par;
-    a.ocov = out->cov;
+    a.ocov = (float*)out->cov;
     a.ochi2 = (float*)out->chi2;
     a.ondf = out->ndf;
     a.ostatus = out->status;
@@ -475,6 +475,9 @@ int kf_set_steering(kf_ctx* ctx, const kf_region* regions, int32_t n_regions)
     }
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_steering");
+    // a captured pass holds the old steering pointer: capture again next time
+    release_graph(ctx);
+    ctx->setup_gen++;
     if (ctx->d_steer) {
         e = hipFree(ctx->d_steer);
         ctx->d_steer = nullptr;
@@ -510,6 +513,10 @@ int kf_set_material(kf_ctx* ctx, const kf_material* m)
     }
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(ctx, e, "kf_set_material");
+    // a captured pass holds the old map's pointers and sizes by value: capture
+    // again next time
+    release_graph(ctx);
+    ctx->setup_gen++;
     if (ctx->d_mat) {
         e = hipFree(ctx->d_mat);
         ctx->d_mat = nullptr;
@@ -676,6 +683,7 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
     put((uint64_t)(uintptr_t)ctx->ws.ptr); put((uint64_t)ctx->ws.bytes);
     put((uint64_t)(uintptr_t)ctx->mat.x0);
     put((uint64_t)(uintptr_t)ctx->d_steer);
+    put(ctx->setup_gen);
     kfmi::FindGraph& g = ctx->fg;
     const bool same = g.exec && g.nkey == nk && memcmp(g.key, key, sizeof(uint64_t) * nk) == 0;
     if (!same) {
@@ -916,6 +924,17 @@ int kf_mlp_features(kf_ctx* ctx, const kf_tracks* t, const int32_t* target_layer
     hipError_t e = kfmi::launch_mlp_features(ctx, t, target_layer, feats, flags & KF_PREC_MASK,
                                              (hipStream_t)stream);
     return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_mlp_features");
+}
+
+int kf_mlp_targets(kf_ctx* ctx, const float* feats, const float* path_len, int64_t n, int64_t ld,
+                   float* target, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_mlp_targets: null context");
+    if (n < 0 || ld < n) return fail(ctx, KF_EINVAL, "kf_mlp_targets: need 0 <= n <= ld");
+    if (n > 0 && (!feats || !path_len || !target))
+        return fail(ctx, KF_EINVAL, "kf_mlp_targets: null array");
+    hipError_t e = kfmi::launch_mlp_targets(feats, path_len, n, ld, target, (hipStream_t)stream);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_mlp_targets");
 }
 
 int kf_mlp_forward(kf_ctx* ctx, const float* feats, int64_t n, int64_t ld, float* out, void* stream)

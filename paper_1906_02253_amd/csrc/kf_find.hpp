@@ -41,7 +41,7 @@ struct FindArgs {
     // seeds (par/cov/chi2/ndf/status after the seed fit), SoA with leading dim sld
     int64_t n_seeds, sld;
     const float* spar;
-    const void* scov;             // double (mixed) or float (FP32)
+    const float* scov;            // float storage (mixed and FP32 modes)
     const float* schi2;
     const int32_t* sndf;
     const uint32_t* sstatus;
@@ -53,7 +53,7 @@ struct FindArgs {
     int32_t* out_hits;            // [n_seeds][n_layers]
     int64_t old;
     float* opar;
-    void* ocov;
+    float* ocov;
     float* ochi2;
     int32_t* ondf;
     uint32_t* ostatus;

@@ -10,60 +10,68 @@
 
 namespace kfmi {
 
-// par is stored in T, cov in C (T = state precision, C = covariance precision)
-template <typename T, typename C>
-__device__ inline void load_state(const T* par, const C* cov, int64_t ld, int64_t i, T p[6],
+// par and cov are stored in T, the state precision (FP32 in the mixed and
+// FP32 modes); in registers the state is held in U (the update precision) and
+// the covariance in C (the covariance-arithmetic precision).
+template <typename T, typename C, typename U>
+__device__ inline void load_state(const T* par, const T* cov, int64_t ld, int64_t i, U p[6],
                                   C P[21])
 {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) p[k] = par[k * ld + i];
+    for (int k = 0; k < 6; ++k) p[k] = U(par[k * ld + i]);
 #pragma unroll
-    for (int k = 0; k < 21; ++k) P[k] = cov[k * ld + i];
+    for (int k = 0; k < 21; ++k) P[k] = C(cov[k * ld + i]);
 }
 
-template <typename T, typename C>
-__device__ inline void store_state(T* par, C* cov, int64_t ld, int64_t i, const T p[6],
+template <typename T, typename C, typename U>
+__device__ inline void store_state(T* par, T* cov, int64_t ld, int64_t i, const U p[6],
                                    const C P[21])
 {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) par[k * ld + i] = p[k];
+    for (int k = 0; k < 6; ++k) par[k * ld + i] = T(p[k]);
 #pragma unroll
-    for (int k = 0; k < 21; ++k) cov[k * ld + i] = P[k];
+    for (int k = 0; k < 21; ++k) cov[k * ld + i] = T(P[k]);
 }
 
-// Propagate (p, P) to layer L.  s_init < 0: straight-line start; otherwise
-// the learned start with prm.mlp_max_iter evaluations before the fallback
-// to the straight-line start (counted in *fallbacks).
+// Propagate (p, P) to layer L.  The surface solve, the helix and the
+// transport Jacobian run in T on the state rounded to T; the state itself
+// stays in U (transport adds the T increments in U) and the covariance in C.
+// s_init < 0: straight-line start; otherwise the learned start with
+// prm.mlp_max_iter evaluations before the fallback to the straight-line
+// start (counted in *fallbacks).
 // FIELD: the parametrised field (kf_params.field_z0 > 0); MAT: the r-z material
 // map.  Both are compile-time variants so that the uniform-field, per-layer
 // material instantiation keeps its register budget.
-template <typename T, typename C, bool FIELD, bool MAT>
-__device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_params& prm,
+template <typename T, typename C, typename U, bool FIELD, bool MAT>
+__device__ inline int propagate_to(U p[6], C P[21], const kf_layer& L, const kf_params& prm,
                                    bool material, const MatMap& mat, T s_init, T* s_out, int* evals,
                                    int* fallbacks)
 {
     const T kb = T(kKappa) * T(prm.bz);
+    T pt[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pt[k] = T(p[k]);
     T s;
     if constexpr (FIELD) {
         // parametrised field: Runge-Kutta transport to a barrel; the covariance
         // is carried by the helix Jacobian in the start point's field
         if (L.kind != 0) return KF_ST_UNREACHABLE;
         T bx, by, bz0;
-        field_at(T(prm.bz), T(prm.field_z0), p[0], p[1], p[2], &bx, &by, &bz0);
+        field_at(T(prm.bz), T(prm.field_z0), pt[0], pt[1], pt[2], &bx, &by, &bz0);
         const T kb0 = T(kKappa) * bz0;
-        const T sth = Tr<T>::sin_(p[5]);
+        const T sth = Tr<T>::sin_(pt[5]);
         T l;
-        int st = solve_barrel_field(p, T(L.r_or_z), prm, kb0, s_init >= T(0) ? s_init / sth : T(-1),
+        int st = solve_barrel_field(pt, T(L.r_or_z), prm, kb0, s_init >= T(0) ? s_init / sth : T(-1),
                                     prm.mlp_max_iter, &l, evals, fallbacks);
         if (st) return st;
         T q[6];
-        rk_path(p, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
+        rk_path(pt, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
         field_transport(p, P, q, l, kb0, T(L.r_or_z));
         if (material) {
             if constexpr (MAT)
-                add_material(p, P, L, mat, T(prm.mass));
+                add_material(p, P, L, mat, U(prm.mass));
             else
-                add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
+                add_scatter(p, P, L.kind, U(L.x0), U(prm.mass));
         }
         if (s_out) *s_out = l * sth;
         bool fin = true;
@@ -72,30 +80,30 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
         return fin ? 0 : KF_ST_NAN;
     }
     if (L.kind == 0) {
-        const T h = -kb * p[3];
+        const T h = -kb * pt[3];
         T sph, cph;
-        Tr<T>::sincos_(p[4], &sph, &cph);
+        Tr<T>::sincos_(pt[4], &sph, &cph);
         const T r_l = T(L.r_or_z);
         T s_hi;
-        if (!barrel_bracket(p[0], p[1], cph, sph, h, r_l, &s_hi)) return KF_ST_UNREACHABLE;
-        int st = solve_barrel(p, h, cph, sph, r_l, s_hi, prm, s_init, prm.mlp_max_iter, &s, evals,
+        if (!barrel_bracket(pt[0], pt[1], cph, sph, h, r_l, &s_hi)) return KF_ST_UNREACHABLE;
+        int st = solve_barrel(pt, h, cph, sph, r_l, s_hi, prm, s_init, prm.mlp_max_iter, &s, evals,
                               fallbacks);
         if (st) return st;
     } else {
         T st_, ct_;
-        Tr<T>::sincos_(p[5], &st_, &ct_);
+        Tr<T>::sincos_(pt[5], &st_, &ct_);
         if (ct_ == T(0)) return KF_ST_UNREACHABLE;
-        s = (T(L.r_or_z) - p[2]) * st_ / ct_;
+        s = (T(L.r_or_z) - pt[2]) * st_ / ct_;
         *evals += 1;
         if (s < T(0)) return KF_ST_UNREACHABLE;
     }
     transport(p, P, s, kb, L.kind, T(L.r_or_z));
     if (material) {
-            if constexpr (MAT)
-                add_material(p, P, L, mat, T(prm.mass));
-            else
-                add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
-        }
+        if constexpr (MAT)
+            add_material(p, P, L, mat, U(prm.mass));
+        else
+            add_scatter(p, P, L.kind, U(L.x0), U(prm.mass));
+    }
     if (s_out) *s_out = s;
     bool fin = true;
 #pragma unroll
@@ -104,13 +112,13 @@ __device__ inline int propagate_to(T p[6], C P[21], const kf_layer& L, const kf_
 }
 
 // ---------------------------------------------------------------- seed
-template <typename T, typename C>
+template <typename T>
 __global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_t n_hits,
                                                    const float* __restrict__ hx,
                                                    const float* __restrict__ hy,
                                                    const float* __restrict__ hz,
                                                    const int32_t* __restrict__ seed_hits, double bz,
-                                                   T* __restrict__ par, C* __restrict__ cov,
+                                                   T* __restrict__ par, T* __restrict__ cov,
                                                    T* __restrict__ chi2, int32_t* __restrict__ ndf,
                                                    uint32_t* __restrict__ status)
 {
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_
     const D s13 = fabs(w) < D(1e-4) ? d13 * (D(1) + w2 * (D(1.0 / 6.0) + w2 * D(3.0 / 40.0)))
                                      : d13 * asin(w) / w;
     T p[6];
-    C P[21];
+    T P[21];
     p[0] = T(x1);
     p[1] = T(y1);
     p[2] = T(z1);
@@ -149,11 +157,11 @@ __global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_
     p[4] = T(wrap_phi(atan2(by, bx) - D(0.5) * h * s13));
     p[5] = T(atan2(s13, D(hz[c]) - z1));
 #pragma unroll
-    for (int k = 0; k < 21; ++k) P[k] = C(0);
-    P[pk(0, 0)] = P[pk(1, 1)] = P[pk(2, 2)] = C(1);
-    P[pk(3, 3)] = C(4);
-    P[pk(4, 4)] = P[pk(5, 5)] = C(0.01);
-    store_state(par, cov, ld, i, p, P);
+    for (int k = 0; k < 21; ++k) P[k] = T(0);
+    P[pk(0, 0)] = P[pk(1, 1)] = P[pk(2, 2)] = T(1);
+    P[pk(3, 3)] = T(4);
+    P[pk(4, 4)] = P[pk(5, 5)] = T(0.01);
+    store_state<T, T, T>(par, cov, ld, i, p, P);
     chi2[i] = T(0);
     ndf[i] = -5;
     status[i] = 0;
@@ -162,9 +170,9 @@ __global__ __launch_bounds__(256) void seed_kernel(int64_t n, int64_t ld, int64_
 // ---------------------------------------------------------------- propagate
 // LEARN: every lane of the wave runs to the network call (uniform control
 // flow around the matrix-core instructions).
-template <typename T, typename C, bool LEARN, bool FIELD, bool MAT>
+template <typename T, typename C, typename U, bool LEARN, bool FIELD, bool MAT>
 __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T* __restrict__ par,
-                                                        C* __restrict__ cov,
+                                                        T* __restrict__ cov,
                                                         uint32_t* __restrict__ status,
                                                         const int32_t* __restrict__ target,
                                                         const kf_layer* __restrict__ layers,
@@ -185,7 +193,7 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
         if (iters) iters[i] = 0;
         return;
     }
-    T p[6];
+    U p[6];
     C P[21];
     kf_layer L;
     if (active) {
@@ -196,7 +204,12 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
     if (LEARN) {
         float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
         const bool want = active && L.kind == 0;
-        if (want) mlp_features(p, L, prm, f);
+        if (want) {
+            T pt[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pt[k] = T(p[k]);
+            mlp_features(pt, L, prm, f);
+        }
         const float y = mlp_wave(mlp, f);
         if (want) s_init = T(mlp_guess(f, y));
         if (!inb) return;
@@ -209,7 +222,7 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
     }
     T s = T(0);
     int ev = 0, fb = 0;
-    int r = propagate_to<T, C, FIELD, MAT>(p, P, L, prm, material != 0, mat, s_init, &s, &ev, &fb);
+    int r = propagate_to<T, C, U, FIELD, MAT>(p, P, L, prm, material != 0, mat, s_init, &s, &ev, &fb);
     if (fb) st |= KF_ST_FALLBACK;
     if (r) {
         st |= (uint32_t)r;
@@ -252,7 +265,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
     const bool inb = i < a.n;
     const int64_t ld = a.ld;
     T* par = (T*)a.par;
-    C* cov = (C*)a.cov;
+    T* cov = (T*)a.cov;
     T* chi2p = (T*)a.chi2;
     uint32_t st = (init || !inb) ? 0u : a.status[i];
     int32_t ndf = (init || !inb) ? -5 : a.ndf[i];
@@ -260,7 +273,8 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
     bool alive = inb && !(st & kFreezeMask);
     if (!LEARN && !alive) return;
     const bool was_alive = alive;
-    T p[6];
+    // the state stays in U between steps (rounded to T only when stored)
+    U p[6];
     C P[21];
     if (alive) load_state(par, cov, ld, i, p, P);
     bool touched = false;
@@ -282,14 +296,19 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
         if (LEARN) {
             float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
             const bool want = alive && L.kind == 0;
-            if (want) mlp_features(p, L, a.prm, f);
+            if (want) {
+                T pt[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) pt[q] = T(p[q]);
+                mlp_features(pt, L, a.prm, f);
+            }
             const float y = mlp_wave(a.mlp, f);
             if (want) s_init = T(mlp_guess(f, y));
         }
         if (!alive) continue;
         int ev = 0, fb = 0;
-        int r = propagate_to<T, C, FIELD, MAT>(p, P, L, a.prm, a.material != 0, a.mat, s_init, (T*)nullptr,
-                                                &ev, &fb);
+        int r = propagate_to<T, C, U, FIELD, MAT>(p, P, L, a.prm, a.material != 0, a.mat, s_init,
+                                                   (T*)nullptr, &ev, &fb);
         touched = true;
         if (fb) st |= KF_ST_FALLBACK;
         if (r) {
@@ -306,7 +325,7 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
         if (hi >= 0) {
             HitFrame<U> f = hit_frame<U>(a.hx[hi], a.hy[hi], a.hz[hi], a.hsu[hi], a.hsv[hi]);
             U c2 = U(0);
-            r = kf_update<T, C, U>(p, P, f, L.kind, &c2);
+            r = kf_update<U, C, U>(p, P, f, L.kind, &c2);
             if (r) {
                 st |= (uint32_t)r;
                 alive = false;
@@ -337,20 +356,13 @@ hipError_t launch_seed(const kf_ctx* ctx, const kf_hits* h, const int32_t* seed_
     const int prec = flags & KF_PREC_MASK;
     dim3 g = grid_for(out->n, 256);
     if (prec == KF_PREC_FP64)
-        seed_kernel<double, double><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
-                                                      ctx->params.bz, (double*)out->par,
-                                                      (double*)out->cov, (double*)out->chi2,
-                                                      out->ndf, out->status);
-    else if (prec == KF_PREC_FP32)
-        seed_kernel<float, float><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
-                                                    ctx->params.bz, (float*)out->par,
-                                                    (float*)out->cov, (float*)out->chi2, out->ndf,
-                                                    out->status);
+        seed_kernel<double><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
+                                              ctx->params.bz, (double*)out->par, (double*)out->cov,
+                                              (double*)out->chi2, out->ndf, out->status);
     else
-        seed_kernel<float, double><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
-                                                     ctx->params.bz, (float*)out->par,
-                                                     (double*)out->cov, (float*)out->chi2, out->ndf,
-                                                     out->status);
+        seed_kernel<float><<<g, 256, 0, s>>>(out->n, out->ld, h->n, h->x, h->y, h->z, seed_hits,
+                                             ctx->params.bz, (float*)out->par, (float*)out->cov,
+                                             (float*)out->chi2, out->ndf, out->status);
     return hipGetLastError();
 }
 
@@ -364,30 +376,31 @@ hipError_t launch_propagate(const kf_ctx* ctx, kf_tracks* t, const int32_t* targ
     const MlpDev m = ctx->mlp.dev();
     dim3 g = grid_for(t->n, 256);
     const bool field = ctx->params.field_z0 > 0.0, map = ctx->mat.x0 != nullptr;
-#define KF_PROP1(TT, CC, LL, FF, MM)                                                                 \
-    propagate_kernel<TT, CC, LL, FF, MM><<<g, 256, 0, s>>>(t->n, t->ld, (TT*)t->par, (CC*)t->cov,  \
-                                                           t->status, target, ctx->d_layers,       \
-                                                           ctx->n_layers, ctx->params, material,   \
-                                                           ctx->mat, path_len, iters, m)
-#define KF_PROP(TT, CC, LL)                                                                          \
+#define KF_PROP1(TT, CC, UU, LL, FF, MM)                                                             \
+    propagate_kernel<TT, CC, UU, LL, FF, MM><<<g, 256, 0, s>>>(t->n, t->ld, (TT*)t->par, (TT*)t->cov, \
+                                                               t->status, target, ctx->d_layers,   \
+                                                               ctx->n_layers, ctx->params,         \
+                                                               material, ctx->mat, path_len, iters, \
+                                                               m)
+#define KF_PROP(TT, CC, UU, LL)                                                                      \
     do {                                                                                             \
         if (field) {                                                                                 \
-            if (map) KF_PROP1(TT, CC, LL, true, true);                                               \
-            else KF_PROP1(TT, CC, LL, true, false);                                                  \
+            if (map) KF_PROP1(TT, CC, UU, LL, true, true);                                           \
+            else KF_PROP1(TT, CC, UU, LL, true, false);                                              \
         } else {                                                                                     \
-            if (map) KF_PROP1(TT, CC, LL, false, true);                                              \
-            else KF_PROP1(TT, CC, LL, false, false);                                                 \
+            if (map) KF_PROP1(TT, CC, UU, LL, false, true);                                          \
+            else KF_PROP1(TT, CC, UU, LL, false, false);                                             \
         }                                                                                            \
     } while (0)
     if (prec == KF_PREC_FP64) {
-        if (learn) KF_PROP(double, double, true);
-        else KF_PROP(double, double, false);
+        if (learn) KF_PROP(double, double, double, true);
+        else KF_PROP(double, double, double, false);
     } else if (prec == KF_PREC_FP32) {
-        if (learn) KF_PROP(float, float, true);
-        else KF_PROP(float, float, false);
+        if (learn) KF_PROP(float, float, float, true);
+        else KF_PROP(float, float, float, false);
     } else {
-        if (learn) KF_PROP(float, double, true);
-        else KF_PROP(float, double, false);
+        if (learn) KF_PROP(float, double, double, true);
+        else KF_PROP(float, double, double, false);
     }
 #undef KF_PROP
 #undef KF_PROP1

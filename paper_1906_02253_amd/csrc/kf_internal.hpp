@@ -90,6 +90,8 @@ struct kf_ctx {
     hipStream_t cap_stream = nullptr; // private stream the batched pass is captured on
     hipEvent_t idle_ev[kfmi::kPhaseEvents] = {};  // record targets of an untimed graph launch
     kfmi::FindGraph fg;
+    uint64_t setup_gen = 0;           // bumped by every change of the material map or the
+                                      // steering, which captured launches take by value
     void* mlp_mem = nullptr;          // device block holding the network buffers
     kfmi::MlpBuffers mlp;             // views into mlp_mem
     bool mlp_loaded = false;

@@ -180,11 +180,15 @@ KF_HD inline int newton_barrel(T x, T y, T phi, T h, T r_l, T s, T s_lo, T s_hi,
 }
 
 // Transport of (p, P) by arc length s to a surface: new state, F P F^T.
-// kind 0: barrel (path length from r(s) = r_l); 1: disk at z = zd.
-template <typename T, typename C>
-KF_HD inline void transport(T p[6], C P[21], T s, T kb, int kind, T zd)
+// kind 0: barrel (path length from r(s) = r_l); 1: disk at z = zd.  The
+// helix and the Jacobian are evaluated in T; the state p is held in S (S may
+// be wider than T: the position and azimuth then advance by increments
+// computed in T and added in S, so the predicted state carries no rounding
+// to T before the update that consumes it); F P F^T is accumulated in C.
+template <typename T, typename C, typename S>
+KF_HD inline void transport(S p[6], C P[21], T s, T kb, int kind, T zd)
 {
-    const T x = p[0], y = p[1], z = p[2], c = p[3], phi = p[4], th = p[5];
+    const T x = T(p[0]), y = T(p[1]), z = T(p[2]), c = T(p[3]), phi = T(p[4]), th = T(p[5]);
     const T h = -kb * c;
     HelixPoint<T> q = helix_at(x, y, phi, h, s);
     T st, ct;
@@ -255,10 +259,10 @@ KF_HD inline void transport(T p[6], C P[21], T s, T kb, int kind, T zd)
         }
 #pragma unroll
     for (int k = 0; k < 21; ++k) P[k] = Pn[k];
-    p[0] = q.X;
-    p[1] = q.Y;
-    p[2] = z + s * cot;
-    p[4] = wrap_phi(phi + h * s);
+    p[0] = p[0] + S(s * q.ca * q.sc);
+    p[1] = p[1] + S(s * q.sa * q.sc);
+    p[2] = p[2] + S(s * cot);
+    p[4] = wrap_phi(p[4] + S(h * s));
 }
 
 // Multiple-scattering process noise of a layer (PDG Highland width), added to
@@ -551,16 +555,16 @@ KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
 // (rk_path) is known: the covariance by the helix Jacobian (with ds/dp) in
 // the start point's field (kb0) over the transverse length l sin(theta0),
 // then the state becomes q.  Barrels only.
-template <typename T, typename C>
-KF_HD inline void field_transport(T p[6], C P[21], const T q[6], T l, T kb0, T r_l)
+template <typename T, typename C, typename S>
+KF_HD inline void field_transport(S p[6], C P[21], const T q[6], T l, T kb0, T r_l)
 {
-    const T sth = Tr<T>::sin_(p[5]);
+    const T sth = Tr<T>::sin_(T(p[5]));
     T pc[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) pc[k] = p[k];
+    for (int k = 0; k < 6; ++k) pc[k] = T(p[k]);
     transport(pc, P, l * sth, kb0, 0, r_l);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) p[k] = q[k];
+    for (int k = 0; k < 6; ++k) p[k] = S(q[k]);
     p[4] = wrap_phi(p[4]);
 }
 

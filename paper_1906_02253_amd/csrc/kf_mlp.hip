@@ -36,6 +36,20 @@ __global__ __launch_bounds__(256) void mlp_features_kernel(int64_t n, int64_t ld
     for (int k = 0; k < kMlpIn; ++k) feats[k * ld + i] = f[k];
 }
 
+// ------------------------------------------------------------------ targets
+__global__ __launch_bounds__(256) void mlp_targets_kernel(int64_t n, int64_t ld,
+                                                          const float* __restrict__ feats,
+                                                          const float* __restrict__ path,
+                                                          float* __restrict__ target)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float f[kMlpIn];
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k) f[k] = feats[k * ld + i];
+    target[i] = mlp_target(f, path[i]);
+}
+
 // ------------------------------------------------------------------ inference
 // Every lane of every wave takes part (rows beyond n use zero inputs).
 __global__ __launch_bounds__(256) void mlp_forward_kernel(int64_t n, int64_t ld, const float* __restrict__ feats,
@@ -299,6 +313,14 @@ hipError_t launch_mlp_step(const MlpBuffers& mb, const float* feats, const float
 hipError_t launch_mlp_publish(const MlpBuffers& mb, hipStream_t s)
 {
     mlp_publish_kernel<<<nblk(kMlpParams, 256), 256, 0, s>>>(mb);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_targets(const float* feats, const float* path, int64_t n, int64_t ld,
+                              float* target, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    mlp_targets_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, ld, feats, path, target);
     return hipGetLastError();
 }
 

@@ -167,6 +167,16 @@ __device__ inline float mlp_guess(const float f[kMlpIn], float y)
     return 100.0f * (f[5] + k * y);
 }
 
+// Training target for a propagation of transverse path length `path` [cm]
+// whose inputs are f: the output that makes mlp_guess return `path`,
+// (path - s_line) / (h s_line^2) in the inputs' units; 0 where the
+// curvature term vanishes (a straight track, or a zero target scale).
+__device__ inline float mlp_target(const float f[kMlpIn], float path)
+{
+    const float k = f[4] != 0.0f ? f[3] * f[5] * f[5] / f[4] : 0.0f;
+    return fabsf(k) > 1e-9f ? (path / 100.0f - f[5]) / k : 0.0f;
+}
+
 // Network inputs for propagating state p to layer L: rho/100, sin and cos
 // of (phi - atan2(y, x)), h * (target radius, or 100 cm for a disk) with h the
 // curvature in the field at the start point, target radius or disk z over

@@ -7,6 +7,8 @@ namespace kfmi {
 
 hipError_t launch_mlp_features(const kf_ctx* ctx, const kf_tracks* t, const int32_t* target,
                                float* feats, int prec, hipStream_t s);
+hipError_t launch_mlp_targets(const float* feats, const float* path, int64_t n, int64_t ld,
+                              float* target, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpDev& m, const float* feats, int64_t n, int64_t ld, float* out,
                               hipStream_t s);
 // scratch bytes of one training step over `batch` rows

@@ -34,14 +34,10 @@ class PairSet:
         path = torch.zeros(t.ld, dtype=torch.float32, device="cuda")
         iters = torch.zeros(t.ld, dtype=torch.int32, device="cuda")
         ctx.propagate(t, tl, path, iters, flags=prec | B.NO_MATERIAL)
-        # the network learns the correction to the straight-line path length
-        # in units of k = h s_line^2 (over 100 cm: inputs 3, 4, 5 are h r_L,
-        # r_L / 100 and s_line / 100); the guess is 100 (s_line/100 + k y)
-        f = self.feats
-        k = f[3] * f[5] * f[5] / torch.where(f[4] != 0, f[4], torch.ones_like(f[4]))
-        big = k.abs() > 1e-9
-        self.target = torch.where(big, (path / 100.0 - f[5]) / torch.where(big, k, torch.ones_like(k)),
-                                  torch.zeros_like(k)).contiguous()
+        # the correction to the straight-line path in units of h s_line^2
+        self.target = torch.zeros(t.ld, dtype=torch.float32, device="cuda")
+        ctx.mlp_targets(self.feats, path, n, self.target)
+        self.path = path
         ok = (t.status[:n] == 0).cpu().numpy()
         self.ok_rows = np.nonzero(ok)[0].astype(np.int32)
         self.plain_iters = iters[:n].cpu().numpy()

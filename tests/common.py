@@ -13,7 +13,8 @@ def wrap(a):
 
 
 def par_error(gpu_par, orc_par):
-    """Relative parameter error in units of the parity scale (1 = at tolerance)."""
+    """Relative parameter error |d| / max(|p_oracle|, floor), phi modulo 2 pi
+    (REL is the tolerance on it)."""
     d = gpu_par - orc_par
     d[:, 4] = wrap(d[:, 4])
     scale = np.maximum(np.abs(orc_par), FLOORS)
@@ -49,7 +50,8 @@ def oracle_find_events(orc, geom, events, inp, n_threads=8, **cfg_kw):
     nl = len(geom)
     out = dict(hits=np.full((ns, nl), -1, np.int64), par=np.zeros((ns, 6)), cov=np.zeros((ns, 21)),
                chi2=np.zeros(ns), ndf=np.zeros(ns, np.int64), status=np.zeros(ns, np.int64),
-               tie=np.full(ns, -1, np.int64), n_prop=0, n_upd=0)
+               tie=np.full(ns, -1, np.int64), visit=np.full((ns, nl), -1, np.int64), n_prop=0,
+               n_upd=0)
     for e, ev in enumerate(events):
         m = np.nonzero(inp["seed_event"] == e)[0]
         if m.size == 0:
@@ -57,16 +59,91 @@ def oracle_find_events(orc, geom, events, inp, n_threads=8, **cfg_kw):
         r = orc.find(cfg, ev, inp["seed_hits_local"][m], binned=True, n_threads=n_threads)
         off = inp["event_off"][e]
         out["hits"][m] = np.where(r["hits"] >= 0, r["hits"] + off, -1)
-        for k in ("par", "cov", "chi2", "ndf", "status", "tie"):
+        for k in ("par", "cov", "chi2", "ndf", "status", "tie", "visit"):
             out[k][m] = r[k]
         out["n_prop"] += r["n_prop"]
         out["n_upd"] += r["n_upd"]
     return out
 
 
+# Excused seeds (oracle ties) may be at most this fraction of all seeds.
+MAX_EXCUSED_FRAC = 1e-3
+
+
 def compare_find(g, o):
-    """Found-hit-list parity: returns (n_exact, n_excused_mismatch, bad_seed_indices)."""
+    """Found-hit-list parity: returns (n_exact, n_excused_mismatch, bad_seed_indices).
+    A differing seed is excused iff the oracle took a decision within 1e-3
+    of its threshold somewhere in that seed's walk (its tie step >= 0): a
+    close pruning decision at one step chooses between lineages whose hit
+    lists can differ at any earlier layer, so the step of the first
+    difference does not locate the decision.  Callers bound the excused count
+    (MAX_EXCUSED_FRAC)."""
     same = (g["hits"] == o["hits"]).all(axis=1)
     tie = o["tie"] >= 0
     bad = np.nonzero(~same & ~tie)[0]
     return int(same.sum()), int((~same & tie).sum()), bad
+
+
+def perturb_ulp(ev, rng):
+    """A copy of event `ev` with every hit coordinate moved by one float32
+    ulp in a random direction (the resolution the hits are given in)."""
+    import copy
+    out = copy.copy(ev)
+
+    def f(a):
+        a32 = np.asarray(a, np.float32)
+        to = np.where(rng.random(a32.shape) < 0.5, np.float32(np.inf), np.float32(-np.inf))
+        return np.nextafter(a32, to).astype(np.asarray(a).dtype)
+    out.x, out.y, out.z = f(ev.x), f(ev.y), f(ev.z)
+    return out
+
+
+def oracle_sensitivity(orc, geom, events, inp, seeds, trials=4, seed=0, **cfg_kw):
+    """Condition estimate of the oracle's result at the hits' resolution: for
+    each seed in `seeds` (global indices into inp), the largest relative
+    parameter change (par_error) of the FP64 oracle's found track over
+    `trials` runs on its event with every hit moved by one float32 ulp; inf
+    where a perturbed run finds another hit list."""
+    cfg = orc.Config(geom, **cfg_kw)
+    rng = np.random.default_rng(seed)
+    seeds = np.asarray(seeds)
+    sens = np.zeros(seeds.size)
+    for e in np.unique(inp["seed_event"][seeds]):
+        m = np.nonzero(inp["seed_event"][seeds] == e)[0]
+        sl = inp["seed_hits_local"][seeds[m]]
+        r0 = orc.find(cfg, events[e], sl, binned=True)
+        for _ in range(trials):
+            r1 = orc.find(cfg, perturb_ulp(events[e], rng), sl, binned=True)
+            d = par_error(r1["par"].copy(), r0["par"]).max(axis=1)
+            d[~(r1["hits"] == r0["hits"]).all(axis=1)] = np.inf
+            sens[m] = np.maximum(sens[m], d)
+    return sens
+
+
+def check_find_params(g, o, label, sens_fn):
+    """Parameter and chi2 parity of the seeds whose hit lists are identical:
+    |dp| < REL (par_error), |dchi2| < CHI2_REL, same ndf.  A seed above REL is
+    accepted only if it is ill-conditioned at the hits' resolution: the
+    oracle's own result moves by at least 0.1 REL when the hits move by one
+    float32 ulp (sens_fn(seed indices) -> oracle_sensitivity), and then it
+    must lie within 10 times that movement; such seeds are counted and may
+    be at most MAX_EXCUSED_FRAC of the seeds."""
+    # status bit 4 (the learned guess fell back) only informs
+    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & ((g["status"] & ~4) == 0)
+    idx = np.nonzero(same)[0]
+    err = par_error(g["par"][same], o["par"][same])
+    e1 = err.max(axis=1)
+    over = idx[e1 >= REL]
+    print(f"{label}: max rel par err {err.max(axis=0) if err.size else 0}; "
+          f"{over.size} seeds above {REL:g}")
+    if over.size:
+        sens = sens_fn(over)
+        eo = e1[e1 >= REL]
+        print(f"{label}: ill-conditioned seeds {over.tolist()[:10]}: errors {eo[:10]}, oracle "
+              f"one-ulp sensitivity {sens[:10]}")
+        assert (sens >= 0.1 * REL).all(), (label, over[sens < 0.1 * REL], eo[sens < 0.1 * REL])
+        assert (eo < 10 * sens).all(), (label, eo, sens)
+        assert over.size <= MAX_EXCUSED_FRAC * max(len(same), 1000)
+    cerr = chi2_error(g["chi2"][same], o["chi2"][same], o["ndf"][same])
+    assert cerr.size == 0 or cerr.max() < CHI2_REL, cerr.max()
+    assert np.array_equal(g["ndf"][same], o["ndf"][same])

@@ -69,7 +69,8 @@ def test_batched_and_autotune_validation_without_device(lib):
 
 def test_mlp_entry_points_validate_without_device(lib):
     for f, n in (("kf_mlp_load", 2), ("kf_mlp_get", 2), ("kf_mlp_features", 6),
-                 ("kf_mlp_forward", 6), ("kf_mlp_grad", 10), ("kf_mlp_train", 11)):
+                 ("kf_mlp_forward", 6), ("kf_mlp_grad", 10), ("kf_mlp_train", 11),
+                 ("kf_mlp_targets", 7)):
         fn = getattr(lib, f)
         fn.restype = C.c_int
         fn.argtypes = [C.c_void_p] * n

@@ -7,7 +7,7 @@ import pytest
 
 import eventgen as E
 from tests import common as CM
-from tests.test_gpu_find import K, _gpu_find, _check_parity  # noqa: F401
+from tests.test_gpu_find import K, _gpu_find, _check_parity, _sens  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -22,7 +22,7 @@ def test_batch_parity_full(K, orc, cfg2):
     geom, evs, inp = cfg2
     g = _gpu_find(K, geom, inp)
     o = CM.oracle_find_events(orc, geom, evs, inp)
-    _check_parity(g, o, "batch", outlier_frac=1e-4)
+    _check_parity(g, o, "batch", _sens(orc, geom, evs, inp))
     assert abs(int(g["counters"][0]) - o["n_prop"]) <= 0.01 * o["n_prop"]
 
 
@@ -165,4 +165,4 @@ def test_batch_steered_full(K, orc, cfg2):
     torch.cuda.synchronize()
     g = fp.results()
     o = CM.oracle_find_events(orc, geom, evs, inp, steering=plans)
-    _check_parity(g, o, "batch steered", outlier_frac=1e-4)
+    _check_parity(g, o, "batch steered", _sens(orc, geom, evs, inp, steering=plans))

@@ -54,17 +54,14 @@ def _sample(lseq, seed):
     return np.sort(np.random.default_rng(seed).choice(ok, 2000, replace=False))
 
 
-def _compare(g, o, rows, label, outlier_frac=0.0):
-    """outlier_frac: fraction of tracks allowed between 1e-4 and 1e-3 relative."""
+def _compare(g, o, rows, label):
     ok = o["status"] == 0
     assert np.array_equal(g["status"][rows], o["status"])
     err = CM.par_error(g["par"][rows][ok], o["par"][ok])
     cerr = CM.chi2_error(g["chi2"][rows][ok], o["chi2"][ok], o["ndf"][ok])
-    n_out = int((err.max(axis=1) >= CM.REL).sum())
     print(f"{label}: {ok.sum()} sampled tracks, max rel par err per parameter {err.max(axis=0)}, "
-          f"{n_out} above 1e-4, chi2 err / tol {cerr.max() / CM.CHI2_REL:.3f}")
-    assert n_out <= outlier_frac * ok.sum()
-    assert err.max() < 10 * CM.REL
+          f"chi2 err / tol {cerr.max() / CM.CHI2_REL:.3f}")
+    assert err.max() < CM.REL
     assert cerr.max() < CM.CHI2_REL
 
 
@@ -86,11 +83,4 @@ def test_material_fit_bench_set(K, orc):
     g = _gpu_fit(K, ctx, ld, hits, lseq, hidx, N)
     rows = _sample(lseq, 8)
     cfg = orc.Config(fgeom, material_map=fmat)
-    # The map's cell at a crossing is an integer that floating point decides: a
-    # crossing within ~1e-5 cm of a cell edge can fall in different cells for
-    # the FP32 and the FP64 state, and on the inner barrels neighbouring cells
-    # differ by tens of percent in thickness, which moves a 0.5 GeV track's
-    # q/pT by a few 1e-4 through the energy loss.  Such tracks (about one in
-    # 10^4 crossings' worth) are allowed up to 1e-3.
-    _compare(g, _oracle_sample(orc, cfg, ld, hits, lseq, hidx, rows), rows, "material fit set",
-             outlier_frac=1e-3)
+    _compare(g, _oracle_sample(orc, cfg, ld, hits, lseq, hidx, rows), rows, "material fit set")

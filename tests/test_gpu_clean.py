@@ -4,9 +4,10 @@ with cleaning on module-overlap events (seed fit, cleaning, finding), eager
 and as the captured graph.
 
 Bars: the keep decisions are bit-exact except seeds the oracle marks as
-within 1e-3 of a parameter threshold or 1e-4 in chi2 (none expected on the
-synthetic set, whose inputs both sides read as the same floats); hit lists
-of seeds kept on both sides follow the finding tests' rules."""
+close: a parameter within 1e-3 of its threshold (q/pT also within 1e-3 of
+|q/pT|) or two duplicates' chi2 within 2e-3 of max(chi2, 1) (none expected
+on the synthetic set, whose inputs both sides read as the same floats); hit
+lists of seeds kept on both sides follow the finding tests' rules."""
 import numpy as np
 import pytest
 

@@ -108,10 +108,13 @@ def test_map_fit_parity(K, orc, sample):
     e64 = CM.par_error(g64["par"][ok], o["par"][ok])
     print(f"fp64: max rel par err {e64.max():.2e}")
     assert e64.max() < 1e-9
-    # per layer = fused with the map too
+    # one launch per step (FP32 state through HBM) with the map too
     b = _fit(K, ctx, ev, K.PER_LAYER)
-    for k in g:
-        assert np.array_equal(g[k], b[k]), k
+    eb = CM.par_error(b["par"][ok], o["par"][ok])
+    cb = CM.chi2_error(b["chi2"][ok], o["chi2"][ok], o["ndf"][ok])
+    print(f"per layer: max rel par err {eb.max():.2e}, chi2 err / tol {cb.max() / CM.CHI2_REL:.3f}")
+    assert np.array_equal(b["status"], o["status"])
+    assert eb.max() < CM.REL and cb.max() < CM.CHI2_REL
 
 
 def test_map_removed_restores_plain(K, sample):
@@ -163,9 +166,55 @@ def test_map_find_matches_oracle(K, orc, batched):
     n_same, n_exc, bad = CM.compare_find(g, o)
     print(f"map find: {n_same}/{g['hits'].shape[0]} identical, {n_exc} excused, {bad.size} unexplained")
     assert bad.size == 0
-    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
-    err = CM.par_error(g["par"][same], o["par"][same])
-    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    assert n_exc <= CM.MAX_EXCUSED_FRAC * max(g["hits"].shape[0], 1000)
+    CM.check_find_params(g, o, "params", lambda s: CM.oracle_sensitivity(
+        orc, geom, evs, inp, s, material_map=mat))
+
+
+def _coarse_map(geom, base=0.04, n_r=50, n_z=50):
+    """A smaller grid (50 x 50 cells over the same r-z area) with the same
+    kind of thickness profile along each barrel; no barrel radius falls on a
+    cell edge (2.4 cm rows)."""
+    r_max, z_min, z_max = EM.R_MAX, EM.Z_MIN, EM.Z_MAX
+    dr, dz = r_max / n_r, (z_max - z_min) / n_z
+    zc = z_min + (np.arange(n_z) + 0.5) * dz
+    x0 = np.zeros((n_r, n_z), np.float32)
+    for L in geom:
+        ir = int(np.floor(L["r_or_z"] / dr))
+        u = np.clip(zc / max(abs(L["lo"]), abs(L["hi"])), -1, 1)
+        x0[ir, :] = base * (1 + 0.5 * u ** 2)
+    return dict(r_max=r_max, z_min=z_min, z_max=z_max, x0=x0, xi=(x0 * EM.X0_SI).astype(np.float32))
+
+
+def test_map_swap_recaptures_graph(K, orc):
+    """The captured pass takes the map's pointers and sizes by value: setting
+    another map (same cell count, other values; then a smaller grid) makes the
+    next kf_find_batched capture again, and every pass matches the FP64 oracle
+    run with the map then set."""
+    import torch
+    geom, mat, evs = EM.eloss_find_events(n_events=2, n_tracks=600, n_noise=30_000)
+    inp = E.find_inputs(evs)
+    ctx = K.Context(geom)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    mat_b = dict(mat, x0=(mat["x0"] * 1.8).astype(np.float32),
+                 xi=(mat["xi"] * 1.8).astype(np.float32))
+    prev = None
+    for m, label in ((mat, "map"), (mat_b, "same cells, other values"), (_coarse_map(geom), "smaller grid")):
+        ctx.set_material(m)
+        for rep in range(2):
+            fp.out_hits.fill_(-7)
+            fp.run_batched()
+            torch.cuda.synchronize()
+        g = fp.results()
+        o = CM.oracle_find_events(orc, geom, evs, inp, material_map=m)
+        n_same, n_exc, bad = CM.compare_find(g, o)
+        print(f"{label}: {n_same}/{g['hits'].shape[0]} identical, {n_exc} excused, {bad.size} unexplained")
+        assert bad.size == 0
+        CM.check_find_params(g, o, label, lambda s: CM.oracle_sensitivity(
+            orc, geom, evs, inp, s, material_map=m))
+        if prev is not None:
+            assert not np.array_equal(prev, g["par"])
+        prev = g["par"].copy()
 
 
 def test_map_find_learned_start_matches_oracle(K, orc):
@@ -190,9 +239,9 @@ def test_map_find_learned_start_matches_oracle(K, orc):
     print(f"learned map find: {n_same}/{g['hits'].shape[0]} identical, {n_exc} excused, "
           f"{bad.size} unexplained; guesses {g['counters'][5]}, fallbacks {g['counters'][6]}")
     assert bad.size == 0
-    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & ((g["status"] & ~K.ST_FALLBACK) == 0)
-    err = CM.par_error(g["par"][same], o["par"][same])
-    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    assert n_exc <= CM.MAX_EXCUSED_FRAC * max(g["hits"].shape[0], 1000)
+    CM.check_find_params(g, o, "params", lambda s: CM.oracle_sensitivity(
+        orc, geom, evs, inp, s, material_map=mat))
 
 
 def test_map_energy_loss_cap(K, orc):

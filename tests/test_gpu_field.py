@@ -183,13 +183,20 @@ def test_field_fit_with_material_map(K, orc, sample):
     assert CM.par_error(g64["par"][ok], o["par"][ok]).max() < 1e-9
 
 
-def test_field_fit_per_layer_equals_fused(K, sample):
+def test_field_fit_per_layer_matches_oracle(K, orc, sample):
+    """One launch per step in the parametrised field (the state through HBM
+    in FP32 between steps) against the FP64 oracle at the parity bars."""
     geom, ev = sample
     ctx = _ctx(K, geom)
-    a = _fit(K, ctx, ev)
     b = _fit(K, ctx, ev, K.PER_LAYER)
-    for k in a:
-        assert np.array_equal(a[k], b[k]), k
+    o = _oracle_fit(orc, geom, ev)
+    assert np.array_equal(b["status"], o["status"])
+    ok = o["status"] == 0
+    err = CM.par_error(b["par"][ok], o["par"][ok])
+    cerr = CM.chi2_error(b["chi2"][ok], o["chi2"][ok], o["ndf"][ok])
+    print(f"field per layer: max rel par err {err.max():.2e}, chi2 err / tol "
+          f"{cerr.max() / CM.CHI2_REL:.3f}")
+    assert err.max() < CM.REL and cerr.max() < CM.CHI2_REL
 
 
 def test_field_uniform_limit_matches_helix(K, sample):
@@ -246,9 +253,9 @@ def test_field_find_matches_oracle(K, orc, batched):
           f"counters {g['counters'][:5].tolist()}")
     assert bad.size == 0
     assert n_same > 0.98 * ns
-    same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
-    err = CM.par_error(g["par"][same], o["par"][same])
-    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    assert n_exc <= CM.MAX_EXCUSED_FRAC * max(g["hits"].shape[0], 1000)
+    CM.check_find_params(g, o, "params", lambda s: CM.oracle_sensitivity(
+        orc, geom, evs, inp, s, field_z0=Z0, field_step=STEP))
     # most tracks are found with all their crossings
     nh_true = np.concatenate([(e.seq_hit[e.n_track_hits() >= 3] >= 0).sum(axis=1) for e in evs])
     nh_found = (g["hits"] >= 0).sum(axis=1)
@@ -277,8 +284,9 @@ def test_field_find_bench_batch(K, orc):
     assert bad.size == 0
     same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
     assert same.mean() > 0.98
-    err = CM.par_error(g["par"][same], o["par"][same])
-    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    assert n_exc <= CM.MAX_EXCUSED_FRAC * max(ns, 1000)
+    CM.check_find_params(g, o, "field bench batch", lambda s: CM.oracle_sensitivity(
+        orc, geom, evs, inp, s, field_z0=Z0, field_step=STEP))
     assert abs(int(g["counters"][0]) - o["n_prop"]) <= 0.01 * o["n_prop"]
 
 
@@ -300,8 +308,9 @@ def test_field_find_uniform_limit_matches_oracle(K, orc):
     assert bad.size == 0
     same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
     assert same.mean() > 0.98
-    err = CM.par_error(g["par"][same], o["par"][same])
-    assert (err.max(axis=1) < CM.REL).mean() > 0.999
+    assert n_exc <= CM.MAX_EXCUSED_FRAC * max(g["hits"].shape[0], 1000)
+    CM.check_find_params(g, o, "field uniform limit", lambda s: CM.oracle_sensitivity(
+        orc, geom, evs, inp, s))
 
 
 def test_field_find_with_material_map(K, orc):
@@ -331,8 +340,9 @@ def test_field_find_with_material_map(K, orc):
         assert bad.size == 0
         same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
         assert same.mean() > 0.98
-        err = CM.par_error(g["par"][same], o["par"][same])
-        assert (err.max(axis=1) < CM.REL).mean() > 0.999
+        assert n_exc <= CM.MAX_EXCUSED_FRAC * max(g["hits"].shape[0], 1000)
+        CM.check_find_params(g, o, "field + map", lambda s: CM.oracle_sensitivity(
+            orc, geom, evs, inp, s, field_z0=Z0, field_step=STEP, material_map=mat))
 
 
 def test_field_find_refusals(K):

@@ -95,19 +95,28 @@ def test_fit_fp64_equals_oracle(K, orc):
     g = _gpu_fit(K, geom, ev, flags=K.PREC_FP64)
     o = _oracle_fit(orc, geom, ev)
     ok = o["status"] == 0
-    err = CM.par_error(g["par"][ok], o["par"][ok]) * CM.REL
+    err = CM.par_error(g["par"][ok], o["par"][ok])
     print("fp64 max rel err:", err.max())
     assert err.max() < 1e-9
     assert np.abs(g["chi2"][ok] - o["chi2"][ok]).max() < 1e-7 * max(1, o["chi2"].max())
 
 
-def test_fit_per_layer_equals_fused(K):
-    import torch
-    geom, ev = E.fit_sample(n_tracks=777, seed=4)
-    a = _gpu_fit(K, geom, ev)
-    b = _gpu_fit(K, geom, ev, flags=K.PER_LAYER)
-    for k in a:
-        assert np.array_equal(a[k], b[k]), k
+def test_fit_per_layer_matches_oracle(K, orc):
+    """One launch per step (the state through HBM in FP32 between steps)
+    against the FP64 oracle at the parity bars, on the fit workload and on the
+    precision workload's tracks (its first 20,000); the fused fit keeps the
+    state in registers between steps, so the two differ by storage rounding."""
+    for geom, ev in (E.fit_sample(n_tracks=777, seed=4), E.precision_sample(20_000)):
+        a = _gpu_fit(K, geom, ev, flags=K.PER_LAYER)
+        o = _oracle_fit(orc, geom, ev)
+        assert np.array_equal(a["status"], o["status"])
+        assert np.array_equal(a["ndf"], o["ndf"])
+        ok = o["status"] == 0
+        err = CM.par_error(a["par"][ok], o["par"][ok])
+        cerr = CM.chi2_error(a["chi2"][ok], o["chi2"][ok], o["ndf"][ok])
+        print(f"per layer: max rel par err {err.max(axis=0)}, chi2 err / tol "
+              f"{cerr.max() / CM.CHI2_REL:.3f}")
+        assert err.max() < CM.REL and cerr.max() < CM.CHI2_REL
 
 
 def test_fit_ld_padding_and_empty(K):
@@ -162,9 +171,10 @@ def test_propagate_parity(K, orc):
         rows.append((ev.truth_out[t, k], ev.seq_layer[t, k + 1]))
     n = len(rows)
     ld = CM.ld_of(n)
-    par = np.array([r[0] for r in rows])
+    # the oracle starts from the same FP32-stored inputs the kernel reads
+    par = np.array([r[0] for r in rows]).astype(np.float32).astype(np.float64)
     P = np.diag([1e-4, 1e-4, 2e-3, 1e-4, 1e-5, 1e-5])
-    cov = np.tile(orc.pack(P), (n, 1))
+    cov = np.tile(orc.pack(P), (n, 1)).astype(np.float32).astype(np.float64)
     tgt = np.array([r[1] for r in rows], np.int32)
     t = K.Tracks.from_numpy(par, cov, ld=ld)
     target = torch.full((ld,), -1, dtype=torch.int32, device="cuda")
@@ -183,7 +193,8 @@ def test_propagate_parity(K, orc):
         assert st == 0
     assert (g["status"] == 0).all()
     err = CM.par_error(g["par"], op)
-    assert err.max() < 0.1, err.max(axis=0)
+    print("propagate: max rel par err", err.max(axis=0))
+    assert err.max() < CM.REL, err.max(axis=0)
     assert np.abs(plen.cpu().numpy()[:n] - os_).max() < 1e-4 * max(1, os_.max())
     for idx in (0, 6, 11, 15, 18, 20):
         assert np.abs(g["cov"][:, idx] / oc[:, idx] - 1).max() < 1e-3, idx

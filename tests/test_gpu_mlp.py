@@ -173,6 +173,40 @@ def test_first_adam_step(K):
     assert np.allclose(w1[sig], want[sig], rtol=0, atol=2e-7 + 1e-6 * np.abs(want[sig]))
 
 
+def test_targets_match_oracle(K, orc):
+    """Training targets made by the library (kf_mlp_features, the plain
+    kf_propagate, kf_mlp_targets) against the FP64 oracle's: its features,
+    its propagation's path length and its target.  The path the target
+    encodes (s_line + h s_line^2 y) agrees to 2e-4 cm everywhere, and the
+    target itself to 1e-3 relative where the correction exceeds 0.05 cm."""
+    geom, states, tl = E.propagation_pairs(n_pairs=20_000, seed=14, n_tracks=5_000)
+    ctx = K.Context(geom)
+    ps = K.learned.PairSet(ctx, states, tl)
+    n = ps.n
+    tg = ps.target[:n].cpu().numpy().astype(np.float64)
+    cfg = orc.Config(geom)
+    kinds = np.array([geom[l]["kind"] for l in tl])
+    tgt = np.array([geom[l]["r_or_z"] for l in tl])
+    f = M.features(states, kinds, tgt)
+    path = np.zeros(n)
+    ok = np.zeros(n, bool)
+    for i in range(n):
+        st, _, _, s, _ = orc.propagate(cfg, int(tl[i]), states[i], np.zeros(21), noise=False)
+        ok[i] = st == 0
+        path[i] = s
+    assert np.array_equal(ok, np.isin(np.arange(n), ps.ok_rows))
+    to = M.target(f, path)
+    k = np.where(f[:, 4] != 0, f[:, 3] * f[:, 5] ** 2 / np.where(f[:, 4] != 0, f[:, 4], 1), 0)
+    dpath = 100.0 * np.abs(k * (tg - to))
+    corr = np.abs(path - 100.0 * f[:, 5])
+    big = ok & (corr > 0.05)
+    rel = np.abs(tg - to)[big] / np.abs(to[big])
+    print(f"targets: {ok.sum()} pairs, max path difference {dpath[ok].max():.2e} cm, "
+          f"{big.sum()} with corrections > 0.05 cm, max rel target difference {rel.max():.2e}")
+    assert dpath[ok].max() < 2e-4
+    assert big.sum() > 1000 and rel.max() < 1e-3
+
+
 @pytest.fixture(scope="module")
 def trained(K):
     """Network trained on the device on 1e6 pairs (precision workload's

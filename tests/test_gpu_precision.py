@@ -1,14 +1,16 @@
 """Precision variants on the ill-conditioned fit workload: 200,000 tracks
 mixing 0.3 GeV loopers and 100 GeV stiff tracks, hit sigma_u log-uniform in
-[0.002, 0.01] cm, sigma_v = 5 sigma_u, no material.  Each GPU variant (all
-FP32; mixed = FP32 state/transport with FP64 covariance and update; all
-FP64) is compared with the FP64 oracle; max and RMS relative error per
-parameter are printed, and the bars are:
-  FP64   max relative error < 1e-9 (same algorithm, rounding order only)
-  mixed  max relative error < 2e-4 and RMS < 2e-5 per parameter, chi2 < 1e-3
-         (FP32 state transport: on 100 GeV tracks with 0.002 cm hits the
-         curvature tail reaches ~1.2e-4 relative, about 1% of its sigma)
-  FP32   reported; must stay finite for >= 99% of tracks
+[0.002, 0.01] cm, sigma_v = 5 sigma_u, no material.  Each GPU variant is
+compared with the FP64 oracle; max and RMS relative error per parameter are
+printed.  Variants and bars:
+  FP64   everything FP64: max relative error < 1e-9 (rounding order only)
+  mixed  FP32 storage, FP32 surface solve / helix / Jacobian, FP64 F P F^T
+         and update with the state held in FP64 between its loads and
+         stores: the parity bars, max < 1e-4 per parameter and chi2 < 1e-3
+         (fused and one launch per step)
+  FP32   everything FP32: measured, not held to the parity bar (F P F^T in
+         FP32 loses the small variances of stiff tracks); bounded at 2e-3
+         per parameter and 1e-2 on chi2 so that a regression shows
 """
 import numpy as np
 import pytest
@@ -46,12 +48,13 @@ def test_precision_fp64(K, cfg3):
     assert err.max() < 1e-9 and cerr.max() < 1e-9
 
 
-def test_precision_mixed(K, cfg3):
+@pytest.mark.parametrize("per_layer", [False, True])
+def test_precision_mixed(K, cfg3, per_layer):
     geom, ev, o = cfg3
-    g = _gpu_fit(K, geom, ev, flags=K.PREC_MIXED)
-    ok, err, cerr = _report("mixed", g, o)
+    g = _gpu_fit(K, geom, ev, flags=K.PREC_MIXED | (K.PER_LAYER if per_layer else 0))
+    ok, err, cerr = _report("mixed per layer" if per_layer else "mixed", g, o)
     assert np.array_equal(g["status"], o["status"])
-    assert err.max() < 2 * CM.REL and cerr.max() < CM.CHI2_REL
+    assert err.max() < CM.REL and cerr.max() < CM.CHI2_REL
     assert np.sqrt((err ** 2).mean(axis=0)).max() < 0.2 * CM.REL
 
 
@@ -60,3 +63,4 @@ def test_precision_fp32(K, cfg3):
     g = _gpu_fit(K, geom, ev, flags=K.PREC_FP32)
     ok, err, cerr = _report("fp32", g, o)
     assert ok.mean() > 0.99
+    assert err.max() < 2e-3 and cerr.max() < 1e-2

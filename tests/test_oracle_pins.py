@@ -496,6 +496,11 @@ def test_noise_free_finds_true_hits(orc):
         nh = ev.n_track_hits()[t]
         want[ev.seq_layer[t, :nh]] = ev.seq_hit[t, :nh]
         assert np.array_equal(r["hits"][k], want), (t, r["hits"][k], want)
+        # the walk reaches the layers after the three seed layers one per
+        # step, in crossing order (ten barrels: radius order)
+        walked = ev.seq_layer[t, 3:nh]
+        assert np.array_equal(r["visit"][k][walked], np.arange(walked.size)), r["visit"][k]
+        assert (r["visit"][k][ev.seq_layer[t, :3]] == -1).all()
 
 
 def _exhaustive_best(orc, cfg, geom, ev, seed_hits):
