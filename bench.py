@@ -14,10 +14,13 @@ propagation of a track or candidate to a surface together with its
 update(s): the three seed-fit steps per seed plus the finding kernel's
 propagations (counted by the kernel itself).
 
-Prints ONE JSON line: metric, value, the roofline of the dominant kernel
-(the finding kernel, arithmetic-bound: algorithmic flops from the operation
-counts of its own code times its event counters, over its HIP-event time),
-the FP64 oracle timed on the host cores, and the fit kernels' figures.
+Prints ONE JSON line: metric, value, the HBM roofline of the dominant kernel
+(the finding kernel: algorithmic bytes of the per-layer state-through-memory
+model, 250 B per propagation plus 108 B per extra child kept, times its
+event counters, over its HIP-event time; its arithmetic rate beside), the
+FP64 oracle timed on the host cores (all of them and one thread), the
+finding pass over 512 events (a working set far above the 256 MB Infinity
+Cache), and the fit kernels' figures (the per-layer step against 244 B).
 """
 import argparse
 import json
@@ -31,14 +34,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VECTOR_PEAK_TFLOPS = 78.6      # MI355X vector FP64, and FP32 without packed math
+FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32 (packed)
+VECTOR_PEAK_TFLOPS = 78.6      # MI355X vector FP64, and FP32 without packed math (unpacked)
 
-# Per-layer fit design (state crosses HBM between layers): par 24 (float) and
-# cov 168 (double) read and written, hit x,y,z,su,sv 20, layer and hit index
-# 8, chi2 / ndf / status read and written 24.  With FP32 storage the
-# covariance is 84 bytes.
-PER_LAYER_BYTES_PER_STEP = 2 * (24 + 168) + 20 + 8 + 24
-PER_LAYER_BYTES_PER_STEP_FP32 = 2 * (24 + 84) + 20 + 8 + 24
+# Algorithmic bytes of one per-layer fit step (the state crosses HBM between
+# layers, FP32 storage): state 24 + covariance 84 read and written, hit
+# x, y, z, su, sv 20, chi2 read and written 8.
+FIT_BYTES_PER_STEP = 2 * (24 + 84) + 20 + 8
+# What the per-layer kernel actually moves per step besides: the hit index
+# and layer index (4 + 4) and ndf and status read and written (16).
+PER_LAYER_BYTES_PER_STEP = FIT_BYTES_PER_STEP + 8 + 16
+# Algorithmic bytes of one finding step, the same per-layer model: the
+# parent's state and covariance read (108), hit index, hit count and chi2
+# (12), the layer's hits amortised over its candidates (~24 at the finding
+# workloads' occupancy) and one child written (108): ~250 B, plus 108 B for
+# every further child kept.
+FIND_BYTES_PER_STEP = 250.0
+FIND_BYTES_PER_EXTRA_CHILD = 108.0
 
 
 def parse():
@@ -53,6 +65,7 @@ def parse():
     ap.add_argument("--no-clean", action="store_true")
     ap.add_argument("--no-material", action="store_true")
     ap.add_argument("--no-field-find", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--fit-tracks", type=int, default=4_000_000)
     ap.add_argument("--field-tracks", type=int, default=1_000_000)
     return ap.parse_args()
@@ -81,6 +94,27 @@ def measured_traffic(kernel):
         return None
     k = d.get("kernels", {}).get(kernel)
     return k["hbm_bytes"] if k else None
+
+
+def find_roofline(cnt, kernel_ms, oc, traffic=None, kernel=None):
+    """HBM roofline of the finding kernel from its event counters
+    (propagations cnt[0], children kept cnt[7]) and its mean kernel time;
+    its arithmetic rate beside."""
+    props, kept = float(cnt[0]), float(cnt[7])
+    nbytes = FIND_BYTES_PER_STEP * props + FIND_BYTES_PER_EXTRA_CHILD * (kept - props)
+    gbs = nbytes / (kernel_ms * 1e-3) / 1e9
+    flops = find_flops(cnt, oc)
+    tf = flops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "kernel_ms": kernel_ms, "bytes_per_launch": nbytes,
+            "bytes_model": "250 B per propagation + 108 B per child kept beyond one",
+            "children_per_propagation": kept / max(props, 1.0),
+            "alu": {"achieved_tflops": tf, "peak_fp32_packed_tflops": FP32_PEAK_TFLOPS,
+                    "frac": tf / FP32_PEAK_TFLOPS,
+                    "peak_unpacked_tflops": VECTOR_PEAK_TFLOPS,
+                    "frac_unpacked": tf / VECTOR_PEAK_TFLOPS, "flops_per_launch": flops},
+            "events_per_launch": cnt.tolist()}
 
 
 def find_flops(cnt, oc):
@@ -171,9 +205,10 @@ def run_fit(K, torch, n, w=None, reps=5):
                 ev[r][1].record(stream)
         torch.cuda.synchronize()
         out[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    gbs = n_steps * PER_LAYER_BYTES_PER_STEP / (out["per_layer"] * 1e-3) / 1e9
-    gbs32 = n_steps * PER_LAYER_BYTES_PER_STEP_FP32 / (out["per_layer_fp32"] * 1e-3) / 1e9
-    return {"workload": f"fit of {n} tracks, precision-workload mix, 10 barrel layers, mixed precision",
+    gbs = n_steps * FIT_BYTES_PER_STEP / (out["per_layer"] * 1e-3) / 1e9
+    gbs32 = n_steps * FIT_BYTES_PER_STEP / (out["per_layer_fp32"] * 1e-3) / 1e9
+    return {"workload": f"fit of {n} tracks, precision-workload mix, 10 barrel layers, mixed "
+                        f"precision (FP32 storage)",
             "kf_steps": n_steps,
             "fused_kernel_ms": out["fused"], "fused_steps_per_s": n_steps / (out["fused"] * 1e-3),
             "fused_learned_kernel_ms": out.get("fused_learned"),
@@ -183,12 +218,13 @@ def run_fit(K, torch, n, w=None, reps=5):
             "per_layer_steps_per_s": n_steps / (out["per_layer"] * 1e-3),
             "per_layer_hbm": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": gbs / HBM_PEAK_GBS,
-                              "bytes_per_step": PER_LAYER_BYTES_PER_STEP},
+                              "bytes_per_step": FIT_BYTES_PER_STEP,
+                              "bytes_moved_per_step": PER_LAYER_BYTES_PER_STEP},
             "per_layer_fp32_ms": out["per_layer_fp32"],
             "per_layer_fp32_steps_per_s": n_steps / (out["per_layer_fp32"] * 1e-3),
             "per_layer_fp32_hbm": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS,
                                    "unit": "GB/s", "frac": gbs32 / HBM_PEAK_GBS,
-                                   "bytes_per_step": PER_LAYER_BYTES_PER_STEP_FP32}}
+                                   "bytes_per_step": FIT_BYTES_PER_STEP}}
 
 
 FIELD_Z0, FIELD_STEP = 300.0, 2.0
@@ -429,6 +465,37 @@ def run_field_find(K, torch, steps, warmup, width, largest_first):
     return out
 
 
+LARGE_COPIES = 8
+
+
+def run_large_find(K, torch, oc, geom, evs, steps, warmup, width, largest_first):
+    """The batched finding pass over the batch replicated LARGE_COPIES times
+    at distinct addresses (512 events, a working set of several GB, far above
+    the 256 MB Infinity Cache): ms per pass, KF steps/s, the phases and the
+    finding kernel's HBM roofline."""
+    import eventgen as E
+    from paper_1906_02253_amd import pipeline
+    big = list(evs) * LARGE_COPIES
+    inp = E.find_inputs(big)
+    n_seeds = int(inp["seed_hits"].shape[0])
+    n_hits = int(inp["x"].shape[0])
+    ctx = K.Context(geom)
+    ctx.set_find_config(width, largest_first)
+    fp = pipeline.FindProblem(ctx, inp)
+    ms, ph, cnt = timed_pass(torch, ctx, fp, 0, steps, warmup)
+    kf = 3 * n_seeds + float(cnt[0])
+    out = {"workload": f"batched finding over {len(big)} events: the 64-event batch replicated "
+                       f"{LARGE_COPIES} times at distinct addresses",
+           "n_events": len(big), "n_seeds": n_seeds, "n_hits": n_hits,
+           "hit_input_bytes": n_hits * 24, "binned_hit_bytes": n_hits * 32, "width": width,
+           "ms_per_pass": ms, "steps_per_s": kf / (ms * 1e-3), "kf_steps_per_pass": kf,
+           "phases_ms": {"seed_and_seed_fit": ph[0], "binning": ph[1], "seed_order": ph[2],
+                         "find_kernel": ph[3]},
+           "roofline": find_roofline(cnt, ph[3], oc, None, FIND_KERNEL)}
+    del fp, ctx
+    return out
+
+
 def run_clean_pass(K, torch, steps, warmup, width, largest_first):
     """The batched pass on the 64-event batch with module-overlap duplicate
     seeds (overlap hits at 10% per barrel and 30% per disk crossing on each
@@ -556,6 +623,45 @@ def oracle_find_all(oracle, geom, evs, inp, threads):
     return n_prop
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu), or '' where it cannot be read."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return ""
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return ""
+
+
+def cpu_baseline(geom, evs, inp, single_events=16):
+    """The FP64 oracle's seed fit and finding timed on the host: over the
+    whole batch on all host threads (capped at 16, the host share one GPU
+    gets), and over its first `single_events` events on one thread."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    n_seeds = int(inp["seed_hits"].shape[0])
+    c0 = time.perf_counter()
+    n_prop = oracle_find_all(oracle, geom, evs, inp, threads)
+    cdt = time.perf_counter() - c0
+    csteps = 3 * n_seeds + n_prop
+    sub = evs[:single_events]
+    n_sub = int((inp["seed_event"] < single_events).sum())
+    c1 = time.perf_counter()
+    n_prop1 = oracle_find_all(oracle, geom, sub, inp, 1)
+    c1dt = time.perf_counter() - c1
+    s1 = 3 * n_sub + n_prop1
+    return {"value": csteps / cdt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle seed fit + finding over the same 64-event batch on {threads} "
+                      f"threads: {csteps} KF steps in {cdt:.2f} s",
+            "single_thread": {"value": s1 / c1dt, "unit": "steps/s", "cores": 1,
+                              "sample": f"the batch's first {single_events} events on one "
+                                        f"thread: {s1} KF steps in {c1dt:.2f} s"},
+            "host_threads": os.cpu_count(), "cpu_model": cpu_model()}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -599,8 +705,7 @@ def main():
         torch, ctx, fp, 0, args.steps, args.warmup)
     kf_steps = 3 * n_seeds + cnt[0]
     value = kf_steps / (ms_per_step * 1e-3)
-    flops = find_flops(cnt, oc)
-    tflops = flops / (ms_kernel * 1e-3) / 1e12
+    roof = find_roofline(cnt, ms_kernel, oc, measured_traffic(FIND_KERNEL), FIND_KERNEL)
     print(f"# {ms_per_step:.3f} ms/step, find kernel {ms_kernel:.3f} ms, seed+fit {ms_seed:.3f} ms, "
           f"binning {ms_bin:.3f} ms, seed order {ms_sort:.3f} ms, {kf_steps:.0f} KF steps/pass",
           file=sys.stderr, flush=True)
@@ -616,7 +721,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32 storage, f32+f64 arithmetic",
         "data": "synthetic",
         "config": {"workload": "batched finding: 64 events, N ~ Poisson(U(200,4000)), 60 noise "
                                "hits/track, 10 barrel layers + 2x7 disks, |eta|<2.5, 0.02 X0, "
@@ -626,17 +731,22 @@ def main():
                    "tile_order": "largest events first" if largest_first else "event, eta, phi",
                    "autotune_ms": {f"{w}/{int(lf)}": ms for (w, lf), ms in sorted(tune.items())}
                    if tune else None,
-                   "launch": "hipGraph replay (kf_find_batched)", "precision": "mixed",
+                   "launch": "hipGraph replay (kf_find_batched)",
+                   "precision": "mixed (FP32 storage, FP64 covariance arithmetic and update)",
                    "init": "plain"},
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic(FIND_KERNEL),
-                     "kernel": FIND_KERNEL, "kernel_ms": ms_kernel,
-                     "flops_per_launch": flops, "events_per_launch": cnt.tolist()},
+        "roofline": roof,
         "phases_ms": {"seed_and_seed_fit": ms_seed, "binning": ms_bin, "seed_order": ms_sort,
                       "find_kernel": ms_kernel},
         "copy_probe": probe,
     }
+
+    if not args.no_large:
+        result["find_large"] = run_large_find(K, torch, oc, geom, evs, args.steps, args.warmup,
+                                              width, largest_first)
+        fl = result["find_large"]
+        print(f"# {fl['n_events']} events: {fl['ms_per_pass']:.3f} ms/pass "
+              f"({fl['steps_per_s']:.3e} steps/s), find kernel {fl['phases_ms']['find_kernel']:.3f} "
+              f"ms, {fl['roofline']['achieved']:.0f} GB/s by the model", file=sys.stderr, flush=True)
 
     # learned start: train on the device, then the same timed pass
     w, rep = train_guess(K, torch, E)
@@ -720,16 +830,11 @@ def main():
               f"-> {mm['fit_map']['steps_per_s']:.3e} steps/s", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
-        import oracle
-        threads = min(os.cpu_count() or 1, 16)
-        c0 = time.perf_counter()
-        n_prop = oracle_find_all(oracle, geom, evs, inp, threads)
-        cdt = time.perf_counter() - c0
-        csteps = 3 * n_seeds + n_prop
-        result["cpu_baseline"] = {"value": csteps / cdt, "unit": "steps/s", "cores": threads,
-                                  "kind": "oracle",
-                                  "sample": f"FP64 oracle finding (seed fit + find) over the same "
-                                            f"64-event batch: {csteps} KF steps in {cdt:.2f} s"}
+        result["cpu_baseline"] = cpu_baseline(geom, evs, inp)
+        cb = result["cpu_baseline"]
+        print(f"# cpu oracle: {cb['value']:.3e} steps/s on {cb['cores']} threads, "
+              f"{cb['single_thread']['value']:.3e} on one ({cb['cpu_model']})", file=sys.stderr,
+              flush=True)
     print(json.dumps(result))
 
 

@@ -279,9 +279,10 @@ int kf_remove_duplicates(kf_ctx* ctx, const kf_hits* hits, kf_tracks* tracks,
  *               layer (global hit index), -1 = none
  *   out         n_seeds tracks, out->n == seeds->n: best candidate's state at its
  *               last surface, chi2, ndf = 2*hits - 5, status
- *   counters    optional [7] uint64, incremented by (propagations, updates,
+ *   counters    optional [8] uint64, incremented by (propagations, updates,
  *               chi2 tests, Newton evaluations, disk-crossing tests, learned
- *               guesses evaluated, learned guesses that fell back)
+ *               guesses evaluated, learned guesses that fell back, candidates
+ *               kept from the children of propagated parents)
  * Per layer a candidate is propagated to its next surface (the first reached
  * of the next barrel outward and the next disk ahead; in the parametrised
  * field the next barrel outward, by the Runge-Kutta radius solve), every hit in the chi2

@@ -61,8 +61,8 @@ class KfTrainCfg(C.Structure):
 
 
 MLP_NPARAM, MLP_NIN = 4801, 8
-N_COUNTERS = 7      # propagations, updates, chi2 tests, Newton evaluations, disk tests,
-                    # learned guesses, learned guesses that fell back
+N_COUNTERS = 8      # propagations, updates, chi2 tests, Newton evaluations, disk tests,
+                    # learned guesses, learned guesses that fell back, children kept
 
 
 def _load():
@@ -311,7 +311,7 @@ class Context:
              flags=0):
         """event_off: int32 [n_events+1]; seed_event: int32 [n_seeds];
         seed_hits: int32 [3, seeds.ld]; out_hits: int32 [n_seeds, n_layers];
-        counters: optional int64 [7], accumulated."""
+        counters: optional int64 [8], accumulated."""
         n_events = int(event_off.shape[0]) - 1
         self._check(lib.kf_find(self.h, C.byref(hits.c()), _ptr(event_off), n_events,
                                 C.byref(seeds.c()), _ptr(seed_event), _ptr(seed_hits),

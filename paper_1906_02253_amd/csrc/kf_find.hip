@@ -578,7 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     const int lbase = t - slot;             // lane of this seed's slot 0
     const T kb = T(kKappa) * T(a.prm.bz);
     const float cut = float(a.prm.chi2_cut);
-    unsigned n_prop = 0, n_upd = 0, n_chi2 = 0;   // per lane: far below 2^32
+    unsigned n_prop = 0, n_upd = 0, n_chi2 = 0, n_kept = 0;   // per lane: far below 2^32
     int n_newton = 0, n_disk = 0, n_guess = 0, n_fallback = 0;
     int2* bp_base = a.bp + (size_t)blockIdx.x * nl * S * kMaxCands;
 
@@ -1100,6 +1100,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     if constexpr (STEER) pos = (m3 >> 16) & 0xFF;
                     const int nk = sh.nchild[tj];
                     if (ppl >= 0) {
+                        ++n_kept;
                         if (c < nk) {
                             const int bi = sh.cbidx[c * W + tj];
                             const BinnedHit hh = a.bh[bi];
@@ -1171,7 +1172,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         unsigned long long c[kFindCounters] = {(unsigned long long)n_prop, (unsigned long long)n_upd,
                                                (unsigned long long)n_chi2, (unsigned long long)n_newton,
                                                (unsigned long long)n_disk, (unsigned long long)n_guess,
-                                               (unsigned long long)n_fallback};
+                                               (unsigned long long)n_fallback, (unsigned long long)n_kept};
 #pragma unroll
         for (int q = 0; q < kFindCounters; ++q) {
             for (int o = 32; o > 0; o >>= 1) c[q] += __shfl_xor(c[q], o);

@@ -7,7 +7,7 @@ namespace kfmi {
 
 constexpr int kMaxCands = 8;    // candidate slots per seed the kernel is built for
 constexpr int kMaxLayerBins = 16384;   // nbin_phi * nbin_2 of one layer (LDS histogram)
-constexpr int kFindCounters = 7;       // event counters of a finding call
+constexpr int kFindCounters = 8;       // event counters of a finding call
 
 // Seeds per workgroup of the finding kernel: max_cands lanes per seed, and a
 // seed never straddles two waves (its candidates exchange state by shuffles).
@@ -61,7 +61,8 @@ struct FindArgs {
     int2* bp;                     // per workgroup: [n_layers][S][kMaxCands] back-pointers
     int32_t* tile_counter;
     unsigned long long* counters; // optional [kFindCounters]: propagations, updates, chi2 tests,
-                                  // Newton evaluations, disk tests, learned guesses, fallbacks
+                                  // Newton evaluations, disk tests, learned guesses, fallbacks,
+                                  // children kept from propagated parents
     // geometry and parameters
     const kf_layer* layers;
     int n_layers;

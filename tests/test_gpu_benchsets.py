@@ -84,3 +84,44 @@ def test_material_fit_bench_set(K, orc):
     rows = _sample(lseq, 8)
     cfg = orc.Config(fgeom, material_map=fmat)
     _compare(g, _oracle_sample(orc, cfg, ld, hits, lseq, hidx, rows), rows, "material fit set")
+
+
+def test_large_find_set(K, orc):
+    """The finding pass over the bench's 512-event set (the 64-event batch
+    replicated eight times at distinct addresses), replayed as the bench
+    replays it: every copy gives the first copy's results bit for bit, and
+    2,000 sampled seeds of the first copy match the FP64 oracle (hit lists
+    under the finding tests' tie rule, parameters at the parity bars)."""
+    import torch
+    import eventgen as E
+    from paper_1906_02253_amd import pipeline
+    geom, evs = E.batch_events()
+    big = list(evs) * bench.LARGE_COPIES
+    inp = E.find_inputs(big)
+    ctx = K.Context(geom)
+    fp = pipeline.FindProblem(ctx, inp)
+    fp.run_batched()
+    fp.run_batched()
+    torch.cuda.synchronize()
+    g = fp.results()
+    ns1 = int((inp["seed_event"] < len(evs)).sum())
+    assert g["hits"].shape[0] == bench.LARGE_COPIES * ns1
+    for c in range(1, bench.LARGE_COPIES):
+        sl = slice(c * ns1, (c + 1) * ns1)
+        off = int(inp["event_off"][c * len(evs)])
+        gh = np.where(g["hits"][sl] >= 0, g["hits"][sl] - off, -1)
+        assert np.array_equal(gh, g["hits"][:ns1]), c
+        for k in ("par", "cov", "chi2", "ndf", "status"):
+            assert np.array_equal(g[k][sl], g[k][:ns1]), (c, k)
+    rows = np.sort(np.random.default_rng(9).choice(ns1, 2000, replace=False))
+    inp1 = E.find_inputs(evs)
+    sub = {k: (v[rows] if k in ("seed_hits", "seed_hits_local", "seed_event", "seed_track",
+                                "seed_layers") and hasattr(v, "shape") and v.shape[0] == ns1
+               else v) for k, v in inp1.items()}
+    o = CM.oracle_find_events(orc, geom, evs, sub, n_threads=16)
+    gs = {k: g[k][rows] for k in ("hits", "par", "cov", "chi2", "ndf", "status")}
+    n_same, n_exc, bad = CM.compare_find(gs, o)
+    print(f"512-event set: copies identical; sampled {n_same}/2000 identical, {n_exc} excused")
+    assert bad.size == 0 and n_exc <= 2
+    CM.check_find_params(gs, o, "512-event set", lambda s: CM.oracle_sensitivity(
+        orc, geom, evs, sub, s))
