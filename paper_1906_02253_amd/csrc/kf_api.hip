@@ -192,7 +192,7 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.seed_event = seed_event;
     a.n_events = n_events;
     a.seed_hits = seed_hits;
-    a.order = pl.order;
+    a.order = pl.tile_order;
     a.out_hits = out_hits;
     a.old = out->ld;
     a.opar = (float*)out->par;
@@ -243,6 +243,7 @@ hipError_t phase_order(const kf_ctx* ctx, const kfmi::FindLaunch& L, hipStream_t
     if (e == hipSuccess && L.clean)
         e = kfmi::launch_clean(L.pl, L.seeds, L.seed_event, (int)L.n_events, L.seed_hits,
                                L.hits->n, ctx->params, s);
+    if (e == hipSuccess) e = kfmi::launch_cost_order(L.pl, L.seeds, L.a.n_tiles, L.a.seeds_per_tile, s);
     if (e == hipSuccess) e = kfmi::launch_fill(L.pl.tile_counter, 64, 0, s);
     return e;
 }

@@ -417,6 +417,80 @@ __global__ __launch_bounds__(256) void cell_sort_kernel(int64_t n_cells, const i
     }
 }
 
+// Tiles of seeds of like cost.  A tile runs as long as its slowest seed,
+// and low-pT seeds (loopers, which curl back through the detector with ever
+// wider windows) walk longest, so inside each tile queue's contiguous range
+// of the processing order the seeds are partitioned, stably, by a cost class
+// of |q/pT|, costliest first: fewer tiles wait on one looper, and the long
+// tiles start first instead of ending the pass.  (Sparser tiles for the
+// loopers, a few seeds per wave, cost more than they saved.)
+constexpr int kCostClasses = 3;
+__device__ inline int cost_class(float c)
+{
+    const float a = fabsf(c);
+    return a > 1.0f / 0.6f ? 0 : (a > 1.0f ? 1 : 2);   // pT < 0.6, < 1 GeV, the rest
+}
+
+// One workgroup of 1024 lanes per queue range [q chunk, (q + 1) chunk) of
+// the cell order; chunk is a whole number of tiles.
+__global__ __launch_bounds__(1024) void cost_order_kernel(int64_t n, int64_t ld,
+                                                          const float* __restrict__ par,
+                                                          const int32_t* __restrict__ order,
+                                                          int64_t chunk, int32_t* __restrict__ out)
+{
+    __shared__ int wtot[16][kCostClasses];   // per wave and class: entries of the batch
+    __shared__ int run[kCostClasses];        // per class: entries placed so far
+    __shared__ int cbase[kCostClasses];      // per class: first position in the range
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    if (lo >= hi) return;
+    const int t = threadIdx.x, wave = t >> 6, ln = t & 63;
+    // class totals of the range
+    int cnt[kCostClasses] = {0, 0, 0};
+    for (int64_t i = lo + t; i < hi; i += 1024) ++cnt[cost_class(par[3 * ld + order[i]])];
+    if (t < kCostClasses) run[t] = 0;
+    __syncthreads();
+    for (int k = 0; k < kCostClasses; ++k)
+        if (cnt[k]) atomicAdd(&run[k], cnt[k]);
+    __syncthreads();
+    if (t == 0) {
+        int b = 0;
+        for (int k = 0; k < kCostClasses; ++k) {
+            cbase[k] = b;
+            b += run[k];
+            run[k] = 0;
+        }
+    }
+    __syncthreads();
+    // stable placement, 1024 entries per batch: position = class base + entries
+    // of the class in earlier batches + earlier waves + earlier lanes
+    for (int64_t b0 = lo; b0 < hi; b0 += 1024) {
+        const int64_t i = b0 + t;
+        const int k = i < hi ? cost_class(par[3 * ld + order[i]]) : -1;
+        int below = 0;
+        for (int c = 0; c < kCostClasses; ++c) {
+            const unsigned long long m = __ballot(k == c);
+            if (ln == 0) wtot[wave][c] = __popcll(m);
+            if (k == c)
+                below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        }
+        __syncthreads();
+        if (k >= 0) {
+            int pos = cbase[k] + run[k] + below;
+            for (int w = 0; w < wave; ++w) pos += wtot[w][k];
+            out[lo + pos] = order[i];
+        }
+        __syncthreads();
+        if (t < kCostClasses) {
+            int sum = 0;
+            for (int w = 0; w < 16; ++w) sum += wtot[w][t];
+            run[t] += sum;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ find
 // LDS writes of one wave made visible to that wave's other lanes
 __device__ inline void wave_fence()
@@ -1271,6 +1345,16 @@ hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event
     return hipGetLastError();
 }
 
+hipError_t launch_cost_order(const FindPlan& pl, const kf_tracks* seeds, int n_tiles,
+                             int seeds_per_tile, hipStream_t s)
+{
+    if (seeds->n == 0) return hipSuccess;
+    const int64_t chunk = (int64_t)((n_tiles + kQueues - 1) / kQueues) * seeds_per_tile;
+    cost_order_kernel<<<kQueues, 1024, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
+                                                pl.order, chunk, pl.tile_order);
+    return hipGetLastError();
+}
+
 hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
                              const int32_t* event_off, int n_events, int largest_first,
                              hipStream_t s)
@@ -1618,6 +1702,7 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     pl->erank = (int32_t*)take(sizeof(int32_t) * n_events);
     pl->cell = (int32_t*)take(sizeof(int32_t) * ns);
     pl->order = (int32_t*)take(sizeof(int32_t) * ns);
+    pl->tile_order = (int32_t*)take(sizeof(int32_t) * ns);
     pl->bsum = (int32_t*)take(sizeof(int32_t) * nsum);
     pl->bp = (int2*)take(sizeof(int2) * (size_t)grid * n_layers * seeds_per_tile * kMaxCands);
     pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);

@@ -98,7 +98,9 @@ struct FindPlan {
     int32_t* soff;      // [n_events * cells + 1] its exclusive prefix sum
     int32_t* erank;     // [n_events] processing position of each event
     int32_t* cell;      // [n_seeds] cell of each seed
-    int32_t* order;     // [n_seeds] seeds in processing order
+    int32_t* order;     // [n_seeds] seeds in (event, eta, phi) cell order
+    int32_t* tile_order;  // [n_seeds] the finding kernel's order: the cell order partitioned
+                          // by cost class inside each tile queue's range
     int32_t* bsum;      // chunk totals of the prefix sums
     int2* bp;
     int32_t* tile_counter;
@@ -129,6 +131,9 @@ hipError_t launch_clean(const FindPlan& pl, const kf_tracks* seeds, const int32_
 hipError_t launch_dedup(const FindPlan& pl, int64_t n, int nl, const int32_t* rows,
                         const float* chi2, uint32_t* status, const int32_t* event, int64_t n_hits,
                         double frac, hipStream_t s);
+// The finding kernel's tile order (pl.tile_order) from the cell order.
+hipError_t launch_cost_order(const FindPlan& pl, const kf_tracks* seeds, int n_tiles,
+                             int seeds_per_tile, hipStream_t s);
 hipError_t launch_seed_order(const FindPlan& pl, const kf_tracks* seeds, const int32_t* seed_event,
                              const int32_t* event_off, int n_events, int largest_first,
                              hipStream_t s);
