@@ -79,7 +79,13 @@ KERNEL_SOURCES = ["kf_find.hip", "kf_find.hpp", "kf_math.hpp", "kf_mlp.hpp", "kf
 FIND_KERNEL = "kfmi::find_kernel<float, double, double, false, false, false, false>"
 
 
-def measured_traffic(kernel):
+FIT_SOURCES = ["kf_fit.hip", "kf_math.hpp", "kf_mlp.hpp", "kf_internal.hpp", "kf_matmap.hpp"]
+PER_LAYER_KERNEL = "kfmi::fit_kernel<float, double, double, false, false, false> (per layer)"
+
+
+def measured_traffic(kernel, sources=KERNEL_SOURCES, hash_key="kernel_source_hash"):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary,
+    or None when the kernel's sources changed since it was taken."""
     import hashlib
     try:
         with open(TRAFFIC_JSON) as f:
@@ -87,10 +93,10 @@ def measured_traffic(kernel):
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for s in KERNEL_SOURCES:
+    for s in sources:
         with open(os.path.join(ROOT, "paper_1906_02253_amd", "csrc", s), "rb") as f:
             h.update(f.read())
-    if d.get("kernel_source_hash") != h.hexdigest()[:16]:
+    if d.get(hash_key) != h.hexdigest()[:16]:
         return None
     k = d.get("kernels", {}).get(kernel)
     return k["hbm_bytes"] if k else None
@@ -219,7 +225,10 @@ def run_fit(K, torch, n, w=None, reps=5):
             "per_layer_hbm": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": gbs / HBM_PEAK_GBS,
                               "bytes_per_step": FIT_BYTES_PER_STEP,
-                              "bytes_moved_per_step": PER_LAYER_BYTES_PER_STEP},
+                              "bytes_moved_per_step": PER_LAYER_BYTES_PER_STEP,
+                              "traffic_per_launch": measured_traffic(PER_LAYER_KERNEL, FIT_SOURCES,
+                                                                     "fit_source_hash"),
+                              "steps_per_launch": n_steps / 10.0},
             "per_layer_fp32_ms": out["per_layer_fp32"],
             "per_layer_fp32_steps_per_s": n_steps / (out["per_layer_fp32"] * 1e-3),
             "per_layer_fp32_hbm": {"bound": "hbm", "achieved": gbs32, "peak": HBM_PEAK_GBS,

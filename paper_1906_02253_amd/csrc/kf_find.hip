@@ -597,7 +597,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     const int MC = a.prm.max_cands;
     const int nl = a.n_layers;
     // seeds and outputs are stored in T; in registers a candidate's state is
-    // held in U and its covariance in C
+    // held in T and its covariance in C (the update runs in U)
     const T* scov = (const T*)a.scov;
     T* ocov = (T*)a.ocov;
     FindShared<C> sh;
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         const bool bad_event = ev < 0 || ev >= a.n_events;
         if (bad_event) ev = 0;
         // candidate registers
-        U p[6];
+        T p[6];
         C P[21];
         float chi2 = 0.0f;
         int nhits = 0, misses = 0;
@@ -699,7 +699,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         bool done = true;
         if (occupied) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) p[k] = U(a.spar[k * a.sld + sid]);
+            for (int k = 0; k < 6; ++k) p[k] = T(a.spar[k * a.sld + sid]);
 #pragma unroll
             for (int k = 0; k < 21; ++k) P[k] = C(scov[k * a.sld + sid]);
             chi2 = a.schi2[sid];
@@ -708,7 +708,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             done = (status & kFreezeMask) != 0;
         } else {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) p[k] = U(0);
+            for (int k = 0; k < 6; ++k) p[k] = T(0);
 #pragma unroll
             for (int k = 0; k < 21; ++k) P[k] = C(0);
         }
@@ -749,17 +749,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         for (int step = 0; step < nl; ++step) {
             const bool live = occupied && !done;
             if (!__syncthreads_or(live)) break;
-            // the surface solves, helix and window run on the state rounded to T
-            T pt[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) pt[k] = T(p[k]);
             // ---- a3: navigate and propagate (LEARN: the whole wave first
             // evaluates the learned start of its candidates' barrel solves)
             T s_guess = T(-1);
             if (LEARN) {
                 float f[kMlpIn] = {0, 0, 0, 0, 0, 0, 0, 0};
-                const int bl = live ? next_barrel(pt, sh.layers, *sh.nav) : -1;
-                if (bl >= 0) mlp_features(pt, sh.layers[bl], a.prm, f);
+                const int bl = live ? next_barrel(p, sh.layers, *sh.nav) : -1;
+                if (bl >= 0) mlp_features(p, sh.layers[bl], a.prm, f);
                 const float y = mlp_wave(a.mlp, f);
                 if (bl >= 0) {
                     s_guess = T(mlp_guess(f, y));
@@ -773,13 +769,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 T fl = T(0), fkb = T(0);
                 T fq[6];
                 if constexpr (FIELD)
-                    layer = navigate_field(pt, sh.layers, nl, a.prm, &fl, fq, &fkb, &status,
+                    layer = navigate_field(p, sh.layers, nl, a.prm, &fl, fq, &fkb, &status,
                                            &n_newton);
                 else if constexpr (STEER)
-                    layer = steer_next(pt, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
+                    layer = steer_next(p, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
                                        a.prm, kb, &s, &status, &n_newton, &n_disk);
                 else
-                    layer = navigate(pt, sh.layers, *sh.nav, a.prm, kb, &s, &status, &n_newton, &n_disk,
+                    layer = navigate(p, sh.layers, *sh.nav, a.prm, kb, &s, &status, &n_newton, &n_disk,
                                      s_guess, LEARN ? a.prm.mlp_max_iter : 0, &n_fallback);
                 if (layer < 0) {
                     done = true;
@@ -792,9 +788,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                         transport(p, P, s, kb, L.kind, T(L.r_or_z));
                     if (a.material) {
                         if constexpr (MAT)
-                            add_material(p, P, L, a.mat, U(a.prm.mass));
+                            add_material(p, P, L, a.mat, T(a.prm.mass));
                         else
-                            add_scatter(p, P, L.kind, U(L.x0), U(a.prm.mass));
+                            add_scatter(p, P, L.kind, T(L.x0), T(a.prm.mass));
                     }
                     bool fin = true;
 #pragma unroll
@@ -836,15 +832,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             int nrow = 0, row_lo = 0, v0 = 0, v1 = 0, np = 1, n2 = 1, row0 = 0;
             if (pl >= 0) {
                 const kf_layer L = sh.layers[pl];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) pt[k] = T(p[k]);
-                const Window<T> Wn = make_window<T, C>(pt, P, L, T(cut));
+                const Window<T> Wn = make_window<T, C>(p, P, L, T(cut));
                 if (Wn.ok) {
                     np = L.nbin_phi;
                     n2 = L.nbin_2;
                     int b_lo = 0, b_hi = np - 1;
                     if (!Wn.all_phi) {
-                        const T phi = Tr<T>::atan2_(pt[1], pt[0]);
+                        const T phi = Tr<T>::atan2_(p[1], p[0]);
                         b_lo = (int)Tr<T>::floor_((phi - Wn.dphi + T(kPi)) * T(np) / T(2.0 * kPi));
                         b_hi = (int)Tr<T>::floor_((phi + Wn.dphi + T(kPi)) * T(np) / T(2.0 * kPi));
                         if (b_hi - b_lo + 1 >= np || b_hi < b_lo) {
@@ -857,9 +851,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     v0 = coord_bin_of(float(Wn.vlo), float(L.lo), float(L.hi), n2);
                     v1 = coord_bin_of(float(Wn.vhi), float(L.lo), float(L.hi), n2);
                     row0 = ev * a.bl.per_event + a.bl.base[pl];
-                    const T rho = Tr<T>::sqrt_(pt[0] * pt[0] + pt[1] * pt[1]);
-                    sh.own[0 * W + t] = float(pt[0] / rho);
-                    sh.own[1 * W + t] = float(pt[1] / rho);
+                    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+                    sh.own[0 * W + t] = float(p[0] / rho);
+                    sh.own[1 * W + t] = float(p[1] / rho);
                     sh.own[2 * W + t] = float(Wn.sin_dphi);
                     sh.own[3 * W + t] = float(Wn.wv);
                     sh.own[4 * W + t] = __int_as_float((Wn.all_phi ? 1 : 0) | (L.kind << 1));
@@ -1187,7 +1181,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                             f.vu = U(hh.su) * U(hh.su);
                             f.vv = U(hh.sv) * U(hh.sv);
                             U c2 = U(0);
-                            const int r = kf_update<U, C, U>(p, P, f, sh.layers[ppl].kind, &c2);
+                            const int r = kf_update<T, C, U>(p, P, f, sh.layers[ppl].kind, &c2);
                             ++n_upd;
                             if (r) {
                                 status |= (uint32_t)r;

@@ -69,9 +69,9 @@ __device__ inline int propagate_to(U p[6], C P[21], const kf_layer& L, const kf_
         field_transport(p, P, q, l, kb0, T(L.r_or_z));
         if (material) {
             if constexpr (MAT)
-                add_material(p, P, L, mat, U(prm.mass));
+                add_material(p, P, L, mat, T(prm.mass));
             else
-                add_scatter(p, P, L.kind, U(L.x0), U(prm.mass));
+                add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
         }
         if (s_out) *s_out = l * sth;
         bool fin = true;
@@ -100,9 +100,9 @@ __device__ inline int propagate_to(U p[6], C P[21], const kf_layer& L, const kf_
     transport(p, P, s, kb, L.kind, T(L.r_or_z));
     if (material) {
         if constexpr (MAT)
-            add_material(p, P, L, mat, U(prm.mass));
+            add_material(p, P, L, mat, T(prm.mass));
         else
-            add_scatter(p, P, L.kind, U(L.x0), U(prm.mass));
+            add_scatter(p, P, L.kind, T(L.x0), T(prm.mass));
     }
     if (s_out) *s_out = s;
     bool fin = true;

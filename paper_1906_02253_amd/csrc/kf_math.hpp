@@ -266,11 +266,15 @@ KF_HD inline void transport(S p[6], C P[21], T s, T kb, int kind, T zd)
 }
 
 // Multiple-scattering process noise of a layer (PDG Highland width), added to
-// the (c, phi, theta) block at the propagated state.
-template <typename T, typename C>
-KF_HD inline void add_scatter(const T p[6], C P[21], int kind, T x0, T mass)
+// the (c, phi, theta) block at the propagated state.  Evaluated in T on the
+// state (held in S) rounded to T.
+template <typename T, typename C, typename S>
+KF_HD inline void add_scatter(const S ps[6], C P[21], int kind, T x0, T mass)
 {
     if (!(x0 > T(0))) return;
+    T p[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = T(ps[k]);
     T st, ct;
     Tr<T>::sincos_(p[5], &st, &ct);
     T cosa;
@@ -319,21 +323,26 @@ KF_HD inline T bethe_si(T p, T m)
 // crossing point gives the thickness for the noise and the areal density for
 // the mean energy loss (|p| lowered at fixed direction, c' = c p/p', the
 // covariance's c row and column scaled by dc'/dc = (p/p')^3 E'/E).
-template <typename T, typename C>
-KF_HD inline void add_material(T p[6], C P[21], const kf_layer& L, const MatMap& m, T mass)
+// The state is held in S; the lookup takes the crossing point in double, the
+// noise and the loss are evaluated in T, and q/pT is scaled in S.
+template <typename T, typename C, typename S>
+KF_HD inline void add_material(S ps[6], C P[21], const kf_layer& L, const MatMap& m, T mass)
 {
     if (!m.x0) {
-        add_scatter(p, P, L.kind, T(L.x0), mass);
+        add_scatter(ps, P, L.kind, T(L.x0), mass);
         return;
     }
-    const double r = sqrt((double)p[0] * (double)p[0] + (double)p[1] * (double)p[1]);
+    const double r = sqrt((double)ps[0] * (double)ps[0] + (double)ps[1] * (double)ps[1]);
     int ir = (int)floor(r / (m.r_max / m.nr));
-    int iz = (int)floor(((double)p[2] - m.z_min) / ((m.z_max - m.z_min) / m.nz));
+    int iz = (int)floor(((double)ps[2] - m.z_min) / ((m.z_max - m.z_min) / m.nz));
     ir = ir < 0 ? 0 : (ir >= m.nr ? m.nr - 1 : ir);
     iz = iz < 0 ? 0 : (iz >= m.nz ? m.nz - 1 : iz);
     const T x0 = T(m.x0[ir * m.nz + iz]), xi = T(m.xi[ir * m.nz + iz]);
-    add_scatter(p, P, L.kind, x0, mass);
+    add_scatter(ps, P, L.kind, x0, mass);
     if (!(xi > T(0))) return;
+    T p[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = T(ps[k]);
     T st, ct;
     Tr<T>::sincos_(p[5], &st, &ct);
     T cosa;
@@ -356,7 +365,7 @@ KF_HD inline void add_material(T p[6], C P[21], const kf_layer& L, const MatMap&
     const T p1 = Tr<T>::sqrt_(E1 * E1 - mass * mass);
     const T ratio = pm / p1;
     const C J = C(ratio * ratio * ratio * (E1 / E));
-    p[3] *= ratio;
+    ps[3] *= S(ratio);
 #pragma unroll
     for (int k = 0; k < 6; ++k) P[pk(3, k)] *= J;
     P[pk(3, 3)] *= J;

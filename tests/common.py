@@ -147,3 +147,28 @@ def check_find_params(g, o, label, sens_fn):
     cerr = chi2_error(g["chi2"][same], o["chi2"][same], o["ndf"][same])
     assert cerr.size == 0 or cerr.max() < CHI2_REL, cerr.max()
     assert np.array_equal(g["ndf"][same], o["ndf"][same])
+
+
+def check_fit_params(g, o, label, sens_fn):
+    """Fit parity: status equal, |dp| < REL, |dchi2| < CHI2_REL on the tracks
+    the oracle fitted.  A track above REL is accepted only if it is
+    ill-conditioned at the hits' resolution (sens_fn(track indices) -> the
+    oracle's largest relative parameter change over refits with its hits
+    moved by one float32 ulp, >= 0.1 REL) and lies within 10 times that
+    change; such tracks may be at most MAX_EXCUSED_FRAC of the tracks."""
+    assert np.array_equal(g["status"], o["status"]), label
+    ok = np.nonzero(o["status"] == 0)[0]
+    err = par_error(g["par"][ok], o["par"][ok])
+    e1 = err.max(axis=1)
+    cerr = chi2_error(g["chi2"][ok], o["chi2"][ok], o["ndf"][ok])
+    over = ok[e1 >= REL]
+    print(f"{label}: {ok.size} tracks, max rel par err per parameter {err.max(axis=0)}, "
+          f"{over.size} above {REL:g}, chi2 err / tol {cerr.max() / CHI2_REL:.3f}")
+    if over.size:
+        sens = sens_fn(over)
+        eo = e1[e1 >= REL]
+        print(f"{label}: ill-conditioned tracks {over.tolist()[:10]}: errors {eo[:10]}, oracle "
+              f"one-ulp sensitivity {sens[:10]}")
+        assert (sens >= 0.1 * REL).all() and (eo < 10 * sens).all(), (label, eo, sens)
+        assert over.size <= MAX_EXCUSED_FRAC * max(ok.size, 1000)
+    assert cerr.max() < CHI2_REL
