@@ -298,6 +298,23 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
             const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
             int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream);
 
+/* kf_find for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same pass and results as kf_find, with its scratch taken from a
+ * static device array of 64 MiB that the library holds on every device it
+ * runs on until the process ends (its address looked up once per device by
+ * kf_create), instead of the context's workspace.  No allocation, no
+ * freeing, no phase timing.  A call whose scratch would exceed 64 MiB
+ * (about 88 B per hit, 140 B per seed, the back-pointers of the resident
+ * workgroups and 0.4 MB of bins per event at 24 layers of 128 x 32 bins)
+ * returns KF_EINVAL with the sizes in kf_last_error.  Every call on one
+ * device shares that device's array and leaves its contents behind (each
+ * call clears what it needs): calls that overlap on one device - two
+ * streams, two contexts or two host threads - race and must not be issued. */
+int kf_find_noalloc(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+                    const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
+                    int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream);
+
 /* The whole finding pass over a batch of events as one captured HIP graph
  * (paper Sec. 3.2: seeds processed in parallel; events of uneven size in one
  * persistent launch): kf_seed of every seed from its three hits, kf_fit over

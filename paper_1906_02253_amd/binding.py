@@ -82,6 +82,8 @@ def _load():
     L.kf_fit.argtypes = [vp, C.POINTER(KfTracks), C.POINTER(KfHits), vp, vp, i32, C.c_int, vp]
     L.kf_find.argtypes = [vp, C.POINTER(KfHits), vp, i32, C.POINTER(KfTracks), vp, vp, vp,
                           C.POINTER(KfTracks), vp, C.c_int, vp]
+    L.kf_find_noalloc.argtypes = [vp, C.POINTER(KfHits), vp, i32, C.POINTER(KfTracks), vp, vp, vp,
+                                  C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_find_batched.argtypes = [vp, C.POINTER(KfHits), vp, i32, vp, vp, vp, C.POINTER(KfTracks),
                                   vp, C.POINTER(KfTracks), vp, C.c_int, vp]
     L.kf_set_material.argtypes = [vp, C.POINTER(KfMaterial)]
@@ -104,7 +106,7 @@ def _load():
     L.kf_mlp_targets.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.kf_mlp_grad.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp, vp, vp]
     L.kf_mlp_train.argtypes = [vp, vp, vp, i64, i64, vp, i32, i32, C.POINTER(KfTrainCfg), vp, vp]
-    for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_find_batched",
+    for f in ("kf_seed", "kf_propagate", "kf_fit", "kf_find", "kf_find_batched", "kf_find_noalloc",
               "kf_set_find_config", "kf_get_find_config", "kf_autotune", "kf_set_timing",
               "kf_timings", "kf_mlp_load", "kf_mlp_get", "kf_mlp_features", "kf_mlp_forward",
               "kf_mlp_targets",
@@ -317,6 +319,15 @@ class Context:
                                 C.byref(seeds.c()), _ptr(seed_event), _ptr(seed_hits),
                                 _ptr(out_hits), C.byref(out.c()), _ptr(counters), flags,
                                 _stream()), "kf_find")
+
+    def find_noalloc(self, hits, event_off, seeds, seed_event, seed_hits, out_hits, out,
+                     counters=None, flags=0):
+        """kf_find with the library's static scratch (no device allocation)."""
+        n_events = int(event_off.shape[0]) - 1
+        self._check(lib.kf_find_noalloc(self.h, C.byref(hits.c()), _ptr(event_off), n_events,
+                                        C.byref(seeds.c()), _ptr(seed_event), _ptr(seed_hits),
+                                        _ptr(out_hits), C.byref(out.c()), _ptr(counters), flags,
+                                        _stream()), "kf_find_noalloc")
 
     def find_batched(self, hits, event_off, seed_hits, seed_layers, seed_event, seeds, out_hits,
                      out, counters=None, flags=0):

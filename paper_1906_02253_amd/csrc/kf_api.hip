@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "kf_find.hpp"
 #include "kf_mlp_api.hpp"
@@ -109,7 +110,7 @@ namespace {
 int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
                  const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
                  int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, const char* what,
-                 kfmi::FindLaunch* L)
+                 kfmi::FindLaunch* L, void* fixed_ws = nullptr, size_t fixed_bytes = 0)
 {
     int r = check_tracks(ctx, seeds, what);
     if (r) return r;
@@ -173,8 +174,16 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     if (grid > n_tiles) grid = n_tiles;
     if (grid < 1) grid = 1;
     const size_t bytes = kfmi::plan_find(&pl, nullptr, hits->n, n_events, seeds->n, nl, (int)grid, S);
-    void* base = ctx->ws.get(bytes);
-    if (!base) return fail(ctx, KF_ENOMEM, "%s: workspace of %zu bytes", what, bytes);
+    void* base = nullptr;
+    if (fixed_ws) {
+        if (bytes > fixed_bytes)
+            return fail(ctx, KF_EINVAL, "%s: the call needs %zu bytes of scratch, the static scratch "
+                        "holds %zu", what, bytes, fixed_bytes);
+        base = fixed_ws;
+    } else {
+        base = ctx->ws.get(bytes);
+        if (!base) return fail(ctx, KF_ENOMEM, "%s: workspace of %zu bytes", what, bytes);
+    }
     kfmi::plan_find(&pl, base, hits->n, n_events, seeds->n, nl, (int)grid, S);
     kfmi::FindArgs& a = L->a;
     a.bh = (const kfmi::BinnedHit*)pl.binned;
@@ -290,6 +299,32 @@ hipError_t capture(kf_ctx* ctx, hipGraph_t* out, F f)
     return hipSuccess;
 }
 
+// Static scratch of kf_find_noalloc: one copy per device, alive until the
+// process ends.  In host code `scratch` names a host-side stand-in; the
+// device address comes from hipGetSymbolAddress, once per device, at
+// kf_create.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kfmi::kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev`, looked up on the
+// first call for that device.
+hipError_t scratch_address(int dev, void** out)
+{
+    if (dev < 0 || dev >= kfmi::kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -349,6 +384,7 @@ int kf_create(kf_ctx** out, const kf_layer* layers, int32_t n_layers, const kf_p
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&ctx->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                   ctx->device);
+    if (e == hipSuccess) e = scratch_address(ctx->device, &ctx->noalloc_scratch);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_layers, sizeof(kf_layer) * kfmi::kMaxLayers);
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_layers, ctx->layers, sizeof(kf_layer) * n_layers, hipMemcpyHostToDevice);
@@ -630,6 +666,25 @@ int kf_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t 
         if (e == hipSuccess) ctx->timing_used++;
     }
     return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_find");
+}
+
+int kf_find_noalloc(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,
+                    const kf_tracks* seeds, const int32_t* seed_event, const int32_t* seed_hits,
+                    int32_t* out_hits, kf_tracks* out, uint64_t* counters, int flags, void* stream)
+{
+    if (!ctx) return fail(nullptr, KF_EINVAL, "kf_find_noalloc: null context");
+    if (!ctx->noalloc_scratch) return fail(ctx, KF_EHIP, "kf_find_noalloc: no static scratch");
+    kfmi::FindLaunch L;
+    int r = prepare_find(ctx, hits, event_off, n_events, seeds, seed_event, seed_hits, out_hits,
+                         out, counters, flags, "kf_find_noalloc", &L, ctx->noalloc_scratch,
+                         kNoAllocScratchBytes);
+    if (r) return r;
+    if (seeds->n == 0) return KF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = phase_bin(ctx, L, s);
+    if (e == hipSuccess) e = phase_order(ctx, L, s);
+    if (e == hipSuccess) e = phase_find(ctx, L, s);
+    return e == hipSuccess ? KF_OK : hip_fail(ctx, e, "kf_find_noalloc");
 }
 
 int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int32_t n_events,

@@ -13,6 +13,7 @@
 namespace kfmi {
 
 constexpr int kMaxLayers = 64;
+constexpr int kMaxDevices = 64;   // devices the static scratch of kf_find_noalloc tracks
 
 // Device-resident workspace, grown on demand and reused between calls.
 struct Workspace {
@@ -90,6 +91,7 @@ struct kf_ctx {
     hipStream_t cap_stream = nullptr; // private stream the batched pass is captured on
     hipEvent_t idle_ev[kfmi::kPhaseEvents] = {};  // record targets of an untimed graph launch
     kfmi::FindGraph fg;
+    void* noalloc_scratch = nullptr;  // device address of kf_find_noalloc's static scratch
     uint64_t setup_gen = 0;           // bumped by every change of the material map or the
                                       // steering, which captured launches take by value
     void* mlp_mem = nullptr;          // device block holding the network buffers

@@ -54,7 +54,7 @@ def test_batched_and_autotune_validation_without_device(lib):
     """The graph and autotuning entry points reject a null context before any
     device work."""
     for f, n in (("kf_find_batched", 13), ("kf_autotune", 13), ("kf_clean_seeds", 8),
-                 ("kf_remove_duplicates", 7)):
+                 ("kf_remove_duplicates", 7), ("kf_find_noalloc", 12)):
         fn = getattr(lib, f)
         fn.restype = C.c_int
         fn.argtypes = [C.c_void_p] * n
