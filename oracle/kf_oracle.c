@@ -32,7 +32,7 @@
  *     equal steps of at most field_step; the propagate-to-radius solve is
  *     the same bracketed Newton iteration on the integrated radius, and the
  *     transport Jacobian is the helix one in the field at the start point.
- *     Barrel targets only.
+ *     Disks are reached by the same Newton iteration on the integrated z.
  */
 #include "kf_oracle.h"
 
@@ -328,16 +328,56 @@ static int solve_barrel_field(const orc_cfg* cfg, const double p[6], double r_l,
     return ORC_ST_NOCONV;
 }
 
+/* Propagate-to-z in the parametrised field: bracketed Newton on the 3D path
+ * length l with z(l) from the Runge-Kutta transport and dz/dl = cos theta(l).
+ * Start: the straight line l0 = (z_d - z) / cos theta (exact in a uniform
+ * field), or l_init >= 0.  The plane must lie ahead (l0 >= 0).  Bracket
+ * [0, 2 l0]: the field's radial component bends theta only slightly, and a
+ * track that has not reached the plane after twice the straight path does
+ * not reach it (NOCONV).  Same stopping rule as the radius solve. */
+static int solve_disk_field(const orc_cfg* cfg, const double p[6], double z_d, double l_init,
+                            double* l_out, int* iters_out)
+{
+    double ct = cos(p[5]);
+    double l0 = ct != 0.0 ? (z_d - p[2]) / ct : -1.0;
+    if (!(l0 >= 0.0)) {
+        if (iters_out) *iters_out = 0;
+        return ORC_ST_UNREACHABLE;
+    }
+    double sgn = ct > 0.0 ? 1.0 : -1.0;
+    double l_lo = 0.0, l_hi = 2.0 * l0;
+    double l = l_init >= 0.0 ? l_init : l0;
+    if (l < l_lo) l = l_lo;
+    if (l > l_hi) l = l_hi;
+    for (int it = 1; it <= cfg->max_newton; ++it) {
+        double q[6];
+        orc_rk_path(cfg, p, l, q);
+        double res = sgn * (q[2] - z_d);      /* > 0: past the plane */
+        double drdl = sgn * cos(q[5]);
+        if (res < 0.0) { if (l > l_lo) l_lo = l; }
+        else { if (l < l_hi) l_hi = l; }
+        if (fabs(res) < cfg->newton_tol) {
+            if (drdl > 0.0) l -= res / drdl;
+            *l_out = l;
+            if (iters_out) *iters_out = it;
+            return ORC_ST_OK;
+        }
+        double ln = l - res / drdl;
+        if (!(drdl > 0.0) || !(ln > l_lo && ln < l_hi)) ln = 0.5 * (l_lo + l_hi);
+        l = ln;
+    }
+    *l_out = l;
+    if (iters_out) *iters_out = cfg->max_newton;
+    return ORC_ST_NOCONV;
+}
+
 /* path length to a layer, no covariance */
 static int path_to_layer(const orc_cfg* cfg, int layer, const double p[6], double* s, int* iters)
 {
     const orc_layer* L = &cfg->layers[layer];
     if (cfg->field_z0 > 0.0) {
-        /* parametrised field: barrels only; s is the 3D path length here */
-        if (L->kind != 0) {
-            if (iters) *iters = 0;
-            return ORC_ST_UNREACHABLE;
-        }
+        /* parametrised field: s is the 3D path length here */
+        if (L->kind != 0) return solve_disk_field(cfg, p, L->r_or_z, -1.0, s, iters);
         return solve_barrel_field(cfg, p, L->r_or_z, -1.0, s, iters);
     }
     if (L->kind == 0) return orc_solve_barrel(cfg, p, L->r_or_z, -1.0, s, iters);
@@ -406,11 +446,25 @@ static void transport_parts(const orc_cfg* cfg, const orc_layer* L, const double
                             double q[6], double F[6][6])
 {
     if (cfg->field_z0 > 0.0) {
-        double x0[3] = {p[0], p[1], p[2]}, B0[3];
-        orc_field(cfg, x0, B0);
         orc_rk_path(cfg, p, s, q);
-        /* the helix Jacobian in the start point's field, over the transverse path */
-        jacobian_at_bz(B0[2], L, p, s * sin(p[5]), F);
+        /* the helix Jacobian over the transverse path, in the path's mean
+         * effective axial field: the transverse turning rate is
+         * -kappa c (Bz - cot(theta) B_T . t_T), where the transverse field
+         * bends a track that moves along z; averaged by Simpson's rule over
+         * the start, the chord's midpoint (mean direction) and the end */
+        double dphi = wrap_pi(q[4] - p[4]);
+        double pts[3][5] = {{p[0], p[1], p[2], p[4], p[5]},
+                            {0.5 * (p[0] + q[0]), 0.5 * (p[1] + q[1]), 0.5 * (p[2] + q[2]),
+                             p[4] + 0.5 * dphi, 0.5 * (p[5] + q[5])},
+                            {q[0], q[1], q[2], q[4], q[5]}};
+        double beff[3];
+        for (int k = 0; k < 3; ++k) {
+            double B[3];
+            orc_field(cfg, pts[k], B);
+            double bt = B[0] * cos(pts[k][3]) + B[1] * sin(pts[k][3]);
+            beff[k] = B[2] - cos(pts[k][4]) / sin(pts[k][4]) * bt;
+        }
+        jacobian_at_bz((beff[0] + 4.0 * beff[1] + beff[2]) / 6.0, L, p, s * sin(p[5]), F);
     } else {
         orc_helix(p, s, cfg->bz, q);
         jacobian_at(cfg, L, p, s, F);
@@ -893,10 +947,15 @@ static void free_index(const orc_cfg* cfg, event_index* E)
  * margin below 1e-3.
  */
 /*
- * Next surface in the parametrised field (only barrels are surfaces there):
- * the next barrel outward (radius above rho + NEXT_BARREL_EPS), reached by
- * the Runge-Kutta radius solve, crossing inside |z| <= hi, within half a turn
- * of the start point's curvature in the transverse plane.
+ * Next surface in the parametrised field: whichever comes first along the
+ * 3D path, the next barrel outward (radius above rho + NEXT_BARREL_EPS),
+ * reached by the Runge-Kutta radius solve and crossed inside |z| <= hi, or a
+ * disk ahead (|dz| > DISK_AHEAD_EPS in the direction of travel), reached by
+ * the Runge-Kutta z solve and crossed inside its radial extent; both within
+ * half a turn of the start point's curvature in the transverse plane.  The
+ * disks are taken in layer order; a disk whose straight-line path already
+ * exceeds the best path found by more than 1% + 1 cm is not solved (the
+ * solved path differs from the straight one by far less).
  */
 static int navigate_field(const orc_cfg* cfg, const double p[6], int* stat, int* close)
 {
@@ -909,33 +968,69 @@ static int navigate_field(const orc_cfg* cfg, const double p[6], int* stat, int*
         if (L->r_or_z > rho + NEXT_BARREL_EPS && (bl < 0 || L->r_or_z < cfg->layers[bl].r_or_z))
             bl = l;
     }
-    if (bl < 0) return -1;
-    const orc_layer* L = &cfg->layers[bl];
     double x0[3] = {p[0], p[1], p[2]}, B0[3];
     orc_field(cfg, x0, B0);
     double hh = fabs(KAPPA * B0[2] * p[3]);
     double s_max = hh > 0.0 ? PI / hh : INFINITY;
     double h0 = -KAPPA * B0[2] * p[3];
-    if (h0 != 0.0) {
-        /* reachability comes from the start point's helix: its farthest radius */
-        double cx = p[0] - sin(p[4]) / h0, cy = p[1] + cos(p[4]) / h0;
-        double rmax = hypot(cx, cy) + 1.0 / fabs(h0);
-        if (fabs(rmax - L->r_or_z) < CLOSE_REL * L->r_or_z) *close = 1;
+    double st = sin(p[5]), ct = cos(p[5]);
+    double best = INFINITY, l_b = INFINITY;
+    int best_l = -1;
+    if (bl >= 0) {
+        const orc_layer* L = &cfg->layers[bl];
+        if (h0 != 0.0) {
+            /* reachability comes from the start point's helix: its farthest radius */
+            double cx = p[0] - sin(p[4]) / h0, cy = p[1] + cos(p[4]) / h0;
+            double rmax = hypot(cx, cy) + 1.0 / fabs(h0);
+            if (fabs(rmax - L->r_or_z) < CLOSE_REL * L->r_or_z) *close = 1;
+        }
+        double l;
+        int r = solve_barrel_field(cfg, p, L->r_or_z, -1.0, &l, NULL);
+        if (r == ORC_ST_NOCONV) {
+            *stat |= ORC_ST_NOCONV;
+            return -1;
+        }
+        if (r == ORC_ST_OK) {
+            double q[6];
+            orc_rk_path(cfg, p, l, q);
+            double s = l * st;
+            if (fabs(fabs(q[2]) - L->hi) < CLOSE_REL * L->hi) *close = 1;
+            if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+            if (fabs(q[2]) <= L->hi && s <= s_max) {
+                best = l_b = l;
+                best_l = bl;
+            }
+        }
     }
-    double l;
-    int st = solve_barrel_field(cfg, p, L->r_or_z, -1.0, &l, NULL);
-    if (st == ORC_ST_NOCONV) {
-        *stat |= ORC_ST_NOCONV;
-        return -1;
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        const orc_layer* L = &cfg->layers[l];
+        if (L->kind != 1) continue;
+        double dz = L->r_or_z - p[2];
+        if (fabs(fabs(dz) - DISK_AHEAD_EPS) < CLOSE_REL * DISK_AHEAD_EPS) *close = 1;
+        if (!(dz * ct > 0.0) || fabs(dz) <= DISK_AHEAD_EPS) continue;
+        double l_line = dz / ct;
+        if (l_line > 1.01 * best + 1.0) continue;
+        double ld;
+        int r = solve_disk_field(cfg, p, L->r_or_z, -1.0, &ld, NULL);
+        if (r == ORC_ST_NOCONV) {
+            *stat |= ORC_ST_NOCONV;
+            return -1;
+        }
+        if (r != ORC_ST_OK) continue;
+        double q[6];
+        orc_rk_path(cfg, p, ld, q);
+        double rr = hypot(q[0], q[1]);
+        double s = ld * st;
+        if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+        if (fabs(rr - L->lo) < CLOSE_REL * L->lo || fabs(rr - L->hi) < CLOSE_REL * L->hi) *close = 1;
+        if (s > s_max || rr < L->lo || rr > L->hi) continue;
+        if (isfinite(l_b) && fabs(ld - l_b) < CLOSE_REL * (ld > l_b ? ld : l_b)) *close = 1;
+        if (ld < best) {
+            best = ld;
+            best_l = l;
+        }
     }
-    if (st != ORC_ST_OK) return -1;
-    double q[6];
-    orc_rk_path(cfg, p, l, q);
-    double s = l * sin(p[5]);
-    if (fabs(fabs(q[2]) - L->hi) < CLOSE_REL * L->hi) *close = 1;
-    if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
-    if (fabs(q[2]) > L->hi || s > s_max) return -1;
-    return bl;
+    return best_l;
 }
 
 static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close)

@@ -206,3 +206,122 @@ def test_field_find_uniform_limit_equals_helix_finder(orc):
     assert ok.mean() > 0.99
     assert CM.par_error(f["par"][ok], u["par"][ok]).max() < 1e-9
     assert np.max(np.abs(f["chi2"][ok] - u["chi2"][ok]) / np.maximum(u["chi2"][ok], 1.0)) < 1e-8
+
+
+# ---------------------------------------------------------------- disks in the field
+def test_field_propagation_to_disk(orc):
+    """Propagate-to-z in the parametrised field: the converged crossing lies
+    on the disk plane, at the place the adaptive integration of the same
+    trajectory reaches after the same path length; in the uniform limit it
+    is the closed-form helix crossing of the plane."""
+    from tests import bruteforce as BF
+    geom = E.geometry.barrel10_disks14(x0=0.0)
+    cfg = _cfg(orc, geom=geom)
+    cfg_u = _cfg(orc, z0=1e9, step=0.5, geom=geom)
+    rng = np.random.default_rng(110)
+    P0 = np.zeros(21)
+    n_ok = 0
+    for p in _tracks(rng, 40, 1.0, 10.0):
+        p[0] = p[1] = 0.0
+        p[2] = rng.uniform(-5, 5)
+        p[5] = rng.uniform(0.2, 0.6) if rng.random() < 0.5 else np.pi - rng.uniform(0.2, 0.6)
+        layer = 12 if np.cos(p[5]) > 0 else 19          # z = +-110 cm
+        zd = geom[layer]["r_or_z"]
+        st, q, _, l, it = orc.propagate(cfg, layer, p, P0, noise=False)
+        assert st == 0
+        n_ok += 1
+        assert q[2] == pytest.approx(zd, abs=1e-9)
+        ref = _ref_path(p, l, 300.0)
+        assert np.allclose(q[:3], ref[:3], atol=5e-5)
+        assert 1 <= it <= 10
+        st, qu, _, lu, _ = orc.propagate(cfg_u, layer, p, P0, noise=False)
+        cf, s_cf = BF.cf_disk(p, zd, 3.8)
+        assert lu * np.sin(p[5]) == pytest.approx(s_cf, rel=1e-9)
+        assert np.allclose(qu[:3], cf[:3], atol=1e-6)
+    assert n_ok == 40
+    # a disk behind the track is unreachable
+    p = np.array([0.0, 0.0, 0.0, 0.5, 0.3, 0.4])
+    st, *_ = orc.propagate(cfg, 19, p, P0, noise=False)
+    assert st == orc.ST_UNREACHABLE
+
+
+def test_field_disk_fit_pulls(orc):
+    """Fit in the parametrised field of barrel and endcap tracks (|eta| < 2.5)
+    traced by the generator's fine-step integrator through barrels and disks:
+    unit pulls at the last surface and chi2/ndf near 1 (disks reached by the
+    Runge-Kutta z solve)."""
+    geom, evs = EF.field_disk_events(n_events=1, n_tracks=1500, n_noise=0, seed=31)
+    ev = evs[0]
+    cfg = _cfg(orc, geom=geom)
+    par0, cov0 = orc.seeds_for_event(ev)
+    r = orc.fit(cfg, dict(x=ev.x, y=ev.y, z=ev.z, su=ev.su, sv=ev.sv), ev.seq_layer, ev.seq_hit,
+                par0, cov0, n_threads=8)
+    nh = ev.n_track_hits()
+    kinds = np.array([L["kind"] for L in geom])
+    last = ev.seq_layer[np.arange(ev.n_tracks), np.maximum(nh - 1, 0)]
+    ok = (r["status"] == 0) & (nh >= 7)
+    disk_end = ok & (kinds[last] == 1)
+    assert disk_end.sum() > 300 and ok.sum() > 1000
+    truth = ev.truth_at[np.arange(ev.n_tracks), np.maximum(nh - 1, 0)][ok]
+    P = orc.unpack(r["cov"][ok])
+    d = r["par"][ok] - truth
+    d[:, 4] = (d[:, 4] + np.pi) % (2 * np.pi) - np.pi
+    for k in (3, 4, 5):
+        pull = d[:, k] / np.sqrt(P[:, k, k])
+        assert abs(pull.mean()) < 0.1, (k, pull.mean())
+        assert 0.9 < pull.std() < 1.1, (k, pull.std())
+    c2 = r["chi2"][ok] / r["ndf"][ok]
+    assert 0.9 < c2.mean() < 1.1
+
+
+def test_field_find_with_disks(orc):
+    """Finding in the parametrised field over barrels and disks (the next
+    surface the first reached of the next barrel and the disks ahead, each by
+    its Runge-Kutta solve) on tracks traced by the generator among uniform
+    noise: nearly every true hit beyond the seed is found, chi2/ndf near 1,
+    and the binned search equals the all-hits scan."""
+    from tests import common as CM
+    geom, evs = EF.field_disk_events(n_events=2, n_tracks=400, n_noise=24_000, seed=32)
+    inp = E.find_inputs(evs)
+    f = CM.oracle_find_events(orc, geom, evs, inp, field_z0=300.0, field_step=2.0)
+    found = tot = 0
+    disk_hits = 0
+    kinds = np.array([L["kind"] for L in geom])
+    for s in range(inp["seed_hits"].shape[0]):
+        e, t = inp["seed_event"][s], inp["seed_track"][s]
+        true = evs[e].seq_hit[t]
+        true = set((true[true >= 0][3:] + inp["event_off"][e]).tolist())
+        got = f["hits"][s][f["hits"][s] >= 0]
+        disk_hits += int((kinds[np.nonzero(f["hits"][s] >= 0)[0]] == 1).sum())
+        found += len(true & set(got.tolist()))
+        tot += len(true)
+    c2 = np.median(f["chi2"] / np.maximum(f["ndf"], 1))
+    print(f"field finding with disks: efficiency {found / tot:.4f}, disk hits {disk_hits}, "
+          f"median chi2/ndf {c2:.3f}")
+    assert found / tot > 0.99 and disk_hits > 1000
+    assert 0.8 < c2 < 1.1
+    ev = evs[0]
+    m = np.nonzero(inp["seed_event"] == 0)[0]
+    cfg = _cfg(orc, geom=geom)
+    rb = orc.find(cfg, ev, inp["seed_hits_local"][m], binned=True)
+    ra = orc.find(cfg, ev, inp["seed_hits_local"][m], binned=False)
+    assert np.array_equal(rb["hits"], ra["hits"])
+
+
+def test_field_find_with_disks_uniform_limit(orc):
+    """With Z0 = 1e9 cm, finding in the field over barrels and disks
+    reproduces the closed-form helix finder on the same events (uniform-field
+    barrel + endcap events) hit for hit, states to 1e-8."""
+    from tests import common as CM
+    rng = np.random.default_rng(33)
+    geom = E.geometry.barrel10_disks14(x0=0.0)
+    evs = [E.make_event(rng, geom, 300, E.pt_power2(0.5, 50.0), 2.5, 1000) for _ in range(2)]
+    inp = E.find_inputs(evs)
+    u = CM.oracle_find_events(orc, geom, evs, inp)
+    f = CM.oracle_find_events(orc, geom, evs, inp, field_z0=1e9, field_step=0.5)
+    kinds = np.array([L["kind"] for L in geom])
+    assert (u["hits"][:, kinds == 1] >= 0).sum() > 500
+    same = (u["hits"] == f["hits"]).all(axis=1)
+    assert same.mean() > 0.995, same.mean()
+    ok = same & (u["status"] == 0)
+    assert CM.par_error(f["par"][ok], u["par"][ok]).max() < 1e-8
