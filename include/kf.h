@@ -106,7 +106,11 @@ typedef struct {
     double field_z0;       /* 0: uniform field bz along z.  > 0: parametrised solenoid-like
                               field Bz = bz / (1 + (z/field_z0)^2), Br = -(r/2) dBz/dz, tracks
                               integrated by fourth-order Runge-Kutta (kf_propagate, kf_fit,
-                              kf_find; barrels are the only surfaces, disks report UNREACHABLE;
+                              kf_find; barrels by a Newton iteration on the integrated radius,
+                              disks on the integrated z, each over at most 1000 cm of path (a
+                              surface further along the track is UNREACHABLE); the covariance by
+                              the helix Jacobian in
+                              the path's mean effective axial field Bz - cot(theta) B_T.t_T;
                               finding in this field takes neither KF_INIT_MLP nor steering) */
     double field_step;     /* largest Runge-Kutta step [cm] in the parametrised field (> 0) */
     double clean_deta;     /* seed cleaning: |d eta| below which two seeds may be duplicates,
@@ -285,7 +289,7 @@ int kf_remove_duplicates(kf_ctx* ctx, const kf_hits* hits, kf_tracks* tracks,
  *               kept from the children of propagated parents)
  * Per layer a candidate is propagated to its next surface (the first reached
  * of the next barrel outward and the next disk ahead; in the parametrised
- * field the next barrel outward, by the Runge-Kutta radius solve), every hit in the chi2
+ * field along the 3D path, by the Runge-Kutta radius and z solves), every hit in the chi2
  * window's bins passing chi2 < chi2_cut becomes a child (best max_cands per
  * parent), plus one no-hit child; per seed the best max_cands children by
  * (most hits, lowest chi2, parent rank, hit index) survive.  A candidate stops

@@ -33,6 +33,7 @@
  *     the same bracketed Newton iteration on the integrated radius, and the
  *     transport Jacobian is the helix one in the field at the start point.
  *     Disks are reached by the same Newton iteration on the integrated z.
+ *     Both solves search at most MAX_FIELD_PATH (1000 cm) of 3D path.
  */
 #include "kf_oracle.h"
 
@@ -44,6 +45,7 @@
 #define KAPPA 0.00299792458
 #define NEXT_BARREL_EPS 0.05      /* cm: a barrel is "ahead" if r > rho + eps */
 #define DISK_AHEAD_EPS 0.05       /* cm: a disk is "ahead" if |dz| > eps in the travel direction */
+#define MAX_FIELD_PATH 1000.0     /* cm: longest 3D path the field's Runge-Kutta solves search */
 #define WIN_REL 1.001             /* window = chi2-ellipse bounding box, 1e-3 relative margin */
 #define WIN_ABS 1e-4              /* plus an absolute margin (rad or cm) */
 #define CLOSE_REL 1e-3            /* relative margin below which a decision counts as a tie */
@@ -262,7 +264,9 @@ void orc_rk_path(const orc_cfg* cfg, const double p[6], double l, double out[6])
 /* Propagate-to-radius in the parametrised field: bracketed Newton on the 3D
  * path length l with r(l) from the Runge-Kutta transport.  Start: the
  * straight-line intersection (l_init < 0) or l_init.  Bracket: the helix of
- * the start point's field (its apex), as in the uniform case. */
+ * the start point's field (its apex), as in the uniform case, cut at
+ * MAX_FIELD_PATH; a barrel whose straight-line path exceeds that is
+ * unreachable. */
 static int solve_barrel_field(const orc_cfg* cfg, const double p[6], double r_l, double l_init,
                               double* l_out, int* iters_out)
 {
@@ -293,16 +297,18 @@ static int solve_barrel_field(const orc_cfg* cfg, const double p[6], double r_l,
         if (sw < 0) sw += 2.0 * PI;
         s_hi = sw / fabs(h);
     }
-    double l_lo = 0.0, l_hi = s_hi / st;
-    double l;
-    if (l_init >= 0.0) {
-        l = l_init;
-    } else {
-        double cphi = cos(p[4]), sphi = sin(p[4]);
-        double pu = p[0] * cphi + p[1] * sphi;
-        double disc = pu * pu - (p[0] * p[0] + p[1] * p[1]) + r_l * r_l;
-        l = (disc > 0.0 ? -pu + sqrt(disc) : -pu) / st;
+    double cphi = cos(p[4]), sphi = sin(p[4]);
+    double pu = p[0] * cphi + p[1] * sphi;
+    double disc = pu * pu - (p[0] * p[0] + p[1] * p[1]) + r_l * r_l;
+    double l_line = (disc > 0.0 ? -pu + sqrt(disc) : -pu) / st;
+    /* the straight line is the shortest way to the radius: beyond the
+     * searched path the barrel is out of reach */
+    if (l_line > MAX_FIELD_PATH) {
+        if (iters_out) *iters_out = 0;
+        return ORC_ST_UNREACHABLE;
     }
+    double l_lo = 0.0, l_hi = fmin(s_hi / st, MAX_FIELD_PATH);
+    double l = l_init >= 0.0 ? l_init : l_line;
     if (l < l_lo) l = l_lo;
     if (l > l_hi) l = l_hi;
     for (int it = 1; it <= cfg->max_newton; ++it) {
@@ -331,21 +337,22 @@ static int solve_barrel_field(const orc_cfg* cfg, const double p[6], double r_l,
 /* Propagate-to-z in the parametrised field: bracketed Newton on the 3D path
  * length l with z(l) from the Runge-Kutta transport and dz/dl = cos theta(l).
  * Start: the straight line l0 = (z_d - z) / cos theta (exact in a uniform
- * field), or l_init >= 0.  The plane must lie ahead (l0 >= 0).  Bracket
- * [0, 2 l0]: the field's radial component bends theta only slightly, and a
- * track that has not reached the plane after twice the straight path does
- * not reach it (NOCONV).  Same stopping rule as the radius solve. */
+ * field), or l_init >= 0.  The plane must lie ahead (0 <= l0 <=
+ * MAX_FIELD_PATH).  Bracket [0, min(2 l0, MAX_FIELD_PATH)]: the field's
+ * radial component bends theta only slightly, and a track that has not
+ * reached the plane after twice the straight path does not reach it
+ * (NOCONV).  Same stopping rule as the radius solve. */
 static int solve_disk_field(const orc_cfg* cfg, const double p[6], double z_d, double l_init,
                             double* l_out, int* iters_out)
 {
     double ct = cos(p[5]);
     double l0 = ct != 0.0 ? (z_d - p[2]) / ct : -1.0;
-    if (!(l0 >= 0.0)) {
+    if (!(l0 >= 0.0) || l0 > MAX_FIELD_PATH) {
         if (iters_out) *iters_out = 0;
         return ORC_ST_UNREACHABLE;
     }
     double sgn = ct > 0.0 ? 1.0 : -1.0;
-    double l_lo = 0.0, l_hi = 2.0 * l0;
+    double l_lo = 0.0, l_hi = fmin(2.0 * l0, MAX_FIELD_PATH);
     double l = l_init >= 0.0 ? l_init : l0;
     if (l < l_lo) l = l_lo;
     if (l > l_hi) l = l_hi;
@@ -938,15 +945,6 @@ static void free_index(const orc_cfg* cfg, event_index* E)
 }
 
 /*
- * Next surface (dynamic navigation): the candidate moves to whichever is
- * reached first along the helix, the next barrel outward (smallest radius
- * above the current one, reachable, crossing inside its z extent) or the
- * first disk ahead in z whose crossing lies inside its radial extent.
- * Returns the layer or -1 (no surface left); *stat gets NOCONV if the
- * barrel solve failed.  *close is set when a decision had a relative
- * margin below 1e-3.
- */
-/*
  * Next surface in the parametrised field: whichever comes first along the
  * 3D path, the next barrel outward (radius above rho + NEXT_BARREL_EPS),
  * reached by the Runge-Kutta radius solve and crossed inside |z| <= hi, or a
@@ -954,8 +952,9 @@ static void free_index(const orc_cfg* cfg, event_index* E)
  * the Runge-Kutta z solve and crossed inside its radial extent; both within
  * half a turn of the start point's curvature in the transverse plane.  The
  * disks are taken in layer order; a disk whose straight-line path already
- * exceeds the best path found by more than 1% + 1 cm is not solved (the
- * solved path differs from the straight one by far less).
+ * exceeds the best path found, or whose straight-line transverse path exceeds
+ * half a turn, by more than 1% + 1 cm is not solved (the solved path differs
+ * from the straight one by far less).
  */
 static int navigate_field(const orc_cfg* cfg, const double p[6], int* stat, int* close)
 {
@@ -1009,7 +1008,7 @@ static int navigate_field(const orc_cfg* cfg, const double p[6], int* stat, int*
         if (fabs(fabs(dz) - DISK_AHEAD_EPS) < CLOSE_REL * DISK_AHEAD_EPS) *close = 1;
         if (!(dz * ct > 0.0) || fabs(dz) <= DISK_AHEAD_EPS) continue;
         double l_line = dz / ct;
-        if (l_line > 1.01 * best + 1.0) continue;
+        if (l_line > 1.01 * best + 1.0 || l_line * st > 1.01 * s_max + 1.0) continue;
         double ld;
         int r = solve_disk_field(cfg, p, L->r_or_z, -1.0, &ld, NULL);
         if (r == ORC_ST_NOCONV) {
@@ -1033,6 +1032,15 @@ static int navigate_field(const orc_cfg* cfg, const double p[6], int* stat, int*
     return best_l;
 }
 
+/*
+ * Next surface (dynamic navigation): the candidate moves to whichever is
+ * reached first along the helix, the next barrel outward (smallest radius
+ * above the current one, reachable, crossing inside its z extent) or the
+ * first disk ahead in z whose crossing lies inside its radial extent.
+ * Returns the layer or -1 (no surface left); *stat gets NOCONV if the
+ * barrel solve failed.  *close is set when a decision had a relative
+ * margin below 1e-3.
+ */
 static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close)
 {
     if (cfg->field_z0 > 0.0) return navigate_field(cfg, p, stat, close);

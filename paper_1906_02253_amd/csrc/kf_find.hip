@@ -766,11 +766,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             if (live) {
                 T s;
                 int layer;
-                T fl = T(0), fkb = T(0);
+                T fl = T(0);
                 T fq[6];
                 if constexpr (FIELD)
-                    layer = navigate_field(p, sh.layers, nl, a.prm, &fl, fq, &fkb, &status,
-                                           &n_newton);
+                    layer = navigate_field(p, sh.layers, nl, a.prm, &fl, fq, &status, &n_newton,
+                                           &n_disk);
                 else if constexpr (STEER)
                     layer = steer_next(p, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
                                        a.prm, kb, &s, &status, &n_newton, &n_disk);
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     ++n_prop;
                     const kf_layer L = sh.layers[layer];
                     if constexpr (FIELD)
-                        field_transport(p, P, fq, fl, fkb, T(L.r_or_z));
+                        field_transport(p, P, fq, fl, a.prm, L.kind, T(L.r_or_z));
                     else
                         transport(p, P, s, kb, L.kind, T(L.r_or_z));
                     if (a.material) {

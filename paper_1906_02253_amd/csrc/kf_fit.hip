@@ -53,20 +53,25 @@ __device__ inline int propagate_to(U p[6], C P[21], const kf_layer& L, const kf_
     for (int k = 0; k < 6; ++k) pt[k] = T(p[k]);
     T s;
     if constexpr (FIELD) {
-        // parametrised field: Runge-Kutta transport to a barrel; the covariance
-        // is carried by the helix Jacobian in the start point's field
-        if (L.kind != 0) return KF_ST_UNREACHABLE;
-        T bx, by, bz0;
-        field_at(T(prm.bz), T(prm.field_z0), pt[0], pt[1], pt[2], &bx, &by, &bz0);
-        const T kb0 = T(kKappa) * bz0;
+        // parametrised field: Runge-Kutta transport to the barrel's radius or
+        // the disk's z; the covariance is carried by the helix Jacobian in the
+        // path's mean effective axial field
         const T sth = Tr<T>::sin_(pt[5]);
         T l;
-        int st = solve_barrel_field(pt, T(L.r_or_z), prm, kb0, s_init >= T(0) ? s_init / sth : T(-1),
+        int st;
+        if (L.kind != 0) {
+            st = solve_disk_field(pt, T(L.r_or_z), prm, &l, evals);
+        } else {
+            T bx, by, bz0;
+            field_at(T(prm.bz), T(prm.field_z0), pt[0], pt[1], pt[2], &bx, &by, &bz0);
+            const T kb0 = T(kKappa) * bz0;
+            st = solve_barrel_field(pt, T(L.r_or_z), prm, kb0, s_init >= T(0) ? s_init / sth : T(-1),
                                     prm.mlp_max_iter, &l, evals, fallbacks);
+        }
         if (st) return st;
         T q[6];
         rk_path(pt, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
-        field_transport(p, P, q, l, kb0, T(L.r_or_z));
+        field_transport(p, P, q, l, prm, L.kind, T(L.r_or_z));
         if (material) {
             if constexpr (MAT)
                 add_material(p, P, L, mat, T(prm.mass));

@@ -25,6 +25,7 @@ constexpr double kKappa = 0.00299792458;   // GeV / (T cm)
 constexpr double kPi = 3.14159265358979323846;
 constexpr float kNextBarrelEps = 0.05f;    // cm
 constexpr float kDiskAheadEps = 0.05f;     // cm
+constexpr float kMaxFieldPath = 1000.0f;   // cm: longest 3D path the field's Runge-Kutta solves search
 
 // packed upper-triangle index of a symmetric 6x6
 __host__ __device__ constexpr int pk(int i, int j)
@@ -44,6 +45,7 @@ template <> struct Tr<float> {
     KF_HD static inline float cos_(float x) { return cosf(x); }
     KF_HD static inline float sin_(float x) { return sinf(x); }
     KF_HD static inline float floor_(float x) { return floorf(x); }
+    KF_HD static inline float min_(float a, float b) { return fminf(a, b); }
 };
 template <> struct Tr<double> {
     KF_HD static inline void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
@@ -56,6 +58,7 @@ template <> struct Tr<double> {
     KF_HD static inline double cos_(double x) { return cos(x); }
     KF_HD static inline double sin_(double x) { return sin(x); }
     KF_HD static inline double floor_(double x) { return floor(x); }
+    KF_HD static inline double min_(double a, double b) { return fmin(a, b); }
 };
 
 template <typename T>
@@ -511,7 +514,10 @@ KF_HD inline void field_at(T B0, T Z0, T x, T y, T z, T* bx, T* by, T* bz)
 // direction) with q/p = c sin(theta) conserved, n = ceil(|l| / step) equal
 // steps (backwards for l < 0: the polish step of the radius solve can end a
 // hair behind the start).  Output in the state parametrisation (x, y, z, c,
-// phi, theta).
+// phi, theta).  The position is accumulated as the displacement from the
+// start, added to the start once at the end: summed onto |z| ~ 200 cm in
+// FP32 the steps' rounding makes z(l) jump by ~2e-4 cm between neighbouring
+// l, more than the solves' tolerance.
 template <typename T>
 KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
 {
@@ -519,13 +525,24 @@ KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
     Tr<T>::sincos_(p[5], &st, &ct);
     Tr<T>::sincos_(p[4], &sp, &cp);
     const T kq = T(kKappa) * p[3] * st;
-    T y0 = p[0], y1 = p[1], y2 = p[2], t0 = st * cp, t1 = st * sp, t2 = ct;
+    const T x0 = p[0], x1 = p[1], x2 = p[2];
+    T y0 = T(0), y1 = T(0), y2 = T(0), t0 = st * cp, t1 = st * sp, t2 = ct;
     const int n = (int)ceil(double(Tr<T>::abs_(l) / step));
     const T h = n > 0 ? l / T(n) : T(0);
-    // derivative of (position, direction) at (x, t)
-    auto der = [&](T x0, T x1, T x2, T u0, T u1, T u2, T d[6]) {
+    // compensated (Kahan) sums of the steps: in FP32 the rounding of a few
+    // hundred like increments onto the position and the direction is biased
+    // enough to move z(l) by 1e-3 cm, ten times the solves' tolerance
+    T e[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    auto csum = [](T& sum, T& err, T inc) {
+        const T v = inc - err;
+        const T t = sum + v;
+        err = (t - sum) - v;
+        sum = t;
+    };
+    // derivative at the displacement (e0, e1, e2) from the start, direction u
+    auto der = [&](T e0, T e1, T e2, T u0, T u1, T u2, T d[6]) {
         T bx, by, bz;
-        field_at(B0, Z0, x0, x1, x2, &bx, &by, &bz);
+        field_at(B0, Z0, x0 + e0, x1 + e1, x2 + e2, &bx, &by, &bz);
         d[0] = u0;
         d[1] = u1;
         d[2] = u2;
@@ -544,34 +561,56 @@ KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
         der(y0 + h * c[0], y1 + h * c[1], y2 + h * c[2], t0 + h * c[3], t1 + h * c[4],
             t2 + h * c[5], d);
         const T w = h / T(6);
-        y0 += w * (a[0] + T(2) * b[0] + T(2) * c[0] + d[0]);
-        y1 += w * (a[1] + T(2) * b[1] + T(2) * c[1] + d[1]);
-        y2 += w * (a[2] + T(2) * b[2] + T(2) * c[2] + d[2]);
-        t0 += w * (a[3] + T(2) * b[3] + T(2) * c[3] + d[3]);
-        t1 += w * (a[4] + T(2) * b[4] + T(2) * c[4] + d[4]);
-        t2 += w * (a[5] + T(2) * b[5] + T(2) * c[5] + d[5]);
+        csum(y0, e[0], w * (a[0] + T(2) * b[0] + T(2) * c[0] + d[0]));
+        csum(y1, e[1], w * (a[1] + T(2) * b[1] + T(2) * c[1] + d[1]));
+        csum(y2, e[2], w * (a[2] + T(2) * b[2] + T(2) * c[2] + d[2]));
+        csum(t0, e[3], w * (a[3] + T(2) * b[3] + T(2) * c[3] + d[3]));
+        csum(t1, e[4], w * (a[4] + T(2) * b[4] + T(2) * c[4] + d[4]));
+        csum(t2, e[5], w * (a[5] + T(2) * b[5] + T(2) * c[5] + d[5]));
     }
     const T tt = Tr<T>::sqrt_(t0 * t0 + t1 * t1);
-    out[0] = y0;
-    out[1] = y1;
-    out[2] = y2;
+    out[0] = x0 + y0;
+    out[1] = x1 + y1;
+    out[2] = x2 + y2;
     out[5] = Tr<T>::atan2_(tt, t2);
     out[4] = Tr<T>::atan2_(t1, t0);
     out[3] = p[3] * st / Tr<T>::sin_(out[5]);
 }
 
 // Propagation along the 3D path l in the parametrised field whose end state q
-// (rk_path) is known: the covariance by the helix Jacobian (with ds/dp) in
-// the start point's field (kb0) over the transverse length l sin(theta0),
-// then the state becomes q.  Barrels only.
-template <typename T, typename C, typename S>
-KF_HD inline void field_transport(S p[6], C P[21], const T q[6], T l, T kb0, T r_l)
+// (rk_path) is known: the covariance by the helix Jacobian (with ds/dp for the
+// barrel or the disk at zd) over the transverse length l sin(theta0), in the
+// path's mean effective axial field, then the state becomes q.  The effective
+// field is what turns the transverse direction: Bz - cot(theta) B_T . t_T (the
+// transverse field bends a track that also moves along z), averaged by
+// Simpson's rule over the start, the chord's midpoint (with the mean
+// direction) and the end.
+template <typename T>
+KF_HD inline T effective_bz(T B0, T Z0, T x, T y, T z, T phi, T theta)
 {
-    const T sth = Tr<T>::sin_(T(p[5]));
+    T bx, by, bz, sp, cp, st, ct;
+    field_at(B0, Z0, x, y, z, &bx, &by, &bz);
+    Tr<T>::sincos_(phi, &sp, &cp);
+    Tr<T>::sincos_(theta, &st, &ct);
+    return bz - ct / st * (bx * cp + by * sp);
+}
+
+template <typename T, typename C, typename S>
+KF_HD inline void field_transport(S p[6], C P[21], const T q[6], T l, const kf_params& prm, int kind,
+                                  T zd)
+{
     T pc[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) pc[k] = T(p[k]);
-    transport(pc, P, l * sth, kb0, 0, r_l);
+    const T B0 = T(prm.bz), Z0 = T(prm.field_z0);
+    const T half = T(0.5);
+    const T b_a = effective_bz(B0, Z0, pc[0], pc[1], pc[2], pc[4], pc[5]);
+    const T b_m = effective_bz(B0, Z0, half * (pc[0] + q[0]), half * (pc[1] + q[1]),
+                               half * (pc[2] + q[2]), pc[4] + half * wrap_phi(q[4] - pc[4]),
+                               half * (pc[5] + q[5]));
+    const T b_b = effective_bz(B0, Z0, q[0], q[1], q[2], q[4], q[5]);
+    const T kb = T(kKappa) * ((b_a + T(4) * b_m + b_b) / T(6));
+    transport(pc, P, l * Tr<T>::sin_(pc[5]), kb, kind, zd);
 #pragma unroll
     for (int k = 0; k < 6; ++k) p[k] = S(q[k]);
     p[4] = wrap_phi(p[4]);
@@ -666,7 +705,9 @@ KF_HD inline int solve_barrel(const T p[6], T h, T cph, T sph, T r_l, T s_hi, co
 
 // Propagate-to-radius in the parametrised field: bracketed Newton on the 3D
 // path length l, r(l) from rk_path.  The bracket and reachability come from
-// the helix in the start point's field (kb0 = kappa Bz(start)); the start is
+// the helix in the start point's field (kb0 = kappa Bz(start)), the bracket
+// cut at kMaxFieldPath (a barrel whose straight-line path exceeds it is
+// unreachable); the start is
 // the straight line, or l_guess >= 0 with learned_it evaluations before the
 // fallback to the straight line (counted in *fallbacks).
 template <typename T>
@@ -679,10 +720,12 @@ KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T
     const T h = -kb0 * p[3];
     T s_hi;
     if (!barrel_bracket(p[0], p[1], cph, sph, h, r_l, &s_hi)) return KF_ST_UNREACHABLE;
-    const T l_top = s_hi / sth;
+    const T l_line = line_guess(p[0], p[1], cph, sph, r_l) / sth;
+    // the straight line is the shortest way to the radius
+    if (l_line > T(kMaxFieldPath)) return KF_ST_UNREACHABLE;
+    const T l_top = Tr<T>::min_(s_hi / sth, T(kMaxFieldPath));
     const T B0 = T(prm.bz), Z0 = T(prm.field_z0), step = T(prm.field_step);
     const T tol = T(prm.newton_tol);
-    const T l_line = line_guess(p[0], p[1], cph, sph, r_l) / sth;
     // bracketed Newton from l within [0, l_top] with at most max_it evaluations
     auto newton = [&](T l, int max_it) -> int {
         T lo = T(0), hi = l_top;
@@ -723,35 +766,117 @@ KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T
     return newton(l_line, prm.max_newton);
 }
 
-// Next surface in the parametrised field, where only barrels are surfaces:
-// the next barrel outward (next_barrel), reached by the Runge-Kutta radius
-// solve, crossing inside |z| <= hi within half a turn of the start point's
-// curvature.  Returns the layer with the 3D path, the end state and kb0 =
-// kappa Bz(start), or -1 (a failed solve sets NOCONV).
+// Propagate-to-z in the parametrised field: bracketed Newton on the 3D path
+// length l, z(l) from rk_path with dz/dl = cos theta(l).  Start: the straight
+// line l0 = (z_d - z) / cos theta, exact in a uniform field; the plane must
+// lie ahead (0 <= l0 <= kMaxFieldPath).  Bracket [0, min(2 l0,
+// kMaxFieldPath)]: the radial field bends theta only slightly, and a track
+// short of the plane after twice the straight path does not reach it
+// (NOCONV).  Same stopping rule as the radius solve.
+template <typename T>
+KF_HD inline int solve_disk_field(const T p[6], T z_d, const kf_params& prm, T* l_out, int* evals)
+{
+    T sth, cth;
+    Tr<T>::sincos_(p[5], &sth, &cth);
+    if (cth == T(0)) return KF_ST_UNREACHABLE;
+    const T l0 = (z_d - p[2]) / cth;
+    if (!(l0 >= T(0)) || l0 > T(kMaxFieldPath)) return KF_ST_UNREACHABLE;
+    const T sgn = cth > T(0) ? T(1) : T(-1);
+    const T B0 = T(prm.bz), Z0 = T(prm.field_z0), step = T(prm.field_step);
+    const T tol = T(prm.newton_tol);
+    T lo = T(0), hi = Tr<T>::min_(T(2) * l0, T(kMaxFieldPath)), l = l0;
+    for (int it = 1; it <= prm.max_newton; ++it) {
+        T q[6];
+        rk_path(p, l, B0, Z0, step, q);
+        const T res = sgn * (q[2] - z_d);      // > 0: past the plane
+        const T dzdl = sgn * Tr<T>::cos_(q[5]);
+        ++*evals;
+        if (res < T(0)) {
+            if (l > lo) lo = l;
+        } else {
+            if (l < hi) hi = l;
+        }
+        if (Tr<T>::abs_(res) < tol) {
+            if (dzdl > T(0)) l -= res / dzdl;
+            *l_out = l;
+            return 0;
+        }
+        T ln = l - res / dzdl;
+        if (!(dzdl > T(0)) || !(ln > lo && ln < hi)) ln = T(0.5) * (lo + hi);
+        l = ln;
+    }
+    *l_out = l;
+    return (int)KF_ST_NOCONV;
+}
+
+// Next surface in the parametrised field: whichever comes first along the 3D
+// path, the next barrel outward (next_barrel), reached by the Runge-Kutta
+// radius solve and crossed inside |z| <= hi, or a disk ahead (|dz| >
+// kDiskAheadEps in the direction of travel), reached by the Runge-Kutta z
+// solve and crossed inside its radial extent; both within half a turn of the
+// start point's curvature in the transverse plane.  Disks are taken in layer
+// order; one whose straight-line path exceeds the best path found, or whose
+// straight-line transverse path exceeds half a turn, by more than 1% + 1 cm
+// is not solved (the solved path differs from the straight one by far less).  Returns the layer with the 3D path and the end state, or
+// -1 (no surface left; a failed solve sets NOCONV).
 template <typename T>
 KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const kf_params& prm,
-                                T* l_out, T q[6], T* kb0_out, uint32_t* st, int* newton_evals)
+                                T* l_out, T q[6], uint32_t* st, int* newton_evals, int* disk_evals)
 {
-    const int bl = next_barrel(p, L, nl);
-    if (bl < 0) return -1;
+    const T B0 = T(prm.bz), Z0 = T(prm.field_z0), step = T(prm.field_step);
     T bx, by, bz0;
-    field_at(T(prm.bz), T(prm.field_z0), p[0], p[1], p[2], &bx, &by, &bz0);
+    field_at(B0, Z0, p[0], p[1], p[2], &bx, &by, &bz0);
     const T kb0 = T(kKappa) * bz0;
     const T hh = Tr<T>::abs_(kb0 * p[3]);
     const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
-    T l;
-    int fb = 0;
-    const int r = solve_barrel_field(p, T(L[bl].r_or_z), prm, kb0, T(-1), 0, &l, newton_evals, &fb);
-    if (r == (int)KF_ST_NOCONV) {
-        *st |= KF_ST_NOCONV;
-        return -1;
+    T sth, cth;
+    Tr<T>::sincos_(p[5], &sth, &cth);
+    T best = T(1e30);
+    int best_l = -1;
+    const int bl = next_barrel(p, L, nl);
+    if (bl >= 0) {
+        T l;
+        int fb = 0;
+        const int r = solve_barrel_field(p, T(L[bl].r_or_z), prm, kb0, T(-1), 0, &l, newton_evals, &fb);
+        if (r == (int)KF_ST_NOCONV) {
+            *st |= KF_ST_NOCONV;
+            return -1;
+        }
+        if (r == 0) {
+            rk_path(p, l, B0, Z0, step, q);
+            if (Tr<T>::abs_(q[2]) <= T(L[bl].hi) && l * sth <= s_max) {
+                best = l;
+                best_l = bl;
+            }
+        }
     }
-    if (r) return -1;
-    rk_path(p, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
-    if (Tr<T>::abs_(q[2]) > T(L[bl].hi) || l * Tr<T>::sin_(p[5]) > s_max) return -1;
-    *l_out = l;
-    *kb0_out = kb0;
-    return bl;
+    for (int d = 0; d < nl; ++d) {
+        if (L[d].kind != 1) continue;
+        const T dz = T(L[d].r_or_z) - p[2];
+        if (!(dz * cth > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
+        const T l_line = dz / cth;
+        if (l_line > T(1.01) * best + T(1) || l_line * sth > T(1.01) * s_max + T(1)) continue;
+        T ld;
+        ++*disk_evals;
+        const int r = solve_disk_field(p, T(L[d].r_or_z), prm, &ld, newton_evals);
+        if (r == (int)KF_ST_NOCONV) {
+            *st |= KF_ST_NOCONV;
+            return -1;
+        }
+        if (r) continue;
+        T qd[6];
+        rk_path(p, ld, B0, Z0, step, qd);
+        const T rr = Tr<T>::sqrt_(qd[0] * qd[0] + qd[1] * qd[1]);
+        if (ld * sth > s_max || rr < T(L[d].lo) || rr > T(L[d].hi)) continue;
+        if (ld < best) {
+            best = ld;
+            best_l = d;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) q[k] = qd[k];
+        }
+    }
+    if (best_l >= 0) *l_out = best;
+    return best_l;
 }
 
 // Steering: from plan entry *pos on, the first layer the candidate reaches

@@ -55,6 +55,7 @@ template <> struct Tr<Cnt> {
     static Cnt cos_(Cnt x) { ++g_sfu; return Cnt(std::cos(x.v)); }
     static Cnt sin_(Cnt x) { ++g_sfu; return Cnt(std::sin(x.v)); }
     static Cnt floor_(Cnt x) { return Cnt(std::floor(x.v)); }
+    static Cnt min_(Cnt a, Cnt b) { return Cnt(std::fmin(a.v, b.v)); }
 };
 }  // namespace kfmi
 

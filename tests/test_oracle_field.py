@@ -243,6 +243,14 @@ def test_field_propagation_to_disk(orc):
     p = np.array([0.0, 0.0, 0.0, 0.5, 0.3, 0.4])
     st, *_ = orc.propagate(cfg, 19, p, P0, noise=False)
     assert st == orc.ST_UNREACHABLE
+    # so is one more than 1000 cm of path ahead (z = 30 cm at cot(theta) =
+    # 0.02), which the uniform field's closed form still reaches
+    p = np.array([0.0, 0.0, 0.0, 0.1, 0.3, np.pi / 2 - 0.02])
+    st, *_ = orc.propagate(cfg, 10, p, P0, noise=False)
+    assert st == orc.ST_UNREACHABLE
+    assert orc.propagate(_cfg(orc, z0=0.0, geom=geom), 10, p, P0, noise=False)[0] == 0
+    p[5] = np.pi / 2 - 0.04                             # 750 cm: reached
+    assert orc.propagate(cfg, 10, p, P0, noise=False)[0] == 0
 
 
 def test_field_disk_fit_pulls(orc):
