@@ -584,13 +584,18 @@ def timed_pass(torch, ctx, fp, flags, steps, warmup):
     return wall * 1e3 / steps, phases, cnt
 
 
-def train_guess(K, torch, E):
+def train_guess(K, torch, E, workload):
     """Trains the learned start on the device: 1e6 pairs from the plain
-    propagator at the precision workload's distribution, 20 epochs of batch
-    4096, Adam 1e-3.  Returns (weights, report)."""
+    propagator at the distribution it will serve ("batch": the finding batch's
+    states at every surface paired with the next barrel outward, drawn from
+    64 events of their own; "precision": the fit throughput set's barrel
+    hops), 20 epochs of batch 4096, Adam 1e-3.  Returns (weights, report)."""
     from paper_1906_02253_amd import learned
     t0 = time.time()
-    geom, states, tl = E.propagation_pairs(n_pairs=1_000_000, seed=4)
+    if workload == "batch":
+        geom, states, tl = E.batch_propagation_pairs(n_pairs=1_000_000, seed=5)
+    else:
+        geom, states, tl = E.propagation_pairs(n_pairs=1_000_000, seed=4)
     ctx = K.Context(geom)
     ps = learned.PairSet(ctx, states, tl)
     tr, va, te = learned.split_rows(ps.ok_rows, seed=4)
@@ -607,7 +612,7 @@ def train_guess(K, torch, E):
     ok = r["plain"]["status"] == 0
     it_p, it_l = r["plain"]["iters"][ok], r["learned"]["iters"][ok]
     n_steps = losses.shape[0]
-    rep = {"pairs": int(ps.n), "train_rows": int(tr.size), "epochs": 20, "batch": 4096,
+    rep = {"workload": workload, "pairs": int(ps.n), "train_rows": int(tr.size), "epochs": 20, "batch": 4096,
            "adam_steps": int(n_steps), "train_ms": train_ms,
            "train_rows_per_s": n_steps * 4096 / (train_ms * 1e-3),
            "train_tflops": n_steps * 4096 * 3 * 2 * 4672 / (train_ms * 1e-3) / 1e12,
@@ -758,7 +763,7 @@ def main():
               f"ms, {fl['roofline']['achieved']:.0f} GB/s by the model", file=sys.stderr, flush=True)
 
     # learned start: train on the device, then the same timed pass
-    w, rep = train_guess(K, torch, E)
+    w, rep = train_guess(K, torch, E, "batch")
     ctx.mlp_load(w)
     if width < 64:
         ctx.set_find_config(64, largest_first)
@@ -800,7 +805,9 @@ def main():
     del sfp, sctx
 
     if not args.no_fit:
-        result["fit"] = run_fit(K, torch, args.fit_tracks, w)
+        w_fit, rep_fit = train_guess(K, torch, E, "precision")
+        result["fit"] = run_fit(K, torch, args.fit_tracks, w_fit)
+        result["fit"]["learned_training"] = rep_fit
         print(f"# fit: {result['fit']['fused_steps_per_s']:.3e} steps/s fused", file=sys.stderr,
               flush=True)
 

@@ -8,7 +8,8 @@ import numpy as np
 from . import geometry
 from .generate import (Event, fit_sample, precision_sample, find_events,
                        batch_events, make_event, pt_uniform, pt_power2,
-                       pt_two_values, sig_loguniform, KAPPA, propagation_pairs, mlp_init)
+                       pt_two_values, sig_loguniform, KAPPA, propagation_pairs, batch_propagation_pairs,
+                       mlp_init)
 
 
 def concat_events(events):
@@ -62,5 +63,5 @@ def find_inputs(events, min_hits=3):
 
 __all__ = ["find_inputs", "geometry", "Event", "fit_sample", "precision_sample", "find_events",
            "batch_events", "make_event", "concat_events", "pt_uniform",
-           "pt_power2", "pt_two_values", "sig_loguniform", "KAPPA", "propagation_pairs",
+           "pt_power2", "pt_two_values", "sig_loguniform", "KAPPA", "propagation_pairs", "batch_propagation_pairs",
            "mlp_init"]

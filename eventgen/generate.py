@@ -420,6 +420,39 @@ def propagation_pairs(n_pairs=1_000_000, seed=4, n_tracks=200_000):
     return geom, st[sel], tg[sel]
 
 
+def batch_propagation_pairs(n_pairs=1_000_000, seed=5, n_events=64):
+    """Starting states and target layers for learning the propagation path
+    length at the batching workload's distribution (batch_events: ten barrels
+    and 2 x 7 disks, |eta| < 2.5, pT^-2 on 0.5-50 GeV, 0.02 X0): every state
+    a track passes through (its vertex and its state after each crossing,
+    barrel or disk) paired with the next barrel outward (the smallest radius
+    above rho + 0.05 cm), the surface whose radius solve the learned start
+    begins during finding, whatever surface the track meets first; states with
+    no barrel left are dropped.  Shuffled, the first n_pairs.  Returns (geom,
+    state [n, 6] float64, target layer [n] int32)."""
+    geom, evs = batch_events(n_events=n_events, seed=seed, noise_per_track=0)
+    barrels = np.array([i for i, L in enumerate(geom) if L["kind"] == 0])
+    radii = np.array([geom[i]["r_or_z"] for i in barrels])
+    order = np.argsort(radii, kind="stable")
+    barrels, radii = barrels[order], radii[order]
+    states = []
+    for ev in evs:
+        nh = ev.n_track_hits()
+        states.append(ev.truth0)
+        for k in range(ev.truth_out.shape[1]):
+            m = nh > k
+            states.append(ev.truth_out[m, k])
+    st = np.concatenate(states)
+    rho = np.hypot(st[:, 0], st[:, 1])
+    j = np.searchsorted(radii, rho + 0.05, side="right")
+    keep = j < radii.size
+    st = st[keep]
+    tg = barrels[j[keep]].astype(np.int32)
+    rng = np.random.default_rng(seed + 1000)
+    sel = rng.permutation(st.shape[0])[:n_pairs]
+    return geom, st[sel], tg[sel]
+
+
 def mlp_init(seed=4, n_in=8, n_hidden=64):
     """Initial network parameters, flat float32 in the order W1[64][8], b1,
     W2[64][64], b2, w3[64], b3: weights uniform in +-sqrt(6 / (fan_in +

@@ -311,6 +311,19 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
             if (want) s_init = T(mlp_guess(f, y));
         }
         if (!alive) continue;
+        // the step's hit is read before the propagation, so that its two
+        // dependent loads (index, then coordinates) overlap the state's loads
+        // and the transport instead of following them
+        const int32_t hi = a.hit_idx[(int64_t)k * ld + i];
+        const bool has_hit = hi >= 0 && hi < a.n_hits;
+        float hx = 0.f, hy = 0.f, hz = 0.f, hsu = 0.f, hsv = 0.f;
+        if (has_hit) {
+            hx = a.hx[hi];
+            hy = a.hy[hi];
+            hz = a.hz[hi];
+            hsu = a.hsu[hi];
+            hsv = a.hsv[hi];
+        }
         int ev = 0, fb = 0;
         int r = propagate_to<T, C, U, FIELD, MAT>(p, P, L, a.prm, a.material != 0, a.mat, s_init,
                                                    (T*)nullptr, &ev, &fb);
@@ -321,14 +334,13 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
             alive = false;
             continue;
         }
-        const int32_t hi = a.hit_idx[(int64_t)k * ld + i];
         if (hi >= a.n_hits) {
             st |= KF_ST_BADINPUT;
             alive = false;
             continue;
         }
-        if (hi >= 0) {
-            HitFrame<U> f = hit_frame<U>(a.hx[hi], a.hy[hi], a.hz[hi], a.hsu[hi], a.hsv[hi]);
+        if (has_hit) {
+            HitFrame<U> f = hit_frame<U>(hx, hy, hz, hsu, hsv);
             U c2 = U(0);
             r = kf_update<U, C, U>(p, P, f, L.kind, &c2);
             if (r) {
