@@ -236,14 +236,23 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(int64_t n_hits, const 
     }
 }
 
-// Level 2: one workgroup per segment sorts its records by bin.
+// Level 2: one workgroup per segment sorts its records by bin.  The bin
+// counts are histogrammed and scanned in LDS; then every record's place is
+// drawn from its bin's counter and, for segments of up to kBinSrcCap records,
+// kept as the inverse permutation in LDS, so that the records are written in
+// output order (full lines, one read gathered from the segment's own recent
+// records each) instead of scattered 32-byte writes that leave their lines
+// partly written when the L2 evicts them.  Larger segments scatter directly.
 constexpr int kBinThreads = 1024;
+constexpr int kBinSrcCap = 12288;
 __global__ __launch_bounds__(kBinThreads) void bin_segment_kernel(
     const int32_t* __restrict__ seg_off, const BinnedHit* __restrict__ seg_rec,
     const int32_t* __restrict__ seg_bin, const kf_layer* __restrict__ layers, int n_layers,
-    int n_seg, BinLayout bl, int32_t* __restrict__ bin_off, BinnedHit* __restrict__ out)
+    int n_seg, int nb_max, BinLayout bl, int32_t* __restrict__ bin_off, BinnedHit* __restrict__ out)
 {
-    __shared__ int hist[kMaxLayerBins];
+    extern __shared__ int bin_smem[];
+    int* hist = bin_smem;                 // [nb_max]
+    int* src = bin_smem + nb_max;         // [kBinSrcCap]
     __shared__ int lds[kBinThreads / 64];
     const int seg = blockIdx.x;
     const int e = seg / n_layers, l = seg - e * n_layers;
@@ -272,7 +281,13 @@ __global__ __launch_bounds__(kBinThreads) void bin_segment_kernel(
         }
     if (seg == n_seg - 1 && t == 0) bin_off[(int64_t)(e + 1) * bl.per_event] = hi;
     __syncthreads();
-    for (int i = lo + t; i < hi; i += kBinThreads) out[atomicAdd(&hist[seg_bin[i]], 1)] = seg_rec[i];
+    if (hi - lo <= kBinSrcCap) {
+        for (int i = lo + t; i < hi; i += kBinThreads) src[atomicAdd(&hist[seg_bin[i]], 1) - lo] = i;
+        __syncthreads();
+        for (int j = t; j < hi - lo; j += kBinThreads) out[lo + j] = seg_rec[src[j]];
+    } else {
+        for (int i = lo + t; i < hi; i += kBinThreads) out[atomicAdd(&hist[seg_bin[i]], 1)] = seg_rec[i];
+    }
 }
 
 // ------------------------------------------------------------------ prefix sums
@@ -1333,8 +1348,15 @@ hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event
                                                   pl.seg_bin);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    bin_segment_kernel<<<(unsigned)n_seg, kBinThreads, 0, s>>>(
-        pl.seg_off, (const BinnedHit*)pl.seg_rec, pl.seg_bin, d_layers, n_layers, (int)n_seg,
+    // the largest layer's bin count, from the layout's per-layer bases
+    int nb_max = 1;
+    for (int l = 0; l < n_layers; ++l) {
+        const int nb = (l + 1 < n_layers ? pl.bl.base[l + 1] : pl.bl.per_event) - pl.bl.base[l];
+        if (nb > nb_max) nb_max = nb;
+    }
+    const size_t lds = sizeof(int) * ((size_t)nb_max + kBinSrcCap);
+    bin_segment_kernel<<<(unsigned)n_seg, kBinThreads, lds, s>>>(
+        pl.seg_off, (const BinnedHit*)pl.seg_rec, pl.seg_bin, d_layers, n_layers, (int)n_seg, nb_max,
         pl.bl, pl.off, (BinnedHit*)pl.binned);
     return hipGetLastError();
 }
