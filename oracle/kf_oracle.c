@@ -1116,9 +1116,75 @@ static int navigate(const orc_cfg* cfg, const double p[6], int* stat, int* close
  * are passed over.  Returns the layer (and sets *pos past it) or -1 when the
  * plan is exhausted; a failed barrel solve sets NOCONV and returns -1.
  */
+/*
+ * Steering in the parametrised field: the same rule along the 3D path, each
+ * plan entry reached by its Runge-Kutta solve (radius or z) as in
+ * navigate_field, half a turn taken at the start point's curvature; a disk
+ * whose straight-line transverse path exceeds half a turn by more than 1% +
+ * 1 cm is not solved.
+ */
+static int steer_field(const orc_cfg* cfg, const orc_region* R, int* pos, const double p[6],
+                       int* stat, int* close)
+{
+    double rho = hypot(p[0], p[1]);
+    double x0[3] = {p[0], p[1], p[2]}, B0[3];
+    orc_field(cfg, x0, B0);
+    double h0 = -KAPPA * B0[2] * p[3];
+    double s_max = h0 != 0.0 ? PI / fabs(h0) : INFINITY;
+    double st = sin(p[5]), ct = cos(p[5]);
+    for (; *pos < R->n; ++*pos) {
+        int l = R->layers[*pos];
+        const orc_layer* L = &cfg->layers[l];
+        double q[6];
+        if (L->kind == 0) {
+            if (fabs(L->r_or_z - (rho + NEXT_BARREL_EPS)) < CLOSE_REL * NEXT_BARREL_EPS) *close = 1;
+            if (!(L->r_or_z > rho + NEXT_BARREL_EPS)) continue;
+            if (h0 != 0.0) {
+                double cx = p[0] - sin(p[4]) / h0, cy = p[1] + cos(p[4]) / h0;
+                double rmax = hypot(cx, cy) + 1.0 / fabs(h0);
+                if (fabs(rmax - L->r_or_z) < CLOSE_REL * L->r_or_z) *close = 1;
+            }
+            double ll;
+            int r = solve_barrel_field(cfg, p, L->r_or_z, -1.0, &ll, NULL);
+            if (r == ORC_ST_NOCONV) {
+                *stat |= ORC_ST_NOCONV;
+                return -1;
+            }
+            if (r != ORC_ST_OK) continue;
+            orc_rk_path(cfg, p, ll, q);
+            double s = ll * st;
+            if (fabs(fabs(q[2]) - L->hi) < CLOSE_REL * L->hi) *close = 1;
+            if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+            if (fabs(q[2]) > L->hi || s > s_max) continue;
+        } else {
+            double dz = L->r_or_z - p[2];
+            if (fabs(fabs(dz) - DISK_AHEAD_EPS) < CLOSE_REL * DISK_AHEAD_EPS) *close = 1;
+            if (!(dz * ct > 0.0) || fabs(dz) <= DISK_AHEAD_EPS) continue;
+            if (dz / ct * st > 1.01 * s_max + 1.0) continue;
+            double ld;
+            int r = solve_disk_field(cfg, p, L->r_or_z, -1.0, &ld, NULL);
+            if (r == ORC_ST_NOCONV) {
+                *stat |= ORC_ST_NOCONV;
+                return -1;
+            }
+            if (r != ORC_ST_OK) continue;
+            orc_rk_path(cfg, p, ld, q);
+            double rr = hypot(q[0], q[1]);
+            double s = ld * st;
+            if (fabs(s - s_max) < CLOSE_REL * s_max) *close = 1;
+            if (fabs(rr - L->lo) < CLOSE_REL * L->lo || fabs(rr - L->hi) < CLOSE_REL * L->hi) *close = 1;
+            if (s > s_max || rr < L->lo || rr > L->hi) continue;
+        }
+        ++*pos;
+        return l;
+    }
+    return -1;
+}
+
 static int steer(const orc_cfg* cfg, const orc_region* R, int* pos, const double p[6], int* stat,
                  int* close)
 {
+    if (cfg->field_z0 > 0.0) return steer_field(cfg, R, pos, p, stat, close);
     double rho = hypot(p[0], p[1]);
     double hh = fabs(KAPPA * cfg->bz * p[3]);
     double s_max = hh > 0.0 ? PI / hh : INFINITY;

@@ -85,3 +85,41 @@ def test_five_region_plans_keep_efficiency(orc):
     same = (dyn["hits"] == st["hits"]).all(axis=1).mean()
     print(f"identical hit lists: {same:.3f}")
     assert same > 0.8
+
+
+def test_field_steering_uniform_limit(orc):
+    """Steering in the parametrised field with Z0 = 1e9 cm (Runge-Kutta solves
+    of the plan's barrels and disks) reproduces the closed-form helix
+    steering on uniform-field barrel + endcap events hit for hit."""
+    rng = np.random.default_rng(34)
+    geom = E.geometry.barrel10_disks14(x0=0.0)
+    evs = [E.make_event(rng, geom, 300, E.pt_power2(0.5, 50.0), 2.5, 1000) for _ in range(2)]
+    inp = E.find_inputs(evs)
+    plans = E.geometry.steering_plans(geom)
+    u = _find(orc, geom, evs, inp, steering=plans)
+    f = _find(orc, geom, evs, inp, steering=plans, field_z0=1e9, field_step=0.5)
+    kinds = np.array([L["kind"] for L in geom])
+    assert (u["hits"][:, kinds == 1] >= 0).sum() > 500
+    same = (u["hits"] == f["hits"]).all(axis=1)
+    print(f"identical: {same.mean():.4f}")
+    assert same.mean() > 0.995
+    ok = same & (u["status"] == 0)
+    assert CM.par_error(f["par"][ok], u["par"][ok]).max() < 1e-8
+
+
+def test_field_steering_keeps_efficiency(orc):
+    """Tracks traced through the field over barrels and disks: finding that
+    follows the five-region plans in the field recovers about as many true
+    hits as the field's dynamic navigation, and most hit lists agree."""
+    import eventgen.field as EF
+    geom, evs = EF.field_disk_events(n_events=2, n_tracks=400, n_noise=24_000, seed=32)
+    inp = E.find_inputs(evs)
+    kw = dict(field_z0=300.0, field_step=2.0)
+    dyn = _find(orc, geom, evs, inp, **kw)
+    st = _find(orc, geom, evs, inp, steering=E.geometry.steering_plans(geom), **kw)
+    e_dyn, e_st = _efficiency(evs, inp, dyn), _efficiency(evs, inp, st)
+    same = (dyn["hits"] == st["hits"]).all(axis=1).mean()
+    print(f"field: hit efficiency dynamic {e_dyn:.4f}, plans {e_st:.4f}; identical {same:.3f}")
+    assert e_dyn > 0.95
+    assert e_st > e_dyn - 0.02
+    assert same > 0.8
