@@ -109,9 +109,10 @@ typedef struct {
                               kf_find; barrels by a Newton iteration on the integrated radius,
                               disks on the integrated z, each over at most 1000 cm of path (a
                               surface further along the track is UNREACHABLE); the covariance by
-                              the helix Jacobian in
-                              the path's mean effective axial field Bz - cot(theta) B_T.t_T;
-                              finding in this field takes neither KF_INIT_MLP nor steering) */
+                              the helix Jacobian in the path's mean effective axial field
+                              Bz - cot(theta) B_T.t_T; in finding, steering and the learned start
+                              work as in the uniform field, their surfaces reached by these solves
+                              along the 3D path) */
     double field_step;     /* largest Runge-Kutta step [cm] in the parametrised field (> 0) */
     double clean_deta;     /* seed cleaning: |d eta| below which two seeds may be duplicates,
                               0 .. 0.09375 (the width of a seed cell in eta) */
@@ -186,8 +187,9 @@ typedef struct {
  * disk ahead (|dz| > 0.05 cm) crossed within half a turn inside its radial
  * extent - passing over entries it does not reach.  Without steering the
  * next surface is found dynamically (the first reached of the next barrel
- * outward and the next disk ahead).  Steering excludes KF_INIT_MLP and the
- * parametrised field.
+ * outward and the next disk ahead).  Steering excludes KF_INIT_MLP; in the
+ * parametrised field the plan's surfaces are reached by the Runge-Kutta radius
+ * and z solves along the 3D path (half a turn at the start point's curvature).
  * Synchronous; do not call while work that uses the context is in flight. */
 int kf_set_steering(kf_ctx* ctx, const kf_region* regions, int32_t n_regions);
 

@@ -128,10 +128,6 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     if (learn && !ctx->mlp_loaded) return fail(ctx, KF_EUNSUPPORTED, "%s: no learned model loaded", what);
     if (learn && ctx->d_steer)
         return fail(ctx, KF_EUNSUPPORTED, "%s: steering and the learned guess exclude each other", what);
-    if (field && (learn || ctx->d_steer))
-        return fail(ctx, KF_EUNSUPPORTED,
-                    "%s: finding in the parametrised field takes neither the learned guess nor steering",
-                    what);
     if (learn && ctx->find_width < 64)
         return fail(ctx, KF_EUNSUPPORTED, "%s: the learned guess needs a width of at least 64", what);
     if (out->n != seeds->n) return fail(ctx, KF_EINVAL, "%s: out->n must equal seeds->n", what);

@@ -783,9 +783,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                 int layer;
                 T fl = T(0);
                 T fq[6];
-                if constexpr (FIELD)
+                if constexpr (FIELD && STEER)
+                    layer = steer_next_field(p, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
+                                             a.prm, &fl, fq, &status, &n_newton, &n_disk);
+                else if constexpr (FIELD)
                     layer = navigate_field(p, sh.layers, nl, a.prm, &fl, fq, &status, &n_newton,
-                                           &n_disk);
+                                           &n_disk, s_guess >= T(0) ? s_guess / Tr<T>::sin_(p[5]) : T(-1),
+                                           LEARN ? a.prm.mlp_max_iter : 0, &n_fallback);
                 else if constexpr (STEER)
                     layer = steer_next(p, sh.layers, a.steer->layers[rg], a.steer->len[rg], &pos,
                                        a.prm, kb, &s, &status, &n_newton, &n_disk);
@@ -1274,19 +1278,23 @@ size_t find_shared_size(int W, int S, int nl, int prec)
     return find_shared_bytes(W, S, nl, prec == KF_PREC_FP32 ? sizeof(float) : sizeof(double));
 }
 
-// Instantiations: (precision) x (plain, learned, steered, parametrised field)
-// x (material map); learned, steered and field exclude each other.
+// Instantiations: (precision) x (plain, learned, steered; each also in the
+// parametrised field) x (material map); learned and steered exclude each other.
 template <typename T, typename C, typename U, bool LEARN, bool MAT>
 static hipError_t find_occ2(bool steer, bool field, int W, size_t lds, int* out)
 {
-    if constexpr (!LEARN) {
-        if (field)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                out, find_kernel<T, C, U, false, MAT, false, true>, W, lds);
+    if (field) {
+        if constexpr (!LEARN)
+            if (steer)
+                return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    out, find_kernel<T, C, U, false, MAT, true, true>, W, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, MAT, false, true>,
+                                                            W, lds);
+    }
+    if constexpr (!LEARN)
         if (steer)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 out, find_kernel<T, C, U, false, MAT, true, false>, W, lds);
-    }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, find_kernel<T, C, U, LEARN, MAT, false, false>,
                                                         W, lds);
 }
@@ -1734,16 +1742,20 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
 template <typename T, typename C, typename U, bool LEARN, bool MAT>
 static void find_launch2(const FindArgs& a, int W, int grid, size_t lds, hipStream_t s)
 {
-    if constexpr (!LEARN) {
-        if (a.prm.field_z0 > 0.0) {
-            find_kernel<T, C, U, false, MAT, false, true><<<grid, W, lds, s>>>(a);
-            return;
-        }
+    if (a.prm.field_z0 > 0.0) {
+        if constexpr (!LEARN)
+            if (a.steer) {
+                find_kernel<T, C, U, false, MAT, true, true><<<grid, W, lds, s>>>(a);
+                return;
+            }
+        find_kernel<T, C, U, LEARN, MAT, false, true><<<grid, W, lds, s>>>(a);
+        return;
+    }
+    if constexpr (!LEARN)
         if (a.steer) {
             find_kernel<T, C, U, false, MAT, true, false><<<grid, W, lds, s>>>(a);
             return;
         }
-    }
     find_kernel<T, C, U, LEARN, MAT, false, false><<<grid, W, lds, s>>>(a);
 }
 

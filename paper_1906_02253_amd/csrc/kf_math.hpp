@@ -818,10 +818,13 @@ KF_HD inline int solve_disk_field(const T p[6], T z_d, const kf_params& prm, T* 
 // order; one whose straight-line path exceeds the best path found, or whose
 // straight-line transverse path exceeds half a turn, by more than 1% + 1 cm
 // is not solved (the solved path differs from the straight one by far less).  Returns the layer with the 3D path and the end state, or
-// -1 (no surface left; a failed solve sets NOCONV).
+// -1 (no surface left; a failed solve sets NOCONV).  l_guess >= 0: the
+// learned start of the barrel solve (3D path), with learned_it evaluations
+// before the fallback (counted in *fallbacks).
 template <typename T>
 KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const kf_params& prm,
-                                T* l_out, T q[6], uint32_t* st, int* newton_evals, int* disk_evals)
+                                T* l_out, T q[6], uint32_t* st, int* newton_evals, int* disk_evals,
+                                T l_guess = T(-1), int learned_it = 0, int* fallbacks = nullptr)
 {
     const T B0 = T(prm.bz), Z0 = T(prm.field_z0), step = T(prm.field_step);
     T bx, by, bz0;
@@ -837,7 +840,9 @@ KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const k
     if (bl >= 0) {
         T l;
         int fb = 0;
-        const int r = solve_barrel_field(p, T(L[bl].r_or_z), prm, kb0, T(-1), 0, &l, newton_evals, &fb);
+        const int r = solve_barrel_field(p, T(L[bl].r_or_z), prm, kb0, l_guess, learned_it, &l,
+                                         newton_evals, &fb);
+        if (fallbacks) *fallbacks += fb;
         if (r == (int)KF_ST_NOCONV) {
             *st |= KF_ST_NOCONV;
             return -1;
@@ -877,6 +882,67 @@ KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const k
     }
     if (best_l >= 0) *l_out = best;
     return best_l;
+}
+
+// Steering in the parametrised field: as steer_next, each plan entry reached
+// by its Runge-Kutta solve along the 3D path (as in navigate_field), half a
+// turn taken at the start point's curvature; a disk whose straight-line
+// transverse path exceeds half a turn by more than 1% + 1 cm is not solved.
+// Returns the layer with the 3D path and the end state, or -1 when the plan
+// is exhausted (a failed solve sets NOCONV and returns -1).
+template <typename T>
+KF_HD inline int steer_next_field(const T p[6], const kf_layer* L, const uint8_t* plan, int n_plan,
+                                  int* pos, const kf_params& prm, T* l_out, T q[6], uint32_t* st,
+                                  int* newton_evals, int* disk_evals)
+{
+    const T B0 = T(prm.bz), Z0 = T(prm.field_z0), step = T(prm.field_step);
+    T bx, by, bz0;
+    field_at(B0, Z0, p[0], p[1], p[2], &bx, &by, &bz0);
+    const T kb0 = T(kKappa) * bz0;
+    const T hh = Tr<T>::abs_(kb0 * p[3]);
+    const T s_max = hh > T(0) ? T(kPi) / hh : T(1e30);
+    const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
+    T sth, cth;
+    Tr<T>::sincos_(p[5], &sth, &cth);
+    for (int qi = *pos; qi < n_plan; ++qi) {
+        const int l = plan[qi];
+        const kf_layer& Ly = L[l];
+        T ll;
+        if (Ly.kind == 0) {
+            const T r_l = T(Ly.r_or_z);
+            if (!(r_l > rho + T(kNextBarrelEps))) continue;
+            int fb = 0;
+            const int r = solve_barrel_field(p, r_l, prm, kb0, T(-1), 0, &ll, newton_evals, &fb);
+            if (r == (int)KF_ST_NOCONV) {
+                *st |= KF_ST_NOCONV;
+                *pos = qi + 1;
+                return -1;
+            }
+            if (r) continue;
+            rk_path(p, ll, B0, Z0, step, q);
+            if (Tr<T>::abs_(q[2]) > T(Ly.hi) || ll * sth > s_max) continue;
+        } else {
+            const T dz = T(Ly.r_or_z) - p[2];
+            if (!(dz * cth > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
+            if (dz / cth * sth > T(1.01) * s_max + T(1)) continue;
+            ++*disk_evals;
+            const int r = solve_disk_field(p, T(Ly.r_or_z), prm, &ll, newton_evals);
+            if (r == (int)KF_ST_NOCONV) {
+                *st |= KF_ST_NOCONV;
+                *pos = qi + 1;
+                return -1;
+            }
+            if (r) continue;
+            rk_path(p, ll, B0, Z0, step, q);
+            const T rr = Tr<T>::sqrt_(q[0] * q[0] + q[1] * q[1]);
+            if (ll * sth > s_max || rr < T(Ly.lo) || rr > T(Ly.hi)) continue;
+        }
+        *l_out = ll;
+        *pos = qi + 1;
+        return l;
+    }
+    *pos = n_plan;
+    return -1;
 }
 
 // Steering: from plan entry *pos on, the first layer the candidate reaches

@@ -504,23 +504,94 @@ def test_field_find_with_material_map(K, orc):
             orc, geom, evs, inp, s, field_z0=Z0, field_step=STEP, material_map=mat))
 
 
-def test_field_find_refusals(K):
-    """Finding in the parametrised field takes neither the learned guess nor
-    steering."""
+def _steer_check(K, orc, geom, evs, inp, ctx, label, **cfg_kw):
+    """Steered finding (eager, then the captured graph) against the oracle's
+    steered finder with the same field; counters checked on the eager pass."""
     import torch
-    geom, evs = E.find_events(n_events=1, n_tracks=50, n_noise=0, seed=1)
+    plans = E.geometry.steering_plans(geom)
+    ctx.set_steering(plans)
+    fp = K.pipeline.FindProblem(ctx, inp)
+    o = CM.oracle_find_events(orc, geom, evs, inp, steering=plans, **cfg_kw)
+    for batched in (False, True):
+        if batched:
+            fp.run_batched()
+        else:
+            fp.run()
+        torch.cuda.synchronize()
+        g = fp.results()
+        n_same, n_exc, bad = CM.compare_find(g, o)
+        ns = g["hits"].shape[0]
+        print(f"{label} ({'graph' if batched else 'eager'}): {n_same}/{ns} identical, {n_exc} excused, "
+              f"{bad.size} unexplained")
+        assert bad.size == 0
+        same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+        assert same.mean() > 0.98
+        assert n_exc <= CM.MAX_EXCUSED_FRAC * max(ns, 1000)
+        CM.check_find_params(g, o, label, lambda s: CM.oracle_sensitivity(
+            orc, geom, evs, inp, s, steering=plans, **cfg_kw))
+        if not batched:
+            assert abs(int(g["counters"][0]) - o["n_prop"]) <= 0.01 * o["n_prop"]
+    return o
+
+
+def test_field_find_steered_matches_oracle(K, orc):
+    """Steering in the parametrised field (the five-region plans, each entry
+    reached by its Runge-Kutta radius or z solve) on field-traced barrel +
+    endcap events against the FP64 oracle's steered finder in the same field,
+    eager and as the captured graph."""
+    geom, evs = EF.field_disk_events(n_events=2, n_tracks=400, n_noise=24_000, seed=32)
+    inp = E.find_inputs(evs)
+    o = _steer_check(K, orc, geom, evs, inp, _ctx(K, geom), "field steered",
+                     field_z0=Z0, field_step=STEP)
+    kinds = np.array([L["kind"] for L in geom])
+    assert (o["hits"][:, kinds == 1] >= 0).sum() > 1000
+
+
+def test_field_find_steered_uniform_limit(K, orc):
+    """The kernel's steered field path with Z0 = 1e9 cm against the oracle's
+    closed-form helix steering on uniform-field barrel + endcap events."""
+    rng = np.random.default_rng(34)
+    geom = E.geometry.barrel10_disks14(x0=0.0)
+    evs = [E.make_event(rng, geom, 300, E.pt_power2(0.5, 50.0), 2.5, 1000) for _ in range(2)]
+    inp = E.find_inputs(evs)
+    _steer_check(K, orc, geom, evs, inp, K.Context(geom, field_z0=1e9, field_step=0.5),
+                 "field steered, uniform limit")
+
+
+def test_field_find_learned_matches_oracle(K, orc, trained_field):
+    """Finding in the field with the learned start of the barrel solves (the
+    network trained on the field's propagations) on field-traced barrel +
+    endcap events: the hit lists and states of the plain finder, against the
+    FP64 oracle, eager and as the captured graph; the guesses are taken."""
+    import torch
+    geom, evs = EF.field_disk_events(n_events=2, n_tracks=400, n_noise=24_000, seed=32)
+    inp = E.find_inputs(evs)
     ctx = _ctx(K, geom)
-    ctx.set_steering([dict(eta_lo=-10.0, eta_hi=10.0, layers=list(range(10)))])
-    p = K.pipeline.FindProblem(ctx, E.find_inputs(evs))
-    p.seed_fit()
-    with pytest.raises(K.KFError, match="parametrised field"):
-        p.find()
-    ctx.set_steering(None)
-    ctx.mlp_load(E.mlp_init(1))
-    with pytest.raises(K.KFError, match="parametrised field"):
-        p.find(K.INIT_MLP)
-    p.find()
-    torch.cuda.synchronize()
+    ctx.set_find_config(64, False)
+    ctx.mlp_load(trained_field["ctx"].mlp_get())
+    fp = K.pipeline.FindProblem(ctx, inp)
+    o = CM.oracle_find_events(orc, geom, evs, inp, field_z0=Z0, field_step=STEP)
+    for batched in (False, True):
+        c0 = fp.counters.clone()
+        if batched:
+            fp.run_batched(K.INIT_MLP)
+        else:
+            fp.run(K.INIT_MLP)
+        torch.cuda.synchronize()
+        g = fp.results()
+        g["status"] = g["status"] & ~K.ST_FALLBACK
+        cnt = (fp.counters - c0).cpu().numpy()
+        n_same, n_exc, bad = CM.compare_find(g, o)
+        ns = g["hits"].shape[0]
+        print(f"field learned ({'graph' if batched else 'eager'}): {n_same}/{ns} identical, {n_exc} excused; "
+              f"guesses {cnt[5]}, fallbacks {cnt[6]}, RK evaluations per propagation {cnt[3] / cnt[0]:.3f}")
+        assert bad.size == 0
+        same = (g["hits"] == o["hits"]).all(axis=1) & (o["status"] == 0) & (g["status"] == 0)
+        assert same.mean() > 0.98
+        assert n_exc <= CM.MAX_EXCUSED_FRAC * max(ns, 1000)
+        CM.check_find_params(g, o, "field learned", lambda s: CM.oracle_sensitivity(
+            orc, geom, evs, inp, s, field_z0=Z0, field_step=STEP))
+        assert cnt[5] > 0.5 * cnt[0]
 
 
 def test_field_bad_params_rejected(K, sample):
