@@ -446,63 +446,82 @@ __device__ inline int cost_class(float c)
     return a > 1.0f / 0.6f ? 0 : (a > 1.0f ? 1 : 2);   // pT < 0.6, < 1 GeV, the rest
 }
 
-// One workgroup of 1024 lanes per queue range [q chunk, (q + 1) chunk) of
-// the cell order; chunk is a whole number of tiles.
-__global__ __launch_bounds__(1024) void cost_order_kernel(int64_t n, int64_t ld,
-                                                          const float* __restrict__ par,
-                                                          const int32_t* __restrict__ order,
-                                                          int64_t chunk, int32_t* __restrict__ out)
+// Two passes over blocks of kCostBlock entries of each queue range [q chunk,
+// (q + 1) chunk) of the cell order (chunk is a whole number of tiles): the
+// blocks' class counts, then each block places its entries at the class's
+// base in the range plus the class's entries in earlier blocks, lanes and
+// waves (a stable partition).
+constexpr int kCostBlock = 1024;
+
+__device__ inline void cost_block_range(int64_t n, int64_t chunk, int nbq, int64_t* lo, int64_t* hi)
 {
-    __shared__ int wtot[16][kCostClasses];   // per wave and class: entries of the batch
-    __shared__ int run[kCostClasses];        // per class: entries placed so far
-    __shared__ int cbase[kCostClasses];      // per class: first position in the range
-    const int64_t lo = (int64_t)blockIdx.x * chunk;
-    const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    if (lo >= hi) return;
-    const int t = threadIdx.x, wave = t >> 6, ln = t & 63;
-    // class totals of the range
-    int cnt[kCostClasses] = {0, 0, 0};
-    for (int64_t i = lo + t; i < hi; i += 1024) ++cnt[cost_class(par[3 * ld + order[i]])];
-    if (t < kCostClasses) run[t] = 0;
+    const int q = blockIdx.x / nbq, b = blockIdx.x - q * nbq;
+    const int64_t qhi = (int64_t)(q + 1) * chunk < n ? (int64_t)(q + 1) * chunk : n;
+    *lo = (int64_t)q * chunk + (int64_t)b * kCostBlock;
+    *hi = *lo + kCostBlock < qhi ? *lo + kCostBlock : qhi;
+}
+
+__global__ __launch_bounds__(kCostBlock) void cost_count_kernel(int64_t n, int64_t ld,
+                                                                const float* __restrict__ par,
+                                                                const int32_t* __restrict__ order,
+                                                                int64_t chunk, int nbq,
+                                                                int32_t* __restrict__ cnt)
+{
+    __shared__ int tot[kCostClasses];
+    int64_t lo, hi;
+    cost_block_range(n, chunk, nbq, &lo, &hi);
+    const int t = threadIdx.x;
+    if (t < kCostClasses) tot[t] = 0;
     __syncthreads();
-    for (int k = 0; k < kCostClasses; ++k)
-        if (cnt[k]) atomicAdd(&run[k], cnt[k]);
-    __syncthreads();
-    if (t == 0) {
-        int b = 0;
-        for (int k = 0; k < kCostClasses; ++k) {
-            cbase[k] = b;
-            b += run[k];
-            run[k] = 0;
-        }
+    const int64_t i = lo + t;
+    const int k = i < hi ? cost_class(par[3 * ld + order[i]]) : -1;
+    for (int c = 0; c < kCostClasses; ++c) {
+        const unsigned long long m = __ballot(k == c);
+        if ((t & 63) == 0 && m) atomicAdd(&tot[c], __popcll(m));
     }
     __syncthreads();
-    // stable placement, 1024 entries per batch: position = class base + entries
-    // of the class in earlier batches + earlier waves + earlier lanes
-    for (int64_t b0 = lo; b0 < hi; b0 += 1024) {
-        const int64_t i = b0 + t;
-        const int k = i < hi ? cost_class(par[3 * ld + order[i]]) : -1;
-        int below = 0;
-        for (int c = 0; c < kCostClasses; ++c) {
-            const unsigned long long m = __ballot(k == c);
-            if (ln == 0) wtot[wave][c] = __popcll(m);
-            if (k == c)
-                below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (t < kCostClasses) cnt[(size_t)blockIdx.x * kCostClasses + t] = tot[t];
+}
+
+__global__ __launch_bounds__(kCostBlock) void cost_place_kernel(int64_t n, int64_t ld,
+                                                                const float* __restrict__ par,
+                                                                const int32_t* __restrict__ order,
+                                                                int64_t chunk, int nbq,
+                                                                const int32_t* __restrict__ cnt,
+                                                                int32_t* __restrict__ out)
+{
+    __shared__ int wtot[kCostBlock / 64][kCostClasses];   // per wave and class
+    __shared__ int base[kCostClasses];                      // class base of this block in the range
+    int64_t lo, hi;
+    cost_block_range(n, chunk, nbq, &lo, &hi);
+    if (lo >= hi) return;
+    const int q = blockIdx.x / nbq, b = blockIdx.x - q * nbq;
+    const int t = threadIdx.x, wave = t >> 6, ln = t & 63;
+    if (t < kCostClasses) {
+        // entries of the range in the costlier classes, then this class's in earlier blocks
+        int before = 0, costlier = 0;
+        for (int bb = 0; bb < nbq; ++bb) {
+            const int32_t* c = cnt + ((size_t)q * nbq + bb) * kCostClasses;
+            for (int k = 0; k < t; ++k) costlier += c[k];
+            if (bb < b) before += c[t];
         }
-        __syncthreads();
-        if (k >= 0) {
-            int pos = cbase[k] + run[k] + below;
-            for (int w = 0; w < wave; ++w) pos += wtot[w][k];
-            out[lo + pos] = order[i];
-        }
-        __syncthreads();
-        if (t < kCostClasses) {
-            int sum = 0;
-            for (int w = 0; w < 16; ++w) sum += wtot[w][t];
-            run[t] += sum;
-        }
-        __syncthreads();
+        base[t] = costlier + before;
+    }
+    const int64_t i = lo + t;
+    const int k = i < hi ? cost_class(par[3 * ld + order[i]]) : -1;
+    int below = 0;
+    for (int c = 0; c < kCostClasses; ++c) {
+        const unsigned long long m = __ballot(k == c);
+        if (ln == 0) wtot[wave][c] = __popcll(m);
+        if (k == c)
+            below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    }
+    __syncthreads();
+    if (k >= 0) {
+        int pos = base[k] + below;
+        for (int w = 0; w < wave; ++w) pos += wtot[w][k];
+        out[(int64_t)q * chunk + pos] = order[i];
     }
 }
 
@@ -1374,8 +1393,11 @@ hipError_t launch_cost_order(const FindPlan& pl, const kf_tracks* seeds, int n_t
 {
     if (seeds->n == 0) return hipSuccess;
     const int64_t chunk = (int64_t)((n_tiles + kQueues - 1) / kQueues) * seeds_per_tile;
-    cost_order_kernel<<<kQueues, 1024, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
-                                                pl.order, chunk, pl.tile_order);
+    const int nbq = (int)((chunk + kCostBlock - 1) / kCostBlock);
+    cost_count_kernel<<<kQueues * nbq, kCostBlock, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
+                                                          pl.order, chunk, nbq, pl.cost_cnt);
+    cost_place_kernel<<<kQueues * nbq, kCostBlock, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
+                                                          pl.order, chunk, nbq, pl.cost_cnt, pl.tile_order);
     return hipGetLastError();
 }
 
@@ -1727,6 +1749,14 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
     pl->cell = (int32_t*)take(sizeof(int32_t) * ns);
     pl->order = (int32_t*)take(sizeof(int32_t) * ns);
     pl->tile_order = (int32_t*)take(sizeof(int32_t) * ns);
+    {
+        // class counts per block of the cost order, blocks as launch_cost_order makes them
+        const int64_t S = seeds_per_tile > 0 ? seeds_per_tile : 1;
+        const int64_t n_tiles = (ns + S - 1) / S;
+        const int64_t chunk = (n_tiles + kQueues - 1) / kQueues * S;
+        const int64_t nbq = (chunk + kCostBlock - 1) / kCostBlock;
+        pl->cost_cnt = (int32_t*)take(sizeof(int32_t) * kCostClasses * kQueues * (size_t)nbq);
+    }
     pl->bsum = (int32_t*)take(sizeof(int32_t) * nsum);
     pl->bp = (int2*)take(sizeof(int2) * (size_t)grid * n_layers * seeds_per_tile * kMaxCands);
     pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);

@@ -101,6 +101,7 @@ struct FindPlan {
     int32_t* order;     // [n_seeds] seeds in (event, eta, phi) cell order
     int32_t* tile_order;  // [n_seeds] the finding kernel's order: the cell order partitioned
                           // by cost class inside each tile queue's range
+    int32_t* cost_cnt;  // [kQueues][blocks][3] cost classes per block of the tile order
     int32_t* bsum;      // chunk totals of the prefix sums
     int2* bp;
     int32_t* tile_counter;
