@@ -377,13 +377,14 @@ def build_field_fit_set(n_total, n_unique=100_000, seed=7):
 def field_flops_per_step(oc, evals, lengths):
     """Operations of one field propagation and update: the solve's set-up,
     each evaluation (its Runge-Kutta transport over the path taken as the
-    converged one), the final transport, the covariance transport and the
-    update; special-function calls counted as one.  evals and lengths are
-    per-propagation arrays (3D path, cm)."""
+    converged one), the converged solve's polish step and state, the field
+    transport of the covariance and the update; special-function calls
+    counted as one.  evals and lengths are per-propagation arrays (3D path,
+    cm)."""
     f = lambda k: oc[k]["ops"] + oc[k]["sfu"]
     n = np.ceil(np.abs(lengths) / FIELD_STEP)
-    per = (f("field_setup") + f("field_at") + evals * (f("field_eval") + f("rk_fixed"))
-           + (evals + 1) * n * f("rk_step") + f("rk_fixed") + f("transport_barrel") + f("update"))
+    per = (f("field_setup") + f("field_at") + evals * (f("field_eval") + f("rk_fixed") + n * f("rk_step"))
+           + f("field_final") + f("field_transport") + f("update"))
     return float(per.mean())
 
 

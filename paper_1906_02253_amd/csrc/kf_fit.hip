@@ -58,19 +58,18 @@ __device__ inline int propagate_to(U p[6], C P[21], const kf_layer& L, const kf_
         // path's mean effective axial field
         const T sth = Tr<T>::sin_(pt[5]);
         T l;
+        T q[6];
         int st;
         if (L.kind != 0) {
-            st = solve_disk_field(pt, T(L.r_or_z), prm, &l, evals);
+            st = solve_disk_field(pt, T(L.r_or_z), prm, &l, q, evals);
         } else {
             T bx, by, bz0;
             field_at(T(prm.bz), T(prm.field_z0), pt[0], pt[1], pt[2], &bx, &by, &bz0);
             const T kb0 = T(kKappa) * bz0;
             st = solve_barrel_field(pt, T(L.r_or_z), prm, kb0, s_init >= T(0) ? s_init / sth : T(-1),
-                                    prm.mlp_max_iter, &l, evals, fallbacks);
+                                    prm.mlp_max_iter, &l, q, evals, fallbacks);
         }
         if (st) return st;
-        T q[6];
-        rk_path(pt, l, T(prm.bz), T(prm.field_z0), T(prm.field_step), q);
         field_transport(p, P, q, l, prm, L.kind, T(L.r_or_z));
         if (material) {
             if constexpr (MAT)

@@ -519,7 +519,7 @@ KF_HD inline void field_at(T B0, T Z0, T x, T y, T z, T* bx, T* by, T* bz)
 // FP32 the steps' rounding makes z(l) jump by ~2e-4 cm between neighbouring
 // l, more than the solves' tolerance.
 template <typename T>
-KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
+KF_HD inline void rk_cart(const T p[6], T l, T B0, T Z0, T step, T y_out[3], T t_out[3])
 {
     T st, ct, sp, cp;
     Tr<T>::sincos_(p[5], &st, &ct);
@@ -568,13 +568,54 @@ KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
         csum(t1, e[4], w * (a[4] + T(2) * b[4] + T(2) * c[4] + d[4]));
         csum(t2, e[5], w * (a[5] + T(2) * b[5] + T(2) * c[5] + d[5]));
     }
-    const T tt = Tr<T>::sqrt_(t0 * t0 + t1 * t1);
-    out[0] = x0 + y0;
-    out[1] = x1 + y1;
-    out[2] = x2 + y2;
-    out[5] = Tr<T>::atan2_(tt, t2);
-    out[4] = Tr<T>::atan2_(t1, t0);
-    out[3] = p[3] * st / Tr<T>::sin_(out[5]);
+    y_out[0] = x0 + y0;
+    y_out[1] = x1 + y1;
+    y_out[2] = x2 + y2;
+    t_out[0] = t0;
+    t_out[1] = t1;
+    t_out[2] = t2;
+}
+
+// The state parametrisation (x, y, z, c, phi, theta) of a position y and unit
+// direction t reached from p (q/p = c sin(theta) conserved).
+template <typename T>
+KF_HD inline void rk_params(const T p[6], const T y[3], const T t[3], T out[6])
+{
+    const T tt = Tr<T>::sqrt_(t[0] * t[0] + t[1] * t[1]);
+    out[0] = y[0];
+    out[1] = y[1];
+    out[2] = y[2];
+    out[5] = Tr<T>::atan2_(tt, t[2]);
+    out[4] = Tr<T>::atan2_(t[1], t[0]);
+    out[3] = p[3] * Tr<T>::sin_(p[5]) / Tr<T>::sin_(out[5]);
+}
+
+template <typename T>
+KF_HD inline void rk_path(const T p[6], T l, T B0, T Z0, T step, T out[6])
+{
+    T y[3], t[3];
+    rk_cart(p, l, B0, Z0, step, y, t);
+    rk_params(p, y, t, out);
+}
+
+// A Cartesian state (position y, unit direction t) of the track from p moved
+// by a short path d: the solves' polish step after their last evaluation,
+// first order in d (|d| below the solve's tolerance, so the neglected terms
+// are below 1e-8 of it).
+template <typename T>
+KF_HD inline void rk_nudge(const T p[6], T B0, T Z0, T d, T y[3], T t[3])
+{
+    T bx, by, bz;
+    field_at(B0, Z0, y[0], y[1], y[2], &bx, &by, &bz);
+    const T kq = T(kKappa) * p[3] * Tr<T>::sin_(p[5]);
+    const T d0 = kq * (t[1] * bz - t[2] * by), d1 = kq * (t[2] * bx - t[0] * bz),
+            d2 = kq * (t[0] * by - t[1] * bx);
+    y[0] += d * t[0];
+    y[1] += d * t[1];
+    y[2] += d * t[2];
+    t[0] += d * d0;
+    t[1] += d * d1;
+    t[2] += d * d2;
 }
 
 // Propagation along the 3D path l in the parametrised field whose end state q
@@ -704,15 +745,17 @@ KF_HD inline int solve_barrel(const T p[6], T h, T cph, T sph, T r_l, T s_hi, co
 }
 
 // Propagate-to-radius in the parametrised field: bracketed Newton on the 3D
-// path length l, r(l) from rk_path.  The bracket and reachability come from
-// the helix in the start point's field (kb0 = kappa Bz(start)), the bracket
-// cut at kMaxFieldPath (a barrel whose straight-line path exceeds it is
-// unreachable); the start is
-// the straight line, or l_guess >= 0 with learned_it evaluations before the
-// fallback to the straight line (counted in *fallbacks).
+// path length l, r(l) from the Cartesian end state of rk_cart.  The bracket
+// and reachability come from the helix in the start point's field (kb0 =
+// kappa Bz(start)), the bracket cut at kMaxFieldPath (a barrel whose
+// straight-line path exceeds it is unreachable); the start is the straight
+// line, or l_guess >= 0 with learned_it evaluations before the fallback to the
+// straight line (counted in *fallbacks).  On convergence the polish step is
+// taken from the last evaluation's state (rk_nudge), and q_out gets the end
+// state at the polished path *l_out.
 template <typename T>
 KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T kb0, T l_guess,
-                                    int learned_it, T* l_out, int* evals, int* fallbacks)
+                                    int learned_it, T* l_out, T q_out[6], int* evals, int* fallbacks)
 {
     T sph, cph, sth, cth;
     Tr<T>::sincos_(p[4], &sph, &cph);
@@ -732,14 +775,11 @@ KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T
         if (l < lo) l = lo;
         if (l > hi) l = hi;
         for (int it = 1; it <= max_it; ++it) {
-            T q[6];
-            rk_path(p, l, B0, Z0, step, q);
-            T sq, cq, sq5, cq5;
-            Tr<T>::sincos_(q[4], &sq, &cq);
-            Tr<T>::sincos_(q[5], &sq5, &cq5);
-            const T r = Tr<T>::sqrt_(q[0] * q[0] + q[1] * q[1]);
+            T y[3], t[3];
+            rk_cart(p, l, B0, Z0, step, y, t);
+            const T r = Tr<T>::sqrt_(y[0] * y[0] + y[1] * y[1]);
             const T res = r - r_l;
-            const T drdl = sq5 * (q[0] * cq + q[1] * sq) / r;
+            const T drdl = (y[0] * t[0] + y[1] * t[1]) / r;
             ++*evals;
             if (res < T(0)) {
                 if (l > lo) lo = l;
@@ -747,8 +787,11 @@ KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T
                 if (l < hi) hi = l;
             }
             if (Tr<T>::abs_(res) < tol) {
-                if (drdl > T(0)) l -= res / drdl;
-                *l_out = l;
+                // the polish step, taken from this evaluation's state
+                const T d = drdl > T(0) ? -res / drdl : T(0);
+                rk_nudge(p, B0, Z0, d, y, t);
+                rk_params(p, y, t, q_out);
+                *l_out = l + d;
                 return 0;
             }
             T ln = l - res / drdl;
@@ -767,14 +810,16 @@ KF_HD inline int solve_barrel_field(const T p[6], T r_l, const kf_params& prm, T
 }
 
 // Propagate-to-z in the parametrised field: bracketed Newton on the 3D path
-// length l, z(l) from rk_path with dz/dl = cos theta(l).  Start: the straight
+// length l, z(l) from rk_cart with dz/dl = cos theta(l), the end state as in
+// the radius solve.  Start: the straight
 // line l0 = (z_d - z) / cos theta, exact in a uniform field; the plane must
 // lie ahead (0 <= l0 <= kMaxFieldPath).  Bracket [0, min(2 l0,
 // kMaxFieldPath)]: the radial field bends theta only slightly, and a track
 // short of the plane after twice the straight path does not reach it
 // (NOCONV).  Same stopping rule as the radius solve.
 template <typename T>
-KF_HD inline int solve_disk_field(const T p[6], T z_d, const kf_params& prm, T* l_out, int* evals)
+KF_HD inline int solve_disk_field(const T p[6], T z_d, const kf_params& prm, T* l_out, T q_out[6],
+                                  int* evals)
 {
     T sth, cth;
     Tr<T>::sincos_(p[5], &sth, &cth);
@@ -786,10 +831,10 @@ KF_HD inline int solve_disk_field(const T p[6], T z_d, const kf_params& prm, T* 
     const T tol = T(prm.newton_tol);
     T lo = T(0), hi = Tr<T>::min_(T(2) * l0, T(kMaxFieldPath)), l = l0;
     for (int it = 1; it <= prm.max_newton; ++it) {
-        T q[6];
-        rk_path(p, l, B0, Z0, step, q);
-        const T res = sgn * (q[2] - z_d);      // > 0: past the plane
-        const T dzdl = sgn * Tr<T>::cos_(q[5]);
+        T y[3], t[3];
+        rk_cart(p, l, B0, Z0, step, y, t);
+        const T res = sgn * (y[2] - z_d);      // > 0: past the plane
+        const T dzdl = sgn * t[2];
         ++*evals;
         if (res < T(0)) {
             if (l > lo) lo = l;
@@ -797,8 +842,11 @@ KF_HD inline int solve_disk_field(const T p[6], T z_d, const kf_params& prm, T* 
             if (l < hi) hi = l;
         }
         if (Tr<T>::abs_(res) < tol) {
-            if (dzdl > T(0)) l -= res / dzdl;
-            *l_out = l;
+            // the polish step, taken from this evaluation's state
+            const T d = dzdl > T(0) ? -res / dzdl : T(0);
+            rk_nudge(p, B0, Z0, d, y, t);
+            rk_params(p, y, t, q_out);
+            *l_out = l + d;
             return 0;
         }
         T ln = l - res / dzdl;
@@ -840,7 +888,7 @@ KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const k
     if (bl >= 0) {
         T l;
         int fb = 0;
-        const int r = solve_barrel_field(p, T(L[bl].r_or_z), prm, kb0, l_guess, learned_it, &l,
+        const int r = solve_barrel_field(p, T(L[bl].r_or_z), prm, kb0, l_guess, learned_it, &l, q,
                                          newton_evals, &fb);
         if (fallbacks) *fallbacks += fb;
         if (r == (int)KF_ST_NOCONV) {
@@ -848,7 +896,6 @@ KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const k
             return -1;
         }
         if (r == 0) {
-            rk_path(p, l, B0, Z0, step, q);
             if (Tr<T>::abs_(q[2]) <= T(L[bl].hi) && l * sth <= s_max) {
                 best = l;
                 best_l = bl;
@@ -863,14 +910,13 @@ KF_HD inline int navigate_field(const T p[6], const kf_layer* L, int nl, const k
         if (l_line > T(1.01) * best + T(1) || l_line * sth > T(1.01) * s_max + T(1)) continue;
         T ld;
         ++*disk_evals;
-        const int r = solve_disk_field(p, T(L[d].r_or_z), prm, &ld, newton_evals);
+        T qd[6];
+        const int r = solve_disk_field(p, T(L[d].r_or_z), prm, &ld, qd, newton_evals);
         if (r == (int)KF_ST_NOCONV) {
             *st |= KF_ST_NOCONV;
             return -1;
         }
         if (r) continue;
-        T qd[6];
-        rk_path(p, ld, B0, Z0, step, qd);
         const T rr = Tr<T>::sqrt_(qd[0] * qd[0] + qd[1] * qd[1]);
         if (ld * sth > s_max || rr < T(L[d].lo) || rr > T(L[d].hi)) continue;
         if (ld < best) {
@@ -912,28 +958,26 @@ KF_HD inline int steer_next_field(const T p[6], const kf_layer* L, const uint8_t
             const T r_l = T(Ly.r_or_z);
             if (!(r_l > rho + T(kNextBarrelEps))) continue;
             int fb = 0;
-            const int r = solve_barrel_field(p, r_l, prm, kb0, T(-1), 0, &ll, newton_evals, &fb);
+            const int r = solve_barrel_field(p, r_l, prm, kb0, T(-1), 0, &ll, q, newton_evals, &fb);
             if (r == (int)KF_ST_NOCONV) {
                 *st |= KF_ST_NOCONV;
                 *pos = qi + 1;
                 return -1;
             }
             if (r) continue;
-            rk_path(p, ll, B0, Z0, step, q);
             if (Tr<T>::abs_(q[2]) > T(Ly.hi) || ll * sth > s_max) continue;
         } else {
             const T dz = T(Ly.r_or_z) - p[2];
             if (!(dz * cth > T(0)) || Tr<T>::abs_(dz) <= T(kDiskAheadEps)) continue;
             if (dz / cth * sth > T(1.01) * s_max + T(1)) continue;
             ++*disk_evals;
-            const int r = solve_disk_field(p, T(Ly.r_or_z), prm, &ll, newton_evals);
+            const int r = solve_disk_field(p, T(Ly.r_or_z), prm, &ll, q, newton_evals);
             if (r == (int)KF_ST_NOCONV) {
                 *st |= KF_ST_NOCONV;
                 *pos = qi + 1;
                 return -1;
             }
             if (r) continue;
-            rk_path(p, ll, B0, Z0, step, q);
             const T rr = Tr<T>::sqrt_(q[0] * q[0] + q[1] * q[1]);
             if (ll * sth > s_max || rr < T(Ly.lo) || rr > T(Ly.hi)) continue;
         }

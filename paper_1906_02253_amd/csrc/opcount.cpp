@@ -187,12 +187,28 @@ int main()
     // solve besides its transport (a step longer than any path makes every
     // transport a single step)
     Tally rk_fixed = count([&] {
-        T q[6];
-        rk_path(p, T(0.0), T(3.8), T(300.0), T(2.0), q);
+        T y[3], t[3];
+        rk_cart(p, T(0.0), T(3.8), T(300.0), T(2.0), y, t);
     });
     Tally rk_one = count([&] {
-        T q[6];
-        rk_path(p, T(1.5), T(3.8), T(300.0), T(2.0), q);
+        T y[3], t[3];
+        rk_cart(p, T(1.5), T(3.8), T(300.0), T(2.0), y, t);
+    });
+    // a converged solve's end: the polish step and the state parametrisation
+    Tally field_final = count([&] {
+        T y[3] = {p[0], p[1], p[2]}, t[3] = {T(0.6), T(0.0), T(0.8)}, q[6];
+        rk_nudge(p, T(3.8), T(300.0), T(1e-5), y, t);
+        rk_params(p, y, t, q);
+    });
+    // the field transport's Jacobian field and the transport itself
+    Tally field_transport_t = count([&] {
+        T q[6] = {p[0] + T(1), p[1] + T(1), p[2] + T(1), p[3], p[4], p[5]};
+        T x[6] = {p[0], p[1], p[2], p[3], p[4], p[5]};
+        T Q[21];
+        for (int k = 0; k < 21; ++k) Q[k] = P[k];
+        kf_params fq = prm;
+        fq.field_z0 = 300.0;
+        field_transport(x, Q, q, T(1.5), fq, 0, T(50.0));
     });
     Tally rk_step{rk_one.ops - rk_fixed.ops, rk_one.sfu - rk_fixed.sfu};
     kf_params fp = prm;
@@ -202,10 +218,11 @@ int main()
     T lo;
     const T kb0 = T(kKappa * 3.8);
     fp.max_newton = 1;
-    Tally f1 = count([&] { solve_barrel_field(p, T(50.0), fp, kb0, T(-1.0), 0, &lo, &fe, &ffb); });
+    T qo[6];
+    Tally f1 = count([&] { solve_barrel_field(p, T(50.0), fp, kb0, T(-1.0), 0, &lo, qo, &fe, &ffb); });
     fp.max_newton = 2;
     fp.newton_tol = 1e-300;
-    Tally f2 = count([&] { solve_barrel_field(p, T(50.0), fp, kb0, T(-1.0), 0, &lo, &fe, &ffb); });
+    Tally f2 = count([&] { solve_barrel_field(p, T(50.0), fp, kb0, T(-1.0), 0, &lo, qo, &fe, &ffb); });
     Tally field_eval{f2.ops - f1.ops - rk_one.ops, f2.sfu - f1.sfu - rk_one.sfu};
     Tally field_setup{f1.ops - (f2.ops - f1.ops), f1.sfu - (f2.sfu - f1.sfu)};
     Tally field_at_t = count([&] {
@@ -229,6 +246,8 @@ int main()
     pr("rk_fixed", rk_fixed);
     pr("field_eval", field_eval);
     pr("field_setup", field_setup);
+    pr("field_final", field_final);
+    pr("field_transport", field_transport_t);
     pr("field_at", field_at_t, true);
     printf("}\n");
     return 0;
