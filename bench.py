@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--width", type=int, default=0,
                     help="finding workgroup width; 0 = autotune width and tile order")
+    ap.add_argument("--largest-first", action="store_true",
+                    help="with --width: events largest first in the tile order")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
     ap.add_argument("--no-clean", action="store_true")
@@ -651,7 +653,7 @@ def cpu_model():
     return ""
 
 
-def cpu_baseline(geom, evs, inp, single_events=16):
+def cpu_baseline(geom, evs, inp, single_events=64):
     """The FP64 oracle's seed fit and finding timed on the host: over the
     whole batch on all host threads (capped at 16, the host share one GPU
     gets), and over its first `single_events` events on one thread."""
@@ -707,7 +709,7 @@ def main():
     fp.run()
     tune = None
     if args.width:
-        ctx.set_find_config(args.width, False)
+        ctx.set_find_config(args.width, args.largest_first)
     else:
         tune = fp.autotune(reps=3)
         print("# autotune (width, largest_first) -> ms: " +
