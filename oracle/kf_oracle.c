@@ -31,8 +31,9 @@
  *     tracks integrated in 3D path length by fourth-order Runge-Kutta with
  *     equal steps of at most field_step; the propagate-to-radius solve is
  *     the same bracketed Newton iteration on the integrated radius, and the
- *     transport Jacobian is the helix one in the field at the start point.
- *     Disks are reached by the same Newton iteration on the integrated z.
+ *     transport Jacobian is the helix one in the path's mean effective
+ *     axial field (see transport_parts).  Disks are reached by the same
+ *     Newton iteration on the integrated z.
  *     Both solves search at most MAX_FIELD_PATH (1000 cm) of 3D path.
  */
 #include "kf_oracle.h"
