@@ -433,17 +433,21 @@ __global__ __launch_bounds__(256) void cell_sort_kernel(int64_t n_cells, const i
 }
 
 // Tiles of seeds of like cost.  A tile runs as long as its slowest seed,
-// and low-pT seeds (loopers, which curl back through the detector with ever
-// wider windows) walk longest, so inside each tile queue's contiguous range
-// of the processing order the seeds are partitioned, stably, by a cost class
-// of |q/pT|, costliest first: fewer tiles wait on one looper, and the long
-// tiles start first instead of ending the pass.  (Sparser tiles for the
-// loopers, a few seeds per wave, cost more than they saved.)
-constexpr int kCostClasses = 3;
-__device__ inline int cost_class(float c)
+// and low-pT seeds in the central barrel (loopers, which curl back through
+// the layers with ever wider windows) walk longest, so inside each tile
+// queue's contiguous range of the processing order the seeds are
+// partitioned, stably, by a cost class of |q/pT| and |eta|, costliest first:
+// fewer tiles wait on one looper, and the long tiles start first instead of
+// ending the pass.  (Sparser tiles for the loopers, a few seeds per wave, do
+// not end sooner: a tile's scan is set by its widest windows.)
+constexpr int kCostClasses = 4;
+__device__ inline int cost_class(float c, float theta)
 {
-    const float a = fabsf(c);
-    return a > 1.0f / 0.6f ? 0 : (a > 1.0f ? 1 : 2);   // pT < 0.6, < 1 GeV, the rest
+    // |theta - pi/2| < 0.4803: |eta| < 0.5; < 0.8658: |eta| < 1
+    const float a = fabsf(c), e = fabsf(theta - 1.57079633f);
+    if (a > 1.0f / 0.6f && e < 0.4803f) return 0;   // central loopers, pT < 0.6 GeV
+    if (a > 1.0f / 0.7f && e < 0.8658f) return 1;   // pT < 0.7 GeV, |eta| < 1
+    return a > 1.0f ? 2 : 3;                         // pT < 1 GeV, the rest
 }
 
 // Two passes over blocks of kCostBlock entries of each queue range [q chunk,
@@ -474,7 +478,7 @@ __global__ __launch_bounds__(kCostBlock) void cost_count_kernel(int64_t n, int64
     if (t < kCostClasses) tot[t] = 0;
     __syncthreads();
     const int64_t i = lo + t;
-    const int k = i < hi ? cost_class(par[3 * ld + order[i]]) : -1;
+    const int k = i < hi ? cost_class(par[3 * ld + order[i]], par[5 * ld + order[i]]) : -1;
     for (int c = 0; c < kCostClasses; ++c) {
         const unsigned long long m = __ballot(k == c);
         if ((t & 63) == 0 && m) atomicAdd(&tot[c], __popcll(m));
@@ -508,7 +512,7 @@ __global__ __launch_bounds__(kCostBlock) void cost_place_kernel(int64_t n, int64
         base[t] = costlier + before;
     }
     const int64_t i = lo + t;
-    const int k = i < hi ? cost_class(par[3 * ld + order[i]]) : -1;
+    const int k = i < hi ? cost_class(par[3 * ld + order[i]], par[5 * ld + order[i]]) : -1;
     int below = 0;
     for (int c = 0; c < kCostClasses; ++c) {
         const unsigned long long m = __ballot(k == c);
@@ -974,31 +978,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     if (2 * ln + 1 < nseg) sg_pre[2 * ln + 1] = pre + la;
                     if (ln == 0) sg_pre[nseg] = H;
                     wave_fence();
-                    // (3) the flattened hits, 64 x kScanBatch per round
-                    for (int g0 = 0; g0 < H; g0 += wlanes * kScanBatch) {
+                    // (3) the flattened hits, 64 x kScanBatch per round.  Lane ln
+                    //     walks its own contiguous segment of the list, kScanBatch
+                    //     hits per round, so that a round holds hits of many owners
+                    //     and their insertions below run side by side.  Owners
+                    //     still rise with the lane, so a round's accepted hits of
+                    //     one owner stay one range of the compaction.
+                    const int nround = (H + wlanes * kScanBatch - 1) / (wlanes * kScanBatch);
+                    const int gseg = ln * kScanBatch * nround;   // first hit of the segment
+                    // the lane's current row, held in registers: its end in the
+                    // list, owner, and binned index minus list position
+                    int row = 0, r_end = H, r_own = -1, r_base = 0;
+                    if (gseg < H) {
+                        int hi = nseg;                            // sg_pre[row] <= gseg < sg_pre[hi]
+                        while (hi - row > 1) {
+                            const int mid = (row + hi) >> 1;
+                            if (sg_pre[mid] <= gseg) row = mid;
+                            else hi = mid;
+                        }
+                        r_end = sg_pre[row + 1];
+                        r_own = sg_own[row];
+                        r_base = sg_h0[row] - sg_pre[row];
+                    }
+                    for (int ir = 0; ir < nround; ++ir) {
                         float4 r0[kScanBatch], r1[kScanBatch];
                         int own[kScanBatch], bix[kScanBatch];
-                        // lane ln takes kScanBatch consecutive hits: one search for
-                        // the row of the first, then step over row ends
-                        const int gb = g0 + ln * kScanBatch;
-                        int row = 0;
-                        if (gb < H) {
-                            int hi = nseg;                        // sg_pre[row] <= gb < sg_pre[hi]
-                            while (hi - row > 1) {
-                                const int mid = (row + hi) >> 1;
-                                if (sg_pre[mid] <= gb) row = mid;
-                                else hi = mid;
-                            }
-                        }
+                        const int gb = gseg + ir * kScanBatch;
 #pragma unroll
                         for (int q = 0; q < kScanBatch; ++q) {
                             const int g = gb + q;
                             own[q] = -1;
                             bix[q] = 0;
                             if (g < H) {
-                                while (sg_pre[row + 1] <= g) ++row;   // sg_pre[nseg] = H > g
-                                own[q] = sg_own[row];
-                                bix[q] = sg_h0[row] + (g - sg_pre[row]);
+                                while (g >= r_end) {                 // sg_pre[nseg] = H > g
+                                    ++row;
+                                    r_end = sg_pre[row + 1];
+                                    r_own = sg_own[row];
+                                    r_base = sg_h0[row] - sg_pre[row];
+                                }
+                                own[q] = r_own;
+                                bix[q] = r_base + g;
                             }
                             r0[q] = *(const float4*)&a.bh[bix[q]].x;
                             r1[q] = *(const float4*)&a.bh[bix[q]].sv;
@@ -1056,8 +1075,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                         int nok = 0;
 #pragma unroll
                         for (int q = 0; q < kScanBatch; ++q) nok += okq[q] ? 1 : 0;
-                        int n_round = 0;
-                        int pos = wave_scan(nok, &n_round);
+                        // exclusive prefix of nok (< 8) over the lanes, bit by bit
+                        static_assert(kScanBatch < 8, "nok takes three bits");
+                        int pos = 0;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const uint64_t m = __ballot((nok >> b) & 1);
+                            pos += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))
+                                   << b;
+                        }
 #pragma unroll
                         for (int q = 0; q < kScanBatch; ++q)
                             if (okq[q]) {
