@@ -207,6 +207,7 @@ int prepare_find(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, int
     a.ostatus = out->status;
     a.bp = pl.bp;
     a.tile_counter = pl.tile_counter;
+    a.queue_loopers = pl.queue_loopers;
     a.counters = (unsigned long long*)counters;
     a.layers = ctx->d_layers;
     a.n_layers = nl;

@@ -438,9 +438,17 @@ __global__ __launch_bounds__(256) void cell_sort_kernel(int64_t n_cells, const i
 // queue's contiguous range of the processing order the seeds are
 // partitioned, stably, by a cost class of |q/pT| and |eta|, costliest first:
 // fewer tiles wait on one looper, and the long tiles start first instead of
-// ending the pass.  (Sparser tiles for the loopers, a few seeds per wave, do
-// not end sooner: a tile's scan is set by its widest windows.)
+// ending the pass.  The costliest class, the central loopers, comes in tiles
+// of half the seeds: a tile's window scan is shared by its candidates, so
+// such a tile ends in about half the time, and the few longest tiles no
+// longer outlast the rest of the pass.
 constexpr int kCostClasses = 4;
+
+// seeds in a tile of the costliest class: half a tile
+__host__ __device__ inline int looper_tile_seeds(int S)
+{
+    return S / 2 > 1 ? S / 2 : 1;
+}
 __device__ inline int cost_class(float c, float theta)
 {
     // |theta - pi/2| < 0.4803: |eta| < 0.5; < 0.8658: |eta| < 1
@@ -492,15 +500,22 @@ __global__ __launch_bounds__(kCostBlock) void cost_place_kernel(int64_t n, int64
                                                                 const int32_t* __restrict__ order,
                                                                 int64_t chunk, int nbq,
                                                                 const int32_t* __restrict__ cnt,
-                                                                int32_t* __restrict__ out)
+                                                                int32_t* __restrict__ out,
+                                                                int32_t* __restrict__ queue_loopers)
 {
     __shared__ int wtot[kCostBlock / 64][kCostClasses];   // per wave and class
     __shared__ int base[kCostClasses];                      // class base of this block in the range
     int64_t lo, hi;
     cost_block_range(n, chunk, nbq, &lo, &hi);
-    if (lo >= hi) return;
     const int q = blockIdx.x / nbq, b = blockIdx.x - q * nbq;
     const int t = threadIdx.x, wave = t >> 6, ln = t & 63;
+    if (b == 0 && t == 0) {
+        // the range's costliest-class seeds (its head after the partition)
+        int c0 = 0;
+        for (int bb = 0; bb < nbq; ++bb) c0 += cnt[((size_t)q * nbq + bb) * kCostClasses];
+        queue_loopers[q] = c0;
+    }
+    if (lo >= hi) return;
     if (t < kCostClasses) {
         // entries of the range in the costlier classes, then this class's in earlier blocks
         int before = 0, costlier = 0;
@@ -580,7 +595,7 @@ struct FindShared {
     int32_t* nsel;      // [S]
     kf_layer* layers;   // [n_layers]
     NavOrder* nav;      // surface orders of the dynamic navigation
-    int32_t* misc;      // [4] tile id
+    int32_t* misc;      // [4] the tile: first position in the order, seed count
     // cooperative window scan, per lane (owner of a window) and per wave
     float* own;         // [5][W] cos/sin of the predicted azimuth, sin(dphi), wv, flags
     int32_t* seg;       // [n_waves][3][kSeg] queued phi rows: owner lane, first hit, count
@@ -697,33 +712,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     for (;;) {
         __syncthreads();
         if (t == 0) {
-            // tiles are split into kQueues contiguous chunks, one per XCD
-            // (workgroups are dispatched to the XCDs round-robin), so that a
-            // chunk's neighbouring eta-phi tiles share that XCD's L2; a
-            // workgroup whose chunk is exhausted takes tiles from the others
-            const int chunk = (a.n_tiles + kQueues - 1) / kQueues;
+            // the processing order is split into kQueues contiguous ranges of
+            // whole tiles, one per XCD (workgroups are dispatched to the XCDs
+            // round-robin), so that a range's neighbouring eta-phi tiles share
+            // that XCD's L2; a workgroup whose range is exhausted takes tiles
+            // from the others.  A range's costliest-class seeds, at its head,
+            // come in tiles of SL seeds, the rest in tiles of S.
+            const int64_t cs = (int64_t)((a.n_tiles + kQueues - 1) / kQueues) * S;
+            const int SL = looper_tile_seeds(S);
             const int home = blockIdx.x % kQueues;
-            int tile = a.n_tiles;
+            int start = -1, cnt = 0;
             for (int d = 0; d < kQueues; ++d) {
                 const int q = (home + d) % kQueues;
-                const int lo = q * chunk;
-                const int hi = lo + chunk < a.n_tiles ? lo + chunk : a.n_tiles;
+                const int64_t lo = q * cs;
+                const int64_t hi = lo + cs < a.n_seeds ? lo + cs : a.n_seeds;
                 if (lo >= hi) continue;
+                const int nq = (int)(hi - lo);
+                int c0 = a.queue_loopers[q];
+                c0 = c0 < 0 ? 0 : (c0 > nq ? nq : c0);
+                const int nlt = (c0 + SL - 1) / SL;
                 const int i = atomicAdd(&a.tile_counter[q], 1);
-                if (lo + i < hi) {
-                    tile = lo + i;
+                if (i < nlt) {
+                    start = (int)lo + i * SL;
+                    cnt = c0 - i * SL < SL ? c0 - i * SL : SL;
+                    break;
+                }
+                const int64_t j0 = c0 + (int64_t)(i - nlt) * S;   // first seed of a full tile
+                if (j0 < nq) {
+                    start = (int)(lo + j0);
+                    cnt = nq - j0 < S ? (int)(nq - j0) : S;
                     break;
                 }
             }
-            sh.misc[0] = tile;
+            sh.misc[0] = start;
+            sh.misc[1] = cnt;
         }
         __syncthreads();
-        const int tile = sh.misc[0];
-        if (tile >= a.n_tiles) break;
+        const int tstart = sh.misc[0], tcount = sh.misc[1];
+        if (tstart < 0) break;
 
-        const int64_t g = (int64_t)tile * S + s_loc;
-        const bool valid = lane_ok && g < a.n_seeds;
-        const int sid = valid ? a.order[g] : 0;
+        const bool valid = lane_ok && s_loc < tcount;
+        const int sid = valid ? a.order[tstart + s_loc] : 0;
         int ev = valid ? a.seed_event[sid] : 0;
         const bool bad_event = ev < 0 || ev >= a.n_events;
         if (bad_event) ev = 0;
@@ -1418,13 +1447,14 @@ hipError_t launch_bin(const FindPlan& pl, const kf_hits* h, const int32_t* event
 hipError_t launch_cost_order(const FindPlan& pl, const kf_tracks* seeds, int n_tiles,
                              int seeds_per_tile, hipStream_t s)
 {
-    if (seeds->n == 0) return hipSuccess;
+    if (seeds->n == 0) return launch_fill(pl.queue_loopers, kQueues, 0, s);
     const int64_t chunk = (int64_t)((n_tiles + kQueues - 1) / kQueues) * seeds_per_tile;
     const int nbq = (int)((chunk + kCostBlock - 1) / kCostBlock);
     cost_count_kernel<<<kQueues * nbq, kCostBlock, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
                                                           pl.order, chunk, nbq, pl.cost_cnt);
     cost_place_kernel<<<kQueues * nbq, kCostBlock, 0, s>>>(seeds->n, seeds->ld, (const float*)seeds->par,
-                                                          pl.order, chunk, nbq, pl.cost_cnt, pl.tile_order);
+                                                          pl.order, chunk, nbq, pl.cost_cnt, pl.tile_order,
+                                                          pl.queue_loopers);
     return hipGetLastError();
 }
 
@@ -1784,6 +1814,7 @@ size_t plan_find(FindPlan* pl, void* base, int64_t n_hits, int n_events, int64_t
         const int64_t nbq = (chunk + kCostBlock - 1) / kCostBlock;
         pl->cost_cnt = (int32_t*)take(sizeof(int32_t) * kCostClasses * kQueues * (size_t)nbq);
     }
+    pl->queue_loopers = (int32_t*)take(sizeof(int32_t) * kQueues);
     pl->bsum = (int32_t*)take(sizeof(int32_t) * nsum);
     pl->bp = (int2*)take(sizeof(int2) * (size_t)grid * n_layers * seeds_per_tile * kMaxCands);
     pl->tile_counter = (int32_t*)take(sizeof(int32_t) * 64);

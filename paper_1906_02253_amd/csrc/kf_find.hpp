@@ -60,6 +60,8 @@ struct FindArgs {
     // scratch
     int2* bp;                     // per workgroup: [n_layers][S][kMaxCands] back-pointers
     int32_t* tile_counter;
+    const int32_t* queue_loopers; // [kQueues] costliest-class seeds at the head of each tile
+                                  // queue's range (served in sparser tiles)
     unsigned long long* counters; // optional [kFindCounters]: propagations, updates, chi2 tests,
                                   // Newton evaluations, disk tests, learned guesses, fallbacks,
                                   // children kept from propagated parents
@@ -101,7 +103,8 @@ struct FindPlan {
     int32_t* order;     // [n_seeds] seeds in (event, eta, phi) cell order
     int32_t* tile_order;  // [n_seeds] the finding kernel's order: the cell order partitioned
                           // by cost class inside each tile queue's range
-    int32_t* cost_cnt;  // [kQueues][blocks][3] cost classes per block of the tile order
+    int32_t* cost_cnt;  // [kQueues][blocks][classes] cost classes per block of the tile order
+    int32_t* queue_loopers;  // [kQueues] seeds of the costliest class in each queue's range
     int32_t* bsum;      // chunk totals of the prefix sums
     int2* bp;
     int32_t* tile_counter;
