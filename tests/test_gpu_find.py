@@ -119,3 +119,25 @@ def test_find_edge_cases(K, orc):
     g = _gpu_find(K, geom, inp)
     o = CM.oracle_find_events(orc, geom, [ev1, ev2], inp)
     _check_parity(g, o, "edge", _sens(orc, geom, [ev1, ev2], inp))
+
+
+def test_find_central_loopers_half_tiles(K, orc):
+    """Seeds that are all central low-pT loopers (pT 0.5-0.6 GeV, |eta| < 0.4),
+    the class the tile order serves in tiles of half the seeds: events of 1, 5,
+    7 and 130 tracks (ragged half tiles, tile queues holding none of them),
+    parity with the oracle and bit-identical results at every width and tile
+    order."""
+    rng = np.random.default_rng(62)
+    geom = E.geometry.barrel10(x0=0.02)
+    evs = [E.make_event(rng, geom, n, E.pt_uniform(0.5, 0.6), 0.4, 100) for n in (1, 5, 7, 130)]
+    inp = E.find_inputs(evs)
+    ns = int(inp["seed_hits"].shape[0])
+    assert ns >= 100
+    ref = _gpu_find(K, geom, inp, 64, True)
+    o = CM.oracle_find_events(orc, geom, evs, inp)
+    _check_parity(ref, o, "central loopers", _sens(orc, geom, evs, inp))
+    for w in (32, 128, 256):
+        for lf in (False, True):
+            r = _gpu_find(K, geom, inp, w, lf)
+            for k in ("hits", "par", "cov", "chi2", "ndf", "status"):
+                assert np.array_equal(r[k], ref[k]), (w, lf, k)
