@@ -582,11 +582,29 @@ __device__ inline uint64_t merge_key(int nhits, float c2, int j, int c)
            ((uint64_t)c << 8);
 }
 
-// LDS layout of one workgroup (W lanes), all arrays lane-minor
+// Row stride of the window owners' position covariance in LDS: six values
+// padded to whole 16-byte reads (three for FP64, two for FP32)
+template <typename C> constexpr int kOwnCov = sizeof(C) == 8 ? 6 : 8;
+
+template <typename C>
+__device__ inline void load_owner_cov(const C* r, C pc[6])
+{
+    if constexpr (sizeof(C) == 8) {
+        const double2 a = *(const double2*)r, b = *(const double2*)(r + 2), c = *(const double2*)(r + 4);
+        pc[0] = a.x; pc[1] = a.y; pc[2] = b.x; pc[3] = b.y; pc[4] = c.x; pc[5] = c.y;
+    } else {
+        const float4 a = *(const float4*)r;
+        const float2 b = *(const float2*)(r + 4);
+        pc[0] = a.x; pc[1] = a.y; pc[2] = a.z; pc[3] = a.w; pc[4] = b.x; pc[5] = b.y;
+    }
+}
+
+// LDS layout of one workgroup (W lanes); arrays lane-minor unless noted
 template <typename C>
 struct FindShared {
-    C* posc;            // [6][W]   predicted position covariance P00 P01 P02 P11 P12 P22
-    float* pred;        // [4][W]   predicted (or frozen) x, y, z and chi2
+    C* ocov;            // [W][kOwnCov] window owner's predicted position covariance
+                        //          P00 P01 P02 P11 P12 P22 (16-byte rows)
+    float* pchi2;       // [W]      chi2 of each lane's candidate
     int32_t* meta;      // [4][W]   nhits, misses, status, (done | (layer + 1) << 8)
     float* cchi2;       // [kMaxCands][W]  accepted hit chi2, ascending
     int32_t* cbidx;     // [kMaxCands][W]  binned index of those hits
@@ -597,7 +615,8 @@ struct FindShared {
     NavOrder* nav;      // surface orders of the dynamic navigation
     int32_t* misc;      // [4] the tile: first position in the order, seed count
     // cooperative window scan, per lane (owner of a window) and per wave
-    float* own;         // [5][W] cos/sin of the predicted azimuth, sin(dphi), wv, flags
+    float* orec;        // [W][8] window owner record: predicted x, y, z, cos and sin of its
+                        //        azimuth, sin(dphi), wv, flags (two 16-byte reads)
     int32_t* seg;       // [n_waves][3][kSeg] queued phi rows: owner lane, first hit, count
     int32_t* segpre;    // [n_waves][kSeg + 1] prefix of the rows' hit counts
     int32_t* acc;       // [n_waves][3][kAcc] per owner lane its accepted hits' first and last
@@ -614,8 +633,8 @@ constexpr int kInsBatch = 4;    // accepted hits an owner loads together
 __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t csize)
 {
     size_t b = 0;
-    b += csize * 6 * W;
-    b += sizeof(float) * 4 * W;
+    b += csize * (csize == 8 ? 6 : 8) * W;
+    b += sizeof(float) * W;
     b += sizeof(int32_t) * 4 * W;
     b += sizeof(float) * kMaxCands * W;
     b += sizeof(int32_t) * kMaxCands * W;
@@ -628,7 +647,7 @@ __host__ __device__ inline size_t find_shared_bytes(int W, int S, int nl, size_t
     b += 2 * S * kMaxCands;
     b = (b + 15) & ~size_t(15);
     const size_t nw = (W + 63) / 64;
-    b += sizeof(float) * 5 * W;
+    b += sizeof(float) * 8 * W;
     b += sizeof(int32_t) * nw * (3 * kSeg + kSeg + 1 + 3 * kAcc);
     b += sizeof(float) * nw * kAcc;
     b += sizeof(int32_t) * nw * 5 * 64;
@@ -656,10 +675,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
     FindShared<C> sh;
     {
         unsigned char* q = smem;
-        sh.posc = (C*)q;
-        q += sizeof(C) * 6 * W;
-        sh.pred = (float*)q;
-        q += sizeof(float) * 4 * W;
+        sh.ocov = (C*)q;
+        q += sizeof(C) * kOwnCov<C> * W;
+        sh.pchi2 = (float*)q;
+        q += sizeof(float) * W;
         sh.meta = (int32_t*)q;
         q += sizeof(int32_t) * 4 * W;
         sh.cchi2 = (float*)q;
@@ -681,8 +700,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
         q += 2 * S * kMaxCands;
         q = smem + (((size_t)(q - smem) + 15) & ~size_t(15));
         const int nw = (W + 63) / 64;
-        sh.own = (float*)q;
-        q += sizeof(float) * 5 * W;
+        sh.orec = (float*)q;
+        q += sizeof(float) * 8 * W;
         sh.seg = (int32_t*)q;
         q += sizeof(int32_t) * nw * 3 * kSeg;
         sh.segpre = (int32_t*)q;
@@ -882,14 +901,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
             // lane inserts its own into its sorted list.
             if (lane_ok) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) sh.pred[k * W + t] = float(p[k]);
-                sh.pred[3 * W + t] = chi2;
-                sh.posc[0 * W + t] = P[pk(0, 0)];
-                sh.posc[1 * W + t] = P[pk(0, 1)];
-                sh.posc[2 * W + t] = P[pk(0, 2)];
-                sh.posc[3 * W + t] = P[pk(1, 1)];
-                sh.posc[4 * W + t] = P[pk(1, 2)];
-                sh.posc[5 * W + t] = P[pk(2, 2)];
+                for (int k = 0; k < 3; ++k) sh.orec[t * 8 + k] = float(p[k]);
+                sh.pchi2[t] = chi2;
+                C* oc = sh.ocov + t * kOwnCov<C>;
+                oc[0] = P[pk(0, 0)];
+                oc[1] = P[pk(0, 1)];
+                oc[2] = P[pk(0, 2)];
+                oc[3] = P[pk(1, 1)];
+                oc[4] = P[pk(1, 2)];
+                oc[5] = P[pk(2, 2)];
             }
             // this candidate's accepted hits, best first: key and binned index
             uint64_t lk[kMaxCands];
@@ -923,11 +943,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     v1 = coord_bin_of(float(Wn.vhi), float(L.lo), float(L.hi), n2);
                     row0 = ev * a.bl.per_event + a.bl.base[pl];
                     const T rho = Tr<T>::sqrt_(p[0] * p[0] + p[1] * p[1]);
-                    sh.own[0 * W + t] = float(p[0] / rho);
-                    sh.own[1 * W + t] = float(p[1] / rho);
-                    sh.own[2 * W + t] = float(Wn.sin_dphi);
-                    sh.own[3 * W + t] = float(Wn.wv);
-                    sh.own[4 * W + t] = __int_as_float((Wn.all_phi ? 1 : 0) | (L.kind << 1));
+                    sh.orec[t * 8 + 3] = float(p[0] / rho);
+                    sh.orec[t * 8 + 4] = float(p[1] / rho);
+                    sh.orec[t * 8 + 5] = float(Wn.sin_dphi);
+                    sh.orec[t * 8 + 6] = float(Wn.wv);
+                    sh.orec[t * 8 + 7] = __int_as_float((Wn.all_phi ? 1 : 0) | (L.kind << 1));
                 }
             }
             {
@@ -1061,12 +1081,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                             if (o >= 0) {
                                 const int ot = (wave << 6) + o;
                                 const float hcp = r1[q].y, hsp = r1[q].z;
-                                const T cpp = T(sh.own[0 * W + ot]), spp = T(sh.own[1 * W + ot]);
-                                const T sin_dphi = T(sh.own[2 * W + ot]), wv = T(sh.own[3 * W + ot]);
-                                const int fl = __float_as_int(sh.own[4 * W + ot]);
+                                const float4 oa = *(const float4*)&sh.orec[ot * 8];
+                                const float4 ob = *(const float4*)&sh.orec[ot * 8 + 4];
+                                const T ox = T(oa.x), oy = T(oa.y), oz = T(oa.z);
+                                const T cpp = T(oa.w), spp = T(ob.x);
+                                const T sin_dphi = T(ob.y), wv = T(ob.z);
+                                const int fl = __float_as_int(ob.w);
                                 const int kind = fl >> 1;
-                                const T ox = T(sh.pred[0 * W + ot]), oy = T(sh.pred[1 * W + ot]),
-                                        oz = T(sh.pred[2 * W + ot]);
                                 // |azimuth difference| <= dphi (< pi/2): same half-plane, |sin| bounded
                                 bool pass = (fl & 1) || (T(hcp) * cpp + T(hsp) * spp > T(0) &&
                                                          !(Tr<T>::abs_(T(hsp) * cpp - T(hcp) * spp) >
@@ -1086,11 +1107,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                                     f.s = U(hsp);
                                     f.vu = U(r0[q].w) * U(r0[q].w);
                                     f.vv = U(r1[q].x) * U(r1[q].x);
-                                    const U c2u = hit_chi2_pos<U>(
-                                        U(ox), U(oy), U(oz), U(sh.posc[0 * W + ot]),
-                                        U(sh.posc[1 * W + ot]), U(sh.posc[2 * W + ot]),
-                                        U(sh.posc[3 * W + ot]), U(sh.posc[4 * W + ot]),
-                                        U(sh.posc[5 * W + ot]), f, kind);
+                                    C pc[6];
+                                    load_owner_cov(sh.ocov + ot * kOwnCov<C>, pc);
+                                    const U c2u = hit_chi2_pos<U>(U(ox), U(oy), U(oz), U(pc[0]), U(pc[1]),
+                                                                  U(pc[2]), U(pc[3]), U(pc[4]), U(pc[5]),
+                                                                  f, kind);
                                     ++n_chi2;
                                     ok = c2u < U(cut);
                                     c2f = float(c2u);
@@ -1198,7 +1219,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     if (!stop) {
                         // head: the best child (nk == 0: the child without a hit)
                         const int nh = sh.meta[0 * W + base + j];
-                        const float c0 = sh.pred[3 * W + base + j];
+                        const float c0 = sh.pchi2[base + j];
                         K[j] = nkj > 0 ? merge_key(nh + 1, c0 + sh.cchi2[0 * W + base + j], j, 0)
                                        : merge_key(nh, c0, j, 0);
                     }
@@ -1217,7 +1238,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     // child without a hit, then nothing
                     const int tj = base + bj, cn = c + 1;
                     const int n = sh.nchild[tj], h0 = sh.meta[0 * W + tj];
-                    const float cc0 = sh.pred[3 * W + tj];
+                    const float cc0 = sh.pchi2[tj];
                     const float cx = sh.cchi2[(cn < kMaxCands ? cn : kMaxCands - 1) * W + tj];
                     const uint64_t nkey = cn < n    ? merge_key(h0 + 1, cc0 + cx, bj, cn)
                                           : cn == n ? merge_key(h0, cc0, bj, cn)
@@ -1252,7 +1273,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                     const int j = sel_j;
                     const int c = sel_c;
                     const int tj = lbase + j;
-                    chi2 = sh.pred[3 * W + tj];
+                    chi2 = sh.pchi2[tj];
                     nhits = sh.meta[0 * W + tj];
                     misses = sh.meta[1 * W + tj];
                     status = (uint32_t)sh.meta[2 * W + tj];
