@@ -340,7 +340,10 @@ int kf_find_batched(kf_ctx* ctx, const kf_hits* hits, const int32_t* event_off, 
 /* Workgroup width of the finding kernel (32, 64, 128 or 256 lanes; a lane per
  * candidate slot, floor(64 / max_cands) seeds per wave) and tile order (0:
  * seeds sorted by event, eta, phi; 1: events largest first (up to 16,384
- * events; more keep their order), then eta, phi).  Default 64, 0.  Results do
+ * events; more keep their order), then eta, phi).  Either order is cut into
+ * eight ranges, one tile queue each, and within a range the seeds go by a
+ * cost class of pT and |eta|, costliest first; the costliest (pT < 0.6 GeV,
+ * |eta| < 0.5) come in tiles of half the seeds.  Default 64, 0.  Results do
  * not depend on either; speed does. */
 int kf_set_find_config(kf_ctx* ctx, int32_t width, int32_t largest_first);
 /* The configuration in use (host outputs). */
