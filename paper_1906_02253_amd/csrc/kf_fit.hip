@@ -214,7 +214,8 @@ __global__ __launch_bounds__(256) void propagate_kernel(int64_t n, int64_t ld, T
             for (int k = 0; k < 6; ++k) pt[k] = T(p[k]);
             mlp_features(pt, L, prm, f);
         }
-        const float y = mlp_wave(mlp, f);
+        const uint64_t wmask = __ballot(want);
+        const float y = wmask ? mlp_wave(mlp, f, wmask) : 0.0f;
         if (want) s_init = T(mlp_guess(f, y));
         if (!inb) return;
         if (!active) {
@@ -306,7 +307,8 @@ __global__ __launch_bounds__(256) void fit_kernel(FitArgs a, int k0, int k1, int
                 for (int q = 0; q < 6; ++q) pt[q] = T(p[q]);
                 mlp_features(pt, L, a.prm, f);
             }
-            const float y = mlp_wave(a.mlp, f);
+            const uint64_t wmask = __ballot(want);
+            const float y = wmask ? mlp_wave(a.mlp, f, wmask) : 0.0f;
             if (want) s_init = T(mlp_guess(f, y));
         }
         if (!alive) continue;

@@ -134,14 +134,18 @@ __device__ inline float mlp_tile(const MlpDev& m, bf16x4 xb, f32x4 h1[4], f32x4 
 }
 
 // Whole-wave inference: lane L passes the inputs of its own row and gets its
-// own output.  Must be called by all 64 lanes (uniform control flow).
-__device__ inline float mlp_wave(const MlpDev& m, const float f[kMlpIn])
+// own output.  Must be called by all 64 lanes (uniform control flow).  want:
+// the lanes whose output is used (a wave-uniform mask); the 16-row tile of a
+// group of 16 lanes none of which wants its output is skipped, and those
+// lanes get 0.
+__device__ inline float mlp_wave(const MlpDev& m, const float f[kMlpIn], uint64_t want = ~0ull)
 {
     const int ln = (int)(threadIdx.x & 63);
     const int r = ln & 15, g = ln >> 4;
     float mine = 0.0f;
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
+        if (((want >> (16 * ct)) & 0xFFFFull) == 0) continue;
         const int src = 16 * ct + r;
         float v[4];
 #pragma unroll
