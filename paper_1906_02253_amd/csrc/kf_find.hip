@@ -1167,16 +1167,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KF_FIND_WAV
                                 int32_t bi = bb[u];
                                 ++nacc;
                                 if (!(e < lk[kMaxCands - 1])) continue;
+                                // the list is ascending, so "e below entry q" holds
+                                // from the insertion point on: every slot takes
+                                // its own, its predecessor's or the new entry,
+                                // all decided from the old entries at once
+                                bool lt[kMaxCands];
 #pragma unroll
-                                for (int q = 0; q < kMaxCands; ++q) {
-                                    const bool lt = e < lk[q];
-                                    const uint64_t te = lt ? lk[q] : e;
-                                    const int32_t tb = lt ? lbi[q] : bi;
-                                    lk[q] = lt ? e : lk[q];
-                                    lbi[q] = lt ? bi : lbi[q];
-                                    e = te;
-                                    bi = tb;
+                                for (int q = 0; q < kMaxCands; ++q) lt[q] = e < lk[q];
+#pragma unroll
+                                for (int q = kMaxCands - 1; q > 0; --q) {
+                                    lk[q] = lt[q] ? (lt[q - 1] ? lk[q - 1] : e) : lk[q];
+                                    lbi[q] = lt[q] ? (lt[q - 1] ? lbi[q - 1] : bi) : lbi[q];
                                 }
+                                lk[0] = lt[0] ? e : lk[0];
+                                lbi[0] = lt[0] ? bi : lbi[0];
                             }
                         }
                         ac_first[ln] = 0x7fffffff;
